@@ -1,0 +1,48 @@
+"""Scalar diagnostics (oracle).
+
+Test infrastructure only (see ``oracle/__init__``).
+
+* field energy W = 1/2 sum_cells (eps0 |E|^2 + |B|^2 / mu0) dV  (Sec. 2, item iii);
+* relative L2 error ||F_n - F_h|| / ||F_n||  (Sec. 5.2, eq. ``L2_norm_error``);
+* total charge sum_i rho_i dV;
+* Gauss residual || [k]_s . E_hat + i rho_hat / eps0 || / || rho_hat / eps0 ||
+  (App. A, Gauss's law used in the derivation of the update).
+"""
+
+import numpy as np
+
+from . import psatd, transforms
+from .transforms import E_NAMES, OFFSETS
+
+EPS0 = 1.0
+MU0 = 1.0
+
+
+def field_energy(E, B, spacing):
+    dV = spacing[0] * spacing[1] * spacing[2]
+    e = sum(np.sum(np.asarray(c, dtype=np.float64) ** 2) for c in E)
+    b = sum(np.sum(np.asarray(c, dtype=np.float64) ** 2) for c in B)
+    return 0.5 * (EPS0 * e + b / MU0) * dV
+
+
+def rel_l2(ref, test):
+    ref = np.asarray(ref, dtype=np.float64)
+    test = np.asarray(test, dtype=np.float64)
+    den = np.sqrt(np.sum(ref ** 2))
+    return float(np.sqrt(np.sum((test - ref) ** 2)) / den) if den > 0 else float(np.sqrt(np.sum(test ** 2)))
+
+
+def total_charge(rho, spacing):
+    return float(np.sum(rho) * spacing[0] * spacing[1] * spacing[2])
+
+
+def gauss_residual(E_stag, rho, spacing, psatd_order):
+    shape = rho.shape
+    ks = psatd.staggered_wave_vector(shape, spacing, psatd_order)
+    Eh = [transforms.forward(E_stag[d], spacing, OFFSETS[E_NAMES[d]]) for d in range(3)]
+    rh = transforms.forward(rho, spacing, OFFSETS["rho"])
+    div = ks[0] * Eh[0] + ks[1] * Eh[1] + ks[2] * Eh[2]
+    res = div + 1j * rh / EPS0
+    den = np.sqrt(np.sum(np.abs(rh / EPS0) ** 2))
+    num = np.sqrt(np.sum(np.abs(res) ** 2))
+    return float(num / den) if den > 0 else float(num)

@@ -1,0 +1,100 @@
+"""Standard PSATD on the staggered grid (oracle).
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Sec. 4.1 (notation) and Sec. 4.2, eqs. ``eq_update_B_with_rho_standard`` and
+``eq_update_E_with_rho_standard``:
+    B^{n+1} = C B^n - i (S/w_s) [k]_s x E^n + i X1 [k]_s x J^{n+1/2}
+    E^{n+1} = C E^n + i c^2 (S/w_s) [k]_s x B^n + X4 J^{n+1/2}
+              + i (X3 rho^n - X2 rho^{n+1}) [k]_s
+with w_s = c |[k]_s|, C = cos(w_s dt), S = sin(w_s dt) and
+    X1 = (1 - C)/(eps0 w_s^2),  X2 = c^2 (1 - S/(w_s dt))/(eps0 w_s^2),
+    X3 = c^2 (C - S/(w_s dt))/(eps0 w_s^2),  X4 = -S/(eps0 w_s).
+
+The paper leaves w_s = 0 out ("assuming w_s != 0", end of Sec. 4.1).  Reading
+used here: each coefficient takes its limit w_s -> 0 (S/w_s -> dt,
+X1 -> dt^2/(2 eps0), X2 -> c^2 dt^2/(6 eps0), X3 -> -c^2 dt^2/(3 eps0),
+X4 -> -dt/eps0).  Below w_s dt = 0.2 every coefficient is evaluated by the
+Taylor series of its definition (eight terms; the same functions, free of the
+cancellation in 1 - S/(w_s dt) and C - S/(w_s dt)); above it 1 - C is written
+2 sin^2(w_s dt / 2).
+"""
+
+from math import factorial
+
+import numpy as np
+
+from .fornberg import k_staggered
+from .transforms import wave_vectors
+
+C_LIGHT = 1.0
+EPS0 = 1.0
+SERIES_BELOW = 0.2
+
+
+def staggered_wave_vector(shape, spacing, order):
+    """([k^x]_s, [k^y]_s, [k^z]_s) as broadcastable 3D arrays."""
+    kx, ky, kz = wave_vectors(shape, spacing)
+    dx, dy, dz = spacing
+    return (k_staggered(kx, dx, order), k_staggered(ky, dy, order), k_staggered(kz, dz, order))
+
+
+def _series(x2, coef):
+    """sum_k coef[k] * x2**k (Horner)."""
+    out = np.zeros_like(x2)
+    for c in reversed(coef):
+        out = out * x2 + c
+    return out
+
+
+# Taylor coefficients in x^2 (x = w_s dt), k = 0..7, from the sine and cosine series:
+#   sin(x)/x            = sum_k (-1)^k x^(2k) / (2k+1)!
+#   (1 - cos x)/x^2     = sum_k (-1)^k x^(2k) / (2k+2)!
+#   (1 - sin(x)/x)/x^2  = sum_k (-1)^k x^(2k) / (2k+3)!
+#   (cos x - sin(x)/x)/x^2 = sum_k (-1)^(k+1) x^(2k) (2k+2) / (2k+3)!
+_SINC = [(-1) ** k / factorial(2 * k + 1) for k in range(8)]
+_ONE_MINUS_COS = [(-1) ** k / factorial(2 * k + 2) for k in range(8)]
+_ONE_MINUS_SINC = [(-1) ** k / factorial(2 * k + 3) for k in range(8)]
+_COS_MINUS_SINC = [(-1) ** (k + 1) * (2 * k + 2) / factorial(2 * k + 3) for k in range(8)]
+
+
+def coefficients(ks, dt):
+    """C, S/w_s, X1, X2, X3, X4 on the (broadcast) grid of modified wave vectors ``ks``."""
+    ksx, ksy, ksz = np.broadcast_arrays(*ks)
+    w = C_LIGHT * np.sqrt(ksx ** 2 + ksy ** 2 + ksz ** 2)
+    x = w * dt
+    small = x < SERIES_BELOW
+    wsafe = np.where(small, 1.0, w)
+    x2 = np.where(small, x * x, 0.0)
+
+    C = np.cos(x)
+    S = np.sin(x)
+    S_over_w = np.where(small, dt * _series(x2, _SINC), S / wsafe)
+    X1 = np.where(small, dt ** 2 * _series(x2, _ONE_MINUS_COS) / EPS0,
+                  2.0 * np.sin(0.5 * x) ** 2 / (EPS0 * wsafe ** 2))
+    X2 = np.where(small, C_LIGHT ** 2 * dt ** 2 * _series(x2, _ONE_MINUS_SINC) / EPS0,
+                  C_LIGHT ** 2 * (1 - S / (wsafe * dt)) / (EPS0 * wsafe ** 2))
+    X3 = np.where(small, C_LIGHT ** 2 * dt ** 2 * _series(x2, _COS_MINUS_SINC) / EPS0,
+                  C_LIGHT ** 2 * (C - S / (wsafe * dt)) / (EPS0 * wsafe ** 2))
+    X4 = -S_over_w / EPS0
+    return {"C": C, "S_over_w": S_over_w, "X1": X1, "X2": X2, "X3": X3, "X4": X4}
+
+
+def cross(a, b):
+    """Component-wise cross product of two 3-lists of arrays."""
+    return (a[1] * b[2] - a[2] * b[1],
+            a[2] * b[0] - a[0] * b[2],
+            a[0] * b[1] - a[1] * b[0])
+
+
+def update(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, coef):
+    """One standard-PSATD step of the paper-convention spectra; returns (E_new, B_new) 3-tuples."""
+    C, Sw = coef["C"], coef["S_over_w"]
+    X1, X2, X3, X4 = coef["X1"], coef["X2"], coef["X3"], coef["X4"]
+    kxE = cross(ks, Eh)
+    kxB = cross(ks, Bh)
+    kxJ = cross(ks, Jh)
+    B_new = tuple(C * Bh[d] - 1j * Sw * kxE[d] + 1j * X1 * kxJ[d] for d in range(3))
+    E_new = tuple(C * Eh[d] + 1j * C_LIGHT ** 2 * Sw * kxB[d] + X4 * Jh[d]
+                  + 1j * (X3 * rho_old_h - X2 * rho_new_h) * ks[d] for d in range(3))
+    return E_new, B_new

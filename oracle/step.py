@@ -1,0 +1,113 @@
+"""One hybrid nodal-staggered PSATD PIC cycle (oracle).
+
+Test infrastructure only (see ``oracle/__init__``).
+
+Sec. 2, the hybrid cycle: push particles -> deposit rho, J on the nodal grid ->
+centre J from the nodal to the Yee grid -> solve Maxwell's equations on the
+Yee grid in Fourier space -> centre E, B from the Yee to the nodal grid ->
+gather E, B from the nodal grid.  One call of ``step`` starts from the state
+(E, B on the Yee grid at time n; positions x^n; momenta u^{n-1/2};
+rho^n on the nodes) and runs, in this order:
+  1. E_nod, B_nod = staggered-to-nodal centering of E^n, B^n;
+  2. gather + Boris push: u^{n-1/2} -> u^{n+1/2}, x^n -> x^{n+1};
+  3. deposit rho^{n+1} (plus a static background) and J^{n+1/2} on the nodes;
+  4. J on the Yee grid = nodal-to-staggered centering of J;
+  5. standard PSATD update of (E, B) in the paper's Fourier convention;
+  6. back to real space; rho^n <- rho^{n+1}.
+Immobile species (m = inf) are never pushed and deposit rho only.
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import centering, particles, psatd, transforms
+from .transforms import B_NAMES, E_NAMES, J_NAMES, OFFSETS
+
+
+@dataclass
+class Params:
+    shape: tuple            # (nx, ny, nz)
+    spacing: tuple          # (dx, dy, dz)
+    dt: float
+    shape_order: int = 1    # 1 = CIC, 3 = cubic B-spline
+    center_order: int = 8   # 2 m_c
+    psatd_order: int = 16   # 2 m_p for [k]_s; 0 = infinite
+
+    @property
+    def lengths(self):
+        return tuple(n * d for n, d in zip(self.shape, self.spacing))
+
+
+def center_fields_s2n(E_stag, B_stag, p):
+    m = p.center_order // 2
+    E_nod = [centering.s2n(E_NAMES[d], E_stag[d], m) for d in range(3)]
+    B_nod = [centering.s2n(B_NAMES[d], B_stag[d], m) for d in range(3)]
+    return E_nod, B_nod
+
+
+def center_current_n2s(J_nod, p):
+    m = p.center_order // 2
+    return [centering.n2s(J_NAMES[d], J_nod[d], m) for d in range(3)]
+
+
+def gather_push(sp, E_nod, B_nod, p):
+    """Advance one species in place; returns v^{n+1/2} (3, Np) and the half-step positions."""
+    pos, u = sp["pos"], sp["u"]
+    if not np.isfinite(sp["m"]):
+        return np.zeros((3, pos.shape[0])), pos.copy()
+    EB = particles.gather(list(E_nod) + list(B_nod), pos, p.spacing, p.shape_order)
+    u_new = particles.boris(u.T, EB[:3], EB[3:], sp["q"], sp["m"], p.dt)
+    v = u_new / particles.gamma(u_new)
+    pos_half = particles.wrap(pos + 0.5 * p.dt * v.T, p.lengths)
+    pos_new = particles.wrap(pos + p.dt * v.T, p.lengths)
+    sp["pos"] = pos_new
+    sp["u"] = u_new.T.copy()
+    return v, pos_half
+
+
+def deposit_rho(species, p, rho_static=None):
+    rho = np.zeros(p.shape) if rho_static is None else np.array(rho_static, dtype=np.float64)
+    for sp in species:
+        rho += particles.deposit([sp["q"] * sp["w"]], sp["pos"], p.shape, p.spacing, p.shape_order)[0]
+    return rho
+
+
+def deposit_current(sp, v, pos_half, p):
+    qw = sp["q"] * sp["w"]
+    return particles.deposit([qw * v[0], qw * v[1], qw * v[2]], pos_half, p.shape, p.spacing, p.shape_order)
+
+
+def push_fields(E_stag, B_stag, J_stag, rho_old, rho_new, p):
+    """Standard PSATD update of the Yee-grid fields from time n to n+1 (Sec. 4.2)."""
+    ks = psatd.staggered_wave_vector(p.shape, p.spacing, p.psatd_order)
+    coef = psatd.coefficients(ks, p.dt)
+    fw = lambda f, name: transforms.forward(f, p.spacing, OFFSETS[name])
+    Eh = [fw(E_stag[d], E_NAMES[d]) for d in range(3)]
+    Bh = [fw(B_stag[d], B_NAMES[d]) for d in range(3)]
+    Jh = [fw(J_stag[d], J_NAMES[d]) for d in range(3)]
+    rho_old_h = fw(rho_old, "rho")
+    rho_new_h = fw(rho_new, "rho")
+    E_new, B_new = psatd.update(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, coef)
+    E_out = [transforms.inverse(E_new[d], p.spacing, OFFSETS[E_NAMES[d]]) for d in range(3)]
+    B_out = [transforms.inverse(B_new[d], p.spacing, OFFSETS[B_NAMES[d]]) for d in range(3)]
+    return E_out, B_out
+
+
+def step(state, species, p, rho_static=None):
+    """Advance ``state`` (dict: E_stag, B_stag, rho_old) and ``species`` (list of dicts) by one cycle.
+
+    Returns a dict of the intermediate arrays of the step (for stage-by-stage parity)."""
+    E_nod, B_nod = center_fields_s2n(state["E_stag"], state["B_stag"], p)
+    J_nod = [np.zeros(p.shape) for _ in range(3)]
+    for sp in species:
+        v, pos_half = gather_push(sp, E_nod, B_nod, p)
+        if np.isfinite(sp["m"]):
+            Jc = deposit_current(sp, v, pos_half, p)
+            for d in range(3):
+                J_nod[d] += Jc[d]
+    rho_new = deposit_rho(species, p, rho_static)
+    J_stag = center_current_n2s(J_nod, p)
+    E_out, B_out = push_fields(state["E_stag"], state["B_stag"], J_stag, state["rho_old"], rho_new, p)
+    state["E_stag"], state["B_stag"], state["rho_old"] = E_out, B_out, rho_new
+    return {"E_nod": E_nod, "B_nod": B_nod, "J_nod": J_nod, "J_stag": J_stag, "rho_new": rho_new}
