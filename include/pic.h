@@ -1,0 +1,183 @@
+/*
+ * pic.h -- C ABI of the hybrid nodal-staggered PSATD particle-in-cell step on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Scheme: Zoni et al., "A hybrid nodal-staggered pseudo-spectral
+ * electromagnetic particle-in-cell method with finite-order centering",
+ * arXiv 2106.12919.  One step follows the hybrid cycle of Sec. 2:
+ * centre E,B from the Yee grid to the nodes -> gather on the nodes and push ->
+ * deposit rho, J on the nodes -> centre J from the nodes to the Yee grid ->
+ * standard PSATD update of E,B on the Yee grid in Fourier space (Sec. 4.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Normalised units: c = eps0 = mu0 = 1.  Charges and masses are in units of
+ *   the elementary charge and the electron mass.
+ * - Grids are triply periodic, nx*ny*nz points, stored C-order (z fastest).
+ *   Node (i,j,k) sits at (i*dx, j*dy, k*dz).  A Yee component is stored at the
+ *   index of the node at or below its position: E^x[i][j][k] is the value at
+ *   ((i+1/2)dx, j dy, k dz), B^x[i][j][k] at (i dx, (j+1/2)dy, (k+1/2)dz), etc.
+ *   (App. A list of positions; J sits with E, rho is nodal).
+ * - Every array argument is caller-owned DEVICE memory on the context's
+ *   device, in the context's dtype (float for PIC_F32, double for PIC_F64),
+ *   aligned to at least 16 bytes.  The library keeps no pointer beyond a call.
+ * - Every call enqueues work asynchronously on the context's HIP stream and
+ *   returns without waiting (pic_sync waits).  Errors detected on the host are
+ *   returned before anything is enqueued; asynchronous device errors surface as
+ *   PIC_EHIP at a later call or at pic_sync.  pic_last_error gives the text.
+ * - A context is not thread-safe: use one context per host thread/stream.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_ctx_s* pic_ctx;
+
+typedef enum {
+  PIC_OK = 0,
+  PIC_EINVAL = 1,        /* bad argument: null pointer, out-of-range value, dtype mismatch */
+  PIC_EUNSUPPORTED = 2,  /* valid but not supported (grid size, order) */
+  PIC_EHIP = 3,          /* HIP runtime or kernel error */
+  PIC_ENOMEM = 4,        /* device allocation failed */
+  PIC_ESTATE = 5         /* call order violated (e.g. destroyed context) */
+} pic_status;
+
+typedef enum { PIC_F32 = 0, PIC_F64 = 1 } pic_dtype;
+
+/* pic_center directions and field selectors */
+enum { PIC_N2S = 0, PIC_S2N = 1 };
+enum { PIC_J = 0, PIC_E = 1, PIC_B = 2 };
+/* pic_deposit modes */
+enum { PIC_DEP_RHO_AND_J = 0, PIC_DEP_RHO_ONLY = 1 };
+
+typedef struct {
+  int32_t nx, ny, nz;     /* each even, of the form 2^a 3^b, 8 <= n <= 1024 */
+  double dx, dy, dz;      /* cell sizes, > 0 */
+  double dt;              /* time step, 0 < c*dt <= min(dx,dy,dz) (a particle moves < 1 cell per step) */
+  int32_t shape_order;    /* particle shape: 1 = linear (CIC), 3 = cubic B-spline */
+  int32_t center_order;   /* finite-order centering 2m, even, 2..32, with 2m <= min(nx,ny,nz) (Sec. 3) */
+  int32_t psatd_order;    /* order 2m_p of the staggered modified wave number [k]_s, even 2..64; 0 = infinite */
+  pic_dtype dtype;        /* precision of fields, particles, FFTs; tables are always built in FP64 */
+  uint32_t flags;         /* reserved, must be 0 */
+} pic_params;
+
+/* One particle species, structure of arrays, caller-owned device memory.
+ * Position = node index + offset: the particle lies at
+ * ((i + off[0]) dx, (j + off[1]) dy, (k + off[2]) dz) with cell = (i*ny + j)*nz + k
+ * and every offset in [0, 1).  u = gamma v / c.  Immobile species use m = INFINITY:
+ * they are never pushed and deposit charge only. */
+typedef struct {
+  int64_t n;              /* number of particles (>= 0) */
+  int32_t* cell;          /* [n] linear cell index */
+  void* off[3];           /* [n] each, dtype */
+  void* u[3];             /* [n] each, dtype */
+  void* w;                /* [n] per-particle weight (dtype), or NULL to use w_const */
+  double w_const;         /* weight used when w == NULL */
+  double q, m;            /* charge and mass of one weight unit */
+} pic_species;
+
+/* Grid arrays of one step, each nx*ny*nz elements of dtype (see conventions). */
+typedef struct {
+  void* E_stag[3];        /* E on the Yee grid at time n (state) */
+  void* B_stag[3];        /* B on the Yee grid at time n (state) */
+  void* E_nod[3];         /* E centred to the nodes (output of pic_center S2N) */
+  void* B_nod[3];         /* B centred to the nodes */
+  void* J_nod[3];         /* J^{n+1/2} on the nodes (output of pic_deposit) */
+  void* J_stag[3];        /* J^{n+1/2} on the Yee grid (output of pic_center N2S) */
+  void* rho_old;          /* rho^n on the nodes */
+  void* rho_new;          /* rho^{n+1} on the nodes */
+  const void* rho_static; /* optional static background charge added by pic_deposit, or NULL */
+} pic_fields;
+
+/* Create a context on the current HIP device.  Validates *p, builds in FP64 on
+ * the host the Fornberg coefficients (Sec. 3, eq. eq_Fornberg_staggered), the
+ * staggered modified wave numbers [k]_s (Sec. 4.1) and the per-mode PSATD
+ * coefficients C, S/w_s, X1, X2, X3 (Sec. 4.2; X4 = -S/w_s; w_s = 0 takes the
+ * limits), casts them to dtype and uploads them with the FFT plans and
+ * the k-space work buffers (owned by the context).  hip_stream may be NULL
+ * (null stream).  On error *out is set to NULL and the error text is available
+ * from pic_last_error(NULL). */
+pic_status pic_init(const pic_params* p, void* hip_stream, pic_ctx* out);
+
+/* Free everything the context owns.  Waits for its stream first. */
+pic_status pic_destroy(pic_ctx ctx);
+
+/* Change the stream later calls enqueue on. */
+pic_status pic_set_stream(pic_ctx ctx, void* hip_stream);
+
+/* Deposit rho^{n+1} and J^{n+1/2} on the nodal grid (Sec. 2, hybrid cycle; time
+ * levels of Sec. 4.2).  Called after pic_gather_push, so positions are x^{n+1}
+ * and momenta u^{n+1/2}.  Zeroes f->rho_new, adds f->rho_static (if not NULL),
+ * then adds sum_p q w S(x_p^{n+1} - x_i)/dV.  With PIC_DEP_RHO_AND_J it also zeroes
+ * f->J_nod and adds sum_p q w v_p S(x_p^{n+1/2} - x_i)/dV with
+ * x^{n+1/2} = x^{n+1} - dt v/2 (direct deposition).  S is the B-spline of
+ * shape_order.  Immobile species contribute to rho only.  nsp >= 0 species. */
+pic_status pic_deposit(pic_ctx ctx, const pic_species* sp, int nsp, pic_fields* f, int mode);
+
+/* Finite-order centering (Sec. 3, eq. staggered_finite_sum, order center_order):
+ *   dir = PIC_N2S, what = PIC_J : J_nod -> J_stag, J^d along axis d,
+ *         f_{j+1/2} = sum_n alpha^s_{m,n} (f_{j+n} + f_{j+1-n}) / 2;
+ *   dir = PIC_S2N, what = PIC_E : E_stag -> E_nod, E^d along axis d,
+ *   dir = PIC_S2N, what = PIC_B : B_stag -> B_nod, B^d along the two other axes,
+ *         f_j = sum_n alpha^s_{m,n} (f_{j+n-1/2} + f_{j-n+1/2}) / 2.
+ * Other (dir, what) pairs return PIC_EINVAL. */
+pic_status pic_center(pic_ctx ctx, int dir, int what, pic_fields* f);
+
+/* Standard PSATD update on the staggered grid (Sec. 4.2, eqs.
+ * eq_update_B_with_rho_standard and eq_update_E_with_rho_standard) in the
+ * Fourier convention of App. A (each component transformed at its own Yee
+ * position).  Reads E_stag, B_stag (time n), J_stag, rho_old, rho_new and
+ * overwrites E_stag, B_stag with time n+1.  Uses 11 forward and 6 inverse
+ * real 3D FFTs. */
+pic_status psatd_push_fields(pic_ctx ctx, pic_fields* f);
+
+/* Gather E_nod, B_nod at x^n with the shape_order B-spline (one weight set for
+ * all six nodal components) and advance every mobile species with the
+ * relativistic Boris scheme: u^{n-1/2} -> u^{n+1/2}, x^{n+1} = x^n + dt u/gamma,
+ * periodic wrap of cell and offset. */
+pic_status pic_gather_push(pic_ctx ctx, const pic_fields* f, pic_species* sp, int nsp);
+
+/* nsteps >= 0 complete hybrid cycles.  State on entry: E_stag, B_stag at time n,
+ * particles at x^n with u^{n-1/2}, rho_old = rho^n.  Each step runs
+ * S2N centering -> gather+push -> deposit -> N2S centering -> PSATD update.  On
+ * return E_stag, B_stag, particles and rho_old are at time n+nsteps, and E_nod,
+ * B_nod, J_nod, J_stag, rho_new hold the intermediates of the last step.  E and
+ * B stay in Fourier space between the steps of one call (7 forward transforms on
+ * entry, then 4 forward and 6 inverse per step).  Particles of each species may
+ * be reordered (all per-particle arrays together) to group them by grid tile. */
+pic_status pic_step(pic_ctx ctx, pic_fields* f, pic_species* sp, int nsp, int nsteps);
+
+/* Wait for the context's stream; returns PIC_EHIP if a device error occurred, and
+ * PIC_EINVAL if particles with a cell index outside [0, nx*ny*nz) were skipped by
+ * pic_gather_push / pic_deposit / pic_step since the last pic_sync (the kernels
+ * never access memory through such an index). */
+pic_status pic_sync(pic_ctx ctx);
+
+/* Diagnostics, computed on the device and accumulated in FP64 (synchronous):
+ * out[0] = field energy W = 1/2 sum (|E|^2 + |B|^2) dV of the Yee-grid state
+ * (Sec. 2 item iii), out[1] = total charge sum(rho_old) dV. */
+pic_status pic_diagnostics(pic_ctx ctx, const pic_fields* f, double out[2]);
+
+/* Per-stage timing with HIP events on the context stream.  When enabled, each
+ * stage launch of pic_step is bracketed by events; pic_stage_times returns, for
+ * stage s < nstage, the accumulated milliseconds and the number of launches since
+ * the last reset.  Stage names: pic_stage_name(s). */
+pic_status pic_profile(pic_ctx ctx, int enable);
+pic_status pic_stage_times(pic_ctx ctx, double* ms, int64_t* count, int nstage);
+const char* pic_stage_name(int s);
+int pic_num_stages(void);
+
+/* Text of the last error of ctx (or of the last failed pic_init when ctx is NULL). */
+const char* pic_last_error(pic_ctx ctx);
+const char* pic_strerror(pic_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

@@ -1,0 +1,67 @@
+"""Builds libpic.so (the HIP library behind include/pic.h) for gfx950 with hipcc.
+
+Usage:  python -m paper_2106_12919_amd.build   (or build() from Python).
+Each translation unit is compiled to an object in ``_build/`` in parallel, then
+linked in-tree to ``paper_2106_12919_amd/libpic.so``.
+"""
+
+import os
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libpic.so")
+SOURCES = ["api.hip", "fft.hip", "centering.hip", "psatd.hip", "particles.hip", "diag.hip", "tables.cpp"]
+
+ARCH = "gfx950"
+FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # packed FP32 instructions are disabled on purpose
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+    "-I", os.path.join(ROOT, "include"),
+]
+
+
+def _hipcc():
+    h = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(h):
+        raise RuntimeError("hipcc not found (ROCm is required to build libpic)")
+    return h
+
+
+def _compile(src):
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    cmd = [_hipcc(), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    return src, obj, r.returncode, r.stdout
+
+
+def build(verbose=False, jobs=None):
+    """Compile every source and link libpic.so; raises RuntimeError on failure."""
+    os.makedirs(BUILD, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 4)))
+    with ThreadPoolExecutor(jobs) as ex:
+        results = list(ex.map(_compile, SOURCES))
+    errors = [(s, out) for s, _, rc, out in results if rc != 0]
+    for s, _, rc, out in results:
+        if verbose and out.strip():
+            print(f"--- {s}\n{out}")
+    if errors:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(f"--- {s}\n{out}" for s, out in errors))
+    tmp = LIB + ".tmp"
+    cmd = [_hipcc(), "-shared", "-o", tmp] + [o for _, o, _, _ in results] + [f"--offload-arch={ARCH}", "-fPIC"]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n" + r.stdout)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,684 @@
+// C ABI of libpic (include/pic.h): context, validation, table upload and the
+// orchestration of one hybrid PSATD PIC cycle (Sec. 2) from the HIP kernels.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/pic.h"
+#include "kernels.h"
+
+using namespace pic;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+const char* const kStageNames[] = {"center_s2n", "gather_push", "deposit", "center_n2s",
+                                   "fft_forward", "psatd_update", "fft_inverse", "entry_forward"};
+constexpr int kNumStages = 8;
+enum Stage { ST_S2N = 0, ST_PUSH, ST_DEPOSIT, ST_N2S, ST_FFT_FWD, ST_UPDATE, ST_FFT_INV, ST_ENTRY };
+
+struct EventPair {
+  hipEvent_t a, b;
+  int stage;
+};
+
+struct EngineBase {
+  virtual ~EngineBase() = default;
+};
+
+bool factor23(int n) {
+  if (n <= 0) return false;
+  while (n % 2 == 0) n /= 2;
+  while (n % 3 == 0) n /= 3;
+  return n == 1;
+}
+
+}  // namespace
+
+struct pic_ctx_s {
+  pic_params p{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::string err;
+  std::unique_ptr<EngineBase> eng;
+  std::vector<double> ccoef;  // alpha^s_{m,n}/2 for the centering order
+  // profiling
+  bool profiling = false;
+  std::vector<EventPair> pending;
+  std::vector<EventPair> pool;
+  double stage_ms[kNumStages] = {0};
+  int64_t stage_count[kNumStages] = {0};
+  double* d_acc = nullptr;  // 2 doubles for reductions
+  int* d_bad = nullptr;     // count of particles skipped for an out-of-range cell index
+
+  pic_status fail(pic_status s, const std::string& msg) {
+    err = msg;
+    return s;
+  }
+  pic_status check(const char* where) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(PIC_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+    return PIC_OK;
+  }
+  void stage_begin(int st, EventPair& ev) {
+    if (!profiling) return;
+    if (pool.empty()) {
+      EventPair e{};
+      (void)hipEventCreate(&e.a);
+      (void)hipEventCreate(&e.b);
+      pool.push_back(e);
+    }
+    ev = pool.back();
+    pool.pop_back();
+    ev.stage = st;
+    (void)hipEventRecord(ev.a, stream);
+  }
+  void stage_end(EventPair& ev) {
+    if (!profiling) return;
+    (void)hipEventRecord(ev.b, stream);
+    pending.push_back(ev);
+  }
+  void collect() {
+    for (auto& ev : pending) {
+      float ms = 0;
+      if (hipEventSynchronize(ev.b) == hipSuccess && hipEventElapsedTime(&ms, ev.a, ev.b) == hipSuccess) {
+        stage_ms[ev.stage] += ms;
+        stage_count[ev.stage] += 1;
+      }
+      pool.push_back(ev);
+    }
+    pending.clear();
+  }
+};
+
+namespace {
+
+struct StageScope {
+  pic_ctx_s* c;
+  EventPair ev{};
+  StageScope(pic_ctx_s* c_, int st) : c(c_) { c->stage_begin(st, ev); }
+  ~StageScope() { c->stage_end(ev); }
+};
+
+template <typename T>
+struct Engine : EngineBase {
+  Fft3D<T> fft;
+  PsatdTables<T> tab;
+  cplx<T>* Eh[3] = {nullptr, nullptr, nullptr};
+  cplx<T>* Bh[3] = {nullptr, nullptr, nullptr};
+  cplx<T>* Jh[3] = {nullptr, nullptr, nullptr};
+  cplx<T>* rh[2] = {nullptr, nullptr};
+  cplx<T>* scratch[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  T* tmp = nullptr;
+  std::vector<void*> allocs;
+
+  ~Engine() override {
+    for (void* a : allocs) (void)hipFree(a);
+    fft.release();
+  }
+  template <typename P>
+  hipError_t alloc(P** out, size_t count) {
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(P) > 0 ? count * sizeof(P) : 1);
+    if (e != hipSuccess) return e;
+    allocs.push_back(q);
+    *out = reinterpret_cast<P*>(q);
+    return hipSuccess;
+  }
+  template <typename P>
+  hipError_t upload(P** out, const std::vector<P>& h) {
+    hipError_t e = alloc(out, h.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*out, h.data(), h.size() * sizeof(P), hipMemcpyHostToDevice);
+  }
+};
+
+template <typename T>
+hipError_t build_engine(const pic_params& p, Engine<T>& e) {
+  hipError_t err = e.fft.init(p.nx, p.ny, p.nz);
+  if (err != hipSuccess) return err;
+  const int n[3] = {p.nx, p.ny, p.nz};
+  const double d[3] = {p.dx, p.dy, p.dz};
+  const int nzh = e.fft.nzh;
+  // per-axis [k]_s and the staggered phase operators D+- = i [k]_s exp(+-i k d / 2)
+  std::vector<double> ks[3];
+  for (int a = 0; a < 3; ++a) {
+    ks[a].resize(n[a]);
+    k_staggered_axis(n[a], d[a], p.psatd_order, ks[a].data());
+    const int len = (a == 2) ? nzh : n[a];
+    std::vector<cplx<T>> dp(len), dm(len);
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int i = 0; i < len; ++i) {
+      const int f = (i <= (n[a] - 1) / 2) ? i : i - n[a];
+      const double k = two_pi * f / (n[a] * d[a]);
+      const double sh = std::sin(0.5 * k * d[a]), ch = std::cos(0.5 * k * d[a]);
+      dp[i] = cmake((T)(-ks[a][i] * sh), (T)(ks[a][i] * ch));
+      dm[i] = cmake((T)(ks[a][i] * sh), (T)(ks[a][i] * ch));
+    }
+    if ((err = e.upload(&e.tab.Dp[a], dp)) != hipSuccess) return err;
+    if ((err = e.upload(&e.tab.Dm[a], dm)) != hipSuccess) return err;
+  }
+  // 3D per-mode tables on the unpadded half spectrum
+  const size_t M = (size_t)p.nx * p.ny * nzh;
+  std::vector<T> C(M), Sw(M), X1(M), X2(M), X3(M);
+  for (int i = 0; i < p.nx; ++i)
+    for (int j = 0; j < p.ny; ++j)
+      for (int k = 0; k < nzh; ++k) {
+        const size_t idx = ((size_t)i * p.ny + j) * nzh + k;
+        const double w = std::sqrt(ks[0][i] * ks[0][i] + ks[1][j] * ks[1][j] + ks[2][k] * ks[2][k]);
+        double c, s, x1, x2, x3;
+        psatd_coefficients(w, p.dt, &c, &s, &x1, &x2, &x3);
+        C[idx] = (T)c;
+        Sw[idx] = (T)s;
+        X1[idx] = (T)x1;
+        X2[idx] = (T)x2;
+        X3[idx] = (T)x3;
+      }
+  if ((err = e.upload(&e.tab.C, C)) != hipSuccess) return err;
+  if ((err = e.upload(&e.tab.Sw, Sw)) != hipSuccess) return err;
+  if ((err = e.upload(&e.tab.X1, X1)) != hipSuccess) return err;
+  if ((err = e.upload(&e.tab.X2, X2)) != hipSuccess) return err;
+  if ((err = e.upload(&e.tab.X3, X3)) != hipSuccess) return err;
+  // spectra and scratch, zeroed once (padding columns stay zero)
+  const size_t ns = e.fft.spectrum_elems();
+  cplx<T>** bufs[17] = {&e.Eh[0], &e.Eh[1], &e.Eh[2], &e.Bh[0], &e.Bh[1], &e.Bh[2], &e.Jh[0], &e.Jh[1], &e.Jh[2],
+                        &e.rh[0], &e.rh[1], &e.scratch[0], &e.scratch[1], &e.scratch[2], &e.scratch[3],
+                        &e.scratch[4], &e.scratch[5]};
+  for (auto b : bufs) {
+    if ((err = e.alloc(b, ns)) != hipSuccess) return err;
+    if ((err = hipMemset(*b, 0, ns * sizeof(cplx<T>))) != hipSuccess) return err;
+  }
+  if ((err = e.alloc(&e.tmp, (size_t)p.nx * p.ny * p.nz)) != hipSuccess) return err;
+  return hipSuccess;
+}
+
+pic_status validate_params(const pic_params* p, std::string& msg) {
+  if (!p) { msg = "params is NULL"; return PIC_EINVAL; }
+  const int n[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 8 || n[a] > 1024 || n[a] % 2) { msg = "grid sizes must be even and in [8, 1024]"; return PIC_EUNSUPPORTED; }
+    if (!factor23(n[a])) { msg = "grid sizes must be of the form 2^a 3^b"; return PIC_EUNSUPPORTED; }
+  }
+  const double d[3] = {p->dx, p->dy, p->dz};
+  for (double x : d)
+    if (!(x > 0) || !std::isfinite(x)) { msg = "cell sizes must be positive and finite"; return PIC_EINVAL; }
+  const double dmin = std::fmin(p->dx, std::fmin(p->dy, p->dz));
+  if (!(p->dt > 0) || !std::isfinite(p->dt) || p->dt > dmin) { msg = "need 0 < c*dt <= min(dx, dy, dz)"; return PIC_EINVAL; }
+  if (p->shape_order != 1 && p->shape_order != 3) { msg = "shape_order must be 1 or 3"; return PIC_EUNSUPPORTED; }
+  const int nmin = std::min(p->nx, std::min(p->ny, p->nz));
+  if (p->center_order < 2 || p->center_order > 32 || p->center_order % 2 || p->center_order > nmin) {
+    msg = "center_order must be even, in [2, 32] and <= the smallest grid size";
+    return PIC_EUNSUPPORTED;
+  }
+  if (p->psatd_order != 0 && (p->psatd_order < 2 || p->psatd_order > 64 || p->psatd_order % 2)) {
+    msg = "psatd_order must be 0 or even in [2, 64]";
+    return PIC_EUNSUPPORTED;
+  }
+  if (p->dtype != PIC_F32 && p->dtype != PIC_F64) { msg = "dtype must be PIC_F32 or PIC_F64"; return PIC_EINVAL; }
+  if (p->flags != 0) { msg = "flags must be 0"; return PIC_EINVAL; }
+  return PIC_OK;
+}
+
+bool aligned(const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; }
+
+pic_status check_ptr(pic_ctx c, const void* q, const char* name) {
+  if (!q) return c->fail(PIC_EINVAL, std::string(name) + " is NULL");
+  if (!aligned(q)) return c->fail(PIC_EINVAL, std::string(name) + " is not 16-byte aligned");
+  return PIC_OK;
+}
+
+pic_status check_species(pic_ctx c, const pic_species* sp, int nsp) {
+  if (nsp < 0) return c->fail(PIC_EINVAL, "nsp < 0");
+  if (nsp > 0 && !sp) return c->fail(PIC_EINVAL, "species array is NULL");
+  for (int s = 0; s < nsp; ++s) {
+    const pic_species& x = sp[s];
+    if (x.n < 0) return c->fail(PIC_EINVAL, "species n < 0");
+    if (x.n > 0x7fffffffLL * 64) return c->fail(PIC_EUNSUPPORTED, "species too large");
+    if (!std::isfinite(x.q)) return c->fail(PIC_EINVAL, "species charge must be finite");
+    if (!(x.m > 0)) return c->fail(PIC_EINVAL, "species mass must be > 0 (INFINITY for immobile)");
+    if (x.n == 0) continue;
+    pic_status st;
+    if ((st = check_ptr(c, x.cell, "species cell")) != PIC_OK) return st;
+    for (int d = 0; d < 3; ++d) {
+      if ((st = check_ptr(c, x.off[d], "species off")) != PIC_OK) return st;
+      if ((st = check_ptr(c, x.u[d], "species u")) != PIC_OK) return st;
+    }
+    if (x.w && !aligned(x.w)) return c->fail(PIC_EINVAL, "species w is not 16-byte aligned");
+    if (!x.w && !std::isfinite(x.w_const)) return c->fail(PIC_EINVAL, "species w_const must be finite");
+  }
+  return PIC_OK;
+}
+
+template <typename T>
+SpeciesView<T> view(const pic_species& x) {
+  SpeciesView<T> v{};
+  v.n = x.n;
+  v.cell = x.cell;
+  for (int d = 0; d < 3; ++d) {
+    v.off[d] = static_cast<T*>(x.off[d]);
+    v.u[d] = static_cast<T*>(x.u[d]);
+  }
+  v.w = static_cast<T*>(x.w);
+  v.w_const = x.w_const;
+  v.q = x.q;
+  v.m = x.m;
+  return v;
+}
+
+GridGeom geom(const pic_params& p) {
+  return GridGeom{p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order};
+}
+
+size_t ncells(const pic_params& p) { return (size_t)p.nx * p.ny * p.nz; }
+
+// ------------------------------------------------------------------ stages
+
+template <typename T>
+pic_status do_center(pic_ctx c, int dir, int what, pic_fields* f) {
+  Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
+  const pic_params& p = c->p;
+  const int m = p.center_order / 2;
+  const double* cf = c->ccoef.data();
+  if (dir == PIC_N2S && what == PIC_J) {
+    for (int d = 0; d < 3; ++d)
+      center_axis<T>(static_cast<const T*>(f->J_nod[d]), static_cast<T*>(f->J_stag[d]), p.nx, p.ny, p.nz, d, 0, m,
+                     cf, c->stream);
+  } else if (dir == PIC_S2N && what == PIC_E) {
+    for (int d = 0; d < 3; ++d)
+      center_axis<T>(static_cast<const T*>(f->E_stag[d]), static_cast<T*>(f->E_nod[d]), p.nx, p.ny, p.nz, d, -1, m,
+                     cf, c->stream);
+  } else if (dir == PIC_S2N && what == PIC_B) {
+    for (int d = 0; d < 3; ++d) {
+      const int a0 = (d == 0) ? 1 : 0;
+      const int a1 = (d == 2) ? 1 : 2;
+      center_axis<T>(static_cast<const T*>(f->B_stag[d]), e.tmp, p.nx, p.ny, p.nz, a0, -1, m, cf, c->stream);
+      center_axis<T>(e.tmp, static_cast<T*>(f->B_nod[d]), p.nx, p.ny, p.nz, a1, -1, m, cf, c->stream);
+    }
+  } else {
+    return c->fail(PIC_EINVAL, "unsupported (dir, what) pair for pic_center");
+  }
+  return c->check("pic_center");
+}
+
+template <typename T>
+pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, int mode) {
+  const pic_params& p = c->p;
+  const size_t N = ncells(p);
+  T* rho = static_cast<T*>(f->rho_new);
+  if (f->rho_static)
+    (void)hipMemcpyAsync(rho, f->rho_static, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+  else
+    (void)hipMemsetAsync(rho, 0, N * sizeof(T), c->stream);
+  const bool with_j = (mode == PIC_DEP_RHO_AND_J);
+  T* J[3] = {static_cast<T*>(f->J_nod[0]), static_cast<T*>(f->J_nod[1]), static_cast<T*>(f->J_nod[2])};
+  if (with_j)
+    for (int d = 0; d < 3; ++d) (void)hipMemsetAsync(J[d], 0, N * sizeof(T), c->stream);
+  const GridGeom g = geom(p);
+  for (int s = 0; s < nsp; ++s) {
+    const bool mobile = std::isfinite(sp[s].m);
+    deposit<T>(g, view<T>(sp[s]), rho, J, with_j && mobile, c->d_bad, c->stream);
+  }
+  return c->check("pic_deposit");
+}
+
+template <typename T>
+pic_status do_gather_push(pic_ctx c, const pic_fields* f, pic_species* sp, int nsp) {
+  const GridGeom g = geom(c->p);
+  const T* E[3] = {static_cast<const T*>(f->E_nod[0]), static_cast<const T*>(f->E_nod[1]),
+                   static_cast<const T*>(f->E_nod[2])};
+  const T* B[3] = {static_cast<const T*>(f->B_nod[0]), static_cast<const T*>(f->B_nod[1]),
+                   static_cast<const T*>(f->B_nod[2])};
+  for (int s = 0; s < nsp; ++s)
+    if (std::isfinite(sp[s].m)) gather_push<T>(g, E, B, view<T>(sp[s]), c->d_bad, c->stream);
+  return c->check("pic_gather_push");
+}
+
+// forward transforms of the state (E, B) and/or sources (J, rho_old, rho_new)
+template <typename T>
+void forward_batch(pic_ctx c, Engine<T>& e, const T* const* src, cplx<T>* const* dst, int count) {
+  Batch<const T*> in{};
+  Batch<cplx<T>*> out{};
+  for (int i = 0; i < count; ++i) {
+    in.p[i] = src[i];
+    out.p[i] = dst[i];
+  }
+  e.fft.forward(in, out, count, c->stream);
+}
+
+template <typename T>
+void update_and_inverse(pic_ctx c, Engine<T>& e, pic_fields* f, int rho_old_slot) {
+  const pic_params& p = c->p;
+  {
+    StageScope sc(c, ST_UPDATE);
+    psatd_update<T>(e.tab, e.Eh, e.Bh, e.Jh, e.rh[rho_old_slot], e.rh[1 - rho_old_slot], p.nx, p.ny, e.fft.nzh,
+                    e.fft.pz, c->stream);
+  }
+  StageScope sc(c, ST_FFT_INV);
+  Batch<const cplx<T>*> in{};
+  Batch<cplx<T>*> scr{};
+  Batch<T*> out{};
+  for (int d = 0; d < 3; ++d) {
+    in.p[d] = e.Eh[d];
+    in.p[3 + d] = e.Bh[d];
+    out.p[d] = static_cast<T*>(f->E_stag[d]);
+    out.p[3 + d] = static_cast<T*>(f->B_stag[d]);
+  }
+  for (int i = 0; i < 6; ++i) scr.p[i] = e.scratch[i];
+  e.fft.inverse(in, scr, out, 6, (T)(1.0 / (double)ncells(p)), c->stream);
+}
+
+template <typename T>
+pic_status do_push_fields(pic_ctx c, pic_fields* f) {
+  Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
+  {
+    StageScope sc(c, ST_FFT_FWD);
+    const T* src[11];
+    cplx<T>* dst[11];
+    for (int d = 0; d < 3; ++d) {
+      src[d] = static_cast<const T*>(f->E_stag[d]);
+      dst[d] = e.Eh[d];
+      src[3 + d] = static_cast<const T*>(f->B_stag[d]);
+      dst[3 + d] = e.Bh[d];
+      src[6 + d] = static_cast<const T*>(f->J_stag[d]);
+      dst[6 + d] = e.Jh[d];
+    }
+    src[9] = static_cast<const T*>(f->rho_old);
+    dst[9] = e.rh[0];
+    src[10] = static_cast<const T*>(f->rho_new);
+    dst[10] = e.rh[1];
+    forward_batch<T>(c, e, src, dst, 11);
+  }
+  update_and_inverse<T>(c, e, f, 0);
+  return c->check("psatd_push_fields");
+}
+
+template <typename T>
+pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nsteps) {
+  Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
+  const pic_params& p = c->p;
+  if (nsteps == 0) return PIC_OK;
+  int slot = 0;  // rh[slot] holds rho^n
+  {
+    StageScope sc(c, ST_ENTRY);
+    const T* src[7];
+    cplx<T>* dst[7];
+    for (int d = 0; d < 3; ++d) {
+      src[d] = static_cast<const T*>(f->E_stag[d]);
+      dst[d] = e.Eh[d];
+      src[3 + d] = static_cast<const T*>(f->B_stag[d]);
+      dst[3 + d] = e.Bh[d];
+    }
+    src[6] = static_cast<const T*>(f->rho_old);
+    dst[6] = e.rh[slot];
+    forward_batch<T>(c, e, src, dst, 7);
+  }
+  pic_status st;
+  for (int n = 0; n < nsteps; ++n) {
+    {
+      StageScope sc(c, ST_S2N);
+      if ((st = do_center<T>(c, PIC_S2N, PIC_E, f)) != PIC_OK) return st;
+      if ((st = do_center<T>(c, PIC_S2N, PIC_B, f)) != PIC_OK) return st;
+    }
+    {
+      StageScope sc(c, ST_PUSH);
+      if ((st = do_gather_push<T>(c, f, sp, nsp)) != PIC_OK) return st;
+    }
+    {
+      StageScope sc(c, ST_DEPOSIT);
+      if ((st = do_deposit<T>(c, sp, nsp, f, PIC_DEP_RHO_AND_J)) != PIC_OK) return st;
+    }
+    {
+      StageScope sc(c, ST_N2S);
+      if ((st = do_center<T>(c, PIC_N2S, PIC_J, f)) != PIC_OK) return st;
+    }
+    {
+      StageScope sc(c, ST_FFT_FWD);
+      const T* src[4] = {static_cast<const T*>(f->J_stag[0]), static_cast<const T*>(f->J_stag[1]),
+                         static_cast<const T*>(f->J_stag[2]), static_cast<const T*>(f->rho_new)};
+      cplx<T>* dst[4] = {e.Jh[0], e.Jh[1], e.Jh[2], e.rh[1 - slot]};
+      forward_batch<T>(c, e, src, dst, 4);
+    }
+    update_and_inverse<T>(c, e, f, slot);
+    slot = 1 - slot;
+    if ((st = c->check("pic_step")) != PIC_OK) return st;
+  }
+  (void)hipMemcpyAsync(f->rho_old, f->rho_new, ncells(p) * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+  return c->check("pic_step");
+}
+
+template <typename T>
+pic_status do_diag(pic_ctx c, const pic_fields* f, double out[2]) {
+  const pic_params& p = c->p;
+  const size_t N = ncells(p);
+  (void)hipMemsetAsync(c->d_acc, 0, 2 * sizeof(double), c->stream);
+  Batch<const T*> a{};
+  for (int d = 0; d < 3; ++d) {
+    a.p[d] = static_cast<const T*>(f->E_stag[d]);
+    a.p[3 + d] = static_cast<const T*>(f->B_stag[d]);
+  }
+  sum_squares<T>(a, 6, (int64_t)N, c->d_acc, c->stream);
+  sum_plain<T>(static_cast<const T*>(f->rho_old), (int64_t)N, c->d_acc + 1, c->stream);
+  double h[2];
+  hipError_t e = hipMemcpyAsync(h, c->d_acc, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return c->fail(PIC_EHIP, std::string("pic_diagnostics: ") + hipGetErrorString(e));
+  const double dV = p.dx * p.dy * p.dz;
+  out[0] = 0.5 * h[0] * dV;
+  out[1] = h[1] * dV;
+  return PIC_OK;
+}
+
+pic_status check_fields(pic_ctx c, const pic_fields* f, bool E_stag, bool B_stag, bool E_nod, bool B_nod, bool J_nod,
+                        bool J_stag, bool rho_old, bool rho_new) {
+  if (!f) return c->fail(PIC_EINVAL, "fields is NULL");
+  pic_status st;
+  for (int d = 0; d < 3; ++d) {
+    if (E_stag && (st = check_ptr(c, f->E_stag[d], "E_stag")) != PIC_OK) return st;
+    if (B_stag && (st = check_ptr(c, f->B_stag[d], "B_stag")) != PIC_OK) return st;
+    if (E_nod && (st = check_ptr(c, f->E_nod[d], "E_nod")) != PIC_OK) return st;
+    if (B_nod && (st = check_ptr(c, f->B_nod[d], "B_nod")) != PIC_OK) return st;
+    if (J_nod && (st = check_ptr(c, f->J_nod[d], "J_nod")) != PIC_OK) return st;
+    if (J_stag && (st = check_ptr(c, f->J_stag[d], "J_stag")) != PIC_OK) return st;
+  }
+  if (rho_old && (st = check_ptr(c, f->rho_old, "rho_old")) != PIC_OK) return st;
+  if (rho_new && (st = check_ptr(c, f->rho_new, "rho_new")) != PIC_OK) return st;
+  if (f->rho_static && !aligned(f->rho_static)) return c->fail(PIC_EINVAL, "rho_static is not 16-byte aligned");
+  return PIC_OK;
+}
+
+pic_status device_ok(pic_ctx c) {
+  if (!c) return PIC_ESTATE;
+  if (!c->eng) return c->fail(PIC_ESTATE, "context has no engine");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device) (void)hipSetDevice(c->device);
+  return PIC_OK;
+}
+
+}  // namespace
+
+#define PIC_DISPATCH(ctx, fn, ...) \
+  ((ctx)->p.dtype == PIC_F32 ? fn<float>(ctx, __VA_ARGS__) : fn<double>(ctx, __VA_ARGS__))
+
+extern "C" {
+
+pic_status pic_init(const pic_params* p, void* hip_stream, pic_ctx* out) {
+  if (!out) {
+    g_init_error = "out is NULL";
+    return PIC_EINVAL;
+  }
+  *out = nullptr;
+  std::string msg;
+  pic_status st = validate_params(p, msg);
+  if (st != PIC_OK) {
+    g_init_error = msg;
+    return st;
+  }
+  auto c = std::make_unique<pic_ctx_s>();
+  c->p = *p;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    g_init_error = "no HIP device";
+    return PIC_EHIP;
+  }
+  const int m = p->center_order / 2;
+  c->ccoef.resize(m);
+  alpha_staggered(m, c->ccoef.data());
+  for (double& a : c->ccoef) a *= 0.5;
+  hipError_t e;
+  if (p->dtype == PIC_F32) {
+    auto eng = std::make_unique<Engine<float>>();
+    e = build_engine<float>(*p, *eng);
+    c->eng = std::move(eng);
+  } else {
+    auto eng = std::make_unique<Engine<double>>();
+    e = build_engine<double>(*p, *eng);
+    c->eng = std::move(eng);
+  }
+  if (e == hipSuccess) e = hipMalloc(&c->d_acc, 2 * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&c->d_bad, sizeof(int));
+  if (e == hipSuccess) e = hipMemset(c->d_bad, 0, sizeof(int));
+  if (e != hipSuccess) {
+    g_init_error = std::string("pic_init: ") + hipGetErrorString(e);
+    (void)hipGetLastError();
+    return (e == hipErrorOutOfMemory) ? PIC_ENOMEM : PIC_EHIP;
+  }
+  *out = c.release();
+  return PIC_OK;
+}
+
+pic_status pic_destroy(pic_ctx ctx) {
+  if (!ctx) return PIC_EINVAL;
+  (void)hipStreamSynchronize(ctx->stream);
+  ctx->collect();
+  for (auto& ev : ctx->pool) {
+    (void)hipEventDestroy(ev.a);
+    (void)hipEventDestroy(ev.b);
+  }
+  if (ctx->d_acc) (void)hipFree(ctx->d_acc);
+  if (ctx->d_bad) (void)hipFree(ctx->d_bad);
+  ctx->eng.reset();
+  delete ctx;
+  return PIC_OK;
+}
+
+pic_status pic_set_stream(pic_ctx ctx, void* hip_stream) {
+  if (!ctx) return PIC_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return PIC_OK;
+}
+
+pic_status pic_deposit(pic_ctx ctx, const pic_species* sp, int nsp, pic_fields* f, int mode) {
+  pic_status st = device_ok(ctx);
+  if (st != PIC_OK) return st;
+  if (mode != PIC_DEP_RHO_AND_J && mode != PIC_DEP_RHO_ONLY) return ctx->fail(PIC_EINVAL, "bad deposit mode");
+  if ((st = check_species(ctx, sp, nsp)) != PIC_OK) return st;
+  if ((st = check_fields(ctx, f, false, false, false, false, mode == PIC_DEP_RHO_AND_J, false, false, true)) != PIC_OK)
+    return st;
+  return PIC_DISPATCH(ctx, do_deposit, sp, nsp, f, mode);
+}
+
+pic_status pic_center(pic_ctx ctx, int dir, int what, pic_fields* f) {
+  pic_status st = device_ok(ctx);
+  if (st != PIC_OK) return st;
+  if (!f) return ctx->fail(PIC_EINVAL, "fields is NULL");
+  if (dir == PIC_N2S && what == PIC_J)
+    st = check_fields(ctx, f, false, false, false, false, true, true, false, false);
+  else if (dir == PIC_S2N && what == PIC_E)
+    st = check_fields(ctx, f, true, false, true, false, false, false, false, false);
+  else if (dir == PIC_S2N && what == PIC_B)
+    st = check_fields(ctx, f, false, true, false, true, false, false, false, false);
+  else
+    return ctx->fail(PIC_EINVAL, "unsupported (dir, what) pair for pic_center");
+  if (st != PIC_OK) return st;
+  return PIC_DISPATCH(ctx, do_center, dir, what, f);
+}
+
+pic_status psatd_push_fields(pic_ctx ctx, pic_fields* f) {
+  pic_status st = device_ok(ctx);
+  if (st != PIC_OK) return st;
+  if ((st = check_fields(ctx, f, true, true, false, false, false, true, true, true)) != PIC_OK) return st;
+  return PIC_DISPATCH(ctx, do_push_fields, f);
+}
+
+pic_status pic_gather_push(pic_ctx ctx, const pic_fields* f, pic_species* sp, int nsp) {
+  pic_status st = device_ok(ctx);
+  if (st != PIC_OK) return st;
+  if ((st = check_species(ctx, sp, nsp)) != PIC_OK) return st;
+  if ((st = check_fields(ctx, f, false, false, true, true, false, false, false, false)) != PIC_OK) return st;
+  return PIC_DISPATCH(ctx, do_gather_push, f, sp, nsp);
+}
+
+pic_status pic_step(pic_ctx ctx, pic_fields* f, pic_species* sp, int nsp, int nsteps) {
+  pic_status st = device_ok(ctx);
+  if (st != PIC_OK) return st;
+  if (nsteps < 0) return ctx->fail(PIC_EINVAL, "nsteps < 0");
+  if ((st = check_species(ctx, sp, nsp)) != PIC_OK) return st;
+  if ((st = check_fields(ctx, f, true, true, true, true, true, true, true, true)) != PIC_OK) return st;
+  return PIC_DISPATCH(ctx, do_step, f, sp, nsp, nsteps);
+}
+
+pic_status pic_sync(pic_ctx ctx) {
+  if (!ctx) return PIC_EINVAL;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipGetLastError();
+  int bad = 0;
+  if (e == hipSuccess) e = hipMemcpy(&bad, ctx->d_bad, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return ctx->fail(PIC_EHIP, std::string("pic_sync: ") + hipGetErrorString(e));
+  if (bad != 0) {
+    (void)hipMemset(ctx->d_bad, 0, sizeof(int));
+    return ctx->fail(PIC_EINVAL, "pic_sync: " + std::to_string(bad) +
+                                     " particle(s) had an out-of-range cell index and were skipped");
+  }
+  return PIC_OK;
+}
+
+pic_status pic_diagnostics(pic_ctx ctx, const pic_fields* f, double out[2]) {
+  pic_status st = device_ok(ctx);
+  if (st != PIC_OK) return st;
+  if (!out) return ctx->fail(PIC_EINVAL, "out is NULL");
+  if ((st = check_fields(ctx, f, true, true, false, false, false, false, true, false)) != PIC_OK) return st;
+  return PIC_DISPATCH(ctx, do_diag, f, out);
+}
+
+pic_status pic_profile(pic_ctx ctx, int enable) {
+  if (!ctx) return PIC_EINVAL;
+  ctx->profiling = enable != 0;
+  return PIC_OK;
+}
+
+pic_status pic_stage_times(pic_ctx ctx, double* ms, int64_t* count, int nstage) {
+  if (!ctx) return PIC_EINVAL;
+  if ((nstage > 0 && (!ms || !count)) || nstage < 0) return ctx->fail(PIC_EINVAL, "bad output arrays");
+  ctx->collect();
+  for (int s = 0; s < nstage && s < kNumStages; ++s) {
+    ms[s] = ctx->stage_ms[s];
+    count[s] = ctx->stage_count[s];
+  }
+  for (int s = 0; s < kNumStages; ++s) {
+    ctx->stage_ms[s] = 0;
+    ctx->stage_count[s] = 0;
+  }
+  return PIC_OK;
+}
+
+const char* pic_stage_name(int s) { return (s >= 0 && s < kNumStages) ? kStageNames[s] : "unknown"; }
+int pic_num_stages(void) { return kNumStages; }
+
+const char* pic_last_error(pic_ctx ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
+
+const char* pic_strerror(pic_status s) {
+  switch (s) {
+    case PIC_OK: return "success";
+    case PIC_EINVAL: return "invalid argument";
+    case PIC_EUNSUPPORTED: return "unsupported configuration";
+    case PIC_EHIP: return "HIP error";
+    case PIC_ENOMEM: return "out of device memory";
+    case PIC_ESTATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,122 @@
+// Finite-order centering between the nodal grid and the Yee grid (Sec. 3,
+// eq. staggered_finite_sum; the staggered-to-nodal form is also App. C).
+//
+//   nodes -> centres:  f_{j+1/2} = sum_{n=1}^{m} alpha^s_{m,n} (f_{j+n} + f_{j+1-n}) / 2
+//   centres -> nodes:  f_j       = sum_{n=1}^{m} alpha^s_{m,n} (f_{j+n-1/2} + f_{j-n+1/2}) / 2
+// With a staggered array holding f_{j+1/2} at index j, both are
+//   out[j] = sum_n c_n (in[j+n+shift] + in[j-n+1+shift]),  c_n = alpha^s_{m,n}/2,
+// with shift = 0 (nodes -> centres) or -1 (centres -> nodes); periodic in j.
+//
+// Strided axes (x, y): one thread per contiguous column element marches over L
+// outputs along the axis with a register window of L + 2m - 1 inputs (each input
+// loaded once per window, loads coalesced across the column index).  Contiguous
+// axis (z): a block stages whole z-lines plus the periodic halo in LDS.
+#include "kernels.h"
+
+namespace pic {
+
+namespace {
+
+template <typename T>
+struct Coef {
+  T c[16];
+};
+
+template <typename T, int M, int L>
+__global__ void __launch_bounds__(256) k_center_strided(const T* __restrict__ in, T* __restrict__ out, Coef<T> cf,
+                                                        int Na, long long sa, int C, long long outer_stride,
+                                                        int shift) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const int j0 = blockIdx.y * L;
+  const size_t base = (size_t)blockIdx.z * outer_stride + c;
+  constexpr int W = L + 2 * M - 1;
+  T w[W];
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    int row = j0 - M + 1 + shift + i;
+    row %= Na;
+    if (row < 0) row += Na;
+    w[i] = in[base + (size_t)row * sa];
+  }
+#pragma unroll
+  for (int q = 0; q < L; ++q) {
+    if (j0 + q < Na) {
+      T acc = 0;
+#pragma unroll
+      for (int n = 1; n <= M; ++n) acc += cf.c[n - 1] * (w[q + n + M - 1] + w[q - n + M]);
+      out[base + (size_t)(j0 + q) * sa] = acc;
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_center_z(const T* __restrict__ in, T* __restrict__ out, Coef<T> cf, int nz,
+                                                  int nlines, int lpb, int m, int shift) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* s = reinterpret_cast<T*>(smem);
+  const int W = nz + 2 * m - 1;
+  const int line0 = blockIdx.x * lpb;
+  const int nl = min(lpb, nlines - line0);
+  for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
+    const int l = e / W, i = e - l * W;
+    int z = i + 1 - m + shift;
+    z %= nz;
+    if (z < 0) z += nz;
+    s[e] = in[(size_t)(line0 + l) * nz + z];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nl * nz; e += blockDim.x) {
+    const int l = e / nz, z = e - l * nz;
+    const T* sl = s + l * W;
+    T acc = 0;
+    for (int n = 1; n <= m; ++n) acc += cf.c[n - 1] * (sl[z + n + m - 1] + sl[z - n + m]);
+    out[(size_t)(line0 + l) * nz + z] = acc;
+  }
+}
+
+template <typename T, int M>
+void launch_strided(const T* in, T* out, const Coef<T>& cf, int Na, long long sa, int C, int O, long long os,
+                    int shift, hipStream_t s) {
+  constexpr int L = (sizeof(T) == 4) ? 16 : 8;
+  dim3 grid((C + 255) / 256, (Na + L - 1) / L, O);
+  hipLaunchKernelGGL((k_center_strided<T, M, L>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift);
+}
+
+template <typename T>
+void dispatch_strided(int m, const T* in, T* out, const Coef<T>& cf, int Na, long long sa, int C, int O,
+                      long long os, int shift, hipStream_t s) {
+  switch (m) {
+#define PIC_CASE(MM) \
+  case MM: launch_strided<T, MM>(in, out, cf, Na, sa, C, O, os, shift, s); break;
+    PIC_CASE(1) PIC_CASE(2) PIC_CASE(3) PIC_CASE(4) PIC_CASE(5) PIC_CASE(6) PIC_CASE(7) PIC_CASE(8)
+    PIC_CASE(9) PIC_CASE(10) PIC_CASE(11) PIC_CASE(12) PIC_CASE(13) PIC_CASE(14) PIC_CASE(15) PIC_CASE(16)
+#undef PIC_CASE
+    default: break;
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void center_axis(const T* in, T* out, int nx, int ny, int nz, int axis, int shift, int m, const double* c,
+                 hipStream_t s) {
+  Coef<T> cf{};
+  for (int n = 0; n < m && n < 16; ++n) cf.c[n] = (T)c[n];
+  if (axis == 0) {
+    dispatch_strided<T>(m, in, out, cf, nx, (long long)ny * nz, ny * nz, 1, 0, shift, s);
+  } else if (axis == 1) {
+    dispatch_strided<T>(m, in, out, cf, ny, nz, nz, nx, (long long)ny * nz, shift, s);
+  } else {
+    const int nlines = nx * ny;
+    const int lpb = nz >= 256 ? 1 : 256 / nz;
+    const size_t lds = (size_t)lpb * (nz + 2 * m - 1) * sizeof(T);
+    hipLaunchKernelGGL((k_center_z<T>), dim3((nlines + lpb - 1) / lpb), dim3(256), lds, s, in, out, cf, nz, nlines,
+                       lpb, m, shift);
+  }
+}
+
+template void center_axis<float>(const float*, float*, int, int, int, int, int, int, const double*, hipStream_t);
+template void center_axis<double>(const double*, double*, int, int, int, int, int, int, const double*, hipStream_t);
+
+}  // namespace pic

@@ -1,0 +1,67 @@
+// Internal declarations shared by the HIP translation units of libpic.
+// Nothing here is part of the public ABI (include/pic.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+
+namespace pic {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+  T x, y;
+};
+
+template <typename T>
+__host__ __device__ inline cplx<T> cmake(T x, T y) { cplx<T> c; c.x = x; c.y = y; return c; }
+template <typename T>
+__host__ __device__ inline cplx<T> cadd(cplx<T> a, cplx<T> b) { return cmake(a.x + b.x, a.y + b.y); }
+template <typename T>
+__host__ __device__ inline cplx<T> csub(cplx<T> a, cplx<T> b) { return cmake(a.x - b.x, a.y - b.y); }
+template <typename T>
+__host__ __device__ inline cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return cmake(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename T>
+__host__ __device__ inline cplx<T> cscale(cplx<T> a, T s) { return cmake(a.x * s, a.y * s); }
+template <typename T>
+__host__ __device__ inline cplx<T> cconj(cplx<T> a) { return cmake(a.x, -a.y); }
+// multiply by -i (sign < 0) or +i (sign > 0)
+template <typename T, int SIGN>
+__host__ __device__ inline cplx<T> cmul_i(cplx<T> a) {
+  return SIGN > 0 ? cmake(-a.y, a.x) : cmake(a.y, -a.x);
+}
+
+constexpr int kMaxStages = 12;
+constexpr int kMaxBatch = 12;
+
+// One axis of the mixed-radix Stockham FFT.  Stage s has radix radix[s]; ns[s] is
+// the product of the radices of the stages before it; the twiddles of stage s,
+// exp(-2 pi i k r / (ns R)) for k < ns and 1 <= r < R, start at twoff[s] of the
+// table (entry k*(R-1) + r-1).
+struct FftPlan {
+  int n;
+  int nstages;
+  int radix[kMaxStages];
+  int ns[kMaxStages];
+  int twoff[kMaxStages];
+  int twcount;
+};
+
+FftPlan make_fft_plan(int n);
+// FP64 twiddles of a plan, 2*twcount doubles (re, im) of exp(-2 pi i k r/(ns R)).
+void fft_twiddles(const FftPlan& p, double* out);
+
+// Pointer batches passed to kernels by value.
+template <typename P>
+struct Batch {
+  P p[kMaxBatch];
+};
+
+// Host FP64 tables (tables.cpp).
+void alpha_staggered(int m, double* out);                  // out[n-1], n = 1..m
+void k_staggered_axis(int n, double d, int order, double* out);  // [k]_s on fftfreq order
+void psatd_coefficients(double w, double dt, double* C, double* S_over_w, double* X1, double* X2, double* X3);
+
+}  // namespace pic

@@ -1,0 +1,333 @@
+// LDS-staged mixed-radix Stockham FFT for gfx950 (radices 2, 3, 4, 8).
+//
+// The paper's field solve transforms every grid quantity to Fourier space and
+// back (Sec. 2, "solve Maxwell's equations on the Yee grid in Fourier space";
+// discrete transform of App. A).  The staggered half-cell phase factors are not
+// applied here: they are folded into the per-mode update (psatd.hip), so these
+// kernels compute the plain index-space DFT.
+//
+// A real 3D transform runs three passes, each one read and one write of the
+// array in HBM:
+//   z pass  (r2c/c2r): two real z-lines packed as one complex line, one
+//           workgroup per group of line pairs, lines contiguous in LDS;
+//   y, x    (c2c):     a tile of TL lines that are adjacent in memory (the kz
+//           index, or the flattened (ky,kz) index for x), so every global
+//           access is a TL-wide contiguous row; in LDS the tile is stored
+//           element-major with the line index fastest, which keeps the
+//           butterfly reads and writes free of bank conflicts.
+// Each Stockham stage reads its radix-R butterfly inputs from one LDS buffer and
+// writes the outputs in autosorted order to the other buffer.
+#include "kernels.h"
+
+namespace pic {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+template <typename T, int SIGN>
+__device__ inline void dft2(cplx<T>* v) {
+  cplx<T> a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <typename T, int SIGN>
+__device__ inline void dft3(cplx<T>* v) {
+  // X1 = v0 - (v1+v2)/2 + SIGN i (sqrt3/2)(v1 - v2), X2 = conjugate combination.
+  const T h = (T)0.86602540378443864676372317075294;
+  cplx<T> t = cadd(v[1], v[2]);
+  cplx<T> d = csub(v[1], v[2]);
+  cplx<T> m = cmake(v[0].x - (T)0.5 * t.x, v[0].y - (T)0.5 * t.y);
+  cplx<T> r = cscale(cmul_i<T, SIGN>(d), h);
+  v[0] = cadd(v[0], t);
+  v[1] = cadd(m, r);
+  v[2] = csub(m, r);
+}
+
+template <typename T, int SIGN>
+__device__ inline void dft4(cplx<T>* v) {
+  cplx<T> t0 = cadd(v[0], v[2]);
+  cplx<T> t1 = csub(v[0], v[2]);
+  cplx<T> t2 = cadd(v[1], v[3]);
+  cplx<T> t3 = cmul_i<T, SIGN>(csub(v[1], v[3]));
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+template <typename T, int SIGN>
+__device__ inline void dft8(cplx<T>* v) {
+  const T s = (T)0.70710678118654752440084436210485;
+  cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
+  cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<T, SIGN>(e);
+  dft4<T, SIGN>(o);
+  // twiddles w^k = exp(SIGN i 2 pi k / 8), k = 0..3
+  cplx<T> o1 = cmake(s * (o[1].x - (T)SIGN * o[1].y), s * (o[1].y + (T)SIGN * o[1].x));
+  cplx<T> o2 = cmul_i<T, SIGN>(o[2]);
+  cplx<T> o3 = cmake(s * (-o[3].x - (T)SIGN * o[3].y), s * (-o[3].y + (T)SIGN * o[3].x));
+  v[0] = cadd(e[0], o[0]);
+  v[4] = csub(e[0], o[0]);
+  v[1] = cadd(e[1], o1);
+  v[5] = csub(e[1], o1);
+  v[2] = cadd(e[2], o2);
+  v[6] = csub(e[2], o2);
+  v[3] = cadd(e[3], o3);
+  v[7] = csub(e[3], o3);
+}
+
+template <typename T, int SIGN, int R>
+__device__ inline void dft(cplx<T>* v) {
+  if constexpr (R == 2) dft2<T, SIGN>(v);
+  else if constexpr (R == 3) dft3<T, SIGN>(v);
+  else if constexpr (R == 4) dft4<T, SIGN>(v);
+  else dft8<T, SIGN>(v);
+}
+
+// One butterfly of a Stockham stage: reads src[(b + r*nb)] and writes dst[j0 + r*ns].
+template <typename T, int SIGN, int R>
+__device__ inline void butterfly(const cplx<T>* __restrict__ src, cplx<T>* __restrict__ dst, int lbase, int js,
+                                 int b, int nb, int ns, const cplx<T>* __restrict__ tw) {
+  cplx<T> v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = src[lbase + (b + r * nb) * js];
+  const int k = b % ns;
+  if (ns > 1) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      cplx<T> w = tw[k * (R - 1) + r - 1];
+      if (SIGN > 0) w.y = -w.y;
+      v[r] = cmul(v[r], w);
+    }
+  }
+  dft<T, SIGN, R>(v);
+  const int j0 = (b / ns) * ns * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[lbase + (j0 + r * ns) * js] = v[r];
+}
+
+// Transforms ``nlines`` lines held in LDS buffer a (element (l, j) at l*ls + j*js),
+// using b as the second buffer.  Returns the buffer holding the result.
+template <typename T, int SIGN>
+__device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nlines, int ls, int js, const FftPlan& p,
+                            const cplx<T>* __restrict__ tw, bool line_fastest) {
+  const int N = p.n;
+  for (int s = 0; s < p.nstages; ++s) {
+    const int R = p.radix[s], ns = p.ns[s];
+    const int nb = N / R;
+    const int total = nlines * nb;
+    const cplx<T>* tws = tw + p.twoff[s];
+    for (int w = threadIdx.x; w < total; w += blockDim.x) {
+      int l, bi;
+      if (line_fastest) { l = w % nlines; bi = w / nlines; }
+      else { bi = w % nb; l = w / nb; }
+      const int lbase = l * ls;
+      switch (R) {
+        case 2: butterfly<T, SIGN, 2>(a, b, lbase, js, bi, nb, ns, tws); break;
+        case 3: butterfly<T, SIGN, 3>(a, b, lbase, js, bi, nb, ns, tws); break;
+        case 4: butterfly<T, SIGN, 4>(a, b, lbase, js, bi, nb, ns, tws); break;
+        default: butterfly<T, SIGN, 8>(a, b, lbase, js, bi, nb, ns, tws); break;
+      }
+    }
+    __syncthreads();
+    cplx<T>* t = a; a = b; b = t;
+  }
+  return a;
+}
+
+// z pass, real -> half spectrum.  Block = P line pairs of one array (blockIdx.y).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_r2c_z(Batch<const T*> in, Batch<cplx<T>*> out, FftPlan p,
+                                                  const cplx<T>* __restrict__ tw, int nlines, int pz, int P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int N = p.n;
+  cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* b = a + (size_t)P * N;
+  const T* __restrict__ src = in.p[blockIdx.y];
+  cplx<T>* __restrict__ dst = out.p[blockIdx.y];
+  const int pair0 = blockIdx.x * P;
+  const int np = min(P, nlines / 2 - pair0);
+  for (int e = threadIdx.x; e < np * N; e += blockDim.x) {
+    const int q = e / N, j = e - q * N;
+    const size_t l = 2 * (size_t)(pair0 + q);
+    a[q * N + j] = cmake(src[l * N + j], src[(l + 1) * N + j]);
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lds<T, -1>(a, b, np, N, 1, p, tw, false);
+  const int nh = N / 2 + 1;
+  for (int e = threadIdx.x; e < np * nh; e += blockDim.x) {
+    const int q = e / nh, k = e - q * nh;
+    const cplx<T> zk = res[q * N + k];
+    const cplx<T> zn = res[q * N + (k == 0 ? 0 : N - k)];
+    const cplx<T> F = cmake((T)0.5 * (zk.x + zn.x), (T)0.5 * (zk.y - zn.y));
+    const cplx<T> G = cmake((T)0.5 * (zk.y + zn.y), (T)0.5 * (zn.x - zk.x));
+    const size_t l = 2 * (size_t)(pair0 + q);
+    dst[l * pz + k] = F;
+    dst[(l + 1) * pz + k] = G;
+  }
+}
+
+// z pass, half spectrum -> real (scaled).  The imaginary parts of the kz = 0 and
+// kz = nz/2 bins are dropped (real-output convention).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_c2r_z(Batch<const cplx<T>*> in, Batch<T*> out, FftPlan p,
+                                                  const cplx<T>* __restrict__ tw, int nlines, int pz, int P, T scale) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int N = p.n;
+  cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* b = a + (size_t)P * N;
+  const cplx<T>* __restrict__ src = in.p[blockIdx.y];
+  T* __restrict__ dst = out.p[blockIdx.y];
+  const int pair0 = blockIdx.x * P;
+  const int np = min(P, nlines / 2 - pair0);
+  const int half = N / 2;
+  for (int e = threadIdx.x; e < np * N; e += blockDim.x) {
+    const int q = e / N, k = e - q * N;
+    const size_t l = 2 * (size_t)(pair0 + q);
+    cplx<T> F, G;
+    if (k <= half) {
+      F = src[l * pz + k];
+      G = src[(l + 1) * pz + k];
+      if (k == 0 || k == half) { F.y = 0; G.y = 0; }
+    } else {
+      F = cconj(src[l * pz + (N - k)]);
+      G = cconj(src[(l + 1) * pz + (N - k)]);
+    }
+    a[q * N + k] = cmake(F.x - G.y, F.y + G.x);
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lds<T, +1>(a, b, np, N, 1, p, tw, false);
+  for (int e = threadIdx.x; e < np * N; e += blockDim.x) {
+    const int q = e / N, j = e - q * N;
+    const size_t l = 2 * (size_t)(pair0 + q);
+    const cplx<T> v = res[q * N + j];
+    dst[l * N + j] = v.x * scale;
+    dst[(l + 1) * N + j] = v.y * scale;
+  }
+}
+
+// y or x pass, complex -> complex along a strided axis, TL adjacent lines per block.
+template <typename T, int SIGN>
+__global__ void __launch_bounds__(kBlock) k_fft_strided(Batch<const cplx<T>*> in, Batch<cplx<T>*> out, FftPlan p,
+                                                        const cplx<T>* __restrict__ tw, int TL, int inner_count,
+                                                        int tiles_per_outer, long long outer_stride,
+                                                        long long elem_stride) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int N = p.n;
+  cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* b = a + (size_t)TL * N;
+  const cplx<T>* __restrict__ src = in.p[blockIdx.y];
+  cplx<T>* __restrict__ dst = out.p[blockIdx.y];
+  const int tile = blockIdx.x;
+  const int outer = tile / tiles_per_outer;
+  const int inner0 = (tile - outer * tiles_per_outer) * TL;
+  const int nl = min(TL, inner_count - inner0);
+  const size_t base = (size_t)outer * outer_stride + inner0;
+  for (int e = threadIdx.x; e < N * TL; e += blockDim.x) {
+    const int j = e / TL, i = e - j * TL;
+    a[e] = (i < nl) ? src[base + i + (size_t)j * elem_stride] : cmake((T)0, (T)0);
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lds<T, SIGN>(a, b, TL, 1, TL, p, tw, true);
+  for (int e = threadIdx.x; e < N * TL; e += blockDim.x) {
+    const int j = e / TL, i = e - j * TL;
+    if (i < nl) dst[base + i + (size_t)j * elem_stride] = res[e];
+  }
+}
+
+constexpr size_t kLdsBudget = 65536;
+
+template <typename T>
+int pairs_per_block(int n) {
+  int P = 2048 / n;
+  if (P < 1) P = 1;
+  while (P > 1 && 2 * (size_t)P * n * sizeof(cplx<T>) > kLdsBudget) P /= 2;
+  return P;
+}
+
+template <typename T>
+int lines_per_tile(int n) {
+  int TL = 16;
+  while (TL > 1 && 2 * (size_t)TL * n * sizeof(cplx<T>) > kLdsBudget) TL /= 2;
+  return TL;
+}
+
+template <typename T, int SIGN>
+void strided_pass(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& out, int count, const FftPlan& p,
+                  const cplx<T>* tw, int outer_count, int inner_count, long long outer_stride, long long elem_stride,
+                  hipStream_t s) {
+  const int TL = lines_per_tile<T>(p.n);
+  const int tpo = (inner_count + TL - 1) / TL;
+  dim3 grid(outer_count * tpo, count);
+  const size_t lds = 2 * (size_t)TL * p.n * sizeof(cplx<T>);
+  hipLaunchKernelGGL((k_fft_strided<T, SIGN>), grid, dim3(kBlock), lds, s, in, out, p, tw, TL, inner_count, tpo,
+                     outer_stride, elem_stride);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t Fft3D<T>::init(int nx_, int ny_, int nz_) {
+  nx = nx_; ny = ny_; nz = nz_;
+  nzh = nz / 2 + 1;
+  const int align = (int)(128 / sizeof(cplx<T>));
+  pz = (nzh + align - 1) / align * align;
+  const int n[3] = {nx, ny, nz};
+  for (int d = 0; d < 3; ++d) {
+    plan[d] = make_fft_plan(n[d]);
+    if (plan[d].nstages < 0) return hipErrorInvalidValue;
+    const int cnt = plan[d].twcount > 0 ? plan[d].twcount : 1;
+    double* h = new double[2 * (size_t)cnt]();
+    fft_twiddles(plan[d], h);
+    cplx<T>* hc = new cplx<T>[cnt];
+    for (int i = 0; i < cnt; ++i) hc[i] = cmake((T)h[2 * i], (T)h[2 * i + 1]);
+    hipError_t e = hipMalloc(&tw[d], cnt * sizeof(cplx<T>));
+    if (e == hipSuccess) e = hipMemcpy(tw[d], hc, cnt * sizeof(cplx<T>), hipMemcpyHostToDevice);
+    delete[] h;
+    delete[] hc;
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+void Fft3D<T>::release() {
+  for (int d = 0; d < 3; ++d) {
+    if (tw[d]) (void)hipFree(tw[d]);
+    tw[d] = nullptr;
+  }
+}
+
+template <typename T>
+void Fft3D<T>::forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, int count, hipStream_t s) const {
+  const int nlines = nx * ny;
+  const int P = pairs_per_block<T>(nz);
+  dim3 grid((nlines / 2 + P - 1) / P, count);
+  hipLaunchKernelGGL((k_r2c_z<T>), grid, dim3(kBlock), 2 * (size_t)P * nz * sizeof(cplx<T>), s, in, out, plan[2],
+                     tw[2], nlines, pz, P);
+  Batch<const cplx<T>*> cin;
+  for (int i = 0; i < count; ++i) cin.p[i] = out.p[i];
+  strided_pass<T, -1>(cin, out, count, plan[1], tw[1], nx, nzh, (long long)ny * pz, pz, s);
+  strided_pass<T, -1>(cin, out, count, plan[0], tw[0], 1, ny * pz, 0, (long long)ny * pz, s);
+}
+
+template <typename T>
+void Fft3D<T>::inverse(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& scratch, const Batch<T*>& out,
+                       int count, T scale, hipStream_t s) const {
+  strided_pass<T, +1>(in, scratch, count, plan[0], tw[0], 1, ny * pz, 0, (long long)ny * pz, s);
+  Batch<const cplx<T>*> cs;
+  for (int i = 0; i < count; ++i) cs.p[i] = scratch.p[i];
+  strided_pass<T, +1>(cs, scratch, count, plan[1], tw[1], nx, nzh, (long long)ny * pz, pz, s);
+  const int nlines = nx * ny;
+  const int P = pairs_per_block<T>(nz);
+  dim3 grid((nlines / 2 + P - 1) / P, count);
+  hipLaunchKernelGGL((k_c2r_z<T>), grid, dim3(kBlock), 2 * (size_t)P * nz * sizeof(cplx<T>), s, cs, out, plan[2],
+                     tw[2], nlines, pz, P, scale);
+}
+
+template struct Fft3D<float>;
+template struct Fft3D<double>;
+
+}  // namespace pic

@@ -1,0 +1,83 @@
+// Host-side launchers of the HIP kernels (internal to libpic).
+#pragma once
+
+#include "common.h"
+
+namespace pic {
+
+// ---------------------------------------------------------------- FFT (fft.hip)
+// Real 3D transforms of (nx, ny, nz) arrays, z contiguous.  The half spectrum is
+// stored (nx, ny, pz) with kz contiguous, kz < nz/2+1 used, pz >= nz/2+1 the row
+// pitch.  Forward: X[k] = sum_j x[j] exp(-2 pi i j.k / n) per axis (unnormalised).
+template <typename T>
+struct Fft3D {
+  int nx = 0, ny = 0, nz = 0, nzh = 0, pz = 0;
+  FftPlan plan[3];
+  cplx<T>* tw[3] = {nullptr, nullptr, nullptr};
+  hipError_t init(int nx, int ny, int nz);   // builds plans, uploads twiddles
+  void release();
+  size_t spectrum_elems() const { return (size_t)nx * ny * pz; }
+  // count <= kMaxBatch arrays, real -> spectrum
+  void forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, int count, hipStream_t s) const;
+  // spectrum -> real; ``scratch`` receives the partially transformed spectra (``in`` is preserved);
+  // the result is scaled by ``scale``.
+  void inverse(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& scratch, const Batch<T*>& out, int count,
+               T scale, hipStream_t s) const;
+};
+
+// ---------------------------------------------------------------- centering (centering.hip)
+// out = centering of in along ``axis`` at order 2m with coefficients c[n-1] = alpha^s_{m,n}/2.
+// shift = 0: nodes -> cell centres; shift = -1: cell centres -> nodes.
+template <typename T>
+void center_axis(const T* in, T* out, int nx, int ny, int nz, int axis, int shift, int m, const double* c,
+                 hipStream_t s);
+
+// ---------------------------------------------------------------- PSATD update (psatd.hip)
+template <typename T>
+struct PsatdTables {
+  T* C = nullptr;        // [nx*ny*nzh] each
+  T* Sw = nullptr;
+  T* X1 = nullptr;
+  T* X2 = nullptr;
+  T* X3 = nullptr;
+  cplx<T>* Dp[3] = {nullptr, nullptr, nullptr};  // i [k_d]_s exp(+i k_d d_d / 2), per axis (z: nzh entries)
+  cplx<T>* Dm[3] = {nullptr, nullptr, nullptr};  // i [k_d]_s exp(-i k_d d_d / 2)
+};
+template <typename T>
+void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B[3], const cplx<T>* const J[3],
+                  const cplx<T>* rho_old, const cplx<T>* rho_new, int nx, int ny, int nzh, int pz, hipStream_t s);
+
+// ---------------------------------------------------------------- particles (particles.hip)
+struct GridGeom {
+  int nx, ny, nz;
+  double dx, dy, dz, dt;
+  int shape_order;
+};
+template <typename T>
+struct SpeciesView {
+  int64_t n;
+  int32_t* cell;
+  T* off[3];
+  T* u[3];
+  T* w;         // may be null
+  double w_const, q, m;
+};
+template <typename T>
+void gather_push(const GridGeom& g, const T* const E[3], const T* const B[3], const SpeciesView<T>& sp, int* bad,
+                 hipStream_t s);
+// adds this species' rho (at x) and, when with_j, J (at x - dt v/2) to the nodal arrays.
+// Particles with an out-of-range cell index are skipped and counted in *bad.
+template <typename T>
+void deposit(const GridGeom& g, const SpeciesView<T>& sp, T* rho, T* const J[3], bool with_j, int* bad,
+             hipStream_t s);
+
+// ---------------------------------------------------------------- reductions (diag.hip)
+// acc[0] += sum of squares over ``count`` arrays of n elements; acc[1] += sum of ``sum_arr``.
+template <typename T>
+void sum_squares(const Batch<const T*>& arrs, int count, int64_t n, double* acc, hipStream_t s);
+template <typename T>
+void sum_plain(const T* arr, int64_t n, double* acc, hipStream_t s);
+template <typename T>
+void add_into(T* dst, const T* src, int64_t n, hipStream_t s);
+
+}  // namespace pic

@@ -1,0 +1,90 @@
+// Per-mode standard PSATD update on the staggered grid (Sec. 4.2, eqs.
+// eq_update_B_with_rho_standard and eq_update_E_with_rho_standard), c = eps0 = 1:
+//   B' = C B - i (S/w) [k]_s x E + i X1 [k]_s x J
+//   E' = C E + i (S/w) [k]_s x B + X4 J + i (X3 rho^n - X2 rho^{n+1}) [k]_s,   X4 = -S/w.
+// The paper states the update in the Fourier convention of App. A, where every
+// component is transformed at its own Yee position.  The spectra handled here are
+// plain index-space DFTs; multiplying the paper's equations through by the
+// components' half-cell phase factors turns each i[k^d]_s into
+//   D+_d = i [k^d]_s exp(+i k^d dx_d / 2)   (derivative from nodes to centres, App. A
+//                                            eq. staggered_finite_difference_nodal),
+//   D-_d = i [k^d]_s exp(-i k^d dx_d / 2)   (centres to nodes, the inverse shift),
+// so the update needs no extra phase:
+//   bx' = C bx - Sw (D+y ez - D+z ey) + X1 (D+y jz - D+z jy)            (and cyclic)
+//   ex' = C ex + Sw (D-y bz - D-z by) - Sw jx + (X3 ro - X2 rn) D+x      (and cyclic)
+// One thread per half-spectrum mode; every array is read and written once.
+#include "kernels.h"
+
+namespace pic {
+
+namespace {
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cplx<T>*> F, Batch<const cplx<T>*> S,
+                                                      int nx, int ny, int nzh, int pz) {
+  const long long total = (long long)nx * ny * nzh;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int kz = (int)(idx % nzh);
+  const long long r = idx / nzh;
+  const int j = (int)(r % ny);
+  const int i = (int)(r / ny);
+  const size_t a = (size_t)r * pz + kz;
+
+  const T C = t.C[idx], Sw = t.Sw[idx], X1 = t.X1[idx], X2 = t.X2[idx], X3 = t.X3[idx];
+  const cplx<T> px = t.Dp[0][i], py = t.Dp[1][j], pzd = t.Dp[2][kz];
+  const cplx<T> mx = t.Dm[0][i], my = t.Dm[1][j], mz = t.Dm[2][kz];
+
+  const cplx<T> ex = F.p[0][a], ey = F.p[1][a], ez = F.p[2][a];
+  const cplx<T> bx = F.p[3][a], by = F.p[4][a], bz = F.p[5][a];
+  const cplx<T> jx = S.p[0][a], jy = S.p[1][a], jz = S.p[2][a];
+  const cplx<T> ro = S.p[3][a], rn = S.p[4][a];
+
+  // B update: curl terms with D+ (E, J live on edges; B on faces)
+  const cplx<T> cEx = csub(cmul(py, ez), cmul(pzd, ey));
+  const cplx<T> cEy = csub(cmul(pzd, ex), cmul(px, ez));
+  const cplx<T> cEz = csub(cmul(px, ey), cmul(py, ex));
+  const cplx<T> cJx = csub(cmul(py, jz), cmul(pzd, jy));
+  const cplx<T> cJy = csub(cmul(pzd, jx), cmul(px, jz));
+  const cplx<T> cJz = csub(cmul(px, jy), cmul(py, jx));
+  F.p[3][a] = cadd(csub(cscale(bx, C), cscale(cEx, Sw)), cscale(cJx, X1));
+  F.p[4][a] = cadd(csub(cscale(by, C), cscale(cEy, Sw)), cscale(cJy, X1));
+  F.p[5][a] = cadd(csub(cscale(bz, C), cscale(cEz, Sw)), cscale(cJz, X1));
+
+  // E update: curl of B with D-, source terms
+  const cplx<T> cBx = csub(cmul(my, bz), cmul(mz, by));
+  const cplx<T> cBy = csub(cmul(mz, bx), cmul(mx, bz));
+  const cplx<T> cBz = csub(cmul(mx, by), cmul(my, bx));
+  const cplx<T> rr = csub(cscale(ro, X3), cscale(rn, X2));
+  F.p[0][a] = cadd(csub(cadd(cscale(ex, C), cscale(cBx, Sw)), cscale(jx, Sw)), cmul(rr, px));
+  F.p[1][a] = cadd(csub(cadd(cscale(ey, C), cscale(cBy, Sw)), cscale(jy, Sw)), cmul(rr, py));
+  F.p[2][a] = cadd(csub(cadd(cscale(ez, C), cscale(cBz, Sw)), cscale(jz, Sw)), cmul(rr, pzd));
+}
+
+}  // namespace
+
+template <typename T>
+void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B[3], const cplx<T>* const J[3],
+                  const cplx<T>* rho_old, const cplx<T>* rho_new, int nx, int ny, int nzh, int pz, hipStream_t s) {
+  Batch<cplx<T>*> F{};
+  Batch<const cplx<T>*> S{};
+  for (int d = 0; d < 3; ++d) {
+    F.p[d] = E[d];
+    F.p[3 + d] = B[d];
+    S.p[d] = J[d];
+  }
+  S.p[3] = rho_old;
+  S.p[4] = rho_new;
+  const long long total = (long long)nx * ny * nzh;
+  hipLaunchKernelGGL((k_psatd_update<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, t, F, S, nx, ny, nzh,
+                     pz);
+}
+
+template void psatd_update<float>(const PsatdTables<float>&, cplx<float>* const*, cplx<float>* const*,
+                                  const cplx<float>* const*, const cplx<float>*, const cplx<float>*, int, int, int,
+                                  int, hipStream_t);
+template void psatd_update<double>(const PsatdTables<double>&, cplx<double>* const*, cplx<double>* const*,
+                                   const cplx<double>* const*, const cplx<double>*, const cplx<double>*, int, int,
+                                   int, int, hipStream_t);
+
+}  // namespace pic

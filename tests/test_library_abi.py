@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports every entry point of include/pic.h; host-side
+validation rejects bad parameters before any device work (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2106_12919_amd import lib as piclib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "pic.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:pic|psatd)_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("pic_init", "pic_deposit", "pic_center", "psatd_push_fields", "pic_gather_push", "pic_step"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported():
+    lib = piclib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert ctypes.cast(getattr(lib, name), ctypes.c_void_p).value
+
+
+def test_strerror_and_stage_names():
+    lib = piclib.load()
+    assert lib.pic_strerror(0).decode() == "success"
+    assert lib.pic_num_stages() >= 7
+    names = [lib.pic_stage_name(i).decode() for i in range(lib.pic_num_stages())]
+    assert "psatd_update" in names and "fft_forward" in names
+
+
+def good_params(**kw):
+    p = dict(shape=(16, 16, 16), spacing=(1.0, 1.0, 1.0), dt=0.5, shape_order=1, center_order=4,
+             psatd_order=16, dtype="f32")
+    p.update(kw)
+    return piclib.make_params(**p)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(shape=(16, 16, 20)), piclib.PIC_EUNSUPPORTED),        # 20 = 2^2 * 5
+    (dict(shape=(16, 16, 9)), piclib.PIC_EUNSUPPORTED),         # odd
+    (dict(shape=(4, 16, 16)), piclib.PIC_EUNSUPPORTED),         # too small
+    (dict(shape=(2048, 16, 16)), piclib.PIC_EUNSUPPORTED),      # too large
+    (dict(dt=1.5), piclib.PIC_EINVAL),                          # particles could cross > 1 cell
+    (dict(dt=0.0), piclib.PIC_EINVAL),
+    (dict(spacing=(1.0, -1.0, 1.0)), piclib.PIC_EINVAL),
+    (dict(shape_order=2), piclib.PIC_EUNSUPPORTED),
+    (dict(center_order=3), piclib.PIC_EUNSUPPORTED),
+    (dict(center_order=34), piclib.PIC_EUNSUPPORTED),
+    (dict(center_order=0), piclib.PIC_EUNSUPPORTED),
+    (dict(psatd_order=7), piclib.PIC_EUNSUPPORTED),
+    (dict(psatd_order=66), piclib.PIC_EUNSUPPORTED),
+])
+def test_init_rejects_bad_params(kw, code):
+    lib = piclib.load()
+    p = good_params(**kw)
+    ctx = ctypes.c_void_p()
+    st = lib.pic_init(ctypes.byref(p), None, ctypes.byref(ctx))
+    assert st == code
+    assert ctx.value is None
+    assert lib.pic_last_error(None).decode()
+
+
+def test_init_rejects_flags_and_dtype():
+    lib = piclib.load()
+    p = good_params()
+    p.flags = 1
+    ctx = ctypes.c_void_p()
+    assert lib.pic_init(ctypes.byref(p), None, ctypes.byref(ctx)) == piclib.PIC_EINVAL
+    p = good_params()
+    p.dtype = 7
+    assert lib.pic_init(ctypes.byref(p), None, ctypes.byref(ctx)) == piclib.PIC_EINVAL
+    assert lib.pic_init(None, None, ctypes.byref(ctx)) == piclib.PIC_EINVAL
+
+
+def test_null_context_is_rejected():
+    lib = piclib.load()
+    assert lib.pic_sync(None) == piclib.PIC_EINVAL
+    assert lib.pic_destroy(None) == piclib.PIC_EINVAL
+    f = piclib.pic_fields()
+    assert lib.pic_center(None, 0, 0, ctypes.byref(f)) == piclib.PIC_ESTATE
