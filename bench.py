@@ -1,0 +1,197 @@
+#!/usr/bin/env python
+"""Throughput of the hybrid nodal-staggered PSATD PIC step on one MI355X.
+
+Workload (default): 128x128x256 periodic grid, Gaussian laser (wavelength 16
+cells, a0 = 2, waist 20, FWHM duration 30, x-polarised, +z) entering a cold
+electron plasma at 2 particles/cell for z >= 64 (6,291,456 macro-particles),
+immobile ions as a static background, cubic B-spline shape, centering order 16,
+PSATD order 16, c*dt = 0.5 cell, float32 fields and particles (FP64-built
+tables).  Synthetic and seeded (paper_2106_12919_amd.inputs).
+
+One "step" is one full hybrid cycle: staggered-to-nodal centering of E, B ->
+gather + Boris push -> deposition of rho, J -> nodal-to-staggered centering of
+J -> forward FFTs of J, rho -> per-mode PSATD update -> inverse FFTs of E, B.
+The timed region is a single pic_step call of K steps with every input
+resident in HBM (E, B stay in Fourier space between steps; the call's entry
+transforms are inside the timed region).
+
+Prints one JSON line.  Rates: particle-pushes/s = Np*K/T (``value``) and grid
+cell updates/s = N*K/T.  ``roofline`` is the dominant stage's algorithmic bytes
+per launch over its mean duration, timed with HIP events on the stream the
+library launches on.  ``cpu_baseline`` times the FP64 NumPy oracle on the host
+on a bounded sample (the full grid part of one step plus 1/8 of the particles;
+the particle part is scaled by 8, it is linear in the particle count).
+"""
+
+import argparse
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+CONFIG_TEXT = {
+    "laser128": "laser128: 128x128x256 periodic, laser a0=2 lambda=16 waist=20 fwhm=30 into 2 ppc cold plasma "
+                "(z>=64), cubic shape, centering order 16, PSATD order 16, c*dt=0.5",
+    "laser64": "laser64: 64x64x128 periodic, laser a0=1 lambda=16 waist=12 fwhm=30 into 4 ppc cold plasma, "
+               "cubic shape, centering order 8, PSATD order 16, c*dt=0.5",
+    "thermal32": "thermal32: 32^3 periodic thermal plasma 8 ppc u_th=0.01, CIC, centering order 8, PSATD order 16",
+    "thermal256": "thermal256: 256^3 periodic thermal plasma 8 ppc u_th=0.05, CIC, PSATD order 16",
+}
+
+
+def stage_bytes(stage, N, M, Np, s):
+    """Algorithmic (compulsory) HBM bytes of one launch of a pic_step stage.
+
+    N cells, M = nx*ny*(nz/2+1) half-spectrum modes, Np particles, s = sizeof(real)."""
+    part_rw = 2 * (4 + 6 * s)          # cell + 3 offsets + 3 momenta, read and written
+    part_r = 4 + 7 * s                 # cell, offsets, momenta, weight, read
+    return {
+        "center_s2n": 12 * N * s,      # 6 staggered components in, 6 nodal out
+        "gather_push": 6 * N * s + Np * part_rw,
+        "deposit": 4 * N * s + Np * part_r,
+        "center_n2s": 6 * N * s,       # 3 in, 3 out
+        "fft_forward": 4 * (N * s + M * 2 * s),          # J (3) and rho: real in, half spectrum out
+        "psatd_update": M * (11 * 2 * s + 5 * s + 6 * 2 * s),  # 11 spectra + 5 tables in, 6 out
+        "fft_inverse": 6 * (M * 2 * s + N * s),          # E, B: half spectrum in, real out
+        "entry_forward": 7 * (N * s + M * 2 * s),
+        "tile_sort": Np * 12,          # cell read twice (count, rank), slot written
+    }[stage]
+
+
+def cpu_baseline(wl, Np):
+    """FP64 oracle on the host: grid part of one step + 1/8 of the particles, particle part scaled by 8."""
+    import numpy as np
+
+    from oracle import step as ostep
+
+    p = ostep.Params(wl.shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order)
+    frac = 8
+    sel = slice(0, wl.electrons.n // frac)
+    sp = {"pos": wl.electrons.positions(wl.spacing)[sel], "u": wl.electrons.u[sel].copy(),
+          "w": wl.electrons.w[sel], "q": wl.electrons.q, "m": wl.electrons.m}
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    t0 = time.perf_counter()
+    E_nod, B_nod = ostep.center_fields_s2n(wl.E, wl.B, p)
+    t1 = time.perf_counter()
+    v, pos_half = ostep.gather_push(sp, E_nod, B_nod, p)
+    rho_new = ostep.deposit_rho([sp], p)
+    J_nod = ostep.deposit_current(sp, v, pos_half, p)
+    t2 = time.perf_counter()
+    J_stag = ostep.center_current_n2s(J_nod, p)
+    ostep.push_fields(wl.E, wl.B, J_stag, np.zeros(wl.shape), rho_new, p)
+    t3 = time.perf_counter()
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    grid_s = (t1 - t0) + (t3 - t2)
+    part_s = (t2 - t1) * frac
+    step_s = grid_s + part_s
+    cpu_s = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    cores = max(1, round(cpu_s / (t3 - t0)))
+    return {
+        "value": Np / step_s, "unit": "particle-pushes/s", "cores": cores, "kind": "oracle",
+        "sample": f"one FP64 NumPy oracle step: full grid part ({grid_s:.1f} s) + particle part on "
+                  f"{wl.electrons.n // frac} of {wl.electrons.n} electrons ({t2 - t1:.1f} s, scaled x{frac}); "
+                  f"{step_s:.1f} s per step",
+        "cell_updates_per_s": wl.cells / step_s,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="laser128", choices=sorted(CONFIG_TEXT))
+    ap.add_argument("--dtype", default=None, choices=["f32", "f64"])
+    ap.add_argument("--center-order", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs the hybrid PSATD step on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU domain decomposition is described in DESIGN.md, not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2106_12919_amd import inputs
+    from paper_2106_12919_amd import lib as piclib
+
+    torch.cuda.set_device(0)
+    wl = inputs.config(args.config, dtype=args.dtype, center_order=args.center_order)
+    print(f"[bench] workload {args.config} dtype={wl.dtype} cells={wl.cells} particles={wl.electrons.n}",
+          file=sys.stderr, flush=True)
+    ctx = piclib.Context.for_workload(wl)
+    f = ctx.fields_from_workload(wl)
+    el = piclib.Species.from_host(wl.electrons, wl.shape, wl.dtype)
+    ions = piclib.Species.from_host(wl.ions, wl.shape, wl.dtype)
+    ctx.init_charge(f, el, ions)
+    del ions
+    piclib.pic_step(ctx.ctx, f, [el], args.warmup)
+    piclib.pic_sync(ctx.ctx)
+    print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
+
+    piclib.pic_stage_times(ctx.ctx)  # reset
+    piclib.pic_profile(ctx.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    piclib.pic_step(ctx.ctx, f, [el], args.steps)
+    piclib.pic_sync(ctx.ctx)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    stages = piclib.pic_stage_times(ctx.ctx)
+    piclib.pic_profile(ctx.ctx, False)
+    W, Q = piclib.pic_diagnostics(ctx.ctx, f)
+    print(f"[bench] timed {args.steps} steps in {T:.4f} s; field energy {W:.6e}, total charge {Q:.3e}",
+          file=sys.stderr, flush=True)
+
+    K = args.steps
+    N = wl.cells
+    M = wl.shape[0] * wl.shape[1] * (wl.shape[2] // 2 + 1)
+    Np = el.n
+    s = 4 if wl.dtype == "f32" else 8
+    breakdown = {}
+    for name, (ms, cnt) in stages.items():
+        if cnt == 0:
+            continue
+        avg = ms / cnt
+        b = stage_bytes(name, N, M, Np, s)
+        breakdown[name] = {"ms_avg": round(avg, 5), "launches": cnt, "algo_bytes": b,
+                           "GBps": round(b / (avg * 1e-3) / 1e9, 1)}
+    dom = max((k for k in breakdown if k != "entry_forward"), key=lambda k: breakdown[k]["ms_avg"] * breakdown[k]["launches"])
+    d = breakdown[dom]
+    achieved = d["algo_bytes"] / (d["ms_avg"] * 1e-3) / 1e9
+    result = {
+        "metric": "particle-pushes/s and grid-cell updates/s per PIC step, FP32 vs FP64, fwd and fwd+bwd",
+        "value": Np * K / T,
+        "unit": "particle-pushes/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * T / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": wl.dtype,
+        "data": "synthetic (seeded laser + plasma workload)",
+        "config": {"workload": CONFIG_TEXT[args.config], "cells": N, "particles": Np,
+                   "center_order": wl.center_order, "shape_order": wl.shape_order, "pass": "forward"},
+        "cell_updates_per_s": N * K / T,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "stages": breakdown,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample ...", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(wl, Np)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

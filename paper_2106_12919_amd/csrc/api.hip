@@ -15,10 +15,10 @@ namespace {
 
 thread_local std::string g_init_error;
 
-const char* const kStageNames[] = {"center_s2n", "gather_push", "deposit", "center_n2s",
-                                   "fft_forward", "psatd_update", "fft_inverse", "entry_forward"};
-constexpr int kNumStages = 8;
-enum Stage { ST_S2N = 0, ST_PUSH, ST_DEPOSIT, ST_N2S, ST_FFT_FWD, ST_UPDATE, ST_FFT_INV, ST_ENTRY };
+const char* const kStageNames[] = {"center_s2n",   "gather_push", "deposit",     "center_n2s", "fft_forward",
+                                   "psatd_update", "fft_inverse", "entry_forward", "tile_sort"};
+constexpr int kNumStages = 9;
+enum Stage { ST_S2N = 0, ST_PUSH, ST_DEPOSIT, ST_N2S, ST_FFT_FWD, ST_UPDATE, ST_FFT_INV, ST_ENTRY, ST_SORT };
 
 struct EventPair {
   hipEvent_t a, b;
@@ -103,10 +103,29 @@ struct StageScope {
   ~StageScope() { c->stage_end(ev); }
 };
 
+// Per-species particle scratch: a second set of SoA arrays (ping-pong with the
+// caller's arrays while pic_step keeps particles in tile order) and sort indices.
+template <typename T>
+struct SpeciesScratch {
+  int64_t cap = 0;
+  int32_t* cell = nullptr;
+  T* off[3] = {nullptr, nullptr, nullptr};
+  T* u[3] = {nullptr, nullptr, nullptr};
+  T* w = nullptr;
+  int* dst = nullptr;
+  int* perm = nullptr;
+};
+
 template <typename T>
 struct Engine : EngineBase {
   Fft3D<T> fft;
   PsatdTables<T> tab;
+  TileGeom tiles{};
+  int* t_counts = nullptr;  // ntiles + 1
+  int* t_starts = nullptr;  // ntiles + 2
+  int* t_cursor = nullptr;  // ntiles + 1
+  T* stage = nullptr;       // per-tile deposition boxes, ntiles * 4 * deposit_box^3
+  std::vector<SpeciesScratch<T>> sps;
   cplx<T>* Eh[3] = {nullptr, nullptr, nullptr};
   cplx<T>* Bh[3] = {nullptr, nullptr, nullptr};
   cplx<T>* Jh[3] = {nullptr, nullptr, nullptr};
@@ -126,6 +145,36 @@ struct Engine : EngineBase {
     if (e != hipSuccess) return e;
     allocs.push_back(q);
     *out = reinterpret_cast<P*>(q);
+    return hipSuccess;
+  }
+  hipError_t release_one(void* q) {
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i] == q) {
+        allocs.erase(allocs.begin() + i);
+        return hipFree(q);
+      }
+    return hipSuccess;
+  }
+  // grows the scratch of species s to n particles
+  hipError_t ensure_species(size_t s, int64_t n) {
+    if (sps.size() <= s) sps.resize(s + 1);
+    SpeciesScratch<T>& x = sps[s];
+    if (x.cap >= n) return hipSuccess;
+    void* old[10] = {x.cell, x.off[0], x.off[1], x.off[2], x.u[0], x.u[1], x.u[2], x.w, x.dst, x.perm};
+    for (void* q : old)
+      if (q) (void)release_one(q);
+    x = SpeciesScratch<T>{};
+    hipError_t e;
+    const size_t m = (size_t)(n > 0 ? n : 1);
+    if ((e = alloc(&x.cell, m)) != hipSuccess) return e;
+    for (int d = 0; d < 3; ++d) {
+      if ((e = alloc(&x.off[d], m)) != hipSuccess) return e;
+      if ((e = alloc(&x.u[d], m)) != hipSuccess) return e;
+    }
+    if ((e = alloc(&x.w, m)) != hipSuccess) return e;
+    if ((e = alloc(&x.dst, m)) != hipSuccess) return e;
+    if ((e = alloc(&x.perm, m)) != hipSuccess) return e;
+    x.cap = n;
     return hipSuccess;
   }
   template <typename P>
@@ -192,6 +241,16 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
     if ((err = hipMemset(*b, 0, ns * sizeof(cplx<T>))) != hipSuccess) return err;
   }
   if ((err = e.alloc(&e.tmp, (size_t)p.nx * p.ny * p.nz)) != hipSuccess) return err;
+  // deposition tiles of 8^3 cells: the int64 LDS box (4 components) is at most
+  // 4 * 13^3 * 8 B = 70 KiB (two workgroups per CU); the gather box 6 * 11^3 * sizeof(T)
+  const GridGeom g{p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order};
+  const int ts = 8;
+  e.tiles = make_tiles(g, ts);
+  if ((err = e.alloc(&e.t_counts, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;
+  if ((err = e.alloc(&e.t_starts, (size_t)e.tiles.ntiles + 2)) != hipSuccess) return err;
+  if ((err = e.alloc(&e.t_cursor, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;
+  const size_t B = (size_t)deposit_box(p.shape_order, ts);
+  if ((err = e.alloc(&e.stage, (size_t)e.tiles.ntiles * 4 * B * B * B)) != hipSuccess) return err;
   return hipSuccess;
 }
 
@@ -304,36 +363,94 @@ pic_status do_center(pic_ctx c, int dir, int what, pic_fields* f) {
 }
 
 template <typename T>
-pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, int mode) {
-  const pic_params& p = c->p;
-  const size_t N = ncells(p);
-  T* rho = static_cast<T*>(f->rho_new);
+void zero_sources(pic_ctx c, pic_fields* f, bool with_j) {
+  const size_t N = ncells(c->p);
   if (f->rho_static)
-    (void)hipMemcpyAsync(rho, f->rho_static, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(f->rho_new, f->rho_static, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
   else
-    (void)hipMemsetAsync(rho, 0, N * sizeof(T), c->stream);
-  const bool with_j = (mode == PIC_DEP_RHO_AND_J);
-  T* J[3] = {static_cast<T*>(f->J_nod[0]), static_cast<T*>(f->J_nod[1]), static_cast<T*>(f->J_nod[2])};
+    (void)hipMemsetAsync(f->rho_new, 0, N * sizeof(T), c->stream);
   if (with_j)
-    for (int d = 0; d < 3; ++d) (void)hipMemsetAsync(J[d], 0, N * sizeof(T), c->stream);
-  const GridGeom g = geom(p);
+    for (int d = 0; d < 3; ++d) (void)hipMemsetAsync(f->J_nod[d], 0, N * sizeof(T), c->stream);
+}
+
+template <typename T>
+void J_ptrs(pic_fields* f, T* J[3]) {
+  for (int d = 0; d < 3; ++d) J[d] = static_cast<T*>(f->J_nod[d]);
+}
+
+template <typename T>
+pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, int mode) {
+  Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
+  const bool with_j = (mode == PIC_DEP_RHO_AND_J);
+  zero_sources<T>(c, f, with_j);
+  T* J[3];
+  J_ptrs<T>(f, J);
+  const GridGeom g = geom(c->p);
   for (int s = 0; s < nsp; ++s) {
+    if (sp[s].n == 0) continue;
+    hipError_t he = e.ensure_species((size_t)s, sp[s].n);
+    if (he != hipSuccess) return c->fail(PIC_ENOMEM, std::string("pic_deposit: ") + hipGetErrorString(he));
+    SpeciesScratch<T>& x = e.sps[s];
+    const SpeciesView<T> v = view<T>(sp[s]);
+    // visit the caller's particles in tile order through a permutation (caller order untouched)
+    tile_sort(g, e.tiles, v.cell, v.n, e.t_counts, e.t_starts, e.t_cursor, x.dst, c->d_bad, c->stream);
+    invert_perm(x.dst, x.perm, v.n, c->stream);
     const bool mobile = std::isfinite(sp[s].m);
-    deposit<T>(g, view<T>(sp[s]), rho, J, with_j && mobile, c->d_bad, c->stream);
+    deposit_tiled<T>(g, e.tiles, v, x.perm, e.t_starts, static_cast<T*>(f->rho_new), J, with_j && mobile, e.stage,
+                     c->d_bad, c->stream);
   }
   return c->check("pic_deposit");
 }
 
 template <typename T>
+void EB_nod(const pic_fields* f, const T* E[3], const T* B[3]) {
+  for (int d = 0; d < 3; ++d) {
+    E[d] = static_cast<const T*>(f->E_nod[d]);
+    B[d] = static_cast<const T*>(f->B_nod[d]);
+  }
+}
+
+template <typename T>
 pic_status do_gather_push(pic_ctx c, const pic_fields* f, pic_species* sp, int nsp) {
+  Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
   const GridGeom g = geom(c->p);
-  const T* E[3] = {static_cast<const T*>(f->E_nod[0]), static_cast<const T*>(f->E_nod[1]),
-                   static_cast<const T*>(f->E_nod[2])};
-  const T* B[3] = {static_cast<const T*>(f->B_nod[0]), static_cast<const T*>(f->B_nod[1]),
-                   static_cast<const T*>(f->B_nod[2])};
+  const T *E[3], *B[3];
+  EB_nod<T>(f, E, B);
   for (int s = 0; s < nsp; ++s)
-    if (std::isfinite(sp[s].m)) gather_push<T>(g, E, B, view<T>(sp[s]), c->d_bad, c->stream);
+    if (std::isfinite(sp[s].m) && sp[s].n > 0) {
+      hipError_t he = e.ensure_species((size_t)s, sp[s].n);
+      if (he != hipSuccess) return c->fail(PIC_ENOMEM, std::string("pic_gather_push: ") + hipGetErrorString(he));
+      SpeciesScratch<T>& x = e.sps[s];
+      const SpeciesView<T> v = view<T>(sp[s]);
+      // tile order through a permutation; every particle is updated in place
+      tile_sort(g, e.tiles, v.cell, v.n, e.t_counts, e.t_starts, e.t_cursor, x.dst, c->d_bad, c->stream);
+      invert_perm(x.dst, x.perm, v.n, c->stream);
+      gather_push_tiled<T>(g, e.tiles, E, B, v, v, x.perm, e.t_starts, false, c->d_bad, c->stream);
+    }
   return c->check("pic_gather_push");
+}
+
+template <typename T>
+SpeciesView<T> scratch_view(const SpeciesScratch<T>& x, const pic_species& like) {
+  SpeciesView<T> v = view<T>(like);
+  v.cell = x.cell;
+  for (int d = 0; d < 3; ++d) {
+    v.off[d] = x.off[d];
+    v.u[d] = x.u[d];
+  }
+  v.w = like.w ? x.w : nullptr;
+  return v;
+}
+
+template <typename T>
+void copy_species(const SpeciesView<T>& from, const SpeciesView<T>& to, hipStream_t st) {
+  const size_t n = (size_t)from.n;
+  (void)hipMemcpyAsync(to.cell, from.cell, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+  for (int d = 0; d < 3; ++d) {
+    (void)hipMemcpyAsync(to.off[d], from.off[d], n * sizeof(T), hipMemcpyDeviceToDevice, st);
+    (void)hipMemcpyAsync(to.u[d], from.u[d], n * sizeof(T), hipMemcpyDeviceToDevice, st);
+  }
+  if (from.w) (void)hipMemcpyAsync(to.w, from.w, n * sizeof(T), hipMemcpyDeviceToDevice, st);
 }
 
 // forward transforms of the state (E, B) and/or sources (J, rho_old, rho_new)
@@ -415,6 +532,16 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
     dst[6] = e.rh[slot];
     forward_batch<T>(c, e, src, dst, 7);
   }
+  const GridGeom g = geom(p);
+  const T *Enod[3], *Bnod[3];
+  EB_nod<T>(f, Enod, Bnod);
+  T* Jn[3];
+  J_ptrs<T>(f, Jn);
+  std::vector<char> in_scratch(nsp, 0);
+  for (int q = 0; q < nsp; ++q) {
+    hipError_t he = e.ensure_species((size_t)q, sp[q].n);
+    if (he != hipSuccess) return c->fail(PIC_ENOMEM, std::string("pic_step: ") + hipGetErrorString(he));
+  }
   pic_status st;
   for (int n = 0; n < nsteps; ++n) {
     {
@@ -423,12 +550,33 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
       if ((st = do_center<T>(c, PIC_S2N, PIC_B, f)) != PIC_OK) return st;
     }
     {
-      StageScope sc(c, ST_PUSH);
-      if ((st = do_gather_push<T>(c, f, sp, nsp)) != PIC_OK) return st;
-    }
-    {
       StageScope sc(c, ST_DEPOSIT);
-      if ((st = do_deposit<T>(c, sp, nsp, f, PIC_DEP_RHO_AND_J)) != PIC_OK) return st;
+      zero_sources<T>(c, f, true);
+    }
+    for (int q = 0; q < nsp; ++q) {
+      if (sp[q].n == 0) continue;
+      SpeciesScratch<T>& x = e.sps[q];
+      const SpeciesView<T> cur = in_scratch[q] ? scratch_view<T>(x, sp[q]) : view<T>(sp[q]);
+      const SpeciesView<T> alt = in_scratch[q] ? view<T>(sp[q]) : scratch_view<T>(x, sp[q]);
+      const bool mobile = std::isfinite(sp[q].m);
+      {
+        StageScope sc(c, ST_SORT);
+        tile_sort(g, e.tiles, cur.cell, cur.n, e.t_counts, e.t_starts, e.t_cursor, x.dst, c->d_bad, c->stream);
+        if (mobile) invert_perm(x.dst, x.perm, cur.n, c->stream);
+      }
+      {
+        StageScope sc(c, ST_PUSH);
+        if (mobile)
+          gather_push_tiled<T>(g, e.tiles, Enod, Bnod, cur, alt, x.perm, e.t_starts, true, c->d_bad, c->stream);
+        else
+          permute_species<T>(cur, alt, x.dst, c->stream);
+      }
+      {
+        StageScope sc(c, ST_DEPOSIT);
+        deposit_tiled<T>(g, e.tiles, alt, nullptr, e.t_starts, static_cast<T*>(f->rho_new), Jn, mobile, e.stage,
+                         c->d_bad, c->stream);
+      }
+      in_scratch[q] = !in_scratch[q];
     }
     {
       StageScope sc(c, ST_N2S);
@@ -445,6 +593,9 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
     slot = 1 - slot;
     if ((st = c->check("pic_step")) != PIC_OK) return st;
   }
+  // particles left in the scratch arrays go back to the caller's arrays (tile order kept)
+  for (int q = 0; q < nsp; ++q)
+    if (in_scratch[q] && sp[q].n > 0) copy_species<T>(scratch_view<T>(e.sps[q], sp[q]), view<T>(sp[q]), c->stream);
   (void)hipMemcpyAsync(f->rho_old, f->rho_new, ncells(p) * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
   return c->check("pic_step");
 }

@@ -62,14 +62,42 @@ struct SpeciesView {
   T* w;         // may be null
   double w_const, q, m;
 };
+struct TileGeom {
+  int ts, ntx, nty, ntz, ntiles;
+};
+TileGeom make_tiles(const GridGeom& g, int ts);
+// Edge length (nodes) of the LDS box of one deposition tile (the tile's support plus a
+// one-cell margin) and of one gather tile (the tile's support).
+int deposit_box(int shape_order, int ts);
+int gather_box(int shape_order, int ts);
+// Counting sort by tile of the particles' current cells: counts[ntiles+1],
+// starts[ntiles+2], cursor[ntiles+1] (scratch), dst[n] = each particle's slot in
+// tile order (tiles in order, then particles with invalid cells, counted in *bad).
+void tile_sort(const GridGeom& g, const TileGeom& t, const int32_t* cell, int64_t n, int* counts, int* starts,
+               int* cursor, int* dst, int* bad, hipStream_t s);
+void invert_perm(const int* dst, int* perm, int64_t n, hipStream_t s);
+
+// Gather at the current positions and push; particle p of ``in`` is written to slot
+// dst[p] of ``out`` (dst == nullptr: slot p; ``out`` may alias ``in`` only then).
 template <typename T>
-void gather_push(const GridGeom& g, const T* const E[3], const T* const B[3], const SpeciesView<T>& sp, int* bad,
-                 hipStream_t s);
-// adds this species' rho (at x) and, when with_j, J (at x - dt v/2) to the nodal arrays.
-// Particles with an out-of-range cell index are skipped and counted in *bad.
+void gather_push(const GridGeom& g, const T* const E[3], const T* const B[3], const SpeciesView<T>& in,
+                 const SpeciesView<T>& out, const int* dst, int* bad, hipStream_t s);
+// Tile-ordered gather + push: slot q of tile t (q in [starts[t], starts[t+1])) reads
+// particle perm[q] of ``in`` and writes it to slot q of ``out`` (write_sorted) or to
+// perm[q] (in place when out == in).
 template <typename T>
-void deposit(const GridGeom& g, const SpeciesView<T>& sp, T* rho, T* const J[3], bool with_j, int* bad,
-             hipStream_t s);
+void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3], const T* const B[3],
+                       const SpeciesView<T>& in, const SpeciesView<T>& out, const int* perm, const int* starts,
+                       bool write_sorted, int* bad, hipStream_t s);
+template <typename T>
+void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const int* dst, hipStream_t s);
+// Adds the species' rho (at its positions) and, when with_j, J (at x - dt v/2) to the
+// nodal arrays.  Particles are visited tile by tile: tile t owns sorted slots
+// [starts[t], starts[t+1]); slot q holds particle perm[q] (perm == nullptr: q).
+// ``stage`` holds ntiles * (with_j ? 4 : 1) * deposit_box^3 elements.
+template <typename T>
+void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
+                   T* rho, T* const J[3], bool with_j, T* stage, int* bad, hipStream_t s);
 
 // ---------------------------------------------------------------- reductions (diag.hip)
 // acc[0] += sum of squares over ``count`` arrays of n elements; acc[1] += sum of ``sum_arr``.

@@ -1,0 +1,119 @@
+// Counting sort of particles by grid tile (support for the tiled deposition).
+//
+// Tiles are ts^3 blocks of cells (partial at the upper end of an axis); particles
+// with an out-of-range cell index go to one extra bucket after the last tile so
+// the sorted order has no holes (they are counted and never deposited).  Three
+// launches: count per tile, exclusive scan of the counts, rank (each particle's
+// slot in tile order).  Particles that share a tile within a wavefront are
+// combined before touching the tile counter, so a wave issues one atomic per
+// distinct tile: with particles already grouped by tile (the previous step's
+// order) that is one or two atomics per wave instead of 64.
+#include "kernels.h"
+
+namespace pic {
+
+namespace {
+
+__device__ inline int tile_key(int c, const GridGeom& g, const TileGeom& t) {
+  if (c < 0 || c >= g.nx * g.ny * g.nz) return t.ntiles;
+  const int k = c % g.nz;
+  const int r = c / g.nz;
+  const int j = r % g.ny;
+  const int i = r / g.ny;
+  return ((i / t.ts) * t.nty + j / t.ts) * t.ntz + k / t.ts;
+}
+
+// Adds one per valid lane to counters[key]; returns each lane's previous-value
+// slot (counter value before the lane's increment, lanes of one key in lane order).
+__device__ inline int wave_aggregated_add(int* counters, int key, bool valid) {
+  unsigned long long active = __ballot(valid);
+  const int lane = __lane_id();
+  int slot = -1;
+  while (active) {
+    const int leader = __ffsll((unsigned long long)active) - 1;
+    const int lkey = __shfl(key, leader);
+    const unsigned long long same = __ballot(valid && key == lkey) & active;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counters[lkey], __popcll(same));
+    base = __shfl(base, leader);
+    if ((same >> lane) & 1ull) slot = base + __popcll(same & ((1ull << lane) - 1ull));
+    active &= ~same;
+  }
+  return slot;
+}
+
+__global__ void __launch_bounds__(256) k_tile_count(GridGeom g, TileGeom t, const int32_t* __restrict__ cell, long long n,
+                                                    int* counts) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int key = (p < n) ? tile_key(cell[p], g, t) : 0;
+  (void)wave_aggregated_add(counts, key, p < n);
+}
+
+__global__ void __launch_bounds__(256) k_tile_rank(GridGeom g, TileGeom t, const int32_t* __restrict__ cell, long long n,
+                                                   int* cursor, int* dst, int* bad) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int key = (p < n) ? tile_key(cell[p], g, t) : 0;
+  const int slot = wave_aggregated_add(cursor, key, p < n);
+  if (p < n) {
+    if (key == t.ntiles && bad) atomicAdd(bad, 1);
+    dst[p] = slot;
+  }
+}
+
+// Exclusive scan of counts[0..m) into starts[0..m] and cursor[0..m), one block.
+__global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ counts, int* starts, int* cursor, int m) {
+  __shared__ int part[1024];
+  const int tid = threadIdx.x;
+  const int chunk = (m + blockDim.x - 1) / blockDim.x;
+  const int lo = min(m, tid * chunk), hi = min(m, lo + chunk);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += counts[i];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    const int v = (tid >= off) ? part[tid - off] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - s;  // exclusive prefix of this chunk
+  for (int i = lo; i < hi; ++i) {
+    starts[i] = run;
+    cursor[i] = run;
+    run += counts[i];
+  }
+  if (tid == blockDim.x - 1) starts[m] = part[tid];
+}
+
+__global__ void __launch_bounds__(256) k_invert(const int* __restrict__ dst, int* perm, long long n) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) perm[dst[p]] = (int)p;
+}
+
+}  // namespace
+
+TileGeom make_tiles(const GridGeom& g, int ts) {
+  TileGeom t{};
+  t.ts = ts;
+  t.ntx = (g.nx + ts - 1) / ts;
+  t.nty = (g.ny + ts - 1) / ts;
+  t.ntz = (g.nz + ts - 1) / ts;
+  t.ntiles = t.ntx * t.nty * t.ntz;
+  return t;
+}
+
+void tile_sort(const GridGeom& g, const TileGeom& t, const int32_t* cell, int64_t n, int* counts, int* starts,
+               int* cursor, int* dst, int* bad, hipStream_t s) {
+  // buckets 0..ntiles-1 are tiles, bucket ntiles collects invalid cells
+  (void)hipMemsetAsync(counts, 0, sizeof(int) * (t.ntiles + 1), s);
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (n > 0) hipLaunchKernelGGL(k_tile_count, dim3(nb), dim3(256), 0, s, g, t, cell, (long long)n, counts);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, starts, cursor, t.ntiles + 1);
+  if (n > 0) hipLaunchKernelGGL(k_tile_rank, dim3(nb), dim3(256), 0, s, g, t, cell, (long long)n, cursor, dst, bad);
+}
+
+void invert_perm(const int* dst, int* perm, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_invert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, perm, (long long)n);
+}
+
+}  // namespace pic

@@ -51,6 +51,9 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"libpic.so not found at {LIB_PATH}: build it with `python -m paper_2106_12919_amd.build`")
+    # torch first: libpic must bind to the HIP runtime torch already uses (same soname),
+    # so that torch's streams and device pointers are valid in the library.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "pic_init": (c_int, [POINTER(pic_params), c_void_p, POINTER(c_void_p)]),
