@@ -61,6 +61,7 @@ def stage_bytes(stage, N, M, Np, s):
         "fft_inverse": 6 * (M * 2 * s + N * s),          # E, B: half spectrum in, real out
         "entry_forward": 7 * (N * s + M * 2 * s),
         "tile_sort": Np * 12,          # cell read twice (count, rank), slot written
+        "clear_sources": 4 * N * s,    # rho <- static background, J <- 0
     }[stage]
 
 

@@ -35,32 +35,35 @@ def _hipcc():
     return h
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS
+def _compile(src, build_dir=BUILD, extra=()):
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [_hipcc(), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS + list(extra)
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     return src, obj, r.returncode, r.stdout
 
 
-def build(verbose=False, jobs=None):
-    """Compile every source and link libpic.so; raises RuntimeError on failure."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose=False, jobs=None, out=LIB, build_dir=BUILD, extra_flags=()):
+    """Compile every source and link ``out`` (default: the in-tree libpic.so).
+
+    ``extra_flags`` (e.g. -D tuning macros) and another ``out``/``build_dir`` build a variant
+    for A/B timing without touching the in-tree library.  Raises RuntimeError on failure."""
+    os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, (os.cpu_count() or 4)))
     with ThreadPoolExecutor(jobs) as ex:
-        results = list(ex.map(_compile, SOURCES))
-    errors = [(s, out) for s, _, rc, out in results if rc != 0]
-    for s, _, rc, out in results:
-        if verbose and out.strip():
-            print(f"--- {s}\n{out}")
+        results = list(ex.map(lambda s: _compile(s, build_dir, extra_flags), SOURCES))
+    errors = [(s, log) for s, _, rc, log in results if rc != 0]
+    for s, _, rc, log in results:
+        if verbose and log.strip():
+            print(f"--- {s}\n{log}")
     if errors:
-        raise RuntimeError("hipcc failed:\n" + "\n".join(f"--- {s}\n{out}" for s, out in errors))
-    tmp = LIB + ".tmp"
+        raise RuntimeError("hipcc failed:\n" + "\n".join(f"--- {s}\n{log}" for s, log in errors))
+    tmp = out + ".tmp"
     cmd = [_hipcc(), "-shared", "-o", tmp] + [o for _, o, _, _ in results] + [f"--offload-arch={ARCH}", "-fPIC"]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -15,10 +15,10 @@ namespace {
 
 thread_local std::string g_init_error;
 
-const char* const kStageNames[] = {"center_s2n",   "gather_push", "deposit",     "center_n2s", "fft_forward",
-                                   "psatd_update", "fft_inverse", "entry_forward", "tile_sort"};
-constexpr int kNumStages = 9;
-enum Stage { ST_S2N = 0, ST_PUSH, ST_DEPOSIT, ST_N2S, ST_FFT_FWD, ST_UPDATE, ST_FFT_INV, ST_ENTRY, ST_SORT };
+const char* const kStageNames[] = {"center_s2n",   "gather_push", "deposit",       "center_n2s", "fft_forward",
+                                   "psatd_update", "fft_inverse", "entry_forward", "tile_sort",  "clear_sources"};
+constexpr int kNumStages = 10;
+enum Stage { ST_S2N = 0, ST_PUSH, ST_DEPOSIT, ST_N2S, ST_FFT_FWD, ST_UPDATE, ST_FFT_INV, ST_ENTRY, ST_SORT, ST_CLEAR };
 
 struct EventPair {
   hipEvent_t a, b;
@@ -550,7 +550,7 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
       if ((st = do_center<T>(c, PIC_S2N, PIC_B, f)) != PIC_OK) return st;
     }
     {
-      StageScope sc(c, ST_DEPOSIT);
+      StageScope sc(c, ST_CLEAR);
       zero_sources<T>(c, f, true);
     }
     for (int q = 0; q < nsp; ++q) {

@@ -13,6 +13,13 @@
 
 #include "kernels.h"
 
+#ifndef PIC_GATHER_BLOCK
+#define PIC_GATHER_BLOCK 512
+#endif
+#ifndef PIC_DEPOSIT_BLOCK
+#define PIC_DEPOSIT_BLOCK 512
+#endif
+
 namespace pic {
 
 namespace {
@@ -166,7 +173,7 @@ __global__ void __launch_bounds__(256) k_gather_push(GridGeom g, Batch<const T*>
 // particle perm[q] of ``in`` and writes it to slot q (write_sorted) or back to
 // perm[q] of ``out``.  Block ntiles carries particles with invalid cells along.
 template <typename T, int ORDER>
-__global__ void __launch_bounds__(256) k_gather_push_tiled(GridGeom g, TileGeom tg, Batch<const T*> F,
+__global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_tiled(GridGeom g, TileGeom tg, Batch<const T*> F,
                                                            SpeciesView<T> in, SpeciesView<T> out,
                                                            const int* __restrict__ perm, const int* __restrict__ starts,
                                                            int write_sorted, T qdt2m, T dtx, T dty, T dtz, int* bad) {
@@ -308,12 +315,55 @@ __device__ inline void scatter(const GridGeom& g, int i, int j, int k, T ox, T o
   }
 }
 
+// Fixed-point accumulators of the LDS deposition box.  FP32 runs accumulate int32
+// (one v_cvt per contribution, ds_add_u32) scaled so that the tile's bound on any
+// node sum stays below 2^30: a resolution of about 2^-31 * 8/27 * sum|q w| per
+// contribution, comparable to FP32 rounding.  FP64 runs accumulate int64 scaled
+// to 2^-50 of the largest |q w|, rounded with the exact 1.5*2^52 add.
+template <typename T>
+struct Fixed;
+
+// shift(): the scale exponent for a tile whose partial sums are bounded by 2^e_sum,
+// whose single contributions are bounded by 2^e_max, with fewer than 2^h particles.
+template <>
+struct Fixed<float> {
+  using acc_t = int;
+  __device__ static inline int shift(int e_sum, int e_max, int h) { return 30 - e_sum; }
+  __device__ static inline acc_t conv(float x) { return __float2int_rn(x); }
+  __device__ static inline void add(acc_t* a, acc_t v) { atomicAdd(a, v); }
+};
+
+template <>
+struct Fixed<double> {
+  using acc_t = long long;
+  // |sum| < 2^(h + e_max + sh) <= 2^62; each contribution < 2^50 (exact rounding below)
+  __device__ static inline int shift(int e_sum, int e_max, int h) { return min(62 - e_max - h, 50 - e_max); }
+  __device__ static inline acc_t conv(double x) {
+    return __double_as_longlong(x + 6755399441055744.0) - 0x4338000000000000LL;
+  }
+  __device__ static inline void add(acc_t* a, acc_t v) {
+    atomicAdd(reinterpret_cast<unsigned long long*>(a), (unsigned long long)v);
+  }
+};
+
+// Largest single-node weight of the 3D shape: 1 (linear) and (2/3)^3 (cubic).
+template <int ORDER>
+struct MaxWeight;
+template <>
+struct MaxWeight<1> {
+  static constexpr double value = 1.0;
+};
+template <>
+struct MaxWeight<3> {
+  static constexpr double value = 8.0 / 27.0;
+};
+
 // Adds the shape-weighted values of one particle, as fixed-point integers scaled by
-// 2^sh, to a (B x B x B) int64 LDS box whose first support node is (lx, ly, lz).
+// 2^sh, to a (B x B x B) LDS box whose first support node is (lx, ly, lz).
 // Integer LDS atomics retire about 20x faster than float LDS atomics on gfx950.
 template <typename T, int ORDER>
-__device__ inline void scatter_lds(long long* box, int B, int lx, int ly, int lz, T ox, T oy, T oz, const T* val,
-                                   int nval, int sh) {
+__device__ inline void scatter_lds(typename Fixed<T>::acc_t* box, int B, int lx, int ly, int lz, T ox, T oy, T oz,
+                                   const T* val, int nval, int sh) {
   using S = Shape<T, ORDER>;
   constexpr int NW = S::NW;
   T wx[NW], wy[NW], wz[NW];
@@ -332,9 +382,7 @@ __device__ inline void scatter_lds(long long* box, int B, int lx, int ly, int lz
 #pragma unroll
       for (int cc = 0; cc < NW; ++cc) {
         const T w = wab * wz[cc];
-        for (int q = 0; q < nval; ++q)
-          atomicAdd(reinterpret_cast<unsigned long long*>(&box[q * B3 + row + cc]),
-                    (unsigned long long)(long long)rint(w * sv[q]));
+        for (int q = 0; q < nval; ++q) Fixed<T>::add(&box[q * B3 + row + cc], Fixed<T>::conv(w * sv[q]));
       }
     }
   }
@@ -355,15 +403,17 @@ __device__ inline int box_index(int i, int t0, int n, int ts) {
 // boxes on the grid.  (A particle outside the margin is added to the grid
 // directly with global atomics.)
 template <typename T, int ORDER>
-__global__ void __launch_bounds__(256) k_deposit_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp,
+__global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp,
                                                        const int* __restrict__ perm, const int* __restrict__ starts,
                                                        Batch<T*> out, T* __restrict__ stage, T qdv, int with_j, T hdtx,
                                                        T hdty, T hdtz, int* bad) {
   using S = Shape<T, ORDER>;
   constexpr int NW = S::NW;
+  using acc_t = typename Fixed<T>::acc_t;
   extern __shared__ __align__(16) unsigned char smem[];
-  long long* box = reinterpret_cast<long long*>(smem);
-  __shared__ T red[8];
+  acc_t* box = reinterpret_cast<acc_t*>(smem);
+  __shared__ T red[PIC_DEPOSIT_BLOCK / 64];
+  __shared__ T redm[PIC_DEPOSIT_BLOCK / 64];
   const int tile = blockIdx.x;
   const int beg = starts[tile], end = starts[tile + 1];
   if (beg == end) return;
@@ -371,28 +421,44 @@ __global__ void __launch_bounds__(256) k_deposit_tiled(GridGeom g, TileGeom tg, 
   const int B = ts + NW + 1;
   const int B3 = B * B * B;
   const int ncomp = with_j ? 4 : 1;
-  // Fixed-point scale 2^sh: every contribution is at most max|q w|/dV (|v| < c, shape
-  // weights <= 1) < 2^e, and a node receives at most cnt < 2^h of them, so
-  // |sum| < 2^(sh + e + h) = 2^62: no overflow, resolution 2^-(62-h) of max|q w|.
-  T mq = 0;
+  // Fixed-point scale 2^sh.  A node of this box receives, from each particle of the
+  // tile, at most MaxWeight * |q w| / dV (|v| < c): every partial sum is bounded by
+  // MaxWeight * sum|q w| / dV < 2^e_sum, every contribution by max|q w| / dV < 2^e_max.
+  T sw = 0, mw = 0;
   if (sp.w) {
-    for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) mq = fmax(mq, fabs(sp.w[perm ? perm[qq] : qq]));
+    for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
+      const T a = fabs(sp.w[perm ? perm[qq] : qq]);
+      sw += a;
+      mw = fmax(mw, a);
+    }
   } else {
-    mq = fabs((T)sp.w_const);
+    sw = (threadIdx.x == 0) ? fabs((T)sp.w_const) * (T)(end - beg) : (T)0;
+    mw = fabs((T)sp.w_const);
   }
-  for (int o = 32; o > 0; o >>= 1) mq = fmax(mq, __shfl_xor(mq, o, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mq;
+  for (int o = 32; o > 0; o >>= 1) {
+    sw += __shfl_xor(sw, o, 64);
+    mw = fmax(mw, __shfl_xor(mw, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = sw;
+    redm[threadIdx.x >> 6] = mw;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    T m = 0;
-    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) m = fmax(m, red[w]);
-    red[0] = m * fabs(qdv);
+    T m = 0, x = 0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) {
+      m += red[w];
+      x = fmax(x, redm[w]);
+    }
+    // a little slack on the bound covers the rounding of the FP sum itself
+    red[0] = m * fabs(qdv) * (T)(MaxWeight<ORDER>::value * 1.001);
+    redm[0] = x * fabs(qdv);
   }
   __syncthreads();
-  int e = 0;
-  (void)frexp(red[0], &e);
-  const int h = 32 - __clz(end - beg);
-  const int sh = 62 - e - h;
+  int e_sum = 0, e_max = 0;
+  (void)frexp(red[0], &e_sum);
+  (void)frexp(redm[0], &e_max);
+  const int sh = Fixed<T>::shift(e_sum, e_max, 32 - __clz(end - beg));
   const int tk = tile % tg.ntz;
   const int tr = tile / tg.ntz;
   const int tj = tr % tg.nty;
@@ -557,10 +623,10 @@ void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3]
   if (g.shape_order == 1) allow_lds((const void*)k_gather_push_tiled<T, 1>, lds);
   else allow_lds((const void*)k_gather_push_tiled<T, 3>, lds);
   if (g.shape_order == 1)
-    hipLaunchKernelGGL((k_gather_push_tiled<T, 1>), dim3(t.ntiles + 1), dim3(256), lds, s, g, t, F, in, out, perm,
+    hipLaunchKernelGGL((k_gather_push_tiled<T, 1>), dim3(t.ntiles + 1), dim3(PIC_GATHER_BLOCK), lds, s, g, t, F, in, out, perm,
                        starts, ws, qdt2m, dtx, dty, dtz, bad);
   else
-    hipLaunchKernelGGL((k_gather_push_tiled<T, 3>), dim3(t.ntiles + 1), dim3(256), lds, s, g, t, F, in, out, perm,
+    hipLaunchKernelGGL((k_gather_push_tiled<T, 3>), dim3(t.ntiles + 1), dim3(PIC_GATHER_BLOCK), lds, s, g, t, F, in, out, perm,
                        starts, ws, qdt2m, dtx, dty, dtz, bad);
 }
 
@@ -576,17 +642,17 @@ void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& s
   const int wj = with_j ? 1 : 0;
   const int ncomp = with_j ? 4 : 1;
   const int B = deposit_box(g.shape_order, t.ts);
-  const size_t lds = (size_t)ncomp * B * B * B * sizeof(long long);
+  const size_t lds = (size_t)ncomp * B * B * B * sizeof(typename Fixed<T>::acc_t);
   const long long N = (long long)g.nx * g.ny * g.nz;
   const unsigned nr = (unsigned)std::min<long long>((N + 255) / 256, 65536);
   if (g.shape_order == 1) allow_lds((const void*)k_deposit_tiled<T, 1>, lds);
   else allow_lds((const void*)k_deposit_tiled<T, 3>, lds);
   if (g.shape_order == 1) {
-    hipLaunchKernelGGL((k_deposit_tiled<T, 1>), dim3(t.ntiles), dim3(256), lds, s, g, t, sp, perm, starts, out, stage,
+    hipLaunchKernelGGL((k_deposit_tiled<T, 1>), dim3(t.ntiles), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm, starts, out, stage,
                        qdv, wj, hx, hy, hz, bad);
     hipLaunchKernelGGL((k_deposit_reduce<T, 1>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, out, ncomp);
   } else {
-    hipLaunchKernelGGL((k_deposit_tiled<T, 3>), dim3(t.ntiles), dim3(256), lds, s, g, t, sp, perm, starts, out, stage,
+    hipLaunchKernelGGL((k_deposit_tiled<T, 3>), dim3(t.ntiles), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm, starts, out, stage,
                        qdv, wj, hx, hy, hz, bad);
     hipLaunchKernelGGL((k_deposit_reduce<T, 3>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, out, ncomp);
   }

@@ -14,7 +14,8 @@ from ctypes import POINTER, Structure, c_char_p, c_double, c_int, c_int32, c_int
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpic.so")
+# PIC_LIBRARY may name another build of the same sources (A/B timing of build variants).
+LIB_PATH = os.environ.get("PIC_LIBRARY") or os.path.join(HERE, "libpic.so")
 
 PIC_OK, PIC_EINVAL, PIC_EUNSUPPORTED, PIC_EHIP, PIC_ENOMEM, PIC_ESTATE = range(6)
 PIC_F32, PIC_F64 = 0, 1
