@@ -34,6 +34,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "laser128_f32_hbm_traffic.md")
+
+
+def kernel_source_hash():
+    """sha256 over the HIP sources: a recorded traffic figure is valid only for the sources it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2106_12919_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(stage):
+    """Measured HBM bytes per launch of ``stage`` from the committed counter summary, or None
+    when there is none or the kernel sources changed since the counters were taken."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(block)
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch", {}).get(stage)
 
 CONFIG_TEXT = {
     "laser128": "laser128: 128x128x256 periodic, laser a0=2 lambda=16 waist=20 fwhm=30 into 2 ppc cold plasma "
@@ -54,7 +80,8 @@ def stage_bytes(stage, N, M, Np, s):
     return {
         "center_s2n": 12 * N * s,      # 6 staggered components in, 6 nodal out
         "gather_push": 6 * N * s + Np * part_rw,
-        "deposit": 4 * N * s + Np * part_r,
+        "deposit": Np * part_r,        # particles read; the per-tile boxes are not algorithmic
+        "deposit_reduce": 4 * N * s,   # rho, J written once
         "center_n2s": 6 * N * s,       # 3 in, 3 out
         "fft_forward": 4 * (N * s + M * 2 * s),          # J (3) and rho: real in, half spectrum out
         "psatd_update": M * (11 * 2 * s + 5 * s + 6 * 2 * s),  # 11 spectra + 5 tables in, 6 out
@@ -111,6 +138,9 @@ def main():
     ap.add_argument("--dtype", default=None, choices=["f32", "f64"])
     ap.add_argument("--center-order", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the timed region, copy a MIB-MiB float32 tensor 3 times (a plain copy kernel "
+                         "of known size, the reference for the FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -136,6 +166,15 @@ def main():
     piclib.pic_step(ctx.ctx, f, [el], args.warmup)
     piclib.pic_sync(ctx.ctx)
     print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: 3 x {args.calibrate_copy} MiB", file=sys.stderr, flush=True)
+        del src, dst
 
     piclib.pic_stage_times(ctx.ctx)  # reset
     piclib.pic_profile(ctx.ctx, True)
@@ -184,7 +223,8 @@ def main():
                    "center_order": wl.center_order, "shape_order": wl.shape_order, "pass": "forward"},
         "cell_updates_per_s": N * K / T,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dom),
+                     "algo_bytes_per_launch": d["algo_bytes"], "ms_per_launch": d["ms_avg"]},
         "stages": breakdown,
     }
     ctx.close()

@@ -16,9 +16,12 @@ namespace {
 thread_local std::string g_init_error;
 
 const char* const kStageNames[] = {"center_s2n",   "gather_push", "deposit",       "center_n2s", "fft_forward",
-                                   "psatd_update", "fft_inverse", "entry_forward", "tile_sort",  "clear_sources"};
-constexpr int kNumStages = 10;
-enum Stage { ST_S2N = 0, ST_PUSH, ST_DEPOSIT, ST_N2S, ST_FFT_FWD, ST_UPDATE, ST_FFT_INV, ST_ENTRY, ST_SORT, ST_CLEAR };
+                                   "psatd_update", "fft_inverse", "entry_forward", "tile_sort",  "clear_sources",
+                                   "deposit_reduce"};
+constexpr int kNumStages = 11;
+enum Stage {
+  ST_S2N = 0, ST_PUSH, ST_DEPOSIT, ST_N2S, ST_FFT_FWD, ST_UPDATE, ST_FFT_INV, ST_ENTRY, ST_SORT, ST_CLEAR, ST_REDUCE
+};
 
 struct EventPair {
   hipEvent_t a, b;
@@ -396,8 +399,9 @@ pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, 
     tile_sort(g, e.tiles, v.cell, v.n, e.t_counts, e.t_starts, e.t_cursor, x.dst, c->d_bad, c->stream);
     invert_perm(x.dst, x.perm, v.n, c->stream);
     const bool mobile = std::isfinite(sp[s].m);
-    deposit_tiled<T>(g, e.tiles, v, x.perm, e.t_starts, static_cast<T*>(f->rho_new), J, with_j && mobile, e.stage,
-                     c->d_bad, c->stream);
+    deposit_tiled<T>(g, e.tiles, v, x.perm, e.t_starts, with_j && mobile, e.stage, c->d_bad,
+                     static_cast<T*>(f->rho_new), J, c->stream);
+    deposit_reduce<T>(g, e.tiles, e.t_starts, e.stage, with_j && mobile, static_cast<T*>(f->rho_new), J, c->stream);
   }
   return c->check("pic_deposit");
 }
@@ -573,8 +577,12 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
       }
       {
         StageScope sc(c, ST_DEPOSIT);
-        deposit_tiled<T>(g, e.tiles, alt, nullptr, e.t_starts, static_cast<T*>(f->rho_new), Jn, mobile, e.stage,
-                         c->d_bad, c->stream);
+        deposit_tiled<T>(g, e.tiles, alt, nullptr, e.t_starts, mobile, e.stage, c->d_bad, static_cast<T*>(f->rho_new),
+                         Jn, c->stream);
+      }
+      {
+        StageScope sc(c, ST_REDUCE);
+        deposit_reduce<T>(g, e.tiles, e.t_starts, e.stage, mobile, static_cast<T*>(f->rho_new), Jn, c->stream);
       }
       in_scratch[q] = !in_scratch[q];
     }

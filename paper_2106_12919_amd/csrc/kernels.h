@@ -91,13 +91,18 @@ void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3]
                        bool write_sorted, int* bad, hipStream_t s);
 template <typename T>
 void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const int* dst, hipStream_t s);
-// Adds the species' rho (at its positions) and, when with_j, J (at x - dt v/2) to the
-// nodal arrays.  Particles are visited tile by tile: tile t owns sorted slots
-// [starts[t], starts[t+1]); slot q holds particle perm[q] (perm == nullptr: q).
-// ``stage`` holds ntiles * (with_j ? 4 : 1) * deposit_box^3 elements.
+// Deposition of one species in two launches.  deposit_tiled accumulates rho (at the
+// particles' positions) and, when with_j, J (at x - dt v/2) tile by tile (tile t owns
+// sorted slots [starts[t], starts[t+1]); slot q holds particle perm[q], perm == nullptr:
+// q) into per-tile boxes in ``stage`` (ntiles * (with_j ? 4 : 1) * deposit_box^3
+// elements); particles that left the one-cell margin go straight to rho/J.
+// deposit_reduce then adds the overlapping boxes to the nodal arrays.
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
-                   T* rho, T* const J[3], bool with_j, T* stage, int* bad, hipStream_t s);
+                   bool with_j, T* stage, int* bad, T* rho, T* const J[3], hipStream_t s);
+template <typename T>
+void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, const T* stage, bool with_j, T* rho,
+                    T* const J[3], hipStream_t s);
 
 // ---------------------------------------------------------------- reductions (diag.hip)
 // acc[0] += sum of squares over ``count`` arrays of n elements; acc[1] += sum of ``sum_arr``.

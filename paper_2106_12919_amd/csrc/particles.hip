@@ -632,7 +632,7 @@ void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3]
 
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
-                   T* rho, T* const J[3], bool with_j, T* stage, int* bad, hipStream_t s) {
+                   bool with_j, T* stage, int* bad, T* rho, T* const J[3], hipStream_t s) {
   if (sp.n <= 0) return;
   Batch<T*> out{};
   out.p[0] = rho;
@@ -643,19 +643,29 @@ void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& s
   const int ncomp = with_j ? 4 : 1;
   const int B = deposit_box(g.shape_order, t.ts);
   const size_t lds = (size_t)ncomp * B * B * B * sizeof(typename Fixed<T>::acc_t);
-  const long long N = (long long)g.nx * g.ny * g.nz;
-  const unsigned nr = (unsigned)std::min<long long>((N + 255) / 256, 65536);
   if (g.shape_order == 1) allow_lds((const void*)k_deposit_tiled<T, 1>, lds);
   else allow_lds((const void*)k_deposit_tiled<T, 3>, lds);
-  if (g.shape_order == 1) {
-    hipLaunchKernelGGL((k_deposit_tiled<T, 1>), dim3(t.ntiles), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm, starts, out, stage,
-                       qdv, wj, hx, hy, hz, bad);
+  if (g.shape_order == 1)
+    hipLaunchKernelGGL((k_deposit_tiled<T, 1>), dim3(t.ntiles), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm, starts,
+                       out, stage, qdv, wj, hx, hy, hz, bad);
+  else
+    hipLaunchKernelGGL((k_deposit_tiled<T, 3>), dim3(t.ntiles), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm, starts,
+                       out, stage, qdv, wj, hx, hy, hz, bad);
+}
+
+template <typename T>
+void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, const T* stage, bool with_j, T* rho,
+                    T* const J[3], hipStream_t s) {
+  Batch<T*> out{};
+  out.p[0] = rho;
+  for (int d = 0; d < 3; ++d) out.p[1 + d] = J ? J[d] : nullptr;
+  const int ncomp = with_j ? 4 : 1;
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  const unsigned nr = (unsigned)std::min<long long>((N + 255) / 256, 65536);
+  if (g.shape_order == 1)
     hipLaunchKernelGGL((k_deposit_reduce<T, 1>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, out, ncomp);
-  } else {
-    hipLaunchKernelGGL((k_deposit_tiled<T, 3>), dim3(t.ntiles), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm, starts, out, stage,
-                       qdv, wj, hx, hy, hz, bad);
+  else
     hipLaunchKernelGGL((k_deposit_reduce<T, 3>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, out, ncomp);
-  }
 }
 
 #define PIC_INST(T)                                                                                              \
@@ -663,7 +673,9 @@ void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& s
                                const SpeciesView<T>&, const int*, int*, hipStream_t);                            \
   template void permute_species<T>(const SpeciesView<T>&, const SpeciesView<T>&, const int*, hipStream_t);       \
   template void deposit_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*, const int*, \
-                                 T*, T* const*, bool, T*, int*, hipStream_t);                                    \
+                                 bool, T*, int*, T*, T* const*, hipStream_t);                                    \
+  template void deposit_reduce<T>(const GridGeom&, const TileGeom&, const int*, const T*, bool, T*, T* const*,   \
+                                  hipStream_t);                                                                  \
   template void gather_push_tiled<T>(const GridGeom&, const TileGeom&, const T* const*, const T* const*,         \
                                      const SpeciesView<T>&, const SpeciesView<T>&, const int*, const int*, bool,  \
                                      int*, hipStream_t);
