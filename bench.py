@@ -138,6 +138,10 @@ def main():
     ap.add_argument("--dtype", default=None, choices=["f32", "f64"])
     ap.add_argument("--center-order", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep-center-orders", default="", metavar="LIST",
+                    help="after the main measurement, time the same workload at each centering order of the "
+                         "comma-separated LIST ([sweep] lines on stderr, and JSON lines into --extra-json)")
+    ap.add_argument("--extra-json", default="", metavar="PATH")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy a MIB-MiB float32 tensor 3 times (a plain copy kernel "
                          "of known size, the reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -151,46 +155,69 @@ def main():
     import torch
 
     from paper_2106_12919_amd import inputs
-    from paper_2106_12919_amd import lib as piclib
 
     torch.cuda.set_device(0)
     wl = inputs.config(args.config, dtype=args.dtype, center_order=args.center_order)
     print(f"[bench] workload {args.config} dtype={wl.dtype} cells={wl.cells} particles={wl.electrons.n}",
           file=sys.stderr, flush=True)
+    result = run_gpu(wl, args.config, args.steps, args.warmup, args.calibrate_copy)
+    if args.sweep_center_orders:
+        for order in [int(x) for x in args.sweep_center_orders.split(",")]:
+            wl.center_order = order
+            r = run_gpu(wl, args.config, args.steps, args.warmup, 0)
+            line = {"sweep": "center_order", "center_order": order, "dtype": wl.dtype, "value": r["value"],
+                    "ms_per_step": r["ms_per_step"], "cell_updates_per_s": r["cell_updates_per_s"],
+                    "stages": {k: v["ms_avg"] for k, v in r["stages"].items()}}
+            print("[sweep] " + json.dumps(line), file=sys.stderr, flush=True)
+            if args.extra_json:
+                with open(args.extra_json, "a") as fh:
+                    fh.write(json.dumps(line) + "\n")
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample ...", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(wl, result["config"]["particles"])
+    print(json.dumps(result))
+
+
+def run_gpu(wl, config_name, steps, warmup, calibrate_copy):
+    """Times ``steps`` hybrid cycles of the workload (one pic_step call) after ``warmup`` steps."""
+    import torch
+
+    from paper_2106_12919_amd import lib as piclib
+
     ctx = piclib.Context.for_workload(wl)
     f = ctx.fields_from_workload(wl)
     el = piclib.Species.from_host(wl.electrons, wl.shape, wl.dtype)
     ions = piclib.Species.from_host(wl.ions, wl.shape, wl.dtype)
     ctx.init_charge(f, el, ions)
     del ions
-    piclib.pic_step(ctx.ctx, f, [el], args.warmup)
+    piclib.pic_step(ctx.ctx, f, [el], warmup)
     piclib.pic_sync(ctx.ctx)
-    print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
-    if args.calibrate_copy > 0:
-        n = args.calibrate_copy * (1 << 20) // 4
+    print(f"[bench] warmup {warmup} steps done", file=sys.stderr, flush=True)
+    if calibrate_copy > 0:
+        n = calibrate_copy * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(f"[bench] calibration copy: 3 x {args.calibrate_copy} MiB", file=sys.stderr, flush=True)
+        print(f"[bench] calibration copy: 3 x {calibrate_copy} MiB", file=sys.stderr, flush=True)
         del src, dst
 
     piclib.pic_stage_times(ctx.ctx)  # reset
     piclib.pic_profile(ctx.ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    piclib.pic_step(ctx.ctx, f, [el], args.steps)
+    piclib.pic_step(ctx.ctx, f, [el], steps)
     piclib.pic_sync(ctx.ctx)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     stages = piclib.pic_stage_times(ctx.ctx)
     piclib.pic_profile(ctx.ctx, False)
     W, Q = piclib.pic_diagnostics(ctx.ctx, f)
-    print(f"[bench] timed {args.steps} steps in {T:.4f} s; field energy {W:.6e}, total charge {Q:.3e}",
+    print(f"[bench] timed {steps} steps in {T:.4f} s; field energy {W:.6e}, total charge {Q:.3e}",
           file=sys.stderr, flush=True)
 
-    K = args.steps
+    K = steps
     N = wl.cells
     M = wl.shape[0] * wl.shape[1] * (wl.shape[2] // 2 + 1)
     Np = el.n
@@ -203,35 +230,33 @@ def main():
         b = stage_bytes(name, N, M, Np, s)
         breakdown[name] = {"ms_avg": round(avg, 5), "launches": cnt, "algo_bytes": b,
                            "GBps": round(b / (avg * 1e-3) / 1e9, 1)}
-    dom = max((k for k in breakdown if k != "entry_forward"), key=lambda k: breakdown[k]["ms_avg"] * breakdown[k]["launches"])
+    dom = max((k for k in breakdown if k != "entry_forward"),
+              key=lambda k: breakdown[k]["ms_avg"] * breakdown[k]["launches"])
     d = breakdown[dom]
     achieved = d["algo_bytes"] / (d["ms_avg"] * 1e-3) / 1e9
-    result = {
+    ctx.close()
+    return {
         "metric": "particle-pushes/s and grid-cell updates/s per PIC step, FP32 vs FP64, fwd and fwd+bwd",
         "value": Np * K / T,
         "unit": "particle-pushes/s",
         "n_gpus": 1,
         "steps": K,
-        "warmup": args.warmup,
+        "warmup": warmup,
         "ms_per_step": 1e3 * T / K,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": wl.dtype,
         "data": "synthetic (seeded laser + plasma workload)",
-        "config": {"workload": CONFIG_TEXT[args.config], "cells": N, "particles": Np,
+        "config": {"workload": CONFIG_TEXT[config_name], "cells": N, "particles": Np,
                    "center_order": wl.center_order, "shape_order": wl.shape_order, "pass": "forward"},
         "cell_updates_per_s": N * K / T,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(dom),
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic(dom) if (config_name == "laser128" and wl.dtype == "f32") else None,
                      "algo_bytes_per_launch": d["algo_bytes"], "ms_per_launch": d["ms_avg"]},
         "stages": breakdown,
     }
-    ctx.close()
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle sample ...", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(wl, Np)
-    print(json.dumps(result))
 
 
 if __name__ == "__main__":

@@ -363,7 +363,7 @@ struct MaxWeight<3> {
 // Integer LDS atomics retire about 20x faster than float LDS atomics on gfx950.
 template <typename T, int ORDER>
 __device__ inline void scatter_lds(typename Fixed<T>::acc_t* box, int B, int lx, int ly, int lz, T ox, T oy, T oz,
-                                   const T* val, int nval, int sh) {
+                                   const T* val, int nval, const int* sh) {
   using S = Shape<T, ORDER>;
   constexpr int NW = S::NW;
   T wx[NW], wy[NW], wz[NW];
@@ -372,7 +372,7 @@ __device__ inline void scatter_lds(typename Fixed<T>::acc_t* box, int B, int lx,
   S::weights(oz, wz);
   const int B3 = B * B * B;
   T sv[3];
-  for (int q = 0; q < nval; ++q) sv[q] = ldexp(val[q], sh);
+  for (int q = 0; q < nval; ++q) sv[q] = ldexp(val[q], sh[q]);
 #pragma unroll
   for (int a = 0; a < NW; ++a) {
 #pragma unroll
@@ -412,8 +412,9 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
   using acc_t = typename Fixed<T>::acc_t;
   extern __shared__ __align__(16) unsigned char smem[];
   acc_t* box = reinterpret_cast<acc_t*>(smem);
-  __shared__ T red[PIC_DEPOSIT_BLOCK / 64];
-  __shared__ T redm[PIC_DEPOSIT_BLOCK / 64];
+  constexpr int kWaves = PIC_DEPOSIT_BLOCK / 64;
+  __shared__ T red[4 * kWaves];
+  __shared__ T redm[4 * kWaves];
   const int tile = blockIdx.x;
   const int beg = starts[tile], end = starts[tile + 1];
   if (beg == end) return;
@@ -421,44 +422,56 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
   const int B = ts + NW + 1;
   const int B3 = B * B * B;
   const int ncomp = with_j ? 4 : 1;
-  // Fixed-point scale 2^sh.  A node of this box receives, from each particle of the
-  // tile, at most MaxWeight * |q w| / dV (|v| < c): every partial sum is bounded by
-  // MaxWeight * sum|q w| / dV < 2^e_sum, every contribution by max|q w| / dV < 2^e_max.
-  T sw = 0, mw = 0;
-  if (sp.w) {
-    for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
-      const T a = fabs(sp.w[perm ? perm[qq] : qq]);
-      sw += a;
-      mw = fmax(mw, a);
+  // Fixed-point scales 2^sh[c], one per deposited component.  A node of this box
+  // receives from each particle of the tile at most MaxWeight * |q w| / dV (rho) or
+  // MaxWeight * |q w v_c| / dV (J^c): every partial sum is bounded by MaxWeight times the
+  // tile's sum of those magnitudes (< 2^e_sum), every contribution by their max (< 2^e_max).
+  // per component c (rho, J^x, J^y, J^z): sum and max over the tile of |q w| (rho) or
+  // |q w v_c| (J^c), the bounds that set that component's scale
+  T sw[4] = {0, 0, 0, 0}, mw[4] = {0, 0, 0, 0};
+  for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
+    const int p = perm ? perm[qq] : qq;
+    const T a = fabs(sp.w ? sp.w[p] : (T)sp.w_const);
+    sw[0] += a;
+    mw[0] = fmax(mw[0], a);
+    if (with_j) {
+      const T ux = sp.u[0][p], uy = sp.u[1][p], uz = sp.u[2][p];
+      const T ig = (T)1 / sqrt((T)1 + ux * ux + uy * uy + uz * uz);
+      const T v[3] = {fabs(ux * ig), fabs(uy * ig), fabs(uz * ig)};
+      for (int d = 0; d < 3; ++d) {
+        sw[1 + d] += a * v[d];
+        mw[1 + d] = fmax(mw[1 + d], a * v[d]);
+      }
     }
-  } else {
-    sw = (threadIdx.x == 0) ? fabs((T)sp.w_const) * (T)(end - beg) : (T)0;
-    mw = fabs((T)sp.w_const);
   }
-  for (int o = 32; o > 0; o >>= 1) {
-    sw += __shfl_xor(sw, o, 64);
-    mw = fmax(mw, __shfl_xor(mw, o, 64));
-  }
-  if ((threadIdx.x & 63) == 0) {
-    red[threadIdx.x >> 6] = sw;
-    redm[threadIdx.x >> 6] = mw;
+  for (int c = 0; c < ncomp; ++c) {
+    for (int o = 32; o > 0; o >>= 1) {
+      sw[c] += __shfl_xor(sw[c], o, 64);
+      mw[c] = fmax(mw[c], __shfl_xor(mw[c], o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[c * kWaves + (threadIdx.x >> 6)] = sw[c];
+      redm[c * kWaves + (threadIdx.x >> 6)] = mw[c];
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  __shared__ int shs[4];
+  if (threadIdx.x < ncomp) {
+    const int c = threadIdx.x;
     T m = 0, x = 0;
-    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) {
-      m += red[w];
-      x = fmax(x, redm[w]);
+    for (int w = 0; w < kWaves; ++w) {
+      m += red[c * kWaves + w];
+      x = fmax(x, redm[c * kWaves + w]);
     }
     // a little slack on the bound covers the rounding of the FP sum itself
-    red[0] = m * fabs(qdv) * (T)(MaxWeight<ORDER>::value * 1.001);
-    redm[0] = x * fabs(qdv);
+    int e_sum = 0, e_max = 0;
+    (void)frexp(m * fabs(qdv) * (T)(MaxWeight<ORDER>::value * 1.001), &e_sum);
+    (void)frexp(x * fabs(qdv) * (T)1.001, &e_max);
+    shs[c] = Fixed<T>::shift(e_sum, e_max, 32 - __clz(end - beg));
   }
   __syncthreads();
-  int e_sum = 0, e_max = 0;
-  (void)frexp(red[0], &e_sum);
-  (void)frexp(redm[0], &e_max);
-  const int sh = Fixed<T>::shift(e_sum, e_max, 32 - __clz(end - beg));
+  int sh[4];
+  for (int c = 0; c < 4; ++c) sh[c] = (c < ncomp) ? shs[c] : 0;
   const int tk = tile % tg.ntz;
   const int tr = tile / tg.ntz;
   const int tj = tr % tg.nty;
@@ -495,7 +508,7 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
       const int lx = box_index(ih, t0x, g.nx, ts), ly = box_index(jh, t0y, g.ny, ts),
                 lz = box_index(kh, t0z, g.nz, ts);
       if (lx >= 0 && ly >= 0 && lz >= 0) {
-        scatter_lds<T, ORDER>(box + B3, B, lx, ly, lz, hx, hy, hz, val, 3, sh);
+        scatter_lds<T, ORDER>(box + B3, B, lx, ly, lz, hx, hy, hz, val, 3, sh + 1);
       } else {
         T* dst[3] = {out.p[1], out.p[2], out.p[3]};
         scatter<T, ORDER>(g, ih, jh, kh, hx, hy, hz, dst, val, 3);
@@ -505,7 +518,7 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
   __syncthreads();
   // the whole box goes to this tile's staging slot (plain stores, zeros included)
   T* dstage = stage + (size_t)tile * ncomp * B3;
-  for (int k = threadIdx.x; k < ncomp * B3; k += blockDim.x) dstage[k] = ldexp((T)box[k], -sh);
+  for (int k = threadIdx.x; k < ncomp * B3; k += blockDim.x) dstage[k] = ldexp((T)box[k], -sh[k / B3]);
 }
 
 // Sums, for every grid node, the staging boxes of all non-empty tiles that cover it

@@ -1,0 +1,99 @@
+"""Parity at the full sizes of the named workloads, in the launch configuration bench.py times.
+
+* thermal32 (32^3, 262,144 particles, CIC, centering 8, FP64): all 10 steps of the
+  configuration, compared with the FP64 oracle after every step.
+* laser128 (128x128x256, 6,291,456 particles, cubic, centering 16, FP32, the bench
+  workload): one full pic_step compared field by field with the oracle run on the
+  same FP32-rounded inputs, and every particle compared (identities by weight).
+"""
+
+import numpy as np
+import pytest
+
+from gpu_common import banner, max_rel, np64, oracle_species, periodic_pos_err
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import diagnostics  # noqa: E402
+from oracle import step as ostep  # noqa: E402
+from paper_2106_12919_amd import inputs  # noqa: E402
+from paper_2106_12919_amd import lib as piclib  # noqa: E402
+
+
+def rounded(arrs, dtype):
+    npd = np.float32 if dtype == "f32" else np.float64
+    return [np.asarray(a).astype(npd).astype(np.float64) for a in arrs]
+
+
+def distinct_weights(wl):
+    """Weights 2^k (1 + p 2^-23): exact and distinct in FP32, so they identify particles
+    (pic_step regroups particles); the ions share them, so the plasma stays neutral."""
+    n = wl.electrons.n
+    assert n < 2 ** 23
+    base = 2.0 ** np.floor(np.log2(wl.electrons.w[0]))
+    wl.electrons.w = base * (1.0 + np.arange(n) * 2.0 ** -23)
+    wl.ions.w = wl.electrons.w
+
+
+def setup(wl, ids=False):
+    if ids:
+        distinct_weights(wl)
+    ctx = piclib.Context.for_workload(wl)
+    f = ctx.fields_from_workload(wl)
+    el = piclib.Species.from_host(wl.electrons, wl.shape, wl.dtype)
+    ions = piclib.Species.from_host(wl.ions, wl.shape, wl.dtype)
+    ctx.init_charge(f, el, ions)
+    p = ostep.Params(wl.shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order)
+    osp = oracle_species(el, wl.shape, wl.spacing)
+    oion = oracle_species(ions, wl.shape, wl.spacing)
+    rho_static = ostep.deposit_rho([oion], p)
+    state = {"E_stag": rounded(wl.E, wl.dtype), "B_stag": rounded(wl.B, wl.dtype),
+             "rho_old": ostep.deposit_rho([osp], p, rho_static)}
+    return ctx, f, el, p, osp, state, rho_static
+
+
+def test_thermal32_fp64_all_steps():
+    banner("full size thermal32 FP64, 10 steps")
+    wl = inputs.config("thermal32")
+    ctx, f, el, p, osp, state, rho_static = setup(wl)
+    for n in range(wl.steps):
+        piclib.pic_step(ctx.ctx, f, [el], 1)
+        piclib.pic_sync(ctx.ctx)
+        ostep.step(state, [osp], p, rho_static)
+        for d in range(3):
+            assert max_rel(np64(f.E_stag[d]), state["E_stag"][d]) <= 1e-10, (n, "E", d)
+            assert max_rel(np64(f.B_stag[d]), state["B_stag"][d]) <= 1e-10, (n, "B", d)
+        assert max_rel(np64(f.rho_old), state["rho_old"]) <= 1e-10
+        W_gpu, Q_gpu = piclib.pic_diagnostics(ctx.ctx, f)
+        W_ref = diagnostics.field_energy(state["E_stag"], state["B_stag"], p.spacing)
+        assert W_gpu == pytest.approx(W_ref, rel=1e-10)
+        assert abs(Q_gpu) <= 1e-12 * abs(np.sum(osp["q"] * osp["w"]))
+    ctx.close()
+
+
+def test_laser128_fp32_one_step():
+    banner("full size laser128 FP32, 1 step (bench launch configuration)")
+    wl = inputs.config("laser128")
+    ctx, f, el, p, osp, state, rho_static = setup(wl, ids=True)
+    piclib.pic_step(ctx.ctx, f, [el], 1)
+    piclib.pic_sync(ctx.ctx)
+    out = ostep.step(state, [osp], p, rho_static)
+    # FP32 against the FP64 oracle on the same rounded inputs: fields after one step
+    for d in range(3):
+        assert max_rel(np64(f.E_stag[d]), state["E_stag"][d]) <= 2e-5, ("E", d)
+        assert max_rel(np64(f.B_stag[d]), state["B_stag"][d]) <= 2e-5, ("B", d)
+        assert max_rel(np64(f.J_nod[d]), out["J_nod"][d]) <= 2e-5, ("J", d)
+    W_gpu, _ = piclib.pic_diagnostics(ctx.ctx, f)
+    W_ref = diagnostics.field_energy(state["E_stag"], state["B_stag"], p.spacing)
+    assert abs(W_gpu - W_ref) <= 1e-5 * W_ref
+    # every particle, matched by its weight
+    g_w = np64(el.w)
+    gi, oi = np.argsort(g_w), np.argsort(osp["w"])
+    assert np.array_equal(g_w[gi], osp["w"][oi])
+    g_pos = el.positions(wl.shape, wl.spacing)[gi]
+    g_u = np.stack([np64(x) for x in el.u], axis=1)[gi]
+    assert periodic_pos_err(g_pos, osp["pos"][oi], p.lengths) <= 1e-5
+    assert np.max(np.abs(g_u - osp["u"][oi])) <= 1e-5 * (1 + np.max(np.abs(osp["u"])))
+    ctx.close()

@@ -1,0 +1,109 @@
+"""FP32 error statement: the FP32 HIP path against the FP64 oracle on the FP64 inputs.
+
+For each workload and step: max and L2 relative error of every E, B component
+(Sec. 5.2 eq. L2_norm_error), max momentum error relative to max |u|, the
+relative field-energy difference |W32 - W64| / W64, and the charge error of the
+deposit |sum rho_e dV - sum q w| / |sum q w|.  Targets: 1e-5 on field energy,
+1e-6 on charge.  Particles are identified by distinct weights 2^k (1 + p 2^-23)
+(exact in FP32; the ions share them, so the plasma stays neutral).
+
+Long (minutes of oracle time): runs only with PIC_LONG_TESTS=1.  Each workload
+writes its table to gpurun_out/precision_<name>.json.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import ROOT, banner, np64, oracle_species
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not os.environ.get("PIC_LONG_TESTS"),
+                                 reason="long FP32-vs-FP64 error statement; set PIC_LONG_TESTS=1")]
+
+torch = pytest.importorskip("torch")
+
+from oracle import diagnostics  # noqa: E402
+from oracle import step as ostep  # noqa: E402
+from paper_2106_12919_amd import inputs  # noqa: E402
+from paper_2106_12919_amd import lib as piclib  # noqa: E402
+
+
+def thermal_proxy(center_order):
+    """thermal256's per-cell physics (8 ppc, u_th = 0.05, n0 = 0.01, CIC) on a 64^3 box."""
+    rng = np.random.Generator(np.random.PCG64(1003))
+    shape = (64, 64, 64)
+    el = inputs.uniform_plasma(rng, shape, 8, 0.01, 0.05)
+    zero = [np.zeros(shape) for _ in range(3)]
+    return inputs.Workload(f"thermal64_o{center_order}", shape, (1.0, 1.0, 1.0), 0.5, 1, center_order, 16, "f32",
+                           10, el, inputs.ions_of(el), [z.copy() for z in zero], [z.copy() for z in zero])
+
+
+def run_statement(wl, nsteps):
+    n = wl.electrons.n
+    base = 2.0 ** np.floor(np.log2(wl.electrons.w[0]))
+    wl.electrons.w = base * (1.0 + np.arange(n) * 2.0 ** -23)
+    wl.ions.w = wl.electrons.w
+    ctx = piclib.Context.for_workload(wl)
+    f = ctx.fields_from_workload(wl)
+    el = piclib.Species.from_host(wl.electrons, wl.shape, "f32")
+    ions = piclib.Species.from_host(wl.ions, wl.shape, "f32")
+    ctx.init_charge(f, el, ions)
+    p = ostep.Params(wl.shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order)
+    osp = {"pos": wl.electrons.positions(wl.spacing), "u": wl.electrons.u.copy(), "w": wl.electrons.w,
+           "q": -1.0, "m": 1.0}
+    oion = {"pos": wl.ions.positions(wl.spacing), "u": wl.ions.u, "w": wl.ions.w, "q": 1.0, "m": np.inf}
+    rho_static = ostep.deposit_rho([oion], p)
+    state = {"E_stag": [np.array(a) for a in wl.E], "B_stag": [np.array(a) for a in wl.B],
+             "rho_old": ostep.deposit_rho([osp], p, rho_static)}
+    qe = abs(float(np.sum(osp["q"] * osp["w"])))
+    rows = []
+    for step in range(1, nsteps + 1):
+        piclib.pic_step(ctx.ctx, f, [el], 1)
+        piclib.pic_sync(ctx.ctx)
+        out = ostep.step(state, [osp], p, rho_static)
+        row = {"step": step}
+        for name, gl, rl in (("E", f.E_stag, state["E_stag"]), ("B", f.B_stag, state["B_stag"])):
+            for d, ax in enumerate("xyz"):
+                g, r = np64(gl[d]), rl[d]
+                scale = np.max(np.abs(r))
+                row[f"{name}{ax}_max"] = float(np.max(np.abs(g - r)) / scale) if scale > 0 else 0.0
+                row[f"{name}{ax}_l2"] = diagnostics.rel_l2(r, g) if scale > 0 else 0.0
+        W32, _ = piclib.pic_diagnostics(ctx.ctx, f)
+        W64 = diagnostics.field_energy(state["E_stag"], state["B_stag"], p.spacing)
+        row["W_rel"] = abs(W32 - W64) / W64 if W64 > 0 else abs(W32)
+        rho_e = np64(f.rho_new) - rho_static
+        row["charge_rel"] = abs(float(np.sum(rho_e)) * np.prod(p.spacing) + qe) / qe
+        g_w = np64(el.w)
+        gi, oi = np.argsort(g_w), np.argsort(osp["w"])
+        g_u = np.stack([np64(x) for x in el.u], axis=1)[gi]
+        umax = np.max(np.abs(osp["u"]))
+        row["u_max"] = float(np.max(np.abs(g_u - osp["u"][oi])) / umax) if umax > 0 else 0.0
+        rows.append(row)
+        del out
+    ctx.close()
+    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+    with open(os.path.join(ROOT, "gpurun_out", f"precision_{wl.name}.json"), "w") as fh:
+        json.dump({"workload": wl.name, "steps": rows}, fh, indent=1)
+    print(json.dumps({"workload": wl.name, "last": rows[-1]}))
+    return rows
+
+
+@pytest.mark.parametrize("name,nsteps", [("laser64", 10), ("laser128", 4)])
+def test_laser_fp32_statement(name, nsteps):
+    banner(f"precision statement {name} {nsteps} steps")
+    rows = run_statement(inputs.config(name), nsteps)
+    for r in rows:
+        assert r["W_rel"] <= 1e-5
+        assert r["charge_rel"] <= 1e-6
+
+
+@pytest.mark.parametrize("center_order", [2, 4, 8, 16, 32])
+def test_thermal_fp32_statement(center_order):
+    banner(f"precision statement thermal64 proxy, centering {center_order}")
+    rows = run_statement(thermal_proxy(center_order), 10)
+    for r in rows:
+        assert r["W_rel"] <= 1e-5
+        assert r["charge_rel"] <= 1e-6
