@@ -117,6 +117,10 @@ struct SpeciesScratch {
   T* w = nullptr;
   int* dst = nullptr;
   int* perm = nullptr;
+  // tile groupings of pic_step: counts[ntiles + 1], starts[ntiles + 2] (two, alternating)
+  int* counts[2] = {nullptr, nullptr};
+  int* starts[2] = {nullptr, nullptr};
+  int* cursor = nullptr;
 };
 
 template <typename T>
@@ -163,12 +167,19 @@ struct Engine : EngineBase {
     if (sps.size() <= s) sps.resize(s + 1);
     SpeciesScratch<T>& x = sps[s];
     if (x.cap >= n) return hipSuccess;
-    void* old[10] = {x.cell, x.off[0], x.off[1], x.off[2], x.u[0], x.u[1], x.u[2], x.w, x.dst, x.perm};
+    void* old[15] = {x.cell, x.off[0], x.off[1], x.off[2], x.u[0], x.u[1], x.u[2], x.w, x.dst, x.perm,
+                     x.counts[0], x.counts[1], x.starts[0], x.starts[1], x.cursor};
     for (void* q : old)
       if (q) (void)release_one(q);
     x = SpeciesScratch<T>{};
     hipError_t e;
     const size_t m = (size_t)(n > 0 ? n : 1);
+    const size_t nt = (size_t)tiles.ntiles;
+    for (int b = 0; b < 2; ++b) {
+      if ((e = alloc(&x.counts[b], nt + 1)) != hipSuccess) return e;
+      if ((e = alloc(&x.starts[b], nt + 2)) != hipSuccess) return e;
+    }
+    if ((e = alloc(&x.cursor, nt + 1)) != hipSuccess) return e;
     if ((e = alloc(&x.cell, m)) != hipSuccess) return e;
     for (int d = 0; d < 3; ++d) {
       if ((e = alloc(&x.off[d], m)) != hipSuccess) return e;
@@ -399,7 +410,7 @@ pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, 
     tile_sort(g, e.tiles, v.cell, v.n, e.t_counts, e.t_starts, e.t_cursor, x.dst, c->d_bad, c->stream);
     invert_perm(x.dst, x.perm, v.n, c->stream);
     const bool mobile = std::isfinite(sp[s].m);
-    deposit_tiled<T>(g, e.tiles, v, x.perm, e.t_starts, with_j && mobile, e.stage, c->d_bad,
+    deposit_tiled<T>(g, e.tiles, v, x.perm, e.t_starts, with_j && mobile, e.stage, c->d_bad, nullptr,
                      static_cast<T*>(f->rho_new), J, c->stream);
     deposit_reduce<T>(g, e.tiles, e.t_starts, e.stage, with_j && mobile, static_cast<T*>(f->rho_new), J, c->stream);
   }
@@ -429,7 +440,7 @@ pic_status do_gather_push(pic_ctx c, const pic_fields* f, pic_species* sp, int n
       // tile order through a permutation; every particle is updated in place
       tile_sort(g, e.tiles, v.cell, v.n, e.t_counts, e.t_starts, e.t_cursor, x.dst, c->d_bad, c->stream);
       invert_perm(x.dst, x.perm, v.n, c->stream);
-      gather_push_tiled<T>(g, e.tiles, E, B, v, v, x.perm, e.t_starts, false, c->d_bad, c->stream);
+      gather_push_tiled<T>(g, e.tiles, E, B, v, v, x.perm, e.t_starts, false, nullptr, c->stream);
     }
   return c->check("pic_gather_push");
 }
@@ -542,6 +553,7 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
   T* Jn[3];
   J_ptrs<T>(f, Jn);
   std::vector<char> in_scratch(nsp, 0);
+  std::vector<int> layout(nsp, 0);  // which of the species' two groupings describes its current arrays
   for (int q = 0; q < nsp; ++q) {
     hipError_t he = e.ensure_species((size_t)q, sp[q].n);
     if (he != hipSuccess) return c->fail(PIC_ENOMEM, std::string("pic_step: ") + hipGetErrorString(he));
@@ -563,28 +575,45 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
       const SpeciesView<T> cur = in_scratch[q] ? scratch_view<T>(x, sp[q]) : view<T>(sp[q]);
       const SpeciesView<T> alt = in_scratch[q] ? view<T>(sp[q]) : scratch_view<T>(x, sp[q]);
       const bool mobile = std::isfinite(sp[q].m);
+      const size_t nt = (size_t)e.tiles.ntiles;
+      // Grouping: on the first step a full counting sort of the caller's order; afterwards
+      // the deposition of the previous step has counted the tiles of the current cells.
+      const int L = layout[q];
+      const bool first = (n == 0);
       {
         StageScope sc(c, ST_SORT);
-        tile_sort(g, e.tiles, cur.cell, cur.n, e.t_counts, e.t_starts, e.t_cursor, x.dst, c->d_bad, c->stream);
-        if (mobile) invert_perm(x.dst, x.perm, cur.n, c->stream);
+        if (first) {
+          tile_sort(g, e.tiles, cur.cell, cur.n, x.counts[0], x.starts[0], x.cursor, x.dst, c->d_bad, c->stream);
+          invert_perm(x.dst, x.perm, cur.n, c->stream);
+        } else if (mobile) {
+          scan_counts(e.tiles, x.counts[1 - L], x.starts[1 - L], x.cursor, c->stream);
+        }
+        if (mobile) (void)hipMemsetAsync(x.counts[first ? 1 : L], 0, sizeof(int) * (nt + 1), c->stream);
       }
+      const int* dep_starts = first ? x.starts[0] : (mobile ? x.starts[1 - L] : x.starts[L]);
       {
         StageScope sc(c, ST_PUSH);
-        if (mobile)
-          gather_push_tiled<T>(g, e.tiles, Enod, Bnod, cur, alt, x.perm, e.t_starts, true, c->d_bad, c->stream);
-        else
+        if (first && mobile)
+          gather_push_tiled<T>(g, e.tiles, Enod, Bnod, cur, alt, x.perm, x.starts[0], true, nullptr, c->stream);
+        else if (first)
           permute_species<T>(cur, alt, x.dst, c->stream);
+        else if (mobile)
+          gather_push_tiled<T>(g, e.tiles, Enod, Bnod, cur, alt, nullptr, x.starts[L], true, x.cursor, c->stream);
       }
+      const SpeciesView<T> dep = (first || mobile) ? alt : cur;  // immobile species stay put after the first step
       {
         StageScope sc(c, ST_DEPOSIT);
-        deposit_tiled<T>(g, e.tiles, alt, nullptr, e.t_starts, mobile, e.stage, c->d_bad, static_cast<T*>(f->rho_new),
-                         Jn, c->stream);
+        int* nextc = mobile ? x.counts[first ? 1 : L] : nullptr;
+        deposit_tiled<T>(g, e.tiles, dep, nullptr, dep_starts, mobile, e.stage, c->d_bad, nextc,
+                         static_cast<T*>(f->rho_new), Jn, c->stream);
       }
       {
         StageScope sc(c, ST_REDUCE);
-        deposit_reduce<T>(g, e.tiles, e.t_starts, e.stage, mobile, static_cast<T*>(f->rho_new), Jn, c->stream);
+        deposit_reduce<T>(g, e.tiles, dep_starts, e.stage, mobile, static_cast<T*>(f->rho_new), Jn, c->stream);
       }
-      in_scratch[q] = !in_scratch[q];
+      if (first || mobile) in_scratch[q] = !in_scratch[q];
+      // layout index of the grouping the particles are now in
+      if (mobile) layout[q] = first ? 0 : 1 - L;
     }
     {
       StageScope sc(c, ST_N2S);

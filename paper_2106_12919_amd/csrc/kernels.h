@@ -66,29 +66,28 @@ struct TileGeom {
   int ts, ntx, nty, ntz, ntiles;
 };
 TileGeom make_tiles(const GridGeom& g, int ts);
-// Edge length (nodes) of the LDS box of one deposition tile (the tile's support plus a
-// one-cell margin) and of one gather tile (the tile's support).
+// Edge length (nodes) of the LDS boxes of one tile: the tile, the shape support and a
+// one-cell margin on each side (particles move less than one cell per step).
 int deposit_box(int shape_order, int ts);
-int gather_box(int shape_order, int ts);
 // Counting sort by tile of the particles' current cells: counts[ntiles+1],
 // starts[ntiles+2], cursor[ntiles+1] (scratch), dst[n] = each particle's slot in
 // tile order (tiles in order, then particles with invalid cells, counted in *bad).
 void tile_sort(const GridGeom& g, const TileGeom& t, const int32_t* cell, int64_t n, int* counts, int* starts,
                int* cursor, int* dst, int* bad, hipStream_t s);
 void invert_perm(const int* dst, int* perm, int64_t n, hipStream_t s);
+// Exclusive scan of counts[ntiles + 1] into starts[ntiles + 2] and cursor[ntiles + 1].
+void scan_counts(const TileGeom& t, const int* counts, int* starts, int* cursor, hipStream_t s);
 
-// Gather at the current positions and push; particle p of ``in`` is written to slot
-// dst[p] of ``out`` (dst == nullptr: slot p; ``out`` may alias ``in`` only then).
-template <typename T>
-void gather_push(const GridGeom& g, const T* const E[3], const T* const B[3], const SpeciesView<T>& in,
-                 const SpeciesView<T>& out, const int* dst, int* bad, hipStream_t s);
-// Tile-ordered gather + push: slot q of tile t (q in [starts[t], starts[t+1])) reads
+// Tile-ordered gather + push.  Either through a permutation (home_cursor == nullptr):
+// slot q of tile t (q in [starts[t], starts[t+1]), tiles of the current cells) reads
 // particle perm[q] of ``in`` and writes it to slot q of ``out`` (write_sorted) or to
-// perm[q] (in place when out == in).
+// perm[q] (in place when out == in); or, in pic_step's steady state, ``in`` grouped by
+// home tile (starts = home ranges) is written to ``out`` grouped by the tile of each
+// particle's current cell, slots reserved per block from home_cursor (the new starts).
 template <typename T>
 void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3], const T* const B[3],
                        const SpeciesView<T>& in, const SpeciesView<T>& out, const int* perm, const int* starts,
-                       bool write_sorted, int* bad, hipStream_t s);
+                       bool write_sorted, int* home_cursor, hipStream_t s);
 template <typename T>
 void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const int* dst, hipStream_t s);
 // Deposition of one species in two launches.  deposit_tiled accumulates rho (at the
@@ -97,9 +96,11 @@ void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const 
 // q) into per-tile boxes in ``stage`` (ntiles * (with_j ? 4 : 1) * deposit_box^3
 // elements); particles that left the one-cell margin go straight to rho/J.
 // deposit_reduce then adds the overlapping boxes to the nodal arrays.
+// With next_counts != nullptr, the particles are also counted per tile of their cells
+// (the grouping of the next step), into next_counts[ntiles + 1] (invalid cells last).
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
-                   bool with_j, T* stage, int* bad, T* rho, T* const J[3], hipStream_t s);
+                   bool with_j, T* stage, int* bad, int* next_counts, T* rho, T* const J[3], hipStream_t s);
 template <typename T>
 void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, const T* stage, bool with_j, T* rho,
                     T* const J[3], hipStream_t s);

@@ -93,54 +93,136 @@ __device__ inline int advance_offset(T& off, T disp) {
   return sh;
 }
 
+// ---------------------------------------------------------------- tiles
+
+__device__ inline void tile_coords(int tile, const TileGeom& tg, int& tx, int& ty, int& tz) {
+  tz = tile % tg.ntz;
+  const int r = tile / tg.ntz;
+  ty = r % tg.nty;
+  tx = r / tg.nty;
+}
+
+__device__ inline int tile_of(int i, int j, int k, const TileGeom& tg) {
+  return ((i / tg.ts) * tg.nty + j / tg.ts) * tg.ntz + k / tg.ts;
+}
+
+// Index 0..26 of ``key`` among the 27 tiles around (tx, ty, tz) (periodic), or -1.
+__device__ inline int neighbour_index(int key, int tx, int ty, int tz, const TileGeom& tg) {
+  int kx, ky, kz;
+  tile_coords(key, tg, kx, ky, kz);
+  int d[3] = {kx - tx, ky - ty, kz - tz};
+  const int nt[3] = {tg.ntx, tg.nty, tg.ntz};
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] > 1) d[a] -= nt[a];
+    if (d[a] < -1) d[a] += nt[a];
+    if (d[a] < -1 || d[a] > 1) return -1;
+  }
+  return ((d[0] + 1) * 3 + (d[1] + 1)) * 3 + (d[2] + 1);
+}
+
+__device__ inline int neighbour_key(int nb, int tx, int ty, int tz, const TileGeom& tg) {
+  const int dx = nb / 9 - 1, dy = (nb / 3) % 3 - 1, dz = nb % 3 - 1;
+  return (modi(tx + dx, tg.ntx) * tg.nty + modi(ty + dy, tg.nty)) * tg.ntz + modi(tz + dz, tg.ntz);
+}
+
+// box-local index (0 .. B-1) of the first support node of a particle in cell i of a
+// tile starting at cell t0, for boxes whose node 0 is t0 - 1 + BASE (one-cell
+// margin); -1 if the particle is outside the margin.
+__device__ inline int box_index(int i, int t0, int n, int ts) {
+  int l = (i - t0 + 1) % n;
+  if (l < 0) l += n;
+  return (l <= ts + 1) ? l : -1;
+}
+
+// ---------------------------------------------------------------- gather + push
+
+// Nodal field box in LDS, node-major with the six components adjacent (8 slots for
+// float: two 16-byte reads per node; 6 for double: three 16-byte reads).
+template <typename T>
+struct FieldSlots;
+template <>
+struct FieldSlots<float> {
+  static constexpr int FS = 8;
+  __device__ static inline void read(const float* p, float* v) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    const float2 b = *reinterpret_cast<const float2*>(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y;
+  }
+};
+template <>
+struct FieldSlots<double> {
+  static constexpr int FS = 6;
+  __device__ static inline void read(const double* p, double* v) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    const double2 c = *reinterpret_cast<const double2*>(p + 4);
+    v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x; v[5] = c.y;
+  }
+};
+
+// Stages the six nodal components over the B^3 box of tile (t0x, t0y, t0z).
 template <typename T, int ORDER>
-__global__ void __launch_bounds__(256) k_gather_push(GridGeom g, Batch<const T*> F, SpeciesView<T> in,
-                                                     SpeciesView<T> out, const int* __restrict__ dst, T qdt2m,
-                                                     T dtx, T dty, T dtz, int* bad) {
+__device__ inline void load_field_box(T* box, const Batch<const T*>& F, const GridGeom& g, int t0x, int t0y, int t0z,
+                                      int B) {
+  using S = Shape<T, ORDER>;
+  constexpr int FS = FieldSlots<T>::FS;
+  const int ox0 = t0x - 1 + S::BASE, oy0 = t0y - 1 + S::BASE, oz0 = t0z - 1 + S::BASE;
+  const int B3 = B * B * B;
+  for (int e = threadIdx.x; e < B3; e += blockDim.x) {
+    const int lx = e / (B * B), ly = (e / B) % B, lz = e % B;
+    const size_t gi = ((size_t)modi(ox0 + lx, g.nx) * g.ny + modi(oy0 + ly, g.ny)) * g.nz + modi(oz0 + lz, g.nz);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) box[e * FS + c] = F.p[c][gi];
+  }
+}
+
+// Gather at one particle from the LDS box (first support node at box index l*) or,
+// outside the margin, from the grid; then the relativistic Boris push and the move.
+template <typename T, int ORDER>
+__device__ inline void gather_push_one(const T* box, int B, const Batch<const T*>& F, const GridGeom& g, int lx, int ly,
+                                       int lz, int& i, int& j, int& k, T& ox, T& oy, T& oz, T& ux, T& uy, T& uz,
+                                       T qdt2m, T dtx, T dty, T dtz) {
   using S = Shape<T, ORDER>;
   constexpr int NW = S::NW;
-  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= in.n) return;
-  const long long q = dst ? dst[p] : p;  // output slot (tile order when dst is given)
-  int i, j, k;
-  const int c = in.cell[p];
-  if (!decode_cell(c, g, bad, i, j, k)) {  // carried along untouched
-    out.cell[q] = c;
-    for (int d = 0; d < 3; ++d) {
-      out.off[d][q] = in.off[d][p];
-      out.u[d][q] = in.u[d][p];
-    }
-    if (in.w) out.w[q] = in.w[p];
-    return;
-  }
-  T ox = in.off[0][p], oy = in.off[1][p], oz = in.off[2][p];
+  constexpr int FS = FieldSlots<T>::FS;
   T wx[NW], wy[NW], wz[NW];
   S::weights(ox, wx);
   S::weights(oy, wy);
   S::weights(oz, wz);
-  int kk[NW];
-#pragma unroll
-  for (int cc = 0; cc < NW; ++cc) kk[cc] = wrapi(k + cc + S::BASE, g.nz);
   T f[6] = {0, 0, 0, 0, 0, 0};
+  if (lx >= 0 && ly >= 0 && lz >= 0) {
 #pragma unroll
-  for (int a = 0; a < NW; ++a) {
-    const int ii = wrapi(i + a + S::BASE, g.nx);
+    for (int a = 0; a < NW; ++a) {
 #pragma unroll
-    for (int b = 0; b < NW; ++b) {
-      const int jj = wrapi(j + b + S::BASE, g.ny);
-      const size_t row = ((size_t)ii * g.ny + jj) * g.nz;
-      const T wab = wx[a] * wy[b];
+      for (int b = 0; b < NW; ++b) {
+        const int row = ((lx + a) * B + (ly + b)) * B + lz;
+        const T wab = wx[a] * wy[b];
 #pragma unroll
-      for (int cc = 0; cc < NW; ++cc) {
-        const T w = wab * wz[cc];
-        const size_t idx = row + kk[cc];
+        for (int cc = 0; cc < NW; ++cc) {
+          const T w = wab * wz[cc];
+          T v[6];
+          FieldSlots<T>::read(box + (size_t)(row + cc) * FS, v);
 #pragma unroll
-        for (int m = 0; m < 6; ++m) f[m] += w * F.p[m][idx];
+          for (int m = 0; m < 6; ++m) f[m] += w * v[m];
+        }
+      }
+    }
+  } else {
+    for (int a = 0; a < NW; ++a) {
+      const int ii = modi(i + a + S::BASE, g.nx);
+      for (int b = 0; b < NW; ++b) {
+        const int jj = modi(j + b + S::BASE, g.ny);
+        const size_t row = ((size_t)ii * g.ny + jj) * g.nz;
+        const T wab = wx[a] * wy[b];
+        for (int cc = 0; cc < NW; ++cc) {
+          const T w = wab * wz[cc];
+          const size_t idx = row + modi(k + cc + S::BASE, g.nz);
+          for (int m = 0; m < 6; ++m) f[m] += w * F.p[m][idx];
+        }
       }
     }
   }
   // relativistic Boris (c = 1)
-  const T ux = in.u[0][p], uy = in.u[1][p], uz = in.u[2][p];
   const T umx = ux + qdt2m * f[0], umy = uy + qdt2m * f[1], umz = uz + qdt2m * f[2];
   const T gm = sqrt((T)1 + umx * umx + umy * umy + umz * umz);
   const T tf = qdt2m / gm;
@@ -150,121 +232,145 @@ __global__ void __launch_bounds__(256) k_gather_push(GridGeom g, Batch<const T*>
   const T upx = umx + (umy * tz - umz * ty);
   const T upy = umy + (umz * tx - umx * tz);
   const T upz = umz + (umx * ty - umy * tx);
-  const T npx = umx + (upy * sz - upz * sy) + qdt2m * f[0];
-  const T npy = umy + (upz * sx - upx * sz) + qdt2m * f[1];
-  const T npz = umz + (upx * sy - upy * sx) + qdt2m * f[2];
-  const T ig = (T)1 / sqrt((T)1 + npx * npx + npy * npy + npz * npz);
-  i = modi(i + advance_offset(ox, dtx * npx * ig), g.nx);
-  j = modi(j + advance_offset(oy, dty * npy * ig), g.ny);
-  k = modi(k + advance_offset(oz, dtz * npz * ig), g.nz);
-  out.u[0][q] = npx;
-  out.u[1][q] = npy;
-  out.u[2][q] = npz;
-  out.off[0][q] = ox;
-  out.off[1][q] = oy;
-  out.off[2][q] = oz;
-  out.cell[q] = (i * g.ny + j) * g.nz + k;
-  if (in.w && out.w != in.w) out.w[q] = in.w[p];
+  ux = umx + (upy * sz - upz * sy) + qdt2m * f[0];
+  uy = umy + (upz * sx - upx * sz) + qdt2m * f[1];
+  uz = umz + (upx * sy - upy * sx) + qdt2m * f[2];
+  const T ig = (T)1 / sqrt((T)1 + ux * ux + uy * uy + uz * uz);
+  i = modi(i + advance_offset(ox, dtx * ux * ig), g.nx);
+  j = modi(j + advance_offset(oy, dty * uy * ig), g.ny);
+  k = modi(k + advance_offset(oz, dtz * uz * ig), g.nz);
 }
 
-// Tile-ordered gather + push: one block per tile stages the 6 nodal field
-// components over the tile's support box (G = ts + NW - 1 nodes per axis) in LDS,
-// then every particle of the tile gathers from LDS.  Slot q of the tile reads
-// particle perm[q] of ``in`` and writes it to slot q (write_sorted) or back to
-// perm[q] of ``out``.  Block ntiles carries particles with invalid cells along.
+template <typename T>
+__device__ inline void copy_particle(const SpeciesView<T>& in, long long p, const SpeciesView<T>& out, long long q) {
+  out.cell[q] = in.cell[p];
+  for (int d = 0; d < 3; ++d) {
+    out.off[d][q] = in.off[d][p];
+    out.u[d][q] = in.u[d][p];
+  }
+  if (in.w) out.w[q] = in.w[p];
+}
+
+// Gather + push through a permutation: one block per tile t of the particles'
+// current cells, slots q in [starts[t], starts[t+1]); slot q reads particle perm[q]
+// of ``in`` and writes it to slot q (write_sorted) or back to perm[q] of ``out``.
+// Block ntiles carries particles with invalid cells along.
 template <typename T, int ORDER>
-__global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_tiled(GridGeom g, TileGeom tg, Batch<const T*> F,
-                                                           SpeciesView<T> in, SpeciesView<T> out,
-                                                           const int* __restrict__ perm, const int* __restrict__ starts,
-                                                           int write_sorted, T qdt2m, T dtx, T dty, T dtz, int* bad) {
+__global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_perm(GridGeom g, TileGeom tg, Batch<const T*> F,
+                                                                       SpeciesView<T> in, SpeciesView<T> out,
+                                                                       const int* __restrict__ perm,
+                                                                       const int* __restrict__ starts, int write_sorted,
+                                                                       T qdt2m, T dtx, T dty, T dtz) {
   using S = Shape<T, ORDER>;
-  constexpr int NW = S::NW;
   extern __shared__ __align__(16) unsigned char smem[];
   T* box = reinterpret_cast<T*>(smem);
   const int tile = blockIdx.x;
   const int beg = starts[tile], end = starts[tile + 1];
   if (beg == end) return;
-  if (tile == tg.ntiles) {  // invalid cells: carried along untouched
+  if (tile == tg.ntiles) {
     for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
       const int p = perm[qq];
-      const int wi = write_sorted ? qq : p;
-      out.cell[wi] = in.cell[p];
-      for (int d = 0; d < 3; ++d) {
-        out.off[d][wi] = in.off[d][p];
-        out.u[d][wi] = in.u[d][p];
-      }
-      if (in.w) out.w[wi] = in.w[p];
+      copy_particle(in, p, out, write_sorted ? qq : p);
     }
     return;
   }
-  const int ts = tg.ts;
-  const int G = ts + NW - 1;
-  const int G3 = G * G * G;
-  const int tk = tile % tg.ntz;
-  const int tr = tile / tg.ntz;
-  const int tj = tr % tg.nty;
-  const int ti = tr / tg.nty;
-  const int t0x = ti * ts, t0y = tj * ts, t0z = tk * ts;
-  const int ox0 = t0x + S::BASE, oy0 = t0y + S::BASE, oz0 = t0z + S::BASE;
-  for (int e = threadIdx.x; e < 6 * G3; e += blockDim.x) {
-    const int c = e / G3;
-    const int r = e - c * G3;
-    const int lx = r / (G * G), ly = (r / G) % G, lz = r % G;
-    const size_t gi = ((size_t)modi(ox0 + lx, g.nx) * g.ny + modi(oy0 + ly, g.ny)) * g.nz + modi(oz0 + lz, g.nz);
-    box[e] = F.p[c][gi];
-  }
+  const int B = tg.ts + S::NW + 1;
+  int tx, ty, tz;
+  tile_coords(tile, tg, tx, ty, tz);
+  const int t0x = tx * tg.ts, t0y = ty * tg.ts, t0z = tz * tg.ts;
+  load_field_box<T, ORDER>(box, F, g, t0x, t0y, t0z, B);
   __syncthreads();
   for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
     const int p = perm[qq];
     const int wi = write_sorted ? qq : p;
     int i, j, k;
-    (void)decode_cell(in.cell[p], g, nullptr, i, j, k);  // valid: sorted into this tile
+    (void)decode_cell(in.cell[p], g, nullptr, i, j, k);
     T ox = in.off[0][p], oy = in.off[1][p], oz = in.off[2][p];
-    T wx[NW], wy[NW], wz[NW];
-    S::weights(ox, wx);
-    S::weights(oy, wy);
-    S::weights(oz, wz);
-    const int lx = i - t0x, ly = j - t0y, lz = k - t0z;  // in [0, ts)
-    T f[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int a = 0; a < NW; ++a) {
-#pragma unroll
-      for (int b = 0; b < NW; ++b) {
-        const int row = ((lx + a) * G + (ly + b)) * G + lz;
-        const T wab = wx[a] * wy[b];
-#pragma unroll
-        for (int cc = 0; cc < NW; ++cc) {
-          const T w = wab * wz[cc];
-#pragma unroll
-          for (int m = 0; m < 6; ++m) f[m] += w * box[m * G3 + row + cc];
-        }
-      }
-    }
-    const T ux = in.u[0][p], uy = in.u[1][p], uz = in.u[2][p];
-    const T umx = ux + qdt2m * f[0], umy = uy + qdt2m * f[1], umz = uz + qdt2m * f[2];
-    const T gm = sqrt((T)1 + umx * umx + umy * umy + umz * umz);
-    const T tf = qdt2m / gm;
-    const T tx = tf * f[3], ty = tf * f[4], tz = tf * f[5];
-    const T sf = (T)2 / ((T)1 + tx * tx + ty * ty + tz * tz);
-    const T sx = sf * tx, sy = sf * ty, sz = sf * tz;
-    const T upx = umx + (umy * tz - umz * ty);
-    const T upy = umy + (umz * tx - umx * tz);
-    const T upz = umz + (umx * ty - umy * tx);
-    const T npx = umx + (upy * sz - upz * sy) + qdt2m * f[0];
-    const T npy = umy + (upz * sx - upx * sz) + qdt2m * f[1];
-    const T npz = umz + (upx * sy - upy * sx) + qdt2m * f[2];
-    const T ig = (T)1 / sqrt((T)1 + npx * npx + npy * npy + npz * npz);
-    i = modi(i + advance_offset(ox, dtx * npx * ig), g.nx);
-    j = modi(j + advance_offset(oy, dty * npy * ig), g.ny);
-    k = modi(k + advance_offset(oz, dtz * npz * ig), g.nz);
-    out.u[0][wi] = npx;
-    out.u[1][wi] = npy;
-    out.u[2][wi] = npz;
+    T ux = in.u[0][p], uy = in.u[1][p], uz = in.u[2][p];
+    const int lx = box_index(i, t0x, g.nx, tg.ts), ly = box_index(j, t0y, g.ny, tg.ts),
+              lz = box_index(k, t0z, g.nz, tg.ts);
+    gather_push_one<T, ORDER>(box, B, F, g, lx, ly, lz, i, j, k, ox, oy, oz, ux, uy, uz, qdt2m, dtx, dty, dtz);
+    out.u[0][wi] = ux;
+    out.u[1][wi] = uy;
+    out.u[2][wi] = uz;
     out.off[0][wi] = ox;
     out.off[1][wi] = oy;
     out.off[2][wi] = oz;
     out.cell[wi] = (i * g.ny + j) * g.nz + k;
     if (in.w && (write_sorted || out.w != in.w)) out.w[wi] = in.w[p];
+  }
+}
+
+// Steady-state gather + push of pic_step.  ``in`` is grouped by home tile h (the
+// tile of the previous step's positions; slots [home[h], home[h+1])), so every
+// particle lies within one cell of its home tile and the LDS box of h covers it.
+// Each particle is written to ``out`` grouped by the tile of its current cell
+// (before the push): a block first counts its particles per neighbour tile in LDS,
+// reserves one contiguous run per neighbour tile with a single atomic on ``cursor``
+// (the start of each tile in the new grouping, from the counts the previous
+// deposition took), then gathers, pushes and writes each particle to base + its
+// rank from a second LDS count.  Block ntiles carries invalid cells to the last bucket.
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom g, TileGeom tg, Batch<const T*> F,
+                                                                       SpeciesView<T> in, SpeciesView<T> out,
+                                                                       const int* __restrict__ home, int* cursor,
+                                                                       T qdt2m, T dtx, T dty, T dtz) {
+  using S = Shape<T, ORDER>;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* box = reinterpret_cast<T*>(smem);
+  __shared__ int cnt[27];
+  __shared__ int base[27];
+  const int tile = blockIdx.x;
+  const int beg = home[tile], end = home[tile + 1];
+  if (beg == end) return;
+  if (tile == tg.ntiles) {
+    if (threadIdx.x == 0) base[0] = atomicAdd(&cursor[tg.ntiles], end - beg);
+    __syncthreads();
+    for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) copy_particle(in, qq, out, base[0] + qq - beg);
+    return;
+  }
+  const int B = tg.ts + S::NW + 1;
+  int tx, ty, tz;
+  tile_coords(tile, tg, tx, ty, tz);
+  const int t0x = tx * tg.ts, t0y = ty * tg.ts, t0z = tz * tg.ts;
+  if (threadIdx.x < 27) cnt[threadIdx.x] = 0;
+  load_field_box<T, ORDER>(box, F, g, t0x, t0y, t0z, B);
+  __syncthreads();
+  // pass 1: particles per neighbour tile of the new grouping
+  for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
+    int i, j, k;
+    (void)decode_cell(in.cell[qq], g, nullptr, i, j, k);
+    const int nb = neighbour_index(tile_of(i, j, k, tg), tx, ty, tz, tg);
+    if (nb >= 0) atomicAdd(&cnt[nb], 1);
+  }
+  __syncthreads();
+  // one contiguous run per neighbour tile, reserved with a single atomic each
+  if (threadIdx.x < 27) {
+    const int n = cnt[threadIdx.x];
+    base[threadIdx.x] = n > 0 ? atomicAdd(&cursor[neighbour_key(threadIdx.x, tx, ty, tz, tg)], n) : 0;
+    cnt[threadIdx.x] = 0;
+  }
+  __syncthreads();
+  // pass 2: gather, push and write each particle to its slot
+  for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
+    int i, j, k;
+    (void)decode_cell(in.cell[qq], g, nullptr, i, j, k);
+    const int key = tile_of(i, j, k, tg);
+    const int nb = neighbour_index(key, tx, ty, tz, tg);
+    const int slot = nb >= 0 ? base[nb] + atomicAdd(&cnt[nb], 1) : atomicAdd(&cursor[key], 1);
+    T ox = in.off[0][qq], oy = in.off[1][qq], oz = in.off[2][qq];
+    T ux = in.u[0][qq], uy = in.u[1][qq], uz = in.u[2][qq];
+    const int lx = box_index(i, t0x, g.nx, tg.ts), ly = box_index(j, t0y, g.ny, tg.ts),
+              lz = box_index(k, t0z, g.nz, tg.ts);
+    gather_push_one<T, ORDER>(box, B, F, g, lx, ly, lz, i, j, k, ox, oy, oz, ux, uy, uz, qdt2m, dtx, dty, dtz);
+    out.u[0][slot] = ux;
+    out.u[1][slot] = uy;
+    out.u[2][slot] = uz;
+    out.off[0][slot] = ox;
+    out.off[1][slot] = oy;
+    out.off[2][slot] = oz;
+    out.cell[slot] = (i * g.ny + j) * g.nz + k;
+    if (in.w) out.w[slot] = in.w[qq];
   }
 }
 
@@ -388,13 +494,6 @@ __device__ inline void scatter_lds(typename Fixed<T>::acc_t* box, int B, int lx,
   }
 }
 
-// box-local index of the first support node of a particle in cell i of a tile
-// starting at cell t0, or -1 if the particle has left the one-cell margin.
-__device__ inline int box_index(int i, int t0, int n, int ts) {
-  int l = (i - t0 + 1) % n;
-  if (l < 0) l += n;
-  return (l <= ts + 1) ? l : -1;
-}
 
 // One block per tile: rho (at x) and J (at x - dt v/2) of the tile's particles are
 // accumulated in LDS over a box of B = ts + NW + 1 nodes per axis (the tile, the
@@ -406,7 +505,7 @@ template <typename T, int ORDER>
 __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp,
                                                        const int* __restrict__ perm, const int* __restrict__ starts,
                                                        Batch<T*> out, T* __restrict__ stage, T qdv, int with_j, T hdtx,
-                                                       T hdty, T hdtz, int* bad) {
+                                                       T hdty, T hdtz, int* bad, int* next_counts) {
   using S = Shape<T, ORDER>;
   constexpr int NW = S::NW;
   using acc_t = typename Fixed<T>::acc_t;
@@ -415,9 +514,14 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
   constexpr int kWaves = PIC_DEPOSIT_BLOCK / 64;
   __shared__ T red[4 * kWaves];
   __shared__ T redm[4 * kWaves];
+  __shared__ int cnt[27];
   const int tile = blockIdx.x;
   const int beg = starts[tile], end = starts[tile + 1];
   if (beg == end) return;
+  if (tile == tg.ntiles) {  // invalid cells: never deposited, kept in the last bucket
+    if (next_counts && threadIdx.x == 0) atomicAdd(&next_counts[tg.ntiles], end - beg);
+    return;
+  }
   const int ts = tg.ts;
   const int B = ts + NW + 1;
   const int B3 = B * B * B;
@@ -472,12 +576,11 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
   __syncthreads();
   int sh[4];
   for (int c = 0; c < 4; ++c) sh[c] = (c < ncomp) ? shs[c] : 0;
-  const int tk = tile % tg.ntz;
-  const int tr = tile / tg.ntz;
-  const int tj = tr % tg.nty;
-  const int ti = tr / tg.nty;
+  int ti, tj, tk;
+  tile_coords(tile, tg, ti, tj, tk);
   const int t0x = ti * ts, t0y = tj * ts, t0z = tk * ts;
   for (int k = threadIdx.x; k < ncomp * B3; k += blockDim.x) box[k] = 0;
+  if (threadIdx.x < 27) cnt[threadIdx.x] = 0;
   __syncthreads();
   for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
     const int p = perm ? perm[qq] : qq;
@@ -485,6 +588,12 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
     if (!decode_cell(sp.cell[p], g, bad, i, j, k)) continue;
     const T ox = sp.off[0][p], oy = sp.off[1][p], oz = sp.off[2][p];
     const T qw = qdv * (sp.w ? sp.w[p] : (T)sp.w_const);
+    if (next_counts) {  // the tile of this position groups the particle in the next step
+      const int key = tile_of(i, j, k, tg);
+      const int nb = neighbour_index(key, ti, tj, tk, tg);
+      if (nb >= 0) atomicAdd(&cnt[nb], 1);
+      else atomicAdd(&next_counts[key], 1);
+    }
     {
       const int lx = box_index(i, t0x, g.nx, ts), ly = box_index(j, t0y, g.ny, ts), lz = box_index(k, t0z, g.nz, ts);
       T val[1] = {qw};
@@ -516,6 +625,8 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
     }
   }
   __syncthreads();
+  if (next_counts && threadIdx.x < 27 && cnt[threadIdx.x] > 0)
+    atomicAdd(&next_counts[neighbour_key(threadIdx.x, ti, tj, tk, tg)], cnt[threadIdx.x]);
   // the whole box goes to this tile's staging slot (plain stores, zeros included)
   T* dstage = stage + (size_t)tile * ncomp * B3;
   for (int k = threadIdx.x; k < ncomp * B3; k += blockDim.x) dstage[k] = ldexp((T)box[k], -sh[k / B3]);
@@ -583,24 +694,6 @@ __global__ void __launch_bounds__(256) k_deposit_reduce(GridGeom g, TileGeom tg,
 }  // namespace
 
 template <typename T>
-void gather_push(const GridGeom& g, const T* const E[3], const T* const B[3], const SpeciesView<T>& in,
-                 const SpeciesView<T>& out, const int* dst, int* bad, hipStream_t s) {
-  if (in.n <= 0) return;
-  Batch<const T*> F{};
-  for (int d = 0; d < 3; ++d) {
-    F.p[d] = E[d];
-    F.p[3 + d] = B[d];
-  }
-  const T qdt2m = (T)(in.q * g.dt / (2.0 * in.m));
-  const T dtx = (T)(g.dt / g.dx), dty = (T)(g.dt / g.dy), dtz = (T)(g.dt / g.dz);
-  const unsigned nb = (unsigned)((in.n + 255) / 256);
-  if (g.shape_order == 1)
-    hipLaunchKernelGGL((k_gather_push<T, 1>), dim3(nb), dim3(256), 0, s, g, F, in, out, dst, qdt2m, dtx, dty, dtz, bad);
-  else
-    hipLaunchKernelGGL((k_gather_push<T, 3>), dim3(nb), dim3(256), 0, s, g, F, in, out, dst, qdt2m, dtx, dty, dtz, bad);
-}
-
-template <typename T>
 void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const int* dst, hipStream_t s) {
   if (in.n <= 0) return;
   hipLaunchKernelGGL((k_permute<T>), dim3((unsigned)((in.n + 255) / 256)), dim3(256), 0, s, in, out, dst);
@@ -616,12 +709,10 @@ void allow_lds(const void* kernel, size_t bytes) {
 }
 
 int deposit_box(int shape_order, int ts) { return ts + (shape_order == 1 ? 2 : 4) + 1; }
-int gather_box(int shape_order, int ts) { return ts + (shape_order == 1 ? 2 : 4) - 1; }
-
 template <typename T>
 void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3], const T* const B[3],
                        const SpeciesView<T>& in, const SpeciesView<T>& out, const int* perm, const int* starts,
-                       bool write_sorted, int* bad, hipStream_t s) {
+                       bool write_sorted, int* home_cursor, hipStream_t s) {
   if (in.n <= 0) return;
   Batch<const T*> F{};
   for (int d = 0; d < 3; ++d) {
@@ -630,22 +721,36 @@ void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3]
   }
   const T qdt2m = (T)(in.q * g.dt / (2.0 * in.m));
   const T dtx = (T)(g.dt / g.dx), dty = (T)(g.dt / g.dy), dtz = (T)(g.dt / g.dz);
-  const int G = gather_box(g.shape_order, t.ts);
-  const size_t lds = 6 * (size_t)G * G * G * sizeof(T);
-  const int ws = write_sorted ? 1 : 0;
-  if (g.shape_order == 1) allow_lds((const void*)k_gather_push_tiled<T, 1>, lds);
-  else allow_lds((const void*)k_gather_push_tiled<T, 3>, lds);
-  if (g.shape_order == 1)
-    hipLaunchKernelGGL((k_gather_push_tiled<T, 1>), dim3(t.ntiles + 1), dim3(PIC_GATHER_BLOCK), lds, s, g, t, F, in, out, perm,
-                       starts, ws, qdt2m, dtx, dty, dtz, bad);
-  else
-    hipLaunchKernelGGL((k_gather_push_tiled<T, 3>), dim3(t.ntiles + 1), dim3(PIC_GATHER_BLOCK), lds, s, g, t, F, in, out, perm,
-                       starts, ws, qdt2m, dtx, dty, dtz, bad);
+  const int Bx = deposit_box(g.shape_order, t.ts);
+  const size_t lds = (size_t)Bx * Bx * Bx * FieldSlots<T>::FS * sizeof(T);
+  const dim3 grid(t.ntiles + 1), block(PIC_GATHER_BLOCK);
+  if (home_cursor) {
+    if (g.shape_order == 1) {
+      allow_lds((const void*)k_gather_push_home<T, 1>, lds);
+      hipLaunchKernelGGL((k_gather_push_home<T, 1>), grid, block, lds, s, g, t, F, in, out, starts, home_cursor,
+                         qdt2m, dtx, dty, dtz);
+    } else {
+      allow_lds((const void*)k_gather_push_home<T, 3>, lds);
+      hipLaunchKernelGGL((k_gather_push_home<T, 3>), grid, block, lds, s, g, t, F, in, out, starts, home_cursor,
+                         qdt2m, dtx, dty, dtz);
+    }
+  } else {
+    const int ws = write_sorted ? 1 : 0;
+    if (g.shape_order == 1) {
+      allow_lds((const void*)k_gather_push_perm<T, 1>, lds);
+      hipLaunchKernelGGL((k_gather_push_perm<T, 1>), grid, block, lds, s, g, t, F, in, out, perm, starts, ws, qdt2m,
+                         dtx, dty, dtz);
+    } else {
+      allow_lds((const void*)k_gather_push_perm<T, 3>, lds);
+      hipLaunchKernelGGL((k_gather_push_perm<T, 3>), grid, block, lds, s, g, t, F, in, out, perm, starts, ws, qdt2m,
+                         dtx, dty, dtz);
+    }
+  }
 }
 
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
-                   bool with_j, T* stage, int* bad, T* rho, T* const J[3], hipStream_t s) {
+                   bool with_j, T* stage, int* bad, int* next_counts, T* rho, T* const J[3], hipStream_t s) {
   if (sp.n <= 0) return;
   Batch<T*> out{};
   out.p[0] = rho;
@@ -659,11 +764,11 @@ void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& s
   if (g.shape_order == 1) allow_lds((const void*)k_deposit_tiled<T, 1>, lds);
   else allow_lds((const void*)k_deposit_tiled<T, 3>, lds);
   if (g.shape_order == 1)
-    hipLaunchKernelGGL((k_deposit_tiled<T, 1>), dim3(t.ntiles), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm, starts,
-                       out, stage, qdv, wj, hx, hy, hz, bad);
+    hipLaunchKernelGGL((k_deposit_tiled<T, 1>), dim3(t.ntiles + 1), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm,
+                       starts, out, stage, qdv, wj, hx, hy, hz, bad, next_counts);
   else
-    hipLaunchKernelGGL((k_deposit_tiled<T, 3>), dim3(t.ntiles), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm, starts,
-                       out, stage, qdv, wj, hx, hy, hz, bad);
+    hipLaunchKernelGGL((k_deposit_tiled<T, 3>), dim3(t.ntiles + 1), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm,
+                       starts, out, stage, qdv, wj, hx, hy, hz, bad, next_counts);
 }
 
 template <typename T>
@@ -682,11 +787,9 @@ void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, con
 }
 
 #define PIC_INST(T)                                                                                              \
-  template void gather_push<T>(const GridGeom&, const T* const*, const T* const*, const SpeciesView<T>&,         \
-                               const SpeciesView<T>&, const int*, int*, hipStream_t);                            \
   template void permute_species<T>(const SpeciesView<T>&, const SpeciesView<T>&, const int*, hipStream_t);       \
   template void deposit_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*, const int*, \
-                                 bool, T*, int*, T*, T* const*, hipStream_t);                                    \
+                                 bool, T*, int*, int*, T*, T* const*, hipStream_t);                              \
   template void deposit_reduce<T>(const GridGeom&, const TileGeom&, const int*, const T*, bool, T*, T* const*,   \
                                   hipStream_t);                                                                  \
   template void gather_push_tiled<T>(const GridGeom&, const TileGeom&, const T* const*, const T* const*,         \

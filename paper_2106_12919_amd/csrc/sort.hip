@@ -112,6 +112,10 @@ void tile_sort(const GridGeom& g, const TileGeom& t, const int32_t* cell, int64_
   if (n > 0) hipLaunchKernelGGL(k_tile_rank, dim3(nb), dim3(256), 0, s, g, t, cell, (long long)n, cursor, dst, bad);
 }
 
+void scan_counts(const TileGeom& t, const int* counts, int* starts, int* cursor, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, starts, cursor, t.ntiles + 1);
+}
+
 void invert_perm(const int* dst, int* perm, int64_t n, hipStream_t s) {
   if (n > 0) hipLaunchKernelGGL(k_invert, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, dst, perm, (long long)n);
 }
