@@ -121,6 +121,7 @@ struct SpeciesScratch {
   int* counts[2] = {nullptr, nullptr};
   int* starts[2] = {nullptr, nullptr};
   int* cursor = nullptr;
+  int* nbr = nullptr;  // [27 * ntiles]: per tile, particles per neighbour tile (from the deposition)
 };
 
 template <typename T>
@@ -167,8 +168,8 @@ struct Engine : EngineBase {
     if (sps.size() <= s) sps.resize(s + 1);
     SpeciesScratch<T>& x = sps[s];
     if (x.cap >= n) return hipSuccess;
-    void* old[15] = {x.cell, x.off[0], x.off[1], x.off[2], x.u[0], x.u[1], x.u[2], x.w, x.dst, x.perm,
-                     x.counts[0], x.counts[1], x.starts[0], x.starts[1], x.cursor};
+    void* old[16] = {x.cell, x.off[0], x.off[1], x.off[2], x.u[0], x.u[1], x.u[2], x.w, x.dst, x.perm,
+                     x.counts[0], x.counts[1], x.starts[0], x.starts[1], x.cursor, x.nbr};
     for (void* q : old)
       if (q) (void)release_one(q);
     x = SpeciesScratch<T>{};
@@ -180,6 +181,7 @@ struct Engine : EngineBase {
       if ((e = alloc(&x.starts[b], nt + 2)) != hipSuccess) return e;
     }
     if ((e = alloc(&x.cursor, nt + 1)) != hipSuccess) return e;
+    if ((e = alloc(&x.nbr, 27 * nt)) != hipSuccess) return e;
     if ((e = alloc(&x.cell, m)) != hipSuccess) return e;
     for (int d = 0; d < 3; ++d) {
       if ((e = alloc(&x.off[d], m)) != hipSuccess) return e;
@@ -255,15 +257,14 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
     if ((err = hipMemset(*b, 0, ns * sizeof(cplx<T>))) != hipSuccess) return err;
   }
   if ((err = e.alloc(&e.tmp, (size_t)p.nx * p.ny * p.nz)) != hipSuccess) return err;
-  // deposition tiles of 8^3 cells: the int64 LDS box (4 components) is at most
-  // 4 * 13^3 * 8 B = 70 KiB (two workgroups per CU); the gather box 6 * 11^3 * sizeof(T)
-  const GridGeom g{p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order};
-  const int ts = 8;
-  e.tiles = make_tiles(g, ts);
+  // deposition tiles of kTile^3 = 8^3 cells: the LDS box of 4 components is at most
+  // 4 * 13^3 * 8 B = 70 KiB (FP64, cubic); the gather box 13^3 nodes * 6 components
+  const GridGeom g = make_geom(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order);
+  e.tiles = make_tiles(g);
   if ((err = e.alloc(&e.t_counts, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_starts, (size_t)e.tiles.ntiles + 2)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_cursor, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;
-  const size_t B = (size_t)deposit_box(p.shape_order, ts);
+  const size_t B = (size_t)deposit_box(p.shape_order);
   if ((err = e.alloc(&e.stage, (size_t)e.tiles.ntiles * 4 * B * B * B)) != hipSuccess) return err;
   return hipSuccess;
 }
@@ -342,7 +343,7 @@ SpeciesView<T> view(const pic_species& x) {
 }
 
 GridGeom geom(const pic_params& p) {
-  return GridGeom{p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order};
+  return make_geom(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order);
 }
 
 size_t ncells(const pic_params& p) { return (size_t)p.nx * p.ny * p.nz; }
@@ -410,7 +411,7 @@ pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, 
     tile_sort(g, e.tiles, v.cell, v.n, e.t_counts, e.t_starts, e.t_cursor, x.dst, c->d_bad, c->stream);
     invert_perm(x.dst, x.perm, v.n, c->stream);
     const bool mobile = std::isfinite(sp[s].m);
-    deposit_tiled<T>(g, e.tiles, v, x.perm, e.t_starts, with_j && mobile, e.stage, c->d_bad, nullptr,
+    deposit_tiled<T>(g, e.tiles, v, x.perm, e.t_starts, with_j && mobile, e.stage, c->d_bad, nullptr, nullptr,
                      static_cast<T*>(f->rho_new), J, c->stream);
     deposit_reduce<T>(g, e.tiles, e.t_starts, e.stage, with_j && mobile, static_cast<T*>(f->rho_new), J, c->stream);
   }
@@ -440,7 +441,7 @@ pic_status do_gather_push(pic_ctx c, const pic_fields* f, pic_species* sp, int n
       // tile order through a permutation; every particle is updated in place
       tile_sort(g, e.tiles, v.cell, v.n, e.t_counts, e.t_starts, e.t_cursor, x.dst, c->d_bad, c->stream);
       invert_perm(x.dst, x.perm, v.n, c->stream);
-      gather_push_tiled<T>(g, e.tiles, E, B, v, v, x.perm, e.t_starts, false, nullptr, c->stream);
+      gather_push_tiled<T>(g, e.tiles, E, B, v, v, x.perm, e.t_starts, false, nullptr, nullptr, c->stream);
     }
   return c->check("pic_gather_push");
 }
@@ -594,18 +595,20 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
       {
         StageScope sc(c, ST_PUSH);
         if (first && mobile)
-          gather_push_tiled<T>(g, e.tiles, Enod, Bnod, cur, alt, x.perm, x.starts[0], true, nullptr, c->stream);
+          gather_push_tiled<T>(g, e.tiles, Enod, Bnod, cur, alt, x.perm, x.starts[0], true, nullptr, nullptr,
+                               c->stream);
         else if (first)
           permute_species<T>(cur, alt, x.dst, c->stream);
         else if (mobile)
-          gather_push_tiled<T>(g, e.tiles, Enod, Bnod, cur, alt, nullptr, x.starts[L], true, x.cursor, c->stream);
+          gather_push_tiled<T>(g, e.tiles, Enod, Bnod, cur, alt, nullptr, x.starts[L], true, x.cursor, x.nbr,
+                               c->stream);
       }
       const SpeciesView<T> dep = (first || mobile) ? alt : cur;  // immobile species stay put after the first step
       {
         StageScope sc(c, ST_DEPOSIT);
         int* nextc = mobile ? x.counts[first ? 1 : L] : nullptr;
         deposit_tiled<T>(g, e.tiles, dep, nullptr, dep_starts, mobile, e.stage, c->d_bad, nextc,
-                         static_cast<T*>(f->rho_new), Jn, c->stream);
+                         mobile ? x.nbr : nullptr, static_cast<T*>(f->rho_new), Jn, c->stream);
       }
       {
         StageScope sc(c, ST_REDUCE);

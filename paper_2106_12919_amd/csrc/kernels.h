@@ -48,11 +48,25 @@ void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B
                   const cplx<T>* rho_old, const cplx<T>* rho_new, int nx, int ny, int nzh, int pz, hipStream_t s);
 
 // ---------------------------------------------------------------- particles (particles.hip)
+// Division by a fixed divisor d (1 <= d < 2^31) as a multiply-high and a shift:
+// n / d == (mulhi(n, m) + n) >> s for 0 <= n < 2^31, with s = ceil(log2 d) and
+// m = floor(2^32 (2^s - d) / d) + 1 (Granlund and Montgomery, PLDI 1994, Sec. 4).
+struct FastDiv {
+  uint32_t d, m, s;
+};
+FastDiv make_fastdiv(uint32_t d);
+
 struct GridGeom {
   int nx, ny, nz;
   double dx, dy, dz, dt;
   int shape_order;
+  FastDiv ny_div, nz_div;  // decode of linear cell indices
 };
+GridGeom make_geom(int nx, int ny, int nz, double dx, double dy, double dz, double dt, int shape_order);
+
+// Edge of the deposition / gather tiles in cells.  A compile-time constant, so that
+// every LDS offset inside a tile's box is an instruction immediate.
+constexpr int kTile = 8;
 template <typename T>
 struct SpeciesView {
   int64_t n;
@@ -63,12 +77,12 @@ struct SpeciesView {
   double w_const, q, m;
 };
 struct TileGeom {
-  int ts, ntx, nty, ntz, ntiles;
+  int ntx, nty, ntz, ntiles;
 };
-TileGeom make_tiles(const GridGeom& g, int ts);
+TileGeom make_tiles(const GridGeom& g);  // tiles of kTile^3 cells
 // Edge length (nodes) of the LDS boxes of one tile: the tile, the shape support and a
 // one-cell margin on each side (particles move less than one cell per step).
-int deposit_box(int shape_order, int ts);
+int deposit_box(int shape_order);
 // Counting sort by tile of the particles' current cells: counts[ntiles+1],
 // starts[ntiles+2], cursor[ntiles+1] (scratch), dst[n] = each particle's slot in
 // tile order (tiles in order, then particles with invalid cells, counted in *bad).
@@ -83,11 +97,13 @@ void scan_counts(const TileGeom& t, const int* counts, int* starts, int* cursor,
 // particle perm[q] of ``in`` and writes it to slot q of ``out`` (write_sorted) or to
 // perm[q] (in place when out == in); or, in pic_step's steady state, ``in`` grouped by
 // home tile (starts = home ranges) is written to ``out`` grouped by the tile of each
-// particle's current cell, slots reserved per block from home_cursor (the new starts).
+// particle's current cell, slots reserved per block from home_cursor (the new starts);
+// nbr_counts (optional) holds, per home tile, its particles per neighbour tile
+// [27 * ntiles] as the deposition that grouped them counted them.
 template <typename T>
 void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3], const T* const B[3],
                        const SpeciesView<T>& in, const SpeciesView<T>& out, const int* perm, const int* starts,
-                       bool write_sorted, int* home_cursor, hipStream_t s);
+                       bool write_sorted, int* home_cursor, const int* nbr_counts, hipStream_t s);
 template <typename T>
 void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const int* dst, hipStream_t s);
 // Deposition of one species in two launches.  deposit_tiled accumulates rho (at the
@@ -97,10 +113,13 @@ void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const 
 // elements); particles that left the one-cell margin go straight to rho/J.
 // deposit_reduce then adds the overlapping boxes to the nodal arrays.
 // With next_counts != nullptr, the particles are also counted per tile of their cells
-// (the grouping of the next step), into next_counts[ntiles + 1] (invalid cells last).
+// (the grouping of the next step), into next_counts[ntiles + 1] (invalid cells last),
+// and, when nbr_counts != nullptr, per tile t of this grouping and neighbour nb of t
+// (0..26, the tile offsets in {-1,0,1}^3 in x-major order) into nbr_counts[27 t + nb].
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
-                   bool with_j, T* stage, int* bad, int* next_counts, T* rho, T* const J[3], hipStream_t s);
+                   bool with_j, T* stage, int* bad, int* next_counts, int* nbr_counts, T* rho, T* const J[3],
+                   hipStream_t s);
 template <typename T>
 void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, const T* stage, bool with_j, T* rho,
                     T* const J[3], hipStream_t s);

@@ -63,20 +63,24 @@ __device__ inline int modi(int i, int n) {
   return (i < 0) ? i + n : i;
 }
 
-// Decodes a linear cell index; returns false (and counts the particle) when it is out of range.
+__device__ inline int fdiv(int n, const FastDiv& f) { return (int)((__umulhi((uint32_t)n, f.m) + (uint32_t)n) >> f.s); }
+
+// Decodes a linear cell index c = (i ny + j) nz + k; returns false (and counts the
+// particle when ``bad`` is given) when it is out of range.
 __device__ inline bool decode_cell(int c, const GridGeom& g, int* bad, int& i, int& j, int& k) {
   if (c < 0 || c >= g.nx * g.ny * g.nz) {
     if (bad) atomicAdd(bad, 1);
     return false;
   }
-  k = c % g.nz;
-  const int t = c / g.nz;
-  j = t % g.ny;
-  i = t / g.ny;
+  const int r = fdiv(c, g.nz_div);
+  k = c - r * g.nz;
+  i = fdiv(r, g.ny_div);
+  j = r - i * g.ny;
   return true;
 }
 
-// offset + displacement (in cells) -> (new offset in [0,1), integer shift), |displacement| < 1.
+// offset + displacement (in cells) -> (new offset in [0,1), integer shift in -1..1),
+// |displacement| < 1.
 template <typename T>
 __device__ inline int advance_offset(T& off, T disp) {
   T o = off + disp;
@@ -103,15 +107,15 @@ __device__ inline void tile_coords(int tile, const TileGeom& tg, int& tx, int& t
 }
 
 __device__ inline int tile_of(int i, int j, int k, const TileGeom& tg) {
-  return ((i / tg.ts) * tg.nty + j / tg.ts) * tg.ntz + k / tg.ts;
+  return ((i / kTile) * tg.nty + j / kTile) * tg.ntz + k / kTile;
 }
 
-// Index 0..26 of ``key`` among the 27 tiles around (tx, ty, tz) (periodic), or -1.
-__device__ inline int neighbour_index(int key, int tx, int ty, int tz, const TileGeom& tg) {
-  int kx, ky, kz;
-  tile_coords(key, tg, kx, ky, kz);
-  int d[3] = {kx - tx, ky - ty, kz - tz};
+// Index 0..26 of the tile of cell (i, j, k) among the 27 tiles around (tx, ty, tz)
+// (periodic), or -1.  13 is the tile itself.
+__device__ inline int neighbour_of_cell(int i, int j, int k, int tx, int ty, int tz, const TileGeom& tg) {
+  int d[3] = {i / kTile - tx, j / kTile - ty, k / kTile - tz};
   const int nt[3] = {tg.ntx, tg.nty, tg.ntz};
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (d[a] > 1) d[a] -= nt[a];
     if (d[a] < -1) d[a] += nt[a];
@@ -125,14 +129,23 @@ __device__ inline int neighbour_key(int nb, int tx, int ty, int tz, const TileGe
   return (modi(tx + dx, tg.ntx) * tg.nty + modi(ty + dy, tg.nty)) * tg.ntz + modi(tz + dz, tg.ntz);
 }
 
-// box-local index (0 .. B-1) of the first support node of a particle in cell i of a
-// tile starting at cell t0, for boxes whose node 0 is t0 - 1 + BASE (one-cell
-// margin); -1 if the particle is outside the margin.
-__device__ inline int box_index(int i, int t0, int n, int ts) {
-  int l = (i - t0 + 1) % n;
-  if (l < 0) l += n;
-  return (l <= ts + 1) ? l : -1;
+// box-local index (0 .. B-1) of the first support node of a particle in cell i
+// (0 <= i < n) of a tile starting at cell t0, for boxes whose node 0 is t0 - 1 + BASE
+// (one-cell margin); -1 if the particle is outside the margin.
+__device__ inline int box_index(int i, int t0, int n) {
+  const int l = wrapi(i - t0 + 1, n);
+  return (l <= kTile + 1) ? l : -1;
 }
+
+// Box geometry of one tile for a shape of NW nodes per axis: B = kTile + NW + 1
+// nodes per edge, z fastest.
+template <int NW>
+struct Box {
+  static constexpr int B = kTile + NW + 1;
+  static constexpr int B2 = B * B;
+  static constexpr int B3 = B2 * B;
+  __device__ static inline int at(int lx, int ly, int lz) { return (lx * B + ly) * B + lz; }
+};
 
 // ---------------------------------------------------------------- gather + push
 
@@ -160,16 +173,15 @@ struct FieldSlots<double> {
   }
 };
 
-// Stages the six nodal components over the B^3 box of tile (t0x, t0y, t0z).
+// Stages the six nodal components over the box of tile (t0x, t0y, t0z).
 template <typename T, int ORDER>
-__device__ inline void load_field_box(T* box, const Batch<const T*>& F, const GridGeom& g, int t0x, int t0y, int t0z,
-                                      int B) {
+__device__ inline void load_field_box(T* box, const Batch<const T*>& F, const GridGeom& g, int t0x, int t0y, int t0z) {
   using S = Shape<T, ORDER>;
+  using X = Box<S::NW>;
   constexpr int FS = FieldSlots<T>::FS;
   const int ox0 = t0x - 1 + S::BASE, oy0 = t0y - 1 + S::BASE, oz0 = t0z - 1 + S::BASE;
-  const int B3 = B * B * B;
-  for (int e = threadIdx.x; e < B3; e += blockDim.x) {
-    const int lx = e / (B * B), ly = (e / B) % B, lz = e % B;
+  for (int e = threadIdx.x; e < X::B3; e += blockDim.x) {
+    const int lx = e / X::B2, ly = (e / X::B) % X::B, lz = e % X::B;
     const size_t gi = ((size_t)modi(ox0 + lx, g.nx) * g.ny + modi(oy0 + ly, g.ny)) * g.nz + modi(oz0 + lz, g.nz);
 #pragma unroll
     for (int c = 0; c < 6; ++c) box[e * FS + c] = F.p[c][gi];
@@ -179,10 +191,11 @@ __device__ inline void load_field_box(T* box, const Batch<const T*>& F, const Gr
 // Gather at one particle from the LDS box (first support node at box index l*) or,
 // outside the margin, from the grid; then the relativistic Boris push and the move.
 template <typename T, int ORDER>
-__device__ inline void gather_push_one(const T* box, int B, const Batch<const T*>& F, const GridGeom& g, int lx, int ly,
+__device__ inline void gather_push_one(const T* box, const Batch<const T*>& F, const GridGeom& g, int lx, int ly,
                                        int lz, int& i, int& j, int& k, T& ox, T& oy, T& oz, T& ux, T& uy, T& uz,
                                        T qdt2m, T dtx, T dty, T dtz) {
   using S = Shape<T, ORDER>;
+  using X = Box<S::NW>;
   constexpr int NW = S::NW;
   constexpr int FS = FieldSlots<T>::FS;
   T wx[NW], wy[NW], wz[NW];
@@ -191,17 +204,17 @@ __device__ inline void gather_push_one(const T* box, int B, const Batch<const T*
   S::weights(oz, wz);
   T f[6] = {0, 0, 0, 0, 0, 0};
   if (lx >= 0 && ly >= 0 && lz >= 0) {
+    const T* p0 = box + (size_t)X::at(lx, ly, lz) * FS;
 #pragma unroll
     for (int a = 0; a < NW; ++a) {
 #pragma unroll
       for (int b = 0; b < NW; ++b) {
-        const int row = ((lx + a) * B + (ly + b)) * B + lz;
         const T wab = wx[a] * wy[b];
 #pragma unroll
         for (int cc = 0; cc < NW; ++cc) {
           const T w = wab * wz[cc];
           T v[6];
-          FieldSlots<T>::read(box + (size_t)(row + cc) * FS, v);
+          FieldSlots<T>::read(p0 + (a * X::B2 + b * X::B + cc) * FS, v);
 #pragma unroll
           for (int m = 0; m < 6; ++m) f[m] += w * v[m];
         }
@@ -236,9 +249,9 @@ __device__ inline void gather_push_one(const T* box, int B, const Batch<const T*
   uy = umy + (upz * sx - upx * sz) + qdt2m * f[1];
   uz = umz + (upx * sy - upy * sx) + qdt2m * f[2];
   const T ig = (T)1 / sqrt((T)1 + ux * ux + uy * uy + uz * uz);
-  i = modi(i + advance_offset(ox, dtx * ux * ig), g.nx);
-  j = modi(j + advance_offset(oy, dty * uy * ig), g.ny);
-  k = modi(k + advance_offset(oz, dtz * uz * ig), g.nz);
+  i = wrapi(i + advance_offset(ox, dtx * ux * ig), g.nx);
+  j = wrapi(j + advance_offset(oy, dty * uy * ig), g.ny);
+  k = wrapi(k + advance_offset(oz, dtz * uz * ig), g.nz);
 }
 
 template <typename T>
@@ -261,7 +274,6 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_perm(GridGeom 
                                                                        const int* __restrict__ perm,
                                                                        const int* __restrict__ starts, int write_sorted,
                                                                        T qdt2m, T dtx, T dty, T dtz) {
-  using S = Shape<T, ORDER>;
   extern __shared__ __align__(16) unsigned char smem[];
   T* box = reinterpret_cast<T*>(smem);
   const int tile = blockIdx.x;
@@ -274,11 +286,10 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_perm(GridGeom 
     }
     return;
   }
-  const int B = tg.ts + S::NW + 1;
   int tx, ty, tz;
   tile_coords(tile, tg, tx, ty, tz);
-  const int t0x = tx * tg.ts, t0y = ty * tg.ts, t0z = tz * tg.ts;
-  load_field_box<T, ORDER>(box, F, g, t0x, t0y, t0z, B);
+  const int t0x = tx * kTile, t0y = ty * kTile, t0z = tz * kTile;
+  load_field_box<T, ORDER>(box, F, g, t0x, t0y, t0z);
   __syncthreads();
   for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
     const int p = perm[qq];
@@ -287,9 +298,8 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_perm(GridGeom 
     (void)decode_cell(in.cell[p], g, nullptr, i, j, k);
     T ox = in.off[0][p], oy = in.off[1][p], oz = in.off[2][p];
     T ux = in.u[0][p], uy = in.u[1][p], uz = in.u[2][p];
-    const int lx = box_index(i, t0x, g.nx, tg.ts), ly = box_index(j, t0y, g.ny, tg.ts),
-              lz = box_index(k, t0z, g.nz, tg.ts);
-    gather_push_one<T, ORDER>(box, B, F, g, lx, ly, lz, i, j, k, ox, oy, oz, ux, uy, uz, qdt2m, dtx, dty, dtz);
+    const int lx = box_index(i, t0x, g.nx), ly = box_index(j, t0y, g.ny), lz = box_index(k, t0z, g.nz);
+    gather_push_one<T, ORDER>(box, F, g, lx, ly, lz, i, j, k, ox, oy, oz, ux, uy, uz, qdt2m, dtx, dty, dtz);
     out.u[0][wi] = ux;
     out.u[1][wi] = uy;
     out.u[2][wi] = uz;
@@ -314,8 +324,8 @@ template <typename T, int ORDER>
 __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom g, TileGeom tg, Batch<const T*> F,
                                                                        SpeciesView<T> in, SpeciesView<T> out,
                                                                        const int* __restrict__ home, int* cursor,
-                                                                       T qdt2m, T dtx, T dty, T dtz) {
-  using S = Shape<T, ORDER>;
+                                                                       const int* __restrict__ nbr_counts, T qdt2m,
+                                                                       T dtx, T dty, T dtz) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* box = reinterpret_cast<T*>(smem);
   __shared__ int cnt[27];
@@ -329,19 +339,25 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
     for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) copy_particle(in, qq, out, base[0] + qq - beg);
     return;
   }
-  const int B = tg.ts + S::NW + 1;
   int tx, ty, tz;
   tile_coords(tile, tg, tx, ty, tz);
-  const int t0x = tx * tg.ts, t0y = ty * tg.ts, t0z = tz * tg.ts;
-  if (threadIdx.x < 27) cnt[threadIdx.x] = 0;
-  load_field_box<T, ORDER>(box, F, g, t0x, t0y, t0z, B);
+  const int t0x = tx * kTile, t0y = ty * kTile, t0z = tz * kTile;
+  if (threadIdx.x < 27) cnt[threadIdx.x] = nbr_counts ? nbr_counts[27 * tile + threadIdx.x] : 0;
+  load_field_box<T, ORDER>(box, F, g, t0x, t0y, t0z);
   __syncthreads();
-  // pass 1: particles per neighbour tile of the new grouping
-  for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
+  // pass 1: particles per neighbour tile of the new grouping (the home tile, the
+  // common case, is counted once per wave), unless the deposition that grouped these
+  // particles has counted them already
+  if (!nbr_counts) for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
     int i, j, k;
     (void)decode_cell(in.cell[qq], g, nullptr, i, j, k);
-    const int nb = neighbour_index(tile_of(i, j, k, tg), tx, ty, tz, tg);
-    if (nb >= 0) atomicAdd(&cnt[nb], 1);
+    const int nb = neighbour_of_cell(i, j, k, tx, ty, tz, tg);
+    const unsigned long long own = __ballot(nb == 13);
+    if (nb == 13) {
+      if (__lane_id() == __ffsll(own) - 1) atomicAdd(&cnt[13], __popcll(own));
+    } else if (nb >= 0) {
+      atomicAdd(&cnt[nb], 1);
+    }
   }
   __syncthreads();
   // one contiguous run per neighbour tile, reserved with a single atomic each
@@ -355,14 +371,23 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
   for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
     int i, j, k;
     (void)decode_cell(in.cell[qq], g, nullptr, i, j, k);
-    const int key = tile_of(i, j, k, tg);
-    const int nb = neighbour_index(key, tx, ty, tz, tg);
-    const int slot = nb >= 0 ? base[nb] + atomicAdd(&cnt[nb], 1) : atomicAdd(&cursor[key], 1);
+    const int nb = neighbour_of_cell(i, j, k, tx, ty, tz, tg);
+    int slot;
+    const unsigned long long own = __ballot(nb == 13);
+    if (nb == 13) {
+      const int lane = __lane_id();
+      const int leader = __ffsll(own) - 1;
+      int b0 = 0;
+      if (lane == leader) b0 = atomicAdd(&cnt[13], __popcll(own));
+      b0 = __shfl(b0, leader);
+      slot = base[13] + b0 + __popcll(own & ((1ull << lane) - 1ull));
+    } else {
+      slot = nb >= 0 ? base[nb] + atomicAdd(&cnt[nb], 1) : atomicAdd(&cursor[tile_of(i, j, k, tg)], 1);
+    }
     T ox = in.off[0][qq], oy = in.off[1][qq], oz = in.off[2][qq];
     T ux = in.u[0][qq], uy = in.u[1][qq], uz = in.u[2][qq];
-    const int lx = box_index(i, t0x, g.nx, tg.ts), ly = box_index(j, t0y, g.ny, tg.ts),
-              lz = box_index(k, t0z, g.nz, tg.ts);
-    gather_push_one<T, ORDER>(box, B, F, g, lx, ly, lz, i, j, k, ox, oy, oz, ux, uy, uz, qdt2m, dtx, dty, dtz);
+    const int lx = box_index(i, t0x, g.nx), ly = box_index(j, t0y, g.ny), lz = box_index(k, t0z, g.nz);
+    gather_push_one<T, ORDER>(box, F, g, lx, ly, lz, i, j, k, ox, oy, oz, ux, uy, uz, qdt2m, dtx, dty, dtz);
     out.u[0][slot] = ux;
     out.u[1][slot] = uy;
     out.u[2][slot] = uz;
@@ -421,11 +446,12 @@ __device__ inline void scatter(const GridGeom& g, int i, int j, int k, T ox, T o
   }
 }
 
-// Fixed-point accumulators of the LDS deposition box.  FP32 runs accumulate int32
-// (one v_cvt per contribution, ds_add_u32) scaled so that the tile's bound on any
-// node sum stays below 2^30: a resolution of about 2^-31 * 8/27 * sum|q w| per
-// contribution, comparable to FP32 rounding.  FP64 runs accumulate int64 scaled
-// to 2^-50 of the largest |q w|, rounded with the exact 1.5*2^52 add.
+// Fixed-point accumulators of the LDS deposition box.  A contribution (already scaled
+// by 2^sh) becomes the nearest integer with one FMA and one integer subtraction:
+// adding 1.5 * 2^p (p = 23 for FP32, 52 for FP64) to a value of magnitude at most
+// 2^(p-1) rounds it to an integer that sits in the low bits of the sum.  FP32 runs
+// accumulate int32 (ds_add_u32), FP64 runs int64 (ds_add_u64): integer LDS atomics
+// retire about 20x faster than float ones on gfx950.
 template <typename T>
 struct Fixed;
 
@@ -434,18 +460,21 @@ struct Fixed;
 template <>
 struct Fixed<float> {
   using acc_t = int;
-  __device__ static inline int shift(int e_sum, int e_max, int h) { return 30 - e_sum; }
-  __device__ static inline acc_t conv(float x) { return __float2int_rn(x); }
+  // node sums below 2^30, single contributions at most 2^22 (the rounding add's range)
+  __device__ static inline int shift(int e_sum, int e_max, int h) { return min(30 - e_sum, 22 - e_max); }
+  __device__ static inline acc_t fma_round(float a, float b) {
+    return __float_as_int(fmaf(a, b, 12582912.0f)) - 0x4B400000;
+  }
   __device__ static inline void add(acc_t* a, acc_t v) { atomicAdd(a, v); }
 };
 
 template <>
 struct Fixed<double> {
   using acc_t = long long;
-  // |sum| < 2^(h + e_max + sh) <= 2^62; each contribution < 2^50 (exact rounding below)
+  // |sum| < 2^(h + e_max + sh) <= 2^62; each contribution at most 2^50
   __device__ static inline int shift(int e_sum, int e_max, int h) { return min(62 - e_max - h, 50 - e_max); }
-  __device__ static inline acc_t conv(double x) {
-    return __double_as_longlong(x + 6755399441055744.0) - 0x4338000000000000LL;
+  __device__ static inline acc_t fma_round(double a, double b) {
+    return __double_as_longlong(fma(a, b, 6755399441055744.0)) - 0x4338000000000000LL;
   }
   __device__ static inline void add(acc_t* a, acc_t v) {
     atomicAdd(reinterpret_cast<unsigned long long*>(a), (unsigned long long)v);
@@ -464,57 +493,181 @@ struct MaxWeight<3> {
   static constexpr double value = 8.0 / 27.0;
 };
 
-// Adds the shape-weighted values of one particle, as fixed-point integers scaled by
-// 2^sh, to a (B x B x B) LDS box whose first support node is (lx, ly, lz).
-// Integer LDS atomics retire about 20x faster than float LDS atomics on gfx950.
-template <typename T, int ORDER>
-__device__ inline void scatter_lds(typename Fixed<T>::acc_t* box, int B, int lx, int ly, int lz, T ox, T oy, T oz,
-                                   const T* val, int nval, const int* sh) {
+// Adds the shape-weighted values sv[0..NVAL) (already scaled to fixed point) of one
+// particle to NVAL consecutive components of the LDS box; ``at`` is the box index of
+// the first support node.  Every atomic addresses ``at`` plus a constant, which the
+// instruction carries as an immediate offset.
+template <typename T, int ORDER, int NVAL>
+__device__ inline void scatter_lds(typename Fixed<T>::acc_t* box, int at, T ox, T oy, T oz, const T* sv) {
   using S = Shape<T, ORDER>;
+  using X = Box<S::NW>;
   constexpr int NW = S::NW;
   T wx[NW], wy[NW], wz[NW];
   S::weights(ox, wx);
   S::weights(oy, wy);
   S::weights(oz, wz);
-  const int B3 = B * B * B;
-  T sv[3];
-  for (int q = 0; q < nval; ++q) sv[q] = ldexp(val[q], sh[q]);
+  typename Fixed<T>::acc_t* b0 = box + at;
 #pragma unroll
-  for (int a = 0; a < NW; ++a) {
+  for (int q = 0; q < NVAL; ++q) {
 #pragma unroll
-    for (int b = 0; b < NW; ++b) {
-      const T wab = wx[a] * wy[b];
-      const int row = ((lx + a) * B + (ly + b)) * B + lz;
+    for (int a = 0; a < NW; ++a) {
+      const T xa = sv[q] * wx[a];
 #pragma unroll
-      for (int cc = 0; cc < NW; ++cc) {
-        const T w = wab * wz[cc];
-        for (int q = 0; q < nval; ++q) Fixed<T>::add(&box[q * B3 + row + cc], Fixed<T>::conv(w * sv[q]));
+      for (int b = 0; b < NW; ++b) {
+        const T xab = xa * wy[b];
+#pragma unroll
+        for (int cc = 0; cc < NW; ++cc)
+          Fixed<T>::add(b0 + q * X::B3 + a * X::B2 + b * X::B + cc, Fixed<T>::fma_round(xab, wz[cc]));
       }
     }
   }
 }
 
+// Order of the particles inside a deposition chunk.  LDS atomics of a wave retire
+// without bank conflicts when the 32 lanes of each half wave address distinct words
+// modulo 32 (4-byte accumulators), or the 16 lanes of each quarter wave distinct
+// 8-byte words modulo 16 (measured on gfx950).  All atomics of a particle are at its
+// first support node plus a constant, so particles whose first nodes differ modulo
+// KG never conflict: they are dealt round-robin over the KG residues, row r of the
+// deal holding the r-th particle of every residue that has one.
+template <typename T>
+struct DepositOrder {
+  static constexpr int KG = sizeof(typename Fixed<T>::acc_t) == 4 ? 32 : 16;
+  static constexpr int CH = sizeof(typename Fixed<T>::acc_t) == 4 ? 1024 : 512;  // particles per chunk
+};
+
+// One particle as stored: cell, offsets, momentum (J only) and weight.  Loaded in one
+// go, so that the loads of several particles are in flight together.
+template <typename T>
+struct Raw {
+  int cell;
+  T o[3], u[3], w;
+};
+
+template <typename T, bool WJ>
+__device__ inline void load_raw(const SpeciesView<T>& sp, int p, Raw<T>& r) {
+  r.cell = sp.cell[p];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) r.o[d] = sp.off[d][p];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) r.u[d] = WJ ? sp.u[d][p] : (T)0;
+  r.w = sp.w ? sp.w[p] : (T)sp.w_const;
+}
+
+// What the deposition needs of one particle: its cell and offsets at x, the velocity,
+// the cell and offsets at x - dt v / 2, and the box indices of the first support
+// node at both positions (-1 outside the box margin).
+template <typename T>
+struct DepositPoint {
+  int i, j, k, ih, jh, kh, at_rho, at_j;
+  T ox, oy, oz, hx, hy, hz, vx, vy, vz;
+};
+
+template <typename T, int ORDER, bool WJ>
+__device__ inline bool locate(const Raw<T>& r, const GridGeom& g, int t0x, int t0y, int t0z, T hdtx, T hdty, T hdtz,
+                              int* bad, DepositPoint<T>& d) {
+  using X = Box<Shape<T, ORDER>::NW>;
+  if (!decode_cell(r.cell, g, bad, d.i, d.j, d.k)) return false;
+  d.ox = r.o[0];
+  d.oy = r.o[1];
+  d.oz = r.o[2];
+  {
+    const int lx = box_index(d.i, t0x, g.nx), ly = box_index(d.j, t0y, g.ny), lz = box_index(d.k, t0z, g.nz);
+    d.at_rho = (lx >= 0 && ly >= 0 && lz >= 0) ? X::at(lx, ly, lz) : -1;
+  }
+  d.at_j = -1;
+  if (WJ) {
+    const T ig = (T)1 / sqrt((T)1 + r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
+    d.vx = r.u[0] * ig;
+    d.vy = r.u[1] * ig;
+    d.vz = r.u[2] * ig;
+    // x^{n+1/2} = x^{n+1} - dt v / 2
+    d.hx = d.ox;
+    d.hy = d.oy;
+    d.hz = d.oz;
+    d.ih = wrapi(d.i + advance_offset(d.hx, -hdtx * d.vx), g.nx);
+    d.jh = wrapi(d.j + advance_offset(d.hy, -hdty * d.vy), g.ny);
+    d.kh = wrapi(d.k + advance_offset(d.hz, -hdtz * d.vz), g.nz);
+    const int lx = box_index(d.ih, t0x, g.nx), ly = box_index(d.jh, t0y, g.ny), lz = box_index(d.kh, t0z, g.nz);
+    d.at_j = (lx >= 0 && ly >= 0 && lz >= 0) ? X::at(lx, ly, lz) : -1;
+  }
+  return true;
+}
+
+// Scale bounds of one particle: |q w| (rho) and |q w v_c| (J^c), summed and maxed.
+template <typename T, bool WJ>
+__device__ inline void bound_add(const Raw<T>& r, T* sw, T* mw) {
+  const T a = fabs(r.w);
+  sw[0] += a;
+  mw[0] = fmax(mw[0], a);
+  if (WJ) {
+    const T ig = (T)1 / sqrt((T)1 + r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const T v = a * fabs(r.u[d] * ig);
+      sw[1 + d] += v;
+      mw[1 + d] = fmax(mw[1 + d], v);
+    }
+  }
+}
+
+// In-place exclusive prefix sum of a[0..n) by the whole block (wtot: one int per wave).
+__device__ inline void block_exclusive_scan(int* a, int n, int* wtot) {
+  const int per = (n + (int)blockDim.x - 1) / (int)blockDim.x;
+  const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
+  int s = 0;
+  for (int e = lo; e < hi; ++e) s += a[e];
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  int x = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wtot[wave] = x;
+  __syncthreads();
+  int run = x - s;
+  for (int w = 0; w < wave; ++w) run += wtot[w];
+  for (int e = lo; e < hi; ++e) {
+    const int v = a[e];
+    a[e] = run;
+    run += v;
+  }
+  __syncthreads();
+}
 
 // One block per tile: rho (at x) and J (at x - dt v/2) of the tile's particles are
-// accumulated in LDS over a box of B = ts + NW + 1 nodes per axis (the tile, the
-// shape support and a one-cell margin for particles that moved since the sort),
+// accumulated in LDS over a box of B = kTile + NW + 1 nodes per axis (the tile, the
+// shape support and a one-cell margin for particles that moved since the grouping),
 // then stored to the tile's staging slot; k_deposit_reduce adds the overlapping
-// boxes on the grid.  (A particle outside the margin is added to the grid
-// directly with global atomics.)
-template <typename T, int ORDER>
+// boxes on the grid.  (A particle outside the margin is added to the grid directly
+// with global atomics.)  With next_counts, the tiles of the particles' cells (the
+// next grouping) are counted: per tile in next_counts, per neighbour of this tile in
+// nbr_counts[27 * tile ...] (what the next gather of this tile's particles reserves).
+template <typename T, int ORDER, bool WJ>
 __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp,
-                                                       const int* __restrict__ perm, const int* __restrict__ starts,
-                                                       Batch<T*> out, T* __restrict__ stage, T qdv, int with_j, T hdtx,
-                                                       T hdty, T hdtz, int* bad, int* next_counts) {
+                                                                     const int* __restrict__ perm,
+                                                                     const int* __restrict__ starts, Batch<T*> out,
+                                                                     T* __restrict__ stage, T qdv, T hdtx, T hdty,
+                                                                     T hdtz, int* bad, int* next_counts,
+                                                                     int* nbr_counts) {
   using S = Shape<T, ORDER>;
-  constexpr int NW = S::NW;
+  using X = Box<S::NW>;
+  using O = DepositOrder<T>;
   using acc_t = typename Fixed<T>::acc_t;
+  constexpr int ncomp = WJ ? 4 : 1;
   extern __shared__ __align__(16) unsigned char smem[];
   acc_t* box = reinterpret_cast<acc_t*>(smem);
   constexpr int kWaves = PIC_DEPOSIT_BLOCK / 64;
   __shared__ T red[4 * kWaves];
   __shared__ T redm[4 * kWaves];
+  __shared__ int shs[4];
   __shared__ int cnt[27];
+  __shared__ int wtot[kWaves];
+  __shared__ __align__(16) int hist[O::KG];
+  __shared__ unsigned short kr[O::CH];
+  __shared__ unsigned short order[O::CH];
+  __shared__ unsigned rowmask[O::CH];
+  __shared__ int rowstart[O::CH];
   const int tile = blockIdx.x;
   const int beg = starts[tile], end = starts[tile + 1];
   if (beg == end) return;
@@ -522,127 +675,234 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
     if (next_counts && threadIdx.x == 0) atomicAdd(&next_counts[tg.ntiles], end - beg);
     return;
   }
-  const int ts = tg.ts;
-  const int B = ts + NW + 1;
-  const int B3 = B * B * B;
-  const int ncomp = with_j ? 4 : 1;
-  // Fixed-point scales 2^sh[c], one per deposited component.  A node of this box
-  // receives from each particle of the tile at most MaxWeight * |q w| / dV (rho) or
-  // MaxWeight * |q w v_c| / dV (J^c): every partial sum is bounded by MaxWeight times the
-  // tile's sum of those magnitudes (< 2^e_sum), every contribution by their max (< 2^e_max).
-  // per component c (rho, J^x, J^y, J^z): sum and max over the tile of |q w| (rho) or
-  // |q w v_c| (J^c), the bounds that set that component's scale
-  T sw[4] = {0, 0, 0, 0}, mw[4] = {0, 0, 0, 0};
-  for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
-    const int p = perm ? perm[qq] : qq;
-    const T a = fabs(sp.w ? sp.w[p] : (T)sp.w_const);
-    sw[0] += a;
-    mw[0] = fmax(mw[0], a);
-    if (with_j) {
-      const T ux = sp.u[0][p], uy = sp.u[1][p], uz = sp.u[2][p];
-      const T ig = (T)1 / sqrt((T)1 + ux * ux + uy * uy + uz * uz);
-      const T v[3] = {fabs(ux * ig), fabs(uy * ig), fabs(uz * ig)};
-      for (int d = 0; d < 3; ++d) {
-        sw[1 + d] += a * v[d];
-        mw[1 + d] = fmax(mw[1 + d], a * v[d]);
-      }
-    }
-  }
-  for (int c = 0; c < ncomp; ++c) {
-    for (int o = 32; o > 0; o >>= 1) {
-      sw[c] += __shfl_xor(sw[c], o, 64);
-      mw[c] = fmax(mw[c], __shfl_xor(mw[c], o, 64));
-    }
-    if ((threadIdx.x & 63) == 0) {
-      red[c * kWaves + (threadIdx.x >> 6)] = sw[c];
-      redm[c * kWaves + (threadIdx.x >> 6)] = mw[c];
-    }
-  }
-  __syncthreads();
-  __shared__ int shs[4];
-  if (threadIdx.x < ncomp) {
-    const int c = threadIdx.x;
-    T m = 0, x = 0;
-    for (int w = 0; w < kWaves; ++w) {
-      m += red[c * kWaves + w];
-      x = fmax(x, redm[c * kWaves + w]);
-    }
-    // a little slack on the bound covers the rounding of the FP sum itself
-    int e_sum = 0, e_max = 0;
-    (void)frexp(m * fabs(qdv) * (T)(MaxWeight<ORDER>::value * 1.001), &e_sum);
-    (void)frexp(x * fabs(qdv) * (T)1.001, &e_max);
-    shs[c] = Fixed<T>::shift(e_sum, e_max, 32 - __clz(end - beg));
-  }
-  __syncthreads();
-  int sh[4];
-  for (int c = 0; c < 4; ++c) sh[c] = (c < ncomp) ? shs[c] : 0;
   int ti, tj, tk;
   tile_coords(tile, tg, ti, tj, tk);
-  const int t0x = ti * ts, t0y = tj * ts, t0z = tk * ts;
-  for (int k = threadIdx.x; k < ncomp * B3; k += blockDim.x) box[k] = 0;
-  if (threadIdx.x < 27) cnt[threadIdx.x] = 0;
-  __syncthreads();
-  for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
-    const int p = perm ? perm[qq] : qq;
-    int i, j, k;
-    if (!decode_cell(sp.cell[p], g, bad, i, j, k)) continue;
-    const T ox = sp.off[0][p], oy = sp.off[1][p], oz = sp.off[2][p];
-    const T qw = qdv * (sp.w ? sp.w[p] : (T)sp.w_const);
-    if (next_counts) {  // the tile of this position groups the particle in the next step
-      const int key = tile_of(i, j, k, tg);
-      const int nb = neighbour_index(key, ti, tj, tk, tg);
-      if (nb >= 0) atomicAdd(&cnt[nb], 1);
-      else atomicAdd(&next_counts[key], 1);
+  const int t0x = ti * kTile, t0y = tj * kTile, t0z = tk * kTile;
+  // Fixed-point scales 2^sh[c], one per deposited component (rho, J^x, J^y, J^z).  A
+  // node of this box receives from each particle of the tile at most MaxWeight * |q w|
+  // / dV (rho) or MaxWeight * |q w v_c| / dV (J^c): every partial sum is bounded by
+  // MaxWeight times the tile's sum of those magnitudes (< 2^e_sum), every contribution
+  // by their max (< 2^e_max).  A tile of one chunk takes the bounds in the chunk's
+  // first pass; a larger one in a pass of its own.
+  const bool single = end - beg <= O::CH;
+  T sw[4] = {0, 0, 0, 0}, mw[4] = {0, 0, 0, 0};
+  auto publish_bounds = [&]() {  // wave partials -> red / redm
+#pragma unroll
+    for (int c = 0; c < ncomp; ++c) {
+      for (int o = 32; o > 0; o >>= 1) {
+        sw[c] += __shfl_xor(sw[c], o, 64);
+        mw[c] = fmax(mw[c], __shfl_xor(mw[c], o, 64));
+      }
+      if ((threadIdx.x & 63) == 0) {
+        red[c * kWaves + (threadIdx.x >> 6)] = sw[c];
+        redm[c * kWaves + (threadIdx.x >> 6)] = mw[c];
+      }
     }
-    {
-      const int lx = box_index(i, t0x, g.nx, ts), ly = box_index(j, t0y, g.ny, ts), lz = box_index(k, t0z, g.nz, ts);
-      T val[1] = {qw};
-      if (lx >= 0 && ly >= 0 && lz >= 0) {
-        scatter_lds<T, ORDER>(box, B, lx, ly, lz, ox, oy, oz, val, 1, sh);
+  };
+  auto finish_bounds = [&]() {  // red / redm -> shs (threads 0..ncomp-1)
+    if (threadIdx.x < ncomp) {
+      const int c = threadIdx.x;
+      T m = 0, x = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        m += red[c * kWaves + w];
+        x = fmax(x, redm[c * kWaves + w]);
+      }
+      // a little slack on the bound covers the rounding of the FP sum itself
+      int e_sum = 0, e_max = 0;
+      (void)frexp(m * fabs(qdv) * (T)(MaxWeight<ORDER>::value * 1.001), &e_sum);
+      (void)frexp(x * fabs(qdv) * (T)1.001, &e_max);
+      shs[c] = Fixed<T>::shift(e_sum, e_max, 32 - __clz(end - beg));
+    }
+  };
+  if (!single) {
+    for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
+      Raw<T> r;
+      load_raw<T, WJ>(sp, perm ? perm[qq] : qq, r);
+      bound_add<T, WJ>(r, sw, mw);
+    }
+    publish_bounds();
+    __syncthreads();
+    finish_bounds();
+  }
+  for (int k = threadIdx.x; k < ncomp * X::B3; k += blockDim.x) box[k] = 0;
+  if (threadIdx.x < 27) cnt[threadIdx.x] = 0;
+  for (int cb = beg; cb < end; cb += O::CH) {
+    const int nc = min(O::CH, end - cb);
+    if (threadIdx.x < O::KG) hist[threadIdx.x] = 0;
+    __syncthreads();
+    // pass 1: residue of each particle's first J (rho-only: rho) support node and its
+    // rank among the chunk's particles of that residue; two particles per thread in flight
+    for (int e0 = threadIdx.x; e0 < nc; e0 += 2 * blockDim.x) {
+      Raw<T> r[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = min(e0 + u * (int)blockDim.x, nc - 1);
+        load_raw<T, WJ>(sp, perm ? perm[cb + e] : cb + e, r[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = e0 + u * (int)blockDim.x;
+        if (e < nc) {
+          DepositPoint<T> d;
+          int key = 0;
+          if (locate<T, ORDER, WJ>(r[u], g, t0x, t0y, t0z, hdtx, hdty, hdtz, nullptr, d)) {
+            const int at = WJ ? d.at_j : d.at_rho;
+            key = at >= 0 ? (at & (O::KG - 1)) : 0;
+          }
+          const int rk = atomicAdd(&hist[key], 1);
+          kr[e] = (unsigned short)(rk * O::KG + key);
+          if (single) bound_add<T, WJ>(r[u], sw, mw);
+        }
+      }
+    }
+    if (single) publish_bounds();
+    __syncthreads();
+    if (single) finish_bounds();
+    // row r of the deal: a bit per residue with an r-th particle, and the row's start
+    int R = 0;
+#pragma unroll
+    for (int k = 0; k < O::KG; k += 4) {
+      const int4 h4 = *reinterpret_cast<const int4*>(&hist[k]);
+      R = max(R, max(max(h4.x, h4.y), max(h4.z, h4.w)));
+    }
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+      unsigned m = 0;
+#pragma unroll 4
+      for (int k = 0; k < O::KG; ++k) m |= (hist[k] > r ? 1u : 0u) << k;
+      rowmask[r] = m;
+      rowstart[r] = __popc(m);
+    }
+    __syncthreads();
+    block_exclusive_scan(rowstart, R, wtot);
+    for (int e = threadIdx.x; e < nc; e += blockDim.x) {
+      const int v = kr[e];
+      const int r = v / O::KG, key = v % O::KG;
+      order[rowstart[r] + __popc(rowmask[r] & ((1u << key) - 1u))] = (unsigned short)e;
+    }
+    __syncthreads();
+    int sh[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sh[c] = (c < ncomp) ? shs[c] : 0;
+    // pass 2: deposit in the dealt order, the next particle's loads in flight meanwhile
+    Raw<T> nxt;
+    if ((int)threadIdx.x < nc) {
+      const int q = cb + order[threadIdx.x];
+      load_raw<T, WJ>(sp, perm ? perm[q] : q, nxt);
+    }
+    for (int pos = threadIdx.x; pos < nc; pos += blockDim.x) {
+      const Raw<T> r = nxt;
+      {
+        const int q = cb + order[min(pos + (int)blockDim.x, nc - 1)];
+        load_raw<T, WJ>(sp, perm ? perm[q] : q, nxt);
+      }
+      DepositPoint<T> d;
+      if (!locate<T, ORDER, WJ>(r, g, t0x, t0y, t0z, hdtx, hdty, hdtz, bad, d)) continue;
+      if (next_counts) {  // the tile of this position groups the particle in the next step
+        const int nb = neighbour_of_cell(d.i, d.j, d.k, ti, tj, tk, tg);
+        const unsigned long long own = __ballot(nb == 13);
+        if (nb == 13) {
+          if (__lane_id() == __ffsll(own) - 1) atomicAdd(&cnt[13], __popcll(own));
+        } else if (nb >= 0) {
+          atomicAdd(&cnt[nb], 1);
+        } else {
+          atomicAdd(&next_counts[tile_of(d.i, d.j, d.k, tg)], 1);
+        }
+      }
+      const T qw = qdv * r.w;
+      if (d.at_rho >= 0) {
+        const T sv[1] = {ldexp(qw, sh[0])};
+        scatter_lds<T, ORDER, 1>(box, d.at_rho, d.ox, d.oy, d.oz, sv);
       } else {
         T* dst[1] = {out.p[0]};
-        scatter<T, ORDER>(g, i, j, k, ox, oy, oz, dst, val, 1);
+        const T val[1] = {qw};
+        scatter<T, ORDER>(g, d.i, d.j, d.k, d.ox, d.oy, d.oz, dst, val, 1);
+      }
+      if (WJ) {
+        if (d.at_j >= 0) {
+          const T sv[3] = {ldexp(qw * d.vx, sh[1]), ldexp(qw * d.vy, sh[2]), ldexp(qw * d.vz, sh[3])};
+          scatter_lds<T, ORDER, 3>(box + X::B3, d.at_j, d.hx, d.hy, d.hz, sv);
+        } else {
+          T* dst[3] = {out.p[1], out.p[2], out.p[3]};
+          const T val[3] = {qw * d.vx, qw * d.vy, qw * d.vz};
+          scatter<T, ORDER>(g, d.ih, d.jh, d.kh, d.hx, d.hy, d.hz, dst, val, 3);
+        }
       }
     }
-    if (with_j) {
-      const T ux = sp.u[0][p], uy = sp.u[1][p], uz = sp.u[2][p];
-      const T ig = (T)1 / sqrt((T)1 + ux * ux + uy * uy + uz * uz);
-      const T vx = ux * ig, vy = uy * ig, vz = uz * ig;
-      // x^{n+1/2} = x^{n+1} - dt v / 2
-      T hx = ox, hy = oy, hz = oz;
-      const int ih = modi(i + advance_offset(hx, -hdtx * vx), g.nx);
-      const int jh = modi(j + advance_offset(hy, -hdty * vy), g.ny);
-      const int kh = modi(k + advance_offset(hz, -hdtz * vz), g.nz);
-      T val[3] = {qw * vx, qw * vy, qw * vz};
-      const int lx = box_index(ih, t0x, g.nx, ts), ly = box_index(jh, t0y, g.ny, ts),
-                lz = box_index(kh, t0z, g.nz, ts);
-      if (lx >= 0 && ly >= 0 && lz >= 0) {
-        scatter_lds<T, ORDER>(box + B3, B, lx, ly, lz, hx, hy, hz, val, 3, sh + 1);
-      } else {
-        T* dst[3] = {out.p[1], out.p[2], out.p[3]};
-        scatter<T, ORDER>(g, ih, jh, kh, hx, hy, hz, dst, val, 3);
-      }
-    }
+    __syncthreads();
   }
-  __syncthreads();
-  if (next_counts && threadIdx.x < 27 && cnt[threadIdx.x] > 0)
-    atomicAdd(&next_counts[neighbour_key(threadIdx.x, ti, tj, tk, tg)], cnt[threadIdx.x]);
+  if (next_counts && threadIdx.x < 27) {
+    const int n = cnt[threadIdx.x];
+    if (n > 0) atomicAdd(&next_counts[neighbour_key(threadIdx.x, ti, tj, tk, tg)], n);
+    if (nbr_counts) nbr_counts[27 * tile + threadIdx.x] = n;
+  }
   // the whole box goes to this tile's staging slot (plain stores, zeros included)
-  T* dstage = stage + (size_t)tile * ncomp * B3;
-  for (int k = threadIdx.x; k < ncomp * B3; k += blockDim.x) dstage[k] = ldexp((T)box[k], -sh[k / B3]);
+  T* dstage = stage + (size_t)tile * ncomp * X::B3;
+  for (int k = threadIdx.x; k < ncomp * X::B3; k += blockDim.x) dstage[k] = ldexp((T)box[k], -shs[k / X::B3]);
 }
 
-// Sums, for every grid node, the staging boxes of all non-empty tiles that cover it
-// (box node l of tile t along an axis is grid node (t*ts - 1 + BASE + l) mod n) and
-// adds the sums to the nodal arrays.  Each node is owned by one thread: no atomics.
+// Per axis, the (tile, box index) pairs whose boxes hold grid node x on grids that are
+// whole multiples of the tile: its own tile t at l0 = x mod kTile + 1 - BASE, and
+// t - 1 at l0 + kTile or t + 1 at l0 - kTile when that index lies inside the box.
+template <int ORDER>
+__device__ inline int axis_candidates(int x, int nt, int* t, int* l) {
+  using S = Shape<float, ORDER>;
+  using X = Box<S::NW>;
+  const int tt = x / kTile, l0 = x % kTile + 1 - S::BASE;
+  t[0] = tt;
+  l[0] = l0;
+  if (l0 + kTile < X::B) {
+    t[1] = tt == 0 ? nt - 1 : tt - 1;
+    l[1] = l0 + kTile;
+    return 2;
+  }
+  if (l0 - kTile >= 0) {
+    t[1] = tt == nt - 1 ? 0 : tt + 1;
+    l[1] = l0 - kTile;
+    return 2;
+  }
+  return 1;
+}
+
+// Sums, for every grid node, the staging boxes of the non-empty tiles that cover it
+// and adds the sums to the nodal arrays; each node is owned by one thread, so no
+// atomics.  Grids that are whole multiples of the tile; grid (z blocks, ny, nx).
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGeom tg, const int* __restrict__ starts,
+                                                              const T* __restrict__ stage, Batch<T*> out, int ncomp) {
+  using X = Box<Shape<T, ORDER>::NW>;
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= g.nz) return;
+  const int y = blockIdx.y, x = blockIdx.z;
+  int tx[2], lx[2], ty[2], ly[2], tz[2], lz[2];
+  const int nxc = axis_candidates<ORDER>(x, tg.ntx, tx, lx);
+  const int nyc = axis_candidates<ORDER>(y, tg.nty, ty, ly);
+  const int nzc = axis_candidates<ORDER>(z, tg.ntz, tz, lz);
+  T acc[4] = {0, 0, 0, 0};
+  for (int a = 0; a < nxc; ++a)
+    for (int b = 0; b < nyc; ++b)
+      for (int c = 0; c < nzc; ++c) {
+        const int tile = (tx[a] * tg.nty + ty[b]) * tg.ntz + tz[c];
+        if (starts[tile] == starts[tile + 1]) continue;
+        const T* sb = stage + (size_t)tile * ncomp * X::B3 + X::at(lx[a], ly[b], lz[c]);
+        if (ncomp == 4) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q] += sb[q * X::B3];
+        } else {
+          acc[0] += sb[0];
+        }
+      }
+  const size_t idx = ((size_t)x * g.ny + y) * g.nz + z;
+  for (int q = 0; q < ncomp; ++q) out.p[q][idx] += acc[q];
+}
+
+// The same for any grid (partial tiles at the upper ends): candidate (tile, box index)
+// pairs per axis over the periodic images x - n, x, x + n, box node l of tile t being
+// grid node (t * kTile - 1 + BASE + l) mod n.
 template <typename T, int ORDER>
 __global__ void __launch_bounds__(256) k_deposit_reduce(GridGeom g, TileGeom tg, const int* __restrict__ starts,
                                                         const T* __restrict__ stage, Batch<T*> out, int ncomp) {
   using S = Shape<T, ORDER>;
-  constexpr int NW = S::NW;
-  const int ts = tg.ts;
-  const int B = ts + NW + 1;
-  const int B3 = B * B * B;
+  using X = Box<S::NW>;
   const long long N = (long long)g.nx * g.ny * g.nz;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < N;
        idx += (long long)gridDim.x * blockDim.x) {
@@ -650,7 +910,6 @@ __global__ void __launch_bounds__(256) k_deposit_reduce(GridGeom g, TileGeom tg,
     const long long r = idx / g.nz;
     const int y = (int)(r % g.ny);
     const int x = (int)(r / g.ny);
-    // candidate (tile, box index) pairs per axis over the periodic images x - n, x, x + n
     int ctx_[8], clx[8], cty[8], cly[8], ctz[8], clz[8];
     int nx_ = 0, ny_ = 0, nz_ = 0;
     const int pos[3] = {x, y, z};
@@ -661,13 +920,13 @@ __global__ void __launch_bounds__(256) k_deposit_reduce(GridGeom g, TileGeom tg,
       int* cl = d == 0 ? clx : (d == 1 ? cly : clz);
       int cnt = 0;
       for (int im = -1; im <= 1; ++im) {
-        const int X = pos[d] + im * n[d];
-        // tiles t with 0 <= X - (t*ts - 1 + BASE) < B
-        const int hi = (X + 1 - S::BASE);
-        int tmax = hi >= 0 ? hi / ts : -((-hi + ts - 1) / ts);
+        const int X0 = pos[d] + im * n[d];
+        // tiles t with 0 <= X0 - (t*kTile - 1 + BASE) < B
+        const int hi = (X0 + 1 - S::BASE);
+        int tmax = hi >= 0 ? hi / kTile : -((-hi + kTile - 1) / kTile);
         for (int t = tmax; t >= 0 && cnt < 8; --t) {
-          const int l = X - (t * ts - 1 + S::BASE);
-          if (l >= B) break;
+          const int l = X0 - (t * kTile - 1 + S::BASE);
+          if (l >= X::B) break;
           if (t < nt[d] && l >= 0) {
             ct[cnt] = t;
             cl[cnt] = l;
@@ -683,13 +942,12 @@ __global__ void __launch_bounds__(256) k_deposit_reduce(GridGeom g, TileGeom tg,
         for (int c = 0; c < nz_; ++c) {
           const int tile = (ctx_[a] * tg.nty + cty[b]) * tg.ntz + ctz[c];
           if (starts[tile] == starts[tile + 1]) continue;
-          const T* sb = stage + (size_t)tile * ncomp * B3 + (clx[a] * B + cly[b]) * B + clz[c];
-          for (int q = 0; q < ncomp; ++q) acc[q] += sb[(size_t)q * B3];
+          const T* sb = stage + (size_t)tile * ncomp * X::B3 + X::at(clx[a], cly[b], clz[c]);
+          for (int q = 0; q < ncomp; ++q) acc[q] += sb[(size_t)q * X::B3];
         }
     for (int q = 0; q < ncomp; ++q) out.p[q][idx] += acc[q];
   }
 }
-
 
 }  // namespace
 
@@ -708,11 +966,11 @@ void allow_lds(const void* kernel, size_t bytes) {
   }
 }
 
-int deposit_box(int shape_order, int ts) { return ts + (shape_order == 1 ? 2 : 4) + 1; }
+int deposit_box(int shape_order) { return kTile + (shape_order == 1 ? 2 : 4) + 1; }
 template <typename T>
 void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3], const T* const B[3],
                        const SpeciesView<T>& in, const SpeciesView<T>& out, const int* perm, const int* starts,
-                       bool write_sorted, int* home_cursor, hipStream_t s) {
+                       bool write_sorted, int* home_cursor, const int* nbr_counts, hipStream_t s) {
   if (in.n <= 0) return;
   Batch<const T*> F{};
   for (int d = 0; d < 3; ++d) {
@@ -721,18 +979,18 @@ void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3]
   }
   const T qdt2m = (T)(in.q * g.dt / (2.0 * in.m));
   const T dtx = (T)(g.dt / g.dx), dty = (T)(g.dt / g.dy), dtz = (T)(g.dt / g.dz);
-  const int Bx = deposit_box(g.shape_order, t.ts);
+  const int Bx = deposit_box(g.shape_order);
   const size_t lds = (size_t)Bx * Bx * Bx * FieldSlots<T>::FS * sizeof(T);
   const dim3 grid(t.ntiles + 1), block(PIC_GATHER_BLOCK);
   if (home_cursor) {
     if (g.shape_order == 1) {
       allow_lds((const void*)k_gather_push_home<T, 1>, lds);
       hipLaunchKernelGGL((k_gather_push_home<T, 1>), grid, block, lds, s, g, t, F, in, out, starts, home_cursor,
-                         qdt2m, dtx, dty, dtz);
+                         nbr_counts, qdt2m, dtx, dty, dtz);
     } else {
       allow_lds((const void*)k_gather_push_home<T, 3>, lds);
       hipLaunchKernelGGL((k_gather_push_home<T, 3>), grid, block, lds, s, g, t, F, in, out, starts, home_cursor,
-                         qdt2m, dtx, dty, dtz);
+                         nbr_counts, qdt2m, dtx, dty, dtz);
     }
   } else {
     const int ws = write_sorted ? 1 : 0;
@@ -748,27 +1006,33 @@ void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3]
   }
 }
 
+template <typename T, int ORDER, bool WJ>
+void launch_deposit(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
+                    T* stage, int* bad, int* next_counts, int* nbr_counts, const Batch<T*>& out, hipStream_t s) {
+  const T qdv = (T)(sp.q / (g.dx * g.dy * g.dz));
+  const T hx = (T)(0.5 * g.dt / g.dx), hy = (T)(0.5 * g.dt / g.dy), hz = (T)(0.5 * g.dt / g.dz);
+  constexpr int B = Box<Shape<T, ORDER>::NW>::B;
+  const size_t lds = (size_t)(WJ ? 4 : 1) * B * B * B * sizeof(typename Fixed<T>::acc_t);
+  allow_lds((const void*)k_deposit_tiled<T, ORDER, WJ>, lds);
+  hipLaunchKernelGGL((k_deposit_tiled<T, ORDER, WJ>), dim3(t.ntiles + 1), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp,
+                     perm, starts, out, stage, qdv, hx, hy, hz, bad, next_counts, nbr_counts);
+}
+
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
-                   bool with_j, T* stage, int* bad, int* next_counts, T* rho, T* const J[3], hipStream_t s) {
+                   bool with_j, T* stage, int* bad, int* next_counts, int* nbr_counts, T* rho, T* const J[3],
+                   hipStream_t s) {
   if (sp.n <= 0) return;
   Batch<T*> out{};
   out.p[0] = rho;
   for (int d = 0; d < 3; ++d) out.p[1 + d] = J ? J[d] : nullptr;
-  const T qdv = (T)(sp.q / (g.dx * g.dy * g.dz));
-  const T hx = (T)(0.5 * g.dt / g.dx), hy = (T)(0.5 * g.dt / g.dy), hz = (T)(0.5 * g.dt / g.dz);
-  const int wj = with_j ? 1 : 0;
-  const int ncomp = with_j ? 4 : 1;
-  const int B = deposit_box(g.shape_order, t.ts);
-  const size_t lds = (size_t)ncomp * B * B * B * sizeof(typename Fixed<T>::acc_t);
-  if (g.shape_order == 1) allow_lds((const void*)k_deposit_tiled<T, 1>, lds);
-  else allow_lds((const void*)k_deposit_tiled<T, 3>, lds);
-  if (g.shape_order == 1)
-    hipLaunchKernelGGL((k_deposit_tiled<T, 1>), dim3(t.ntiles + 1), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm,
-                       starts, out, stage, qdv, wj, hx, hy, hz, bad, next_counts);
-  else
-    hipLaunchKernelGGL((k_deposit_tiled<T, 3>), dim3(t.ntiles + 1), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm,
-                       starts, out, stage, qdv, wj, hx, hy, hz, bad, next_counts);
+  if (g.shape_order == 1) {
+    if (with_j) launch_deposit<T, 1, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, out, s);
+    else launch_deposit<T, 1, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, out, s);
+  } else {
+    if (with_j) launch_deposit<T, 3, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, out, s);
+    else launch_deposit<T, 3, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, out, s);
+  }
 }
 
 template <typename T>
@@ -778,6 +1042,15 @@ void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, con
   out.p[0] = rho;
   for (int d = 0; d < 3; ++d) out.p[1 + d] = J ? J[d] : nullptr;
   const int ncomp = with_j ? 4 : 1;
+  if (g.nx % kTile == 0 && g.ny % kTile == 0 && g.nz % kTile == 0) {
+    const unsigned bz = (unsigned)std::min(256, (g.nz + 63) / 64 * 64);
+    const dim3 grid((unsigned)((g.nz + bz - 1) / bz), (unsigned)g.ny, (unsigned)g.nx);
+    if (g.shape_order == 1)
+      hipLaunchKernelGGL((k_deposit_reduce_whole<T, 1>), grid, dim3(bz), 0, s, g, t, starts, stage, out, ncomp);
+    else
+      hipLaunchKernelGGL((k_deposit_reduce_whole<T, 3>), grid, dim3(bz), 0, s, g, t, starts, stage, out, ncomp);
+    return;
+  }
   const long long N = (long long)g.nx * g.ny * g.nz;
   const unsigned nr = (unsigned)std::min<long long>((N + 255) / 256, 65536);
   if (g.shape_order == 1)
@@ -789,12 +1062,12 @@ void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, con
 #define PIC_INST(T)                                                                                              \
   template void permute_species<T>(const SpeciesView<T>&, const SpeciesView<T>&, const int*, hipStream_t);       \
   template void deposit_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*, const int*, \
-                                 bool, T*, int*, int*, T*, T* const*, hipStream_t);                              \
+                                 bool, T*, int*, int*, int*, T*, T* const*, hipStream_t);                        \
   template void deposit_reduce<T>(const GridGeom&, const TileGeom&, const int*, const T*, bool, T*, T* const*,   \
                                   hipStream_t);                                                                  \
   template void gather_push_tiled<T>(const GridGeom&, const TileGeom&, const T* const*, const T* const*,         \
                                      const SpeciesView<T>&, const SpeciesView<T>&, const int*, const int*, bool,  \
-                                     int*, hipStream_t);
+                                     int*, const int*, hipStream_t);
 PIC_INST(float)
 PIC_INST(double)
 #undef PIC_INST

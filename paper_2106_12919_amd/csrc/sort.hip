@@ -1,6 +1,6 @@
 // Counting sort of particles by grid tile (support for the tiled deposition).
 //
-// Tiles are ts^3 blocks of cells (partial at the upper end of an axis); particles
+// Tiles are kTile^3 blocks of cells (partial at the upper end of an axis); particles
 // with an out-of-range cell index go to one extra bucket after the last tile so
 // the sorted order has no holes (they are counted and never deposited).  Three
 // launches: count per tile, exclusive scan of the counts, rank (each particle's
@@ -14,13 +14,15 @@ namespace pic {
 
 namespace {
 
+__device__ inline uint32_t fdiv(uint32_t n, const FastDiv& f) { return (__umulhi(n, f.m) + n) >> f.s; }
+
 __device__ inline int tile_key(int c, const GridGeom& g, const TileGeom& t) {
   if (c < 0 || c >= g.nx * g.ny * g.nz) return t.ntiles;
-  const int k = c % g.nz;
-  const int r = c / g.nz;
-  const int j = r % g.ny;
-  const int i = r / g.ny;
-  return ((i / t.ts) * t.nty + j / t.ts) * t.ntz + k / t.ts;
+  const int r = (int)fdiv((uint32_t)c, g.nz_div);
+  const int k = c - r * g.nz;
+  const int i = (int)fdiv((uint32_t)r, g.ny_div);
+  const int j = r - i * g.ny;
+  return ((i / kTile) * t.nty + j / kTile) * t.ntz + k / kTile;
 }
 
 // Adds one per valid lane to counters[key]; returns each lane's previous-value
@@ -92,12 +94,23 @@ __global__ void __launch_bounds__(256) k_invert(const int* __restrict__ dst, int
 
 }  // namespace
 
-TileGeom make_tiles(const GridGeom& g, int ts) {
+FastDiv make_fastdiv(uint32_t d) {
+  FastDiv f{d, 0u, 0u};
+  while ((1ull << f.s) < d) ++f.s;
+  f.m = (uint32_t)((((1ull << 32) * ((1ull << f.s) - d)) / d) + 1);
+  return f;
+}
+
+GridGeom make_geom(int nx, int ny, int nz, double dx, double dy, double dz, double dt, int shape_order) {
+  GridGeom g{nx, ny, nz, dx, dy, dz, dt, shape_order, make_fastdiv((uint32_t)ny), make_fastdiv((uint32_t)nz)};
+  return g;
+}
+
+TileGeom make_tiles(const GridGeom& g) {
   TileGeom t{};
-  t.ts = ts;
-  t.ntx = (g.nx + ts - 1) / ts;
-  t.nty = (g.ny + ts - 1) / ts;
-  t.ntz = (g.nz + ts - 1) / ts;
+  t.ntx = (g.nx + kTile - 1) / kTile;
+  t.nty = (g.ny + kTile - 1) / kTile;
+  t.ntz = (g.nz + kTile - 1) / kTile;
   t.ntiles = t.ntx * t.nty * t.ntz;
   return t;
 }
