@@ -132,6 +132,7 @@ struct Engine : EngineBase {
   int* t_counts = nullptr;  // ntiles + 1
   int* t_starts = nullptr;  // ntiles + 2
   int* t_cursor = nullptr;  // ntiles + 1
+  int* work = nullptr;      // tile counter of the persistent deposition
   T* stage = nullptr;       // per-tile deposition boxes, ntiles * 4 * deposit_box^3
   std::vector<SpeciesScratch<T>> sps;
   cplx<T>* Eh[3] = {nullptr, nullptr, nullptr};
@@ -264,6 +265,7 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
   if ((err = e.alloc(&e.t_counts, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_starts, (size_t)e.tiles.ntiles + 2)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_cursor, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;
+  if ((err = e.alloc(&e.work, 1)) != hipSuccess) return err;
   const size_t B = (size_t)deposit_box(p.shape_order);
   if ((err = e.alloc(&e.stage, (size_t)e.tiles.ntiles * 4 * B * B * B)) != hipSuccess) return err;
   return hipSuccess;
@@ -411,7 +413,7 @@ pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, 
     tile_sort(g, e.tiles, v.cell, v.n, e.t_counts, e.t_starts, e.t_cursor, x.dst, c->d_bad, c->stream);
     invert_perm(x.dst, x.perm, v.n, c->stream);
     const bool mobile = std::isfinite(sp[s].m);
-    deposit_tiled<T>(g, e.tiles, v, x.perm, e.t_starts, with_j && mobile, e.stage, c->d_bad, nullptr, nullptr,
+    deposit_tiled<T>(g, e.tiles, v, x.perm, e.t_starts, with_j && mobile, e.stage, c->d_bad, nullptr, nullptr, e.work,
                      static_cast<T*>(f->rho_new), J, c->stream);
     deposit_reduce<T>(g, e.tiles, e.t_starts, e.stage, with_j && mobile, static_cast<T*>(f->rho_new), J, c->stream);
   }
@@ -608,7 +610,7 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
         StageScope sc(c, ST_DEPOSIT);
         int* nextc = mobile ? x.counts[first ? 1 : L] : nullptr;
         deposit_tiled<T>(g, e.tiles, dep, nullptr, dep_starts, mobile, e.stage, c->d_bad, nextc,
-                         mobile ? x.nbr : nullptr, static_cast<T*>(f->rho_new), Jn, c->stream);
+                         mobile ? x.nbr : nullptr, e.work, static_cast<T*>(f->rho_new), Jn, c->stream);
       }
       {
         StageScope sc(c, ST_REDUCE);

@@ -116,10 +116,11 @@ void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const 
 // (the grouping of the next step), into next_counts[ntiles + 1] (invalid cells last),
 // and, when nbr_counts != nullptr, per tile t of this grouping and neighbour nb of t
 // (0..26, the tile offsets in {-1,0,1}^3 in x-major order) into nbr_counts[27 t + nb].
+// ``work`` is one int of device scratch (the tile counter of the persistent launch).
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
-                   bool with_j, T* stage, int* bad, int* next_counts, int* nbr_counts, T* rho, T* const J[3],
-                   hipStream_t s);
+                   bool with_j, T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, T* rho,
+                   T* const J[3], hipStream_t s);
 template <typename T>
 void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, const T* stage, bool with_j, T* rho,
                     T* const J[3], hipStream_t s);

@@ -17,7 +17,7 @@
 #define PIC_GATHER_BLOCK 512
 #endif
 #ifndef PIC_DEPOSIT_BLOCK
-#define PIC_DEPOSIT_BLOCK 512
+#define PIC_DEPOSIT_BLOCK 256
 #endif
 
 namespace pic {
@@ -147,6 +147,50 @@ struct Box {
   __device__ static inline int at(int lx, int ly, int lz) { return (lx * B + ly) * B + lz; }
 };
 
+// One particle as stored: cell, offsets, momentum (when WJ) and weight.  Loaded in one
+// go, so that the loads of several particles are in flight together.
+template <typename T>
+struct Raw {
+  int cell;
+  T o[3], u[3], w;
+};
+
+// Stand-in weight array for species without per-particle weights: the weight load
+// is then unconditional (a branch around it would make the compiler wait for every
+// load in flight) and its value is replaced by w_const.
+__device__ float g_no_weight_f[1];
+__device__ double g_no_weight_d[1];
+template <typename T>
+__device__ inline const T* no_weight();
+template <>
+__device__ inline const float* no_weight<float>() { return g_no_weight_f; }
+template <>
+__device__ inline const double* no_weight<double>() { return g_no_weight_d; }
+
+template <typename T, bool WJ>
+__device__ inline void load_raw(const SpeciesView<T>& sp, int p, Raw<T>& r) {
+  r.cell = sp.cell[p];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) r.o[d] = sp.off[d][p];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) r.u[d] = WJ ? sp.u[d][p] : (T)0;
+  const bool has_w = sp.w != nullptr;
+  const T wv = (has_w ? sp.w : no_weight<T>())[has_w ? p : 0];
+  r.w = has_w ? wv : (T)sp.w_const;
+}
+
+// Slots -> particle indices through an optional permutation, all lookups in flight at once.
+template <int U>
+__device__ inline void through_perm(const int* perm, int (&q)[U]) {
+  if (perm) {
+    int t[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) t[u] = perm[q[u]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) q[u] = t[u];
+  }
+}
+
 // ---------------------------------------------------------------- gather + push
 
 // Nodal field box in LDS, node-major with the six components adjacent (8 slots for
@@ -173,18 +217,38 @@ struct FieldSlots<double> {
   }
 };
 
-// Stages the six nodal components over the box of tile (t0x, t0y, t0z).
+// Periodic index of x in [-n, 3n).
+__device__ inline int wrap3(int x, int n) {
+  x += (x < 0) ? n : 0;
+  x -= (x >= n) ? n : 0;
+  return (x >= n) ? x - n : x;
+}
+
+// Stages the six nodal components over the box of tile (t0x, t0y, t0z).  Each thread
+// issues the loads of all its nodes before storing any, so they are in flight together.
 template <typename T, int ORDER>
 __device__ inline void load_field_box(T* box, const Batch<const T*>& F, const GridGeom& g, int t0x, int t0y, int t0z) {
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
   constexpr int FS = FieldSlots<T>::FS;
+  constexpr int PER = (X::B3 + PIC_GATHER_BLOCK - 1) / PIC_GATHER_BLOCK;
   const int ox0 = t0x - 1 + S::BASE, oy0 = t0y - 1 + S::BASE, oz0 = t0z - 1 + S::BASE;
-  for (int e = threadIdx.x; e < X::B3; e += blockDim.x) {
-    const int lx = e / X::B2, ly = (e / X::B) % X::B, lz = e % X::B;
-    const size_t gi = ((size_t)modi(ox0 + lx, g.nx) * g.ny + modi(oy0 + ly, g.ny)) * g.nz + modi(oz0 + lz, g.nz);
+  T v[PER][6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) box[e * FS + c] = F.p[c][gi];
+  for (int u = 0; u < PER; ++u) {
+    const int e = min((int)threadIdx.x + u * PIC_GATHER_BLOCK, X::B3 - 1);
+    const int lx = e / X::B2, ly = (e / X::B) % X::B, lz = e % X::B;
+    const size_t gi = ((size_t)wrap3(ox0 + lx, g.nx) * g.ny + wrap3(oy0 + ly, g.ny)) * g.nz + wrap3(oz0 + lz, g.nz);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[u][c] = F.p[c][gi];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = (int)threadIdx.x + u * PIC_GATHER_BLOCK;
+    if (e < X::B3) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) box[e * FS + c] = v[u][c];
+    }
   }
 }
 
@@ -367,10 +431,15 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
     cnt[threadIdx.x] = 0;
   }
   __syncthreads();
-  // pass 2: gather, push and write each particle to its slot
+  // pass 2: gather, push and write each particle to its slot, the next particle's
+  // loads in flight meanwhile
+  Raw<T> nxt;
+  if (beg + (int)threadIdx.x < end) load_raw<T, true>(in, beg + threadIdx.x, nxt);
   for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
+    const Raw<T> r = nxt;
+    load_raw<T, true>(in, min(qq + (int)blockDim.x, end - 1), nxt);
     int i, j, k;
-    (void)decode_cell(in.cell[qq], g, nullptr, i, j, k);
+    (void)decode_cell(r.cell, g, nullptr, i, j, k);
     const int nb = neighbour_of_cell(i, j, k, tx, ty, tz, tg);
     int slot;
     const unsigned long long own = __ballot(nb == 13);
@@ -384,8 +453,8 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
     } else {
       slot = nb >= 0 ? base[nb] + atomicAdd(&cnt[nb], 1) : atomicAdd(&cursor[tile_of(i, j, k, tg)], 1);
     }
-    T ox = in.off[0][qq], oy = in.off[1][qq], oz = in.off[2][qq];
-    T ux = in.u[0][qq], uy = in.u[1][qq], uz = in.u[2][qq];
+    T ox = r.o[0], oy = r.o[1], oz = r.o[2];
+    T ux = r.u[0], uy = r.u[1], uz = r.u[2];
     const int lx = box_index(i, t0x, g.nx), ly = box_index(j, t0y, g.ny), lz = box_index(k, t0z, g.nz);
     gather_push_one<T, ORDER>(box, F, g, lx, ly, lz, i, j, k, ox, oy, oz, ux, uy, uz, qdt2m, dtx, dty, dtz);
     out.u[0][slot] = ux;
@@ -395,7 +464,7 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
     out.off[1][slot] = oy;
     out.off[2][slot] = oz;
     out.cell[slot] = (i * g.ny + j) * g.nz + k;
-    if (in.w) out.w[slot] = in.w[qq];
+    if (in.w) out.w[slot] = r.w;
   }
 }
 
@@ -534,25 +603,10 @@ template <typename T>
 struct DepositOrder {
   static constexpr int KG = sizeof(typename Fixed<T>::acc_t) == 4 ? 32 : 16;
   static constexpr int CH = sizeof(typename Fixed<T>::acc_t) == 4 ? 1024 : 512;  // particles per chunk
+  static constexpr int RMAX = CH / 4;  // deal rows; a chunk with more keeps its stored order
+  static constexpr int U = CH / PIC_DEPOSIT_BLOCK;  // particles per thread and chunk, loaded together
+  static_assert(CH % PIC_DEPOSIT_BLOCK == 0, "a chunk is a whole number of particles per thread");
 };
-
-// One particle as stored: cell, offsets, momentum (J only) and weight.  Loaded in one
-// go, so that the loads of several particles are in flight together.
-template <typename T>
-struct Raw {
-  int cell;
-  T o[3], u[3], w;
-};
-
-template <typename T, bool WJ>
-__device__ inline void load_raw(const SpeciesView<T>& sp, int p, Raw<T>& r) {
-  r.cell = sp.cell[p];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) r.o[d] = sp.off[d][p];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) r.u[d] = WJ ? sp.u[d][p] : (T)0;
-  r.w = sp.w ? sp.w[p] : (T)sp.w_const;
-}
 
 // What the deposition needs of one particle: its cell and offsets at x, the velocity,
 // the cell and offsets at x - dt v / 2, and the box indices of the first support
@@ -643,32 +697,46 @@ __device__ inline void block_exclusive_scan(int* a, int n, int* wtot) {
 // with global atomics.)  With next_counts, the tiles of the particles' cells (the
 // next grouping) are counted: per tile in next_counts, per neighbour of this tile in
 // nbr_counts[27 * tile ...] (what the next gather of this tile's particles reserves).
+// LDS of a deposition workgroup besides the box.
+template <typename T>
+struct DepositLds {
+  static constexpr int kWaves = PIC_DEPOSIT_BLOCK / 64;
+  using O = DepositOrder<T>;
+  T red[4 * kWaves];
+  T redm[4 * kWaves];
+  int shs[4];
+  int cnt[27];
+  int wtot[kWaves];
+  int next_tile;
+  __align__(16) int hist[O::KG];
+  unsigned short kr[O::CH];
+  unsigned short order[O::CH];
+  unsigned rowmask[O::RMAX];
+  int rowstart[O::RMAX];
+};
+
+// Deposition of one tile by the whole workgroup (see k_deposit_tiled).
 template <typename T, int ORDER, bool WJ>
-__global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp,
-                                                                     const int* __restrict__ perm,
-                                                                     const int* __restrict__ starts, Batch<T*> out,
-                                                                     T* __restrict__ stage, T qdv, T hdtx, T hdty,
-                                                                     T hdtz, int* bad, int* next_counts,
-                                                                     int* nbr_counts) {
+__device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom& tg, const SpeciesView<T>& sp,
+                                    const int* __restrict__ perm, const int* __restrict__ starts,
+                                    const Batch<T*>& out, T* __restrict__ stage, T qdv, T hdtx, T hdty, T hdtz,
+                                    int* bad, int* next_counts, int* nbr_counts,
+                                    typename Fixed<T>::acc_t* box, DepositLds<T>& L) {
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
   using O = DepositOrder<T>;
-  using acc_t = typename Fixed<T>::acc_t;
   constexpr int ncomp = WJ ? 4 : 1;
-  extern __shared__ __align__(16) unsigned char smem[];
-  acc_t* box = reinterpret_cast<acc_t*>(smem);
-  constexpr int kWaves = PIC_DEPOSIT_BLOCK / 64;
-  __shared__ T red[4 * kWaves];
-  __shared__ T redm[4 * kWaves];
-  __shared__ int shs[4];
-  __shared__ int cnt[27];
-  __shared__ int wtot[kWaves];
-  __shared__ __align__(16) int hist[O::KG];
-  __shared__ unsigned short kr[O::CH];
-  __shared__ unsigned short order[O::CH];
-  __shared__ unsigned rowmask[O::CH];
-  __shared__ int rowstart[O::CH];
-  const int tile = blockIdx.x;
+  constexpr int kWaves = DepositLds<T>::kWaves;
+  T* red = L.red;
+  T* redm = L.redm;
+  int* shs = L.shs;
+  int* cnt = L.cnt;
+  int* wtot = L.wtot;
+  int* hist = L.hist;
+  unsigned short* kr = L.kr;
+  unsigned short* order = L.order;
+  unsigned* rowmask = L.rowmask;
+  int* rowstart = L.rowstart;
   const int beg = starts[tile], end = starts[tile + 1];
   if (beg == end) return;
   if (tile == tg.ntiles) {  // invalid cells: never deposited, kept in the last bucket
@@ -715,10 +783,17 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
     }
   };
   if (!single) {
-    for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
-      Raw<T> r;
-      load_raw<T, WJ>(sp, perm ? perm[qq] : qq, r);
-      bound_add<T, WJ>(r, sw, mw);
+    for (int q0 = beg + threadIdx.x; q0 < end; q0 += O::U * PIC_DEPOSIT_BLOCK) {
+      int qi[O::U];
+#pragma unroll
+      for (int u = 0; u < O::U; ++u) qi[u] = min(q0 + u * PIC_DEPOSIT_BLOCK, end - 1);
+      through_perm(perm, qi);
+      Raw<T> r[O::U];
+#pragma unroll
+      for (int u = 0; u < O::U; ++u) load_raw<T, WJ>(sp, qi[u], r[u]);
+#pragma unroll
+      for (int u = 0; u < O::U; ++u)
+        if (q0 + u * PIC_DEPOSIT_BLOCK < end) bound_add<T, WJ>(r[u], sw, mw);
     }
     publish_bounds();
     __syncthreads();
@@ -731,17 +806,19 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
     if (threadIdx.x < O::KG) hist[threadIdx.x] = 0;
     __syncthreads();
     // pass 1: residue of each particle's first J (rho-only: rho) support node and its
-    // rank among the chunk's particles of that residue; two particles per thread in flight
-    for (int e0 = threadIdx.x; e0 < nc; e0 += 2 * blockDim.x) {
-      Raw<T> r[2];
+    // rank among the chunk's particles of that residue; all of a thread's particles in flight
+    {
+      const int e0 = threadIdx.x;
+      int qi[O::U];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int e = min(e0 + u * (int)blockDim.x, nc - 1);
-        load_raw<T, WJ>(sp, perm ? perm[cb + e] : cb + e, r[u]);
-      }
+      for (int u = 0; u < O::U; ++u) qi[u] = cb + min(e0 + u * PIC_DEPOSIT_BLOCK, nc - 1);
+      through_perm(perm, qi);
+      Raw<T> r[O::U];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const int e = e0 + u * (int)blockDim.x;
+      for (int u = 0; u < O::U; ++u) load_raw<T, WJ>(sp, qi[u], r[u]);
+#pragma unroll
+      for (int u = 0; u < O::U; ++u) {
+        const int e = e0 + u * PIC_DEPOSIT_BLOCK;
         if (e < nc) {
           DepositPoint<T> d;
           int key = 0;
@@ -765,6 +842,7 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
       const int4 h4 = *reinterpret_cast<const int4*>(&hist[k]);
       R = max(R, max(max(h4.x, h4.y), max(h4.z, h4.w)));
     }
+    if (R > O::RMAX) R = 0;  // too uneven to deal: stored order
     for (int r = threadIdx.x; r < R; r += blockDim.x) {
       unsigned m = 0;
 #pragma unroll 4
@@ -775,9 +853,13 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
     __syncthreads();
     block_exclusive_scan(rowstart, R, wtot);
     for (int e = threadIdx.x; e < nc; e += blockDim.x) {
-      const int v = kr[e];
-      const int r = v / O::KG, key = v % O::KG;
-      order[rowstart[r] + __popc(rowmask[r] & ((1u << key) - 1u))] = (unsigned short)e;
+      if (R == 0) {
+        order[e] = (unsigned short)e;
+      } else {
+        const int v = kr[e];
+        const int r = v / O::KG, key = v % O::KG;
+        order[rowstart[r] + __popc(rowmask[r] & ((1u << key) - 1u))] = (unsigned short)e;
+      }
     }
     __syncthreads();
     int sh[4];
@@ -786,14 +868,16 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
     // pass 2: deposit in the dealt order, the next particle's loads in flight meanwhile
     Raw<T> nxt;
     if ((int)threadIdx.x < nc) {
-      const int q = cb + order[threadIdx.x];
-      load_raw<T, WJ>(sp, perm ? perm[q] : q, nxt);
+      int q[1] = {cb + order[threadIdx.x]};
+      through_perm(perm, q);
+      load_raw<T, WJ>(sp, q[0], nxt);
     }
     for (int pos = threadIdx.x; pos < nc; pos += blockDim.x) {
       const Raw<T> r = nxt;
       {
-        const int q = cb + order[min(pos + (int)blockDim.x, nc - 1)];
-        load_raw<T, WJ>(sp, perm ? perm[q] : q, nxt);
+        int q[1] = {cb + order[min(pos + (int)blockDim.x, nc - 1)]};
+        through_perm(perm, q);
+        load_raw<T, WJ>(sp, q[0], nxt);
       }
       DepositPoint<T> d;
       if (!locate<T, ORDER, WJ>(r, g, t0x, t0y, t0z, hdtx, hdty, hdtz, bad, d)) continue;
@@ -840,6 +924,36 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK) k_deposit_tiled(GridGeom g,
   for (int k = threadIdx.x; k < ncomp * X::B3; k += blockDim.x) dstage[k] = ldexp((T)box[k], -shs[k / X::B3]);
 }
 
+// Waves per SIMD the register budget allows: FP32 cubic 3 (its LDS box admits three
+// workgroups per CU), FP32 linear 4, FP64 unconstrained.
+// Cubic shapes: persistent workgroups, each taking tiles 0..ntiles (the last one the
+// invalid-cell bucket) from the work counter until none is left, so that one tile's
+// loads overlap other tiles' LDS work.  Linear shapes: one workgroup per tile (their
+// smaller box leaves more workgroups resident).
+template <typename T, int ORDER, bool WJ>
+__global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK, sizeof(T) == 4 ? (ORDER == 3 ? 3 : 4) : 1)
+    k_deposit_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp, const int* __restrict__ perm,
+                    const int* __restrict__ starts, Batch<T*> out, T* __restrict__ stage, T qdv, T hdtx, T hdty,
+                    T hdtz, int* bad, int* next_counts, int* nbr_counts, int* work) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ DepositLds<T> L;
+  auto* box = reinterpret_cast<typename Fixed<T>::acc_t*>(smem);
+  if (ORDER == 3) {
+    for (;;) {
+      if (threadIdx.x == 0) L.next_tile = atomicAdd(work, 1);
+      __syncthreads();
+      const int tile = L.next_tile;
+      __syncthreads();
+      if (tile > tg.ntiles) break;
+      deposit_tile<T, ORDER, WJ>(tile, g, tg, sp, perm, starts, out, stage, qdv, hdtx, hdty, hdtz, bad, next_counts,
+                                 nbr_counts, box, L);
+    }
+  } else {
+    deposit_tile<T, ORDER, WJ>(blockIdx.x, g, tg, sp, perm, starts, out, stage, qdv, hdtx, hdty, hdtz, bad,
+                               next_counts, nbr_counts, box, L);
+  }
+}
+
 // Per axis, the (tile, box index) pairs whose boxes hold grid node x on grids that are
 // whole multiples of the tile: its own tile t at l0 = x mod kTile + 1 - BASE, and
 // t - 1 at l0 + kTile or t + 1 at l0 - kTile when that index lies inside the box.
@@ -866,9 +980,9 @@ __device__ inline int axis_candidates(int x, int nt, int* t, int* l) {
 // Sums, for every grid node, the staging boxes of the non-empty tiles that cover it
 // and adds the sums to the nodal arrays; each node is owned by one thread, so no
 // atomics.  Grids that are whole multiples of the tile; grid (z blocks, ny, nx).
-template <typename T, int ORDER>
+template <typename T, int ORDER, int NCOMP>
 __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGeom tg, const int* __restrict__ starts,
-                                                              const T* __restrict__ stage, Batch<T*> out, int ncomp) {
+                                                              const T* __restrict__ stage, Batch<T*> out) {
   using X = Box<Shape<T, ORDER>::NW>;
   const int z = blockIdx.x * blockDim.x + threadIdx.x;
   if (z >= g.nz) return;
@@ -877,22 +991,37 @@ __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGe
   const int nxc = axis_candidates<ORDER>(x, tg.ntx, tx, lx);
   const int nyc = axis_candidates<ORDER>(y, tg.nty, ty, ly);
   const int nzc = axis_candidates<ORDER>(z, tg.ntz, tz, lz);
-  T acc[4] = {0, 0, 0, 0};
-  for (int a = 0; a < nxc; ++a)
-    for (int b = 0; b < nyc; ++b)
-      for (int c = 0; c < nzc; ++c) {
-        const int tile = (tx[a] * tg.nty + ty[b]) * tg.ntz + tz[c];
-        if (starts[tile] == starts[tile + 1]) continue;
-        const T* sb = stage + (size_t)tile * ncomp * X::B3 + X::at(lx[a], ly[b], lz[c]);
-        if (ncomp == 4) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) acc[q] += sb[q * X::B3];
-        } else {
-          acc[0] += sb[0];
-        }
-      }
+  // the eight combinations are unrolled: first every tile's occupancy, then the
+  // staging loads of the occupied ones, all in flight before any sum (empty tiles'
+  // staging slots hold stale data and are skipped)
   const size_t idx = ((size_t)x * g.ny + y) * g.nz + z;
-  for (int q = 0; q < ncomp; ++q) out.p[q][idx] += acc[q];
+  T acc[NCOMP];
+#pragma unroll
+  for (int q = 0; q < NCOMP; ++q) acc[q] = out.p[q][idx];
+  bool use[8];
+  const T* sb[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int a = m >> 2, b = (m >> 1) & 1, c = m & 1;
+    const bool present = a < nxc && b < nyc && c < nzc;
+    const int ia = present ? a : 0, ib = present ? b : 0, ic = present ? c : 0;
+    const int tile = (tx[ia] * tg.nty + ty[ib]) * tg.ntz + tz[ic];
+    const int s0 = starts[tile], s1 = starts[tile + 1];  // loaded whether present or not
+    use[m] = present & (s0 != s1);
+    sb[m] = stage + (size_t)tile * NCOMP * X::B3 + X::at(lx[ia], ly[ib], lz[ic]);
+  }
+  T v[8][NCOMP];
+#pragma unroll
+  for (int m = 0; m < 8; ++m)
+#pragma unroll
+    for (int q = 0; q < NCOMP; ++q) v[m][q] = use[m] ? sb[m][q * X::B3] : (T)0;
+#pragma unroll
+  for (int q = 0; q < NCOMP; ++q) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) acc[q] += v[m][q];
+  }
+#pragma unroll
+  for (int q = 0; q < NCOMP; ++q) out.p[q][idx] = acc[q];
 }
 
 // The same for any grid (partial tiles at the upper ends): candidate (tile, box index)
@@ -1006,32 +1135,53 @@ void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3]
   }
 }
 
+// Resident workgroups of ``kernel`` the device holds at once (occupancy x compute units).
+int resident_blocks(const void* kernel, int block, size_t lds) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, lds) != hipSuccess || per <= 0 || cus <= 0) {
+    (void)hipGetLastError();
+    return 1024;
+  }
+  return per * cus;
+}
+
 template <typename T, int ORDER, bool WJ>
 void launch_deposit(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
-                    T* stage, int* bad, int* next_counts, int* nbr_counts, const Batch<T*>& out, hipStream_t s) {
+                    T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, const Batch<T*>& out,
+                    hipStream_t s) {
   const T qdv = (T)(sp.q / (g.dx * g.dy * g.dz));
   const T hx = (T)(0.5 * g.dt / g.dx), hy = (T)(0.5 * g.dt / g.dy), hz = (T)(0.5 * g.dt / g.dz);
   constexpr int B = Box<Shape<T, ORDER>::NW>::B;
   const size_t lds = (size_t)(WJ ? 4 : 1) * B * B * B * sizeof(typename Fixed<T>::acc_t);
-  allow_lds((const void*)k_deposit_tiled<T, ORDER, WJ>, lds);
-  hipLaunchKernelGGL((k_deposit_tiled<T, ORDER, WJ>), dim3(t.ntiles + 1), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp,
-                     perm, starts, out, stage, qdv, hx, hy, hz, bad, next_counts, nbr_counts);
+  const void* k = (const void*)k_deposit_tiled<T, ORDER, WJ>;
+  allow_lds(k, lds);
+  int nb = t.ntiles + 1;
+  if (ORDER == 3) {  // persistent launch (see k_deposit_tiled)
+    static int resident = 0;  // per instantiation; the device's occupancy does not change
+    if (resident == 0) resident = resident_blocks(k, PIC_DEPOSIT_BLOCK, lds);
+    nb = std::min(nb, resident);
+    (void)hipMemsetAsync(work, 0, sizeof(int), s);
+  }
+  hipLaunchKernelGGL((k_deposit_tiled<T, ORDER, WJ>), dim3(nb), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm,
+                     starts, out, stage, qdv, hx, hy, hz, bad, next_counts, nbr_counts, work);
 }
 
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
-                   bool with_j, T* stage, int* bad, int* next_counts, int* nbr_counts, T* rho, T* const J[3],
-                   hipStream_t s) {
+                   bool with_j, T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, T* rho,
+                   T* const J[3], hipStream_t s) {
   if (sp.n <= 0) return;
   Batch<T*> out{};
   out.p[0] = rho;
   for (int d = 0; d < 3; ++d) out.p[1 + d] = J ? J[d] : nullptr;
   if (g.shape_order == 1) {
-    if (with_j) launch_deposit<T, 1, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, out, s);
-    else launch_deposit<T, 1, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, out, s);
+    if (with_j) launch_deposit<T, 1, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, out, s);
+    else launch_deposit<T, 1, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, out, s);
   } else {
-    if (with_j) launch_deposit<T, 3, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, out, s);
-    else launch_deposit<T, 3, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, out, s);
+    if (with_j) launch_deposit<T, 3, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, out, s);
+    else launch_deposit<T, 3, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, out, s);
   }
 }
 
@@ -1045,10 +1195,13 @@ void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, con
   if (g.nx % kTile == 0 && g.ny % kTile == 0 && g.nz % kTile == 0) {
     const unsigned bz = (unsigned)std::min(256, (g.nz + 63) / 64 * 64);
     const dim3 grid((unsigned)((g.nz + bz - 1) / bz), (unsigned)g.ny, (unsigned)g.nx);
-    if (g.shape_order == 1)
-      hipLaunchKernelGGL((k_deposit_reduce_whole<T, 1>), grid, dim3(bz), 0, s, g, t, starts, stage, out, ncomp);
-    else
-      hipLaunchKernelGGL((k_deposit_reduce_whole<T, 3>), grid, dim3(bz), 0, s, g, t, starts, stage, out, ncomp);
+    if (g.shape_order == 1) {
+      if (with_j) hipLaunchKernelGGL((k_deposit_reduce_whole<T, 1, 4>), grid, dim3(bz), 0, s, g, t, starts, stage, out);
+      else hipLaunchKernelGGL((k_deposit_reduce_whole<T, 1, 1>), grid, dim3(bz), 0, s, g, t, starts, stage, out);
+    } else {
+      if (with_j) hipLaunchKernelGGL((k_deposit_reduce_whole<T, 3, 4>), grid, dim3(bz), 0, s, g, t, starts, stage, out);
+      else hipLaunchKernelGGL((k_deposit_reduce_whole<T, 3, 1>), grid, dim3(bz), 0, s, g, t, starts, stage, out);
+    }
     return;
   }
   const long long N = (long long)g.nx * g.ny * g.nz;
@@ -1062,7 +1215,7 @@ void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, con
 #define PIC_INST(T)                                                                                              \
   template void permute_species<T>(const SpeciesView<T>&, const SpeciesView<T>&, const int*, hipStream_t);       \
   template void deposit_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*, const int*, \
-                                 bool, T*, int*, int*, int*, T*, T* const*, hipStream_t);                        \
+                                 bool, T*, int*, int*, int*, int*, T*, T* const*, hipStream_t);                  \
   template void deposit_reduce<T>(const GridGeom&, const TileGeom&, const int*, const T*, bool, T*, T* const*,   \
                                   hipStream_t);                                                                  \
   template void gather_push_tiled<T>(const GridGeom&, const TileGeom&, const T* const*, const T* const*,         \
