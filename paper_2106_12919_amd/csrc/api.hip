@@ -121,7 +121,8 @@ struct SpeciesScratch {
   int* counts[2] = {nullptr, nullptr};
   int* starts[2] = {nullptr, nullptr};
   int* cursor = nullptr;
-  int* nbr = nullptr;  // [27 * ntiles]: per tile, particles per neighbour tile (from the deposition)
+  int* nbr = nullptr;       // [27 * ntiles]: per tile, particles per neighbour tile (from the deposition)
+  int* nbr_base = nullptr;  // [27 * ntiles]: per tile, first slot of its run in each neighbour tile
 };
 
 template <typename T>
@@ -169,8 +170,8 @@ struct Engine : EngineBase {
     if (sps.size() <= s) sps.resize(s + 1);
     SpeciesScratch<T>& x = sps[s];
     if (x.cap >= n) return hipSuccess;
-    void* old[16] = {x.cell, x.off[0], x.off[1], x.off[2], x.u[0], x.u[1], x.u[2], x.w, x.dst, x.perm,
-                     x.counts[0], x.counts[1], x.starts[0], x.starts[1], x.cursor, x.nbr};
+    void* old[17] = {x.cell, x.off[0], x.off[1], x.off[2], x.u[0], x.u[1], x.u[2], x.w, x.dst, x.perm,
+                     x.counts[0], x.counts[1], x.starts[0], x.starts[1], x.cursor, x.nbr, x.nbr_base};
     for (void* q : old)
       if (q) (void)release_one(q);
     x = SpeciesScratch<T>{};
@@ -183,6 +184,7 @@ struct Engine : EngineBase {
     }
     if ((e = alloc(&x.cursor, nt + 1)) != hipSuccess) return e;
     if ((e = alloc(&x.nbr, 27 * nt)) != hipSuccess) return e;
+    if ((e = alloc(&x.nbr_base, 27 * nt)) != hipSuccess) return e;
     if ((e = alloc(&x.cell, m)) != hipSuccess) return e;
     for (int d = 0; d < 3; ++d) {
       if ((e = alloc(&x.off[d], m)) != hipSuccess) return e;
@@ -590,6 +592,7 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
           invert_perm(x.dst, x.perm, cur.n, c->stream);
         } else if (mobile) {
           scan_counts(e.tiles, x.counts[1 - L], x.starts[1 - L], x.cursor, c->stream);
+          neighbour_bases(e.tiles, x.starts[L], x.nbr, x.starts[1 - L], x.nbr_base, x.cursor, c->stream);
         }
         if (mobile) (void)hipMemsetAsync(x.counts[first ? 1 : L], 0, sizeof(int) * (nt + 1), c->stream);
       }
@@ -602,7 +605,7 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
         else if (first)
           permute_species<T>(cur, alt, x.dst, c->stream);
         else if (mobile)
-          gather_push_tiled<T>(g, e.tiles, Enod, Bnod, cur, alt, nullptr, x.starts[L], true, x.cursor, x.nbr,
+          gather_push_tiled<T>(g, e.tiles, Enod, Bnod, cur, alt, nullptr, x.starts[L], true, x.cursor, x.nbr_base,
                                c->stream);
       }
       const SpeciesView<T> dep = (first || mobile) ? alt : cur;  // immobile species stay put after the first step

@@ -91,6 +91,12 @@ void tile_sort(const GridGeom& g, const TileGeom& t, const int32_t* cell, int64_
 void invert_perm(const int* dst, int* perm, int64_t n, hipStream_t s);
 // Exclusive scan of counts[ntiles + 1] into starts[ntiles + 2] and cursor[ntiles + 1].
 void scan_counts(const TileGeom& t, const int* counts, int* starts, int* cursor, hipStream_t s);
+// Slot runs of the regrouping: from the per-(source tile, neighbour) counts a deposition
+// published (nbr_counts, source grouping old_starts) and the new grouping's starts,
+// bases[27 S + nb] = first slot of source S's particles bound for neighbour nb, and
+// cursor[D] = first slot of tile D after all its runs (for particles that moved further).
+void neighbour_bases(const TileGeom& t, const int* old_starts, const int* nbr_counts, const int* new_starts,
+                     int* bases, int* cursor, hipStream_t s);
 
 // Tile-ordered gather + push.  Either through a permutation (home_cursor == nullptr):
 // slot q of tile t (q in [starts[t], starts[t+1]), tiles of the current cells) reads
@@ -98,12 +104,13 @@ void scan_counts(const TileGeom& t, const int* counts, int* starts, int* cursor,
 // perm[q] (in place when out == in); or, in pic_step's steady state, ``in`` grouped by
 // home tile (starts = home ranges) is written to ``out`` grouped by the tile of each
 // particle's current cell, slots reserved per block from home_cursor (the new starts);
-// nbr_counts (optional) holds, per home tile, its particles per neighbour tile
-// [27 * ntiles] as the deposition that grouped them counted them.
+// nbr_bases (optional, from neighbour_bases) holds, per home tile, the first slot of
+// its particles bound for each neighbour tile [27 * ntiles]; without it each block
+// counts its particles and reserves the runs with atomics on home_cursor.
 template <typename T>
 void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3], const T* const B[3],
                        const SpeciesView<T>& in, const SpeciesView<T>& out, const int* perm, const int* starts,
-                       bool write_sorted, int* home_cursor, const int* nbr_counts, hipStream_t s);
+                       bool write_sorted, int* home_cursor, const int* nbr_bases, hipStream_t s);
 template <typename T>
 void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const int* dst, hipStream_t s);
 // Deposition of one species in two launches.  deposit_tiled accumulates rho (at the

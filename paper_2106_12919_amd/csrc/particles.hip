@@ -388,7 +388,7 @@ template <typename T, int ORDER>
 __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom g, TileGeom tg, Batch<const T*> F,
                                                                        SpeciesView<T> in, SpeciesView<T> out,
                                                                        const int* __restrict__ home, int* cursor,
-                                                                       const int* __restrict__ nbr_counts, T qdt2m,
+                                                                       const int* __restrict__ nbr_bases, T qdt2m,
                                                                        T dtx, T dty, T dtz) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* box = reinterpret_cast<T*>(smem);
@@ -406,31 +406,35 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
   int tx, ty, tz;
   tile_coords(tile, tg, tx, ty, tz);
   const int t0x = tx * kTile, t0y = ty * kTile, t0z = tz * kTile;
-  if (threadIdx.x < 27) cnt[threadIdx.x] = nbr_counts ? nbr_counts[27 * tile + threadIdx.x] : 0;
+  if (threadIdx.x < 27) {
+    cnt[threadIdx.x] = 0;
+    if (nbr_bases) base[threadIdx.x] = nbr_bases[27 * tile + threadIdx.x];
+  }
   load_field_box<T, ORDER>(box, F, g, t0x, t0y, t0z);
   __syncthreads();
-  // pass 1: particles per neighbour tile of the new grouping (the home tile, the
-  // common case, is counted once per wave), unless the deposition that grouped these
-  // particles has counted them already
-  if (!nbr_counts) for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
-    int i, j, k;
-    (void)decode_cell(in.cell[qq], g, nullptr, i, j, k);
-    const int nb = neighbour_of_cell(i, j, k, tx, ty, tz, tg);
-    const unsigned long long own = __ballot(nb == 13);
-    if (nb == 13) {
-      if (__lane_id() == __ffsll(own) - 1) atomicAdd(&cnt[13], __popcll(own));
-    } else if (nb >= 0) {
-      atomicAdd(&cnt[nb], 1);
+  if (!nbr_bases) {
+    // pass 1: particles per neighbour tile of the new grouping (the home tile, the
+    // common case, is counted once per wave), then one contiguous run per neighbour
+    // tile, reserved with a single atomic each
+    for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
+      int i, j, k;
+      (void)decode_cell(in.cell[qq], g, nullptr, i, j, k);
+      const int nb = neighbour_of_cell(i, j, k, tx, ty, tz, tg);
+      const unsigned long long own = __ballot(nb == 13);
+      if (nb == 13) {
+        if (__lane_id() == __ffsll(own) - 1) atomicAdd(&cnt[13], __popcll(own));
+      } else if (nb >= 0) {
+        atomicAdd(&cnt[nb], 1);
+      }
     }
+    __syncthreads();
+    if (threadIdx.x < 27) {
+      const int n = cnt[threadIdx.x];
+      base[threadIdx.x] = n > 0 ? atomicAdd(&cursor[neighbour_key(threadIdx.x, tx, ty, tz, tg)], n) : 0;
+      cnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // one contiguous run per neighbour tile, reserved with a single atomic each
-  if (threadIdx.x < 27) {
-    const int n = cnt[threadIdx.x];
-    base[threadIdx.x] = n > 0 ? atomicAdd(&cursor[neighbour_key(threadIdx.x, tx, ty, tz, tg)], n) : 0;
-    cnt[threadIdx.x] = 0;
-  }
-  __syncthreads();
   // pass 2: gather, push and write each particle to its slot, the next particle's
   // loads in flight meanwhile
   Raw<T> nxt;
@@ -1099,7 +1103,7 @@ int deposit_box(int shape_order) { return kTile + (shape_order == 1 ? 2 : 4) + 1
 template <typename T>
 void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3], const T* const B[3],
                        const SpeciesView<T>& in, const SpeciesView<T>& out, const int* perm, const int* starts,
-                       bool write_sorted, int* home_cursor, const int* nbr_counts, hipStream_t s) {
+                       bool write_sorted, int* home_cursor, const int* nbr_bases, hipStream_t s) {
   if (in.n <= 0) return;
   Batch<const T*> F{};
   for (int d = 0; d < 3; ++d) {
@@ -1115,11 +1119,11 @@ void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3]
     if (g.shape_order == 1) {
       allow_lds((const void*)k_gather_push_home<T, 1>, lds);
       hipLaunchKernelGGL((k_gather_push_home<T, 1>), grid, block, lds, s, g, t, F, in, out, starts, home_cursor,
-                         nbr_counts, qdt2m, dtx, dty, dtz);
+                         nbr_bases, qdt2m, dtx, dty, dtz);
     } else {
       allow_lds((const void*)k_gather_push_home<T, 3>, lds);
       hipLaunchKernelGGL((k_gather_push_home<T, 3>), grid, block, lds, s, g, t, F, in, out, starts, home_cursor,
-                         nbr_counts, qdt2m, dtx, dty, dtz);
+                         nbr_bases, qdt2m, dtx, dty, dtz);
     }
   } else {
     const int ws = write_sorted ? 1 : 0;

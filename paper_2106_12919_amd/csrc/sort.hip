@@ -87,6 +87,48 @@ __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ counts, i
   if (tid == blockDim.x - 1) starts[m] = part[tid];
 }
 
+// For every destination tile D of the new grouping: the slot runs of the particles that
+// arrive from each neighbour source tile S (grouped by S in the previous step), in the
+// order of the 27 offsets, from starts[D]; bases[27 S + nb] receives the start of the run
+// of S's particles whose offset to D is nb, cursor[D] the first slot after all runs.
+// An offset that names the same S as another (grids of one or two tiles along an axis)
+// is taken once, with the index the particle kernels compute for it.
+// One 32-lane group per destination tile D; lane o < 27 takes the offset o, its source
+// tile and count, and a scan across the group places the runs.
+__global__ void __launch_bounds__(256) k_neighbour_bases(TileGeom t, const int* __restrict__ old_starts,
+                                                         const int* __restrict__ nbr_counts,
+                                                         const int* __restrict__ new_starts, int* bases, int* cursor) {
+  const int D = (blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+  const int o = threadIdx.x & 31;
+  if (D >= t.ntiles) return;  // whole 32-lane groups leave together
+  const int dz = D % t.ntz, dy = (D / t.ntz) % t.nty, dx = D / (t.ntz * t.nty);
+  const int nt[3] = {t.ntx, t.nty, t.ntz};
+  const int dc[3] = {dx, dy, dz};
+  const int off[3] = {o / 9 - 1, (o / 3) % 3 - 1, o % 3 - 1};
+  int sc[3], canon = 0;
+  for (int a = 0; a < 3; ++a) {
+    sc[a] = (dc[a] - off[a] + nt[a]) % nt[a];
+    int d = dc[a] - sc[a];  // as the particle kernels wrap it
+    if (d > 1) d -= nt[a];
+    if (d < -1) d += nt[a];
+    canon = canon * 3 + (d + 1);
+  }
+  const int S = (sc[0] * t.nty + sc[1]) * t.ntz + sc[2];
+  const bool take = o < 27 && canon == o;
+  const int Sv = take ? S : 0;
+  const int s0 = old_starts[Sv], s1 = old_starts[Sv + 1];  // an empty tile published no counts
+  const int cv = nbr_counts[27 * Sv + (take ? o : 0)];
+  const int c = (take && s0 != s1) ? cv : 0;
+  int x = c;  // inclusive scan over the group
+  for (int k = 1; k < 32; k <<= 1) {
+    const int y = __shfl_up(x, k, 32);
+    if (o >= k) x += y;
+  }
+  const int run0 = new_starts[D];
+  if (take && s0 != s1) bases[27 * S + o] = run0 + x - c;
+  if (o == 31) cursor[D] = run0 + x;
+}
+
 __global__ void __launch_bounds__(256) k_invert(const int* __restrict__ dst, int* perm, long long n) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (p < n) perm[dst[p]] = (int)p;
@@ -127,6 +169,12 @@ void tile_sort(const GridGeom& g, const TileGeom& t, const int32_t* cell, int64_
 
 void scan_counts(const TileGeom& t, const int* counts, int* starts, int* cursor, hipStream_t s) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, starts, cursor, t.ntiles + 1);
+}
+
+void neighbour_bases(const TileGeom& t, const int* old_starts, const int* nbr_counts, const int* new_starts,
+                     int* bases, int* cursor, hipStream_t s) {
+  hipLaunchKernelGGL(k_neighbour_bases, dim3((unsigned)((t.ntiles + 7) / 8)), dim3(256), 0, s, t, old_starts,
+                     nbr_counts, new_starts, bases, cursor);
 }
 
 void invert_perm(const int* dst, int* perm, int64_t n, hipStream_t s) {

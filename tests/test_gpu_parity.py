@@ -187,12 +187,14 @@ def test_deposit_rho_only_and_static():
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("shape_order", [1, 3])
-def test_step_parity_small(dtype, shape_order):
-    """Three full hybrid cycles on a small workload (several deposition tiles, a radix-3 axis)."""
-    banner(f"pic_step small dtype={dtype} shape_order={shape_order}")
-    shape = (16, 12, 24)
-    wl = inputs.small(shape, ppc=2, shape_order=shape_order, center_order=8, dtype=dtype, u_th=0.1,
+@pytest.mark.parametrize("shape_order,shape,u_th,nsteps", [(1, (16, 12, 24), 0.1, 3), (3, (16, 12, 24), 0.1, 3),
+                                                           (3, (8, 16, 24), 0.4, 4)])
+def test_step_parity_small(dtype, shape_order, shape, u_th, nsteps):
+    """Full hybrid cycles on small workloads: several deposition tiles, a radix-3 axis, partial
+    tiles, axes of one and two tiles (periodic neighbours that coincide) and, with the hotter
+    plasma, many particles changing tile between steps."""
+    banner(f"pic_step small dtype={dtype} shape_order={shape_order} shape={shape} u_th={u_th}")
+    wl = inputs.small(shape, ppc=2, shape_order=shape_order, center_order=8, dtype=dtype, u_th=u_th,
                       field_amp=0.02, seed=51)
     # distinct weights double as particle identities (pic_step regroups particles by tile)
     wl.electrons.w = wl.electrons.w * (1.0 + 1e-3 * np.arange(wl.electrons.n) / wl.electrons.n)
@@ -208,7 +210,7 @@ def test_step_parity_small(dtype, shape_order):
     state = {"E_stag": rounded(wl.E, dtype), "B_stag": rounded(wl.B, dtype),
              "rho_old": ostep.deposit_rho([osp], p, rho_static)}
     tol = 1e-10 if dtype == "f64" else 1e-4
-    for n in range(3):
+    for n in range(nsteps):
         piclib.pic_step(ctx.ctx, f, [el], 1)
         piclib.pic_sync(ctx.ctx)
         ostep.step(state, [osp], p, rho_static)
