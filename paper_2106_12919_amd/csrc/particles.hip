@@ -191,6 +191,18 @@ __device__ inline void through_perm(const int* perm, int (&q)[U]) {
   }
 }
 
+// Workgroups of a launch go to the eight XCDs of the device round-robin (workgroup b
+// to XCD b mod 8), and each XCD has its own L2.  xcd_major renumbers the workgroups
+// 0..n-1 so that every XCD receives one contiguous range of logical indices: tiles
+// next to each other, whose boxes share halo nodes, then share an L2.  (A bijection
+// for any n; only the speed depends on the dispatch order.)
+__device__ inline int xcd_major(int b, int n) {
+  constexpr int kXcds = 8;
+  const int q = n / kXcds, r = n % kXcds;
+  const int x = b % kXcds, s = b / kXcds;
+  return x * q + min(x, r) + s;
+}
+
 // ---------------------------------------------------------------- gather + push
 
 // Nodal field box in LDS, node-major with the six components adjacent (8 slots for
@@ -340,7 +352,7 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_perm(GridGeom 
                                                                        T qdt2m, T dtx, T dty, T dtz) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* box = reinterpret_cast<T*>(smem);
-  const int tile = blockIdx.x;
+  const int tile = xcd_major(blockIdx.x, gridDim.x);
   const int beg = starts[tile], end = starts[tile + 1];
   if (beg == end) return;
   if (tile == tg.ntiles) {
@@ -394,7 +406,7 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
   T* box = reinterpret_cast<T*>(smem);
   __shared__ int cnt[27];
   __shared__ int base[27];
-  const int tile = blockIdx.x;
+  const int tile = xcd_major(blockIdx.x, gridDim.x);
   const int beg = home[tile], end = home[tile + 1];
   if (beg == end) return;
   if (tile == tg.ntiles) {
@@ -988,9 +1000,13 @@ template <typename T, int ORDER, int NCOMP>
 __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGeom tg, const int* __restrict__ starts,
                                                               const T* __restrict__ stage, Batch<T*> out) {
   using X = Box<Shape<T, ORDER>::NW>;
-  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  // grid (z blocks, ny, nx) flattened and renumbered XCD-major: rows next to each other
+  // read the same staging lines
+  const int nzb = gridDim.x;
+  const int L = xcd_major(blockIdx.x + nzb * (blockIdx.y + gridDim.y * blockIdx.z), nzb * gridDim.y * gridDim.z);
+  const int z = (L % nzb) * blockDim.x + threadIdx.x;
   if (z >= g.nz) return;
-  const int y = blockIdx.y, x = blockIdx.z;
+  const int y = (L / nzb) % g.ny, x = L / (nzb * g.ny);
   int tx[2], lx[2], ty[2], ly[2], tz[2], lz[2];
   const int nxc = axis_candidates<ORDER>(x, tg.ntx, tx, lx);
   const int nyc = axis_candidates<ORDER>(y, tg.nty, ty, ly);
