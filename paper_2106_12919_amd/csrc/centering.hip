@@ -10,7 +10,8 @@
 // Strided axes (x, y): one thread per contiguous column element marches over L
 // outputs along the axis with a register window of L + 2m - 1 inputs (each input
 // loaded once per window, loads coalesced across the column index).  Contiguous
-// axis (z): a block stages whole z-lines plus the periodic halo in LDS.
+// axis (z): a block stages whole z-lines plus the periodic halo in LDS.  Both are
+// specialised on m, so the stencil is unrolled.
 #include "kernels.h"
 
 namespace pic {
@@ -22,14 +23,29 @@ struct Coef {
   T c[16];
 };
 
+// Workgroups go to the eight XCDs round-robin (b to XCD b mod 8), each with its own L2;
+// renumbering them XCD-major gives every XCD one contiguous range of logical indices,
+// so that blocks whose halos overlap share an L2.  A bijection on 0..n-1.
+__device__ inline int xcd_major(int b, int n) {
+  constexpr int kXcds = 8;
+  const int q = n / kXcds, r = n % kXcds;
+  const int x = b % kXcds, s = b / kXcds;
+  return x * q + min(x, r) + s;
+}
+
+// Strided axis: grid (column blocks, row blocks, outer) flattened and renumbered
+// XCD-major, row blocks next to each other (which share halo rows) on one XCD.
 template <typename T, int M, int L>
 __global__ void __launch_bounds__(256) k_center_strided(const T* __restrict__ in, T* __restrict__ out, Coef<T> cf,
                                                         int Na, long long sa, int C, long long outer_stride,
                                                         int shift) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nb = gridDim.x * gridDim.y * gridDim.z;
+  const int lb = xcd_major(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
+  const int bx = lb % gridDim.x, by = (lb / gridDim.x) % gridDim.y, bz = lb / (gridDim.x * gridDim.y);
+  const int c = bx * blockDim.x + threadIdx.x;
   if (c >= C) return;
-  const int j0 = blockIdx.y * L;
-  const size_t base = (size_t)blockIdx.z * outer_stride + c;
+  const int j0 = by * L;
+  const size_t base = (size_t)bz * outer_stride + c;
   constexpr int W = L + 2 * M - 1;
   T w[W];
 #pragma unroll
@@ -50,27 +66,67 @@ __global__ void __launch_bounds__(256) k_center_strided(const T* __restrict__ in
   }
 }
 
+// 16-byte vector of T (four floats or two doubles).
 template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+  __device__ static inline void put(float* d, const float4& v) {
+    d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+  }
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+  __device__ static inline void put(double* d, const double2& v) {
+    d[0] = v.x; d[1] = v.y;
+  }
+};
+
+// Contiguous axis: a block stages lpb whole z-lines plus the periodic halo in LDS (line
+// l at s[l * W + i] holds z = i + 1 - M + shift, W = nz + 2M - 1), the line bodies with
+// 16-byte loads, then every thread forms outputs from LDS.
+template <typename T, int M>
 __global__ void __launch_bounds__(256) k_center_z(const T* __restrict__ in, T* __restrict__ out, Coef<T> cf, int nz,
-                                                  int nlines, int lpb, int m, int shift) {
+                                                  int nlines, int lpb, int shift) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* s = reinterpret_cast<T*>(smem);
-  const int W = nz + 2 * m - 1;
+  constexpr int H = 2 * M - 1;  // halo elements per line
+  constexpr int VN = Vec16<T>::n;
+  const int W = nz + H;
+  const int off = M - 1 - shift;  // index of z = 0
   const int line0 = blockIdx.x * lpb;
   const int nl = min(lpb, nlines - line0);
-  for (int e = threadIdx.x; e < nl * W; e += blockDim.x) {
-    const int l = e / W, i = e - l * W;
-    int z = i + 1 - m + shift;
-    z %= nz;
+  const T* src = in + (size_t)line0 * nz;
+  if (nz % VN == 0) {
+    const int nv = nz / VN;
+    for (int e = threadIdx.x; e < nl * nv; e += blockDim.x) {
+      const int l = e / nv, v = e - l * nv;
+      Vec16<T>::put(s + l * W + off + v * VN, reinterpret_cast<const typename Vec16<T>::type*>(src + (size_t)l * nz)[v]);
+    }
+  } else {
+    for (int e = threadIdx.x; e < nl * nz; e += blockDim.x) {
+      const int l = e / nz, z = e - l * nz;
+      s[l * W + off + z] = src[(size_t)l * nz + z];
+    }
+  }
+  for (int e = threadIdx.x; e < nl * H; e += blockDim.x) {
+    const int l = e / H, h = e - l * H;
+    const int i = h < off ? h : nz + h;  // below z = 0, or beyond z = nz - 1
+    int z = (i - off) % nz;
     if (z < 0) z += nz;
-    s[e] = in[(size_t)(line0 + l) * nz + z];
+    s[l * W + i] = src[(size_t)l * nz + z];
   }
   __syncthreads();
   for (int e = threadIdx.x; e < nl * nz; e += blockDim.x) {
     const int l = e / nz, z = e - l * nz;
-    const T* sl = s + l * W;
+    const T* sl = s + l * W + z;
     T acc = 0;
-    for (int n = 1; n <= m; ++n) acc += cf.c[n - 1] * (sl[z + n + m - 1] + sl[z - n + m]);
+#pragma unroll
+    for (int n = 1; n <= M; ++n) acc += cf.c[n - 1] * (sl[n + M - 1] + sl[M - n]);
     out[(size_t)(line0 + l) * nz + z] = acc;
   }
 }
@@ -109,10 +165,19 @@ void center_axis(const T* in, T* out, int nx, int ny, int nz, int axis, int shif
     dispatch_strided<T>(m, in, out, cf, ny, nz, nz, nx, (long long)ny * nz, shift, s);
   } else {
     const int nlines = nx * ny;
-    const int lpb = nz >= 256 ? 1 : 256 / nz;
+    const int lpb = nz >= 1024 ? 1 : 1024 / nz;
     const size_t lds = (size_t)lpb * (nz + 2 * m - 1) * sizeof(T);
-    hipLaunchKernelGGL((k_center_z<T>), dim3((nlines + lpb - 1) / lpb), dim3(256), lds, s, in, out, cf, nz, nlines,
-                       lpb, m, shift);
+    const dim3 grid((nlines + lpb - 1) / lpb);
+    switch (m) {
+#define PIC_CASE(MM)                                                                                              \
+  case MM:                                                                                                        \
+    hipLaunchKernelGGL((k_center_z<T, MM>), grid, dim3(256), lds, s, in, out, cf, nz, nlines, lpb, shift); \
+    break;
+      PIC_CASE(1) PIC_CASE(2) PIC_CASE(3) PIC_CASE(4) PIC_CASE(5) PIC_CASE(6) PIC_CASE(7) PIC_CASE(8)
+      PIC_CASE(9) PIC_CASE(10) PIC_CASE(11) PIC_CASE(12) PIC_CASE(13) PIC_CASE(14) PIC_CASE(15) PIC_CASE(16)
+#undef PIC_CASE
+      default: break;
+    }
   }
 }
 

@@ -137,6 +137,19 @@ __device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nlines, int ls, int js, 
   return a;
 }
 
+// Largest element count per thread of one block's LDS tile (two buffers of kLdsBudget
+// bytes in all): every thread issues all its global loads before it stores any to LDS.
+constexpr size_t kLdsBudget = 65536;
+template <typename T>
+constexpr int kPerThread = (int)(kLdsBudget / (2 * sizeof(cplx<T>)) / kBlock);
+
+// The plan's twiddles, copied to LDS behind the two tile buffers.
+template <typename T>
+__device__ inline cplx<T>* stage_twiddles(cplx<T>* lds, const cplx<T>* __restrict__ tw, int count) {
+  for (int e = threadIdx.x; e < count; e += blockDim.x) lds[e] = tw[e];
+  return lds;
+}
+
 // z pass, real -> half spectrum.  Block = P line pairs of one array (blockIdx.y).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_r2c_z(Batch<const T*> in, Batch<cplx<T>*> out, FftPlan p,
@@ -149,13 +162,25 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z(Batch<const T*> in, Batch<cplx
   cplx<T>* __restrict__ dst = out.p[blockIdx.y];
   const int pair0 = blockIdx.x * P;
   const int np = min(P, nlines / 2 - pair0);
-  for (int e = threadIdx.x; e < np * N; e += blockDim.x) {
+  const int total = np * N;
+  constexpr int PER = kPerThread<T>;
+  T v0[PER], v1[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = min((int)threadIdx.x + u * kBlock, total - 1);
     const int q = e / N, j = e - q * N;
     const size_t l = 2 * (size_t)(pair0 + q);
-    a[q * N + j] = cmake(src[l * N + j], src[(l + 1) * N + j]);
+    v0[u] = src[l * N + j];
+    v1[u] = src[(l + 1) * N + j];
+  }
+  const cplx<T>* twl = stage_twiddles(b + (size_t)P * N, tw, p.twcount);
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * kBlock;
+    if (e < total) a[e] = cmake(v0[u], v1[u]);
   }
   __syncthreads();
-  cplx<T>* res = fft_lds<T, -1>(a, b, np, N, 1, p, tw, false);
+  cplx<T>* res = fft_lds<T, -1>(a, b, np, N, 1, p, twl, false);
   const int nh = N / 2 + 1;
   for (int e = threadIdx.x; e < np * nh; e += blockDim.x) {
     const int q = e / nh, k = e - q * nh;
@@ -183,22 +208,37 @@ __global__ void __launch_bounds__(kBlock) k_c2r_z(Batch<const cplx<T>*> in, Batc
   const int pair0 = blockIdx.x * P;
   const int np = min(P, nlines / 2 - pair0);
   const int half = N / 2;
-  for (int e = threadIdx.x; e < np * N; e += blockDim.x) {
+  const int total = np * N;
+  constexpr int PER = kPerThread<T>;
+  cplx<T> f[PER], g[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = min((int)threadIdx.x + u * kBlock, total - 1);
     const int q = e / N, k = e - q * N;
     const size_t l = 2 * (size_t)(pair0 + q);
-    cplx<T> F, G;
-    if (k <= half) {
-      F = src[l * pz + k];
-      G = src[(l + 1) * pz + k];
-      if (k == 0 || k == half) { F.y = 0; G.y = 0; }
-    } else {
-      F = cconj(src[l * pz + (N - k)]);
-      G = cconj(src[(l + 1) * pz + (N - k)]);
+    const int kk = k <= half ? k : N - k;
+    f[u] = src[l * pz + kk];
+    g[u] = src[(l + 1) * pz + kk];
+  }
+  const cplx<T>* twl = stage_twiddles(b + (size_t)P * N, tw, p.twcount);
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * kBlock;
+    if (e < total) {
+      const int k = e % N;
+      cplx<T> F = f[u], G = g[u];
+      if (k > half) {
+        F = cconj(F);
+        G = cconj(G);
+      } else if (k == 0 || k == half) {
+        F.y = 0;
+        G.y = 0;
+      }
+      a[e] = cmake(F.x - G.y, F.y + G.x);
     }
-    a[q * N + k] = cmake(F.x - G.y, F.y + G.x);
   }
   __syncthreads();
-  cplx<T>* res = fft_lds<T, +1>(a, b, np, N, 1, p, tw, false);
+  cplx<T>* res = fft_lds<T, +1>(a, b, np, N, 1, p, twl, false);
   for (int e = threadIdx.x; e < np * N; e += blockDim.x) {
     const int q = e / N, j = e - q * N;
     const size_t l = 2 * (size_t)(pair0 + q);
@@ -208,14 +248,16 @@ __global__ void __launch_bounds__(kBlock) k_c2r_z(Batch<const cplx<T>*> in, Batc
   }
 }
 
-// y or x pass, complex -> complex along a strided axis, TL adjacent lines per block.
+// y or x pass, complex -> complex along a strided axis, TL = 2^tl_shift adjacent lines
+// per block.
 template <typename T, int SIGN>
 __global__ void __launch_bounds__(kBlock) k_fft_strided(Batch<const cplx<T>*> in, Batch<cplx<T>*> out, FftPlan p,
-                                                        const cplx<T>* __restrict__ tw, int TL, int inner_count,
+                                                        const cplx<T>* __restrict__ tw, int tl_shift, int inner_count,
                                                         int tiles_per_outer, long long outer_stride,
                                                         long long elem_stride) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = p.n;
+  const int TL = 1 << tl_shift;
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* b = a + (size_t)TL * N;
   const cplx<T>* __restrict__ src = in.p[blockIdx.y];
@@ -225,44 +267,63 @@ __global__ void __launch_bounds__(kBlock) k_fft_strided(Batch<const cplx<T>*> in
   const int inner0 = (tile - outer * tiles_per_outer) * TL;
   const int nl = min(TL, inner_count - inner0);
   const size_t base = (size_t)outer * outer_stride + inner0;
-  for (int e = threadIdx.x; e < N * TL; e += blockDim.x) {
-    const int j = e / TL, i = e - j * TL;
-    a[e] = (i < nl) ? src[base + i + (size_t)j * elem_stride] : cmake((T)0, (T)0);
+  const int total = N * TL;
+  constexpr int PER = kPerThread<T>;
+  cplx<T> v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = min((int)threadIdx.x + u * kBlock, total - 1);
+    const int j = e >> tl_shift, i = min(e & (TL - 1), nl - 1);
+    v[u] = src[base + i + (size_t)j * elem_stride];
+  }
+  const cplx<T>* twl = stage_twiddles(b + (size_t)TL * N, tw, p.twcount);
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * kBlock;
+    if (e < total) a[e] = ((e & (TL - 1)) < nl) ? v[u] : cmake((T)0, (T)0);
   }
   __syncthreads();
-  cplx<T>* res = fft_lds<T, SIGN>(a, b, TL, 1, TL, p, tw, true);
-  for (int e = threadIdx.x; e < N * TL; e += blockDim.x) {
-    const int j = e / TL, i = e - j * TL;
+  cplx<T>* res = fft_lds<T, SIGN>(a, b, TL, 1, TL, p, twl, true);
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    const int j = e >> tl_shift, i = e & (TL - 1);
     if (i < nl) dst[base + i + (size_t)j * elem_stride] = res[e];
   }
 }
 
-constexpr size_t kLdsBudget = 65536;
 
+// Tiles fit the 64 KiB default LDS of a launch together with the twiddles (fewer than
+// n of them).
 template <typename T>
 int pairs_per_block(int n) {
   int P = 2048 / n;
   if (P < 1) P = 1;
-  while (P > 1 && 2 * (size_t)P * n * sizeof(cplx<T>) > kLdsBudget) P /= 2;
+  while (P > 1 && (2 * (size_t)P * n + n) * sizeof(cplx<T>) > kLdsBudget) P /= 2;
   return P;
 }
 
 template <typename T>
-int lines_per_tile(int n) {
-  int TL = 16;
-  while (TL > 1 && 2 * (size_t)TL * n * sizeof(cplx<T>) > kLdsBudget) TL /= 2;
-  return TL;
+int lines_per_tile_shift(int n) {
+  int sh = 4;  // 16 lines
+  while (sh > 0 && (2 * ((size_t)1 << sh) * n + n) * sizeof(cplx<T>) > kLdsBudget) --sh;
+  return sh;
+}
+
+// LDS bytes of a block: two tile buffers of ``elems`` elements and the twiddles.
+template <typename T>
+size_t fft_lds_bytes(size_t elems, const FftPlan& p) {
+  return (2 * elems + (size_t)(p.twcount > 0 ? p.twcount : 1)) * sizeof(cplx<T>);
 }
 
 template <typename T, int SIGN>
 void strided_pass(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& out, int count, const FftPlan& p,
                   const cplx<T>* tw, int outer_count, int inner_count, long long outer_stride, long long elem_stride,
                   hipStream_t s) {
-  const int TL = lines_per_tile<T>(p.n);
+  const int sh = lines_per_tile_shift<T>(p.n);
+  const int TL = 1 << sh;
   const int tpo = (inner_count + TL - 1) / TL;
   dim3 grid(outer_count * tpo, count);
-  const size_t lds = 2 * (size_t)TL * p.n * sizeof(cplx<T>);
-  hipLaunchKernelGGL((k_fft_strided<T, SIGN>), grid, dim3(kBlock), lds, s, in, out, p, tw, TL, inner_count, tpo,
+  const size_t lds = fft_lds_bytes<T>((size_t)TL * p.n, p);
+  hipLaunchKernelGGL((k_fft_strided<T, SIGN>), grid, dim3(kBlock), lds, s, in, out, p, tw, sh, inner_count, tpo,
                      outer_stride, elem_stride);
 }
 
@@ -305,8 +366,8 @@ void Fft3D<T>::forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, in
   const int nlines = nx * ny;
   const int P = pairs_per_block<T>(nz);
   dim3 grid((nlines / 2 + P - 1) / P, count);
-  hipLaunchKernelGGL((k_r2c_z<T>), grid, dim3(kBlock), 2 * (size_t)P * nz * sizeof(cplx<T>), s, in, out, plan[2],
-                     tw[2], nlines, pz, P);
+  hipLaunchKernelGGL((k_r2c_z<T>), grid, dim3(kBlock), fft_lds_bytes<T>((size_t)P * nz, plan[2]), s, in, out,
+                     plan[2], tw[2], nlines, pz, P);
   Batch<const cplx<T>*> cin;
   for (int i = 0; i < count; ++i) cin.p[i] = out.p[i];
   strided_pass<T, -1>(cin, out, count, plan[1], tw[1], nx, nzh, (long long)ny * pz, pz, s);
@@ -323,8 +384,8 @@ void Fft3D<T>::inverse(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& s
   const int nlines = nx * ny;
   const int P = pairs_per_block<T>(nz);
   dim3 grid((nlines / 2 + P - 1) / P, count);
-  hipLaunchKernelGGL((k_c2r_z<T>), grid, dim3(kBlock), 2 * (size_t)P * nz * sizeof(cplx<T>), s, cs, out, plan[2],
-                     tw[2], nlines, pz, P, scale);
+  hipLaunchKernelGGL((k_c2r_z<T>), grid, dim3(kBlock), fft_lds_bytes<T>((size_t)P * nz, plan[2]), s, cs, out,
+                     plan[2], tw[2], nlines, pz, P, scale);
 }
 
 template struct Fft3D<float>;
