@@ -52,6 +52,13 @@ struct Shape<T, 3> {
   }
 };
 
+// 1/sqrt(x) and a/b: the hardware approximations (about 1 ulp) in FP32, exact
+// rounding in FP64 (the FP64 path is held to the FP64 oracle's rounding level).
+__device__ inline float inv_sqrt(float x) { return rsqrtf(x); }
+__device__ inline double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+__device__ inline float quot(float a, float b) { return __fdividef(a, b); }
+__device__ inline double quot(double a, double b) { return a / b; }
+
 __device__ inline int wrapi(int i, int n) {
   i = (i < 0) ? i + n : i;
   return (i >= n) ? i - n : i;
@@ -313,10 +320,9 @@ __device__ inline void gather_push_one(const T* box, const Batch<const T*>& F, c
   }
   // relativistic Boris (c = 1)
   const T umx = ux + qdt2m * f[0], umy = uy + qdt2m * f[1], umz = uz + qdt2m * f[2];
-  const T gm = sqrt((T)1 + umx * umx + umy * umy + umz * umz);
-  const T tf = qdt2m / gm;
+  const T tf = qdt2m * inv_sqrt((T)1 + umx * umx + umy * umy + umz * umz);  // q dt / (2 m gamma)
   const T tx = tf * f[3], ty = tf * f[4], tz = tf * f[5];
-  const T sf = (T)2 / ((T)1 + tx * tx + ty * ty + tz * tz);
+  const T sf = quot((T)2, (T)1 + tx * tx + ty * ty + tz * tz);
   const T sx = sf * tx, sy = sf * ty, sz = sf * tz;
   const T upx = umx + (umy * tz - umz * ty);
   const T upy = umy + (umz * tx - umx * tz);
@@ -324,7 +330,7 @@ __device__ inline void gather_push_one(const T* box, const Batch<const T*>& F, c
   ux = umx + (upy * sz - upz * sy) + qdt2m * f[0];
   uy = umy + (upz * sx - upx * sz) + qdt2m * f[1];
   uz = umz + (upx * sy - upy * sx) + qdt2m * f[2];
-  const T ig = (T)1 / sqrt((T)1 + ux * ux + uy * uy + uz * uz);
+  const T ig = inv_sqrt((T)1 + ux * ux + uy * uy + uz * uz);
   i = wrapi(i + advance_offset(ox, dtx * ux * ig), g.nx);
   j = wrapi(j + advance_offset(oy, dty * uy * ig), g.ny);
   k = wrapi(k + advance_offset(oz, dtz * uz * ig), g.nz);
@@ -647,7 +653,7 @@ __device__ inline bool locate(const Raw<T>& r, const GridGeom& g, int t0x, int t
   }
   d.at_j = -1;
   if (WJ) {
-    const T ig = (T)1 / sqrt((T)1 + r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
+    const T ig = inv_sqrt((T)1 + r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
     d.vx = r.u[0] * ig;
     d.vy = r.u[1] * ig;
     d.vz = r.u[2] * ig;
@@ -671,7 +677,7 @@ __device__ inline void bound_add(const Raw<T>& r, T* sw, T* mw) {
   sw[0] += a;
   mw[0] = fmax(mw[0], a);
   if (WJ) {
-    const T ig = (T)1 / sqrt((T)1 + r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
+    const T ig = inv_sqrt((T)1 + r.u[0] * r.u[0] + r.u[1] * r.u[1] + r.u[2] * r.u[2]);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const T v = a * fabs(r.u[d] * ig);
