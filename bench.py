@@ -87,6 +87,7 @@ def stage_bytes(stage, N, M, Np, s):
         "psatd_update": M * (11 * 2 * s + 5 * s + 6 * 2 * s),  # 11 spectra + 5 tables in, 6 out
         "fft_inverse": 6 * (M * 2 * s + N * s),          # E, B: half spectrum in, real out
         "entry_forward": 7 * (N * s + M * 2 * s),
+        "exit_inverse": 6 * (M * 2 * s + N * s),
         "tile_sort": Np * 12,          # cell read twice (count, rank), slot written
         "clear_sources": 4 * N * s,    # rho <- static background, J <- 0
     }[stage]
@@ -142,6 +143,9 @@ def main():
                     help="after the main measurement, time the same workload at each centering order of the "
                          "comma-separated LIST ([sweep] lines on stderr, and JSON lines into --extra-json)")
     ap.add_argument("--extra-json", default="", metavar="PATH")
+    ap.add_argument("--spectral-centering", action="store_true",
+                    help="apply the finite-order centering as its Fourier symbol inside the per-mode update "
+                         "(PIC_SPECTRAL_CENTERING; same results up to rounding, no real-space centering passes)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy a MIB-MiB float32 tensor 3 times (a plain copy kernel "
                          "of known size, the reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -160,11 +164,12 @@ def main():
     wl = inputs.config(args.config, dtype=args.dtype, center_order=args.center_order)
     print(f"[bench] workload {args.config} dtype={wl.dtype} cells={wl.cells} particles={wl.electrons.n}",
           file=sys.stderr, flush=True)
-    result = run_gpu(wl, args.config, args.steps, args.warmup, args.calibrate_copy)
+    flags = 1 if args.spectral_centering else 0  # PIC_SPECTRAL_CENTERING
+    result = run_gpu(wl, args.config, args.steps, args.warmup, args.calibrate_copy, flags)
     if args.sweep_center_orders:
         for order in [int(x) for x in args.sweep_center_orders.split(",")]:
             wl.center_order = order
-            r = run_gpu(wl, args.config, args.steps, args.warmup, 0)
+            r = run_gpu(wl, args.config, args.steps, args.warmup, 0, flags)
             line = {"sweep": "center_order", "center_order": order, "dtype": wl.dtype, "value": r["value"],
                     "ms_per_step": r["ms_per_step"], "cell_updates_per_s": r["cell_updates_per_s"],
                     "stages": {k: v["ms_avg"] for k, v in r["stages"].items()}}
@@ -178,13 +183,13 @@ def main():
     print(json.dumps(result))
 
 
-def run_gpu(wl, config_name, steps, warmup, calibrate_copy):
+def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0):
     """Times ``steps`` hybrid cycles of the workload (one pic_step call) after ``warmup`` steps."""
     import torch
 
     from paper_2106_12919_amd import lib as piclib
 
-    ctx = piclib.Context.for_workload(wl)
+    ctx = piclib.Context.for_workload(wl, flags=flags)
     f = ctx.fields_from_workload(wl)
     el = piclib.Species.from_host(wl.electrons, wl.shape, wl.dtype)
     ions = piclib.Species.from_host(wl.ions, wl.shape, wl.dtype)
@@ -230,7 +235,7 @@ def run_gpu(wl, config_name, steps, warmup, calibrate_copy):
         b = stage_bytes(name, N, M, Np, s)
         breakdown[name] = {"ms_avg": round(avg, 5), "launches": cnt, "algo_bytes": b,
                            "GBps": round(b / (avg * 1e-3) / 1e9, 1)}
-    dom = max((k for k in breakdown if k != "entry_forward"),
+    dom = max((k for k in breakdown if k not in ("entry_forward", "exit_inverse")),
               key=lambda k: breakdown[k]["ms_avg"] * breakdown[k]["launches"])
     d = breakdown[dom]
     achieved = d["algo_bytes"] / (d["ms_avg"] * 1e-3) / 1e9
@@ -249,7 +254,8 @@ def run_gpu(wl, config_name, steps, warmup, calibrate_copy):
         "dtype": wl.dtype,
         "data": "synthetic (seeded laser + plasma workload)",
         "config": {"workload": CONFIG_TEXT[config_name], "cells": N, "particles": Np,
-                   "center_order": wl.center_order, "shape_order": wl.shape_order, "pass": "forward"},
+                   "center_order": wl.center_order, "shape_order": wl.shape_order, "pass": "forward",
+                   "centering": "spectral" if flags & 1 else "real-space"},
         "cell_updates_per_s": N * K / T,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -54,6 +54,18 @@ enum { PIC_N2S = 0, PIC_S2N = 1 };
 enum { PIC_J = 0, PIC_E = 1, PIC_B = 2 };
 /* pic_deposit modes */
 enum { PIC_DEP_RHO_AND_J = 0, PIC_DEP_RHO_ONLY = 1 };
+/* pic_params.flags */
+enum {
+  /* pic_step applies the finite-order centering of J (nodes -> Yee) and of the updated
+   * E, B (Yee -> nodes) as the stencils' exact Fourier symbols inside the per-mode
+   * update: on the periodic grid the stencil of Sec. 3 is that multiplication (App. C),
+   * so the results equal the real-space cycle up to rounding, without the two
+   * real-space centering passes per step.  At return E_stag, B_stag, J_stag, rho_old and
+   * the particles are as in the real-space cycle; E_nod, B_nod hold the centred fields of
+   * the final time level (the real-space cycle leaves those of the last step's start).
+   * pic_center and psatd_push_fields are unaffected. */
+  PIC_SPECTRAL_CENTERING = 1u << 0
+};
 
 typedef struct {
   int32_t nx, ny, nz;     /* each even, of the form 2^a 3^b, 8 <= n <= 1024 */
@@ -63,7 +75,7 @@ typedef struct {
   int32_t center_order;   /* finite-order centering 2m, even, 2..32, with 2m <= min(nx,ny,nz) (Sec. 3) */
   int32_t psatd_order;    /* order 2m_p of the staggered modified wave number [k]_s, even 2..64; 0 = infinite */
   pic_dtype dtype;        /* precision of fields, particles, FFTs; tables are always built in FP64 */
-  uint32_t flags;         /* reserved, must be 0 */
+  uint32_t flags;         /* 0 or PIC_SPECTRAL_CENTERING; other bits are rejected */
 } pic_params;
 
 /* One particle species, structure of arrays, caller-owned device memory.

@@ -17,10 +17,11 @@ thread_local std::string g_init_error;
 
 const char* const kStageNames[] = {"center_s2n",   "gather_push", "deposit",       "center_n2s", "fft_forward",
                                    "psatd_update", "fft_inverse", "entry_forward", "tile_sort",  "clear_sources",
-                                   "deposit_reduce"};
-constexpr int kNumStages = 11;
+                                   "deposit_reduce", "exit_inverse"};
+constexpr int kNumStages = 12;
 enum Stage {
-  ST_S2N = 0, ST_PUSH, ST_DEPOSIT, ST_N2S, ST_FFT_FWD, ST_UPDATE, ST_FFT_INV, ST_ENTRY, ST_SORT, ST_CLEAR, ST_REDUCE
+  ST_S2N = 0, ST_PUSH, ST_DEPOSIT, ST_N2S, ST_FFT_FWD, ST_UPDATE, ST_FFT_INV, ST_ENTRY, ST_SORT, ST_CLEAR, ST_REDUCE,
+  ST_EXIT
 };
 
 struct EventPair {
@@ -211,6 +212,10 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
   const int n[3] = {p.nx, p.ny, p.nz};
   const double d[3] = {p.dx, p.dy, p.dz};
   const int nzh = e.fft.nzh;
+  const int m = p.center_order / 2;
+  std::vector<double> calpha(m);
+  alpha_staggered(m, calpha.data());
+  for (double& v : calpha) v *= 0.5;
   // per-axis [k]_s and the staggered phase operators D+- = i [k]_s exp(+-i k d / 2)
   std::vector<double> ks[3];
   for (int a = 0; a < 3; ++a) {
@@ -228,6 +233,20 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
     }
     if ((err = e.upload(&e.tab.Dp[a], dp)) != hipSuccess) return err;
     if ((err = e.upload(&e.tab.Dm[a], dm)) != hipSuccess) return err;
+    // Fourier symbol of the nodes -> centres centering along this axis, in the index-space
+    // DFT convention: sum_n c_n (e^{i th n} + e^{-i th (n-1)}), th = 2 pi f / n, c_n = alpha^s_{m,n}/2
+    std::vector<cplx<T>> tc(len);
+    for (int i = 0; i < len; ++i) {
+      const int f = (i <= (n[a] - 1) / 2) ? i : i - n[a];
+      const double th = two_pi * f / n[a];
+      double re = 0, im = 0;
+      for (int q = 1; q <= m; ++q) {
+        re += calpha[q - 1] * (std::cos(th * q) + std::cos(th * (q - 1)));
+        im += calpha[q - 1] * (std::sin(th * q) - std::sin(th * (q - 1)));
+      }
+      tc[i] = cmake((T)re, (T)im);
+    }
+    if ((err = e.upload(&e.tab.Tc[a], tc)) != hipSuccess) return err;
   }
   // 3D per-mode tables on the unpadded half spectrum
   const size_t M = (size_t)p.nx * p.ny * nzh;
@@ -296,7 +315,7 @@ pic_status validate_params(const pic_params* p, std::string& msg) {
     return PIC_EUNSUPPORTED;
   }
   if (p->dtype != PIC_F32 && p->dtype != PIC_F64) { msg = "dtype must be PIC_F32 or PIC_F64"; return PIC_EINVAL; }
-  if (p->flags != 0) { msg = "flags must be 0"; return PIC_EINVAL; }
+  if (p->flags & ~(uint32_t)PIC_SPECTRAL_CENTERING) { msg = "unknown bit in flags"; return PIC_EINVAL; }
   return PIC_OK;
 }
 
@@ -485,15 +504,36 @@ void forward_batch(pic_ctx c, Engine<T>& e, const T* const* src, cplx<T>* const*
   e.fft.forward(in, out, count, c->stream);
 }
 
+// The per-mode update, then the inverse transforms: of the staggered state into E_stag,
+// B_stag, or (spectral centering) of the nodal spectra the update also wrote, in place in
+// the scratch spectra, into E_nod, B_nod.
 template <typename T>
-void update_and_inverse(pic_ctx c, Engine<T>& e, pic_fields* f, int rho_old_slot) {
+void update_and_inverse(pic_ctx c, Engine<T>& e, pic_fields* f, int rho_old_slot, bool spectral = false) {
   const pic_params& p = c->p;
   {
     StageScope sc(c, ST_UPDATE);
     psatd_update<T>(e.tab, e.Eh, e.Bh, e.Jh, e.rh[rho_old_slot], e.rh[1 - rho_old_slot], p.nx, p.ny, e.fft.nzh,
-                    e.fft.pz, c->stream);
+                    e.fft.pz, spectral ? e.scratch : nullptr, c->stream);
   }
   StageScope sc(c, ST_FFT_INV);
+  Batch<const cplx<T>*> in{};
+  Batch<cplx<T>*> scr{};
+  Batch<T*> out{};
+  for (int d = 0; d < 3; ++d) {
+    in.p[d] = spectral ? e.scratch[d] : e.Eh[d];
+    in.p[3 + d] = spectral ? e.scratch[3 + d] : e.Bh[d];
+    out.p[d] = static_cast<T*>(spectral ? f->E_nod[d] : f->E_stag[d]);
+    out.p[3 + d] = static_cast<T*>(spectral ? f->B_nod[d] : f->B_stag[d]);
+  }
+  for (int i = 0; i < 6; ++i) scr.p[i] = e.scratch[i];
+  e.fft.inverse(in, scr, out, 6, (T)(1.0 / (double)ncells(p)), c->stream);
+}
+
+// The staggered state E_stag, B_stag from the resident spectra (end of a spectral-
+// centering pic_step call).
+template <typename T>
+void state_inverse(pic_ctx c, Engine<T>& e, pic_fields* f) {
+  StageScope sc(c, ST_EXIT);
   Batch<const cplx<T>*> in{};
   Batch<cplx<T>*> scr{};
   Batch<T*> out{};
@@ -504,7 +544,7 @@ void update_and_inverse(pic_ctx c, Engine<T>& e, pic_fields* f, int rho_old_slot
     out.p[3 + d] = static_cast<T*>(f->B_stag[d]);
   }
   for (int i = 0; i < 6; ++i) scr.p[i] = e.scratch[i];
-  e.fft.inverse(in, scr, out, 6, (T)(1.0 / (double)ncells(p)), c->stream);
+  e.fft.inverse(in, scr, out, 6, (T)(1.0 / (double)ncells(c->p)), c->stream);
 }
 
 template <typename T>
@@ -564,8 +604,9 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
     if (he != hipSuccess) return c->fail(PIC_ENOMEM, std::string("pic_step: ") + hipGetErrorString(he));
   }
   pic_status st;
+  const bool spectral = (p.flags & PIC_SPECTRAL_CENTERING) != 0;
   for (int n = 0; n < nsteps; ++n) {
-    {
+    if (!spectral || n == 0) {  // spectral centering: later steps get E_nod, B_nod from the update
       StageScope sc(c, ST_S2N);
       if ((st = do_center<T>(c, PIC_S2N, PIC_E, f)) != PIC_OK) return st;
       if ((st = do_center<T>(c, PIC_S2N, PIC_B, f)) != PIC_OK) return st;
@@ -623,20 +664,26 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
       // layout index of the grouping the particles are now in
       if (mobile) layout[q] = first ? 0 : 1 - L;
     }
-    {
+    if (!spectral) {
       StageScope sc(c, ST_N2S);
       if ((st = do_center<T>(c, PIC_N2S, PIC_J, f)) != PIC_OK) return st;
     }
     {
       StageScope sc(c, ST_FFT_FWD);
-      const T* src[4] = {static_cast<const T*>(f->J_stag[0]), static_cast<const T*>(f->J_stag[1]),
-                         static_cast<const T*>(f->J_stag[2]), static_cast<const T*>(f->rho_new)};
+      void* const* J = spectral ? f->J_nod : f->J_stag;  // spectral centering: the update centres J
+      const T* src[4] = {static_cast<const T*>(J[0]), static_cast<const T*>(J[1]), static_cast<const T*>(J[2]),
+                         static_cast<const T*>(f->rho_new)};
       cplx<T>* dst[4] = {e.Jh[0], e.Jh[1], e.Jh[2], e.rh[1 - slot]};
       forward_batch<T>(c, e, src, dst, 4);
     }
-    update_and_inverse<T>(c, e, f, slot);
+    update_and_inverse<T>(c, e, f, slot, spectral);
     slot = 1 - slot;
     if ((st = c->check("pic_step")) != PIC_OK) return st;
+  }
+  if (spectral) {  // the outputs the real-space cycle leaves: the staggered state and J_stag
+    state_inverse<T>(c, e, f);
+    StageScope sc(c, ST_N2S);
+    if ((st = do_center<T>(c, PIC_N2S, PIC_J, f)) != PIC_OK) return st;
   }
   // particles left in the scratch arrays go back to the caller's arrays (tile order kept)
   for (int q = 0; q < nsp; ++q)

@@ -42,10 +42,17 @@ struct PsatdTables {
   T* X3 = nullptr;
   cplx<T>* Dp[3] = {nullptr, nullptr, nullptr};  // i [k_d]_s exp(+i k_d d_d / 2), per axis (z: nzh entries)
   cplx<T>* Dm[3] = {nullptr, nullptr, nullptr};  // i [k_d]_s exp(-i k_d d_d / 2)
+  // Fourier symbol of the nodes -> centres centering along each axis (index-space DFT):
+  // sum_n c_n (e^{i theta n} + e^{-i theta (n-1)}); centres -> nodes is its conjugate.
+  cplx<T>* Tc[3] = {nullptr, nullptr, nullptr};
 };
+// With nodal != nullptr (spectral centering): J holds the NODAL current spectra, centred
+// to the Yee grid by the symbols Tc inside the update, and nodal[0..5] receive the
+// centred spectra of the updated E (0..2) and B (3..5), ready for the inverse FFT.
 template <typename T>
 void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B[3], const cplx<T>* const J[3],
-                  const cplx<T>* rho_old, const cplx<T>* rho_new, int nx, int ny, int nzh, int pz, hipStream_t s);
+                  const cplx<T>* rho_old, const cplx<T>* rho_new, int nx, int ny, int nzh, int pz,
+                  cplx<T>* const* nodal, hipStream_t s);
 
 // ---------------------------------------------------------------- particles (particles.hip)
 // Division by a fixed divisor d (1 <= d < 2^31) as a multiply-high and a shift:

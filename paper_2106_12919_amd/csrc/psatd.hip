@@ -13,15 +13,22 @@
 //   bx' = C bx - Sw (D+y ez - D+z ey) + X1 (D+y jz - D+z jy)            (and cyclic)
 //   ex' = C ex + Sw (D-y bz - D-z by) - Sw jx + (X3 ro - X2 rn) D+x      (and cyclic)
 // One thread per half-spectrum mode; every array is read and written once.
+// Optionally (spectral centering) the nodal current is centred to the Yee grid and the
+// updated fields back to the nodes inside the same pass, by the centering's Fourier
+// symbol: on a periodic grid the finite-order stencil of Sec. 3 is exactly that
+// multiplication (App. C), so the result equals real-space centering up to rounding.
 #include "kernels.h"
 
 namespace pic {
 
 namespace {
 
-template <typename T>
+// SPECTRAL: the currents arrive on the nodes and are centred by Tc (Sec. 3 centering as
+// its exact Fourier symbol on the periodic grid, App. C), and the updated E, B are also
+// written centred back to the nodes (conj Tc along the same axes as in real space).
+template <typename T, bool SPECTRAL>
 __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cplx<T>*> F, Batch<const cplx<T>*> S,
-                                                      int nx, int ny, int nzh, int pz) {
+                                                      Batch<cplx<T>*> NOD, int nx, int ny, int nzh, int pz) {
   const long long total = (long long)nx * ny * nzh;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
@@ -37,7 +44,16 @@ __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cp
 
   const cplx<T> ex = F.p[0][a], ey = F.p[1][a], ez = F.p[2][a];
   const cplx<T> bx = F.p[3][a], by = F.p[4][a], bz = F.p[5][a];
-  const cplx<T> jx = S.p[0][a], jy = S.p[1][a], jz = S.p[2][a];
+  cplx<T> jx = S.p[0][a], jy = S.p[1][a], jz = S.p[2][a];
+  cplx<T> tcx, tcy, tcz;
+  if (SPECTRAL) {
+    tcx = t.Tc[0][i];
+    tcy = t.Tc[1][j];
+    tcz = t.Tc[2][kz];
+    jx = cmul(jx, tcx);
+    jy = cmul(jy, tcy);
+    jz = cmul(jz, tcz);
+  }
   const cplx<T> ro = S.p[3][a], rn = S.p[4][a];
 
   // B update: curl terms with D+ (E, J live on edges; B on faces)
@@ -47,25 +63,41 @@ __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cp
   const cplx<T> cJx = csub(cmul(py, jz), cmul(pzd, jy));
   const cplx<T> cJy = csub(cmul(pzd, jx), cmul(px, jz));
   const cplx<T> cJz = csub(cmul(px, jy), cmul(py, jx));
-  F.p[3][a] = cadd(csub(cscale(bx, C), cscale(cEx, Sw)), cscale(cJx, X1));
-  F.p[4][a] = cadd(csub(cscale(by, C), cscale(cEy, Sw)), cscale(cJy, X1));
-  F.p[5][a] = cadd(csub(cscale(bz, C), cscale(cEz, Sw)), cscale(cJz, X1));
+  const cplx<T> nbx = cadd(csub(cscale(bx, C), cscale(cEx, Sw)), cscale(cJx, X1));
+  const cplx<T> nby = cadd(csub(cscale(by, C), cscale(cEy, Sw)), cscale(cJy, X1));
+  const cplx<T> nbz = cadd(csub(cscale(bz, C), cscale(cEz, Sw)), cscale(cJz, X1));
+  F.p[3][a] = nbx;
+  F.p[4][a] = nby;
+  F.p[5][a] = nbz;
 
   // E update: curl of B with D-, source terms
   const cplx<T> cBx = csub(cmul(my, bz), cmul(mz, by));
   const cplx<T> cBy = csub(cmul(mz, bx), cmul(mx, bz));
   const cplx<T> cBz = csub(cmul(mx, by), cmul(my, bx));
   const cplx<T> rr = csub(cscale(ro, X3), cscale(rn, X2));
-  F.p[0][a] = cadd(csub(cadd(cscale(ex, C), cscale(cBx, Sw)), cscale(jx, Sw)), cmul(rr, px));
-  F.p[1][a] = cadd(csub(cadd(cscale(ey, C), cscale(cBy, Sw)), cscale(jy, Sw)), cmul(rr, py));
-  F.p[2][a] = cadd(csub(cadd(cscale(ez, C), cscale(cBz, Sw)), cscale(jz, Sw)), cmul(rr, pzd));
+  const cplx<T> nex = cadd(csub(cadd(cscale(ex, C), cscale(cBx, Sw)), cscale(jx, Sw)), cmul(rr, px));
+  const cplx<T> ney = cadd(csub(cadd(cscale(ey, C), cscale(cBy, Sw)), cscale(jy, Sw)), cmul(rr, py));
+  const cplx<T> nez = cadd(csub(cadd(cscale(ez, C), cscale(cBz, Sw)), cscale(jz, Sw)), cmul(rr, pzd));
+  F.p[0][a] = nex;
+  F.p[1][a] = ney;
+  F.p[2][a] = nez;
+  if (SPECTRAL) {  // centres -> nodes: E^d along d, B^d along the two other axes
+    const cplx<T> sx = cconj(tcx), sy = cconj(tcy), sz = cconj(tcz);
+    NOD.p[0][a] = cmul(nex, sx);
+    NOD.p[1][a] = cmul(ney, sy);
+    NOD.p[2][a] = cmul(nez, sz);
+    NOD.p[3][a] = cmul(cmul(nbx, sy), sz);
+    NOD.p[4][a] = cmul(cmul(nby, sx), sz);
+    NOD.p[5][a] = cmul(cmul(nbz, sx), sy);
+  }
 }
 
 }  // namespace
 
 template <typename T>
 void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B[3], const cplx<T>* const J[3],
-                  const cplx<T>* rho_old, const cplx<T>* rho_new, int nx, int ny, int nzh, int pz, hipStream_t s) {
+                  const cplx<T>* rho_old, const cplx<T>* rho_new, int nx, int ny, int nzh, int pz,
+                  cplx<T>* const* nodal, hipStream_t s) {
   Batch<cplx<T>*> F{};
   Batch<const cplx<T>*> S{};
   for (int d = 0; d < 3; ++d) {
@@ -75,16 +107,22 @@ void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B
   }
   S.p[3] = rho_old;
   S.p[4] = rho_new;
+  Batch<cplx<T>*> N{};
+  if (nodal)
+    for (int q = 0; q < 6; ++q) N.p[q] = nodal[q];
   const long long total = (long long)nx * ny * nzh;
-  hipLaunchKernelGGL((k_psatd_update<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, t, F, S, nx, ny, nzh,
-                     pz);
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (nodal)
+    hipLaunchKernelGGL((k_psatd_update<T, true>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
+  else
+    hipLaunchKernelGGL((k_psatd_update<T, false>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
 }
 
 template void psatd_update<float>(const PsatdTables<float>&, cplx<float>* const*, cplx<float>* const*,
                                   const cplx<float>* const*, const cplx<float>*, const cplx<float>*, int, int, int,
-                                  int, hipStream_t);
+                                  int, cplx<float>* const*, hipStream_t);
 template void psatd_update<double>(const PsatdTables<double>&, cplx<double>* const*, cplx<double>* const*,
                                    const cplx<double>* const*, const cplx<double>*, const cplx<double>*, int, int,
-                                   int, int, hipStream_t);
+                                   int, int, cplx<double>* const*, hipStream_t);
 
 }  // namespace pic

@@ -22,6 +22,7 @@ PIC_F32, PIC_F64 = 0, 1
 PIC_N2S, PIC_S2N = 0, 1
 PIC_J, PIC_E, PIC_B = 0, 1, 2
 PIC_DEP_RHO_AND_J, PIC_DEP_RHO_ONLY = 0, 1
+PIC_SPECTRAL_CENTERING = 1 << 0
 
 
 class pic_params(Structure):
@@ -246,22 +247,22 @@ class Fields:
         return f
 
 
-def make_params(shape, spacing, dt, shape_order, center_order, psatd_order, dtype):
+def make_params(shape, spacing, dt, shape_order, center_order, psatd_order, dtype, flags=0):
     p = pic_params()
     p.nx, p.ny, p.nz = shape
     p.dx, p.dy, p.dz = spacing
     p.dt = dt
     p.shape_order, p.center_order, p.psatd_order = shape_order, center_order, psatd_order
     p.dtype = PIC_F32 if dtype == "f32" else PIC_F64
-    p.flags = 0
+    p.flags = flags
     return p
 
 
 class Context:
     """Owns a pic_ctx for one workload; thin convenience over the C ABI."""
 
-    def __init__(self, shape, spacing, dt, shape_order, center_order, psatd_order, dtype, stream=None):
-        self.params = make_params(shape, spacing, dt, shape_order, center_order, psatd_order, dtype)
+    def __init__(self, shape, spacing, dt, shape_order, center_order, psatd_order, dtype, stream=None, flags=0):
+        self.params = make_params(shape, spacing, dt, shape_order, center_order, psatd_order, dtype, flags)
         self.shape, self.spacing, self.dt, self.dtype = tuple(shape), tuple(spacing), dt, dtype
         self.ctx = pic_init(self.params, stream)
 

@@ -97,3 +97,32 @@ def test_laser128_fp32_one_step():
     assert periodic_pos_err(g_pos, osp["pos"][oi], p.lengths) <= 1e-5
     assert np.max(np.abs(g_u - osp["u"][oi])) <= 1e-5 * (1 + np.max(np.abs(osp["u"])))
     ctx.close()
+
+
+def test_laser128_fp32_spectral_centering_two_steps():
+    banner("full size laser128 FP32, spectral centering, 2 steps in one call")
+    wl = inputs.config("laser128")
+    distinct_weights(wl)
+    ctx = piclib.Context.for_workload(wl, flags=piclib.PIC_SPECTRAL_CENTERING)
+    f = ctx.fields_from_workload(wl)
+    el = piclib.Species.from_host(wl.electrons, wl.shape, wl.dtype)
+    ions = piclib.Species.from_host(wl.ions, wl.shape, wl.dtype)
+    ctx.init_charge(f, el, ions)
+    p = ostep.Params(wl.shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order)
+    osp = oracle_species(el, wl.shape, wl.spacing)
+    oion = oracle_species(ions, wl.shape, wl.spacing)
+    rho_static = ostep.deposit_rho([oion], p)
+    state = {"E_stag": rounded(wl.E, wl.dtype), "B_stag": rounded(wl.B, wl.dtype),
+             "rho_old": ostep.deposit_rho([osp], p, rho_static)}
+    piclib.pic_step(ctx.ctx, f, [el], 2)
+    piclib.pic_sync(ctx.ctx)
+    for _ in range(2):
+        ostep.step(state, [osp], p, rho_static)
+    for d in range(3):
+        assert max_rel(np64(f.E_stag[d]), state["E_stag"][d]) <= 4e-5, ("E", d)
+        assert max_rel(np64(f.B_stag[d]), state["B_stag"][d]) <= 4e-5, ("B", d)
+    g_w = np64(el.w)
+    gi, oi = np.argsort(g_w), np.argsort(osp["w"])
+    g_pos = el.positions(wl.shape, wl.spacing)[gi]
+    assert periodic_pos_err(g_pos, osp["pos"][oi], p.lengths) <= 2e-5
+    ctx.close()

@@ -187,18 +187,20 @@ def test_deposit_rho_only_and_static():
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("shape_order,shape,u_th,nsteps", [(1, (16, 12, 24), 0.1, 3), (3, (16, 12, 24), 0.1, 3),
-                                                           (3, (8, 16, 24), 0.4, 4)])
-def test_step_parity_small(dtype, shape_order, shape, u_th, nsteps):
+@pytest.mark.parametrize("shape_order,shape,u_th,nsteps,flags", [
+    (1, (16, 12, 24), 0.1, 3, 0), (3, (16, 12, 24), 0.1, 3, 0), (3, (8, 16, 24), 0.4, 4, 0),
+    (1, (16, 12, 24), 0.1, 3, piclib.PIC_SPECTRAL_CENTERING), (3, (8, 16, 24), 0.4, 4, piclib.PIC_SPECTRAL_CENTERING)])
+def test_step_parity_small(dtype, shape_order, shape, u_th, nsteps, flags):
     """Full hybrid cycles on small workloads: several deposition tiles, a radix-3 axis, partial
     tiles, axes of one and two tiles (periodic neighbours that coincide) and, with the hotter
-    plasma, many particles changing tile between steps."""
-    banner(f"pic_step small dtype={dtype} shape_order={shape_order} shape={shape} u_th={u_th}")
+    plasma, many particles changing tile between steps.  With PIC_SPECTRAL_CENTERING the
+    centering is applied as its Fourier symbol and must still match the real-space oracle."""
+    banner(f"pic_step small dtype={dtype} shape_order={shape_order} shape={shape} u_th={u_th} flags={flags}")
     wl = inputs.small(shape, ppc=2, shape_order=shape_order, center_order=8, dtype=dtype, u_th=u_th,
                       field_amp=0.02, seed=51)
     # distinct weights double as particle identities (pic_step regroups particles by tile)
     wl.electrons.w = wl.electrons.w * (1.0 + 1e-3 * np.arange(wl.electrons.n) / wl.electrons.n)
-    ctx = piclib.Context.for_workload(wl)
+    ctx = piclib.Context.for_workload(wl, flags=flags)
     f = ctx.fields_from_workload(wl)
     el = piclib.Species.from_host(wl.electrons, shape, dtype)
     ions = piclib.Species.from_host(wl.ions, shape, dtype)
@@ -225,6 +227,51 @@ def test_step_parity_small(dtype, shape_order, shape, u_th, nsteps):
         g_u = np.stack([np64(x) for x in el.u], axis=1)[gi]
         assert periodic_pos_err(g_pos, osp["pos"][oi], p.lengths) <= (1e-11 if dtype == "f64" else 2e-5)
         assert np.max(np.abs(g_u - osp["u"][oi])) <= (1e-11 if dtype == "f64" else 2e-5)
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape_order", [1, 3])
+def test_spectral_centering_multi_step(dtype, shape_order):
+    """One pic_step call of several steps with PIC_SPECTRAL_CENTERING (nodal fields of the later
+    steps come from the fused update) against the real-space oracle: the staggered state, rho,
+    every particle, and the nodal fields of the final time level."""
+    banner(f"pic_step spectral centering, 4 steps in one call, dtype={dtype} shape_order={shape_order}")
+    shape, nsteps = (16, 12, 24), 4
+    wl = inputs.small(shape, ppc=2, shape_order=shape_order, center_order=8, dtype=dtype, u_th=0.3,
+                      field_amp=0.02, seed=53)
+    wl.electrons.w = wl.electrons.w * (1.0 + 1e-3 * np.arange(wl.electrons.n) / wl.electrons.n)
+    ctx = piclib.Context.for_workload(wl, flags=piclib.PIC_SPECTRAL_CENTERING)
+    f = ctx.fields_from_workload(wl)
+    el = piclib.Species.from_host(wl.electrons, shape, dtype)
+    ions = piclib.Species.from_host(wl.ions, shape, dtype)
+    ctx.init_charge(f, el, ions)
+    p = ostep.Params(shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order)
+    osp = oracle_species(el, shape, wl.spacing)
+    oion = oracle_species(ions, shape, wl.spacing)
+    rho_static = ostep.deposit_rho([oion], p)
+    state = {"E_stag": rounded(wl.E, dtype), "B_stag": rounded(wl.B, dtype),
+             "rho_old": ostep.deposit_rho([osp], p, rho_static)}
+    piclib.pic_step(ctx.ctx, f, [el], nsteps)
+    piclib.pic_sync(ctx.ctx)
+    for _ in range(nsteps):
+        out = ostep.step(state, [osp], p, rho_static)
+    tol = 1e-10 if dtype == "f64" else 2e-4
+    E_nod, B_nod = ostep.center_fields_s2n(state["E_stag"], state["B_stag"], p)
+    J_stag = ostep.center_current_n2s(out["J_nod"], p)
+    for d in range(3):
+        assert max_rel(np64(f.E_stag[d]), state["E_stag"][d]) <= tol, ("E", d)
+        assert max_rel(np64(f.B_stag[d]), state["B_stag"][d]) <= tol, ("B", d)
+        assert max_rel(np64(f.E_nod[d]), E_nod[d]) <= tol, ("E_nod", d)
+        assert max_rel(np64(f.B_nod[d]), B_nod[d]) <= tol, ("B_nod", d)
+        assert max_rel(np64(f.J_stag[d]), J_stag[d]) <= tol, ("J_stag", d)
+    assert max_rel(np64(f.rho_old), state["rho_old"]) <= tol
+    g_w = np64(el.w)
+    gi, oi = np.argsort(g_w), np.argsort(osp["w"])
+    g_pos = el.positions(shape, wl.spacing)[gi]
+    g_u = np.stack([np64(x) for x in el.u], axis=1)[gi]
+    assert periodic_pos_err(g_pos, osp["pos"][oi], p.lengths) <= (1e-11 if dtype == "f64" else 4e-5)
+    assert np.max(np.abs(g_u - osp["u"][oi])) <= (1e-11 if dtype == "f64" else 4e-5)
     ctx.close()
 
 

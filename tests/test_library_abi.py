@@ -74,8 +74,10 @@ def test_init_rejects_bad_params(kw, code):
 def test_init_rejects_flags_and_dtype():
     lib = piclib.load()
     p = good_params()
-    p.flags = 1
+    p.flags = 1 << 5  # an undefined bit (PIC_SPECTRAL_CENTERING is bit 0)
     ctx = ctypes.c_void_p()
+    assert lib.pic_init(ctypes.byref(p), None, ctypes.byref(ctx)) == piclib.PIC_EINVAL
+    p.flags = piclib.PIC_SPECTRAL_CENTERING | (1 << 1)
     assert lib.pic_init(ctypes.byref(p), None, ctypes.byref(ctx)) == piclib.PIC_EINVAL
     p = good_params()
     p.dtype = 7
