@@ -146,6 +146,9 @@ def main():
     ap.add_argument("--spectral-centering", action="store_true",
                     help="apply the finite-order centering as its Fourier symbol inside the per-mode update "
                          "(PIC_SPECTRAL_CENTERING; same results up to rounding, no real-space centering passes)")
+    ap.add_argument("--nodal-solver", action="store_true",
+                    help="the nodal comparison cycle (PIC_NODAL_SOLVER): fields on the nodes, centered [k]_c, "
+                         "no centering")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy a MIB-MiB float32 tensor 3 times (a plain copy kernel "
                          "of known size, the reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -164,7 +167,7 @@ def main():
     wl = inputs.config(args.config, dtype=args.dtype, center_order=args.center_order)
     print(f"[bench] workload {args.config} dtype={wl.dtype} cells={wl.cells} particles={wl.electrons.n}",
           file=sys.stderr, flush=True)
-    flags = 1 if args.spectral_centering else 0  # PIC_SPECTRAL_CENTERING
+    flags = (1 if args.spectral_centering else 0) | (2 if args.nodal_solver else 0)  # PIC_SPECTRAL_CENTERING, PIC_NODAL_SOLVER
     result = run_gpu(wl, args.config, args.steps, args.warmup, args.calibrate_copy, flags)
     if args.sweep_center_orders:
         for order in [int(x) for x in args.sweep_center_orders.split(",")]:
@@ -255,7 +258,7 @@ def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0):
         "data": "synthetic (seeded laser + plasma workload)",
         "config": {"workload": CONFIG_TEXT[config_name], "cells": N, "particles": Np,
                    "center_order": wl.center_order, "shape_order": wl.shape_order, "pass": "forward",
-                   "centering": "spectral" if flags & 1 else "real-space"},
+                   "centering": "none (nodal solver)" if flags & 2 else ("spectral" if flags & 1 else "real-space")},
         "cell_updates_per_s": N * K / T,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

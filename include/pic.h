@@ -64,7 +64,15 @@ enum {
    * the particles are as in the real-space cycle; E_nod, B_nod hold the centred fields of
    * the final time level (the real-space cycle leaves those of the last step's start).
    * pic_center and psatd_push_fields are unaffected. */
-  PIC_SPECTRAL_CENTERING = 1u << 0
+  PIC_SPECTRAL_CENTERING = 1u << 0,
+  /* Nodal comparison solver (Sec. 2, the standard nodal PSATD cycle the hybrid scheme is
+   * measured against): every field sits on the nodes, derivatives use the centered
+   * modified wave number [k]_c (Sec. 4.1 eq. centered_modified_wave_number) with no
+   * half-cell phase, and no centering is done.  The arrays named E_stag, B_stag then hold
+   * the NODAL state, which pic_gather_push inside pic_step reads directly; pic_step leaves
+   * E_nod, B_nod and J_stag untouched; psatd_push_fields reads J_stag as the nodal current.
+   * Excludes PIC_SPECTRAL_CENTERING. */
+  PIC_NODAL_SOLVER = 1u << 1
 };
 
 typedef struct {
@@ -75,7 +83,7 @@ typedef struct {
   int32_t center_order;   /* finite-order centering 2m, even, 2..32, with 2m <= min(nx,ny,nz) (Sec. 3) */
   int32_t psatd_order;    /* order 2m_p of the staggered modified wave number [k]_s, even 2..64; 0 = infinite */
   pic_dtype dtype;        /* precision of fields, particles, FFTs; tables are always built in FP64 */
-  uint32_t flags;         /* 0 or PIC_SPECTRAL_CENTERING; other bits are rejected */
+  uint32_t flags;         /* 0, PIC_SPECTRAL_CENTERING or PIC_NODAL_SOLVER; other bits are rejected */
 } pic_params;
 
 /* One particle species, structure of arrays, caller-owned device memory.
@@ -183,6 +191,34 @@ pic_status pic_profile(pic_ctx ctx, int enable);
 pic_status pic_stage_times(pic_ctx ctx, double* ms, int64_t* count, int nstage);
 const char* pic_stage_name(int s);
 int pic_num_stages(void);
+
+/* ---- Closed-form diagnostics of the discrete scheme: host functions in FP64, no context
+ * and no GPU needed.  Every output is a caller-owned HOST array.  On a bad argument they
+ * return PIC_EINVAL (text in pic_last_error(NULL)). */
+
+/* Modified wave numbers of an axis of n points and spacing d at finite-difference order
+ * `order` (even, 0..64; 0 = the exact k): out[i] for the DFT index i, whose signed
+ * frequency is f = i, or i - n for i > (n-1)/2 (even n: index n/2 is -n/2), k = 2 pi f/(n d).
+ * kind 0: staggered [k]_s (Sec. 4.1 eq. staggered_modified_wave_number, coefficients
+ * eq. eq_Fornberg_staggered); kind 1: centered [k]_c (eq. centered_modified_wave_number,
+ * eq. eq_Fornberg_centered).  The standard PSATD solver propagates vacuum waves at
+ * w = c |[k]| exactly (App. B eq. vacuum_disprel_psatd), so out[i] / k is the numerical
+ * phase velocity over c along the axis (Sec. 2, dispersion figure): n doubles. */
+pic_status pic_modified_wavenumber(int32_t n, double d, int32_t order, int32_t kind, double* out);
+
+/* Fourier factor of the finite-order centering of order center_order = 2m (even, 2..64)
+ * along an axis of n points (App. C): zeta(k) = sum_n alpha^s_{m,n} cos(k (n - 1/2) d), at
+ * the DFT indices as above (k d = 2 pi f / n, so d drops out).  Its deviation from 1 is what
+ * governs the mitigation of the numerical Cherenkov instability (App. C): n doubles. */
+pic_status pic_centering_factor(int32_t n, int32_t center_order, double* out);
+
+/* Stencil extent (Sec. 2 item (ii), eq. eq_stencil_extent) along `axis` (0, 1, 2) of one
+ * standard PSATD coefficient, coefficient 0 = C, 1 = S/w, 2 = X1, 3 = X2, 4 = X3, for the
+ * grid, cell sizes, dt and psatd_order of *p, with [k]_s, or [k]_c when p->flags has
+ * PIC_NODAL_SOLVER:  Gamma(x_j) = | (1/(N_b N_c)) sum_{k_b, k_c} [F^-1_axis g](x_j, k_b, k_c) |
+ * for j = 0 .. n_axis - 1 (cells from the origin; j > n/2 is the distance n - j on the
+ * other side): n_axis doubles.  Costs one coefficient evaluation per mode of the grid. */
+pic_status pic_stencil_extent(const pic_params* p, int32_t axis, int32_t coefficient, double* out);
 
 /* Text of the last error of ctx (or of the last failed pic_init when ctx is NULL). */
 const char* pic_last_error(pic_ctx ctx);

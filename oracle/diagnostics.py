@@ -6,7 +6,9 @@ Test infrastructure only (see ``oracle/__init__``).
 * relative L2 error ||F_n - F_h|| / ||F_n||  (Sec. 5.2, eq. ``L2_norm_error``);
 * total charge sum_i rho_i dV;
 * Gauss residual || [k]_s . E_hat + i rho_hat / eps0 || / || rho_hat / eps0 ||
-  (App. A, Gauss's law used in the derivation of the update).
+  (App. A, Gauss's law used in the derivation of the update);
+* stencil extent Gamma of a PSATD coefficient along an axis (Sec. 2 item (ii),
+  eq. ``eq_stencil_extent``).
 """
 
 import numpy as np
@@ -46,3 +48,14 @@ def gauss_residual(E_stag, rho, spacing, psatd_order):
     den = np.sqrt(np.sum(np.abs(rh / EPS0) ** 2))
     num = np.sqrt(np.sum(np.abs(res) ** 2))
     return float(num / den) if den > 0 else float(num)
+
+
+def stencil_extent(shape, spacing, dt, psatd_order, axis, coefficient, nodal=False):
+    """Sec. 2 item (ii), eq. eq_stencil_extent: Gamma(x) = |(1/(N_b N_c)) sum_{k_b,k_c} F^-1_axis[g]|
+    for the standard PSATD coefficient ``coefficient`` (one of "C", "S_over_w", "X1", "X2", "X3")
+    with [k]_s, or [k]_c for the nodal solver; x = 0 .. n_axis - 1 cells."""
+    from . import psatd
+    ks = (psatd.centered_wave_vector if nodal else psatd.staggered_wave_vector)(shape, spacing, psatd_order)
+    g = np.broadcast_to(psatd.coefficients(ks, dt)[coefficient], shape)
+    others = tuple(a for a in range(3) if a != axis)
+    return np.abs(np.fft.ifft(g, axis=axis).mean(axis=others))

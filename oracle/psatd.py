@@ -24,7 +24,7 @@ from math import factorial
 
 import numpy as np
 
-from .fornberg import k_staggered
+from .fornberg import k_centered, k_staggered
 from .transforms import wave_vectors
 
 C_LIGHT = 1.0
@@ -37,6 +37,13 @@ def staggered_wave_vector(shape, spacing, order):
     kx, ky, kz = wave_vectors(shape, spacing)
     dx, dy, dz = spacing
     return (k_staggered(kx, dx, order), k_staggered(ky, dy, order), k_staggered(kz, dz, order))
+
+
+def centered_wave_vector(shape, spacing, order):
+    """([k^x]_c, [k^y]_c, [k^z]_c): the nodal solver's centered modified wave numbers (Sec. 4.1)."""
+    kx, ky, kz = wave_vectors(shape, spacing)
+    dx, dy, dz = spacing
+    return (k_centered(kx, dx, order), k_centered(ky, dy, order), k_centered(kz, dz, order))
 
 
 def _series(x2, coef):

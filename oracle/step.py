@@ -15,6 +15,10 @@ rho^n on the nodes) and runs, in this order:
   5. standard PSATD update of (E, B) in the paper's Fourier convention;
   6. back to real space; rho^n <- rho^{n+1}.
 Immobile species (m = inf) are never pushed and deposit rho only.
+
+With ``Params.nodal`` the same function runs the standard nodal PSATD cycle the paper
+compares against (Sec. 2, first cycle figure; Sec. 4.1 [k]_c): every field on the nodes,
+no centering, the update with the centered modified wave numbers.
 """
 
 from dataclasses import dataclass
@@ -33,6 +37,7 @@ class Params:
     shape_order: int = 1    # 1 = CIC, 3 = cubic B-spline
     center_order: int = 8   # 2 m_c
     psatd_order: int = 16   # 2 m_p for [k]_s; 0 = infinite
+    nodal: bool = False     # the nodal comparison cycle: every field on the nodes, [k]_c, no centering
 
     @property
     def lengths(self):
@@ -40,6 +45,8 @@ class Params:
 
 
 def center_fields_s2n(E_stag, B_stag, p):
+    if p.nodal:  # nodal cycle: the state is already nodal
+        return [np.array(a) for a in E_stag], [np.array(a) for a in B_stag]
     m = p.center_order // 2
     E_nod = [centering.s2n(E_NAMES[d], E_stag[d], m) for d in range(3)]
     B_nod = [centering.s2n(B_NAMES[d], B_stag[d], m) for d in range(3)]
@@ -47,6 +54,8 @@ def center_fields_s2n(E_stag, B_stag, p):
 
 
 def center_current_n2s(J_nod, p):
+    if p.nodal:
+        return [np.array(a) for a in J_nod]
     m = p.center_order // 2
     return [centering.n2s(J_NAMES[d], J_nod[d], m) for d in range(3)]
 
@@ -79,18 +88,26 @@ def deposit_current(sp, v, pos_half, p):
 
 
 def push_fields(E_stag, B_stag, J_stag, rho_old, rho_new, p):
-    """Standard PSATD update of the Yee-grid fields from time n to n+1 (Sec. 4.2)."""
-    ks = psatd.staggered_wave_vector(p.shape, p.spacing, p.psatd_order)
+    """Standard PSATD update of the Yee-grid fields from time n to n+1 (Sec. 4.2).
+
+    Nodal cycle (p.nodal): the same equations with the centered [k]_c, every component
+    transformed at the nodes (zero offsets)."""
+    if p.nodal:
+        ks = psatd.centered_wave_vector(p.shape, p.spacing, p.psatd_order)
+        offsets = {name: (0.0, 0.0, 0.0) for name in OFFSETS}
+    else:
+        ks = psatd.staggered_wave_vector(p.shape, p.spacing, p.psatd_order)
+        offsets = OFFSETS
     coef = psatd.coefficients(ks, p.dt)
-    fw = lambda f, name: transforms.forward(f, p.spacing, OFFSETS[name])
+    fw = lambda f, name: transforms.forward(f, p.spacing, offsets[name])
     Eh = [fw(E_stag[d], E_NAMES[d]) for d in range(3)]
     Bh = [fw(B_stag[d], B_NAMES[d]) for d in range(3)]
     Jh = [fw(J_stag[d], J_NAMES[d]) for d in range(3)]
     rho_old_h = fw(rho_old, "rho")
     rho_new_h = fw(rho_new, "rho")
     E_new, B_new = psatd.update(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, coef)
-    E_out = [transforms.inverse(E_new[d], p.spacing, OFFSETS[E_NAMES[d]]) for d in range(3)]
-    B_out = [transforms.inverse(B_new[d], p.spacing, OFFSETS[B_NAMES[d]]) for d in range(3)]
+    E_out = [transforms.inverse(E_new[d], p.spacing, offsets[E_NAMES[d]]) for d in range(3)]
+    B_out = [transforms.inverse(B_new[d], p.spacing, offsets[B_NAMES[d]]) for d in range(3)]
     return E_out, B_out
 
 

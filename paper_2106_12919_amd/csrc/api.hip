@@ -217,19 +217,28 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
   alpha_staggered(m, calpha.data());
   for (double& v : calpha) v *= 0.5;
   // per-axis [k]_s and the staggered phase operators D+- = i [k]_s exp(+-i k d / 2)
+  // (nodal solver: the centered [k]_c and D+- = i [k]_c, no half-cell phase)
+  const bool nodal = (p.flags & PIC_NODAL_SOLVER) != 0;
   std::vector<double> ks[3];
   for (int a = 0; a < 3; ++a) {
     ks[a].resize(n[a]);
-    k_staggered_axis(n[a], d[a], p.psatd_order, ks[a].data());
+    if (nodal)
+      k_centered_axis(n[a], d[a], p.psatd_order, ks[a].data());
+    else
+      k_staggered_axis(n[a], d[a], p.psatd_order, ks[a].data());
     const int len = (a == 2) ? nzh : n[a];
     std::vector<cplx<T>> dp(len), dm(len);
     const double two_pi = 6.283185307179586476925286766559;
     for (int i = 0; i < len; ++i) {
       const int f = (i <= (n[a] - 1) / 2) ? i : i - n[a];
       const double k = two_pi * f / (n[a] * d[a]);
-      const double sh = std::sin(0.5 * k * d[a]), ch = std::cos(0.5 * k * d[a]);
-      dp[i] = cmake((T)(-ks[a][i] * sh), (T)(ks[a][i] * ch));
-      dm[i] = cmake((T)(ks[a][i] * sh), (T)(ks[a][i] * ch));
+      const double sh = nodal ? 0.0 : std::sin(0.5 * k * d[a]), ch = nodal ? 1.0 : std::cos(0.5 * k * d[a]);
+      // Nodal solver, Nyquist index of an even axis: the odd operator i [k]_c has no
+      // real-valued action on that self-conjugate mode (finite orders give [k]_c = 0
+      // there anyway; at infinite order the derivative is dropped, omega keeps |k|).
+      const double kd = (nodal && 2 * i == n[a]) ? 0.0 : ks[a][i];
+      dp[i] = cmake((T)(-kd * sh), (T)(kd * ch));
+      dm[i] = cmake((T)(kd * sh), (T)(kd * ch));
     }
     if ((err = e.upload(&e.tab.Dp[a], dp)) != hipSuccess) return err;
     if ((err = e.upload(&e.tab.Dm[a], dm)) != hipSuccess) return err;
@@ -315,7 +324,14 @@ pic_status validate_params(const pic_params* p, std::string& msg) {
     return PIC_EUNSUPPORTED;
   }
   if (p->dtype != PIC_F32 && p->dtype != PIC_F64) { msg = "dtype must be PIC_F32 or PIC_F64"; return PIC_EINVAL; }
-  if (p->flags & ~(uint32_t)PIC_SPECTRAL_CENTERING) { msg = "unknown bit in flags"; return PIC_EINVAL; }
+  if (p->flags & ~(uint32_t)(PIC_SPECTRAL_CENTERING | PIC_NODAL_SOLVER)) {
+    msg = "unknown bit in flags";
+    return PIC_EINVAL;
+  }
+  if ((p->flags & PIC_SPECTRAL_CENTERING) && (p->flags & PIC_NODAL_SOLVER)) {
+    msg = "PIC_SPECTRAL_CENTERING and PIC_NODAL_SOLVER exclude each other (the nodal solver has no centering)";
+    return PIC_EINVAL;
+  }
   return PIC_OK;
 }
 
@@ -593,8 +609,14 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
     forward_batch<T>(c, e, src, dst, 7);
   }
   const GridGeom g = geom(p);
+  const bool nodal = (p.flags & PIC_NODAL_SOLVER) != 0;
   const T *Enod[3], *Bnod[3];
   EB_nod<T>(f, Enod, Bnod);
+  if (nodal)  // nodal solver: the state itself is nodal, gathered directly
+    for (int d = 0; d < 3; ++d) {
+      Enod[d] = static_cast<const T*>(f->E_stag[d]);
+      Bnod[d] = static_cast<const T*>(f->B_stag[d]);
+    }
   T* Jn[3];
   J_ptrs<T>(f, Jn);
   std::vector<char> in_scratch(nsp, 0);
@@ -606,7 +628,7 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
   pic_status st;
   const bool spectral = (p.flags & PIC_SPECTRAL_CENTERING) != 0;
   for (int n = 0; n < nsteps; ++n) {
-    if (!spectral || n == 0) {  // spectral centering: later steps get E_nod, B_nod from the update
+    if (!nodal && (!spectral || n == 0)) {  // spectral centering: later steps get E_nod, B_nod from the update
       StageScope sc(c, ST_S2N);
       if ((st = do_center<T>(c, PIC_S2N, PIC_E, f)) != PIC_OK) return st;
       if ((st = do_center<T>(c, PIC_S2N, PIC_B, f)) != PIC_OK) return st;
@@ -664,13 +686,14 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
       // layout index of the grouping the particles are now in
       if (mobile) layout[q] = first ? 0 : 1 - L;
     }
-    if (!spectral) {
+    if (!spectral && !nodal) {
       StageScope sc(c, ST_N2S);
       if ((st = do_center<T>(c, PIC_N2S, PIC_J, f)) != PIC_OK) return st;
     }
     {
       StageScope sc(c, ST_FFT_FWD);
-      void* const* J = spectral ? f->J_nod : f->J_stag;  // spectral centering: the update centres J
+      // spectral centering: the update centres J; nodal solver: J stays on the nodes
+      void* const* J = (spectral || nodal) ? f->J_nod : f->J_stag;
       const T* src[4] = {static_cast<const T*>(J[0]), static_cast<const T*>(J[1]), static_cast<const T*>(J[2]),
                          static_cast<const T*>(f->rho_new)};
       cplx<T>* dst[4] = {e.Jh[0], e.Jh[1], e.Jh[2], e.rh[1 - slot]};
@@ -911,6 +934,89 @@ const char* pic_stage_name(int s) { return (s >= 0 && s < kNumStages) ? kStageNa
 int pic_num_stages(void) { return kNumStages; }
 
 const char* pic_last_error(pic_ctx ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
+
+// ------------------------------------------------------------------ closed-form diagnostics (host)
+
+pic_status pic_modified_wavenumber(int32_t n, double d, int32_t order, int32_t kind, double* out) {
+  if (!out || n < 2 || !(d > 0) || order < 0 || order > 64 || order % 2 || (kind != 0 && kind != 1)) {
+    g_init_error = "pic_modified_wavenumber: need n >= 2, d > 0, order even in [0, 64], kind 0 or 1, out";
+    return PIC_EINVAL;
+  }
+  if (kind == 0)
+    k_staggered_axis(n, d, order, out);
+  else
+    k_centered_axis(n, d, order, out);
+  return PIC_OK;
+}
+
+pic_status pic_centering_factor(int32_t n, int32_t center_order, double* out) {
+  if (!out || n < 2 || center_order < 2 || center_order > 64 || center_order % 2) {
+    g_init_error = "pic_centering_factor: need n >= 2, center_order even in [2, 64], out";
+    return PIC_EINVAL;
+  }
+  const int m = center_order / 2;
+  std::vector<double> a(m);
+  alpha_staggered(m, a.data());
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int i = 0; i < n; ++i) {
+    const int f = (i <= (n - 1) / 2) ? i : i - n;
+    const double kd = two_pi * f / n;
+    long double z = 0.0L;
+    for (int q = 1; q <= m; ++q) z += (long double)a[q - 1] * std::cos(kd * (q - 0.5));
+    out[i] = (double)z;
+  }
+  return PIC_OK;
+}
+
+pic_status pic_stencil_extent(const pic_params* p, int32_t axis, int32_t coefficient, double* out) {
+  std::string msg;
+  pic_status st = validate_params(p, msg);
+  if (st != PIC_OK) {
+    g_init_error = "pic_stencil_extent: " + msg;
+    return st;
+  }
+  if (!out || axis < 0 || axis > 2 || coefficient < 0 || coefficient > 4) {
+    g_init_error = "pic_stencil_extent: need axis in 0..2, coefficient in 0..4 (C, S/w, X1, X2, X3), out";
+    return PIC_EINVAL;
+  }
+  const int n[3] = {p->nx, p->ny, p->nz};
+  const double d[3] = {p->dx, p->dy, p->dz};
+  const bool nodal = (p->flags & PIC_NODAL_SOLVER) != 0;
+  std::vector<double> ks[3];
+  for (int a = 0; a < 3; ++a) {
+    ks[a].resize(n[a]);
+    if (nodal)
+      k_centered_axis(n[a], d[a], p->psatd_order, ks[a].data());
+    else
+      k_staggered_axis(n[a], d[a], p->psatd_order, ks[a].data());
+  }
+  // g averaged over the two other axes (full spectrum), per index along ``axis``
+  const int b = (axis + 1) % 3, c = (axis + 2) % 3;
+  std::vector<double> gavg(n[axis], 0.0);
+  for (int i = 0; i < n[axis]; ++i) {
+    long double acc = 0.0L;
+    for (int j = 0; j < n[b]; ++j)
+      for (int k = 0; k < n[c]; ++k) {
+        const double w = std::sqrt(ks[axis][i] * ks[axis][i] + ks[b][j] * ks[b][j] + ks[c][k] * ks[c][k]);
+        double v[5];
+        psatd_coefficients(w, p->dt, &v[0], &v[1], &v[2], &v[3], &v[4]);
+        acc += v[coefficient];
+      }
+    gavg[i] = (double)(acc / ((long double)n[b] * n[c]));
+  }
+  // inverse DFT along ``axis``: Gamma(x_j) = | (1/n) sum_i g(k_i) exp(+i k_i x_j) |
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int j = 0; j < n[axis]; ++j) {
+    long double re = 0.0L, im = 0.0L;
+    for (int i = 0; i < n[axis]; ++i) {
+      const double ph = two_pi * (double)(((long long)i * j) % n[axis]) / n[axis];
+      re += gavg[i] * std::cos(ph);
+      im += gavg[i] * std::sin(ph);
+    }
+    out[j] = (double)(std::sqrt(re * re + im * im) / n[axis]);
+  }
+  return PIC_OK;
+}
 
 const char* pic_strerror(pic_status s) {
   switch (s) {

@@ -62,6 +62,8 @@ struct Batch {
 // Host FP64 tables (tables.cpp).
 void alpha_staggered(int m, double* out);                  // out[n-1], n = 1..m
 void k_staggered_axis(int n, double d, int order, double* out);  // [k]_s on fftfreq order
+void alpha_centered(int m, double* out);                   // out[n-1], n = 1..m
+void k_centered_axis(int n, double d, int order, double* out);   // [k]_c on fftfreq order
 void psatd_coefficients(double w, double dt, double* C, double* S_over_w, double* X1, double* X2, double* X3);
 
 }  // namespace pic

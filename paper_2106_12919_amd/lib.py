@@ -23,6 +23,7 @@ PIC_N2S, PIC_S2N = 0, 1
 PIC_J, PIC_E, PIC_B = 0, 1, 2
 PIC_DEP_RHO_AND_J, PIC_DEP_RHO_ONLY = 0, 1
 PIC_SPECTRAL_CENTERING = 1 << 0
+PIC_NODAL_SOLVER = 1 << 1
 
 
 class pic_params(Structure):
@@ -74,6 +75,10 @@ def load():
         "pic_num_stages": (c_int, []),
         "pic_last_error": (c_char_p, [c_void_p]),
         "pic_strerror": (c_char_p, [c_int]),
+        "pic_modified_wavenumber": (c_int, [ctypes.c_int32, c_double, ctypes.c_int32, ctypes.c_int32,
+                                            POINTER(c_double)]),
+        "pic_centering_factor": (c_int, [ctypes.c_int32, ctypes.c_int32, POINTER(c_double)]),
+        "pic_stencil_extent": (c_int, [POINTER(pic_params), ctypes.c_int32, ctypes.c_int32, POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -167,6 +172,28 @@ def pic_stage_times(ctx):
     cnt = (c_int64 * n)()
     _check(lib.pic_stage_times(ctx, ms, cnt, n), ctx)
     return {lib.pic_stage_name(i).decode(): (float(ms[i]), int(cnt[i])) for i in range(n)}
+
+
+def pic_modified_wavenumber(n, d, order, kind):
+    """[k]_s (kind 0) or [k]_c (kind 1) at the DFT indices of an n-point axis (host, FP64)."""
+    out = (c_double * n)()
+    _check(load().pic_modified_wavenumber(n, d, order, kind, out))
+    return [float(x) for x in out]
+
+
+def pic_centering_factor(n, center_order):
+    """zeta(k) of the centering of order center_order at the DFT indices of an n-point axis (host, FP64)."""
+    out = (c_double * n)()
+    _check(load().pic_centering_factor(n, center_order, out))
+    return [float(x) for x in out]
+
+
+def pic_stencil_extent(params, axis, coefficient):
+    """Gamma(x_j), j = 0..n_axis-1, of PSATD coefficient (0 C, 1 S/w, 2 X1, 3 X2, 4 X3) along axis."""
+    n = (params.nx, params.ny, params.nz)[axis]
+    out = (c_double * n)()
+    _check(load().pic_stencil_extent(ctypes.byref(params), axis, coefficient, out))
+    return [float(x) for x in out]
 
 
 # ------------------------------------------------------------------ tensor containers

@@ -107,6 +107,31 @@ def test_psatd_push_fields_parity(dtype, shape, psatd_order):
     ctx.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(16, 24, 32), (12, 8, 48)])
+@pytest.mark.parametrize("psatd_order", [16, 0])
+def test_psatd_push_fields_nodal_solver_parity(dtype, shape, psatd_order):
+    """PIC_NODAL_SOLVER: the update with the centered [k]_c on nodal arrays."""
+    banner(f"psatd_push_fields nodal solver dtype={dtype} shape={shape} order={psatd_order}")
+    dt = 0.5
+    p = ostep.Params(shape, (1.0, 1.0, 1.0), dt, 1, 8, psatd_order, nodal=True)
+    ctx = piclib.Context(shape, (1.0, 1.0, 1.0), dt, 1, 8, psatd_order, dtype, flags=piclib.PIC_NODAL_SOLVER)
+    f = piclib.Fields(shape, dtype)
+    src = rounded(inputs.random_grid(shape, seed=9, count=11), dtype)
+    put(f.E_stag, src[0:3])
+    put(f.B_stag, src[3:6])
+    put(f.J_stag, src[6:9])
+    put([f.rho_old, f.rho_new], src[9:11])
+    piclib.psatd_push_fields(ctx.ctx, f)
+    piclib.pic_sync(ctx.ctx)
+    E_ref, B_ref = ostep.push_fields(src[0:3], src[3:6], src[6:9], src[9], src[10], p)
+    tol = fft_tol(dtype, shape)
+    for d in range(3):
+        assert max_rel(np64(f.E_stag[d]), E_ref[d]) <= tol, (d, max_rel(np64(f.E_stag[d]), E_ref[d]))
+        assert max_rel(np64(f.B_stag[d]), B_ref[d]) <= tol, (d, max_rel(np64(f.B_stag[d]), B_ref[d]))
+    ctx.close()
+
+
 def push_tols(dtype):
     # FP32: ~100 rounding steps on O(1)-conditioned quantities (64 gathered terms, Boris)
     return (1e-12, 1e-12) if dtype == "f64" else (3e-6, 3e-6)
@@ -189,12 +214,14 @@ def test_deposit_rho_only_and_static():
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("shape_order,shape,u_th,nsteps,flags", [
     (1, (16, 12, 24), 0.1, 3, 0), (3, (16, 12, 24), 0.1, 3, 0), (3, (8, 16, 24), 0.4, 4, 0),
-    (1, (16, 12, 24), 0.1, 3, piclib.PIC_SPECTRAL_CENTERING), (3, (8, 16, 24), 0.4, 4, piclib.PIC_SPECTRAL_CENTERING)])
+    (1, (16, 12, 24), 0.1, 3, piclib.PIC_SPECTRAL_CENTERING), (3, (8, 16, 24), 0.4, 4, piclib.PIC_SPECTRAL_CENTERING),
+    (1, (16, 12, 24), 0.1, 3, piclib.PIC_NODAL_SOLVER), (3, (8, 16, 24), 0.4, 3, piclib.PIC_NODAL_SOLVER)])
 def test_step_parity_small(dtype, shape_order, shape, u_th, nsteps, flags):
     """Full hybrid cycles on small workloads: several deposition tiles, a radix-3 axis, partial
     tiles, axes of one and two tiles (periodic neighbours that coincide) and, with the hotter
     plasma, many particles changing tile between steps.  With PIC_SPECTRAL_CENTERING the
-    centering is applied as its Fourier symbol and must still match the real-space oracle."""
+    centering is applied as its Fourier symbol and must still match the real-space oracle; with
+    PIC_NODAL_SOLVER the nodal comparison cycle must match the oracle's nodal cycle."""
     banner(f"pic_step small dtype={dtype} shape_order={shape_order} shape={shape} u_th={u_th} flags={flags}")
     wl = inputs.small(shape, ppc=2, shape_order=shape_order, center_order=8, dtype=dtype, u_th=u_th,
                       field_amp=0.02, seed=51)
@@ -205,7 +232,8 @@ def test_step_parity_small(dtype, shape_order, shape, u_th, nsteps, flags):
     el = piclib.Species.from_host(wl.electrons, shape, dtype)
     ions = piclib.Species.from_host(wl.ions, shape, dtype)
     ctx.init_charge(f, el, ions)
-    p = ostep.Params(shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order)
+    p = ostep.Params(shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order,
+                     nodal=bool(flags & piclib.PIC_NODAL_SOLVER))
     osp = oracle_species(el, shape, wl.spacing)
     oion = oracle_species(ions, shape, wl.spacing)
     rho_static = ostep.deposit_rho([oion], p)

@@ -1,0 +1,113 @@
+"""Closed-form diagnostics of the discrete scheme: the library's host functions against the
+oracle, and the oracle against what the paper states about them (Sec. 2 items (i)-(ii),
+Sec. 4.1, App. B, App. C).  CPU only."""
+
+import numpy as np
+import pytest
+
+from oracle import diagnostics, fornberg
+from oracle.step import Params, push_fields
+from paper_2106_12919_amd import lib as piclib
+
+COEFS = ["C", "S_over_w", "X1", "X2", "X3"]
+
+
+@pytest.mark.parametrize("n,d", [(16, 1.0), (24, 0.5), (30, 2.0)])
+@pytest.mark.parametrize("order", [0, 2, 8, 16, 64])
+def test_modified_wavenumbers_match_oracle(n, d, order):
+    k = fornberg.k_axis(n, d)
+    ks = np.array(piclib.pic_modified_wavenumber(n, d, order, 0))
+    kc = np.array(piclib.pic_modified_wavenumber(n, d, order, 1))
+    np.testing.assert_allclose(ks, fornberg.k_staggered(k, d, order), rtol=1e-13, atol=1e-13 / d)
+    np.testing.assert_allclose(kc, fornberg.k_centered(k, d, order), rtol=1e-13, atol=1e-13 / d)
+
+
+@pytest.mark.parametrize("n", [16, 24, 31])
+@pytest.mark.parametrize("order", [2, 8, 16, 32])
+def test_centering_factor_matches_oracle(n, order):
+    z = np.array(piclib.pic_centering_factor(n, order))
+    np.testing.assert_allclose(z, fornberg.centering_transfer(fornberg.k_axis(n, 1.0), 1.0, order // 2),
+                               rtol=0, atol=1e-14)
+
+
+def test_diagnostics_reject_bad_arguments():
+    lib = piclib.load()
+    out = (piclib.c_double * 16)()
+    assert lib.pic_modified_wavenumber(16, 1.0, 3, 0, out) == piclib.PIC_EINVAL
+    assert lib.pic_modified_wavenumber(16, 1.0, 8, 2, out) == piclib.PIC_EINVAL
+    assert lib.pic_modified_wavenumber(16, -1.0, 8, 0, out) == piclib.PIC_EINVAL
+    assert lib.pic_centering_factor(16, 0, out) == piclib.PIC_EINVAL
+    assert lib.pic_centering_factor(16, 8, None) == piclib.PIC_EINVAL
+    p = piclib.make_params((16, 8, 8), (1.0, 1.0, 1.0), 0.5, 1, 8, 16, "f64")
+    assert lib.pic_stencil_extent(piclib.ctypes.byref(p), 3, 0, out) == piclib.PIC_EINVAL
+    assert lib.pic_stencil_extent(piclib.ctypes.byref(p), 0, 5, out) == piclib.PIC_EINVAL
+
+
+@pytest.mark.parametrize("nodal", [False, True])
+@pytest.mark.parametrize("order", [16, 0])
+def test_stencil_extent_matches_oracle(nodal, order):
+    shape, spacing, dt = (12, 8, 16), (1.0, 1.0, 1.0), 0.5
+    p = piclib.make_params(shape, spacing, dt, 1, 8, order, "f64",
+                           flags=piclib.PIC_NODAL_SOLVER if nodal else 0)
+    for axis in range(3):
+        for c, name in enumerate(COEFS):
+            lib_g = np.array(piclib.pic_stencil_extent(p, axis, c))
+            ref = diagnostics.stencil_extent(shape, spacing, dt, order, axis, name, nodal=nodal)
+            np.testing.assert_allclose(lib_g, ref, rtol=0, atol=1e-13 * max(1.0, np.max(ref)))
+
+
+def test_stencil_extent_tends_to_a_delta_as_dt_vanishes():
+    # C = cos(w dt) -> 1 for every mode: the stencil of the identity is one node
+    g = diagnostics.stencil_extent((8, 8, 32), (1.0, 1.0, 1.0), 1e-4, 16, 2, "C")
+    assert abs(g[0] - 1.0) < 1e-7
+    assert np.max(g[1:]) < 1e-7
+
+
+def test_infinite_order_nodal_and_staggered_stencils_coincide():
+    # Sec. 2 item (ii): at infinite spectral order nodal and staggered solvers give the same stencil
+    for name in COEFS:
+        gs = diagnostics.stencil_extent((8, 8, 32), (1.0, 1.0, 1.0), 0.5, 0, 2, name, nodal=False)
+        gn = diagnostics.stencil_extent((8, 8, 32), (1.0, 1.0, 1.0), 0.5, 0, 2, name, nodal=True)
+        np.testing.assert_allclose(gs, gn, rtol=0, atol=1e-15)
+
+
+def test_staggered_stencil_is_more_local_than_nodal():
+    # Sec. 2 item (ii): at finite order the staggered stencil falls off within fewer cells
+    def extent(nodal, tol=1e-4):
+        g = diagnostics.stencil_extent((16, 16, 128), (1.0, 1.0, 1.0), 0.5, 16, 2, "C", nodal=nodal)
+        half = g[:64]
+        return int(np.max(np.nonzero(half > tol)[0]))
+    assert extent(False) < extent(True)
+
+
+def test_nodal_derivative_vanishes_at_nyquist():
+    # Sec. 2 item (i): the centered [k]_c is zero at the Nyquist wave number for every finite order
+    # (standing waves in the nodal solver), the staggered [k]_s is not
+    for order in (2, 4, 8, 16, 32):
+        assert abs(fornberg.k_centered(np.pi, 1.0, order)) < 1e-14
+        assert fornberg.k_staggered(np.pi, 1.0, order) > 1.0
+
+
+@pytest.mark.parametrize("order", [4, 16, 0])
+def test_nodal_vacuum_plane_wave_dispersion(order):
+    # App. B with the nodal solver's [k]_c: every component on the nodes, w = c |[k]_c|
+    shape, spacing, dt, nsteps = (16, 12, 4), (1.0, 1.0, 1.0), 1.3, 5
+    kx, ky = 2 * np.pi * 3 / 16, 2 * np.pi * 2 / 12
+    Kx, Ky = fornberg.k_centered(kx, 1.0, order), fornberg.k_centered(ky, 1.0, order)
+    w = np.hypot(Kx, Ky)
+    x = np.arange(shape[0])[:, None, None]
+    y = np.arange(shape[1])[None, :, None]
+
+    def state(t):
+        f = np.cos(kx * x + ky * y - w * t) * np.ones(shape)
+        return [np.zeros(shape), np.zeros(shape), f], [Ky / w * f, -Kx / w * f, np.zeros(shape)]
+
+    p = Params(shape, spacing, dt, 1, 2, order, nodal=True)
+    E, B = state(0.0)
+    zero = np.zeros(shape)
+    for _ in range(nsteps):
+        E, B = push_fields(E, B, [zero, zero, zero], zero, zero, p)
+    Eref, Bref = state(nsteps * dt)
+    for d in range(3):
+        np.testing.assert_allclose(E[d], Eref[d], atol=1e-12)
+        np.testing.assert_allclose(B[d], Bref[d], atol=1e-12)
