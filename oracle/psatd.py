@@ -70,7 +70,7 @@ def coefficients(ks, dt):
     ksx, ksy, ksz = np.broadcast_arrays(*ks)
     w = C_LIGHT * np.sqrt(ksx ** 2 + ksy ** 2 + ksz ** 2)
     x = w * dt
-    small = x < SERIES_BELOW
+    small = np.abs(x) < SERIES_BELOW  # |w dt|: the series serves a negative (time-reversed) dt too
     wsafe = np.where(small, 1.0, w)
     x2 = np.where(small, x * x, 0.0)
 
