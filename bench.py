@@ -149,6 +149,9 @@ def main():
     ap.add_argument("--nodal-solver", action="store_true",
                     help="the nodal comparison cycle (PIC_NODAL_SOLVER): fields on the nodes, centered [k]_c, "
                          "no centering")
+    ap.add_argument("--field-adjoint", action="store_true",
+                    help="also time psatd_push_fields and its reverse mode psatd_push_fields_adjoint "
+                         "(\"field_solve\" in the JSON line)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy a MIB-MiB float32 tensor 3 times (a plain copy kernel "
                          "of known size, the reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -169,6 +172,8 @@ def main():
           file=sys.stderr, flush=True)
     flags = (1 if args.spectral_centering else 0) | (2 if args.nodal_solver else 0)  # PIC_SPECTRAL_CENTERING, PIC_NODAL_SOLVER
     result = run_gpu(wl, args.config, args.steps, args.warmup, args.calibrate_copy, flags)
+    if args.field_adjoint:
+        result["field_solve"] = time_field_solve(wl, flags)
     if args.sweep_center_orders:
         for order in [int(x) for x in args.sweep_center_orders.split(",")]:
             wl.center_order = order
@@ -184,6 +189,31 @@ def main():
         print("[bench] timing the CPU oracle sample ...", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(wl, result["config"]["particles"])
     print(json.dumps(result))
+
+
+def time_field_solve(wl, flags, reps=20):
+    """Mean ms of one psatd_push_fields and of one psatd_push_fields_adjoint on the workload grid
+    (11 forward + 6 inverse transforms and the update; 6 forward + 11 inverse and the adjoint)."""
+    import torch
+
+    from paper_2106_12919_amd import lib as piclib
+
+    ctx = piclib.Context.for_workload(wl, flags=flags)
+    f = ctx.fields_from_workload(wl)
+    out = {}
+    for name, fn in (("forward_ms", piclib.psatd_push_fields), ("adjoint_ms", piclib.psatd_push_fields_adjoint)):
+        fn(ctx.ctx, f)
+        torch.cuda.synchronize()
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(reps):
+            fn(ctx.ctx, f)
+        t1.record()
+        torch.cuda.synchronize()
+        out[name] = round(t0.elapsed_time(t1) / reps, 4)
+    ctx.close()
+    out["adjoint_over_forward"] = round(out["adjoint_ms"] / out["forward_ms"], 3)
+    return out
 
 
 def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0):

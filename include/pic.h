@@ -145,7 +145,11 @@ pic_status pic_deposit(pic_ctx ctx, const pic_species* sp, int nsp, pic_fields* 
  *   dir = PIC_S2N, what = PIC_E : E_stag -> E_nod, E^d along axis d,
  *   dir = PIC_S2N, what = PIC_B : B_stag -> B_nod, B^d along the two other axes,
  *         f_j = sum_n alpha^s_{m,n} (f_{j+n-1/2} + f_{j-n+1/2}) / 2.
- * Other (dir, what) pairs return PIC_EINVAL. */
+ * The two directions are exact transposes of each other, so the remaining pairs give the
+ * adjoints (reverse mode) of the three above:
+ *   (PIC_S2N, PIC_J): J_stag -> J_nod, (PIC_N2S, PIC_E): E_nod -> E_stag,
+ *   (PIC_N2S, PIC_B): B_nod -> B_stag (the same two axes).
+ * Other values of dir or what return PIC_EINVAL. */
 pic_status pic_center(pic_ctx ctx, int dir, int what, pic_fields* f);
 
 /* Standard PSATD update on the staggered grid (Sec. 4.2, eqs.
@@ -155,6 +159,15 @@ pic_status pic_center(pic_ctx ctx, int dir, int what, pic_fields* f);
  * overwrites E_stag, B_stag with time n+1.  Uses 11 forward and 6 inverse
  * real 3D FFTs. */
 pic_status psatd_push_fields(pic_ctx ctx, pic_fields* f);
+
+/* Reverse mode of psatd_push_fields (the adjoint of a linear map, for differentiating a
+ * loss through the field solve): on entry E_stag, B_stag hold dL/dE^{n+1}, dL/dB^{n+1};
+ * on return E_stag, B_stag hold dL/dE^n, dL/dB^n and J_stag, rho_old, rho_new hold
+ * dL/dJ^{n+1/2}, dL/drho^n, dL/drho^{n+1} (overwritten).  Per mode it applies the
+ * conjugate transpose of the update of Sec. 4.2 (for a time-symmetric vacuum update this
+ * is the time-reversed update, App. B); the transforms pair as FFT^H = N IFFT.  Honours
+ * PIC_NODAL_SOLVER. */
+pic_status psatd_push_fields_adjoint(pic_ctx ctx, pic_fields* f);
 
 /* Gather E_nod, B_nod at x^n with the shape_order B-spline (one weight set for
  * all six nodal components) and advance every mobile species with the

@@ -410,6 +410,21 @@ pic_status do_center(pic_ctx c, int dir, int what, pic_fields* f) {
       center_axis<T>(static_cast<const T*>(f->B_stag[d]), e.tmp, p.nx, p.ny, p.nz, a0, -1, m, cf, c->stream);
       center_axis<T>(e.tmp, static_cast<T*>(f->B_nod[d]), p.nx, p.ny, p.nz, a1, -1, m, cf, c->stream);
     }
+  } else if (dir == PIC_S2N && what == PIC_J) {  // transpose of (N2S, J)
+    for (int d = 0; d < 3; ++d)
+      center_axis<T>(static_cast<const T*>(f->J_stag[d]), static_cast<T*>(f->J_nod[d]), p.nx, p.ny, p.nz, d, -1, m,
+                     cf, c->stream);
+  } else if (dir == PIC_N2S && what == PIC_E) {  // transpose of (S2N, E)
+    for (int d = 0; d < 3; ++d)
+      center_axis<T>(static_cast<const T*>(f->E_nod[d]), static_cast<T*>(f->E_stag[d]), p.nx, p.ny, p.nz, d, 0, m,
+                     cf, c->stream);
+  } else if (dir == PIC_N2S && what == PIC_B) {  // transpose of (S2N, B): the same two axes
+    for (int d = 0; d < 3; ++d) {
+      const int a0 = (d == 0) ? 1 : 0;
+      const int a1 = (d == 2) ? 1 : 2;
+      center_axis<T>(static_cast<const T*>(f->B_nod[d]), e.tmp, p.nx, p.ny, p.nz, a1, 0, m, cf, c->stream);
+      center_axis<T>(e.tmp, static_cast<T*>(f->B_stag[d]), p.nx, p.ny, p.nz, a0, 0, m, cf, c->stream);
+    }
   } else {
     return c->fail(PIC_EINVAL, "unsupported (dir, what) pair for pic_center");
   }
@@ -586,6 +601,58 @@ pic_status do_push_fields(pic_ctx c, pic_fields* f) {
   }
   update_and_inverse<T>(c, e, f, 0);
   return c->check("psatd_push_fields");
+}
+
+// Reverse mode of psatd_push_fields: E_stag, B_stag hold the adjoints of the fields at
+// n+1 and receive those at n; J_stag, rho_old, rho_new receive the adjoints of the sources.
+// The forward map is real-IFFT(M FFT(x)) with a Hermitian-consistent per-mode M, so its
+// transpose is the same pipeline with M^H (the 1/N and FFT scalings pair up).
+template <typename T>
+pic_status do_push_fields_adjoint(pic_ctx c, pic_fields* f) {
+  Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
+  const pic_params& p = c->p;
+  {
+    StageScope sc(c, ST_FFT_FWD);
+    const T* src[6];
+    cplx<T>* dst[6];
+    for (int d = 0; d < 3; ++d) {
+      src[d] = static_cast<const T*>(f->E_stag[d]);
+      dst[d] = e.Eh[d];
+      src[3 + d] = static_cast<const T*>(f->B_stag[d]);
+      dst[3 + d] = e.Bh[d];
+    }
+    forward_batch<T>(c, e, src, dst, 6);
+  }
+  {
+    StageScope sc(c, ST_UPDATE);
+    psatd_adjoint<T>(e.tab, e.Eh, e.Bh, e.Jh, e.rh[0], e.rh[1], p.nx, p.ny, e.fft.nzh, e.fft.pz, c->stream);
+  }
+  StageScope sc(c, ST_FFT_INV);
+  const T scale = (T)(1.0 / (double)ncells(p));
+  Batch<const cplx<T>*> in{};
+  Batch<cplx<T>*> scr{};
+  Batch<T*> out{};
+  for (int d = 0; d < 3; ++d) {
+    in.p[d] = e.Eh[d];
+    in.p[3 + d] = e.Bh[d];
+    out.p[d] = static_cast<T*>(f->E_stag[d]);
+    out.p[3 + d] = static_cast<T*>(f->B_stag[d]);
+  }
+  for (int i = 0; i < 6; ++i) scr.p[i] = e.scratch[i];
+  e.fft.inverse(in, scr, out, 6, scale, c->stream);
+  // the source adjoints, transformed in place in their own spectra
+  cplx<T>* srcs[5] = {e.Jh[0], e.Jh[1], e.Jh[2], e.rh[0], e.rh[1]};
+  void* dsts[5] = {f->J_stag[0], f->J_stag[1], f->J_stag[2], f->rho_old, f->rho_new};
+  Batch<const cplx<T>*> in2{};
+  Batch<cplx<T>*> scr2{};
+  Batch<T*> out2{};
+  for (int i = 0; i < 5; ++i) {
+    in2.p[i] = srcs[i];
+    scr2.p[i] = srcs[i];
+    out2.p[i] = static_cast<T*>(dsts[i]);
+  }
+  e.fft.inverse(in2, scr2, out2, 5, scale, c->stream);
+  return c->check("psatd_push_fields_adjoint");
 }
 
 template <typename T>
@@ -850,14 +917,14 @@ pic_status pic_center(pic_ctx ctx, int dir, int what, pic_fields* f) {
   pic_status st = device_ok(ctx);
   if (st != PIC_OK) return st;
   if (!f) return ctx->fail(PIC_EINVAL, "fields is NULL");
-  if (dir == PIC_N2S && what == PIC_J)
-    st = check_fields(ctx, f, false, false, false, false, true, true, false, false);
-  else if (dir == PIC_S2N && what == PIC_E)
-    st = check_fields(ctx, f, true, false, true, false, false, false, false, false);
-  else if (dir == PIC_S2N && what == PIC_B)
-    st = check_fields(ctx, f, false, true, false, true, false, false, false, false);
-  else
+  if ((dir != PIC_N2S && dir != PIC_S2N) || (what != PIC_J && what != PIC_E && what != PIC_B))
     return ctx->fail(PIC_EINVAL, "unsupported (dir, what) pair for pic_center");
+  if (what == PIC_J)
+    st = check_fields(ctx, f, false, false, false, false, true, true, false, false);
+  else if (what == PIC_E)
+    st = check_fields(ctx, f, true, false, true, false, false, false, false, false);
+  else
+    st = check_fields(ctx, f, false, true, false, true, false, false, false, false);
   if (st != PIC_OK) return st;
   return PIC_DISPATCH(ctx, do_center, dir, what, f);
 }
@@ -867,6 +934,13 @@ pic_status psatd_push_fields(pic_ctx ctx, pic_fields* f) {
   if (st != PIC_OK) return st;
   if ((st = check_fields(ctx, f, true, true, false, false, false, true, true, true)) != PIC_OK) return st;
   return PIC_DISPATCH(ctx, do_push_fields, f);
+}
+
+pic_status psatd_push_fields_adjoint(pic_ctx ctx, pic_fields* f) {
+  pic_status st = device_ok(ctx);
+  if (st != PIC_OK) return st;
+  if ((st = check_fields(ctx, f, true, true, false, false, false, true, true, true)) != PIC_OK) return st;
+  return PIC_DISPATCH(ctx, do_push_fields_adjoint, f);
 }
 
 pic_status pic_gather_push(pic_ctx ctx, const pic_fields* f, pic_species* sp, int nsp) {

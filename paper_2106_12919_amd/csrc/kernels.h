@@ -53,6 +53,12 @@ template <typename T>
 void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B[3], const cplx<T>* const J[3],
                   const cplx<T>* rho_old, const cplx<T>* rho_new, int nx, int ny, int nzh, int pz,
                   cplx<T>* const* nodal, hipStream_t s);
+// Conjugate transpose of the update per mode (reverse mode): E, B hold the adjoints of the
+// updated fields and receive those of the old fields; J, rho_old, rho_new receive the
+// adjoints of the sources.
+template <typename T>
+void psatd_adjoint(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B[3], cplx<T>* const J[3],
+                   cplx<T>* rho_old, cplx<T>* rho_new, int nx, int ny, int nzh, int pz, hipStream_t s);
 
 // ---------------------------------------------------------------- particles (particles.hip)
 // Division by a fixed divisor d (1 <= d < 2^31) as a multiply-high and a shift:

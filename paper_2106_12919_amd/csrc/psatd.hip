@@ -92,7 +92,66 @@ __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cp
   }
 }
 
+// Adjoint (conjugate transpose per mode) of the update above, for reverse-mode
+// differentiation.  F holds the adjoints of the updated E (0..2) and B (3..5) and is
+// overwritten with those of the old E, B; A receives the adjoints of J (0..2), rho^n (3)
+// and rho^{n+1} (4).  With a x v = A_a v, (A_a)^H w = -(conj a) x w, so
+//   lE = C lE' + Sw (conj D+ x lB'),   lB = C lB' - Sw (conj D- x lE'),
+//   lJ = -X1 (conj D+ x lB') - Sw lE',  lro = X3 conj D+ . lE',  lrn = -X2 conj D+ . lE'.
+template <typename T>
+__global__ void __launch_bounds__(256) k_psatd_adjoint(PsatdTables<T> t, Batch<cplx<T>*> F, Batch<cplx<T>*> A, int nx,
+                                                       int ny, int nzh, int pz) {
+  const long long total = (long long)nx * ny * nzh;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int kz = (int)(idx % nzh);
+  const long long r = idx / nzh;
+  const int j = (int)(r % ny);
+  const int i = (int)(r / ny);
+  const size_t a = (size_t)r * pz + kz;
+  const T C = t.C[idx], Sw = t.Sw[idx], X1 = t.X1[idx], X2 = t.X2[idx], X3 = t.X3[idx];
+  const cplx<T> px = cconj(t.Dp[0][i]), py = cconj(t.Dp[1][j]), pzd = cconj(t.Dp[2][kz]);
+  const cplx<T> mx = cconj(t.Dm[0][i]), my = cconj(t.Dm[1][j]), mz = cconj(t.Dm[2][kz]);
+  const cplx<T> ex = F.p[0][a], ey = F.p[1][a], ez = F.p[2][a];
+  const cplx<T> bx = F.p[3][a], by = F.p[4][a], bz = F.p[5][a];
+  // conj(D+) x lB' and conj(D-) x lE'
+  const cplx<T> pBx = csub(cmul(py, bz), cmul(pzd, by));
+  const cplx<T> pBy = csub(cmul(pzd, bx), cmul(px, bz));
+  const cplx<T> pBz = csub(cmul(px, by), cmul(py, bx));
+  const cplx<T> mEx = csub(cmul(my, ez), cmul(mz, ey));
+  const cplx<T> mEy = csub(cmul(mz, ex), cmul(mx, ez));
+  const cplx<T> mEz = csub(cmul(mx, ey), cmul(my, ex));
+  const cplx<T> dE = cadd(cadd(cmul(px, ex), cmul(py, ey)), cmul(pzd, ez));
+  F.p[0][a] = cadd(cscale(ex, C), cscale(pBx, Sw));
+  F.p[1][a] = cadd(cscale(ey, C), cscale(pBy, Sw));
+  F.p[2][a] = cadd(cscale(ez, C), cscale(pBz, Sw));
+  F.p[3][a] = csub(cscale(bx, C), cscale(mEx, Sw));
+  F.p[4][a] = csub(cscale(by, C), cscale(mEy, Sw));
+  F.p[5][a] = csub(cscale(bz, C), cscale(mEz, Sw));
+  A.p[0][a] = csub(cscale(pBx, -X1), cscale(ex, Sw));
+  A.p[1][a] = csub(cscale(pBy, -X1), cscale(ey, Sw));
+  A.p[2][a] = csub(cscale(pBz, -X1), cscale(ez, Sw));
+  A.p[3][a] = cscale(dE, X3);
+  A.p[4][a] = cscale(dE, -X2);
+}
+
 }  // namespace
+
+template <typename T>
+void psatd_adjoint(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B[3], cplx<T>* const J[3],
+                   cplx<T>* rho_old, cplx<T>* rho_new, int nx, int ny, int nzh, int pz, hipStream_t s) {
+  Batch<cplx<T>*> F{}, A{};
+  for (int d = 0; d < 3; ++d) {
+    F.p[d] = E[d];
+    F.p[3 + d] = B[d];
+    A.p[d] = J[d];
+  }
+  A.p[3] = rho_old;
+  A.p[4] = rho_new;
+  const long long total = (long long)nx * ny * nzh;
+  hipLaunchKernelGGL((k_psatd_adjoint<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, t, F, A, nx, ny,
+                     nzh, pz);
+}
 
 template <typename T>
 void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B[3], const cplx<T>* const J[3],
@@ -125,4 +184,12 @@ template void psatd_update<double>(const PsatdTables<double>&, cplx<double>* con
                                    const cplx<double>* const*, const cplx<double>*, const cplx<double>*, int, int,
                                    int, int, cplx<double>* const*, hipStream_t);
 
+}  // namespace pic
+
+namespace pic {
+template void psatd_adjoint<float>(const PsatdTables<float>&, cplx<float>* const*, cplx<float>* const*,
+                                   cplx<float>* const*, cplx<float>*, cplx<float>*, int, int, int, int, hipStream_t);
+template void psatd_adjoint<double>(const PsatdTables<double>&, cplx<double>* const*, cplx<double>* const*,
+                                    cplx<double>* const*, cplx<double>*, cplx<double>*, int, int, int, int,
+                                    hipStream_t);
 }  // namespace pic

@@ -65,6 +65,7 @@ def load():
         "pic_deposit": (c_int, [c_void_p, POINTER(pic_species), c_int, POINTER(pic_fields), c_int]),
         "pic_center": (c_int, [c_void_p, c_int, c_int, POINTER(pic_fields)]),
         "psatd_push_fields": (c_int, [c_void_p, POINTER(pic_fields)]),
+        "psatd_push_fields_adjoint": (c_int, [c_void_p, POINTER(pic_fields)]),
         "pic_gather_push": (c_int, [c_void_p, POINTER(pic_fields), POINTER(pic_species), c_int]),
         "pic_step": (c_int, [c_void_p, POINTER(pic_fields), POINTER(pic_species), c_int, c_int]),
         "pic_sync": (c_int, [c_void_p]),
@@ -139,6 +140,10 @@ def pic_center(ctx, direction, what, fields):
 
 def psatd_push_fields(ctx, fields):
     _check(load().psatd_push_fields(ctx, ctypes.byref(fields.struct())), ctx)
+
+
+def psatd_push_fields_adjoint(ctx, fields):
+    _check(load().psatd_push_fields_adjoint(ctx, ctypes.byref(fields.struct())), ctx)
 
 
 def pic_gather_push(ctx, fields, species):

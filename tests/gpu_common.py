@@ -48,3 +48,16 @@ def have_gpu():
 
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def rounded(arrs, dtype):
+    """The float64 arrays rounded to the run precision (what the device sees)."""
+    npd = np.float32 if dtype == "f32" else np.float64
+    return [np.asarray(a).astype(npd).astype(np.float64) for a in arrs]
+
+
+def put(dst_list, arrs):
+    """Copy host float64 arrays into device tensors (converted to their dtype)."""
+    import torch
+    for t, a in zip(dst_list, arrs):
+        t.copy_(torch.from_numpy(np.asarray(a)).to(t.dtype))

@@ -1,0 +1,111 @@
+"""Reverse mode of the field solve and of the centering on the GPU: against the oracle's
+brute-force transpose, by the dot-product identity at larger sizes, and through
+torch.autograd (finite-difference gradcheck of the autograd Functions)."""
+
+import numpy as np
+import pytest
+
+from gpu_common import banner, max_rel, np64, put, rounded
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import adjoint as oadj  # noqa: E402
+from oracle import step as ostep  # noqa: E402
+from paper_2106_12919_amd import autograd as pag  # noqa: E402
+from paper_2106_12919_amd import inputs  # noqa: E402
+from paper_2106_12919_amd import lib as piclib  # noqa: E402
+
+
+@pytest.mark.parametrize("nodal", [False, True])
+def test_field_adjoint_matches_oracle_transpose(nodal):
+    banner(f"psatd_push_fields_adjoint vs brute-force oracle transpose, 8^3 FP64, nodal={nodal}")
+    shape = (8, 8, 8)
+    flags = piclib.PIC_NODAL_SOLVER if nodal else 0
+    p = ostep.Params(shape, (1.0, 1.0, 1.0), 0.6, 1, 8, 16, nodal=nodal)
+    ctx = piclib.Context(shape, (1.0, 1.0, 1.0), 0.6, 1, 8, 16, "f64", flags=flags)
+    lam = inputs.random_grid(shape, seed=11, count=6)
+    f = piclib.Fields(shape, "f64")
+    put(f.E_stag, lam[0:3])
+    put(f.B_stag, lam[3:6])
+    piclib.psatd_push_fields_adjoint(ctx.ctx, f)
+    piclib.pic_sync(ctx.ctx)
+    ref = oadj.push_fields_transpose(lam[0:3], lam[3:6], p)
+    got = [np64(a) for a in f.E_stag + f.B_stag + f.J_stag] + [np64(f.rho_old), np64(f.rho_new)]
+    scale = max(np.max(np.abs(r)) for r in ref)
+    for a in range(11):
+        assert np.max(np.abs(got[a] - ref[a])) <= 1e-12 * scale, a
+    ctx.close()
+
+
+def _host(t):
+    return np.asarray(t, dtype=np.float64) if isinstance(t, np.ndarray) else np64(t)
+
+
+def _dot(a, b):
+    return sum(float(np.sum(_host(x) * _host(y))) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(16, 24, 32), (12, 8, 48)])
+def test_field_adjoint_dot_product(dtype, shape):
+    banner(f"field solve dot-product identity dtype={dtype} shape={shape}")
+    ctx = piclib.Context(shape, (1.0, 1.0, 1.0), 0.5, 3, 8, 16, dtype)
+    x = rounded(inputs.random_grid(shape, seed=21, count=11), dtype)
+    lam = rounded(inputs.random_grid(shape, seed=22, count=6), dtype)
+    f = piclib.Fields(shape, dtype)
+    put(f.E_stag, x[0:3])
+    put(f.B_stag, x[3:6])
+    put(f.J_stag, x[6:9])
+    put([f.rho_old, f.rho_new], x[9:11])
+    piclib.psatd_push_fields(ctx.ctx, f)
+    lhs = _dot(lam, f.E_stag + f.B_stag)
+    g = piclib.Fields(shape, dtype)
+    put(g.E_stag, lam[0:3])
+    put(g.B_stag, lam[3:6])
+    piclib.psatd_push_fields_adjoint(ctx.ctx, g)
+    piclib.pic_sync(ctx.ctx)
+    rhs = _dot(x, g.E_stag + g.B_stag + g.J_stag + [g.rho_old, g.rho_new])
+    tol = 1e-11 if dtype == "f64" else 2e-5
+    norm = np.sqrt(_dot(lam, lam) * _dot(x, x))
+    assert abs(lhs - rhs) <= tol * norm, (lhs, rhs)
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("what", ["J", "E", "B"])
+def test_centering_transposes_dot_product(dtype, what):
+    banner(f"centering transposes dtype={dtype} what={what}")
+    shape = (16, 24, 32)
+    ctx = piclib.Context(shape, (1.0, 1.0, 1.0), 0.5, 1, 16, 16, dtype)
+    code = {"J": piclib.PIC_J, "E": piclib.PIC_E, "B": piclib.PIC_B}[what]
+    x = torch.tensor(np.stack(inputs.random_grid(shape, seed=31, count=3)), device="cuda",
+                     dtype=torch.float64 if dtype == "f64" else torch.float32)
+    y = torch.tensor(np.stack(inputs.random_grid(shape, seed=32, count=3)), device="cuda", dtype=x.dtype)
+    for fwd, back in ((piclib.PIC_N2S, piclib.PIC_S2N), (piclib.PIC_S2N, piclib.PIC_N2S)):
+        cx = pag._center(ctx, fwd, code, x)
+        cty = pag._center(ctx, back, code, y)
+        lhs = float(torch.sum(y.double() * cx.double()))
+        rhs = float(torch.sum(cty.double() * x.double()))
+        tol = 1e-12 if dtype == "f64" else 1e-5
+        assert abs(lhs - rhs) <= tol * float(torch.linalg.vector_norm(x.double()) * torch.linalg.vector_norm(y.double()))
+    ctx.close()
+
+
+def test_autograd_gradcheck_field_solve_and_centering():
+    banner("torch.autograd.gradcheck of PsatdPushFields and Center, FP64 8x8x16")
+    shape = (8, 8, 16)
+    ctx = piclib.Context(shape, (1.0, 1.0, 1.0), 0.5, 1, 4, 8, "f64")
+    gen = torch.Generator(device="cuda").manual_seed(3)
+    mk = lambda *s: torch.randn(*s, device="cuda", dtype=torch.float64, generator=gen).requires_grad_(True)
+    E, B, J = mk(3, *shape), mk(3, *shape), mk(3, *shape)
+    ro, rn = mk(*shape), mk(*shape)
+    assert torch.autograd.gradcheck(lambda *a: pag.PsatdPushFields.apply(ctx, *a), (E, B, J, ro, rn),
+                                    fast_mode=True, eps=1e-6, atol=1e-7)
+    for direction, what in ((piclib.PIC_N2S, piclib.PIC_J), (piclib.PIC_S2N, piclib.PIC_E),
+                            (piclib.PIC_S2N, piclib.PIC_B)):
+        x = mk(3, *shape)
+        assert torch.autograd.gradcheck(lambda t: pag.Center.apply(ctx, direction, what, t), (x,),
+                                        fast_mode=True, eps=1e-6, atol=1e-7)
+    ctx.close()

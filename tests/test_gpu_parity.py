@@ -9,7 +9,7 @@ derived from the operation count of each stage (see the per-test comments).
 import numpy as np
 import pytest
 
-from gpu_common import EPS, banner, max_rel, np64, oracle_species, periodic_pos_err
+from gpu_common import EPS, banner, max_rel, np64, oracle_species, periodic_pos_err, put, rounded
 
 pytestmark = pytest.mark.gpu
 
@@ -23,17 +23,6 @@ from paper_2106_12919_amd import inputs  # noqa: E402
 from paper_2106_12919_amd import lib as piclib  # noqa: E402
 
 TD = {"f32": torch.float32, "f64": torch.float64}
-
-
-def rounded(arrs, dtype):
-    """The float64 arrays rounded to the run precision (what the device sees)."""
-    npd = np.float32 if dtype == "f32" else np.float64
-    return [np.asarray(a).astype(npd).astype(np.float64) for a in arrs]
-
-
-def put(dst_list, arrs):
-    for t, a in zip(dst_list, arrs):
-        t.copy_(torch.from_numpy(np.asarray(a)).to(t.dtype))
 
 
 def centering_tol(dtype, m, scale):
