@@ -20,8 +20,11 @@ psatd        standard PSATD coefficients and update on the staggered grid (Sec. 
 centering    finite-order centering nodal <-> staggered (Sec. 3, App. C)
 particles    B-spline shapes, nodal gather, relativistic Boris push, deposition
 step         one hybrid PIC cycle (Sec. 2, the hybrid cycle)
-diagnostics  field energy (Sec. 2 (iii)), relative L2 error (Sec. 5.2), charge
+diagnostics  field energy (Sec. 2 (iii)), relative L2 error (Sec. 5.2), charge; closed-form
+             modified wave numbers, centering factor, stencil extent
+adjoint      reverse mode of one cycle: conjugate-transposed field solve, transposed
+             centering, gather/deposit adjoints, complex-step Boris Jacobians
 dft          brute-force DFT used only to pin ``transforms``
 """
 
-from . import fornberg, transforms, psatd, centering, particles, step, diagnostics, dft  # noqa: F401
+from . import fornberg, transforms, psatd, centering, particles, step, diagnostics, adjoint, dft  # noqa: F401

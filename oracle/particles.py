@@ -41,6 +41,20 @@ def shape_1d(order, d):
     raise ValueError("shape order must be 1 or 3")
 
 
+def shape_1d_deriv(order, d):
+    """Derivative of ``shape_1d`` with respect to d (taken as 0 at the kinks of order 1)."""
+    d = np.asarray(d, dtype=np.float64)
+    a = np.abs(d)
+    sg = np.sign(d)
+    if order == 1:
+        return np.where(a < 1.0, -sg, 0.0)
+    if order == 3:
+        inner = -2.0 * d + 1.5 * d * a
+        outer = -0.5 * sg * (2.0 - a) ** 2
+        return np.where(a <= 1.0, inner, np.where(a < 2.0, outer, 0.0))
+    raise ValueError("shape order must be 1 or 3")
+
+
 def _axis_nodes(xc, order):
     """[(node index, weight)] along one axis for positions ``xc`` in cells."""
     i0 = np.floor(xc).astype(np.int64)

@@ -105,3 +105,21 @@ def update(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, coef):
     E_new = tuple(C * Eh[d] + 1j * C_LIGHT ** 2 * Sw * kxB[d] + X4 * Jh[d]
                   + 1j * (X3 * rho_old_h - X2 * rho_new_h) * ks[d] for d in range(3))
     return E_new, B_new
+
+
+def update_transpose(lam_E, lam_B, ks, coef):
+    """Conjugate transpose of ``update`` acting on the adjoint spectra (dL/dE', dL/dB').
+
+    ``update`` is complex-linear in (E, B, J, rho^n, rho^{n+1}) with real coefficients and
+    real [k]_s, so every term a * x of it contributes conj(a) * lambda to the adjoint of x,
+    and a cross product [k]_s x v contributes -[k]_s x lambda.  Returns
+    (gE, gB, gJ) 3-tuples and g_rho_old, g_rho_new."""
+    C, Sw = coef["C"], coef["S_over_w"]
+    X1, X2, X3, X4 = coef["X1"], coef["X2"], coef["X3"], coef["X4"]
+    kxlE = cross(ks, lam_E)
+    kxlB = cross(ks, lam_B)
+    k_dot_lE = ks[0] * lam_E[0] + ks[1] * lam_E[1] + ks[2] * lam_E[2]
+    gE = tuple(C * lam_E[d] - 1j * Sw * kxlB[d] for d in range(3))
+    gB = tuple(C * lam_B[d] + 1j * C_LIGHT ** 2 * Sw * kxlE[d] for d in range(3))
+    gJ = tuple(1j * X1 * kxlB[d] + X4 * lam_E[d] for d in range(3))
+    return gE, gB, gJ, -1j * X3 * k_dot_lE, 1j * X2 * k_dot_lE
