@@ -72,7 +72,13 @@ enum {
    * the NODAL state, which pic_gather_push inside pic_step reads directly; pic_step leaves
    * E_nod, B_nod and J_stag untouched; psatd_push_fields reads J_stag as the nodal current.
    * Excludes PIC_SPECTRAL_CENTERING. */
-  PIC_NODAL_SOLVER = 1u << 1
+  PIC_NODAL_SOLVER = 1u << 1,
+  /* pic_step keeps every species in the caller's order: each step sorts the particles by
+   * tile through a permutation (one counting sort per step) instead of regrouping the
+   * arrays.  The results are those of the default cycle up to the summation order of the
+   * deposition.  For callers that follow particles by index across steps (the reverse
+   * mode, pic_step_adjoint). */
+  PIC_KEEP_ORDER = 1u << 2
 };
 
 typedef struct {
@@ -83,7 +89,7 @@ typedef struct {
   int32_t center_order;   /* finite-order centering 2m, even, 2..32, with 2m <= min(nx,ny,nz) (Sec. 3) */
   int32_t psatd_order;    /* order 2m_p of the staggered modified wave number [k]_s, even 2..64; 0 = infinite */
   pic_dtype dtype;        /* precision of fields, particles, FFTs; tables are always built in FP64 */
-  uint32_t flags;         /* 0, PIC_SPECTRAL_CENTERING or PIC_NODAL_SOLVER; other bits are rejected */
+  uint32_t flags;         /* 0 or PIC_SPECTRAL_CENTERING or PIC_NODAL_SOLVER, | PIC_KEEP_ORDER; other bits are rejected */
 } pic_params;
 
 /* One particle species, structure of arrays, caller-owned device memory.
@@ -184,6 +190,35 @@ pic_status pic_gather_push(pic_ctx ctx, const pic_fields* f, pic_species* sp, in
  * entry, then 4 forward and 6 inverse per step).  Particles of each species may
  * be reordered (all per-particle arrays together) to group them by grid tile. */
 pic_status pic_step(pic_ctx ctx, pic_fields* f, pic_species* sp, int nsp, int nsteps);
+
+/* Adjoints of one species' particle state (caller-owned device arrays of dtype, n each). */
+typedef struct {
+  void* off[3];           /* dL/d offset (per cell of the axis: the derivative w.r.t. the position in cells) */
+  void* u[3];             /* dL/du */
+} pic_species_adjoint;
+
+/* Reverse mode of one step of pic_step (Sec. 2 cycle), for differentiating a loss through
+ * the cycle: given the state at time n and the adjoint of the state at n+1, returns the
+ * adjoint of the state at n.  The stages are taken in reverse order: the conjugate-
+ * transposed field solve (as psatd_push_fields_adjoint), the transposed centerings
+ * (pic_center's transposed pairs), and per particle the adjoints of the deposition, the
+ * move, the relativistic Boris push and the gather (the B-spline and its derivative), whose
+ * field adjoints are spread back onto the nodes with the particle's shape (the transpose of
+ * the gather).  Forward quantities of the step are recomputed from the state at n.
+ *   f:   the state at n, as pic_step reads it: E_stag, B_stag (read; PIC_NODAL_SOLVER: the
+ *        nodal state); E_nod, B_nod are workspace (overwritten; unused with the nodal solver).
+ *   sp:  the nsp species at time n (x^n, u^{n-1/2}), in the order in which asp indexes them
+ *        (pic_step with PIC_KEEP_ORDER leaves that order unchanged); read only.
+ *   adj: in:  E_stag, B_stag = dL/dE^{n+1}, dL/dB^{n+1}; rho_new = dL/drho^{n+1} (the
+ *             adjoint of the next step's rho_old);
+ *        out: E_stag, B_stag = dL/dE^n, dL/dB^n; rho_old = dL/drho^n;
+ *        J_nod, J_stag, E_nod, B_nod and rho_new are workspace (overwritten).
+ *   asp: per species, in dL/dx^{n+1}, dL/du^{n+1/2}; out dL/dx^n, dL/du^{n-1/2} (in place).
+ * rho_static is constant (no adjoint).  Immobile species receive position adjoints from
+ * the charge they deposit.  Every array must be distinct from the others.  The adjoint of
+ * the spectral-centering cycle is that of the real-space cycle (the same map). */
+pic_status pic_step_adjoint(pic_ctx ctx, pic_fields* f, const pic_species* sp, int nsp, pic_fields* adj,
+                            const pic_species_adjoint* asp);
 
 /* Wait for the context's stream; returns PIC_EHIP if a device error occurred, and
  * PIC_EINVAL if particles with a cell index outside [0, nx*ny*nz) were skipped by

@@ -1,9 +1,15 @@
-"""Reverse mode of the field solve and of the centering, as torch.autograd Functions.
+"""Reverse mode of the hybrid PIC cycle as torch.autograd Functions.
 
-Both are linear maps whose transposes the library computes (``psatd_push_fields_adjoint``,
-and ``pic_center`` with the opposite direction), so a loss can be differentiated through
-them with torch's autograd.  Every computation runs in libpic's HIP kernels; this module
-only moves tensors in and out of a ``Fields`` workspace.
+* ``PsatdPushFields`` and ``Center``: the field solve and the centering, linear maps whose
+  transposes the library computes (``psatd_push_fields_adjoint``, and ``pic_center`` with the
+  opposite direction).
+* ``PicSteps``: nsteps whole cycles (``pic_step`` with the caller's particle order kept) with
+  gradients with respect to the initial fields, charge density, particle offsets and momenta,
+  by ``pic_step_adjoint`` one step at a time, backwards, from states recomputed out of
+  checkpoints kept every ``checkpoint_every`` steps.
+
+Every computation runs in libpic's HIP kernels; this module only moves tensors in and out
+of the library's workspaces and keeps the checkpoints.
 """
 
 import torch
@@ -79,3 +85,108 @@ class Center(torch.autograd.Function):
     def backward(ctx, g):
         back = piclib.PIC_S2N if ctx.direction == piclib.PIC_N2S else piclib.PIC_N2S
         return None, None, None, _center(ctx.pic, back, ctx.what, g.contiguous())
+
+
+class DifferentiableRun:
+    """Fixed data of a differentiable run: a ``lib.Context`` created with PIC_KEEP_ORDER in its
+    flags, one mobile species' charge and mass, an optional static background charge, the
+    number of steps and the checkpoint interval."""
+
+    def __init__(self, pic, q, m, nsteps, checkpoint_every=10, rho_static=None):
+        if not (pic.params.flags & piclib.PIC_KEEP_ORDER):
+            raise ValueError("the context needs PIC_KEEP_ORDER (particles followed by index across steps)")
+        if nsteps < 1 or checkpoint_every < 1:
+            raise ValueError("nsteps and checkpoint_every must be >= 1")
+        self.pic, self.q, self.m = pic, float(q), float(m)
+        self.nsteps, self.every = int(nsteps), int(checkpoint_every)
+        self.rho_static = rho_static
+        self.work = _fields(pic)  # E_nod, B_nod, J, rho_new workspace of the forward steps
+        self.work.rho_static = rho_static
+
+
+class _State:
+    """E, B (Yee), rho^n and one species' cell, offsets, momenta: separate contiguous tensors."""
+
+    def __init__(self, E, B, rho, cell, off, u):
+        self.E, self.B, self.rho, self.cell, self.off, self.u = E, B, rho, cell, off, u
+
+    @classmethod
+    def of(cls, E, B, rho, cell, off, u):
+        c = lambda t: t.detach().clone().contiguous()
+        return cls([c(E[d]) for d in range(3)], [c(B[d]) for d in range(3)], c(rho), c(cell),
+                   [c(off[d]) for d in range(3)], [c(u[d]) for d in range(3)])
+
+    def clone(self):
+        return _State.of(self.E, self.B, self.rho, self.cell, self.off, self.u)
+
+    def fields(self, run):
+        f = run.work
+        f.E_stag, f.B_stag, f.rho_old = self.E, self.B, self.rho
+        return f
+
+    def species(self, run, w):
+        return piclib.Species(self.cell, self.off, self.u, w, run.q, run.m)
+
+    def step(self, run, w, n):
+        piclib.pic_step(run.pic.ctx, self.fields(run), [self.species(run, w)], n)
+
+
+def _zeros_or(g, like):
+    return torch.zeros_like(like) if g is None else g.contiguous()
+
+
+class PicSteps(torch.autograd.Function):
+    """run.nsteps hybrid cycles: (E, B, rho, off, u) at step 0 -> the same at step nsteps.
+
+    E, B: (3, nx, ny, nz) on the Yee grid; rho: (nx, ny, nz) = rho^0 (rho_old); cell: (Np,) int32;
+    w: (Np,) weights; off, u: (3, Np).  Returns (E, B, rho, cell, off, u) after the run, the
+    particles in the input order (cell is not differentiable).  The backward pass recomputes
+    each checkpoint segment forward, keeping its states, and applies pic_step_adjoint from the
+    last step of the segment to the first."""
+
+    @staticmethod
+    def forward(ctx, run, cell, w, E, B, rho, off, u):
+        st = _State.of(E, B, rho, cell, off, u)
+        w = w.detach().contiguous()
+        checkpoints = [st.clone()]
+        n = 0
+        while n < run.nsteps:
+            k = min(run.every, run.nsteps - n)
+            st.step(run, w, k)
+            n += k
+            if n < run.nsteps:
+                checkpoints.append(st.clone())
+        ctx.run, ctx.w, ctx.checkpoints = run, w, checkpoints
+        out_cell = st.cell.clone()
+        ctx.mark_non_differentiable(out_cell)
+        return (torch.stack(st.E), torch.stack(st.B), st.rho.clone(), out_cell, torch.stack(st.off),
+                torch.stack(st.u))
+
+    @staticmethod
+    def backward(ctx, gE, gB, grho, gcell, goff, gu):
+        run, w = ctx.run, ctx.w
+        ref = ctx.checkpoints[0]
+        adj = _fields(run.pic)
+        gE = _zeros_or(gE, torch.stack(ref.E))
+        gB = _zeros_or(gB, torch.stack(ref.B))
+        for d in range(3):
+            adj.E_stag[d].copy_(gE[d])
+            adj.B_stag[d].copy_(gB[d])
+        adj.rho_new.copy_(_zeros_or(grho, ref.rho))
+        goff = _zeros_or(goff, torch.stack(ref.off))
+        gu = _zeros_or(gu, torch.stack(ref.u))
+        asp = piclib.SpeciesAdjoint([goff[d].clone() for d in range(3)], [gu[d].clone() for d in range(3)])
+        for seg in reversed(range(len(ctx.checkpoints))):
+            n0 = seg * run.every
+            k = min(run.every, run.nsteps - n0)
+            st = ctx.checkpoints[seg].clone()
+            states = [st.clone()]
+            for _ in range(k - 1):
+                st.step(run, w, 1)
+                states.append(st.clone())
+            for sj in reversed(states):
+                piclib.pic_step_adjoint(run.pic.ctx, sj.fields(run), [sj.species(run, w)], adj, [asp])
+                adj.rho_old, adj.rho_new = adj.rho_new, adj.rho_old  # dL/drho^n carries to the step before
+        ctx.checkpoints = None
+        return (None, None, None, torch.stack(adj.E_stag), torch.stack(adj.B_stag), adj.rho_new.clone(),
+                torch.stack(asp.off), torch.stack(asp.u))

@@ -136,6 +136,7 @@ struct Engine : EngineBase {
   int* t_cursor = nullptr;  // ntiles + 1
   int* work = nullptr;      // tile counter of the persistent deposition
   T* stage = nullptr;       // per-tile deposition boxes, ntiles * 4 * deposit_box^3
+  T* astage = nullptr;      // per-tile boxes of the reverse mode's scatter, ntiles * 6 * deposit_box^3 (on first use)
   std::vector<SpeciesScratch<T>> sps;
   cplx<T>* Eh[3] = {nullptr, nullptr, nullptr};
   cplx<T>* Bh[3] = {nullptr, nullptr, nullptr};
@@ -324,7 +325,7 @@ pic_status validate_params(const pic_params* p, std::string& msg) {
     return PIC_EUNSUPPORTED;
   }
   if (p->dtype != PIC_F32 && p->dtype != PIC_F64) { msg = "dtype must be PIC_F32 or PIC_F64"; return PIC_EINVAL; }
-  if (p->flags & ~(uint32_t)(PIC_SPECTRAL_CENTERING | PIC_NODAL_SOLVER)) {
+  if (p->flags & ~(uint32_t)(PIC_SPECTRAL_CENTERING | PIC_NODAL_SOLVER | PIC_KEEP_ORDER)) {
     msg = "unknown bit in flags";
     return PIC_EINVAL;
   }
@@ -694,6 +695,7 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
   }
   pic_status st;
   const bool spectral = (p.flags & PIC_SPECTRAL_CENTERING) != 0;
+  const bool keep = (p.flags & PIC_KEEP_ORDER) != 0;
   for (int n = 0; n < nsteps; ++n) {
     if (!nodal && (!spectral || n == 0)) {  // spectral centering: later steps get E_nod, B_nod from the update
       StageScope sc(c, ST_S2N);
@@ -707,6 +709,30 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
     for (int q = 0; q < nsp; ++q) {
       if (sp[q].n == 0) continue;
       SpeciesScratch<T>& x = e.sps[q];
+      if (keep) {  // caller's order: every step visits the particles through a tile permutation
+        const SpeciesView<T> v = view<T>(sp[q]);
+        const bool mobile = std::isfinite(sp[q].m);
+        {
+          StageScope sc(c, ST_SORT);
+          tile_sort(g, e.tiles, v.cell, v.n, x.counts[0], x.starts[0], x.cursor, x.dst, c->d_bad, c->stream);
+          invert_perm(x.dst, x.perm, v.n, c->stream);
+        }
+        if (mobile) {
+          StageScope sc(c, ST_PUSH);
+          gather_push_tiled<T>(g, e.tiles, Enod, Bnod, v, v, x.perm, x.starts[0], false, nullptr, nullptr,
+                               c->stream);
+        }
+        {
+          StageScope sc(c, ST_DEPOSIT);  // positions moved < 1 cell: the grouping still holds them
+          deposit_tiled<T>(g, e.tiles, v, x.perm, x.starts[0], mobile, e.stage, c->d_bad, nullptr, nullptr, e.work,
+                           static_cast<T*>(f->rho_new), Jn, c->stream);
+        }
+        {
+          StageScope sc(c, ST_REDUCE);
+          deposit_reduce<T>(g, e.tiles, x.starts[0], e.stage, mobile, static_cast<T*>(f->rho_new), Jn, c->stream);
+        }
+        continue;
+      }
       const SpeciesView<T> cur = in_scratch[q] ? scratch_view<T>(x, sp[q]) : view<T>(sp[q]);
       const SpeciesView<T> alt = in_scratch[q] ? view<T>(sp[q]) : scratch_view<T>(x, sp[q]);
       const bool mobile = std::isfinite(sp[q].m);
@@ -780,6 +806,110 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
     if (in_scratch[q] && sp[q].n > 0) copy_species<T>(scratch_view<T>(e.sps[q], sp[q]), view<T>(sp[q]), c->stream);
   (void)hipMemcpyAsync(f->rho_old, f->rho_new, ncells(p) * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
   return c->check("pic_step");
+}
+
+// Reverse mode of one pic_step step (see pic_step_adjoint in pic.h).
+template <typename T>
+pic_status do_step_adjoint(pic_ctx c, pic_fields* f, const pic_species* sp, int nsp, pic_fields* a,
+                           const pic_species_adjoint* asp) {
+  Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
+  const pic_params& p = c->p;
+  const size_t N = ncells(p);
+  const GridGeom g = geom(p);
+  const bool nodal = (p.flags & PIC_NODAL_SOLVER) != 0;
+  pic_status st;
+  // nodal fields of the state at n (the nodal solver gathers its state directly)
+  const T* F[6];
+  for (int d = 0; d < 3; ++d) {
+    F[d] = static_cast<const T*>(nodal ? f->E_stag[d] : f->E_nod[d]);
+    F[3 + d] = static_cast<const T*>(nodal ? f->B_stag[d] : f->B_nod[d]);
+  }
+  if (!nodal) {
+    StageScope sc(c, ST_S2N);
+    if ((st = do_center<T>(c, PIC_S2N, PIC_E, f)) != PIC_OK) return st;
+    if ((st = do_center<T>(c, PIC_S2N, PIC_B, f)) != PIC_OK) return st;
+  }
+  // field solve: a->E_stag, a->B_stag in place; dL/dJ into J_stag (nodal solver: J_nod),
+  // dL/drho^n into rho_old, the field solve's dL/drho^{n+1} into E_nod[0] (then added to
+  // the carried adjoint of rho^{n+1} in rho_new)
+  {
+    pic_fields t = *a;
+    t.rho_new = a->E_nod[0];
+    if (nodal)
+      for (int d = 0; d < 3; ++d) t.J_stag[d] = a->J_nod[d];
+    if ((st = do_push_fields_adjoint<T>(c, &t)) != PIC_OK) return st;
+  }
+  add_into<T>(static_cast<T*>(a->rho_new), static_cast<const T*>(a->E_nod[0]), (int64_t)N, c->stream);
+  if (!nodal) {
+    StageScope sc(c, ST_N2S);
+    if ((st = do_center<T>(c, PIC_S2N, PIC_J, a)) != PIC_OK) return st;  // J_stag -> J_nod (transpose of N2S)
+  }
+  for (int d = 0; d < 3; ++d) {
+    (void)hipMemsetAsync(a->E_nod[d], 0, N * sizeof(T), c->stream);
+    (void)hipMemsetAsync(a->B_nod[d], 0, N * sizeof(T), c->stream);
+  }
+  const T* L[4] = {static_cast<const T*>(a->rho_new), static_cast<const T*>(a->J_nod[0]),
+                   static_cast<const T*>(a->J_nod[1]), static_cast<const T*>(a->J_nod[2])};
+  T* out[6];
+  for (int d = 0; d < 3; ++d) {
+    out[d] = static_cast<T*>(a->E_nod[d]);
+    out[3 + d] = static_cast<T*>(a->B_nod[d]);
+  }
+  for (int q = 0; q < nsp; ++q) {
+    if (sp[q].n == 0) continue;
+    hipError_t he = e.ensure_species((size_t)q, sp[q].n);
+    if (he == hipSuccess && !e.astage) {
+      const size_t B = (size_t)deposit_box(p.shape_order);
+      he = e.alloc(&e.astage, (size_t)e.tiles.ntiles * 6 * B * B * B);
+    }
+    if (he != hipSuccess) return c->fail(PIC_ENOMEM, std::string("pic_step_adjoint: ") + hipGetErrorString(he));
+    SpeciesScratch<T>& x = e.sps[q];
+    const SpeciesView<T> v = view<T>(sp[q]);
+    {
+      StageScope sc(c, ST_SORT);
+      tile_sort(g, e.tiles, v.cell, v.n, x.counts[0], x.starts[0], x.cursor, x.dst, c->d_bad, c->stream);
+      invert_perm(x.dst, x.perm, v.n, c->stream);
+    }
+    Batch<T*> lam{}, lamF{};
+    for (int d = 0; d < 3; ++d) {
+      lam.p[d] = static_cast<T*>(asp[q].off[d]);
+      lam.p[3 + d] = static_cast<T*>(asp[q].u[d]);
+      lamF.p[d] = x.off[d];  // the species scratch holds dL/d(E_p, B_p)
+      lamF.p[3 + d] = x.u[d];
+    }
+    {
+      StageScope sc(c, ST_PUSH);
+      particle_adjoint<T>(g, v, lam, x.perm, F, L, lamF, c->stream);
+    }
+    if (std::isfinite(sp[q].m)) {
+      StageScope sc(c, ST_DEPOSIT);
+      const T* val[6] = {x.off[0], x.off[1], x.off[2], x.u[0], x.u[1], x.u[2]};
+      scatter_tiled<T>(g, e.tiles, v, x.perm, x.starts[0], val, out, e.astage, c->stream);
+    }
+  }
+  // the gathered fields' adjoints back to the state grid, added to the field solve's
+  if (nodal) {
+    for (int d = 0; d < 3; ++d) {
+      add_into<T>(static_cast<T*>(a->E_stag[d]), out[d], (int64_t)N, c->stream);
+      add_into<T>(static_cast<T*>(a->B_stag[d]), out[3 + d], (int64_t)N, c->stream);
+    }
+  } else {
+    StageScope sc(c, ST_S2N);
+    pic_fields t{};
+    for (int d = 0; d < 3; ++d) {
+      t.E_nod[d] = a->E_nod[d];
+      t.B_nod[d] = a->B_nod[d];
+      t.E_stag[d] = f->E_nod[d];  // the state's nodal fields are no longer needed: workspace
+      t.B_stag[d] = f->B_nod[d];
+    }
+    if ((st = do_center<T>(c, PIC_N2S, PIC_E, &t)) != PIC_OK) return st;
+    if ((st = do_center<T>(c, PIC_N2S, PIC_B, &t)) != PIC_OK) return st;
+    for (int d = 0; d < 3; ++d) {
+      add_into<T>(static_cast<T*>(a->E_stag[d]), static_cast<const T*>(f->E_nod[d]), (int64_t)N, c->stream);
+      add_into<T>(static_cast<T*>(a->B_stag[d]), static_cast<const T*>(f->B_nod[d]), (int64_t)N, c->stream);
+    }
+  }
+  return c->check("pic_step_adjoint");
 }
 
 template <typename T>
@@ -958,6 +1088,25 @@ pic_status pic_step(pic_ctx ctx, pic_fields* f, pic_species* sp, int nsp, int ns
   if ((st = check_species(ctx, sp, nsp)) != PIC_OK) return st;
   if ((st = check_fields(ctx, f, true, true, true, true, true, true, true, true)) != PIC_OK) return st;
   return PIC_DISPATCH(ctx, do_step, f, sp, nsp, nsteps);
+}
+
+pic_status pic_step_adjoint(pic_ctx ctx, pic_fields* f, const pic_species* sp, int nsp, pic_fields* adj,
+                            const pic_species_adjoint* asp) {
+  pic_status st = device_ok(ctx);
+  if (st != PIC_OK) return st;
+  if ((st = check_species(ctx, sp, nsp)) != PIC_OK) return st;
+  const bool nodal = (ctx->p.flags & PIC_NODAL_SOLVER) != 0;
+  if ((st = check_fields(ctx, f, true, true, !nodal, !nodal, false, false, false, false)) != PIC_OK) return st;
+  if ((st = check_fields(ctx, adj, true, true, true, true, true, true, true, true)) != PIC_OK) return st;
+  if (nsp > 0 && !asp) return ctx->fail(PIC_EINVAL, "species adjoint array is NULL");
+  for (int q = 0; q < nsp; ++q) {
+    if (sp[q].n == 0) continue;
+    for (int d = 0; d < 3; ++d) {
+      if ((st = check_ptr(ctx, asp[q].off[d], "adjoint off")) != PIC_OK) return st;
+      if ((st = check_ptr(ctx, asp[q].u[d], "adjoint u")) != PIC_OK) return st;
+    }
+  }
+  return PIC_DISPATCH(ctx, do_step_adjoint, f, sp, nsp, adj, asp);
 }
 
 pic_status pic_sync(pic_ctx ctx) {

@@ -35,6 +35,11 @@ struct Shape<T, 1> {
     w[0] = (T)1 - d;
     w[1] = d;
   }
+  // d w / d d (the reverse mode's position derivatives)
+  __device__ static inline void dweights(T, T* g) {
+    g[0] = (T)-1;
+    g[1] = (T)1;
+  }
 };
 
 template <typename T>
@@ -49,6 +54,13 @@ struct Shape<T, 3> {
     w[1] = twothird - d * d + (T)0.5 * d * d * d;
     w[2] = twothird - e * e + (T)0.5 * e * e * e;
     w[3] = sixth * d * d * d;
+  }
+  __device__ static inline void dweights(T d, T* g) {
+    const T e = (T)1 - d;
+    g[0] = (T)-0.5 * e * e;
+    g[1] = (T)-2 * d + (T)1.5 * d * d;
+    g[2] = (T)2 * e - (T)1.5 * e * e;
+    g[3] = (T)0.5 * d * d;
   }
 };
 
@@ -271,6 +283,35 @@ __device__ inline void load_field_box(T* box, const Batch<const T*>& F, const Gr
   }
 }
 
+// Relativistic Boris push (c = 1) of u by the gathered f = (E, B), qdt2m = q dt / (2 m):
+//   u- = u + qdt2m E,  t = qdt2m B / gamma(u-),  s = 2 t / (1 + |t|^2),
+//   u' = u- + u- x t,  u+ = u- + u' x s,  u_new = u+ + qdt2m E.
+// The intermediates stay in ``b`` (the reverse mode reuses them).
+template <typename T>
+struct BorisState {
+  T umx, umy, umz, tf, tx, ty, tz, sf, sx, sy, sz, upx, upy, upz;
+};
+template <typename T>
+__device__ inline void boris(const T* f, T qdt2m, T& ux, T& uy, T& uz, BorisState<T>& b) {
+  b.umx = ux + qdt2m * f[0];
+  b.umy = uy + qdt2m * f[1];
+  b.umz = uz + qdt2m * f[2];
+  b.tf = qdt2m * inv_sqrt((T)1 + b.umx * b.umx + b.umy * b.umy + b.umz * b.umz);  // q dt / (2 m gamma)
+  b.tx = b.tf * f[3];
+  b.ty = b.tf * f[4];
+  b.tz = b.tf * f[5];
+  b.sf = quot((T)2, (T)1 + b.tx * b.tx + b.ty * b.ty + b.tz * b.tz);
+  b.sx = b.sf * b.tx;
+  b.sy = b.sf * b.ty;
+  b.sz = b.sf * b.tz;
+  b.upx = b.umx + (b.umy * b.tz - b.umz * b.ty);
+  b.upy = b.umy + (b.umz * b.tx - b.umx * b.tz);
+  b.upz = b.umz + (b.umx * b.ty - b.umy * b.tx);
+  ux = b.umx + (b.upy * b.sz - b.upz * b.sy) + qdt2m * f[0];
+  uy = b.umy + (b.upz * b.sx - b.upx * b.sz) + qdt2m * f[1];
+  uz = b.umz + (b.upx * b.sy - b.upy * b.sx) + qdt2m * f[2];
+}
+
 // Gather at one particle from the LDS box (first support node at box index l*) or,
 // outside the margin, from the grid; then the relativistic Boris push and the move.
 template <typename T, int ORDER>
@@ -318,18 +359,8 @@ __device__ inline void gather_push_one(const T* box, const Batch<const T*>& F, c
       }
     }
   }
-  // relativistic Boris (c = 1)
-  const T umx = ux + qdt2m * f[0], umy = uy + qdt2m * f[1], umz = uz + qdt2m * f[2];
-  const T tf = qdt2m * inv_sqrt((T)1 + umx * umx + umy * umy + umz * umz);  // q dt / (2 m gamma)
-  const T tx = tf * f[3], ty = tf * f[4], tz = tf * f[5];
-  const T sf = quot((T)2, (T)1 + tx * tx + ty * ty + tz * tz);
-  const T sx = sf * tx, sy = sf * ty, sz = sf * tz;
-  const T upx = umx + (umy * tz - umz * ty);
-  const T upy = umy + (umz * tx - umx * tz);
-  const T upz = umz + (umx * ty - umy * tx);
-  ux = umx + (upy * sz - upz * sy) + qdt2m * f[0];
-  uy = umy + (upz * sx - upx * sz) + qdt2m * f[1];
-  uz = umz + (upx * sy - upy * sx) + qdt2m * f[2];
+  BorisState<T> b;
+  boris(f, qdt2m, ux, uy, uz, b);
   const T ig = inv_sqrt((T)1 + ux * ux + uy * uy + uz * uz);
   i = wrapi(i + advance_offset(ox, dtx * ux * ig), g.nx);
   j = wrapi(j + advance_offset(oy, dty * uy * ig), g.ny);
@@ -1091,7 +1122,7 @@ __global__ void __launch_bounds__(256) k_deposit_reduce(GridGeom g, TileGeom tg,
       }
       if (d == 0) nx_ = cnt; else if (d == 1) ny_ = cnt; else nz_ = cnt;
     }
-    T acc[4] = {0, 0, 0, 0};
+    T acc[6] = {0, 0, 0, 0, 0, 0};
     for (int a = 0; a < nx_; ++a)
       for (int b = 0; b < ny_; ++b)
         for (int c = 0; c < nz_; ++c) {
@@ -1102,6 +1133,249 @@ __global__ void __launch_bounds__(256) k_deposit_reduce(GridGeom g, TileGeom tg,
         }
     for (int q = 0; q < ncomp; ++q) out.p[q][idx] += acc[q];
   }
+}
+
+// ---------------------------------------------------------------- reverse mode
+
+// Over the S^3 support nodes of a particle in cell (i, j, k) with offsets o (cells), the
+// shape-weighted sums val[v] = sum_n S_n A_v[n] and the position gradients
+// grad[v][a] = sum_n dS_n/dx_a A_v[n] (x in cells) of NV nodal arrays.
+template <typename T, int ORDER, int NV>
+__device__ inline void stencil_sums(const GridGeom& g, int i, int j, int k, T ox, T oy, T oz, const T* const* A,
+                                    T* val, T (*grad)[3]) {
+  using S = Shape<T, ORDER>;
+  constexpr int NW = S::NW;
+  T wx[NW], wy[NW], wz[NW], gx[NW], gy[NW], gz[NW];
+  S::weights(ox, wx);
+  S::weights(oy, wy);
+  S::weights(oz, wz);
+  S::dweights(ox, gx);
+  S::dweights(oy, gy);
+  S::dweights(oz, gz);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    val[v] = 0;
+    grad[v][0] = grad[v][1] = grad[v][2] = 0;
+  }
+  int kk[NW];
+#pragma unroll
+  for (int c = 0; c < NW; ++c) kk[c] = wrapi(k + c + S::BASE, g.nz);
+#pragma unroll
+  for (int a = 0; a < NW; ++a) {
+    const int ii = wrapi(i + a + S::BASE, g.nx);
+#pragma unroll
+    for (int b = 0; b < NW; ++b) {
+      const int jj = wrapi(j + b + S::BASE, g.ny);
+      const size_t row = ((size_t)ii * g.ny + jj) * g.nz;
+      const T wab = wx[a] * wy[b], gxab = gx[a] * wy[b], gyab = wx[a] * gy[b];
+#pragma unroll
+      for (int c = 0; c < NW; ++c) {
+        const T w = wab * wz[c], dx = gxab * wz[c], dy = gyab * wz[c], dz = wab * gz[c];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const T x = A[v][row + kk[c]];
+          val[v] += w * x;
+          grad[v][0] += dx * x;
+          grad[v][1] += dy * x;
+          grad[v][2] += dz * x;
+        }
+      }
+    }
+  }
+}
+
+// Reverse mode of gather + Boris push + move + deposition for one particle per thread
+// (slot q -> particle perm[q]).  The forward quantities are recomputed from the particle
+// at time n with the forward's own functions; then, with c = q w / dV, hdt = dt / (2 dx)
+// and dtc = dt / dx per axis (positions in cells):
+//   deposition: rho^{n+1} = c S(x^{n+1}), J^{n+1/2} = c v S(x^{n+1} - hdt v)
+//     lx1 = lx + c sum lrho grad S(x^{n+1}) + G,   G = c sum (lJ . v) grad S(x^{n+1/2})
+//     lv  = c sum lJ S(x^{n+1/2}) - hdt G + dtc lx1          (x^{n+1} = x^n + dtc v)
+//     lu' = lu + (lv - v (v . lv)) / gamma                   (v = u'/gamma)
+//   Boris (a = lu'):  lE = qdt2m (a + lum), lB = tf lt, lu^{n-1/2} = lum with
+//     lup = s x a, ls = a x up, lum = a + lup + t x lup - (tf / gamma_-^2) (B . lt) um,
+//     lt = lup x um + sf ls - sf^2 t (t . ls)
+//   gather: lx^n = lx1 + sum_m lF_m grad F_m(x^n);  lF = (lE, lB) goes to lamF for the
+//   scatter onto the nodal grids.
+// Immobile species (never pushed, rho only): lx += c sum lrho grad S(x).
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(256) k_particle_adjoint(GridGeom g, SpeciesView<T> sp, Batch<T*> lam,
+                                                          const int* __restrict__ perm, Batch<const T*> F,
+                                                          Batch<const T*> L, Batch<T*> lamF, T qdt2m, T qdv, T dtx,
+                                                          T dty, T dtz, int mobile) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= sp.n) return;
+  const int p = perm ? perm[q] : (int)q;
+  int i, j, k;
+  if (!decode_cell(sp.cell[p], g, nullptr, i, j, k)) {  // never pushed nor deposited: adjoint passes through
+#pragma unroll
+    for (int m = 0; m < 6; ++m) lamF.p[m][p] = 0;
+    return;
+  }
+  const T ox = sp.off[0][p], oy = sp.off[1][p], oz = sp.off[2][p];
+  const T c = qdv * (sp.w ? sp.w[p] : (T)sp.w_const);
+  T lx[3] = {lam.p[0][p], lam.p[1][p], lam.p[2][p]};
+  const T* Lrho[1] = {L.p[0]};
+  if (!mobile) {
+    T rv[1], rg[1][3];
+    stencil_sums<T, ORDER, 1>(g, i, j, k, ox, oy, oz, Lrho, rv, rg);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) lam.p[a][p] = lx[a] + c * rg[0][a];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) lamF.p[m][p] = 0;
+    return;
+  }
+  const T lu[3] = {lam.p[3][p], lam.p[4][p], lam.p[5][p]};
+  // forward: gather at x^n (with gradients), push, move
+  T f[6], gf[6][3];
+  stencil_sums<T, ORDER, 6>(g, i, j, k, ox, oy, oz, F.p, f, gf);
+  T ux = sp.u[0][p], uy = sp.u[1][p], uz = sp.u[2][p];
+  BorisState<T> b;
+  boris(f, qdt2m, ux, uy, uz, b);
+  const T ig = inv_sqrt((T)1 + ux * ux + uy * uy + uz * uz);
+  const T v[3] = {ux * ig, uy * ig, uz * ig};
+  T o1x = ox, o1y = oy, o1z = oz;
+  const int i1 = wrapi(i + advance_offset(o1x, dtx * ux * ig), g.nx);
+  const int j1 = wrapi(j + advance_offset(o1y, dty * uy * ig), g.ny);
+  const int k1 = wrapi(k + advance_offset(o1z, dtz * uz * ig), g.nz);
+  const T hd[3] = {(T)0.5 * dtx, (T)0.5 * dty, (T)0.5 * dtz};
+  T hx = o1x, hy = o1y, hz = o1z;
+  const int ih = wrapi(i1 + advance_offset(hx, -hd[0] * v[0]), g.nx);
+  const int jh = wrapi(j1 + advance_offset(hy, -hd[1] * v[1]), g.ny);
+  const int kh = wrapi(k1 + advance_offset(hz, -hd[2] * v[2]), g.nz);
+  // deposition
+  T rv[1], rg[1][3], jv[3], jg[3][3];
+  stencil_sums<T, ORDER, 1>(g, i1, j1, k1, o1x, o1y, o1z, Lrho, rv, rg);
+  const T* LJ[3] = {L.p[1], L.p[2], L.p[3]};
+  stencil_sums<T, ORDER, 3>(g, ih, jh, kh, hx, hy, hz, LJ, jv, jg);
+  const T dtc[3] = {dtx, dty, dtz};
+  T lx1[3], lv[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T G = c * (v[0] * jg[0][a] + v[1] * jg[1][a] + v[2] * jg[2][a]);
+    lx1[a] = lx[a] + c * rg[0][a] + G;
+    lv[a] = c * jv[a] - hd[a] * G;
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) lv[a] += dtc[a] * lx1[a];
+  const T vl = v[0] * lv[0] + v[1] * lv[1] + v[2] * lv[2];
+  T ax = lu[0] + (lv[0] - v[0] * vl) * ig;
+  T ay = lu[1] + (lv[1] - v[1] * vl) * ig;
+  T az = lu[2] + (lv[2] - v[2] * vl) * ig;
+  // Boris, reversed
+  const T lupx = b.sy * az - b.sz * ay, lupy = b.sz * ax - b.sx * az, lupz = b.sx * ay - b.sy * ax;  // s x a
+  const T lsx = ay * b.upz - az * b.upy, lsy = az * b.upx - ax * b.upz, lsz = ax * b.upy - ay * b.upx;  // a x up
+  const T tls = b.tx * lsx + b.ty * lsy + b.tz * lsz;
+  const T sf2 = b.sf * b.sf;
+  const T ltx = (lupy * b.umz - lupz * b.umy) + b.sf * lsx - sf2 * b.tx * tls;
+  const T lty = (lupz * b.umx - lupx * b.umz) + b.sf * lsy - sf2 * b.ty * tls;
+  const T ltz = (lupx * b.umy - lupy * b.umx) + b.sf * lsz - sf2 * b.tz * tls;
+  const T ig2 = inv_sqrt((T)1 + b.umx * b.umx + b.umy * b.umy + b.umz * b.umz);
+  const T ktf = -b.tf * ig2 * ig2 * (f[3] * ltx + f[4] * lty + f[5] * ltz);
+  const T lumx = ax + lupx + (b.ty * lupz - b.tz * lupy) + ktf * b.umx;
+  const T lumy = ay + lupy + (b.tz * lupx - b.tx * lupz) + ktf * b.umy;
+  const T lumz = az + lupz + (b.tx * lupy - b.ty * lupx) + ktf * b.umz;
+  const T lF[6] = {qdt2m * (ax + lumx), qdt2m * (ay + lumy), qdt2m * (az + lumz),
+                   b.tf * ltx,          b.tf * lty,          b.tf * ltz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    T x = lx1[a];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) x += lF[m] * gf[m][a];
+    lam.p[a][p] = x;
+  }
+  lam.p[3][p] = lumx;
+  lam.p[4][p] = lumy;
+  lam.p[5][p] = lumz;
+#pragma unroll
+  for (int m = 0; m < 6; ++m) lamF.p[m][p] = lF[m];
+}
+
+// Six per-particle values val_v[p] spread with the particle's shape at its position onto
+// nodal grids: one block per tile of the grouping (slots [starts[t], starts[t+1]) through
+// perm), accumulated in a fixed-point LDS box per component (scales from the tile's sum and
+// max of |val_v|, as in the deposition) and stored to the tile's staging slot for
+// k_deposit_reduce*; a particle outside the box margin goes to the grids with atomics.
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(256) k_scatter_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp,
+                                                       const int* __restrict__ perm, const int* __restrict__ starts,
+                                                       Batch<const T*> val, Batch<T*> out, T* __restrict__ stage) {
+  using S = Shape<T, ORDER>;
+  using X = Box<S::NW>;
+  constexpr int NV = 6;
+  constexpr int kWaves = 256 / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  auto* box = reinterpret_cast<typename Fixed<T>::acc_t*>(smem);
+  __shared__ T red[NV * kWaves], redm[NV * kWaves];
+  __shared__ int shs[NV];
+  const int tile = xcd_major(blockIdx.x, gridDim.x);
+  const int beg = starts[tile], end = starts[tile + 1];
+  if (beg == end) return;
+  int ti, tj, tk;
+  tile_coords(tile, tg, ti, tj, tk);
+  const int t0x = ti * kTile, t0y = tj * kTile, t0z = tk * kTile;
+  T sw[NV], mw[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sw[v] = mw[v] = 0;
+  for (int q = beg + threadIdx.x; q < end; q += blockDim.x) {
+    const int p = perm ? perm[q] : q;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const T a = fabs(val.p[v][p]);
+      sw[v] += a;
+      mw[v] = fmax(mw[v], a);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    for (int o = 32; o > 0; o >>= 1) {
+      sw[v] += __shfl_xor(sw[v], o, 64);
+      mw[v] = fmax(mw[v], __shfl_xor(mw[v], o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[v * kWaves + (threadIdx.x >> 6)] = sw[v];
+      redm[v * kWaves + (threadIdx.x >> 6)] = mw[v];
+    }
+  }
+  for (int e = threadIdx.x; e < NV * X::B3; e += blockDim.x) box[e] = 0;
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int v = threadIdx.x;
+    T m = 0, x = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      m += red[v * kWaves + w];
+      x = fmax(x, redm[v * kWaves + w]);
+    }
+    int e_sum = 0, e_max = 0;
+    (void)frexp(m * (T)(MaxWeight<ORDER>::value * 1.001), &e_sum);
+    (void)frexp(x * (T)1.001, &e_max);
+    shs[v] = Fixed<T>::shift(e_sum, e_max, 32 - __clz(end - beg));
+  }
+  __syncthreads();
+  int sh[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sh[v] = shs[v];
+  for (int q = beg + threadIdx.x; q < end; q += blockDim.x) {
+    const int p = perm ? perm[q] : q;
+    int i, j, k;
+    if (!decode_cell(sp.cell[p], g, nullptr, i, j, k)) continue;
+    const T ox = sp.off[0][p], oy = sp.off[1][p], oz = sp.off[2][p];
+    T x[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v] = val.p[v][p];
+    const int lx = box_index(i, t0x, g.nx), ly = box_index(j, t0y, g.ny), lz = box_index(k, t0z, g.nz);
+    if (lx >= 0 && ly >= 0 && lz >= 0) {
+      T sv[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sv[v] = ldexp(x[v], sh[v]);
+      scatter_lds<T, ORDER, NV>(box, X::at(lx, ly, lz), ox, oy, oz, sv);
+    } else {
+      scatter<T, ORDER>(g, i, j, k, ox, oy, oz, out.p, x, NV);
+    }
+  }
+  __syncthreads();
+  T* dstage = stage + (size_t)tile * NV * X::B3;
+  for (int e = threadIdx.x; e < NV * X::B3; e += blockDim.x) dstage[e] = ldexp((T)box[e], -shs[e / X::B3]);
 }
 
 }  // namespace
@@ -1238,6 +1512,64 @@ void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, con
     hipLaunchKernelGGL((k_deposit_reduce<T, 3>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, out, ncomp);
 }
 
+template <typename T>
+void particle_adjoint(const GridGeom& g, const SpeciesView<T>& sp, const Batch<T*>& lam, const int* perm,
+                      const T* const F[6], const T* const L[4], const Batch<T*>& lamF, hipStream_t s) {
+  if (sp.n <= 0) return;
+  Batch<const T*> f{}, l{};
+  for (int m = 0; m < 6; ++m) f.p[m] = F[m];
+  for (int m = 0; m < 4; ++m) l.p[m] = L[m];
+  const bool mobile = std::isfinite(sp.m);
+  const T qdt2m = mobile ? (T)(sp.q * g.dt / (2.0 * sp.m)) : (T)0;
+  const T qdv = (T)(sp.q / (g.dx * g.dy * g.dz));
+  const T dtx = (T)(g.dt / g.dx), dty = (T)(g.dt / g.dy), dtz = (T)(g.dt / g.dz);
+  const dim3 grid((unsigned)((sp.n + 255) / 256));
+  if (g.shape_order == 1)
+    hipLaunchKernelGGL((k_particle_adjoint<T, 1>), grid, dim3(256), 0, s, g, sp, lam, perm, f, l, lamF, qdt2m, qdv,
+                       dtx, dty, dtz, mobile ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_particle_adjoint<T, 3>), grid, dim3(256), 0, s, g, sp, lam, perm, f, l, lamF, qdt2m, qdv,
+                       dtx, dty, dtz, mobile ? 1 : 0);
+}
+
+template <typename T>
+void scatter_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
+                   const T* const val[6], T* const out[6], T* stage, hipStream_t s) {
+  if (sp.n <= 0) return;
+  Batch<const T*> v{};
+  Batch<T*> o{};
+  for (int m = 0; m < 6; ++m) {
+    v.p[m] = val[m];
+    o.p[m] = out[m];
+  }
+  const int B = deposit_box(g.shape_order);
+  const size_t lds = (size_t)6 * B * B * B * sizeof(typename Fixed<T>::acc_t);
+  const dim3 grid((unsigned)t.ntiles);
+  if (g.shape_order == 1) {
+    allow_lds((const void*)k_scatter_tiled<T, 1>, lds);
+    hipLaunchKernelGGL((k_scatter_tiled<T, 1>), grid, dim3(256), lds, s, g, t, sp, perm, starts, v, o, stage);
+  } else {
+    allow_lds((const void*)k_scatter_tiled<T, 3>, lds);
+    hipLaunchKernelGGL((k_scatter_tiled<T, 3>), grid, dim3(256), lds, s, g, t, sp, perm, starts, v, o, stage);
+  }
+  // the overlapping boxes onto the grids (as the deposition's second launch)
+  if (g.nx % kTile == 0 && g.ny % kTile == 0 && g.nz % kTile == 0) {
+    const unsigned bz = (unsigned)std::min(256, (g.nz + 63) / 64 * 64);
+    const dim3 rgrid((unsigned)((g.nz + bz - 1) / bz), (unsigned)g.ny, (unsigned)g.nx);
+    if (g.shape_order == 1)
+      hipLaunchKernelGGL((k_deposit_reduce_whole<T, 1, 6>), rgrid, dim3(bz), 0, s, g, t, starts, stage, o);
+    else
+      hipLaunchKernelGGL((k_deposit_reduce_whole<T, 3, 6>), rgrid, dim3(bz), 0, s, g, t, starts, stage, o);
+    return;
+  }
+  const long long N = (long long)g.nx * g.ny * g.nz;
+  const unsigned nr = (unsigned)std::min<long long>((N + 255) / 256, 65536);
+  if (g.shape_order == 1)
+    hipLaunchKernelGGL((k_deposit_reduce<T, 1>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, o, 6);
+  else
+    hipLaunchKernelGGL((k_deposit_reduce<T, 3>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, o, 6);
+}
+
 #define PIC_INST(T)                                                                                              \
   template void permute_species<T>(const SpeciesView<T>&, const SpeciesView<T>&, const int*, hipStream_t);       \
   template void deposit_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*, const int*, \
@@ -1246,7 +1578,11 @@ void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, con
                                   hipStream_t);                                                                  \
   template void gather_push_tiled<T>(const GridGeom&, const TileGeom&, const T* const*, const T* const*,         \
                                      const SpeciesView<T>&, const SpeciesView<T>&, const int*, const int*, bool,  \
-                                     int*, const int*, hipStream_t);
+                                     int*, const int*, hipStream_t);                                              \
+  template void particle_adjoint<T>(const GridGeom&, const SpeciesView<T>&, const Batch<T*>&, const int*,         \
+                                    const T* const*, const T* const*, const Batch<T*>&, hipStream_t);             \
+  template void scatter_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*, const int*, \
+                                 const T* const*, T* const*, T*, hipStream_t);
 PIC_INST(float)
 PIC_INST(double)
 #undef PIC_INST

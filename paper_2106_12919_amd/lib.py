@@ -24,6 +24,7 @@ PIC_J, PIC_E, PIC_B = 0, 1, 2
 PIC_DEP_RHO_AND_J, PIC_DEP_RHO_ONLY = 0, 1
 PIC_SPECTRAL_CENTERING = 1 << 0
 PIC_NODAL_SOLVER = 1 << 1
+PIC_KEEP_ORDER = 1 << 2
 
 
 class pic_params(Structure):
@@ -42,6 +43,10 @@ class pic_fields(Structure):
     _fields_ = [("E_stag", c_void_p * 3), ("B_stag", c_void_p * 3), ("E_nod", c_void_p * 3),
                 ("B_nod", c_void_p * 3), ("J_nod", c_void_p * 3), ("J_stag", c_void_p * 3),
                 ("rho_old", c_void_p), ("rho_new", c_void_p), ("rho_static", c_void_p)]
+
+
+class pic_species_adjoint(Structure):
+    _fields_ = [("off", c_void_p * 3), ("u", c_void_p * 3)]
 
 
 _lib = None
@@ -68,6 +73,8 @@ def load():
         "psatd_push_fields_adjoint": (c_int, [c_void_p, POINTER(pic_fields)]),
         "pic_gather_push": (c_int, [c_void_p, POINTER(pic_fields), POINTER(pic_species), c_int]),
         "pic_step": (c_int, [c_void_p, POINTER(pic_fields), POINTER(pic_species), c_int, c_int]),
+        "pic_step_adjoint": (c_int, [c_void_p, POINTER(pic_fields), POINTER(pic_species), c_int,
+                                     POINTER(pic_fields), POINTER(pic_species_adjoint)]),
         "pic_sync": (c_int, [c_void_p]),
         "pic_diagnostics": (c_int, [c_void_p, POINTER(pic_fields), POINTER(c_double)]),
         "pic_profile": (c_int, [c_void_p, c_int]),
@@ -154,6 +161,16 @@ def pic_gather_push(ctx, fields, species):
 def pic_step(ctx, fields, species, nsteps=1):
     arr = _species_array(species)
     _check(load().pic_step(ctx, ctypes.byref(fields.struct()), arr, len(species), nsteps), ctx)
+
+
+def pic_step_adjoint(ctx, fields, species, adj_fields, adj_species):
+    """Reverse mode of one step: ``adj_species`` is a list of SpeciesAdjoint (same order as ``species``)."""
+    arr = _species_array(species)
+    aarr = (pic_species_adjoint * max(1, len(adj_species)))()
+    for i, a in enumerate(adj_species):
+        aarr[i] = a.struct()
+    _check(load().pic_step_adjoint(ctx, ctypes.byref(fields.struct()), arr, len(species),
+                                   ctypes.byref(adj_fields.struct()), aarr), ctx)
 
 
 def pic_sync(ctx):
@@ -250,6 +267,20 @@ class Species:
         idx = np.stack([c // (ny * nz), (c // nz) % ny, c % nz], axis=1)
         off = np.stack([o.cpu().numpy().astype(np.float64) for o in self.off], axis=1)
         return (idx + off) * np.asarray(spacing)[None, :]
+
+
+class SpeciesAdjoint:
+    """dL/d offsets (cells) and dL/du of one species: 3 + 3 contiguous device tensors."""
+
+    def __init__(self, off, u):
+        self.off, self.u = list(off), list(u)
+
+    def struct(self):
+        s = pic_species_adjoint()
+        for d in range(3):
+            s.off[d] = _ptr(self.off[d])
+            s.u[d] = _ptr(self.u[d])
+        return s
 
 
 class Fields:

@@ -1,0 +1,215 @@
+"""Reverse mode of the whole cycle on the GPU (pic_step_adjoint, autograd.PicSteps) against the
+oracle's reverse mode (itself pinned by directional differences of the oracle step), against
+central differences of the GPU forward, and across checkpoint intervals; plus the
+caller's-order forward cycle (PIC_KEEP_ORDER) it differentiates, against the oracle step."""
+
+import numpy as np
+import pytest
+
+from gpu_common import banner, max_rel, np64, oracle_species, periodic_pos_err, put, rounded
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import adjoint as oadj  # noqa: E402
+from oracle import step as ostep  # noqa: E402
+from paper_2106_12919_amd import autograd as pag  # noqa: E402
+from paper_2106_12919_amd import inputs  # noqa: E402
+from paper_2106_12919_amd import lib as piclib  # noqa: E402
+
+TD = {"f32": torch.float32, "f64": torch.float64}
+
+
+def _setup(shape, order, dtype, nodal=False, seed=7, ppc=2, field_amp=0.05, u_th=0.05):
+    wl = inputs.small(shape, ppc=ppc, shape_order=order, center_order=4, dtype=dtype, seed=seed,
+                      field_amp=field_amp, u_th=u_th)
+    flags = piclib.PIC_KEEP_ORDER | (piclib.PIC_NODAL_SOLVER if nodal else 0)
+    ctx = piclib.Context.for_workload(wl, flags=flags)
+    f = piclib.Fields(shape, dtype)
+    put(f.E_stag, rounded(wl.E, dtype))
+    put(f.B_stag, rounded(wl.B, dtype))
+    el = piclib.Species.from_host(wl.electrons, shape, dtype)
+    ions = piclib.Species.from_host(wl.ions, shape, dtype)
+    p = ostep.Params(shape, wl.spacing, wl.dt, order, wl.center_order, wl.psatd_order, nodal=nodal)
+    return wl, ctx, f, el, ions, p
+
+
+@pytest.mark.parametrize("order,nodal", [(1, False), (3, False), (3, True)])
+def test_keep_order_step_matches_oracle(order, nodal):
+    shape = (16, 16, 24)
+    banner(f"pic_step PIC_KEEP_ORDER vs oracle step, FP64, order={order} nodal={nodal} shape={shape}")
+    wl, ctx, f, el, ions, p = _setup(shape, order, "f64", nodal)
+    ctx.init_charge(f, el, ions)
+    state = {"E_stag": [np64(t) for t in f.E_stag], "B_stag": [np64(t) for t in f.B_stag],
+             "rho_old": np64(f.rho_old)}
+    sps = [oracle_species(el, shape, wl.spacing)]
+    rho_static = np64(f.rho_static)
+    piclib.pic_step(ctx.ctx, f, [el], 1)
+    piclib.pic_sync(ctx.ctx)
+    ostep.step(state, sps, p, rho_static)
+    for d in range(3):
+        assert max_rel(np64(f.E_stag[d]), state["E_stag"][d]) <= 1e-10
+        assert max_rel(np64(f.B_stag[d]), state["B_stag"][d]) <= 1e-10
+    assert max_rel(np64(f.rho_old), state["rho_old"]) <= 1e-10
+    # same particle order as the input: compare particle by particle
+    assert periodic_pos_err(el.positions(shape, wl.spacing), sps[0]["pos"], p.lengths) <= 1e-12
+    u = np.stack([np64(x) for x in el.u], axis=1)
+    assert max_rel(u, sps[0]["u"]) <= 1e-12
+    ctx.close()
+
+
+def _device_adjoint(sp, gpos, gu, spacing, dtype):
+    """SpeciesAdjoint from host arrays: dL/dpos (physical) -> dL/doff (cells)."""
+    td = TD[dtype]
+    off = [torch.from_numpy(np.ascontiguousarray(gpos[:, d] * spacing[d])).to("cuda", td) for d in range(3)]
+    u = [torch.from_numpy(np.ascontiguousarray(gu[:, d])).to("cuda", td) for d in range(3)]
+    return piclib.SpeciesAdjoint(off, u)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("order,nodal", [(1, False), (3, False), (3, True)])
+def test_step_adjoint_matches_oracle(dtype, order, nodal):
+    """Every adjoint array elementwise against the oracle's reverse mode (FP64 inputs rounded to dtype)."""
+    shape = (16, 16, 24)
+    banner(f"pic_step_adjoint vs oracle step_vjp, dtype={dtype} order={order} nodal={nodal} shape={shape}")
+    wl, ctx, f, el, ions, p = _setup(shape, order, dtype, nodal, field_amp=0.2, u_th=0.3)
+    rng = np.random.default_rng(31 + order)
+    species = [el, ions]
+    lam_host = {"E": rounded([rng.standard_normal(shape) for _ in range(3)], dtype),
+                "B": rounded([rng.standard_normal(shape) for _ in range(3)], dtype),
+                "rho": rounded([rng.standard_normal(shape)], dtype)[0], "species": []}
+    asps = []
+    for sp in species:
+        gpos = rounded([rng.standard_normal((sp.n, 3))], dtype)[0]
+        gu = rounded([rng.standard_normal((sp.n, 3))], dtype)[0]
+        lam_host["species"].append({"pos": gpos / np.asarray(wl.spacing)[None, :], "u": gu})
+        asps.append(_device_adjoint(sp, lam_host["species"][-1]["pos"], gu, wl.spacing, dtype))
+    adj = piclib.Fields(shape, dtype)
+    put(adj.E_stag, lam_host["E"])
+    put(adj.B_stag, lam_host["B"])
+    put([adj.rho_new], [lam_host["rho"]])
+    state = {"E_stag": [np64(t) for t in f.E_stag], "B_stag": [np64(t) for t in f.B_stag]}
+    osps = [oracle_species(sp, shape, wl.spacing) for sp in species]
+    piclib.pic_step_adjoint(ctx.ctx, f, species, adj, asps)
+    piclib.pic_sync(ctx.ctx)
+    ref = oadj.step_vjp(state, osps, lam_host, p)
+    # FP64: rounding of the same sums in another order; FP32: single-precision arithmetic
+    # through ~10^2-term stencil sums, the FFTs and the 22-bit fixed-point scatter
+    tol = 1e-9 if dtype == "f64" else 2e-4
+    for d in range(3):
+        assert max_rel(np64(adj.E_stag[d]), ref["E"][d]) <= tol, ("E", d)
+        assert max_rel(np64(adj.B_stag[d]), ref["B"][d]) <= tol, ("B", d)
+    assert max_rel(np64(adj.rho_old), ref["rho"]) <= tol
+    for sp, a, r in zip(species, asps, ref["species"]):
+        goff = np.stack([np64(x) for x in a.off], axis=1)
+        gu = np.stack([np64(x) for x in a.u], axis=1)
+        assert max_rel(goff, r["pos"] * np.asarray(wl.spacing)[None, :]) <= tol, "pos"
+        assert max_rel(gu, r["u"]) <= tol, "u"
+    ctx.close()
+
+
+def _run_inputs(wl, ctx, dtype):
+    f = piclib.Fields(wl.shape, dtype)
+    put(f.E_stag, rounded(wl.E, dtype))
+    put(f.B_stag, rounded(wl.B, dtype))
+    el = piclib.Species.from_host(wl.electrons, wl.shape, dtype)
+    ions = piclib.Species.from_host(wl.ions, wl.shape, dtype)
+    ctx.init_charge(f, el, ions)
+    return f, el
+
+
+def _kinetic(u, w):
+    return torch.sum(w * (torch.sqrt(1 + torch.sum(u * u, dim=0)) - 1))
+
+
+def _pic_steps(run, f, el, E, B, u):
+    return pag.PicSteps.apply(run, el.cell, el.w, E, B, f.rho_old, torch.stack(el.off), u)
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_pic_steps_gradient_matches_oracle_chain(order):
+    """Gradient of the final kinetic energy w.r.t. E^0, B^0, u^0 over 3 steps (checkpoints every 2)
+    against the oracle: its forward states, then step_vjp backwards."""
+    shape = (16, 16, 16)
+    banner(f"PicSteps gradient vs oracle chain, FP64, order={order}, 3 steps, checkpoint every 2")
+    wl = inputs.small(shape, ppc=2, shape_order=order, center_order=4, dtype="f64", seed=9, field_amp=0.2,
+                      u_th=0.3)
+    ctx = piclib.Context.for_workload(wl, flags=piclib.PIC_KEEP_ORDER)
+    f, el = _run_inputs(wl, ctx, "f64")
+    run = pag.DifferentiableRun(ctx, el.q, el.m, nsteps=3, checkpoint_every=2, rho_static=f.rho_static)
+    E = torch.stack(f.E_stag).clone().requires_grad_(True)
+    B = torch.stack(f.B_stag).clone().requires_grad_(True)
+    u = torch.stack(el.u).clone().requires_grad_(True)
+    p = ostep.Params(shape, wl.spacing, wl.dt, order, wl.center_order, wl.psatd_order)
+    state = {"E_stag": [np64(t) for t in f.E_stag], "B_stag": [np64(t) for t in f.B_stag],
+             "rho_old": np64(f.rho_old)}
+    osp = oracle_species(el, shape, wl.spacing)
+    rho_static = np64(f.rho_static)
+    out = _pic_steps(run, f, el, E, B, u)
+    loss = _kinetic(out[5], el.w)
+    loss.backward()
+    # oracle: forward keeping each step's input state, then the reverse chain
+    history = []
+    for _ in range(3):
+        history.append(({k: [np.array(a) for a in v] if isinstance(v, list) else np.array(v)
+                         for k, v in state.items()}, [dict(osp, pos=osp["pos"].copy(), u=osp["u"].copy())]))
+        ostep.step(state, [osp], p, rho_static)
+    w = osp["w"]
+    gam = np.sqrt(1 + np.sum(osp["u"] ** 2, axis=1))
+    lam = {"E": [np.zeros(shape)] * 3, "B": [np.zeros(shape)] * 3, "rho": np.zeros(shape),
+           "species": [{"pos": np.zeros_like(osp["pos"]), "u": (w / gam)[:, None] * osp["u"]}]}
+    for st, sps in reversed(history):
+        lam = oadj.step_vjp(st, sps, lam, p)
+    np.testing.assert_allclose(float(loss.detach()), float(np.sum(w * (gam - 1))), rtol=1e-10)
+    for d in range(3):
+        assert max_rel(np64(E.grad[d]), lam["E"][d]) <= 1e-8, ("E", d)
+        assert max_rel(np64(B.grad[d]), lam["B"][d]) <= 1e-8, ("B", d)
+    assert max_rel(np64(u.grad).T, lam["species"][0]["u"]) <= 1e-8
+    ctx.close()
+
+
+def test_pic_steps_gradient_against_central_differences_and_checkpoint_intervals():
+    """Laser into plasma (cubic, centering order 8) on 16x16x32 for 6 steps, FP64: <grad, delta>
+    against central differences of the GPU forward along 8 random directions in (E^0, B^0, u^0),
+    and the same gradient with checkpoints every 1, 2 and 6 steps."""
+    shape = (16, 16, 32)
+    banner(f"PicSteps vs central differences, FP64 laser {shape}, 6 steps")
+    wl = inputs.small(shape, ppc=2, shape_order=3, center_order=8, dtype="f64", seed=12, field_amp=0.0,
+                      u_th=0.0)
+    E0, B0 = inputs.laser_fields(shape, wl.spacing, 1.0, 16.0, 4.0, 30.0, 16.0)
+    wl.E, wl.B = E0, B0
+    ctx = piclib.Context.for_workload(wl, flags=piclib.PIC_KEEP_ORDER)
+    f, el = _run_inputs(wl, ctx, "f64")
+    E_in, B_in, u_in = torch.stack(f.E_stag).clone(), torch.stack(f.B_stag).clone(), torch.stack(el.u).clone()
+    cell0, off0, rho0 = el.cell.clone(), [o.clone() for o in el.off], f.rho_old.clone()
+
+    def loss_of(every, E, B, u):
+        run = pag.DifferentiableRun(ctx, el.q, el.m, nsteps=6, checkpoint_every=every, rho_static=f.rho_static)
+        out = pag.PicSteps.apply(run, cell0, el.w, E, B, rho0, torch.stack(off0), u)
+        return _kinetic(out[5], el.w)
+
+    grads = {}
+    for every in (2, 1, 6):
+        E = E_in.clone().requires_grad_(True)
+        B = B_in.clone().requires_grad_(True)
+        u = u_in.clone().requires_grad_(True)
+        loss_of(every, E, B, u).backward()
+        grads[every] = (E.grad.clone(), B.grad.clone(), u.grad.clone())
+    for every in (1, 6):
+        for a, b in zip(grads[every], grads[2]):
+            assert max_rel(np64(a), np64(b)) <= 1e-12
+    gE, gB, gu = grads[2]
+    rng = np.random.default_rng(40)
+    h = 1e-5
+    for k in range(8):
+        dE = torch.from_numpy(rng.standard_normal(tuple(E_in.shape))).to(E_in) * E_in.abs().max()
+        dB = torch.from_numpy(rng.standard_normal(tuple(B_in.shape))).to(B_in) * B_in.abs().max()
+        du = torch.from_numpy(rng.standard_normal(tuple(u_in.shape))).to(u_in) * 0.05
+        with torch.no_grad():
+            lp = float(loss_of(6, E_in + h * dE, B_in + h * dB, u_in + h * du))
+            lm = float(loss_of(6, E_in - h * dE, B_in - h * dB, u_in - h * du))
+        fd = (lp - lm) / (2 * h)
+        an = float(torch.sum(gE * dE) + torch.sum(gB * dB) + torch.sum(gu * du))
+        assert abs(fd - an) <= 1e-6 * abs(an) + 1e-12, (k, fd, an)
+    ctx.close()
