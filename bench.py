@@ -152,6 +152,11 @@ def main():
     ap.add_argument("--field-adjoint", action="store_true",
                     help="also time psatd_push_fields and its reverse mode psatd_push_fields_adjoint "
                          "(\"field_solve\" in the JSON line)")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the forward+backward measurement of the differentiable workload (laser64, FP32, "
+                         "60 steps, kinetic-energy loss, checkpoints every 10 steps)")
+    ap.add_argument("--adjoint-config", default="laser64", choices=sorted(CONFIG_TEXT))
+    ap.add_argument("--checkpoint-every", type=int, default=10)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy a MIB-MiB float32 tensor 3 times (a plain copy kernel "
                          "of known size, the reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -174,6 +179,9 @@ def main():
     result = run_gpu(wl, args.config, args.steps, args.warmup, args.calibrate_copy, flags)
     if args.field_adjoint:
         result["field_solve"] = time_field_solve(wl, flags)
+    if not args.no_adjoint:
+        print(f"[bench] forward+backward of {args.adjoint_config} ...", file=sys.stderr, flush=True)
+        result["fwd_bwd"] = time_fwd_bwd(args.adjoint_config, args.checkpoint_every)
     if args.sweep_center_orders:
         for order in [int(x) for x in args.sweep_center_orders.split(",")]:
             wl.center_order = order
@@ -214,6 +222,89 @@ def time_field_solve(wl, flags, reps=20):
     ctx.close()
     out["adjoint_over_forward"] = round(out["adjoint_ms"] / out["forward_ms"], 3)
     return out
+
+
+def time_fwd_bwd(config_name, every, reps=3):
+    """Forward + backward of the differentiable workload: its full run (``steps`` of the config)
+    through autograd.PicSteps with checkpoints every ``every`` steps, the loss being the total
+    electron kinetic energy sum w (gamma - 1) at the end, gradients w.r.t. the initial E, B and
+    momenta; set against the same run of the production forward (pic_step, default flags).
+    Means of ``reps`` timed runs after one untimed run."""
+    import torch
+
+    from paper_2106_12919_amd import autograd as pag
+    from paper_2106_12919_amd import inputs
+    from paper_2106_12919_amd import lib as piclib
+
+    wl = inputs.config(config_name)
+    K = wl.steps
+
+    def setup(flags):
+        ctx = piclib.Context.for_workload(wl, flags=flags)
+        f = ctx.fields_from_workload(wl)
+        el = piclib.Species.from_host(wl.electrons, wl.shape, wl.dtype)
+        ions = piclib.Species.from_host(wl.ions, wl.shape, wl.dtype)
+        ctx.init_charge(f, el, ions)
+        return ctx, f, el
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    ctx0, f0, el0 = setup(0)
+    state0 = ([t.clone() for t in f0.E_stag], [t.clone() for t in f0.B_stag], f0.rho_old.clone(),
+              el0.cell.clone(), [t.clone() for t in el0.off], [t.clone() for t in el0.u])
+
+    def forward_only():
+        for d in range(3):
+            f0.E_stag[d].copy_(state0[0][d])
+            f0.B_stag[d].copy_(state0[1][d])
+            el0.off[d].copy_(state0[4][d])
+            el0.u[d].copy_(state0[5][d])
+        f0.rho_old.copy_(state0[2])
+        el0.cell.copy_(state0[3])
+        piclib.pic_step(ctx0.ctx, f0, [el0], K)
+
+    T_fwd = timed(forward_only)
+    ctx0.close()
+    ctx, f, el = setup(piclib.PIC_KEEP_ORDER)
+    E_in, B_in, u_in = torch.stack(f.E_stag), torch.stack(f.B_stag), torch.stack(el.u)
+    off_in = torch.stack(el.off)
+    grads = {}
+
+    def fwd_bwd():
+        run = pag.DifferentiableRun(ctx, el.q, el.m, nsteps=K, checkpoint_every=every, rho_static=f.rho_static)
+        E = E_in.clone().requires_grad_(True)
+        B = B_in.clone().requires_grad_(True)
+        u = u_in.clone().requires_grad_(True)
+        out = pag.PicSteps.apply(run, el.cell, el.w, E, B, f.rho_old, off_in, u)
+        uf = out[5]
+        loss = torch.sum(el.w * (torch.sqrt(1 + torch.sum(uf * uf, dim=0)) - 1))
+        loss.backward()
+        grads["loss"] = float(loss.detach())
+        grads["norm"] = float(torch.sqrt(torch.sum(E.grad ** 2) + torch.sum(B.grad ** 2) + torch.sum(u.grad ** 2)))
+
+    T_fb = timed(fwd_bwd)
+    piclib.pic_stage_times(ctx.ctx)  # reset
+    piclib.pic_profile(ctx.ctx, True)
+    fwd_bwd()
+    torch.cuda.synchronize()
+    stages = piclib.pic_stage_times(ctx.ctx)
+    piclib.pic_profile(ctx.ctx, False)
+    ctx.close()
+    Np = wl.electrons.n
+    return {"workload": CONFIG_TEXT[config_name], "dtype": wl.dtype, "steps": K, "checkpoint_every": every,
+            "loss": "sum w (gamma - 1) at the end; gradients w.r.t. initial E, B (Yee) and u",
+            "forward_ms_per_step": round(1e3 * T_fwd / K, 4), "fwd_bwd_ms_per_step": round(1e3 * T_fb / K, 4),
+            "fwd_bwd_over_forward": round(T_fb / T_fwd, 3),
+            "fwd_bwd_particle_pushes_per_s": Np * K / T_fb, "fwd_bwd_cell_updates_per_s": wl.cells * K / T_fb,
+            "loss_value": grads["loss"], "grad_norm": grads["norm"],
+            "stage_ms_total_one_run": {k: round(v[0], 3) for k, v in stages.items() if v[1]}}
 
 
 def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0):

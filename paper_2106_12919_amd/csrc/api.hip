@@ -879,7 +879,7 @@ pic_status do_step_adjoint(pic_ctx c, pic_fields* f, const pic_species* sp, int 
     }
     {
       StageScope sc(c, ST_PUSH);
-      particle_adjoint<T>(g, v, lam, x.perm, F, L, lamF, c->stream);
+      particle_adjoint<T>(g, e.tiles, v, lam, x.perm, x.starts[0], F, L, lamF, c->stream);
     }
     if (std::isfinite(sp[q].m)) {
       StageScope sc(c, ST_DEPOSIT);

@@ -145,15 +145,18 @@ template <typename T>
 void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, const T* stage, bool with_j, T* rho,
                     T* const J[3], hipStream_t s);
 
-// Reverse mode of gather + push + move + deposition of one species, one particle per
-// thread in slot order (slot q -> particle perm[q]; perm == nullptr: q), particles at time n.
+// Reverse mode of gather + push + move + deposition of one species, particles at time n
+// visited in slot order (slot q -> particle perm[q]; perm == nullptr: q); with the tile
+// grouping of their cells (starts != nullptr) one workgroup per tile reads the fields from
+// LDS boxes when they fit, else one particle per thread reads them from the grids.
 // lam[0..2] (dL/d offsets, cells) and lam[3..5] (dL/du) hold the adjoints of x^{n+1}, u^{n+1/2}
 // and receive those of x^n, u^{n-1/2}.  F: nodal E (0..2) and B (3..5) of the state at n;
 // L: dL/drho^{n+1} (0) and dL/dJ_nod (1..3).  lamF[0..5][p] receives dL/d(E_p, B_p), the
 // adjoints of the fields gathered at the particle (zero for immobile species).
 template <typename T>
-void particle_adjoint(const GridGeom& g, const SpeciesView<T>& sp, const Batch<T*>& lam, const int* perm,
-                      const T* const F[6], const T* const L[4], const Batch<T*>& lamF, hipStream_t s);
+void particle_adjoint(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const Batch<T*>& lam,
+                      const int* perm, const int* starts, const T* const F[6], const T* const L[4],
+                      const Batch<T*>& lamF, hipStream_t s);
 // out[v] += sum_p val[v][p] S(x_p - x_i), v = 0..5 (the transpose of the gather), with the
 // grouping (perm, starts) of the particles' current cells; stage: ntiles * 6 * deposit_box^3.
 template <typename T>

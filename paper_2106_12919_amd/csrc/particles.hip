@@ -1184,10 +1184,52 @@ __device__ inline void stencil_sums(const GridGeom& g, int i, int j, int k, T ox
   }
 }
 
-// Reverse mode of gather + Boris push + move + deposition for one particle per thread
-// (slot q -> particle perm[q]).  The forward quantities are recomputed from the particle
-// at time n with the forward's own functions; then, with c = q w / dV, hdt = dt / (2 dx)
-// and dtc = dt / dx per axis (positions in cells):
+// The same sums from an LDS box holding FS slots per node (components C0.. of the node
+// adjacent); ``at`` is the box index of the first support node.
+template <typename T, int ORDER, int NV, int FS, int C0>
+__device__ inline void box_stencil_sums(const T* box, int at, T ox, T oy, T oz, T* val, T (*grad)[3]) {
+  using S = Shape<T, ORDER>;
+  using X = Box<S::NW>;
+  constexpr int NW = S::NW;
+  T wx[NW], wy[NW], wz[NW], gx[NW], gy[NW], gz[NW];
+  S::weights(ox, wx);
+  S::weights(oy, wy);
+  S::weights(oz, wz);
+  S::dweights(ox, gx);
+  S::dweights(oy, gy);
+  S::dweights(oz, gz);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    val[v] = 0;
+    grad[v][0] = grad[v][1] = grad[v][2] = 0;
+  }
+  const T* b0 = box + (size_t)at * FS + C0;
+#pragma unroll
+  for (int a = 0; a < NW; ++a) {
+#pragma unroll
+    for (int b = 0; b < NW; ++b) {
+      const T wab = wx[a] * wy[b], gxab = gx[a] * wy[b], gyab = wx[a] * gy[b];
+#pragma unroll
+      for (int c = 0; c < NW; ++c) {
+        const T w = wab * wz[c], dx = gxab * wz[c], dy = gyab * wz[c], dz = wab * gz[c];
+        const T* nd = b0 + (a * X::B2 + b * X::B + c) * FS;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const T x = nd[v];
+          val[v] += w * x;
+          grad[v][0] += dx * x;
+          grad[v][1] += dy * x;
+          grad[v][2] += dz * x;
+        }
+      }
+    }
+  }
+}
+
+// Reverse mode of gather + Boris push + move + deposition of particle p at time n (cell
+// (i, j, k) decoded).  The forward quantities are recomputed with the forward's own
+// functions; then, with c = q w / dV, hdt = dt / (2 dx) and dtc = dt / dx per axis
+// (positions in cells):
 //   deposition: rho^{n+1} = c S(x^{n+1}), J^{n+1/2} = c v S(x^{n+1} - hdt v)
 //     lx1 = lx + c sum lrho grad S(x^{n+1}) + G,   G = c sum (lJ . v) grad S(x^{n+1/2})
 //     lv  = c sum lJ S(x^{n+1/2}) - hdt G + dtc lx1          (x^{n+1} = x^n + dtc v)
@@ -1198,27 +1240,18 @@ __device__ inline void stencil_sums(const GridGeom& g, int i, int j, int k, T ox
 //   gather: lx^n = lx1 + sum_m lF_m grad F_m(x^n);  lF = (lE, lB) goes to lamF for the
 //   scatter onto the nodal grids.
 // Immobile species (never pushed, rho only): lx += c sum lrho grad S(x).
-template <typename T, int ORDER>
-__global__ void __launch_bounds__(256) k_particle_adjoint(GridGeom g, SpeciesView<T> sp, Batch<T*> lam,
-                                                          const int* __restrict__ perm, Batch<const T*> F,
-                                                          Batch<const T*> L, Batch<T*> lamF, T qdt2m, T qdv, T dtx,
-                                                          T dty, T dtz, int mobile) {
-  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= sp.n) return;
-  const int p = perm ? perm[q] : (int)q;
-  int i, j, k;
-  if (!decode_cell(sp.cell[p], g, nullptr, i, j, k)) {  // never pushed nor deposited: adjoint passes through
-#pragma unroll
-    for (int m = 0; m < 6; ++m) lamF.p[m][p] = 0;
-    return;
-  }
+// The stencil sums come from the samplers: sF(i, j, k, o.., f, gf) over E, B (6) and
+// sL<C0, NV>(i, j, k, o.., val, grad) over the adjoint sources (rho 0, J 1..3).
+template <typename T, int ORDER, class SF, class SL1, class SL3>
+__device__ inline void adjoint_one(const GridGeom& g, const SpeciesView<T>& sp, const Batch<T*>& lam,
+                                   const Batch<T*>& lamF, int p, int i, int j, int k, T qdt2m, T qdv, T dtx, T dty,
+                                   T dtz, bool mobile, SF sF, SL1 sRho, SL3 sJ) {
   const T ox = sp.off[0][p], oy = sp.off[1][p], oz = sp.off[2][p];
   const T c = qdv * (sp.w ? sp.w[p] : (T)sp.w_const);
   T lx[3] = {lam.p[0][p], lam.p[1][p], lam.p[2][p]};
-  const T* Lrho[1] = {L.p[0]};
   if (!mobile) {
     T rv[1], rg[1][3];
-    stencil_sums<T, ORDER, 1>(g, i, j, k, ox, oy, oz, Lrho, rv, rg);
+    sRho(i, j, k, ox, oy, oz, rv, rg);
 #pragma unroll
     for (int a = 0; a < 3; ++a) lam.p[a][p] = lx[a] + c * rg[0][a];
 #pragma unroll
@@ -1228,7 +1261,7 @@ __global__ void __launch_bounds__(256) k_particle_adjoint(GridGeom g, SpeciesVie
   const T lu[3] = {lam.p[3][p], lam.p[4][p], lam.p[5][p]};
   // forward: gather at x^n (with gradients), push, move
   T f[6], gf[6][3];
-  stencil_sums<T, ORDER, 6>(g, i, j, k, ox, oy, oz, F.p, f, gf);
+  sF(i, j, k, ox, oy, oz, f, gf);
   T ux = sp.u[0][p], uy = sp.u[1][p], uz = sp.u[2][p];
   BorisState<T> b;
   boris(f, qdt2m, ux, uy, uz, b);
@@ -1245,9 +1278,8 @@ __global__ void __launch_bounds__(256) k_particle_adjoint(GridGeom g, SpeciesVie
   const int kh = wrapi(k1 + advance_offset(hz, -hd[2] * v[2]), g.nz);
   // deposition
   T rv[1], rg[1][3], jv[3], jg[3][3];
-  stencil_sums<T, ORDER, 1>(g, i1, j1, k1, o1x, o1y, o1z, Lrho, rv, rg);
-  const T* LJ[3] = {L.p[1], L.p[2], L.p[3]};
-  stencil_sums<T, ORDER, 3>(g, ih, jh, kh, hx, hy, hz, LJ, jv, jg);
+  sRho(i1, j1, k1, o1x, o1y, o1z, rv, rg);
+  sJ(ih, jh, kh, hx, hy, hz, jv, jg);
   const T dtc[3] = {dtx, dty, dtz};
   T lx1[3], lv[3];
 #pragma unroll
@@ -1291,23 +1323,141 @@ __global__ void __launch_bounds__(256) k_particle_adjoint(GridGeom g, SpeciesVie
   for (int m = 0; m < 6; ++m) lamF.p[m][p] = lF[m];
 }
 
+// One particle per thread (slot q -> particle perm[q]), every stencil read from the grids.
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(256) k_particle_adjoint(GridGeom g, SpeciesView<T> sp, Batch<T*> lam,
+                                                          const int* __restrict__ perm, Batch<const T*> F,
+                                                          Batch<const T*> L, Batch<T*> lamF, T qdt2m, T qdv, T dtx,
+                                                          T dty, T dtz, int mobile) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= sp.n) return;
+  const int p = perm ? perm[q] : (int)q;
+  int i, j, k;
+  if (!decode_cell(sp.cell[p], g, nullptr, i, j, k)) {  // never pushed nor deposited: adjoint passes through
+#pragma unroll
+    for (int m = 0; m < 6; ++m) lamF.p[m][p] = 0;
+    return;
+  }
+  const T* LJ[3] = {L.p[1], L.p[2], L.p[3]};
+  auto sF = [&](int a, int b, int c, T x, T y, T z, T* val, T (*grad)[3]) {
+    stencil_sums<T, ORDER, 6>(g, a, b, c, x, y, z, F.p, val, grad);
+  };
+  auto sRho = [&](int a, int b, int c, T x, T y, T z, T* val, T (*grad)[3]) {
+    stencil_sums<T, ORDER, 1>(g, a, b, c, x, y, z, L.p, val, grad);
+  };
+  auto sJ = [&](int a, int b, int c, T x, T y, T z, T* val, T (*grad)[3]) {
+    stencil_sums<T, ORDER, 3>(g, a, b, c, x, y, z, LJ, val, grad);
+  };
+  adjoint_one<T, ORDER>(g, sp, lam, lamF, p, i, j, k, qdt2m, qdv, dtx, dty, dtz, mobile != 0, sF, sRho, sJ);
+}
+
+// One block per tile of the grouping of the particles' cells at n (slots [starts[t],
+// starts[t+1]) through perm): E, B (FieldSlots layout) and the adjoint sources rho, J
+// (4 slots per node) staged over the tile's box in LDS.  x^n, x^{n+1} and x^{n+1/2} lie
+// within one cell of the tile, inside the box; anything outside is read from the grids.
+// Block ntiles passes the particles with invalid cells through.
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_particle_adjoint_tiled(
+    GridGeom g, TileGeom tg, SpeciesView<T> sp, Batch<T*> lam, const int* __restrict__ perm,
+    const int* __restrict__ starts, Batch<const T*> F, Batch<const T*> L, Batch<T*> lamF, T qdt2m, T qdv, T dtx,
+    T dty, T dtz, int mobile) {
+  using S = Shape<T, ORDER>;
+  using X = Box<S::NW>;
+  constexpr int FS = FieldSlots<T>::FS;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* fbox = reinterpret_cast<T*>(smem);
+  T* lbox = fbox + (size_t)X::B3 * FS;
+  const int tile = xcd_major(blockIdx.x, gridDim.x);
+  const int beg = starts[tile], end = starts[tile + 1];
+  if (beg == end) return;
+  if (tile == tg.ntiles) {
+    for (int q = beg + threadIdx.x; q < end; q += blockDim.x) {
+      const int p = perm[q];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) lamF.p[m][p] = 0;
+    }
+    return;
+  }
+  int tx, ty, tz;
+  tile_coords(tile, tg, tx, ty, tz);
+  const int t0x = tx * kTile, t0y = ty * kTile, t0z = tz * kTile;
+  if (mobile) load_field_box<T, ORDER>(fbox, F, g, t0x, t0y, t0z);
+  {
+    constexpr int PER = (X::B3 + PIC_GATHER_BLOCK - 1) / PIC_GATHER_BLOCK;
+    const int ox0 = t0x - 1 + S::BASE, oy0 = t0y - 1 + S::BASE, oz0 = t0z - 1 + S::BASE;
+    T v[PER][4];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = min((int)threadIdx.x + u * PIC_GATHER_BLOCK, X::B3 - 1);
+      const int lx = e / X::B2, ly = (e / X::B) % X::B, lz = e % X::B;
+      const size_t gi = ((size_t)wrap3(ox0 + lx, g.nx) * g.ny + wrap3(oy0 + ly, g.ny)) * g.nz + wrap3(oz0 + lz, g.nz);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[u][c] = L.p[c][gi];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = (int)threadIdx.x + u * PIC_GATHER_BLOCK;
+      if (e < X::B3) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) lbox[e * 4 + c] = v[u][c];
+      }
+    }
+  }
+  __syncthreads();
+  const T* LJ[3] = {L.p[1], L.p[2], L.p[3]};
+  auto at_of = [&](int a, int b, int c) {
+    const int lx = box_index(a, t0x, g.nx), ly = box_index(b, t0y, g.ny), lz = box_index(c, t0z, g.nz);
+    return (lx >= 0 && ly >= 0 && lz >= 0) ? X::at(lx, ly, lz) : -1;
+  };
+  auto sF = [&](int a, int b, int c, T x, T y, T z, T* val, T (*grad)[3]) {
+    const int at = at_of(a, b, c);
+    if (at >= 0) box_stencil_sums<T, ORDER, 6, FS, 0>(fbox, at, x, y, z, val, grad);
+    else stencil_sums<T, ORDER, 6>(g, a, b, c, x, y, z, F.p, val, grad);
+  };
+  auto sRho = [&](int a, int b, int c, T x, T y, T z, T* val, T (*grad)[3]) {
+    const int at = at_of(a, b, c);
+    if (at >= 0) box_stencil_sums<T, ORDER, 1, 4, 0>(lbox, at, x, y, z, val, grad);
+    else stencil_sums<T, ORDER, 1>(g, a, b, c, x, y, z, L.p, val, grad);
+  };
+  auto sJ = [&](int a, int b, int c, T x, T y, T z, T* val, T (*grad)[3]) {
+    const int at = at_of(a, b, c);
+    if (at >= 0) box_stencil_sums<T, ORDER, 3, 4, 1>(lbox, at, x, y, z, val, grad);
+    else stencil_sums<T, ORDER, 3>(g, a, b, c, x, y, z, LJ, val, grad);
+  };
+  for (int q = beg + threadIdx.x; q < end; q += blockDim.x) {
+    const int p = perm[q];
+    int i, j, k;
+    (void)decode_cell(sp.cell[p], g, nullptr, i, j, k);
+    adjoint_one<T, ORDER>(g, sp, lam, lamF, p, i, j, k, qdt2m, qdv, dtx, dty, dtz, mobile != 0, sF, sRho, sJ);
+  }
+}
+
 // Six per-particle values val_v[p] spread with the particle's shape at its position onto
 // nodal grids: one block per tile of the grouping (slots [starts[t], starts[t+1]) through
 // perm), accumulated in a fixed-point LDS box per component (scales from the tile's sum and
 // max of |val_v|, as in the deposition) and stored to the tile's staging slot for
 // k_deposit_reduce*; a particle outside the box margin goes to the grids with atomics.
+// The particles of each chunk are dealt over the residues of their first support node, as
+// in the deposition, so that the lanes of a wave hit distinct LDS banks.
 template <typename T, int ORDER>
 __global__ void __launch_bounds__(256) k_scatter_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp,
                                                        const int* __restrict__ perm, const int* __restrict__ starts,
                                                        Batch<const T*> val, Batch<T*> out, T* __restrict__ stage) {
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
+  using O = DepositOrder<T>;
   constexpr int NV = 6;
   constexpr int kWaves = 256 / 64;
   extern __shared__ __align__(16) unsigned char smem[];
   auto* box = reinterpret_cast<typename Fixed<T>::acc_t*>(smem);
   __shared__ T red[NV * kWaves], redm[NV * kWaves];
   __shared__ int shs[NV];
+  __shared__ int wtot[kWaves];
+  __shared__ __align__(16) int hist[O::KG];
+  __shared__ unsigned short kr[O::CH];
+  __shared__ unsigned short order[O::CH];
+  __shared__ unsigned rowmask[O::RMAX];
+  __shared__ int rowstart[O::RMAX];
   const int tile = xcd_major(blockIdx.x, gridDim.x);
   const int beg = starts[tile], end = starts[tile + 1];
   if (beg == end) return;
@@ -1355,25 +1505,71 @@ __global__ void __launch_bounds__(256) k_scatter_tiled(GridGeom g, TileGeom tg, 
   int sh[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) sh[v] = shs[v];
-  for (int q = beg + threadIdx.x; q < end; q += blockDim.x) {
-    const int p = perm ? perm[q] : q;
-    int i, j, k;
-    if (!decode_cell(sp.cell[p], g, nullptr, i, j, k)) continue;
-    const T ox = sp.off[0][p], oy = sp.off[1][p], oz = sp.off[2][p];
-    T x[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) x[v] = val.p[v][p];
+  auto box_at = [&](int p, int& i, int& j, int& k) {  // -2: invalid cell, -1: outside the box
+    if (!decode_cell(sp.cell[p], g, nullptr, i, j, k)) return -2;
     const int lx = box_index(i, t0x, g.nx), ly = box_index(j, t0y, g.ny), lz = box_index(k, t0z, g.nz);
-    if (lx >= 0 && ly >= 0 && lz >= 0) {
-      T sv[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sv[v] = ldexp(x[v], sh[v]);
-      scatter_lds<T, ORDER, NV>(box, X::at(lx, ly, lz), ox, oy, oz, sv);
-    } else {
-      scatter<T, ORDER>(g, i, j, k, ox, oy, oz, out.p, x, NV);
+    return (lx >= 0 && ly >= 0 && lz >= 0) ? X::at(lx, ly, lz) : -1;
+  };
+  for (int cb = beg; cb < end; cb += O::CH) {
+    const int nc = min(O::CH, end - cb);
+    if (threadIdx.x < O::KG) hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < nc; e += blockDim.x) {
+      const int p = perm ? perm[cb + e] : cb + e;
+      int i, j, k;
+      const int at = box_at(p, i, j, k);
+      const int key = at >= 0 ? (at & (O::KG - 1)) : 0;
+      const int rk = atomicAdd(&hist[key], 1);
+      kr[e] = (unsigned short)(rk * O::KG + key);
     }
+    __syncthreads();
+    int R = 0;
+#pragma unroll
+    for (int k = 0; k < O::KG; k += 4) {
+      const int4 h4 = *reinterpret_cast<const int4*>(&hist[k]);
+      R = max(R, max(max(h4.x, h4.y), max(h4.z, h4.w)));
+    }
+    if (R > O::RMAX) R = 0;  // too uneven to deal: stored order
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+      unsigned m = 0;
+#pragma unroll 4
+      for (int k = 0; k < O::KG; ++k) m |= (hist[k] > r ? 1u : 0u) << k;
+      rowmask[r] = m;
+      rowstart[r] = __popc(m);
+    }
+    __syncthreads();
+    block_exclusive_scan(rowstart, R, wtot);
+    for (int e = threadIdx.x; e < nc; e += blockDim.x) {
+      if (R == 0) {
+        order[e] = (unsigned short)e;
+      } else {
+        const int v = kr[e];
+        const int r = v / O::KG, key = v % O::KG;
+        order[rowstart[r] + __popc(rowmask[r] & ((1u << key) - 1u))] = (unsigned short)e;
+      }
+    }
+    __syncthreads();
+    for (int pos = threadIdx.x; pos < nc; pos += blockDim.x) {
+      const int e = order[pos];
+      const int p = perm ? perm[cb + e] : cb + e;
+      int i, j, k;
+      const int at = box_at(p, i, j, k);
+      if (at == -2) continue;
+      const T ox = sp.off[0][p], oy = sp.off[1][p], oz = sp.off[2][p];
+      T x[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) x[v] = val.p[v][p];
+      if (at >= 0) {
+        T sv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sv[v] = ldexp(x[v], sh[v]);
+        scatter_lds<T, ORDER, NV>(box, at, ox, oy, oz, sv);
+      } else {
+        scatter<T, ORDER>(g, i, j, k, ox, oy, oz, out.p, x, NV);
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
   T* dstage = stage + (size_t)tile * NV * X::B3;
   for (int e = threadIdx.x; e < NV * X::B3; e += blockDim.x) dstage[e] = ldexp((T)box[e], -shs[e / X::B3]);
 }
@@ -1513,8 +1709,9 @@ void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, con
 }
 
 template <typename T>
-void particle_adjoint(const GridGeom& g, const SpeciesView<T>& sp, const Batch<T*>& lam, const int* perm,
-                      const T* const F[6], const T* const L[4], const Batch<T*>& lamF, hipStream_t s) {
+void particle_adjoint(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const Batch<T*>& lam,
+                      const int* perm, const int* starts, const T* const F[6], const T* const L[4],
+                      const Batch<T*>& lamF, hipStream_t s) {
   if (sp.n <= 0) return;
   Batch<const T*> f{}, l{};
   for (int m = 0; m < 6; ++m) f.p[m] = F[m];
@@ -1523,13 +1720,30 @@ void particle_adjoint(const GridGeom& g, const SpeciesView<T>& sp, const Batch<T
   const T qdt2m = mobile ? (T)(sp.q * g.dt / (2.0 * sp.m)) : (T)0;
   const T qdv = (T)(sp.q / (g.dx * g.dy * g.dz));
   const T dtx = (T)(g.dt / g.dx), dty = (T)(g.dt / g.dy), dtz = (T)(g.dt / g.dz);
+  const int mob = mobile ? 1 : 0;
+  // LDS-staged boxes (E, B and the 4 adjoint sources) when they fit a workgroup's LDS
+  const int Bx = deposit_box(g.shape_order);
+  const size_t lds = (size_t)Bx * Bx * Bx * (FieldSlots<T>::FS + 4) * sizeof(T);
+  if (starts && lds <= 160 * 1024) {
+    const dim3 grid((unsigned)t.ntiles + 1);
+    if (g.shape_order == 1) {
+      allow_lds((const void*)k_particle_adjoint_tiled<T, 1>, lds);
+      hipLaunchKernelGGL((k_particle_adjoint_tiled<T, 1>), grid, dim3(PIC_GATHER_BLOCK), lds, s, g, t, sp, lam, perm,
+                         starts, f, l, lamF, qdt2m, qdv, dtx, dty, dtz, mob);
+    } else {
+      allow_lds((const void*)k_particle_adjoint_tiled<T, 3>, lds);
+      hipLaunchKernelGGL((k_particle_adjoint_tiled<T, 3>), grid, dim3(PIC_GATHER_BLOCK), lds, s, g, t, sp, lam, perm,
+                         starts, f, l, lamF, qdt2m, qdv, dtx, dty, dtz, mob);
+    }
+    return;
+  }
   const dim3 grid((unsigned)((sp.n + 255) / 256));
   if (g.shape_order == 1)
     hipLaunchKernelGGL((k_particle_adjoint<T, 1>), grid, dim3(256), 0, s, g, sp, lam, perm, f, l, lamF, qdt2m, qdv,
-                       dtx, dty, dtz, mobile ? 1 : 0);
+                       dtx, dty, dtz, mob);
   else
     hipLaunchKernelGGL((k_particle_adjoint<T, 3>), grid, dim3(256), 0, s, g, sp, lam, perm, f, l, lamF, qdt2m, qdv,
-                       dtx, dty, dtz, mobile ? 1 : 0);
+                       dtx, dty, dtz, mob);
 }
 
 template <typename T>
@@ -1579,8 +1793,9 @@ void scatter_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& s
   template void gather_push_tiled<T>(const GridGeom&, const TileGeom&, const T* const*, const T* const*,         \
                                      const SpeciesView<T>&, const SpeciesView<T>&, const int*, const int*, bool,  \
                                      int*, const int*, hipStream_t);                                              \
-  template void particle_adjoint<T>(const GridGeom&, const SpeciesView<T>&, const Batch<T*>&, const int*,         \
-                                    const T* const*, const T* const*, const Batch<T*>&, hipStream_t);             \
+  template void particle_adjoint<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const Batch<T*>&,    \
+                                    const int*, const int*, const T* const*, const T* const*, const Batch<T*>&,   \
+                                    hipStream_t);                                                                 \
   template void scatter_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*, const int*, \
                                  const T* const*, T* const*, T*, hipStream_t);
 PIC_INST(float)

@@ -27,28 +27,50 @@ __device__ inline int tile_key(int c, const GridGeom& g, const TileGeom& t) {
 
 // Adds one per valid lane to counters[key]; returns each lane's previous-value
 // slot (counter value before the lane's increment, lanes of one key in lane order).
+// The lanes are first grouped by key (ballots only); then the first lane of every group
+// issues the group's atomic, all groups' atomics in the same instruction, so a wave waits
+// for one atomic round trip however many distinct keys it holds.
 __device__ inline int wave_aggregated_add(int* counters, int key, bool valid) {
   unsigned long long active = __ballot(valid);
   const int lane = __lane_id();
-  int slot = -1;
+  int leader_of = lane, rank = 0, group = 0;
   while (active) {
     const int leader = __ffsll((unsigned long long)active) - 1;
     const int lkey = __shfl(key, leader);
     const unsigned long long same = __ballot(valid && key == lkey) & active;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&counters[lkey], __popcll(same));
-    base = __shfl(base, leader);
-    if ((same >> lane) & 1ull) slot = base + __popcll(same & ((1ull << lane) - 1ull));
+    if ((same >> lane) & 1ull) {
+      leader_of = leader;
+      rank = __popcll(same & ((1ull << lane) - 1ull));
+    }
+    if (lane == leader) group = __popcll(same);
     active &= ~same;
   }
-  return slot;
+  int base = 0;
+  if (valid && lane == leader_of) base = atomicAdd(&counters[key], group);
+  base = __shfl(base, leader_of);
+  return valid ? base + rank : -1;
+}
+
+// The same count without the slots: the atomics' results are not waited for.
+__device__ inline void wave_aggregated_count(int* counters, int key, bool valid) {
+  unsigned long long active = __ballot(valid);
+  const int lane = __lane_id();
+  int group = 0;
+  while (active) {
+    const int leader = __ffsll((unsigned long long)active) - 1;
+    const int lkey = __shfl(key, leader);
+    const unsigned long long same = __ballot(valid && key == lkey) & active;
+    if (lane == leader) group = __popcll(same);
+    active &= ~same;
+  }
+  if (group > 0) atomicAdd(&counters[key], group);
 }
 
 __global__ void __launch_bounds__(256) k_tile_count(GridGeom g, TileGeom t, const int32_t* __restrict__ cell, long long n,
                                                     int* counts) {
   const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int key = (p < n) ? tile_key(cell[p], g, t) : 0;
-  (void)wave_aggregated_add(counts, key, p < n);
+  wave_aggregated_count(counts, key, p < n);
 }
 
 __global__ void __launch_bounds__(256) k_tile_rank(GridGeom g, TileGeom t, const int32_t* __restrict__ cell, long long n,
@@ -59,6 +81,65 @@ __global__ void __launch_bounds__(256) k_tile_rank(GridGeom g, TileGeom t, const
   if (p < n) {
     if (key == t.ntiles && bad) atomicAdd(bad, 1);
     dst[p] = slot;
+  }
+}
+
+// The same two passes with a per-workgroup histogram in LDS (grids of at most
+// kSortMaxBuckets - 1 tiles): each workgroup counts its kSortBlock * kSortPer particles
+// per tile in LDS and touches each global counter once per tile it holds, so a counter
+// sees a few atomics per step instead of one per wave (atomics on one address serialise).
+// For the ranks, a workgroup reserves one run per tile on ``cursor`` and places its
+// particles in the run by their LDS ranks.
+constexpr int kSortBlock = 1024, kSortPer = 8;
+constexpr int kSortMaxBuckets = 32768;  // 128 KiB of LDS counters
+
+__global__ void __launch_bounds__(kSortBlock) k_tile_count_lds(GridGeom g, TileGeom t, const int32_t* __restrict__ cell,
+                                                               long long n, int* counts) {
+  extern __shared__ int hist[];
+  const int nbk = t.ntiles + 1;
+  for (int e = threadIdx.x; e < nbk; e += blockDim.x) hist[e] = 0;
+  __syncthreads();
+  const long long p0 = (long long)blockIdx.x * kSortBlock * kSortPer + threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kSortPer; ++u) {
+    const long long p = p0 + (long long)u * kSortBlock;
+    const int key = (p < n) ? tile_key(cell[p], g, t) : 0;
+    wave_aggregated_count(hist, key, p < n);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nbk; e += blockDim.x) {
+    const int c = hist[e];
+    if (c) atomicAdd(&counts[e], c);
+  }
+}
+
+__global__ void __launch_bounds__(kSortBlock) k_tile_rank_lds(GridGeom g, TileGeom t, const int32_t* __restrict__ cell,
+                                                              long long n, int* cursor, int* dst, int* bad) {
+  extern __shared__ int hist[];
+  const int nbk = t.ntiles + 1;
+  for (int e = threadIdx.x; e < nbk; e += blockDim.x) hist[e] = 0;
+  __syncthreads();
+  const long long p0 = (long long)blockIdx.x * kSortBlock * kSortPer + threadIdx.x;
+  int key[kSortPer], rank[kSortPer];
+#pragma unroll
+  for (int u = 0; u < kSortPer; ++u) {
+    const long long p = p0 + (long long)u * kSortBlock;
+    key[u] = (p < n) ? tile_key(cell[p], g, t) : 0;
+    rank[u] = wave_aggregated_add(hist, key[u], p < n);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nbk; e += blockDim.x) {
+    const int c = hist[e];
+    if (c) hist[e] = atomicAdd(&cursor[e], c);  // this workgroup's run of tile e
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kSortPer; ++u) {
+    const long long p = p0 + (long long)u * kSortBlock;
+    if (p < n) {
+      if (key[u] == t.ntiles && bad) atomicAdd(bad, 1);
+      dst[p] = hist[key[u]] + rank[u];
+    }
   }
 }
 
@@ -161,6 +242,21 @@ void tile_sort(const GridGeom& g, const TileGeom& t, const int32_t* cell, int64_
                int* cursor, int* dst, int* bad, hipStream_t s) {
   // buckets 0..ntiles-1 are tiles, bucket ntiles collects invalid cells
   (void)hipMemsetAsync(counts, 0, sizeof(int) * (t.ntiles + 1), s);
+  if (t.ntiles + 1 <= kSortMaxBuckets) {
+    const size_t lds = sizeof(int) * (size_t)(t.ntiles + 1);
+    const unsigned nbl = (unsigned)((n + kSortBlock * kSortPer - 1) / (kSortBlock * kSortPer));
+    if (lds > 64 * 1024) {
+      (void)hipFuncSetAttribute((const void*)k_tile_count_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      (void)hipFuncSetAttribute((const void*)k_tile_rank_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    }
+    if (n > 0)
+      hipLaunchKernelGGL(k_tile_count_lds, dim3(nbl), dim3(kSortBlock), lds, s, g, t, cell, (long long)n, counts);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, starts, cursor, t.ntiles + 1);
+    if (n > 0)
+      hipLaunchKernelGGL(k_tile_rank_lds, dim3(nbl), dim3(kSortBlock), lds, s, g, t, cell, (long long)n, cursor, dst,
+                         bad);
+    return;
+  }
   const unsigned nb = (unsigned)((n + 255) / 256);
   if (n > 0) hipLaunchKernelGGL(k_tile_count, dim3(nb), dim3(256), 0, s, g, t, cell, (long long)n, counts);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, starts, cursor, t.ntiles + 1);
