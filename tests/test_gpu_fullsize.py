@@ -5,6 +5,8 @@
 * laser128 (128x128x256, 6,291,456 particles, cubic, centering 16, FP32, the bench
   workload): one full pic_step compared field by field with the oracle run on the
   same FP32-rounded inputs, and every particle compared (identities by weight).
+* laser64 (64x64x128, 2,097,152 particles, cubic, centering 8, 60 steps): the gradient of
+  the differentiable run (checkpoints every 10 steps) against central differences.
 """
 
 import numpy as np
@@ -126,3 +128,52 @@ def test_laser128_fp32_spectral_centering_two_steps():
     g_pos = el.positions(wl.shape, wl.spacing)[gi]
     assert periodic_pos_err(g_pos, osp["pos"][oi], p.lengths) <= 2e-5
     ctx.close()
+
+
+def test_laser64_gradient_against_central_differences():
+    """The differentiable workload at full size (64x64x128, 2,097,152 particles, cubic, centering 8,
+    60 steps, checkpoints every 10): the gradient of the final kinetic energy sum w (gamma - 1)
+    w.r.t. the initial E, B (Yee) and momenta, taken along 32 random directions, against central
+    differences of the FP64 forward.  FP64 gradient: agreement to the differences' own accuracy;
+    FP32 gradient (the bench configuration): to a few 1e-3 of the directional derivative."""
+    from paper_2106_12919_amd import autograd as pag
+    banner("laser64 full-size gradient vs central differences, 32 directions")
+    grads, fd = {}, []
+    rng = np.random.default_rng(64)
+    dirs = None
+    for dtype in ("f64", "f32"):
+        wl = inputs.config("laser64", dtype=dtype)
+        ctx = piclib.Context.for_workload(wl, flags=piclib.PIC_KEEP_ORDER)
+        f = ctx.fields_from_workload(wl)
+        el = piclib.Species.from_host(wl.electrons, wl.shape, dtype)
+        ions = piclib.Species.from_host(wl.ions, wl.shape, dtype)
+        ctx.init_charge(f, el, ions)
+        E0, B0, u0 = torch.stack(f.E_stag).clone(), torch.stack(f.B_stag).clone(), torch.stack(el.u).clone()
+        off0, cell0, rho0 = torch.stack(el.off).clone(), el.cell.clone(), f.rho_old.clone()
+
+        def loss(E, B, u):
+            run = pag.DifferentiableRun(ctx, el.q, el.m, nsteps=wl.steps, checkpoint_every=10,
+                                        rho_static=f.rho_static)
+            out = pag.PicSteps.apply(run, cell0, el.w, E, B, rho0, off0, u)
+            return torch.sum(el.w * (torch.sqrt(1 + torch.sum(out[5] * out[5], dim=0)) - 1))
+
+        E, B, u = (t.clone().requires_grad_(True) for t in (E0, B0, u0))
+        loss(E, B, u).backward()
+        grads[dtype] = [np64(t.grad) for t in (E, B, u)]
+        if dtype == "f64":
+            sE, sB = float(E0.abs().max()), float(B0.abs().max())
+            dirs = [(rng.standard_normal(tuple(E0.shape)) * sE, rng.standard_normal(tuple(B0.shape)) * sB,
+                     rng.standard_normal(tuple(u0.shape)) * 0.02) for _ in range(32)]
+            h = 1e-5
+            for dE, dB, du in dirs:
+                tE, tB, tu = (torch.from_numpy(x).to(E0) for x in (dE, dB, du))
+                with torch.no_grad():
+                    lp = float(loss(E0 + h * tE, B0 + h * tB, u0 + h * tu))
+                    lm = float(loss(E0 - h * tE, B0 - h * tB, u0 - h * tu))
+                fd.append((lp - lm) / (2 * h))
+        ctx.close()
+    for k, (dE, dB, du) in enumerate(dirs):
+        an64 = sum(float(np.sum(g * d)) for g, d in zip(grads["f64"], (dE, dB, du)))
+        an32 = sum(float(np.sum(g * d)) for g, d in zip(grads["f32"], (dE, dB, du)))
+        assert abs(an64 - fd[k]) <= 1e-5 * abs(fd[k]) + 1e-9, (k, an64, fd[k])
+        assert abs(an32 - fd[k]) <= 5e-3 * abs(fd[k]) + 1e-6, (k, an32, fd[k])
