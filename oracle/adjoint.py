@@ -160,6 +160,8 @@ def step_vjp(state, species, lam, p):
     lam: dict E (3 arrays), B (3), rho (the adjoint of rho^{n+1}, the next step's rho_old),
     species: list of dicts pos (Np, 3), u (Np, 3), the adjoints of x^{n+1}, u^{n+1/2}.
     Returns the same structure for (E^n, B^n, rho^n, x^n, u^{n-1/2})."""
+    if any(v != 0 for v in p.v_gal):
+        raise NotImplementedError("the reverse mode covers the standard PSATD cycle (v_gal = 0)")
     E_nod, B_nod = center_fields_s2n(state["E_stag"], state["B_stag"], p)
     g = push_fields_vjp(lam["E"], lam["B"], p)
     gE, gB, gJs, g_rho_old, g_rho_new = g[0:3], g[3:6], g[6:9], g[9], g[10] + lam["rho"]

@@ -123,3 +123,56 @@ def update_transpose(lam_E, lam_B, ks, coef):
     gB = tuple(C * lam_B[d] + 1j * C_LIGHT ** 2 * Sw * kxlE[d] for d in range(3))
     gJ = tuple(1j * X1 * kxlB[d] + X4 * lam_E[d] for d in range(3))
     return gE, gB, gJ, -1j * X3 * k_dot_lE, 1j * X2 * k_dot_lE
+
+
+# ---------------------------------------------------------------- standard Galilean PSATD (Sec. 4.3)
+
+def galilean_coefficients(ks, kc, v_gal, dt):
+    """Per-mode coefficients of the standard Galilean update on the staggered grid (Sec. 4.1
+    definitions, Sec. 4.3 eqs. ``eq_update_B/E_with_rho_galilean``):
+      w_s = c |[k]_s|, w_c = c |[k]_c|, W = v_gal . [k]_c, C = cos(w_s dt), S = sin(w_s dt),
+      theta = exp(i W dt / 2), chi1 = w_c^2 / (w_s^2 - W^2) (theta* - theta C + i W theta S / w_s),
+      X1 = theta chi1 / (eps0 w_c^2),
+      X2 = c^2 / (theta* - theta) (theta* X1 - theta (1 - C) / (eps0 w_s^2)),
+      X3 = c^2 / (theta* - theta) (theta* X1 - theta* (1 - C) / (eps0 w_s^2)),
+      X4 = i W X1 - theta^2 S / (eps0 w_s).
+    Readings: w_c^2 cancels between chi1 and X1 (it vanishes at the Nyquist index of
+    finite orders, where chi1 and X1 would be 0/0); where W = 0 (k = 0, or [k]_c . v_gal = 0)
+    the coefficients are the standard ones, the paper's W -> 0 limit (``coefficients``).
+    A W that is zero up to the rounding of the sines in [k]_c (|W dt| < 1e-12, e.g. at the
+    Nyquist index, where [k]_c vanishes exactly) counts as zero.
+    Returns complex arrays TC = theta^2 C, TS = theta^2 S/w_s, X1, X2, TX3 = theta^2 X3, X4."""
+    ksx, ksy, ksz = np.broadcast_arrays(*ks)
+    kcx, kcy, kcz = np.broadcast_arrays(*kc)
+    std = coefficients(ks, dt)
+    ws = C_LIGHT * np.sqrt(ksx ** 2 + ksy ** 2 + ksz ** 2)
+    W = v_gal[0] * kcx + v_gal[1] * kcy + v_gal[2] * kcz
+    gal = np.abs(W * dt) >= 1e-12
+    Wg = np.where(gal, W, 0.5)     # placeholders away from every singularity where not used
+    wsg = np.where(gal, ws, 1.0)   # W != 0 implies k != 0, so w_s > |W| > 0 there
+    C, S_over_w = std["C"], std["S_over_w"]
+    theta = np.exp(0.5j * Wg * dt)
+    thetac = np.conj(theta)
+    one_minus_C_over_w2 = np.where(gal, 2.0 * np.sin(0.5 * wsg * dt) ** 2 / wsg ** 2, 0.0)
+    X1 = theta * (thetac - theta * C + 1j * Wg * theta * S_over_w) / (EPS0 * (wsg ** 2 - Wg ** 2))
+    X2 = C_LIGHT ** 2 / (thetac - theta) * (thetac * X1 - theta * one_minus_C_over_w2 / EPS0)
+    X3 = C_LIGHT ** 2 / (thetac - theta) * (thetac * X1 - thetac * one_minus_C_over_w2 / EPS0)
+    X4 = 1j * Wg * X1 - theta ** 2 * S_over_w / EPS0
+    th2 = theta ** 2
+    return {"TC": np.where(gal, th2 * C, C + 0j), "TS": np.where(gal, th2 * S_over_w, S_over_w + 0j),
+            "X1": np.where(gal, X1, std["X1"] + 0j), "X2": np.where(gal, X2, std["X2"] + 0j),
+            "TX3": np.where(gal, th2 * X3, std["X3"] + 0j), "X4": np.where(gal, X4, std["X4"] + 0j)}
+
+
+def update_galilean(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, gc):
+    """One standard-Galilean-PSATD step of the paper-convention spectra (Sec. 4.3):
+      B' = theta^2 C B - i theta^2 (S/w_s) [k]_s x E + i X1 [k]_s x J
+      E' = theta^2 C E + i c^2 theta^2 (S/w_s) [k]_s x B + X4 J + i (theta^2 X3 rho^n - X2 rho^{n+1}) [k]_s"""
+    kxE = cross(ks, Eh)
+    kxB = cross(ks, Bh)
+    kxJ = cross(ks, Jh)
+    TC, TS, X1, X2, TX3, X4 = gc["TC"], gc["TS"], gc["X1"], gc["X2"], gc["TX3"], gc["X4"]
+    B_new = tuple(TC * Bh[d] - 1j * TS * kxE[d] + 1j * X1 * kxJ[d] for d in range(3))
+    E_new = tuple(TC * Eh[d] + 1j * C_LIGHT ** 2 * TS * kxB[d] + X4 * Jh[d]
+                  + 1j * (TX3 * rho_old_h - X2 * rho_new_h) * ks[d] for d in range(3))
+    return E_new, B_new

@@ -16,6 +16,10 @@ rho^n on the nodes) and runs, in this order:
   6. back to real space; rho^n <- rho^{n+1}.
 Immobile species (m = inf) are never pushed and deposit rho only.
 
+With a nonzero ``Params.v_gal`` the field solve is the standard Galilean PSATD update
+(Sec. 4.3) and the particles move in the Galilean frame, x += dt (v - v_gal) (the frame
+whose Fourier-space Maxwell equations carry the -v_gal . grad term of Sec. 4.3).
+
 With ``Params.nodal`` the same function runs the standard nodal PSATD cycle the paper
 compares against (Sec. 2, first cycle figure; Sec. 4.1 [k]_c): every field on the nodes,
 no centering, the update with the centered modified wave numbers.
@@ -38,6 +42,7 @@ class Params:
     center_order: int = 8   # 2 m_c
     psatd_order: int = 16   # 2 m_p for [k]_s; 0 = infinite
     nodal: bool = False     # the nodal comparison cycle: every field on the nodes, [k]_c, no centering
+    v_gal: tuple = (0.0, 0.0, 0.0)  # Galilean velocity (Sec. 4.3); zero = standard PSATD
 
     @property
     def lengths(self):
@@ -68,8 +73,10 @@ def gather_push(sp, E_nod, B_nod, p):
     EB = particles.gather(list(E_nod) + list(B_nod), pos, p.spacing, p.shape_order)
     u_new = particles.boris(u.T, EB[:3], EB[3:], sp["q"], sp["m"], p.dt)
     v = u_new / particles.gamma(u_new)
-    pos_half = particles.wrap(pos + 0.5 * p.dt * v.T, p.lengths)
-    pos_new = particles.wrap(pos + p.dt * v.T, p.lengths)
+    # in the Galilean frame (coordinates moving with v_gal) a particle moves at v - v_gal
+    w = v.T - np.asarray(p.v_gal, dtype=np.float64)[None, :]
+    pos_half = particles.wrap(pos + 0.5 * p.dt * w, p.lengths)
+    pos_new = particles.wrap(pos + p.dt * w, p.lengths)
     sp["pos"] = pos_new
     sp["u"] = u_new.T.copy()
     return v, pos_half
@@ -98,14 +105,18 @@ def push_fields(E_stag, B_stag, J_stag, rho_old, rho_new, p):
     else:
         ks = psatd.staggered_wave_vector(p.shape, p.spacing, p.psatd_order)
         offsets = OFFSETS
-    coef = psatd.coefficients(ks, p.dt)
     fw = lambda f, name: transforms.forward(f, p.spacing, offsets[name])
     Eh = [fw(E_stag[d], E_NAMES[d]) for d in range(3)]
     Bh = [fw(B_stag[d], B_NAMES[d]) for d in range(3)]
     Jh = [fw(J_stag[d], J_NAMES[d]) for d in range(3)]
     rho_old_h = fw(rho_old, "rho")
     rho_new_h = fw(rho_new, "rho")
-    E_new, B_new = psatd.update(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, coef)
+    if any(v != 0 for v in p.v_gal):  # standard Galilean PSATD (Sec. 4.3)
+        kc = psatd.centered_wave_vector(p.shape, p.spacing, p.psatd_order)
+        gc = psatd.galilean_coefficients(ks, kc, p.v_gal, p.dt)
+        E_new, B_new = psatd.update_galilean(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, gc)
+    else:
+        E_new, B_new = psatd.update(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, psatd.coefficients(ks, p.dt))
     E_out = [transforms.inverse(E_new[d], p.spacing, offsets[E_NAMES[d]]) for d in range(3)]
     B_out = [transforms.inverse(B_new[d], p.spacing, offsets[B_NAMES[d]]) for d in range(3)]
     return E_out, B_out
