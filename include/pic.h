@@ -90,6 +90,14 @@ typedef struct {
   int32_t psatd_order;    /* order 2m_p of the staggered modified wave number [k]_s, even 2..64; 0 = infinite */
   pic_dtype dtype;        /* precision of fields, particles, FFTs; tables are always built in FP64 */
   uint32_t flags;         /* 0 or PIC_SPECTRAL_CENTERING or PIC_NODAL_SOLVER, | PIC_KEEP_ORDER; other bits are rejected */
+  double v_gal[3];        /* Galilean velocity (in units of c), |v_gal| < 1; all zero = standard PSATD.  Nonzero:
+                           * the standard Galilean PSATD update of Sec. 4.3 (eqs.
+                           * eq_update_B/E_with_rho_galilean; coefficients built in FP64 from Sec. 4.1
+                           * W = v_gal . [k]_c, theta = exp(i W dt/2), chi_1, X1..X4), on the grid of
+                           * coordinates moving with v_gal: pic_gather_push and pic_step move particles
+                           * by (v - v_gal) dt and deposit J at x^{n+1} - (v - v_gal) dt/2.  Requires a
+                           * finite psatd_order and (c + |v_gal|) dt <= min(dx, dy, dz); not with
+                           * PIC_SPECTRAL_CENTERING; no reverse mode. */
 } pic_params;
 
 /* One particle species, structure of arrays, caller-owned device memory.

@@ -140,7 +140,10 @@ def galilean_coefficients(ks, kc, v_gal, dt):
     finite orders, where chi1 and X1 would be 0/0); where W = 0 (k = 0, or [k]_c . v_gal = 0)
     the coefficients are the standard ones, the paper's W -> 0 limit (``coefficients``).
     A W that is zero up to the rounding of the sines in [k]_c (|W dt| < 1e-12, e.g. at the
-    Nyquist index, where [k]_c vanishes exactly) counts as zero.
+    Nyquist index, where [k]_c vanishes exactly) counts as zero.  Where 0 < |W dt| < 0.05 the
+    closed forms lose about log10(1 / |W dt|) digits to the cancellation behind
+    1 / (theta* - theta); there the same formulas are evaluated in 40-digit arithmetic
+    (mpmath) from the float64 [k]_s, W.
     Returns complex arrays TC = theta^2 C, TS = theta^2 S/w_s, X1, X2, TX3 = theta^2 X3, X4."""
     ksx, ksy, ksz = np.broadcast_arrays(*ks)
     kcx, kcy, kcz = np.broadcast_arrays(*kc)
@@ -159,9 +162,34 @@ def galilean_coefficients(ks, kc, v_gal, dt):
     X3 = C_LIGHT ** 2 / (thetac - theta) * (thetac * X1 - thetac * one_minus_C_over_w2 / EPS0)
     X4 = 1j * Wg * X1 - theta ** 2 * S_over_w / EPS0
     th2 = theta ** 2
-    return {"TC": np.where(gal, th2 * C, C + 0j), "TS": np.where(gal, th2 * S_over_w, S_over_w + 0j),
-            "X1": np.where(gal, X1, std["X1"] + 0j), "X2": np.where(gal, X2, std["X2"] + 0j),
-            "TX3": np.where(gal, th2 * X3, std["X3"] + 0j), "X4": np.where(gal, X4, std["X4"] + 0j)}
+    out = {"TC": np.where(gal, th2 * C, C + 0j), "TS": np.where(gal, th2 * S_over_w, S_over_w + 0j),
+           "X1": np.where(gal, X1, std["X1"] + 0j), "X2": np.where(gal, X2, std["X2"] + 0j),
+           "TX3": np.where(gal, th2 * X3, std["X3"] + 0j), "X4": np.where(gal, X4, std["X4"] + 0j)}
+    for idx in zip(*np.nonzero(gal & (np.abs(W * dt) < 0.05))):
+        vals = _galilean_mp(float(ksx[idx]), float(ksy[idx]), float(ksz[idx]), float(W[idx]), dt)
+        for key, val in vals.items():
+            out[key][idx] = val
+    return out
+
+
+def _galilean_mp(kx, ky, kz, W, dt):
+    """The closed forms of ``galilean_coefficients`` for one mode in 40-digit arithmetic."""
+    import mpmath as mp
+    with mp.workdps(40):
+        c2, eps0 = mp.mpf(C_LIGHT) ** 2, mp.mpf(EPS0)
+        ws = mp.sqrt(c2 * (mp.mpf(kx) ** 2 + mp.mpf(ky) ** 2 + mp.mpf(kz) ** 2))
+        W, dt = mp.mpf(W), mp.mpf(dt)
+        C, S = mp.cos(ws * dt), mp.sin(ws * dt)
+        theta = mp.expj(W * dt / 2)
+        thetac = mp.conj(theta)
+        omc = (1 - C) / ws ** 2
+        X1 = theta * (thetac - theta * C + 1j * W * theta * S / ws) / (eps0 * (ws ** 2 - W ** 2))
+        X2 = c2 / (thetac - theta) * (thetac * X1 - theta * omc / eps0)
+        X3 = c2 / (thetac - theta) * (thetac * X1 - thetac * omc / eps0)
+        X4 = 1j * W * X1 - theta ** 2 * S / ws / eps0
+        th2 = theta ** 2
+        vals = {"TC": th2 * C, "TS": th2 * S / ws, "X1": X1, "X2": X2, "TX3": th2 * X3, "X4": X4}
+        return {k: complex(v) for k, v in vals.items()}
 
 
 def update_galilean(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, gc):

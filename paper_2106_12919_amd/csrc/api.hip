@@ -279,6 +279,28 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
   if ((err = e.upload(&e.tab.X1, X1)) != hipSuccess) return err;
   if ((err = e.upload(&e.tab.X2, X2)) != hipSuccess) return err;
   if ((err = e.upload(&e.tab.X3, X3)) != hipSuccess) return err;
+  if (p.v_gal[0] != 0 || p.v_gal[1] != 0 || p.v_gal[2] != 0) {
+    // standard Galilean PSATD (Sec. 4.3): W = v_gal . [k]_c per mode
+    std::vector<double> kc[3];
+    for (int a = 0; a < 3; ++a) {
+      kc[a].resize(n[a]);
+      k_centered_axis(n[a], d[a], p.psatd_order, kc[a].data());
+    }
+    std::vector<cplx<T>> G[6];
+    for (auto& v : G) v.resize(M);
+    std::complex<double> g[6];
+    for (int i = 0; i < p.nx; ++i)
+      for (int j = 0; j < p.ny; ++j)
+        for (int k = 0; k < nzh; ++k) {
+          const size_t idx = ((size_t)i * p.ny + j) * nzh + k;
+          const double w = std::sqrt(ks[0][i] * ks[0][i] + ks[1][j] * ks[1][j] + ks[2][k] * ks[2][k]);
+          const double W = p.v_gal[0] * kc[0][i] + p.v_gal[1] * kc[1][j] + p.v_gal[2] * kc[2][k];
+          galilean_coefficients(w, W, p.dt, g);
+          for (int q = 0; q < 6; ++q) G[q][idx] = cmake((T)g[q].real(), (T)g[q].imag());
+        }
+    for (int q = 0; q < 6; ++q)
+      if ((err = e.upload(&e.tab.G[q], G[q])) != hipSuccess) return err;
+  }
   // spectra and scratch, zeroed once (padding columns stay zero)
   const size_t ns = e.fft.spectrum_elems();
   cplx<T>** bufs[17] = {&e.Eh[0], &e.Eh[1], &e.Eh[2], &e.Bh[0], &e.Bh[1], &e.Bh[2], &e.Jh[0], &e.Jh[1], &e.Jh[2],
@@ -328,6 +350,20 @@ pic_status validate_params(const pic_params* p, std::string& msg) {
   if (p->flags & ~(uint32_t)(PIC_SPECTRAL_CENTERING | PIC_NODAL_SOLVER | PIC_KEEP_ORDER)) {
     msg = "unknown bit in flags";
     return PIC_EINVAL;
+  }
+  const double vg2 = p->v_gal[0] * p->v_gal[0] + p->v_gal[1] * p->v_gal[1] + p->v_gal[2] * p->v_gal[2];
+  if (!std::isfinite(vg2) || vg2 >= 1.0) { msg = "need |v_gal| < c"; return PIC_EINVAL; }
+  if ((1.0 + std::sqrt(vg2)) * p->dt > dmin) {  // particles move < 1 cell per step relative to the grid
+    msg = "the Galilean frame needs (c + |v_gal|) dt <= min(dx, dy, dz)";
+    return PIC_EINVAL;
+  }
+  if (vg2 > 0 && p->psatd_order == 0) {
+    msg = "the Galilean solver needs a finite psatd_order ([k]_c at the Nyquist index)";
+    return PIC_EUNSUPPORTED;
+  }
+  if (vg2 > 0 && (p->flags & PIC_SPECTRAL_CENTERING)) {
+    msg = "PIC_SPECTRAL_CENTERING is built for the standard PSATD update only";
+    return PIC_EUNSUPPORTED;
   }
   if ((p->flags & PIC_SPECTRAL_CENTERING) && (p->flags & PIC_NODAL_SOLVER)) {
     msg = "PIC_SPECTRAL_CENTERING and PIC_NODAL_SOLVER exclude each other (the nodal solver has no centering)";
@@ -382,8 +418,14 @@ SpeciesView<T> view(const pic_species& x) {
   return v;
 }
 
+bool galilean(const pic_params& p) { return p.v_gal[0] != 0 || p.v_gal[1] != 0 || p.v_gal[2] != 0; }
+
 GridGeom geom(const pic_params& p) {
-  return make_geom(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order);
+  GridGeom g = make_geom(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order);
+  g.sgx = p.v_gal[0] * p.dt / p.dx;
+  g.sgy = p.v_gal[1] * p.dt / p.dy;
+  g.sgz = p.v_gal[2] * p.dt / p.dz;
+  return g;
 }
 
 size_t ncells(const pic_params& p) { return (size_t)p.nx * p.ny * p.nz; }
@@ -1069,6 +1111,7 @@ pic_status psatd_push_fields(pic_ctx ctx, pic_fields* f) {
 pic_status psatd_push_fields_adjoint(pic_ctx ctx, pic_fields* f) {
   pic_status st = device_ok(ctx);
   if (st != PIC_OK) return st;
+  if (galilean(ctx->p)) return ctx->fail(PIC_EUNSUPPORTED, "no reverse mode for the Galilean solver");
   if ((st = check_fields(ctx, f, true, true, false, false, false, true, true, true)) != PIC_OK) return st;
   return PIC_DISPATCH(ctx, do_push_fields_adjoint, f);
 }
@@ -1094,6 +1137,7 @@ pic_status pic_step_adjoint(pic_ctx ctx, pic_fields* f, const pic_species* sp, i
                             const pic_species_adjoint* asp) {
   pic_status st = device_ok(ctx);
   if (st != PIC_OK) return st;
+  if (galilean(ctx->p)) return ctx->fail(PIC_EUNSUPPORTED, "no reverse mode for the Galilean solver");
   if ((st = check_species(ctx, sp, nsp)) != PIC_OK) return st;
   const bool nodal = (ctx->p.flags & PIC_NODAL_SOLVER) != 0;
   if ((st = check_fields(ctx, f, true, true, !nodal, !nodal, false, false, false, false)) != PIC_OK) return st;

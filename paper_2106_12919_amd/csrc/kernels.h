@@ -45,6 +45,9 @@ struct PsatdTables {
   // Fourier symbol of the nodes -> centres centering along each axis (index-space DFT):
   // sum_n c_n (e^{i theta n} + e^{-i theta (n-1)}); centres -> nodes is its conjugate.
   cplx<T>* Tc[3] = {nullptr, nullptr, nullptr};
+  // Standard Galilean PSATD (Sec. 4.3), complex per mode: theta^2 C, theta^2 S/w_s, X1, X2,
+  // theta^2 X3, X4 (all null for standard PSATD)
+  cplx<T>* G[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 // With nodal != nullptr (spectral centering): J holds the NODAL current spectra, centred
 // to the Yee grid by the symbols Tc inside the update, and nodal[0..5] receive the
@@ -74,6 +77,9 @@ struct GridGeom {
   double dx, dy, dz, dt;
   int shape_order;
   FastDiv ny_div, nz_div;  // decode of linear cell indices
+  // Galilean frame (Sec. 4.3): the grid moves with v_gal, so a particle moves by
+  // (v - v_gal) dt per step; sg = v_gal dt / (dx, dy, dz) in cells (0 for standard PSATD)
+  double sgx, sgy, sgz;
 };
 GridGeom make_geom(int nx, int ny, int nz, double dx, double dy, double dz, double dt, int shape_order);
 

@@ -362,9 +362,10 @@ __device__ inline void gather_push_one(const T* box, const Batch<const T*>& F, c
   BorisState<T> b;
   boris(f, qdt2m, ux, uy, uz, b);
   const T ig = inv_sqrt((T)1 + ux * ux + uy * uy + uz * uz);
-  i = wrapi(i + advance_offset(ox, dtx * ux * ig), g.nx);
-  j = wrapi(j + advance_offset(oy, dty * uy * ig), g.ny);
-  k = wrapi(k + advance_offset(oz, dtz * uz * ig), g.nz);
+  // on the grid moving with v_gal (Galilean frame) the particle moves by (v - v_gal) dt
+  i = wrapi(i + advance_offset(ox, dtx * ux * ig - (T)g.sgx), g.nx);
+  j = wrapi(j + advance_offset(oy, dty * uy * ig - (T)g.sgy), g.ny);
+  k = wrapi(k + advance_offset(oz, dtz * uz * ig - (T)g.sgz), g.nz);
 }
 
 template <typename T>
@@ -688,13 +689,13 @@ __device__ inline bool locate(const Raw<T>& r, const GridGeom& g, int t0x, int t
     d.vx = r.u[0] * ig;
     d.vy = r.u[1] * ig;
     d.vz = r.u[2] * ig;
-    // x^{n+1/2} = x^{n+1} - dt v / 2
+    // x^{n+1/2} = x^{n+1} - dt (v - v_gal) / 2
     d.hx = d.ox;
     d.hy = d.oy;
     d.hz = d.oz;
-    d.ih = wrapi(d.i + advance_offset(d.hx, -hdtx * d.vx), g.nx);
-    d.jh = wrapi(d.j + advance_offset(d.hy, -hdty * d.vy), g.ny);
-    d.kh = wrapi(d.k + advance_offset(d.hz, -hdtz * d.vz), g.nz);
+    d.ih = wrapi(d.i + advance_offset(d.hx, -hdtx * d.vx + (T)0.5 * (T)g.sgx), g.nx);
+    d.jh = wrapi(d.j + advance_offset(d.hy, -hdty * d.vy + (T)0.5 * (T)g.sgy), g.ny);
+    d.kh = wrapi(d.k + advance_offset(d.hz, -hdtz * d.vz + (T)0.5 * (T)g.sgz), g.nz);
     const int lx = box_index(d.ih, t0x, g.nx), ly = box_index(d.jh, t0y, g.ny), lz = box_index(d.kh, t0z, g.nz);
     d.at_j = (lx >= 0 && ly >= 0 && lz >= 0) ? X::at(lx, ly, lz) : -1;
   }
@@ -1267,15 +1268,15 @@ __device__ inline void adjoint_one(const GridGeom& g, const SpeciesView<T>& sp, 
   boris(f, qdt2m, ux, uy, uz, b);
   const T ig = inv_sqrt((T)1 + ux * ux + uy * uy + uz * uz);
   const T v[3] = {ux * ig, uy * ig, uz * ig};
-  T o1x = ox, o1y = oy, o1z = oz;
-  const int i1 = wrapi(i + advance_offset(o1x, dtx * ux * ig), g.nx);
-  const int j1 = wrapi(j + advance_offset(o1y, dty * uy * ig), g.ny);
-  const int k1 = wrapi(k + advance_offset(o1z, dtz * uz * ig), g.nz);
+  T o1x = ox, o1y = oy, o1z = oz;  // the forward's move and half position (g.sg* = 0: no Galilean reverse mode)
+  const int i1 = wrapi(i + advance_offset(o1x, dtx * ux * ig - (T)g.sgx), g.nx);
+  const int j1 = wrapi(j + advance_offset(o1y, dty * uy * ig - (T)g.sgy), g.ny);
+  const int k1 = wrapi(k + advance_offset(o1z, dtz * uz * ig - (T)g.sgz), g.nz);
   const T hd[3] = {(T)0.5 * dtx, (T)0.5 * dty, (T)0.5 * dtz};
   T hx = o1x, hy = o1y, hz = o1z;
-  const int ih = wrapi(i1 + advance_offset(hx, -hd[0] * v[0]), g.nx);
-  const int jh = wrapi(j1 + advance_offset(hy, -hd[1] * v[1]), g.ny);
-  const int kh = wrapi(k1 + advance_offset(hz, -hd[2] * v[2]), g.nz);
+  const int ih = wrapi(i1 + advance_offset(hx, -hd[0] * v[0] + (T)0.5 * (T)g.sgx), g.nx);
+  const int jh = wrapi(j1 + advance_offset(hy, -hd[1] * v[1] + (T)0.5 * (T)g.sgy), g.ny);
+  const int kh = wrapi(k1 + advance_offset(hz, -hd[2] * v[2] + (T)0.5 * (T)g.sgz), g.nz);
   // deposition
   T rv[1], rg[1][3], jv[3], jg[3][3];
   sRho(i1, j1, k1, o1x, o1y, o1z, rv, rg);

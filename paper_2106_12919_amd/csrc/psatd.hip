@@ -26,7 +26,12 @@ namespace {
 // SPECTRAL: the currents arrive on the nodes and are centred by Tc (Sec. 3 centering as
 // its exact Fourier symbol on the periodic grid, App. C), and the updated E, B are also
 // written centred back to the nodes (conj Tc along the same axes as in real space).
-template <typename T, bool SPECTRAL>
+// GAL: the standard Galilean update of Sec. 4.3 (eqs. eq_update_B/E_with_rho_galilean) with
+// its complex per-mode coefficients in place of the real ones:
+//   bx' = TC bx - TS (D+y ez - D+z ey) + X1 (D+y jz - D+z jy)
+//   ex' = TC ex + TS (D-y bz - D-z by) + X4 jx + (TX3 ro - X2 rn) D+x,
+// TC = theta^2 C, TS = theta^2 S/w_s, TX3 = theta^2 X3 (theta = exp(i v_gal . [k]_c dt / 2)).
+template <typename T, bool SPECTRAL, bool GAL>
 __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cplx<T>*> F, Batch<const cplx<T>*> S,
                                                       Batch<cplx<T>*> NOD, int nx, int ny, int nzh, int pz) {
   const long long total = (long long)nx * ny * nzh;
@@ -38,9 +43,28 @@ __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cp
   const int i = (int)(r / ny);
   const size_t a = (size_t)r * pz + kz;
 
-  const T C = t.C[idx], Sw = t.Sw[idx], X1 = t.X1[idx], X2 = t.X2[idx], X3 = t.X3[idx];
   const cplx<T> px = t.Dp[0][i], py = t.Dp[1][j], pzd = t.Dp[2][kz];
   const cplx<T> mx = t.Dm[0][i], my = t.Dm[1][j], mz = t.Dm[2][kz];
+  // coefficients as complex numbers (imaginary parts zero for standard PSATD)
+  cplx<T> gC, gS, g1, g2, g3, g4;
+  if (GAL) {
+    gC = t.G[0][idx];
+    gS = t.G[1][idx];
+    g1 = t.G[2][idx];
+    g2 = t.G[3][idx];
+    g3 = t.G[4][idx];
+    g4 = t.G[5][idx];
+  } else {
+    const T Sw = t.Sw[idx];
+    gC = cmake(t.C[idx], (T)0);
+    gS = cmake(Sw, (T)0);
+    g1 = cmake(t.X1[idx], (T)0);
+    g2 = cmake(t.X2[idx], (T)0);
+    g3 = cmake(t.X3[idx], (T)0);
+    g4 = cmake(-Sw, (T)0);
+  }
+  // a * z for a coefficient a of the mode: a real scale in the standard update
+  auto mul = [&](cplx<T> c, cplx<T> z) { return GAL ? cmul(c, z) : cscale(z, c.x); };
 
   const cplx<T> ex = F.p[0][a], ey = F.p[1][a], ez = F.p[2][a];
   const cplx<T> bx = F.p[3][a], by = F.p[4][a], bz = F.p[5][a];
@@ -63,9 +87,9 @@ __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cp
   const cplx<T> cJx = csub(cmul(py, jz), cmul(pzd, jy));
   const cplx<T> cJy = csub(cmul(pzd, jx), cmul(px, jz));
   const cplx<T> cJz = csub(cmul(px, jy), cmul(py, jx));
-  const cplx<T> nbx = cadd(csub(cscale(bx, C), cscale(cEx, Sw)), cscale(cJx, X1));
-  const cplx<T> nby = cadd(csub(cscale(by, C), cscale(cEy, Sw)), cscale(cJy, X1));
-  const cplx<T> nbz = cadd(csub(cscale(bz, C), cscale(cEz, Sw)), cscale(cJz, X1));
+  const cplx<T> nbx = cadd(csub(mul(gC, bx), mul(gS, cEx)), mul(g1, cJx));
+  const cplx<T> nby = cadd(csub(mul(gC, by), mul(gS, cEy)), mul(g1, cJy));
+  const cplx<T> nbz = cadd(csub(mul(gC, bz), mul(gS, cEz)), mul(g1, cJz));
   F.p[3][a] = nbx;
   F.p[4][a] = nby;
   F.p[5][a] = nbz;
@@ -74,10 +98,10 @@ __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cp
   const cplx<T> cBx = csub(cmul(my, bz), cmul(mz, by));
   const cplx<T> cBy = csub(cmul(mz, bx), cmul(mx, bz));
   const cplx<T> cBz = csub(cmul(mx, by), cmul(my, bx));
-  const cplx<T> rr = csub(cscale(ro, X3), cscale(rn, X2));
-  const cplx<T> nex = cadd(csub(cadd(cscale(ex, C), cscale(cBx, Sw)), cscale(jx, Sw)), cmul(rr, px));
-  const cplx<T> ney = cadd(csub(cadd(cscale(ey, C), cscale(cBy, Sw)), cscale(jy, Sw)), cmul(rr, py));
-  const cplx<T> nez = cadd(csub(cadd(cscale(ez, C), cscale(cBz, Sw)), cscale(jz, Sw)), cmul(rr, pzd));
+  const cplx<T> rr = csub(mul(g3, ro), mul(g2, rn));
+  const cplx<T> nex = cadd(cadd(cadd(mul(gC, ex), mul(gS, cBx)), mul(g4, jx)), cmul(rr, px));
+  const cplx<T> ney = cadd(cadd(cadd(mul(gC, ey), mul(gS, cBy)), mul(g4, jy)), cmul(rr, py));
+  const cplx<T> nez = cadd(cadd(cadd(mul(gC, ez), mul(gS, cBz)), mul(g4, jz)), cmul(rr, pzd));
   F.p[0][a] = nex;
   F.p[1][a] = ney;
   F.p[2][a] = nez;
@@ -171,10 +195,12 @@ void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B
     for (int q = 0; q < 6; ++q) N.p[q] = nodal[q];
   const long long total = (long long)nx * ny * nzh;
   const dim3 grid((unsigned)((total + 255) / 256));
-  if (nodal)
-    hipLaunchKernelGGL((k_psatd_update<T, true>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
+  if (nodal)  // spectral centering (standard PSATD only)
+    hipLaunchKernelGGL((k_psatd_update<T, true, false>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
+  else if (t.G[0])
+    hipLaunchKernelGGL((k_psatd_update<T, false, true>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
   else
-    hipLaunchKernelGGL((k_psatd_update<T, false>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
+    hipLaunchKernelGGL((k_psatd_update<T, false, false>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
 }
 
 template void psatd_update<float>(const PsatdTables<float>&, cplx<float>* const*, cplx<float>* const*,

@@ -31,7 +31,7 @@ class pic_params(Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32),
                 ("dx", c_double), ("dy", c_double), ("dz", c_double), ("dt", c_double),
                 ("shape_order", c_int32), ("center_order", c_int32), ("psatd_order", c_int32),
-                ("dtype", c_int), ("flags", c_uint32)]
+                ("dtype", c_int), ("flags", c_uint32), ("v_gal", c_double * 3)]
 
 
 class pic_species(Structure):
@@ -310,7 +310,7 @@ class Fields:
         return f
 
 
-def make_params(shape, spacing, dt, shape_order, center_order, psatd_order, dtype, flags=0):
+def make_params(shape, spacing, dt, shape_order, center_order, psatd_order, dtype, flags=0, v_gal=(0.0, 0.0, 0.0)):
     p = pic_params()
     p.nx, p.ny, p.nz = shape
     p.dx, p.dy, p.dz = spacing
@@ -318,14 +318,17 @@ def make_params(shape, spacing, dt, shape_order, center_order, psatd_order, dtyp
     p.shape_order, p.center_order, p.psatd_order = shape_order, center_order, psatd_order
     p.dtype = PIC_F32 if dtype == "f32" else PIC_F64
     p.flags = flags
+    for d in range(3):
+        p.v_gal[d] = float(v_gal[d])
     return p
 
 
 class Context:
     """Owns a pic_ctx for one workload; thin convenience over the C ABI."""
 
-    def __init__(self, shape, spacing, dt, shape_order, center_order, psatd_order, dtype, stream=None, flags=0):
-        self.params = make_params(shape, spacing, dt, shape_order, center_order, psatd_order, dtype, flags)
+    def __init__(self, shape, spacing, dt, shape_order, center_order, psatd_order, dtype, stream=None, flags=0,
+                 v_gal=(0.0, 0.0, 0.0)):
+        self.params = make_params(shape, spacing, dt, shape_order, center_order, psatd_order, dtype, flags, v_gal)
         self.shape, self.spacing, self.dt, self.dtype = tuple(shape), tuple(spacing), dt, dtype
         self.ctx = pic_init(self.params, stream)
 

@@ -1,0 +1,100 @@
+"""Standard Galilean PSATD (Sec. 4.3) on the GPU against the oracle: the field solve alone
+(staggered and nodal, axis-aligned and oblique Galilean velocities, FP64 and FP32) and whole
+cycles with the particles moving in the Galilean frame.  The library builds its complex
+per-mode tables by quadrature of the update's integral forms; the oracle evaluates the
+paper's closed forms: the two meet only here."""
+
+import numpy as np
+import pytest
+
+from gpu_common import EPS, banner, max_rel, np64, oracle_species, periodic_pos_err, put, rounded
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import step as ostep  # noqa: E402
+from paper_2106_12919_amd import inputs  # noqa: E402
+from paper_2106_12919_amd import lib as piclib  # noqa: E402
+
+
+def fft_tol(dtype, shape):
+    n = np.prod(shape)
+    return 10 * 2 * np.log2(n) * EPS[dtype] * 3
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(16, 24, 32), (12, 8, 48)])
+@pytest.mark.parametrize("v_gal", [(0.0, 0.0, -0.998888), (0.3, -0.4, 0.5)])
+@pytest.mark.parametrize("nodal", [False, True])
+def test_galilean_push_fields_parity(dtype, shape, v_gal, nodal):
+    banner(f"psatd_push_fields Galilean dtype={dtype} shape={shape} v_gal={v_gal} nodal={nodal}")
+    dt = 0.5
+    flags = piclib.PIC_NODAL_SOLVER if nodal else 0
+    p = ostep.Params(shape, (1.0, 1.0, 1.0), dt, 1, 8, 16, nodal=nodal, v_gal=v_gal)
+    ctx = piclib.Context(shape, (1.0, 1.0, 1.0), dt, 1, 8, 16, dtype, flags=flags, v_gal=v_gal)
+    f = piclib.Fields(shape, dtype)
+    src = rounded(inputs.random_grid(shape, seed=17, count=11), dtype)
+    put(f.E_stag, src[0:3])
+    put(f.B_stag, src[3:6])
+    put(f.J_stag, src[6:9])
+    put([f.rho_old, f.rho_new], src[9:11])
+    piclib.psatd_push_fields(ctx.ctx, f)
+    piclib.pic_sync(ctx.ctx)
+    E_ref, B_ref = ostep.push_fields(src[0:3], src[3:6], src[6:9], src[9], src[10], p)
+    tol = fft_tol(dtype, shape)
+    for d in range(3):
+        assert max_rel(np64(f.E_stag[d]), E_ref[d]) <= tol, (d, max_rel(np64(f.E_stag[d]), E_ref[d]))
+        assert max_rel(np64(f.B_stag[d]), B_ref[d]) <= tol, (d, max_rel(np64(f.B_stag[d]), B_ref[d]))
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape_order", [1, 3])
+@pytest.mark.parametrize("flags", [0, piclib.PIC_KEEP_ORDER])
+def test_galilean_step_parity(dtype, shape_order, flags):
+    """Three cycles with v_gal = -0.9 c along z (the boosted-frame setting of the paper's LWFA and
+    PWFA runs, Sec. 5.2-5.3): fields, charge and every particle (by identity) against the oracle."""
+    shape, v_gal = (16, 16, 24), (0.0, 0.0, -0.9)
+    banner(f"pic_step Galilean dtype={dtype} shape_order={shape_order} flags={flags} v_gal={v_gal}")
+    wl = inputs.small(shape, ppc=2, shape_order=shape_order, center_order=8, dtype=dtype, u_th=0.1,
+                      field_amp=0.02, seed=53)
+    # weights 2^k (1 + p 2^-23): exact and distinct in FP32, so they identify the particles
+    base = 2.0 ** np.floor(np.log2(wl.electrons.w[0]))
+    wl.electrons.w = base * (1.0 + np.arange(wl.electrons.n) * 2.0 ** -23)
+    ctx = piclib.Context.for_workload(wl, flags=flags, v_gal=v_gal)
+    f = ctx.fields_from_workload(wl)
+    el = piclib.Species.from_host(wl.electrons, shape, dtype)
+    ions = piclib.Species.from_host(wl.ions, shape, dtype)
+    ctx.init_charge(f, el, ions)
+    p = ostep.Params(shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order, v_gal=v_gal)
+    osp = oracle_species(el, shape, wl.spacing)
+    oion = oracle_species(ions, shape, wl.spacing)
+    rho_static = ostep.deposit_rho([oion], p)
+    state = {"E_stag": rounded(wl.E, dtype), "B_stag": rounded(wl.B, dtype),
+             "rho_old": ostep.deposit_rho([osp], p, rho_static)}
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    for n in range(3):
+        piclib.pic_step(ctx.ctx, f, [el], 1)
+        piclib.pic_sync(ctx.ctx)
+        ostep.step(state, [osp], p, rho_static)
+        for d in range(3):
+            assert max_rel(np64(f.E_stag[d]), state["E_stag"][d]) <= tol, (n, "E", d)
+            assert max_rel(np64(f.B_stag[d]), state["B_stag"][d]) <= tol, (n, "B", d)
+        assert max_rel(np64(f.rho_old), state["rho_old"]) <= tol
+        g_w = np64(el.w)
+        gi, oi = np.argsort(g_w), np.argsort(osp["w"])
+        g_pos = el.positions(shape, wl.spacing)[gi]
+        g_u = np.stack([np64(x) for x in el.u], axis=1)[gi]
+        assert periodic_pos_err(g_pos, osp["pos"][oi], p.lengths) <= (1e-11 if dtype == "f64" else 2e-5)
+        assert np.max(np.abs(g_u - osp["u"][oi])) <= (1e-11 if dtype == "f64" else 2e-5)
+    ctx.close()
+
+
+def test_galilean_rejects_reverse_mode():
+    shape = (16, 16, 16)
+    ctx = piclib.Context(shape, (1.0, 1.0, 1.0), 0.5, 1, 4, 8, "f64", v_gal=(0.0, 0.0, 0.5))
+    f = piclib.Fields(shape, "f64")
+    with pytest.raises(RuntimeError, match="Galilean"):
+        piclib.psatd_push_fields_adjoint(ctx.ctx, f)
+    ctx.close()

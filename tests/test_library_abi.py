@@ -60,6 +60,12 @@ def good_params(**kw):
     (dict(center_order=0), piclib.PIC_EUNSUPPORTED),
     (dict(psatd_order=7), piclib.PIC_EUNSUPPORTED),
     (dict(psatd_order=66), piclib.PIC_EUNSUPPORTED),
+    (dict(v_gal=(0.0, 0.0, -1.0)), piclib.PIC_EINVAL),          # |v_gal| must stay below c
+    (dict(v_gal=(0.6, 0.0, 0.9)), piclib.PIC_EINVAL),
+    (dict(v_gal=(0.0, 0.0, float("nan"))), piclib.PIC_EINVAL),
+    (dict(v_gal=(0.0, 0.0, 0.5), psatd_order=0), piclib.PIC_EUNSUPPORTED),   # Galilean needs finite order
+    (dict(v_gal=(0.0, 0.0, 0.9), dt=0.6), piclib.PIC_EINVAL),   # (c + |v_gal|) dt > dx
+    (dict(v_gal=(0.0, 0.0, 0.5), flags=piclib.PIC_SPECTRAL_CENTERING), piclib.PIC_EUNSUPPORTED),
 ])
 def test_init_rejects_bad_params(kw, code):
     lib = piclib.load()

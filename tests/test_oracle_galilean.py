@@ -128,3 +128,17 @@ def test_particle_at_rest_drifts_backwards_in_the_galilean_frame():
     expect = np.mod(pos0 - 0.5 * np.asarray(v)[None, :], np.asarray(shape, dtype=float)[None, :])
     np.testing.assert_allclose(sp["pos"], expect, atol=1e-14)
     assert max(np.max(np.abs(j)) for j in out["J_nod"]) == 0.0
+
+
+def test_extended_precision_branch_agrees_with_float64_closed_forms():
+    """Where the float64 closed forms are still accurate (|W dt| ~ 0.1), the 40-digit evaluation
+    used below |W dt| = 0.05 gives the same coefficients."""
+    k = (0.7, -0.3, 0.2)
+    for W in (0.1, 0.2, -0.3):
+        dt = 0.5
+        mp = psatd._galilean_mp(*k, W, dt)
+        ks = tuple(np.array([x]) for x in k)
+        kc = (np.array([W]), np.array([0.0]), np.array([0.0]))  # W = v . [k]_c with v = (1, 0, 0)
+        gc = psatd.galilean_coefficients(ks, kc, (1.0, 0.0, 0.0), dt)
+        for key, val in mp.items():
+            assert abs(complex(gc[key][0]) - val) <= 1e-12 * (abs(val) + 1e-3), key
