@@ -152,6 +152,8 @@ def main():
     ap.add_argument("--field-adjoint", action="store_true",
                     help="also time psatd_push_fields and its reverse mode psatd_push_fields_adjoint "
                          "(\"field_solve\" in the JSON line)")
+    ap.add_argument("--galilean", type=float, default=None, metavar="VZ",
+                    help="also time the workload with the standard Galilean solver, v_gal = (0, 0, VZ) c")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the forward+backward measurement of the differentiable workload (laser64, FP32, "
                          "60 steps, kinetic-energy loss, checkpoints every 10 steps)")
@@ -179,6 +181,15 @@ def main():
     result = run_gpu(wl, args.config, args.steps, args.warmup, args.calibrate_copy, flags)
     if args.field_adjoint:
         result["field_solve"] = time_field_solve(wl, flags)
+    if args.galilean is not None:
+        r = run_gpu(wl, args.config, args.steps, args.warmup, 0, flags, v_gal=(0.0, 0.0, args.galilean))
+        M = wl.shape[0] * wl.shape[1] * (wl.shape[2] // 2 + 1)
+        s = 4 if wl.dtype == "f32" else 8
+        upd = M * (11 * 2 * s + 12 * s + 6 * 2 * s)  # 11 spectra and 6 complex tables in, 6 spectra out
+        ms = r["stages"]["psatd_update"]["ms_avg"]
+        result["galilean"] = {"v_gal": [0.0, 0.0, args.galilean], "ms_per_step": r["ms_per_step"],
+                              "value": r["value"], "stages": {k: v["ms_avg"] for k, v in r["stages"].items()},
+                              "psatd_update_algo_bytes": upd, "psatd_update_GBps": round(upd / (ms * 1e-3) / 1e9, 1)}
     if not args.no_adjoint:
         print(f"[bench] forward+backward of {args.adjoint_config} ...", file=sys.stderr, flush=True)
         result["fwd_bwd"] = time_fwd_bwd(args.adjoint_config, args.checkpoint_every)
@@ -307,13 +318,13 @@ def time_fwd_bwd(config_name, every, reps=3):
             "stage_ms_total_one_run": {k: round(v[0], 3) for k, v in stages.items() if v[1]}}
 
 
-def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0):
+def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0, v_gal=(0.0, 0.0, 0.0)):
     """Times ``steps`` hybrid cycles of the workload (one pic_step call) after ``warmup`` steps."""
     import torch
 
     from paper_2106_12919_amd import lib as piclib
 
-    ctx = piclib.Context.for_workload(wl, flags=flags)
+    ctx = piclib.Context.for_workload(wl, flags=flags, v_gal=v_gal)
     f = ctx.fields_from_workload(wl)
     el = piclib.Species.from_host(wl.electrons, wl.shape, wl.dtype)
     ions = piclib.Species.from_host(wl.ions, wl.shape, wl.dtype)
