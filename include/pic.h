@@ -78,7 +78,15 @@ enum {
    * arrays.  The results are those of the default cycle up to the summation order of the
    * deposition.  For callers that follow particles by index across steps (the reverse
    * mode, pic_step_adjoint). */
-  PIC_KEEP_ORDER = 1u << 2
+  PIC_KEEP_ORDER = 1u << 2,
+  /* Averaged Galilean PSATD (Sec. 4.4, eqs. eq_update_B/E_with_rho_averaged): E, B advance with
+   * the Galilean update (v_gal, possibly zero), and each update also writes the averaged fields
+   * <E>^{n+1}, <B>^{n+1} (coefficients Psi1, Psi2, Y1..Y4 of Sec. 4.4, built in FP64) into
+   * pic_fields.E_avg, B_avg on the Yee grid: the means of the step's solution, continued with
+   * the same J, over [t_n + dt/2, t_n + 3 dt/2].  pic_step gathers the particles' fields from
+   * E_avg, B_avg (centred to the nodes): on entry they hold the averaged fields of time n (the
+   * caller sets them, e.g. to E, B at the first step).  Excludes PIC_SPECTRAL_CENTERING. */
+  PIC_AVERAGED = 1u << 3
 };
 
 typedef struct {
@@ -126,6 +134,8 @@ typedef struct {
   void* rho_old;          /* rho^n on the nodes */
   void* rho_new;          /* rho^{n+1} on the nodes */
   const void* rho_static; /* optional static background charge added by pic_deposit, or NULL */
+  void* E_avg[3];         /* PIC_AVERAGED: averaged E, B on the Yee grid (see the flag); else unused, may be NULL */
+  void* B_avg[3];
 } pic_fields;
 
 /* Create a context on the current HIP device.  Validates *p, builds in FP64 on

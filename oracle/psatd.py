@@ -204,3 +204,76 @@ def update_galilean(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, gc):
     E_new = tuple(TC * Eh[d] + 1j * C_LIGHT ** 2 * TS * kxB[d] + X4 * Jh[d]
                   + 1j * (TX3 * rho_old_h - X2 * rho_new_h) * ks[d] for d in range(3))
     return E_new, B_new
+
+
+# ---------------------------------------------------------------- averaged Galilean PSATD (Sec. 4.4)
+
+def _averaged_closed(ws, W, dt, m):
+    """Psi1, Psi2, Y1, Y2, Y3, Y4 of Sec. 4.4 for one mode (or arrays), with the math module ``m``
+    (numpy or mpmath) providing cos, sin, exp; c = eps0 = 1 as everywhere in the oracle:
+      Psi1 = (theta^3 (w S3 + i W C3) - theta (w S1 + i W C1)) / ((w^2 - W^2) dt)
+      Psi2 = (theta^3 (C3 - i W S3 / w) - theta (C1 - i W S1 / w)) / ((w^2 - W^2) dt)
+      Psi3 = -i theta (theta^2 - 1) / (W dt)
+      Y1 = (1 - Psi1 - i W Psi2) / (eps0 (w^2 - W^2))
+      Y2 = i c^2 (eps0 w^2 Y1 - Psi3 + Psi1) / (eps0 w^2 (theta^2 - 1))
+      Y3 = i c^2 (Psi3 - Psi1 - eps0 theta^2 w^2 Y1) / (eps0 w^2 (theta^2 - 1))
+      Y4 = i W Y1 + Psi2 / eps0
+    with C_m = cos(m w dt / 2), S_m = sin(m w dt / 2)."""
+    c2, eps0 = C_LIGHT ** 2, EPS0
+    C1, S1 = m.cos(ws * dt / 2), m.sin(ws * dt / 2)
+    C3, S3 = m.cos(3 * ws * dt / 2), m.sin(3 * ws * dt / 2)
+    th = m.exp(1j * W * dt / 2)
+    th2, th3 = th * th, th * th * th
+    den = (ws * ws - W * W) * dt
+    Psi1 = (th3 * (ws * S3 + 1j * W * C3) - th * (ws * S1 + 1j * W * C1)) / den
+    Psi2 = (th3 * (C3 - 1j * W * S3 / ws) - th * (C1 - 1j * W * S1 / ws)) / den
+    Psi3 = -1j * th * (th2 - 1) / (W * dt)
+    Y1 = (1 - Psi1 - 1j * W * Psi2) / (eps0 * (ws * ws - W * W))
+    Y2 = 1j * c2 * (eps0 * ws * ws * Y1 - Psi3 + Psi1) / (eps0 * ws * ws * (th2 - 1))
+    Y3 = 1j * c2 * (Psi3 - Psi1 - eps0 * th2 * ws * ws * Y1) / (eps0 * ws * ws * (th2 - 1))
+    Y4 = 1j * W * Y1 + Psi2 / eps0
+    return {"Psi1": Psi1, "Psi2": Psi2, "Y1": Y1, "Y2": Y2, "Y3": Y3, "Y4": Y4}
+
+
+def averaged_coefficients(ks, kc, v_gal, dt):
+    """Per-mode coefficients of the averaged Galilean update (Sec. 4.4, eqs.
+    ``eq_update_B/E_with_rho_averaged``).  Reading (the paper defers the averaging to its
+    reference): <f>^{n+1} is the mean of the step's exact solution, continued with the same
+    J^{n+1/2}, over [t_n + dt/2, t_n + 3 dt/2] -- the interval whose end points give the
+    theta, C1, S1, theta^3, C3, S3 of Psi1 and Psi2.
+    The closed forms cancel across the whole spectrum (Y2, Y3 twice: through Y1 and through
+    theta^2 - 1; float64 leaves ~1e-13) and have removable singularities at W = 0 (Psi3, Y2, Y3)
+    and at w_s = W (k = 0 on grids, |v_gal| < c), so every mode is evaluated in 40-digit
+    arithmetic (mpmath), at W = 1e-15 w_s where W = 0 and at w_s = 1e-12 where w_s = 0 (80 digits
+    there): the coefficients are smooth functions of (w_s^2, W), so these values equal the limits
+    to ~1e-15 relative."""
+    import mpmath as mp
+    ksx, ksy, ksz = np.broadcast_arrays(*ks)
+    kcx, kcy, kcz = np.broadcast_arrays(*kc)
+    ws = C_LIGHT * np.sqrt(ksx ** 2 + ksy ** 2 + ksz ** 2)
+    W = v_gal[0] * kcx + v_gal[1] * kcy + v_gal[2] * kcz
+    W = np.where(np.abs(W * dt) < 1e-12, 0.0, W)
+    out = {k: np.zeros(ws.shape, dtype=complex) for k in ("Psi1", "Psi2", "Y1", "Y2", "Y3", "Y4")}
+    for idx in np.ndindex(*ws.shape):
+        w, Wv = float(ws[idx]), float(W[idx])
+        with mp.workdps(80 if (w == 0 or Wv == 0) else 40):
+            wm = mp.mpf(w) if w != 0 else mp.mpf("1e-12")
+            Wm = mp.mpf(Wv) if Wv != 0 else wm * mp.mpf("1e-15")
+            vals = _averaged_closed(wm, Wm, mp.mpf(dt), mp)
+            for key, val in vals.items():
+                out[key][idx] = complex(val)
+    return out
+
+
+def update_averaged(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, ac):
+    """The averaged fields of Sec. 4.4 from the step's start values:
+      <B>^{n+1} = Psi1 B^n + i Psi2 [k]_s x E^n + i Y1 [k]_s x J^{n+1/2}
+      <E>^{n+1} = Psi1 E^n - i c^2 Psi2 [k]_s x B^n + Y4 J^{n+1/2} + (Y3 rho^n + Y2 rho^{n+1}) [k]_s"""
+    kxE = cross(ks, Eh)
+    kxB = cross(ks, Bh)
+    kxJ = cross(ks, Jh)
+    P1, P2, Y1, Y2, Y3, Y4 = ac["Psi1"], ac["Psi2"], ac["Y1"], ac["Y2"], ac["Y3"], ac["Y4"]
+    B_avg = tuple(P1 * Bh[d] + 1j * P2 * kxE[d] + 1j * Y1 * kxJ[d] for d in range(3))
+    E_avg = tuple(P1 * Eh[d] - 1j * C_LIGHT ** 2 * P2 * kxB[d] + Y4 * Jh[d]
+                  + (Y3 * rho_old_h + Y2 * rho_new_h) * ks[d] for d in range(3))
+    return E_avg, B_avg

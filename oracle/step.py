@@ -20,6 +20,11 @@ With a nonzero ``Params.v_gal`` the field solve is the standard Galilean PSATD u
 (Sec. 4.3) and the particles move in the Galilean frame, x += dt (v - v_gal) (the frame
 whose Fourier-space Maxwell equations carry the -v_gal . grad term of Sec. 4.3).
 
+With ``Params.averaged`` (Sec. 4.4) the state also carries the averaged fields E_avg, B_avg:
+the particles are pushed by their centering, and each step replaces them by the means of the
+step's solution over [t_n + dt/2, t_n + 3 dt/2] (``psatd.averaged_coefficients``) while E, B
+advance with the Galilean update.
+
 With ``Params.nodal`` the same function runs the standard nodal PSATD cycle the paper
 compares against (Sec. 2, first cycle figure; Sec. 4.1 [k]_c): every field on the nodes,
 no centering, the update with the centered modified wave numbers.
@@ -43,6 +48,7 @@ class Params:
     psatd_order: int = 16   # 2 m_p for [k]_s; 0 = infinite
     nodal: bool = False     # the nodal comparison cycle: every field on the nodes, [k]_c, no centering
     v_gal: tuple = (0.0, 0.0, 0.0)  # Galilean velocity (Sec. 4.3); zero = standard PSATD
+    averaged: bool = False  # averaged Galilean PSATD (Sec. 4.4): particles see the averaged fields
 
     @property
     def lengths(self):
@@ -122,11 +128,40 @@ def push_fields(E_stag, B_stag, J_stag, rho_old, rho_new, p):
     return E_out, B_out
 
 
+_AVERAGED_CACHE = {}
+
+
+def averaged_fields(E_stag, B_stag, J_stag, rho_old, rho_new, p):
+    """<E>^{n+1}, <B>^{n+1} of the averaged Galilean update (Sec. 4.4) on the Yee grid, from the
+    step's start fields and sources (the Galilean update itself advances E, B)."""
+    if p.nodal:
+        ks = psatd.centered_wave_vector(p.shape, p.spacing, p.psatd_order)
+        offsets = {name: (0.0, 0.0, 0.0) for name in OFFSETS}
+    else:
+        ks = psatd.staggered_wave_vector(p.shape, p.spacing, p.psatd_order)
+        offsets = OFFSETS
+    key = (p.shape, p.spacing, p.psatd_order, p.dt, tuple(p.v_gal), p.nodal)
+    if key not in _AVERAGED_CACHE:  # slow (arbitrary precision): once per configuration
+        kc = psatd.centered_wave_vector(p.shape, p.spacing, p.psatd_order)
+        _AVERAGED_CACHE[key] = psatd.averaged_coefficients(ks, kc, p.v_gal, p.dt)
+    ac = _AVERAGED_CACHE[key]
+    fw = lambda f, name: transforms.forward(f, p.spacing, offsets[name])
+    E_avg, B_avg = psatd.update_averaged([fw(E_stag[d], E_NAMES[d]) for d in range(3)],
+                                         [fw(B_stag[d], B_NAMES[d]) for d in range(3)],
+                                         [fw(J_stag[d], J_NAMES[d]) for d in range(3)],
+                                         fw(rho_old, "rho"), fw(rho_new, "rho"), ks, ac)
+    return ([transforms.inverse(E_avg[d], p.spacing, offsets[E_NAMES[d]]) for d in range(3)],
+            [transforms.inverse(B_avg[d], p.spacing, offsets[B_NAMES[d]]) for d in range(3)])
+
+
 def step(state, species, p, rho_static=None):
     """Advance ``state`` (dict: E_stag, B_stag, rho_old) and ``species`` (list of dicts) by one cycle.
 
     Returns a dict of the intermediate arrays of the step (for stage-by-stage parity)."""
-    E_nod, B_nod = center_fields_s2n(state["E_stag"], state["B_stag"], p)
+    if p.averaged:  # the particles see the averaged fields (state["E_avg"], ["B_avg"] at time n)
+        E_nod, B_nod = center_fields_s2n(state["E_avg"], state["B_avg"], p)
+    else:
+        E_nod, B_nod = center_fields_s2n(state["E_stag"], state["B_stag"], p)
     J_nod = [np.zeros(p.shape) for _ in range(3)]
     for sp in species:
         v, pos_half = gather_push(sp, E_nod, B_nod, p)
@@ -136,6 +171,9 @@ def step(state, species, p, rho_static=None):
                 J_nod[d] += Jc[d]
     rho_new = deposit_rho(species, p, rho_static)
     J_stag = center_current_n2s(J_nod, p)
+    if p.averaged:
+        state["E_avg"], state["B_avg"] = averaged_fields(state["E_stag"], state["B_stag"], J_stag, state["rho_old"],
+                                                         rho_new, p)
     E_out, B_out = push_fields(state["E_stag"], state["B_stag"], J_stag, state["rho_old"], rho_new, p)
     state["E_stag"], state["B_stag"], state["rho_old"] = E_out, B_out, rho_new
     return {"E_nod": E_nod, "B_nod": B_nod, "J_nod": J_nod, "J_stag": J_stag, "rho_new": rho_new}

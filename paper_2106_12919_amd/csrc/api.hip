@@ -143,6 +143,7 @@ struct Engine : EngineBase {
   cplx<T>* Jh[3] = {nullptr, nullptr, nullptr};
   cplx<T>* rh[2] = {nullptr, nullptr};
   cplx<T>* scratch[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  cplx<T>* Ah[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // averaged <E>, <B> spectra
   T* tmp = nullptr;
   std::vector<void*> allocs;
 
@@ -279,15 +280,18 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
   if ((err = e.upload(&e.tab.X1, X1)) != hipSuccess) return err;
   if ((err = e.upload(&e.tab.X2, X2)) != hipSuccess) return err;
   if ((err = e.upload(&e.tab.X3, X3)) != hipSuccess) return err;
-  if (p.v_gal[0] != 0 || p.v_gal[1] != 0 || p.v_gal[2] != 0) {
-    // standard Galilean PSATD (Sec. 4.3): W = v_gal . [k]_c per mode
+  if (p.v_gal[0] != 0 || p.v_gal[1] != 0 || p.v_gal[2] != 0 || (p.flags & PIC_AVERAGED)) {
+    // standard Galilean PSATD (Sec. 4.3): W = v_gal . [k]_c per mode; averaged (Sec. 4.4) too
     std::vector<double> kc[3];
     for (int a = 0; a < 3; ++a) {
       kc[a].resize(n[a]);
       k_centered_axis(n[a], d[a], p.psatd_order, kc[a].data());
     }
-    std::vector<cplx<T>> G[6];
+    const bool avg = (p.flags & PIC_AVERAGED) != 0;
+    std::vector<cplx<T>> G[6], Av[6];
     for (auto& v : G) v.resize(M);
+    if (avg)
+      for (auto& v : Av) v.resize(M);
     std::complex<double> g[6];
     for (int i = 0; i < p.nx; ++i)
       for (int j = 0; j < p.ny; ++j)
@@ -297,9 +301,16 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
           const double W = p.v_gal[0] * kc[0][i] + p.v_gal[1] * kc[1][j] + p.v_gal[2] * kc[2][k];
           galilean_coefficients(w, W, p.dt, g);
           for (int q = 0; q < 6; ++q) G[q][idx] = cmake((T)g[q].real(), (T)g[q].imag());
+          if (avg) {
+            averaged_coefficients(w, W, p.dt, g);
+            for (int q = 0; q < 6; ++q) Av[q][idx] = cmake((T)g[q].real(), (T)g[q].imag());
+          }
         }
     for (int q = 0; q < 6; ++q)
       if ((err = e.upload(&e.tab.G[q], G[q])) != hipSuccess) return err;
+    if (avg)
+      for (int q = 0; q < 6; ++q)
+        if ((err = e.upload(&e.tab.Av[q], Av[q])) != hipSuccess) return err;
   }
   // spectra and scratch, zeroed once (padding columns stay zero)
   const size_t ns = e.fft.spectrum_elems();
@@ -310,6 +321,11 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
     if ((err = e.alloc(b, ns)) != hipSuccess) return err;
     if ((err = hipMemset(*b, 0, ns * sizeof(cplx<T>))) != hipSuccess) return err;
   }
+  if (p.flags & PIC_AVERAGED)
+    for (int q = 0; q < 6; ++q) {
+      if ((err = e.alloc(&e.Ah[q], ns)) != hipSuccess) return err;
+      if ((err = hipMemset(e.Ah[q], 0, ns * sizeof(cplx<T>))) != hipSuccess) return err;
+    }
   if ((err = e.alloc(&e.tmp, (size_t)p.nx * p.ny * p.nz)) != hipSuccess) return err;
   // deposition tiles of kTile^3 = 8^3 cells: the LDS box of 4 components is at most
   // 4 * 13^3 * 8 B = 70 KiB (FP64, cubic); the gather box 13^3 nodes * 6 components
@@ -347,7 +363,7 @@ pic_status validate_params(const pic_params* p, std::string& msg) {
     return PIC_EUNSUPPORTED;
   }
   if (p->dtype != PIC_F32 && p->dtype != PIC_F64) { msg = "dtype must be PIC_F32 or PIC_F64"; return PIC_EINVAL; }
-  if (p->flags & ~(uint32_t)(PIC_SPECTRAL_CENTERING | PIC_NODAL_SOLVER | PIC_KEEP_ORDER)) {
+  if (p->flags & ~(uint32_t)(PIC_SPECTRAL_CENTERING | PIC_NODAL_SOLVER | PIC_KEEP_ORDER | PIC_AVERAGED)) {
     msg = "unknown bit in flags";
     return PIC_EINVAL;
   }
@@ -362,6 +378,10 @@ pic_status validate_params(const pic_params* p, std::string& msg) {
     return PIC_EUNSUPPORTED;
   }
   if (vg2 > 0 && (p->flags & PIC_SPECTRAL_CENTERING)) {
+    msg = "PIC_SPECTRAL_CENTERING is built for the standard PSATD update only";
+    return PIC_EUNSUPPORTED;
+  }
+  if ((p->flags & PIC_AVERAGED) && (p->flags & PIC_SPECTRAL_CENTERING)) {
     msg = "PIC_SPECTRAL_CENTERING is built for the standard PSATD update only";
     return PIC_EUNSUPPORTED;
   }
@@ -418,7 +438,10 @@ SpeciesView<T> view(const pic_species& x) {
   return v;
 }
 
-bool galilean(const pic_params& p) { return p.v_gal[0] != 0 || p.v_gal[1] != 0 || p.v_gal[2] != 0; }
+bool galilean(const pic_params& p) {
+  return p.v_gal[0] != 0 || p.v_gal[1] != 0 || p.v_gal[2] != 0 || (p.flags & PIC_AVERAGED) != 0;
+}
+bool averaged(const pic_params& p) { return (p.flags & PIC_AVERAGED) != 0; }
 
 GridGeom geom(const pic_params& p) {
   GridGeom g = make_geom(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order);
@@ -584,12 +607,26 @@ void forward_batch(pic_ctx c, Engine<T>& e, const T* const* src, cplx<T>* const*
 template <typename T>
 void update_and_inverse(pic_ctx c, Engine<T>& e, pic_fields* f, int rho_old_slot, bool spectral = false) {
   const pic_params& p = c->p;
+  const bool avg = averaged(p);
   {
     StageScope sc(c, ST_UPDATE);
     psatd_update<T>(e.tab, e.Eh, e.Bh, e.Jh, e.rh[rho_old_slot], e.rh[1 - rho_old_slot], p.nx, p.ny, e.fft.nzh,
-                    e.fft.pz, spectral ? e.scratch : nullptr, c->stream);
+                    e.fft.pz, spectral ? e.scratch : (avg ? e.Ah : nullptr), c->stream);
   }
   StageScope sc(c, ST_FFT_INV);
+  if (avg) {  // the averaged fields of Sec. 4.4 to the Yee grid (the particles' next gather)
+    Batch<const cplx<T>*> ain{};
+    Batch<cplx<T>*> ascr{};
+    Batch<T*> aout{};
+    for (int d = 0; d < 3; ++d) {
+      ain.p[d] = e.Ah[d];
+      ain.p[3 + d] = e.Ah[3 + d];
+      aout.p[d] = static_cast<T*>(f->E_avg[d]);
+      aout.p[3 + d] = static_cast<T*>(f->B_avg[d]);
+    }
+    for (int i = 0; i < 6; ++i) ascr.p[i] = e.scratch[i];
+    e.fft.inverse(ain, ascr, aout, 6, (T)(1.0 / (double)ncells(p)), c->stream);
+  }
   Batch<const cplx<T>*> in{};
   Batch<cplx<T>*> scr{};
   Batch<T*> out{};
@@ -722,10 +759,11 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
   const bool nodal = (p.flags & PIC_NODAL_SOLVER) != 0;
   const T *Enod[3], *Bnod[3];
   EB_nod<T>(f, Enod, Bnod);
-  if (nodal)  // nodal solver: the state itself is nodal, gathered directly
+  const bool avg = averaged(p);
+  if (nodal)  // nodal solver: the state itself is nodal, gathered directly (averaged: its mean)
     for (int d = 0; d < 3; ++d) {
-      Enod[d] = static_cast<const T*>(f->E_stag[d]);
-      Bnod[d] = static_cast<const T*>(f->B_stag[d]);
+      Enod[d] = static_cast<const T*>(avg ? f->E_avg[d] : f->E_stag[d]);
+      Bnod[d] = static_cast<const T*>(avg ? f->B_avg[d] : f->B_stag[d]);
     }
   T* Jn[3];
   J_ptrs<T>(f, Jn);
@@ -741,8 +779,14 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
   for (int n = 0; n < nsteps; ++n) {
     if (!nodal && (!spectral || n == 0)) {  // spectral centering: later steps get E_nod, B_nod from the update
       StageScope sc(c, ST_S2N);
-      if ((st = do_center<T>(c, PIC_S2N, PIC_E, f)) != PIC_OK) return st;
-      if ((st = do_center<T>(c, PIC_S2N, PIC_B, f)) != PIC_OK) return st;
+      pic_fields t = *f;  // averaged PSATD: the particles see the averaged fields
+      if (avg)
+        for (int d = 0; d < 3; ++d) {
+          t.E_stag[d] = f->E_avg[d];
+          t.B_stag[d] = f->B_avg[d];
+        }
+      if ((st = do_center<T>(c, PIC_S2N, PIC_E, &t)) != PIC_OK) return st;
+      if ((st = do_center<T>(c, PIC_S2N, PIC_B, &t)) != PIC_OK) return st;
     }
     {
       StageScope sc(c, ST_CLEAR);
@@ -994,6 +1038,16 @@ pic_status check_fields(pic_ctx c, const pic_fields* f, bool E_stag, bool B_stag
   return PIC_OK;
 }
 
+pic_status check_avg(pic_ctx c, const pic_fields* f) {
+  if (!averaged(c->p)) return PIC_OK;
+  pic_status st;
+  for (int d = 0; d < 3; ++d) {
+    if ((st = check_ptr(c, f->E_avg[d], "E_avg")) != PIC_OK) return st;
+    if ((st = check_ptr(c, f->B_avg[d], "B_avg")) != PIC_OK) return st;
+  }
+  return PIC_OK;
+}
+
 pic_status device_ok(pic_ctx c) {
   if (!c) return PIC_ESTATE;
   if (!c->eng) return c->fail(PIC_ESTATE, "context has no engine");
@@ -1105,6 +1159,7 @@ pic_status psatd_push_fields(pic_ctx ctx, pic_fields* f) {
   pic_status st = device_ok(ctx);
   if (st != PIC_OK) return st;
   if ((st = check_fields(ctx, f, true, true, false, false, false, true, true, true)) != PIC_OK) return st;
+  if ((st = check_avg(ctx, f)) != PIC_OK) return st;
   return PIC_DISPATCH(ctx, do_push_fields, f);
 }
 
@@ -1130,6 +1185,7 @@ pic_status pic_step(pic_ctx ctx, pic_fields* f, pic_species* sp, int nsp, int ns
   if (nsteps < 0) return ctx->fail(PIC_EINVAL, "nsteps < 0");
   if ((st = check_species(ctx, sp, nsp)) != PIC_OK) return st;
   if ((st = check_fields(ctx, f, true, true, true, true, true, true, true, true)) != PIC_OK) return st;
+  if ((st = check_avg(ctx, f)) != PIC_OK) return st;
   return PIC_DISPATCH(ctx, do_step, f, sp, nsp, nsteps);
 }
 

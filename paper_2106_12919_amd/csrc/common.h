@@ -66,6 +66,8 @@ void k_staggered_axis(int n, double d, int order, double* out);  // [k]_s on fft
 // Standard Galilean PSATD coefficients of one mode (Sec. 4.3), w = c |[k]_s|, W = v_gal . [k]_c:
 // out = theta^2 C, theta^2 S/w, X1, X2, theta^2 X3, X4 (complex, FP64).
 void galilean_coefficients(double w, double W, double dt, std::complex<double>* out);
+// Averaged Galilean PSATD coefficients of one mode (Sec. 4.4): Psi1, Psi2, Y1, Y2, Y3, Y4.
+void averaged_coefficients(double w, double W, double dt, std::complex<double>* out);
 void alpha_centered(int m, double* out);                   // out[n-1], n = 1..m
 void k_centered_axis(int n, double d, int order, double* out);   // [k]_c on fftfreq order
 void psatd_coefficients(double w, double dt, double* C, double* S_over_w, double* X1, double* X2, double* X3);

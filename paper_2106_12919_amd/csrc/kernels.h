@@ -48,11 +48,15 @@ struct PsatdTables {
   // Standard Galilean PSATD (Sec. 4.3), complex per mode: theta^2 C, theta^2 S/w_s, X1, X2,
   // theta^2 X3, X4 (all null for standard PSATD)
   cplx<T>* G[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // Averaged Galilean PSATD (Sec. 4.4): Psi1, Psi2, Y1, Y2, Y3, Y4 (null unless averaging)
+  cplx<T>* Av[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 // With nodal != nullptr (spectral centering): J holds the NODAL current spectra, centred
 // to the Yee grid by the symbols Tc inside the update, and nodal[0..5] receive the
 // centred spectra of the updated E (0..2) and B (3..5), ready for the inverse FFT.
 template <typename T>
+// With averaged tables (t.Av), ``nodal`` instead receives the averaged spectra <E>, <B> of
+// Sec. 4.4 (Yee grid, 6 arrays), computed from the fields at the step's start.
 void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B[3], const cplx<T>* const J[3],
                   const cplx<T>* rho_old, const cplx<T>* rho_new, int nx, int ny, int nzh, int pz,
                   cplx<T>* const* nodal, hipStream_t s);

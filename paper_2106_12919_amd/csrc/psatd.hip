@@ -31,7 +31,11 @@ namespace {
 //   bx' = TC bx - TS (D+y ez - D+z ey) + X1 (D+y jz - D+z jy)
 //   ex' = TC ex + TS (D-y bz - D-z by) + X4 jx + (TX3 ro - X2 rn) D+x,
 // TC = theta^2 C, TS = theta^2 S/w_s, TX3 = theta^2 X3 (theta = exp(i v_gal . [k]_c dt / 2)).
-template <typename T, bool SPECTRAL, bool GAL>
+// AVG (with GAL): also the averaged fields of Sec. 4.4 (eqs. eq_update_B/E_with_rho_averaged)
+// from the start values, into NOD (Yee-grid spectra), [k]_s = -i D+ for the charge term:
+//   <bx> = Psi1 bx + Psi2 (D+y ez - D+z ey) + Y1 (D+y jz - D+z jy)
+//   <ex> = Psi1 ex - Psi2 (D-y bz - D-z by) + Y4 jx - i (Y3 ro + Y2 rn) D+x.
+template <typename T, bool SPECTRAL, bool GAL, bool AVG = false>
 __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cplx<T>*> F, Batch<const cplx<T>*> S,
                                                       Batch<cplx<T>*> NOD, int nx, int ny, int nzh, int pz) {
   const long long total = (long long)nx * ny * nzh;
@@ -87,6 +91,21 @@ __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cp
   const cplx<T> cJx = csub(cmul(py, jz), cmul(pzd, jy));
   const cplx<T> cJy = csub(cmul(pzd, jx), cmul(px, jz));
   const cplx<T> cJz = csub(cmul(px, jy), cmul(py, jx));
+  if (AVG) {  // from the start values (E, B are overwritten below)
+    const cplx<T> P1 = t.Av[0][idx], P2 = t.Av[1][idx], Y1 = t.Av[2][idx], Y2 = t.Av[3][idx], Y3 = t.Av[4][idx],
+                  Y4 = t.Av[5][idx];
+    const cplx<T> cBx = csub(cmul(my, bz), cmul(mz, by));
+    const cplx<T> cBy = csub(cmul(mz, bx), cmul(mx, bz));
+    const cplx<T> cBz = csub(cmul(mx, by), cmul(my, bx));
+    const cplx<T> r2 = cadd(cmul(Y3, ro), cmul(Y2, rn));
+    const cplx<T> mr = cmake(r2.y, -r2.x);  // -i (Y3 ro + Y2 rn)
+    NOD.p[0][a] = cadd(cadd(csub(cmul(P1, ex), cmul(P2, cBx)), cmul(Y4, jx)), cmul(mr, px));
+    NOD.p[1][a] = cadd(cadd(csub(cmul(P1, ey), cmul(P2, cBy)), cmul(Y4, jy)), cmul(mr, py));
+    NOD.p[2][a] = cadd(cadd(csub(cmul(P1, ez), cmul(P2, cBz)), cmul(Y4, jz)), cmul(mr, pzd));
+    NOD.p[3][a] = cadd(cadd(cmul(P1, bx), cmul(P2, cEx)), cmul(Y1, cJx));
+    NOD.p[4][a] = cadd(cadd(cmul(P1, by), cmul(P2, cEy)), cmul(Y1, cJy));
+    NOD.p[5][a] = cadd(cadd(cmul(P1, bz), cmul(P2, cEz)), cmul(Y1, cJz));
+  }
   const cplx<T> nbx = cadd(csub(mul(gC, bx), mul(gS, cEx)), mul(g1, cJx));
   const cplx<T> nby = cadd(csub(mul(gC, by), mul(gS, cEy)), mul(g1, cJy));
   const cplx<T> nbz = cadd(csub(mul(gC, bz), mul(gS, cEz)), mul(g1, cJz));
@@ -195,8 +214,10 @@ void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B
     for (int q = 0; q < 6; ++q) N.p[q] = nodal[q];
   const long long total = (long long)nx * ny * nzh;
   const dim3 grid((unsigned)((total + 255) / 256));
-  if (nodal)  // spectral centering (standard PSATD only)
+  if (nodal && !t.Av[0])  // spectral centering (standard PSATD only)
     hipLaunchKernelGGL((k_psatd_update<T, true, false>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
+  else if (t.Av[0])
+    hipLaunchKernelGGL((k_psatd_update<T, false, true, true>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
   else if (t.G[0])
     hipLaunchKernelGGL((k_psatd_update<T, false, true>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
   else

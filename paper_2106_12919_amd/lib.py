@@ -25,6 +25,7 @@ PIC_DEP_RHO_AND_J, PIC_DEP_RHO_ONLY = 0, 1
 PIC_SPECTRAL_CENTERING = 1 << 0
 PIC_NODAL_SOLVER = 1 << 1
 PIC_KEEP_ORDER = 1 << 2
+PIC_AVERAGED = 1 << 3
 
 
 class pic_params(Structure):
@@ -42,7 +43,8 @@ class pic_species(Structure):
 class pic_fields(Structure):
     _fields_ = [("E_stag", c_void_p * 3), ("B_stag", c_void_p * 3), ("E_nod", c_void_p * 3),
                 ("B_nod", c_void_p * 3), ("J_nod", c_void_p * 3), ("J_stag", c_void_p * 3),
-                ("rho_old", c_void_p), ("rho_new", c_void_p), ("rho_static", c_void_p)]
+                ("rho_old", c_void_p), ("rho_new", c_void_p), ("rho_static", c_void_p),
+                ("E_avg", c_void_p * 3), ("B_avg", c_void_p * 3)]
 
 
 class pic_species_adjoint(Structure):
@@ -288,7 +290,7 @@ class Fields:
 
     NAMES3 = ("E_stag", "B_stag", "E_nod", "B_nod", "J_nod", "J_stag")
 
-    def __init__(self, shape, dtype, device="cuda"):
+    def __init__(self, shape, dtype, device="cuda", averaged=False):
         import torch
         td = torch.float32 if dtype == "f32" else torch.float64
         self.shape, self.dtype = tuple(shape), dtype
@@ -297,6 +299,9 @@ class Fields:
         self.rho_old = torch.zeros(shape, dtype=td, device=device)
         self.rho_new = torch.zeros(shape, dtype=td, device=device)
         self.rho_static = None
+        # averaged fields (PIC_AVERAGED)
+        self.E_avg = [torch.zeros(shape, dtype=td, device=device) for _ in range(3)] if averaged else None
+        self.B_avg = [torch.zeros(shape, dtype=td, device=device) for _ in range(3)] if averaged else None
 
     def struct(self):
         f = pic_fields()
@@ -307,6 +312,9 @@ class Fields:
         f.rho_old = _ptr(self.rho_old)
         f.rho_new = _ptr(self.rho_new)
         f.rho_static = _ptr(self.rho_static)
+        for d in range(3):
+            f.E_avg[d] = _ptr(self.E_avg[d]) if self.E_avg else None
+            f.B_avg[d] = _ptr(self.B_avg[d]) if self.B_avg else None
         return f
 
 
@@ -350,11 +358,14 @@ class Context:
     def fields_from_workload(self, wl, device="cuda"):
         """Fields with the workload's initial E, B; rho_static from the ions; rho_old = rho^0."""
         import torch
-        f = Fields(self.shape, self.dtype, device)
+        f = Fields(self.shape, self.dtype, device, averaged=bool(self.params.flags & PIC_AVERAGED))
         td = f.rho_old.dtype
         for d in range(3):
             f.E_stag[d].copy_(torch.from_numpy(wl.E[d]).to(td))
             f.B_stag[d].copy_(torch.from_numpy(wl.B[d]).to(td))
+            if f.E_avg:  # the averaged fields of the first step: the initial fields
+                f.E_avg[d].copy_(f.E_stag[d])
+                f.B_avg[d].copy_(f.B_stag[d])
         return f
 
     def init_charge(self, f, electrons, ions):

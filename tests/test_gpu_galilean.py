@@ -98,3 +98,76 @@ def test_galilean_rejects_reverse_mode():
     with pytest.raises(RuntimeError, match="Galilean"):
         piclib.psatd_push_fields_adjoint(ctx.ctx, f)
     ctx.close()
+
+
+# ---------------------------------------------------------------- averaged Galilean PSATD (Sec. 4.4)
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("v_gal", [(0.0, 0.0, -0.998888), (0.3, -0.4, 0.5), (0.0, 0.0, 0.0)])
+@pytest.mark.parametrize("nodal", [False, True])
+def test_averaged_push_fields_parity(dtype, v_gal, nodal):
+    shape, dt = (16, 24, 32), 0.5
+    banner(f"psatd_push_fields averaged dtype={dtype} v_gal={v_gal} nodal={nodal}")
+    flags = piclib.PIC_AVERAGED | (piclib.PIC_NODAL_SOLVER if nodal else 0)
+    p = ostep.Params(shape, (1.0, 1.0, 1.0), dt, 1, 8, 16, nodal=nodal, v_gal=v_gal, averaged=True)
+    ctx = piclib.Context(shape, (1.0, 1.0, 1.0), dt, 1, 8, 16, dtype, flags=flags, v_gal=v_gal)
+    f = piclib.Fields(shape, dtype, averaged=True)
+    src = rounded(inputs.random_grid(shape, seed=19, count=11), dtype)
+    put(f.E_stag, src[0:3])
+    put(f.B_stag, src[3:6])
+    put(f.J_stag, src[6:9])
+    put([f.rho_old, f.rho_new], src[9:11])
+    piclib.psatd_push_fields(ctx.ctx, f)
+    piclib.pic_sync(ctx.ctx)
+    E_ref, B_ref = ostep.push_fields(src[0:3], src[3:6], src[6:9], src[9], src[10], p)
+    Ea_ref, Ba_ref = ostep.averaged_fields(src[0:3], src[3:6], src[6:9], src[9], src[10], p)
+    tol = fft_tol(dtype, shape)
+    for d in range(3):
+        assert max_rel(np64(f.E_stag[d]), E_ref[d]) <= tol, ("E", d)
+        assert max_rel(np64(f.B_stag[d]), B_ref[d]) <= tol, ("B", d)
+        assert max_rel(np64(f.E_avg[d]), Ea_ref[d]) <= tol, ("<E>", d, max_rel(np64(f.E_avg[d]), Ea_ref[d]))
+        assert max_rel(np64(f.B_avg[d]), Ba_ref[d]) <= tol, ("<B>", d, max_rel(np64(f.B_avg[d]), Ba_ref[d]))
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("shape_order", [1, 3])
+def test_averaged_step_parity(dtype, shape_order):
+    """Three cycles of the averaged Galilean scheme (v_gal = -0.9 c along z): the particles are pushed
+    by the averaged fields (the initial fields at the first step), against the oracle."""
+    shape, v_gal = (16, 16, 24), (0.0, 0.0, -0.9)
+    banner(f"pic_step averaged dtype={dtype} shape_order={shape_order}")
+    wl = inputs.small(shape, ppc=2, shape_order=shape_order, center_order=8, dtype=dtype, u_th=0.1,
+                      field_amp=0.05, seed=57)
+    base = 2.0 ** np.floor(np.log2(wl.electrons.w[0]))
+    wl.electrons.w = base * (1.0 + np.arange(wl.electrons.n) * 2.0 ** -23)
+    ctx = piclib.Context.for_workload(wl, flags=piclib.PIC_AVERAGED, v_gal=v_gal)
+    f = ctx.fields_from_workload(wl)
+    el = piclib.Species.from_host(wl.electrons, shape, dtype)
+    ions = piclib.Species.from_host(wl.ions, shape, dtype)
+    ctx.init_charge(f, el, ions)
+    p = ostep.Params(shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order, v_gal=v_gal,
+                     averaged=True)
+    osp = oracle_species(el, shape, wl.spacing)
+    oion = oracle_species(ions, shape, wl.spacing)
+    rho_static = ostep.deposit_rho([oion], p)
+    E0, B0 = rounded(wl.E, dtype), rounded(wl.B, dtype)
+    state = {"E_stag": E0, "B_stag": B0, "rho_old": ostep.deposit_rho([osp], p, rho_static),
+             "E_avg": [a.copy() for a in E0], "B_avg": [b.copy() for b in B0]}
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    for n in range(3):
+        piclib.pic_step(ctx.ctx, f, [el], 1)
+        piclib.pic_sync(ctx.ctx)
+        ostep.step(state, [osp], p, rho_static)
+        for d in range(3):
+            assert max_rel(np64(f.E_stag[d]), state["E_stag"][d]) <= tol, (n, "E", d)
+            assert max_rel(np64(f.B_stag[d]), state["B_stag"][d]) <= tol, (n, "B", d)
+            assert max_rel(np64(f.E_avg[d]), state["E_avg"][d]) <= tol, (n, "<E>", d)
+            assert max_rel(np64(f.B_avg[d]), state["B_avg"][d]) <= tol, (n, "<B>", d)
+        g_w = np64(el.w)
+        gi, oi = np.argsort(g_w), np.argsort(osp["w"])
+        g_pos = el.positions(shape, wl.spacing)[gi]
+        g_u = np.stack([np64(x) for x in el.u], axis=1)[gi]
+        assert periodic_pos_err(g_pos, osp["pos"][oi], p.lengths) <= (1e-11 if dtype == "f64" else 2e-5)
+        assert np.max(np.abs(g_u - osp["u"][oi])) <= (1e-11 if dtype == "f64" else 2e-5)
+    ctx.close()

@@ -142,3 +142,80 @@ def test_extended_precision_branch_agrees_with_float64_closed_forms():
         gc = psatd.galilean_coefficients(ks, kc, (1.0, 0.0, 0.0), dt)
         for key, val in mp.items():
             assert abs(complex(gc[key][0]) - val) <= 1e-12 * (abs(val) + 1e-3), key
+
+
+# ---------------------------------------------------------------- averaged Galilean PSATD (Sec. 4.4)
+
+def _ode_average(ks, W, E0, B0, J, dt):
+    """Mean over [dt/2, 3 dt/2] of the exact solution of the Galilean Fourier-space Maxwell
+    equations (c = eps0 = 1) from (E0, B0) with constant J: the state is integrated to dt/2, then
+    together with its running integral to 3 dt/2."""
+    def rhs(t, y, acc):
+        z = y[:6] + 1j * y[6:12]
+        E, B = z[:3], z[3:]
+        dB = 1j * W * B - 1j * np.cross(ks, E)
+        dE = 1j * W * E + 1j * np.cross(ks, B) - J
+        d = np.concatenate([dE, dB])
+        out = np.concatenate([d.real, d.imag])
+        if acc:
+            out = np.concatenate([out, y[:12] / dt])
+        return out
+    z0 = np.concatenate([E0, B0])
+    y0 = np.concatenate([z0.real, z0.imag])
+    s1 = solve_ivp(lambda t, y: rhs(t, y, False), (0.0, dt / 2), y0, method="DOP853", rtol=1e-13, atol=1e-15)
+    y1 = np.concatenate([s1.y[:, -1], np.zeros(12)])
+    s2 = solve_ivp(lambda t, y: rhs(t, y, True), (dt / 2, 1.5 * dt), y1, method="DOP853", rtol=1e-13, atol=1e-15)
+    a = s2.y[12:, -1]
+    z = a[:6] + 1j * a[6:]
+    return z[:3], z[3:]
+
+
+@pytest.mark.parametrize("order,v", [(16, (0.0, 0.0, -0.999)), (4, (0.2, 0.6, -0.5)), (8, (0.0, 0.0, 0.0))])
+def test_averaged_update_is_the_mean_of_the_exact_solution(order, v):
+    """Sec. 4.4: <E>, <B> equal the mean of the step's exact solution (same J) over
+    [t_n + dt/2, t_n + 3 dt/2], with Gauss-consistent data and the Galilean continuity equation
+    (a high-accuracy ODE integration), including k = 0 and W = 0 modes."""
+    shape, dt = (8, 8, 16), 0.5
+    ks, kc = _grid_k(shape, order)
+    ac = psatd.averaged_coefficients(ks, kc, v, dt)
+    ksx, ksy, ksz = np.broadcast_arrays(*ks)
+    kcx, kcy, kcz = np.broadcast_arrays(*kc)
+    rng = np.random.default_rng(5)
+    picks = [(0, 0, 0), (1, 0, 0), (0, 0, 8)] + [tuple(int(rng.integers(0, n)) for n in shape) for _ in range(14)]
+    for idx in picks:
+        k = np.array([ksx[idx], ksy[idx], ksz[idx]], dtype=float)
+        W = v[0] * kcx[idx] + v[1] * kcy[idx] + v[2] * kcz[idx]
+        W = 0.0 if abs(W * dt) < 1e-12 else W
+        E0 = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        B0 = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        if np.dot(k, k) > 0:
+            B0 = B0 - k * np.dot(k, B0) / np.dot(k, k)
+        J = rng.standard_normal(3) + 1j * rng.standard_normal(3)
+        rho0 = 1j * np.dot(k, E0)
+        kJ = np.dot(k, J)
+        rho1 = np.exp(1j * W * dt) * rho0 + (-1j * kJ) * ((np.exp(1j * W * dt) - 1) / (1j * W) if W != 0 else dt)
+        g = {key: np.array(val[idx]) for key, val in ac.items()}
+        kv = [np.array(x) for x in k]
+        Ea, Ba = psatd.update_averaged([np.array(x) for x in E0], [np.array(x) for x in B0],
+                                       [np.array(x) for x in J], np.array(rho0), np.array(rho1), kv, g)
+        Er, Br = _ode_average(k, W, E0, B0, J, dt)
+        scale = np.max(np.abs(np.concatenate([Er, Br]))) + 1
+        assert np.max(np.abs(np.array([complex(x) for x in Ea]) - Er)) <= 1e-9 * scale, idx
+        assert np.max(np.abs(np.array([complex(x) for x in Ba]) - Br)) <= 1e-9 * scale, idx
+
+
+def test_averaged_coefficients_without_galilean_velocity():
+    """v_gal = 0: the means of cos(w t), -sin(w t)/w and (1 - cos(w t))/w^2 over [dt/2, 3 dt/2]."""
+    shape, dt = (8, 12, 16), 0.7
+    ks, kc = _grid_k(shape, 16)
+    ac = psatd.averaged_coefficients(ks, kc, (0.0, 0.0, 0.0), dt)
+    ksx, ksy, ksz = np.broadcast_arrays(*ks)
+    w = np.sqrt(ksx ** 2 + ksy ** 2 + ksz ** 2)
+    big = w * dt > 0.3
+    wb = w[big]
+    P1 = (np.sin(1.5 * wb * dt) - np.sin(0.5 * wb * dt)) / (wb * dt)
+    P2 = (np.cos(1.5 * wb * dt) - np.cos(0.5 * wb * dt)) / (wb * wb * dt)
+    np.testing.assert_allclose(ac["Psi1"][big], P1, atol=1e-13)
+    np.testing.assert_allclose(ac["Psi2"][big], P2, atol=1e-13)
+    np.testing.assert_allclose(ac["Y1"][big], (1 - P1) / wb ** 2, atol=1e-13)
+    np.testing.assert_allclose(ac["Y4"][big], P2, atol=1e-13)
