@@ -4,6 +4,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pic.h"
@@ -292,8 +293,9 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
     for (auto& v : G) v.resize(M);
     if (avg)
       for (auto& v : Av) v.resize(M);
-    std::complex<double> g[6];
-    for (int i = 0; i < p.nx; ++i)
+    // x-planes of modes spread over the host's threads (quadrature per mode)
+    auto plane = [&](int i) {
+      std::complex<double> g[6];
       for (int j = 0; j < p.ny; ++j)
         for (int k = 0; k < nzh; ++k) {
           const size_t idx = ((size_t)i * p.ny + j) * nzh + k;
@@ -306,6 +308,14 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
             for (int q = 0; q < 6; ++q) Av[q][idx] = cmake((T)g[q].real(), (T)g[q].imag());
           }
         }
+    };
+    const int nth = std::max(1, std::min(std::min(p.nx, 16), (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nth; ++t)
+      pool.emplace_back([&, t] {
+        for (int i = t; i < p.nx; i += nth) plane(i);
+      });
+    for (auto& th : pool) th.join();
     for (int q = 0; q < 6; ++q)
       if ((err = e.upload(&e.tab.G[q], G[q])) != hipSuccess) return err;
     if (avg)
@@ -605,7 +615,8 @@ void forward_batch(pic_ctx c, Engine<T>& e, const T* const* src, cplx<T>* const*
 // B_stag, or (spectral centering) of the nodal spectra the update also wrote, in place in
 // the scratch spectra, into E_nod, B_nod.
 template <typename T>
-void update_and_inverse(pic_ctx c, Engine<T>& e, pic_fields* f, int rho_old_slot, bool spectral = false) {
+void update_and_inverse(pic_ctx c, Engine<T>& e, pic_fields* f, int rho_old_slot, bool spectral = false,
+                        bool state_out = true) {
   const pic_params& p = c->p;
   const bool avg = averaged(p);
   {
@@ -626,6 +637,7 @@ void update_and_inverse(pic_ctx c, Engine<T>& e, pic_fields* f, int rho_old_slot
     }
     for (int i = 0; i < 6; ++i) ascr.p[i] = e.scratch[i];
     e.fft.inverse(ain, ascr, aout, 6, (T)(1.0 / (double)ncells(p)), c->stream);
+    if (!state_out) return;  // pic_step: the state stays in Fourier space until the call's end
   }
   Batch<const cplx<T>*> in{};
   Batch<cplx<T>*> scr{};
@@ -878,10 +890,11 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
       cplx<T>* dst[4] = {e.Jh[0], e.Jh[1], e.Jh[2], e.rh[1 - slot]};
       forward_batch<T>(c, e, src, dst, 4);
     }
-    update_and_inverse<T>(c, e, f, slot, spectral);
+    update_and_inverse<T>(c, e, f, slot, spectral, !avg);
     slot = 1 - slot;
     if ((st = c->check("pic_step")) != PIC_OK) return st;
   }
+  if (avg) state_inverse<T>(c, e, f);  // averaged: the particles used E_avg, B_avg; the state once, here
   if (spectral) {  // the outputs the real-space cycle leaves: the staggered state and J_stag
     state_inverse<T>(c, e, f);
     StageScope sc(c, ST_N2S);
