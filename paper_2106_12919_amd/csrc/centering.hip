@@ -131,19 +131,10 @@ __global__ void __launch_bounds__(256) k_center_z(const T* __restrict__ in, T* _
   }
 }
 
-// L outputs per thread: long windows reuse each input L + 2m - 1 times over; grids too small
-// to give the device enough workgroups that way take L = 4.
 template <typename T, int M>
 void launch_strided(const T* in, T* out, const Coef<T>& cf, int Na, long long sa, int C, int O, long long os,
                     int shift, hipStream_t s) {
   constexpr int L = (sizeof(T) == 4) ? 16 : 8;
-  constexpr int Ls = 4;
-  const long long blocks = (long long)((C + 255) / 256) * ((Na + L - 1) / L) * O;
-  if (blocks < 2048) {
-    dim3 grid((C + 255) / 256, (Na + Ls - 1) / Ls, O);
-    hipLaunchKernelGGL((k_center_strided<T, M, Ls>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift);
-    return;
-  }
   dim3 grid((C + 255) / 256, (Na + L - 1) / L, O);
   hipLaunchKernelGGL((k_center_strided<T, M, L>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift);
 }
