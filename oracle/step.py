@@ -25,6 +25,11 @@ the particles are pushed by their centering, and each step replaces them by the 
 step's solution over [t_n + dt/2, t_n + 3 dt/2] (``psatd.averaged_coefficients``) while E, B
 advance with the Galilean update.
 
+With ``Params.staggered`` it runs the fully staggered cycle the paper compares against (Sec. 2;
+the staggered runs of Sec. 5.2-5.3): every field and J on the Yee grid, each component gathered
+from and deposited to its own Yee positions (the shape centred on x_i + delta_c), rho on the
+nodes, no centering, the same staggered PSATD update.
+
 With ``Params.nodal`` the same function runs the standard nodal PSATD cycle the paper
 compares against (Sec. 2, first cycle figure; Sec. 4.1 [k]_c): every field on the nodes,
 no centering, the update with the centered modified wave numbers.
@@ -49,14 +54,20 @@ class Params:
     nodal: bool = False     # the nodal comparison cycle: every field on the nodes, [k]_c, no centering
     v_gal: tuple = (0.0, 0.0, 0.0)  # Galilean velocity (Sec. 4.3); zero = standard PSATD
     averaged: bool = False  # averaged Galilean PSATD (Sec. 4.4): particles see the averaged fields
+    staggered: bool = False  # the fully staggered comparison cycle: Yee gather and deposition, no centering
 
     @property
     def lengths(self):
         return tuple(n * d for n, d in zip(self.shape, self.spacing))
 
 
+def _yee_shift(name, p):
+    """The half-cell offset vector of a component's Yee position (physical units)."""
+    return np.asarray(OFFSETS[name], dtype=np.float64) * np.asarray(p.spacing, dtype=np.float64)
+
+
 def center_fields_s2n(E_stag, B_stag, p):
-    if p.nodal:  # nodal cycle: the state is already nodal
+    if p.nodal or p.staggered:  # nodal cycle: the state is nodal; staggered cycle: gathered where it lives
         return [np.array(a) for a in E_stag], [np.array(a) for a in B_stag]
     m = p.center_order // 2
     E_nod = [centering.s2n(E_NAMES[d], E_stag[d], m) for d in range(3)]
@@ -65,10 +76,19 @@ def center_fields_s2n(E_stag, B_stag, p):
 
 
 def center_current_n2s(J_nod, p):
-    if p.nodal:
+    if p.nodal or p.staggered:  # staggered cycle: J was deposited on the Yee grid
         return [np.array(a) for a in J_nod]
     m = p.center_order // 2
     return [centering.n2s(J_NAMES[d], J_nod[d], m) for d in range(3)]
+
+
+def gather_fields(E_nod, B_nod, pos, p):
+    """E, B at the particles, shape (6, Np): from the nodes (one weight set), or in the staggered
+    cycle each component from its own Yee positions, S(x_p - (x_i + delta_c))."""
+    if p.staggered:
+        return np.stack([particles.gather([F], pos - _yee_shift(name, p)[None, :], p.spacing, p.shape_order)[0]
+                         for F, name in zip(list(E_nod) + list(B_nod), E_NAMES + B_NAMES)])
+    return particles.gather(list(E_nod) + list(B_nod), pos, p.spacing, p.shape_order)
 
 
 def gather_push(sp, E_nod, B_nod, p):
@@ -76,7 +96,7 @@ def gather_push(sp, E_nod, B_nod, p):
     pos, u = sp["pos"], sp["u"]
     if not np.isfinite(sp["m"]):
         return np.zeros((3, pos.shape[0])), pos.copy()
-    EB = particles.gather(list(E_nod) + list(B_nod), pos, p.spacing, p.shape_order)
+    EB = gather_fields(E_nod, B_nod, pos, p)
     u_new = particles.boris(u.T, EB[:3], EB[3:], sp["q"], sp["m"], p.dt)
     v = u_new / particles.gamma(u_new)
     # in the Galilean frame (coordinates moving with v_gal) a particle moves at v - v_gal
@@ -97,6 +117,9 @@ def deposit_rho(species, p, rho_static=None):
 
 def deposit_current(sp, v, pos_half, p):
     qw = sp["q"] * sp["w"]
+    if p.staggered:  # J^d onto its own Yee positions
+        return [particles.deposit([qw * v[d]], pos_half - _yee_shift(J_NAMES[d], p)[None, :], p.shape, p.spacing,
+                                  p.shape_order)[0] for d in range(3)]
     return particles.deposit([qw * v[0], qw * v[1], qw * v[2]], pos_half, p.shape, p.spacing, p.shape_order)
 
 
