@@ -86,7 +86,15 @@ enum {
    * the same J, over [t_n + dt/2, t_n + 3 dt/2].  pic_step gathers the particles' fields from
    * E_avg, B_avg (centred to the nodes): on entry they hold the averaged fields of time n (the
    * caller sets them, e.g. to E, B at the first step).  Excludes PIC_SPECTRAL_CENTERING. */
-  PIC_AVERAGED = 1u << 3
+  PIC_AVERAGED = 1u << 3,
+  /* The fully staggered cycle the paper compares the hybrid one against (Sec. 2; the staggered runs
+   * of Sec. 5.2-5.3): no centering; pic_gather_push interpolates every component of E_stag, B_stag
+   * from its own Yee positions (the B-spline centred on x_i + delta_c), pic_deposit adds J^d onto
+   * the Yee positions of J^d (into J_stag; rho^{n+1} stays nodal) and pic_step runs that cycle with
+   * the same staggered PSATD update.  Particles keep the caller's order.  One particle per thread
+   * with global atomics (a comparison path, not tuned).  Excludes PIC_NODAL_SOLVER,
+   * PIC_SPECTRAL_CENTERING and PIC_AVERAGED; no reverse mode. */
+  PIC_STAGGERED_CYCLE = 1u << 4
 };
 
 typedef struct {
@@ -162,6 +170,7 @@ pic_status pic_set_stream(pic_ctx ctx, void* hip_stream);
  * x^{n+1/2} = x^{n+1} - dt v/2 (direct deposition).  S is the B-spline of
  * shape_order.  Immobile species contribute to rho only.  nsp >= 0 species. */
 pic_status pic_deposit(pic_ctx ctx, const pic_species* sp, int nsp, pic_fields* f, int mode);
+/* (With PIC_STAGGERED_CYCLE: J^d onto the Yee positions of J^d, into f->J_stag; see the flag.) */
 
 /* Finite-order centering (Sec. 3, eq. staggered_finite_sum, order center_order):
  *   dir = PIC_N2S, what = PIC_J : J_nod -> J_stag, J^d along axis d,
@@ -198,6 +207,7 @@ pic_status psatd_push_fields_adjoint(pic_ctx ctx, pic_fields* f);
  * relativistic Boris scheme: u^{n-1/2} -> u^{n+1/2}, x^{n+1} = x^n + dt u/gamma,
  * periodic wrap of cell and offset. */
 pic_status pic_gather_push(pic_ctx ctx, const pic_fields* f, pic_species* sp, int nsp);
+/* (With PIC_STAGGERED_CYCLE: from E_stag, B_stag, each component at its own Yee positions.) */
 
 /* nsteps >= 0 complete hybrid cycles.  State on entry: E_stag, B_stag at time n,
  * particles at x^n with u^{n-1/2}, rho_old = rho^n.  Each step runs

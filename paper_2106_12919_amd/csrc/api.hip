@@ -373,7 +373,8 @@ pic_status validate_params(const pic_params* p, std::string& msg) {
     return PIC_EUNSUPPORTED;
   }
   if (p->dtype != PIC_F32 && p->dtype != PIC_F64) { msg = "dtype must be PIC_F32 or PIC_F64"; return PIC_EINVAL; }
-  if (p->flags & ~(uint32_t)(PIC_SPECTRAL_CENTERING | PIC_NODAL_SOLVER | PIC_KEEP_ORDER | PIC_AVERAGED)) {
+  if (p->flags &
+      ~(uint32_t)(PIC_SPECTRAL_CENTERING | PIC_NODAL_SOLVER | PIC_KEEP_ORDER | PIC_AVERAGED | PIC_STAGGERED_CYCLE)) {
     msg = "unknown bit in flags";
     return PIC_EINVAL;
   }
@@ -389,6 +390,11 @@ pic_status validate_params(const pic_params* p, std::string& msg) {
   }
   if (vg2 > 0 && (p->flags & PIC_SPECTRAL_CENTERING)) {
     msg = "PIC_SPECTRAL_CENTERING is built for the standard PSATD update only";
+    return PIC_EUNSUPPORTED;
+  }
+  if ((p->flags & PIC_STAGGERED_CYCLE) &&
+      (p->flags & (PIC_NODAL_SOLVER | PIC_SPECTRAL_CENTERING | PIC_AVERAGED))) {
+    msg = "PIC_STAGGERED_CYCLE excludes PIC_NODAL_SOLVER, PIC_SPECTRAL_CENTERING and PIC_AVERAGED";
     return PIC_EUNSUPPORTED;
   }
   if ((p->flags & PIC_AVERAGED) && (p->flags & PIC_SPECTRAL_CENTERING)) {
@@ -452,6 +458,7 @@ bool galilean(const pic_params& p) {
   return p.v_gal[0] != 0 || p.v_gal[1] != 0 || p.v_gal[2] != 0 || (p.flags & PIC_AVERAGED) != 0;
 }
 bool averaged(const pic_params& p) { return (p.flags & PIC_AVERAGED) != 0; }
+bool yee_cycle(const pic_params& p) { return (p.flags & PIC_STAGGERED_CYCLE) != 0; }
 
 GridGeom geom(const pic_params& p) {
   GridGeom g = make_geom(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order);
@@ -523,10 +530,32 @@ void J_ptrs(pic_fields* f, T* J[3]) {
   for (int d = 0; d < 3; ++d) J[d] = static_cast<T*>(f->J_nod[d]);
 }
 
+// The staggered cycle's sources: rho^{n+1} on the nodes, J on the Yee grid (J_stag).
+template <typename T>
+void deposit_yee_all(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, bool with_j) {
+  const size_t N = ncells(c->p);
+  if (f->rho_static)
+    (void)hipMemcpyAsync(f->rho_new, f->rho_static, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+  else
+    (void)hipMemsetAsync(f->rho_new, 0, N * sizeof(T), c->stream);
+  T* J[3];
+  for (int d = 0; d < 3; ++d) {
+    J[d] = static_cast<T*>(f->J_stag[d]);
+    if (with_j) (void)hipMemsetAsync(J[d], 0, N * sizeof(T), c->stream);
+  }
+  const GridGeom g = geom(c->p);
+  for (int s = 0; s < nsp; ++s)
+    deposit_yee<T>(g, view<T>(sp[s]), with_j && std::isfinite(sp[s].m), static_cast<T*>(f->rho_new), J, c->stream);
+}
+
 template <typename T>
 pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, int mode) {
   Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
   const bool with_j = (mode == PIC_DEP_RHO_AND_J);
+  if (yee_cycle(c->p)) {
+    deposit_yee_all<T>(c, sp, nsp, f, with_j);
+    return c->check("pic_deposit");
+  }
   zero_sources<T>(c, f, with_j);
   T* J[3];
   J_ptrs<T>(f, J);
@@ -562,6 +591,14 @@ pic_status do_gather_push(pic_ctx c, const pic_fields* f, pic_species* sp, int n
   const GridGeom g = geom(c->p);
   const T *E[3], *B[3];
   EB_nod<T>(f, E, B);
+  if (yee_cycle(c->p)) {  // every component from its own Yee positions
+    for (int d = 0; d < 3; ++d) {
+      E[d] = static_cast<const T*>(f->E_stag[d]);
+      B[d] = static_cast<const T*>(f->B_stag[d]);
+    }
+    for (int s = 0; s < nsp; ++s) gather_push_yee<T>(g, E, B, view<T>(sp[s]), c->stream);
+    return c->check("pic_gather_push");
+  }
   for (int s = 0; s < nsp; ++s)
     if (std::isfinite(sp[s].m) && sp[s].n > 0) {
       hipError_t he = e.ensure_species((size_t)s, sp[s].n);
@@ -747,11 +784,63 @@ pic_status do_push_fields_adjoint(pic_ctx c, pic_fields* f) {
   return c->check("psatd_push_fields_adjoint");
 }
 
+// pic_step of the fully staggered cycle: gather from the Yee grid, deposit J onto it, no centering.
+template <typename T>
+pic_status do_step_yee(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nsteps) {
+  Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
+  const pic_params& p = c->p;
+  int slot = 0;
+  {
+    StageScope sc(c, ST_ENTRY);
+    const T* src[7];
+    cplx<T>* dst[7];
+    for (int d = 0; d < 3; ++d) {
+      src[d] = static_cast<const T*>(f->E_stag[d]);
+      dst[d] = e.Eh[d];
+      src[3 + d] = static_cast<const T*>(f->B_stag[d]);
+      dst[3 + d] = e.Bh[d];
+    }
+    src[6] = static_cast<const T*>(f->rho_old);
+    dst[6] = e.rh[slot];
+    forward_batch<T>(c, e, src, dst, 7);
+  }
+  const GridGeom g = geom(p);
+  const T *E[3], *B[3];
+  for (int d = 0; d < 3; ++d) {
+    E[d] = static_cast<const T*>(f->E_stag[d]);
+    B[d] = static_cast<const T*>(f->B_stag[d]);
+  }
+  pic_status st;
+  for (int n = 0; n < nsteps; ++n) {
+    {
+      StageScope sc(c, ST_PUSH);
+      for (int q = 0; q < nsp; ++q) gather_push_yee<T>(g, E, B, view<T>(sp[q]), c->stream);
+    }
+    {
+      StageScope sc(c, ST_DEPOSIT);
+      deposit_yee_all<T>(c, sp, nsp, f, true);
+    }
+    {
+      StageScope sc(c, ST_FFT_FWD);
+      const T* src[4] = {static_cast<const T*>(f->J_stag[0]), static_cast<const T*>(f->J_stag[1]),
+                         static_cast<const T*>(f->J_stag[2]), static_cast<const T*>(f->rho_new)};
+      cplx<T>* dst[4] = {e.Jh[0], e.Jh[1], e.Jh[2], e.rh[1 - slot]};
+      forward_batch<T>(c, e, src, dst, 4);
+    }
+    update_and_inverse<T>(c, e, f, slot);
+    slot = 1 - slot;
+    if ((st = c->check("pic_step")) != PIC_OK) return st;
+  }
+  (void)hipMemcpyAsync(f->rho_old, f->rho_new, ncells(p) * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+  return c->check("pic_step");
+}
+
 template <typename T>
 pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nsteps) {
   Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
   const pic_params& p = c->p;
   if (nsteps == 0) return PIC_OK;
+  if (yee_cycle(p)) return do_step_yee<T>(c, f, sp, nsp, nsteps);
   int slot = 0;  // rh[slot] holds rho^n
   {
     StageScope sc(c, ST_ENTRY);
@@ -1147,7 +1236,8 @@ pic_status pic_deposit(pic_ctx ctx, const pic_species* sp, int nsp, pic_fields* 
   if (st != PIC_OK) return st;
   if (mode != PIC_DEP_RHO_AND_J && mode != PIC_DEP_RHO_ONLY) return ctx->fail(PIC_EINVAL, "bad deposit mode");
   if ((st = check_species(ctx, sp, nsp)) != PIC_OK) return st;
-  if ((st = check_fields(ctx, f, false, false, false, false, mode == PIC_DEP_RHO_AND_J, false, false, true)) != PIC_OK)
+  const bool wj = mode == PIC_DEP_RHO_AND_J, yee = yee_cycle(ctx->p);  // staggered cycle: J into J_stag
+  if ((st = check_fields(ctx, f, false, false, false, false, wj && !yee, wj && yee, false, true)) != PIC_OK)
     return st;
   return PIC_DISPATCH(ctx, do_deposit, sp, nsp, f, mode);
 }
@@ -1188,7 +1278,8 @@ pic_status pic_gather_push(pic_ctx ctx, const pic_fields* f, pic_species* sp, in
   pic_status st = device_ok(ctx);
   if (st != PIC_OK) return st;
   if ((st = check_species(ctx, sp, nsp)) != PIC_OK) return st;
-  if ((st = check_fields(ctx, f, false, false, true, true, false, false, false, false)) != PIC_OK) return st;
+  const bool yee = yee_cycle(ctx->p);  // the staggered cycle gathers from the Yee-grid arrays
+  if ((st = check_fields(ctx, f, yee, yee, !yee, !yee, false, false, false, false)) != PIC_OK) return st;
   return PIC_DISPATCH(ctx, do_gather_push, f, sp, nsp);
 }
 
@@ -1207,6 +1298,7 @@ pic_status pic_step_adjoint(pic_ctx ctx, pic_fields* f, const pic_species* sp, i
   pic_status st = device_ok(ctx);
   if (st != PIC_OK) return st;
   if (galilean(ctx->p)) return ctx->fail(PIC_EUNSUPPORTED, "no reverse mode for the Galilean solver");
+  if (yee_cycle(ctx->p)) return ctx->fail(PIC_EUNSUPPORTED, "no reverse mode for the staggered cycle");
   if ((st = check_species(ctx, sp, nsp)) != PIC_OK) return st;
   const bool nodal = (ctx->p.flags & PIC_NODAL_SOLVER) != 0;
   if ((st = check_fields(ctx, f, true, true, !nodal, !nodal, false, false, false, false)) != PIC_OK) return st;

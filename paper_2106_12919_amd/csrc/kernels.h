@@ -173,6 +173,16 @@ template <typename T>
 void scatter_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
                    const T* const val[6], T* const out[6], T* stage, hipStream_t s);
 
+// The fully staggered comparison cycle: gather + push with every component of E, B (Yee-grid
+// arrays) interpolated from its own Yee positions, in place, one particle per thread; and the
+// deposition of rho^{n+1} (nodes) and J (each component onto its own Yee positions) with global
+// atomics (adds to rho and J).
+template <typename T>
+void gather_push_yee(const GridGeom& g, const T* const E[3], const T* const B[3], const SpeciesView<T>& sp,
+                     hipStream_t s);
+template <typename T>
+void deposit_yee(const GridGeom& g, const SpeciesView<T>& sp, bool with_j, T* rho, T* const J[3], hipStream_t s);
+
 // ---------------------------------------------------------------- reductions (diag.hip)
 // acc[0] += sum of squares over ``count`` arrays of n elements; acc[1] += sum of ``sum_arr``.
 template <typename T>

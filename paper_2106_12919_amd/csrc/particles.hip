@@ -1575,6 +1575,125 @@ __global__ void __launch_bounds__(256) k_scatter_tiled(GridGeom g, TileGeom tg, 
   for (int e = threadIdx.x; e < NV * X::B3; e += blockDim.x) dstage[e] = ldexp((T)box[e], -shs[e / X::B3]);
 }
 
+// ---------------------------------------------------------------- fully staggered comparison cycle
+
+// Half-cell Yee offsets (x, y, z) of E^x, E^y, E^z, B^x, B^y, B^z (J as E), in half cells.
+__constant__ int kYee[6][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {0, 1, 1}, {1, 0, 1}, {1, 1, 0}};
+
+// Cell and offset of x - 1/2 cell along one axis (h = 1) or of x itself (h = 0).
+template <typename T>
+__device__ inline void half_back(int& i, T& o, int h, int n) {
+  if (h) {
+    o -= (T)0.5;
+    if (o < (T)0) {
+      o += (T)1;
+      i = (i == 0) ? n - 1 : i - 1;
+    }
+  }
+}
+
+// sum_n S(x - x_n) A[n] over the S^3 support nodes (from the grid).
+template <typename T, int ORDER>
+__device__ inline T stencil_value(const GridGeom& g, int i, int j, int k, T ox, T oy, T oz, const T* __restrict__ A) {
+  using S = Shape<T, ORDER>;
+  constexpr int NW = S::NW;
+  T wx[NW], wy[NW], wz[NW];
+  S::weights(ox, wx);
+  S::weights(oy, wy);
+  S::weights(oz, wz);
+  int kk[NW];
+#pragma unroll
+  for (int c = 0; c < NW; ++c) kk[c] = wrapi(k + c + S::BASE, g.nz);
+  T acc = 0;
+#pragma unroll
+  for (int a = 0; a < NW; ++a) {
+    const int ii = wrapi(i + a + S::BASE, g.nx);
+#pragma unroll
+    for (int b = 0; b < NW; ++b) {
+      const size_t row = ((size_t)ii * g.ny + wrapi(j + b + S::BASE, g.ny)) * g.nz;
+      const T wab = wx[a] * wy[b];
+#pragma unroll
+      for (int c = 0; c < NW; ++c) acc += wab * wz[c] * A[row + kk[c]];
+    }
+  }
+  return acc;
+}
+
+// Gather + push of the staggered cycle, one particle per thread, in place: each component of
+// E, B interpolated from its own Yee positions (the shape centred on x_i + delta_c, i.e. at
+// x - delta_c from the nodes), then the same Boris push and move as the hybrid cycle.
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(256) k_gather_push_yee(GridGeom g, Batch<const T*> F, SpeciesView<T> sp, T qdt2m,
+                                                         T dtx, T dty, T dtz) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= sp.n) return;
+  int i, j, k;
+  if (!decode_cell(sp.cell[p], g, nullptr, i, j, k)) return;
+  T ox = sp.off[0][p], oy = sp.off[1][p], oz = sp.off[2][p];
+  T f[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    int a = i, b = j, d = k;
+    T x = ox, y = oy, z = oz;
+    half_back(a, x, kYee[c][0], g.nx);
+    half_back(b, y, kYee[c][1], g.ny);
+    half_back(d, z, kYee[c][2], g.nz);
+    f[c] = stencil_value<T, ORDER>(g, a, b, d, x, y, z, F.p[c]);
+  }
+  T ux = sp.u[0][p], uy = sp.u[1][p], uz = sp.u[2][p];
+  BorisState<T> bs;
+  boris(f, qdt2m, ux, uy, uz, bs);
+  const T ig = inv_sqrt((T)1 + ux * ux + uy * uy + uz * uz);
+  i = wrapi(i + advance_offset(ox, dtx * ux * ig - (T)g.sgx), g.nx);
+  j = wrapi(j + advance_offset(oy, dty * uy * ig - (T)g.sgy), g.ny);
+  k = wrapi(k + advance_offset(oz, dtz * uz * ig - (T)g.sgz), g.nz);
+  sp.u[0][p] = ux;
+  sp.u[1][p] = uy;
+  sp.u[2][p] = uz;
+  sp.off[0][p] = ox;
+  sp.off[1][p] = oy;
+  sp.off[2][p] = oz;
+  sp.cell[p] = (i * g.ny + j) * g.nz + k;
+}
+
+// Deposition of the staggered cycle, one particle per thread, with global atomics: rho^{n+1} on
+// the nodes at x^{n+1}; J^d = q w v_d onto its own Yee positions at x^{n+1/2} (the hybrid cycle's
+// half position), i.e. at x^{n+1/2} - delta_d from the nodes.
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(256) k_deposit_yee(GridGeom g, SpeciesView<T> sp, Batch<T*> out, T qdv, T hdtx,
+                                                     T hdty, T hdtz, int with_j) {
+  const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= sp.n) return;
+  int i, j, k;
+  if (!decode_cell(sp.cell[p], g, nullptr, i, j, k)) return;
+  const T ox = sp.off[0][p], oy = sp.off[1][p], oz = sp.off[2][p];
+  const T qw = qdv * (sp.w ? sp.w[p] : (T)sp.w_const);
+  {
+    T* dst[1] = {out.p[0]};
+    const T val[1] = {qw};
+    scatter<T, ORDER>(g, i, j, k, ox, oy, oz, dst, val, 1);
+  }
+  if (!with_j) return;
+  const T ux = sp.u[0][p], uy = sp.u[1][p], uz = sp.u[2][p];
+  const T ig = inv_sqrt((T)1 + ux * ux + uy * uy + uz * uz);
+  const T v[3] = {ux * ig, uy * ig, uz * ig};
+  T hx = ox, hy = oy, hz = oz;
+  const int ih = wrapi(i + advance_offset(hx, -hdtx * v[0] + (T)0.5 * (T)g.sgx), g.nx);
+  const int jh = wrapi(j + advance_offset(hy, -hdty * v[1] + (T)0.5 * (T)g.sgy), g.ny);
+  const int kh = wrapi(k + advance_offset(hz, -hdtz * v[2] + (T)0.5 * (T)g.sgz), g.nz);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int a = ih, b = jh, c = kh;
+    T x = hx, y = hy, z = hz;
+    half_back(a, x, kYee[d][0], g.nx);
+    half_back(b, y, kYee[d][1], g.ny);
+    half_back(c, z, kYee[d][2], g.nz);
+    T* dst[1] = {out.p[1 + d]};
+    const T val[1] = {qw * v[d]};
+    scatter<T, ORDER>(g, a, b, c, x, y, z, dst, val, 1);
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -1785,6 +1904,39 @@ void scatter_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& s
     hipLaunchKernelGGL((k_deposit_reduce<T, 3>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, o, 6);
 }
 
+template <typename T>
+void gather_push_yee(const GridGeom& g, const T* const E[3], const T* const B[3], const SpeciesView<T>& sp,
+                     hipStream_t s) {
+  if (sp.n <= 0 || !std::isfinite(sp.m)) return;
+  Batch<const T*> F{};
+  for (int d = 0; d < 3; ++d) {
+    F.p[d] = E[d];
+    F.p[3 + d] = B[d];
+  }
+  const T qdt2m = (T)(sp.q * g.dt / (2.0 * sp.m));
+  const T dtx = (T)(g.dt / g.dx), dty = (T)(g.dt / g.dy), dtz = (T)(g.dt / g.dz);
+  const dim3 grid((unsigned)((sp.n + 255) / 256));
+  if (g.shape_order == 1)
+    hipLaunchKernelGGL((k_gather_push_yee<T, 1>), grid, dim3(256), 0, s, g, F, sp, qdt2m, dtx, dty, dtz);
+  else
+    hipLaunchKernelGGL((k_gather_push_yee<T, 3>), grid, dim3(256), 0, s, g, F, sp, qdt2m, dtx, dty, dtz);
+}
+
+template <typename T>
+void deposit_yee(const GridGeom& g, const SpeciesView<T>& sp, bool with_j, T* rho, T* const J[3], hipStream_t s) {
+  if (sp.n <= 0) return;
+  Batch<T*> out{};
+  out.p[0] = rho;
+  for (int d = 0; d < 3; ++d) out.p[1 + d] = J ? J[d] : nullptr;
+  const T qdv = (T)(sp.q / (g.dx * g.dy * g.dz));
+  const T hx = (T)(0.5 * g.dt / g.dx), hy = (T)(0.5 * g.dt / g.dy), hz = (T)(0.5 * g.dt / g.dz);
+  const dim3 grid((unsigned)((sp.n + 255) / 256));
+  if (g.shape_order == 1)
+    hipLaunchKernelGGL((k_deposit_yee<T, 1>), grid, dim3(256), 0, s, g, sp, out, qdv, hx, hy, hz, with_j ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_deposit_yee<T, 3>), grid, dim3(256), 0, s, g, sp, out, qdv, hx, hy, hz, with_j ? 1 : 0);
+}
+
 #define PIC_INST(T)                                                                                              \
   template void permute_species<T>(const SpeciesView<T>&, const SpeciesView<T>&, const int*, hipStream_t);       \
   template void deposit_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*, const int*, \
@@ -1798,7 +1950,10 @@ void scatter_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& s
                                     const int*, const int*, const T* const*, const T* const*, const Batch<T*>&,   \
                                     hipStream_t);                                                                 \
   template void scatter_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*, const int*, \
-                                 const T* const*, T* const*, T*, hipStream_t);
+                                 const T* const*, T* const*, T*, hipStream_t);                                    \
+  template void gather_push_yee<T>(const GridGeom&, const T* const*, const T* const*, const SpeciesView<T>&,      \
+                                   hipStream_t);                                                                  \
+  template void deposit_yee<T>(const GridGeom&, const SpeciesView<T>&, bool, T*, T* const*, hipStream_t);
 PIC_INST(float)
 PIC_INST(double)
 #undef PIC_INST

@@ -26,6 +26,7 @@ PIC_SPECTRAL_CENTERING = 1 << 0
 PIC_NODAL_SOLVER = 1 << 1
 PIC_KEEP_ORDER = 1 << 2
 PIC_AVERAGED = 1 << 3
+PIC_STAGGERED_CYCLE = 1 << 4
 
 
 class pic_params(Structure):

@@ -66,6 +66,8 @@ def good_params(**kw):
     (dict(v_gal=(0.0, 0.0, 0.5), psatd_order=0), piclib.PIC_EUNSUPPORTED),   # Galilean needs finite order
     (dict(v_gal=(0.0, 0.0, 0.9), dt=0.6), piclib.PIC_EINVAL),   # (c + |v_gal|) dt > dx
     (dict(flags=piclib.PIC_AVERAGED | piclib.PIC_SPECTRAL_CENTERING), piclib.PIC_EUNSUPPORTED),
+    (dict(flags=piclib.PIC_STAGGERED_CYCLE | piclib.PIC_NODAL_SOLVER), piclib.PIC_EUNSUPPORTED),
+    (dict(flags=piclib.PIC_STAGGERED_CYCLE | piclib.PIC_AVERAGED), piclib.PIC_EUNSUPPORTED),
     (dict(v_gal=(0.0, 0.0, 0.5), flags=piclib.PIC_SPECTRAL_CENTERING), piclib.PIC_EUNSUPPORTED),
 ])
 def test_init_rejects_bad_params(kw, code):
