@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--nodal-solver", action="store_true",
                     help="the nodal comparison cycle (PIC_NODAL_SOLVER): fields on the nodes, centered [k]_c, "
                          "no centering")
+    ap.add_argument("--staggered-cycle", action="store_true",
+                    help="run the fully staggered comparison cycle (PIC_STAGGERED_CYCLE) instead of the hybrid one")
     ap.add_argument("--field-adjoint", action="store_true",
                     help="also time psatd_push_fields and its reverse mode psatd_push_fields_adjoint "
                          "(\"field_solve\" in the JSON line)")
@@ -179,7 +181,8 @@ def main():
     wl = inputs.config(args.config, dtype=args.dtype, center_order=args.center_order)
     print(f"[bench] workload {args.config} dtype={wl.dtype} cells={wl.cells} particles={wl.electrons.n}",
           file=sys.stderr, flush=True)
-    flags = (1 if args.spectral_centering else 0) | (2 if args.nodal_solver else 0)  # PIC_SPECTRAL_CENTERING, PIC_NODAL_SOLVER
+    # PIC_SPECTRAL_CENTERING, PIC_NODAL_SOLVER, PIC_STAGGERED_CYCLE
+    flags = (1 if args.spectral_centering else 0) | (2 if args.nodal_solver else 0) | (16 if args.staggered_cycle else 0)
     result = run_gpu(wl, args.config, args.steps, args.warmup, args.calibrate_copy, flags)
     if args.field_adjoint:
         result["field_solve"] = time_field_solve(wl, flags)
@@ -395,7 +398,9 @@ def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0, v_gal=(0.0,
         "data": "synthetic (seeded laser + plasma workload)",
         "config": {"workload": CONFIG_TEXT[config_name], "cells": N, "particles": Np,
                    "center_order": wl.center_order, "shape_order": wl.shape_order, "pass": "forward",
-                   "centering": "none (nodal solver)" if flags & 2 else ("spectral" if flags & 1 else "real-space")},
+                   "centering": ("none (nodal solver)" if flags & 2 else
+                                 "none (staggered cycle)" if flags & 16 else
+                                 "spectral" if flags & 1 else "real-space")},
         "cell_updates_per_s": N * K / T,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -544,8 +544,20 @@ void deposit_yee_all(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, b
     if (with_j) (void)hipMemsetAsync(J[d], 0, N * sizeof(T), c->stream);
   }
   const GridGeom g = geom(c->p);
-  for (int s = 0; s < nsp; ++s)
-    deposit_yee<T>(g, view<T>(sp[s]), with_j && std::isfinite(sp[s].m), static_cast<T*>(f->rho_new), J, c->stream);
+  Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
+  for (int s = 0; s < nsp; ++s) {
+    if (sp[s].n == 0) continue;
+    const SpeciesView<T> v = view<T>(sp[s]);
+    const bool wj = with_j && std::isfinite(sp[s].m);
+    if (e.ensure_species((size_t)s, sp[s].n) != hipSuccess) {  // no scratch: the untiled path
+      deposit_yee<T>(g, v, wj, static_cast<T*>(f->rho_new), J, c->stream);
+      continue;
+    }
+    SpeciesScratch<T>& x = e.sps[s];
+    tile_sort(g, e.tiles, v.cell, v.n, x.counts[0], x.starts[0], x.cursor, x.dst, c->d_bad, c->stream);
+    invert_perm(x.dst, x.perm, v.n, c->stream);
+    deposit_yee_tiled<T>(g, e.tiles, v, x.perm, x.starts[0], wj, e.stage, static_cast<T*>(f->rho_new), J, c->stream);
+  }
 }
 
 template <typename T>
@@ -811,14 +823,39 @@ pic_status do_step_yee(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int n
     B[d] = static_cast<const T*>(f->B_stag[d]);
   }
   pic_status st;
+  for (int q = 0; q < nsp; ++q) {
+    hipError_t he = e.ensure_species((size_t)q, sp[q].n);
+    if (he != hipSuccess) return c->fail(PIC_ENOMEM, std::string("pic_step: ") + hipGetErrorString(he));
+  }
+  const size_t N = ncells(p);
   for (int n = 0; n < nsteps; ++n) {
     {
-      StageScope sc(c, ST_PUSH);
-      for (int q = 0; q < nsp; ++q) gather_push_yee<T>(g, E, B, view<T>(sp[q]), c->stream);
+      StageScope sc(c, ST_CLEAR);
+      if (f->rho_static)
+        (void)hipMemcpyAsync(f->rho_new, f->rho_static, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+      else
+        (void)hipMemsetAsync(f->rho_new, 0, N * sizeof(T), c->stream);
+      for (int d = 0; d < 3; ++d) (void)hipMemsetAsync(f->J_stag[d], 0, N * sizeof(T), c->stream);
     }
-    {
-      StageScope sc(c, ST_DEPOSIT);
-      deposit_yee_all<T>(c, sp, nsp, f, true);
+    T* J[3] = {static_cast<T*>(f->J_stag[0]), static_cast<T*>(f->J_stag[1]), static_cast<T*>(f->J_stag[2])};
+    for (int q = 0; q < nsp; ++q) {
+      if (sp[q].n == 0) continue;
+      SpeciesScratch<T>& x = e.sps[q];
+      const SpeciesView<T> v = view<T>(sp[q]);
+      {
+        StageScope sc(c, ST_SORT);  // one grouping (cells at n) serves the gather and the deposition
+        tile_sort(g, e.tiles, v.cell, v.n, x.counts[0], x.starts[0], x.cursor, x.dst, c->d_bad, c->stream);
+        invert_perm(x.dst, x.perm, v.n, c->stream);
+      }
+      {
+        StageScope sc(c, ST_PUSH);
+        gather_push_yee_tiled<T>(g, e.tiles, E, B, v, x.perm, x.starts[0], c->stream);
+      }
+      {
+        StageScope sc(c, ST_DEPOSIT);
+        deposit_yee_tiled<T>(g, e.tiles, v, x.perm, x.starts[0], std::isfinite(sp[q].m), e.stage,
+                             static_cast<T*>(f->rho_new), J, c->stream);
+      }
     }
     {
       StageScope sc(c, ST_FFT_FWD);

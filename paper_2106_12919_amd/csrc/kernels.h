@@ -182,6 +182,15 @@ void gather_push_yee(const GridGeom& g, const T* const E[3], const T* const B[3]
                      hipStream_t s);
 template <typename T>
 void deposit_yee(const GridGeom& g, const SpeciesView<T>& sp, bool with_j, T* rho, T* const J[3], hipStream_t s);
+// The same through per-tile fixed-point LDS boxes (grouping of the current cells: perm, starts;
+// stage as deposit_tiled's with 4 components) and the deposition's box reduction.
+template <typename T>
+void deposit_yee_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm,
+                       const int* starts, bool with_j, T* stage, T* rho, T* const J[3], hipStream_t s);
+// gather_push_yee through the grouping of the particles' cells and per-tile LDS boxes of E, B.
+template <typename T>
+void gather_push_yee_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3], const T* const B[3],
+                           const SpeciesView<T>& sp, const int* perm, const int* starts, hipStream_t s);
 
 // ---------------------------------------------------------------- reductions (diag.hip)
 // acc[0] += sum of squares over ``count`` arrays of n elements; acc[1] += sum of ``sum_arr``.

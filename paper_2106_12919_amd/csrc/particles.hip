@@ -1694,6 +1694,197 @@ __global__ void __launch_bounds__(256) k_deposit_yee(GridGeom g, SpeciesView<T> 
   }
 }
 
+// Tiled gather + push of the staggered cycle: one block per tile of the grouping of the particles'
+// cells (slots [starts[t], starts[t+1]) through perm), E, B staged over the tile's box in LDS
+// (FieldSlots layout); each component read at its own shifted stencil; particles updated in
+// place.  Block ntiles (invalid cells) does nothing.
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_yee_tiled(GridGeom g, TileGeom tg, Batch<const T*> F,
+                                                                            SpeciesView<T> sp,
+                                                                            const int* __restrict__ perm,
+                                                                            const int* __restrict__ starts, T qdt2m,
+                                                                            T dtx, T dty, T dtz) {
+  using S = Shape<T, ORDER>;
+  using X = Box<S::NW>;
+  constexpr int NW = S::NW;
+  constexpr int FS = FieldSlots<T>::FS;
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* box = reinterpret_cast<T*>(smem);
+  const int tile = xcd_major(blockIdx.x, gridDim.x);
+  const int beg = starts[tile], end = starts[tile + 1];
+  if (beg == end || tile == tg.ntiles) return;
+  int tx, ty, tz;
+  tile_coords(tile, tg, tx, ty, tz);
+  const int t0x = tx * kTile, t0y = ty * kTile, t0z = tz * kTile;
+  load_field_box<T, ORDER>(box, F, g, t0x, t0y, t0z);
+  __syncthreads();
+  for (int q = beg + threadIdx.x; q < end; q += blockDim.x) {
+    const int p = perm[q];
+    int i, j, k;
+    (void)decode_cell(sp.cell[p], g, nullptr, i, j, k);
+    T ox = sp.off[0][p], oy = sp.off[1][p], oz = sp.off[2][p];
+    T f[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      int a = i, b = j, d = k;
+      T x = ox, y = oy, z = oz;
+      half_back(a, x, kYee[c][0], g.nx);
+      half_back(b, y, kYee[c][1], g.ny);
+      half_back(d, z, kYee[c][2], g.nz);
+      const int lx = box_index(a, t0x, g.nx), ly = box_index(b, t0y, g.ny), lz = box_index(d, t0z, g.nz);
+      if (lx >= 0 && ly >= 0 && lz >= 0) {
+        T wx[NW], wy[NW], wz[NW];
+        S::weights(x, wx);
+        S::weights(y, wy);
+        S::weights(z, wz);
+        const T* b0 = box + (size_t)X::at(lx, ly, lz) * FS + c;
+        T acc = 0;
+#pragma unroll
+        for (int u = 0; u < NW; ++u)
+#pragma unroll
+          for (int v = 0; v < NW; ++v) {
+            const T wuv = wx[u] * wy[v];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) acc += wuv * wz[w] * b0[(u * X::B2 + v * X::B + w) * FS];
+          }
+        f[c] = acc;
+      } else {
+        f[c] = stencil_value<T, ORDER>(g, a, b, d, x, y, z, F.p[c]);
+      }
+    }
+    T ux = sp.u[0][p], uy = sp.u[1][p], uz = sp.u[2][p];
+    BorisState<T> bs;
+    boris(f, qdt2m, ux, uy, uz, bs);
+    const T ig = inv_sqrt((T)1 + ux * ux + uy * uy + uz * uz);
+    i = wrapi(i + advance_offset(ox, dtx * ux * ig - (T)g.sgx), g.nx);
+    j = wrapi(j + advance_offset(oy, dty * uy * ig - (T)g.sgy), g.ny);
+    k = wrapi(k + advance_offset(oz, dtz * uz * ig - (T)g.sgz), g.nz);
+    sp.u[0][p] = ux;
+    sp.u[1][p] = uy;
+    sp.u[2][p] = uz;
+    sp.off[0][p] = ox;
+    sp.off[1][p] = oy;
+    sp.off[2][p] = oz;
+    sp.cell[p] = (i * g.ny + j) * g.nz + k;
+  }
+}
+
+// Tiled deposition of the staggered cycle: one block per tile of the grouping of the particles'
+// current cells (x^{n+1}), rho at x^{n+1} and each J^d at x^{n+1/2} - delta_d (all within one
+// cell of the tile) accumulated in a fixed-point LDS box per component, as in k_scatter_tiled,
+// then staged for the deposition's box reduction.
+template <typename T, int ORDER>
+__global__ void __launch_bounds__(256) k_deposit_yee_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp,
+                                                           const int* __restrict__ perm,
+                                                           const int* __restrict__ starts, Batch<T*> out,
+                                                           T* __restrict__ stage, T qdv, T hdtx, T hdty, T hdtz,
+                                                           int with_j) {
+  using S = Shape<T, ORDER>;
+  using X = Box<S::NW>;
+  constexpr int NV = 4;
+  constexpr int kWaves = 256 / 64;
+  extern __shared__ __align__(16) unsigned char smem[];
+  auto* box = reinterpret_cast<typename Fixed<T>::acc_t*>(smem);
+  __shared__ T red[NV * kWaves], redm[NV * kWaves];
+  __shared__ int shs[NV];
+  const int tile = xcd_major(blockIdx.x, gridDim.x);
+  const int beg = starts[tile], end = starts[tile + 1];
+  if (beg == end) return;
+  int ti, tj, tk;
+  tile_coords(tile, tg, ti, tj, tk);
+  const int t0x = ti * kTile, t0y = tj * kTile, t0z = tk * kTile;
+  // the values: q w / dV and q w v_d / dV
+  auto values = [&](int p, T* val, T* v) {
+    const T qw = qdv * (sp.w ? sp.w[p] : (T)sp.w_const);
+    const T ux = sp.u[0][p], uy = sp.u[1][p], uz = sp.u[2][p];
+    const T ig = inv_sqrt((T)1 + ux * ux + uy * uy + uz * uz);
+    v[0] = ux * ig;
+    v[1] = uy * ig;
+    v[2] = uz * ig;
+    val[0] = qw;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) val[1 + d] = with_j ? qw * v[d] : (T)0;
+  };
+  T sw[NV], mw[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) sw[c] = mw[c] = 0;
+  for (int q = beg + threadIdx.x; q < end; q += blockDim.x) {
+    T val[NV], v[3];
+    values(perm[q], val, v);
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      sw[c] += fabs(val[c]);
+      mw[c] = fmax(mw[c], fabs(val[c]));
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    for (int o = 32; o > 0; o >>= 1) {
+      sw[c] += __shfl_xor(sw[c], o, 64);
+      mw[c] = fmax(mw[c], __shfl_xor(mw[c], o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[c * kWaves + (threadIdx.x >> 6)] = sw[c];
+      redm[c * kWaves + (threadIdx.x >> 6)] = mw[c];
+    }
+  }
+  for (int e = threadIdx.x; e < NV * X::B3; e += blockDim.x) box[e] = 0;
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int c = threadIdx.x;
+    T m = 0, x = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      m += red[c * kWaves + w];
+      x = fmax(x, redm[c * kWaves + w]);
+    }
+    int e_sum = 0, e_max = 0;
+    (void)frexp(m * (T)(MaxWeight<ORDER>::value * 1.001), &e_sum);
+    (void)frexp(x * (T)1.001, &e_max);
+    shs[c] = Fixed<T>::shift(e_sum, e_max, 32 - __clz(end - beg));
+  }
+  __syncthreads();
+  int sh[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) sh[c] = shs[c];
+  auto put = [&](int comp, int i, int j, int k, T ox, T oy, T oz, T val) {
+    const int lx = box_index(i, t0x, g.nx), ly = box_index(j, t0y, g.ny), lz = box_index(k, t0z, g.nz);
+    if (lx >= 0 && ly >= 0 && lz >= 0) {
+      const T sv[1] = {(T)ldexp(val, sh[comp])};
+      scatter_lds<T, ORDER, 1>(box + comp * X::B3, X::at(lx, ly, lz), ox, oy, oz, sv);
+    } else {
+      T* dst[1] = {out.p[comp]};
+      const T v1[1] = {val};
+      scatter<T, ORDER>(g, i, j, k, ox, oy, oz, dst, v1, 1);
+    }
+  };
+  for (int q = beg + threadIdx.x; q < end; q += blockDim.x) {
+    const int p = perm[q];
+    int i, j, k;
+    if (!decode_cell(sp.cell[p], g, nullptr, i, j, k)) continue;
+    const T ox = sp.off[0][p], oy = sp.off[1][p], oz = sp.off[2][p];
+    T val[NV], v[3];
+    values(p, val, v);
+    put(0, i, j, k, ox, oy, oz, val[0]);
+    if (!with_j) continue;
+    T hx = ox, hy = oy, hz = oz;
+    const int ih = wrapi(i + advance_offset(hx, -hdtx * v[0] + (T)0.5 * (T)g.sgx), g.nx);
+    const int jh = wrapi(j + advance_offset(hy, -hdty * v[1] + (T)0.5 * (T)g.sgy), g.ny);
+    const int kh = wrapi(k + advance_offset(hz, -hdtz * v[2] + (T)0.5 * (T)g.sgz), g.nz);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int a = ih, b = jh, c = kh;
+      T x = hx, y = hy, z = hz;
+      half_back(a, x, kYee[d][0], g.nx);
+      half_back(b, y, kYee[d][1], g.ny);
+      half_back(c, z, kYee[d][2], g.nz);
+      put(1 + d, a, b, c, x, y, z, val[1 + d]);
+    }
+  }
+  __syncthreads();
+  T* dstage = stage + (size_t)tile * NV * X::B3;
+  for (int e = threadIdx.x; e < NV * X::B3; e += blockDim.x) dstage[e] = ldexp((T)box[e], -shs[e / X::B3]);
+}
+
 }  // namespace
 
 template <typename T>
@@ -1923,6 +2114,55 @@ void gather_push_yee(const GridGeom& g, const T* const E[3], const T* const B[3]
 }
 
 template <typename T>
+void gather_push_yee_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3], const T* const B[3],
+                           const SpeciesView<T>& sp, const int* perm, const int* starts, hipStream_t s) {
+  if (sp.n <= 0 || !std::isfinite(sp.m)) return;
+  Batch<const T*> F{};
+  for (int d = 0; d < 3; ++d) {
+    F.p[d] = E[d];
+    F.p[3 + d] = B[d];
+  }
+  const T qdt2m = (T)(sp.q * g.dt / (2.0 * sp.m));
+  const T dtx = (T)(g.dt / g.dx), dty = (T)(g.dt / g.dy), dtz = (T)(g.dt / g.dz);
+  const int Bx = deposit_box(g.shape_order);
+  const size_t lds = (size_t)Bx * Bx * Bx * FieldSlots<T>::FS * sizeof(T);
+  const dim3 grid(t.ntiles + 1), block(PIC_GATHER_BLOCK);
+  if (g.shape_order == 1) {
+    allow_lds((const void*)k_gather_push_yee_tiled<T, 1>, lds);
+    hipLaunchKernelGGL((k_gather_push_yee_tiled<T, 1>), grid, block, lds, s, g, t, F, sp, perm, starts, qdt2m, dtx,
+                       dty, dtz);
+  } else {
+    allow_lds((const void*)k_gather_push_yee_tiled<T, 3>, lds);
+    hipLaunchKernelGGL((k_gather_push_yee_tiled<T, 3>), grid, block, lds, s, g, t, F, sp, perm, starts, qdt2m, dtx,
+                       dty, dtz);
+  }
+}
+
+template <typename T>
+void deposit_yee_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm,
+                       const int* starts, bool with_j, T* stage, T* rho, T* const J[3], hipStream_t s) {
+  if (sp.n <= 0) return;
+  Batch<T*> out{};
+  out.p[0] = rho;
+  for (int d = 0; d < 3; ++d) out.p[1 + d] = J[d];
+  const T qdv = (T)(sp.q / (g.dx * g.dy * g.dz));
+  const T hx = (T)(0.5 * g.dt / g.dx), hy = (T)(0.5 * g.dt / g.dy), hz = (T)(0.5 * g.dt / g.dz);
+  const int B = deposit_box(g.shape_order);
+  const size_t lds = (size_t)4 * B * B * B * sizeof(typename Fixed<T>::acc_t);
+  const dim3 grid((unsigned)t.ntiles);
+  if (g.shape_order == 1) {
+    allow_lds((const void*)k_deposit_yee_tiled<T, 1>, lds);
+    hipLaunchKernelGGL((k_deposit_yee_tiled<T, 1>), grid, dim3(256), lds, s, g, t, sp, perm, starts, out, stage, qdv,
+                       hx, hy, hz, with_j ? 1 : 0);
+  } else {
+    allow_lds((const void*)k_deposit_yee_tiled<T, 3>, lds);
+    hipLaunchKernelGGL((k_deposit_yee_tiled<T, 3>), grid, dim3(256), lds, s, g, t, sp, perm, starts, out, stage, qdv,
+                       hx, hy, hz, with_j ? 1 : 0);
+  }
+  deposit_reduce<T>(g, t, starts, stage, true, rho, J, s);
+}
+
+template <typename T>
 void deposit_yee(const GridGeom& g, const SpeciesView<T>& sp, bool with_j, T* rho, T* const J[3], hipStream_t s) {
   if (sp.n <= 0) return;
   Batch<T*> out{};
@@ -1953,7 +2193,11 @@ void deposit_yee(const GridGeom& g, const SpeciesView<T>& sp, bool with_j, T* rh
                                  const T* const*, T* const*, T*, hipStream_t);                                    \
   template void gather_push_yee<T>(const GridGeom&, const T* const*, const T* const*, const SpeciesView<T>&,      \
                                    hipStream_t);                                                                  \
-  template void deposit_yee<T>(const GridGeom&, const SpeciesView<T>&, bool, T*, T* const*, hipStream_t);
+  template void deposit_yee<T>(const GridGeom&, const SpeciesView<T>&, bool, T*, T* const*, hipStream_t);        \
+  template void deposit_yee_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*,         \
+                                     const int*, bool, T*, T*, T* const*, hipStream_t);                           \
+  template void gather_push_yee_tiled<T>(const GridGeom&, const TileGeom&, const T* const*, const T* const*,      \
+                                         const SpeciesView<T>&, const int*, const int*, hipStream_t);
 PIC_INST(float)
 PIC_INST(double)
 #undef PIC_INST
