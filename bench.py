@@ -68,6 +68,10 @@ CONFIG_TEXT = {
                "cubic shape, centering order 8, PSATD order 16, c*dt=0.5",
     "thermal32": "thermal32: 32^3 periodic thermal plasma 8 ppc u_th=0.01, CIC, centering order 8, PSATD order 16",
     "thermal256": "thermal256: 256^3 periodic thermal plasma 8 ppc u_th=0.05, CIC, PSATD order 16",
+    "beam384": "beam384: 384x384x768 periodic beam-driven wake, 1 ppc cold plasma n0=2/256 plus an electron beam "
+               "sigma_r=8 sigma_z=16 gamma=1000 8 ppc inside 3 sigma with its self-fields, cubic shape, "
+               "centering order 16, PSATD order 16, c*dt=0.5",
+    "beam96": "beam96: the beam384 setup scaled by 1/4 per axis (96x96x192)",
 }
 
 

@@ -13,6 +13,11 @@ N(0, u_th^2).  The generator is NumPy's PCG64 seeded per workload.
 Immobile neutralising ions sit on the initial electron positions; each side
 deposits them once into the static charge background.
 
+The beam-driven configuration adds a cold electron beam (Gaussian density, 8 particles per cell
+inside 3 sigma, weights from the density at each particle) to a 1-ppc cold plasma, and starts
+from the beam's relativistic self-fields, solved from its continuous density with the exact wave
+vector and sampled at the Yee positions; only the plasma is neutralised by ions.
+
 The laser of the two laser configurations is sampled at each component's Yee
 position, E_x = E0 exp(-r^2/w0^2) exp(-(z-z0)^2/L^2) cos(k0 (z-z0)), B_y = E_x,
 with E0 = a0 * omega0, k0 = omega0 = 2 pi / wavelength, L = FWHM / (2 sqrt(ln 2)),
@@ -130,6 +135,73 @@ def laser_fields(shape, spacing, a0, wavelength, waist, fwhm, z0):
     return E, B
 
 
+def beam_plasma(rng, shape, n0, gamma, sigma_r, sigma_z, center, ppc_beam=8, extent=3.0):
+    """Cold plasma at 1 particle per cell everywhere plus a cold electron drive beam: 8 particles
+    per cell in the cells whose centres lie inside the ellipsoid of semi-axes 3 sigma, moving
+    along +z with Lorentz factor gamma, weights n_b(x_p) dV / ppc_beam with the Gaussian density
+    n_b = n0 exp(-r^2 / (2 sigma_r^2) - (z - z_c)^2 / (2 sigma_z^2)) (peak n0)."""
+    plasma = uniform_plasma(rng, shape, 1, n0, 0.0)
+    xc, yc, zc = center
+    r = [np.arange(int(np.floor(c - extent * s)), int(np.ceil(c + extent * s)) + 1)
+         for c, s in ((xc, sigma_r), (yc, sigma_r), (zc, sigma_z))]
+    ii, jj, kk = np.meshgrid(*r, indexing="ij")
+    inside = (((ii + 0.5 - xc) / (extent * sigma_r)) ** 2 + ((jj + 0.5 - yc) / (extent * sigma_r)) ** 2
+              + ((kk + 0.5 - zc) / (extent * sigma_z)) ** 2) <= 1.0
+    cells = np.stack([ii[inside], jj[inside], kk[inside]], axis=1).astype(np.int64)
+    cell = np.repeat(cells, ppc_beam, axis=0)
+    n = cell.shape[0]
+    off = rng.random((n, 3))
+    pos = cell + off
+    nb = n0 * np.exp(-((pos[:, 0] - xc) ** 2 + (pos[:, 1] - yc) ** 2) / (2 * sigma_r ** 2)
+                     - (pos[:, 2] - zc) ** 2 / (2 * sigma_z ** 2))
+    u = np.zeros((n, 3))
+    u[:, 2] = np.sqrt(gamma ** 2 - 1.0)
+    beam = Species(cell=cell % np.asarray(shape)[None, :], off=off, u=u, w=nb / ppc_beam, q=-1.0, m=1.0)
+    electrons = Species(cell=np.concatenate([plasma.cell, beam.cell]), off=np.concatenate([plasma.off, beam.off]),
+                        u=np.concatenate([plasma.u, beam.u]), w=np.concatenate([plasma.w, beam.w]))
+    return electrons, plasma
+
+
+def beam_fields(shape, spacing, n0, gamma, sigma_r, sigma_z, center):
+    """Self-fields of the beam's (continuous) Gaussian charge density -n_b, moving along +z at
+    beta = sqrt(1 - 1/gamma^2): phi = rho / (kx^2 + ky^2 + kz^2 / gamma^2),
+    E = -i (kx, ky, kz / gamma^2) phi, B = beta z x E, with the exact (continuum) wave vector,
+    k = 0 set to zero, each component sampled at its Yee position (FFTs of scipy, threaded)."""
+    import scipy.fft as sfft
+    nx, ny, nz = shape
+    xc, yc, zc = center
+    X = (np.arange(nx) - xc)[:, None, None]
+    Y = (np.arange(ny) - yc)[None, :, None]
+    Z = (np.arange(nz) - zc)[None, None, :]
+    rho = -(n0 * np.exp(-(X * X) / (2 * sigma_r ** 2)) * np.exp(-(Y * Y) / (2 * sigma_r ** 2))
+            * np.exp(-(Z * Z) / (2 * sigma_z ** 2)))
+    rh = sfft.fftn(rho.astype(np.complex128), workers=-1)
+    del rho
+    kx = (2 * np.pi * np.fft.fftfreq(nx, spacing[0]))[:, None, None]
+    ky = (2 * np.pi * np.fft.fftfreq(ny, spacing[1]))[None, :, None]
+    kz = (2 * np.pi * np.fft.fftfreq(nz, spacing[2]))[None, None, :]
+    den = kx * kx + ky * ky + kz * kz / gamma ** 2
+    den[0, 0, 0] = 1.0
+    rh /= den
+    rh[0, 0, 0] = 0.0
+    del den
+    beta = np.sqrt(1.0 - 1.0 / gamma ** 2)
+
+    def at(name, comp):  # real samples at the component's Yee positions of the spectrum comp
+        o = _YEE[name]
+        ph = (np.exp(1j * kx * o[0] * spacing[0]) * np.exp(1j * ky * o[1] * spacing[1])
+              * np.exp(1j * kz * o[2] * spacing[2]))
+        return sfft.ifftn(comp * ph, workers=-1).real
+
+    Ex = at("Ex", -1j * kx * rh)
+    Ey = at("Ey", -1j * ky * rh)
+    Ez = at("Ez", -1j * kz / gamma ** 2 * rh)
+    # B = beta z x E: (Bx, By, Bz) = (-beta Ey, beta Ex, 0), at the B components' own positions
+    Bx = at("Bx", 1j * beta * ky * rh)
+    By = at("By", -1j * beta * kx * rh)
+    return [Ex, Ey, Ez], [Bx, By, np.zeros(shape)]
+
+
 def config(name, dtype=None, center_order=None, seed=None):
     """The named workloads (see the module docstring for the common recipe)."""
     if name == "thermal32":
@@ -156,6 +228,20 @@ def config(name, dtype=None, center_order=None, seed=None):
         E, B = laser_fields(shape, (1.0, 1.0, 1.0), a0, 16.0, waist, 30.0, 32.0)
         return Workload(name, shape, (1.0, 1.0, 1.0), 0.5, 3, center_order or corder, 16, dtype or "f32",
                         steps, el, ions_of(el), E, B)
+    if name in ("beam384", "beam96"):
+        # Beam-driven wake: 384x384x768 (beam96: the same setup scaled by 1/4 per axis, for tests),
+        # plasma 1 ppc cold everywhere at n0 = 2/256 (k_p sigma_z = sqrt 2 with sigma_z = 16), electron
+        # drive beam sigma_r = 8, sigma_z = 16, gamma = 1000, 8 ppc inside 3 sigma, centred at
+        # (192, 192, 576) (scaled); cubic shape, centering order 16, float32, 100 steps.
+        sc = 1 if name == "beam384" else 4
+        shape = (384 // sc, 384 // sc, 768 // sc)
+        n0, gamma, sr, sz = 2.0 / 256.0, 1000.0, 8.0 / sc, 16.0 / sc
+        center = (192.0 / sc, 192.0 / sc, 576.0 / sc)
+        rng = np.random.Generator(np.random.PCG64(1005 if seed is None else seed))
+        el, plasma = beam_plasma(rng, shape, n0, gamma, sr, sz, center)
+        E, B = beam_fields(shape, (1.0, 1.0, 1.0), n0, gamma, sr, sz, center)
+        return Workload(name, shape, (1.0, 1.0, 1.0), 0.5, 3, center_order or 16, 16, dtype or "f32", 100,
+                        el, ions_of(plasma), E, B)
     if name == "thermal256":
         # 256^3 periodic thermal plasma, 8 ppc, u_th = 0.05, CIC, centering order swept, 20 steps.
         shape, ppc, u_th, n0 = (256, 256, 256), 8, 0.05, 0.01

@@ -177,3 +177,77 @@ def test_laser64_gradient_against_central_differences():
         an32 = sum(float(np.sum(g * d)) for g, d in zip(grads["f32"], (dE, dB, du)))
         assert abs(an64 - fd[k]) <= 1e-5 * abs(fd[k]) + 1e-9, (k, an64, fd[k])
         assert abs(an32 - fd[k]) <= 5e-3 * abs(fd[k]) + 1e-6, (k, an32, fd[k])
+
+
+def test_beam384_fp32_one_step_sampled():
+    """The beam-driven configuration at full size (384x384x768, 113,246,208 plasma electrons plus the
+    926,488-particle beam, cubic, centering 16, FP32), one pic_step (caller's particle order), checked
+    on samples the oracle computes one by one: the staggered-to-nodal centering at 2,000 nodes per
+    component, gather + push of 4,000 particles (plasma and beam) from the GPU's nodal fields, and
+    the deposition's totals (charge and current, partition of unity)."""
+    from oracle import centering as ocent
+    from oracle import particles as opart
+    from oracle.transforms import B_NAMES, E_NAMES, OFFSETS
+    banner("beam384 full size, one step, sampled checks")
+    wl = inputs.config("beam384")
+    shape = wl.shape
+    ctx = piclib.Context.for_workload(wl, flags=piclib.PIC_KEEP_ORDER)
+    f = ctx.fields_from_workload(wl)
+    el = piclib.Species.from_host(wl.electrons, shape, "f32")
+    ions = piclib.Species.from_host(wl.ions, shape, "f32")
+    ctx.init_charge(f, el, ions)
+    del ions
+    q_ions = float(np.sum(wl.ions.w))
+    del wl
+    rng = np.random.default_rng(384)
+    nel, nplasma = el.n, int(np.prod(shape))  # the plasma (1 per cell) first, then the beam
+    pick = np.concatenate([rng.integers(0, nplasma, 2000), rng.integers(nplasma, nel, 2000)])
+    pos0 = el.positions(shape, (1.0, 1.0, 1.0))[pick]
+    u0 = np.stack([np64(x)[pick] for x in el.u], axis=1)
+    w = np64(el.w)[pick]
+    E0 = [t.cpu().numpy() for t in f.E_stag]
+    B0 = [t.cpu().numpy() for t in f.B_stag]
+    piclib.pic_step(ctx.ctx, f, [el], 1)
+    piclib.pic_sync(ctx.ctx)
+    m, dt = 8, 0.5  # centering order 16, c dt = 0.5
+    # 1. centering at sampled nodes (lines and planes through each sample)
+    for d in range(3):
+        Enod = f.E_nod[d].cpu().numpy()
+        for _ in range(2000 // 50):
+            i, j, k = (int(rng.integers(0, n)) for n in shape)
+            if d == 0:
+                ref = ocent.s2n_axis(E0[0][:, j, k].astype(np.float64), 0, m)[i]
+            elif d == 1:
+                ref = ocent.s2n_axis(E0[1][i, :, k].astype(np.float64), 0, m)[j]
+            else:
+                ref = ocent.s2n_axis(E0[2][i, j, :].astype(np.float64), 0, m)[k]
+            assert abs(float(Enod[i, j, k]) - ref) <= 1e-5 * np.max(np.abs(E0[d])) + 1e-12, ("E", d)
+        Bnod = f.B_nod[d].cpu().numpy()
+        for _ in range(2000 // 50):
+            i, j, k = (int(rng.integers(0, n)) for n in shape)
+            if d == 0:
+                ref = ocent.s2n_axis(ocent.s2n_axis(B0[0][i].astype(np.float64), 0, m), 1, m)[j, k]
+            elif d == 1:
+                ref = ocent.s2n_axis(ocent.s2n_axis(B0[1][:, j, :].astype(np.float64), 0, m), 1, m)[i, k]
+            else:
+                ref = ocent.s2n_axis(ocent.s2n_axis(B0[2][:, :, k].astype(np.float64), 0, m), 1, m)[i, j]
+            assert abs(float(Bnod[i, j, k]) - ref) <= 1e-5 * np.max(np.abs(B0[d])) + 1e-12, ("B", d)
+    # 2. gather + push of the sampled particles from the GPU's nodal fields
+    EB = opart.gather([t.cpu().numpy() for t in f.E_nod] + [t.cpu().numpy() for t in f.B_nod], pos0,
+                      (1.0, 1.0, 1.0), 3)
+    u1 = opart.boris(u0.T, EB[:3], EB[3:], -1.0, 1.0, dt)
+    v1 = u1 / opart.gamma(u1)
+    pos1 = opart.wrap(pos0 + dt * v1.T, shape)
+    g_u = np.stack([np64(x)[pick] for x in el.u], axis=1)
+    g_pos = el.positions(shape, (1.0, 1.0, 1.0))[pick]
+    assert np.max(np.abs(g_u - u1.T) / (np.abs(u1.T) + 1.0)) <= 2e-5
+    assert periodic_pos_err(g_pos, pos1, shape) <= 2e-5
+    # 3. deposition totals (partition of unity): charge and current
+    q_el = -float(torch.sum(el.w.double()))
+    rho_tot = float(torch.sum(f.rho_old.double()))
+    assert abs(rho_tot - (q_el + q_ions)) <= 1e-5 * abs(q_el)
+    uz = el.u[2].double()
+    gam = torch.sqrt(1 + el.u[0].double() ** 2 + el.u[1].double() ** 2 + uz ** 2)
+    jz = -float(torch.sum(el.w.double() * uz / gam))
+    assert abs(float(torch.sum(f.J_nod[2].double())) - jz) <= 1e-4 * abs(jz)
+    ctx.close()
