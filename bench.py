@@ -167,6 +167,9 @@ def main():
                          "60 steps, kinetic-energy loss, checkpoints every 10 steps)")
     ap.add_argument("--adjoint-config", default="laser64", choices=sorted(CONFIG_TEXT))
     ap.add_argument("--checkpoint-every", type=int, default=10)
+    ap.add_argument("--adjoint-steps", type=int, default=0, metavar="K",
+                    help="steps of the forward+backward run (default: the configuration's length)")
+    ap.add_argument("--adjoint-reps", type=int, default=3)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy a MIB-MiB float32 tensor 3 times (a plain copy kernel "
                          "of known size, the reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -204,7 +207,8 @@ def main():
                               "psatd_update_algo_bytes": upd, "psatd_update_GBps": round(upd / (ms * 1e-3) / 1e9, 1)}
     if not args.no_adjoint:
         print(f"[bench] forward+backward of {args.adjoint_config} ...", file=sys.stderr, flush=True)
-        result["fwd_bwd"] = time_fwd_bwd(args.adjoint_config, args.checkpoint_every)
+        result["fwd_bwd"] = time_fwd_bwd(args.adjoint_config, args.checkpoint_every, reps=args.adjoint_reps,
+                                         steps=args.adjoint_steps)
     if args.sweep_center_orders:
         for order in [int(x) for x in args.sweep_center_orders.split(",")]:
             wl.center_order = order
@@ -247,7 +251,7 @@ def time_field_solve(wl, flags, reps=20):
     return out
 
 
-def time_fwd_bwd(config_name, every, reps=3):
+def time_fwd_bwd(config_name, every, reps=3, steps=0):
     """Forward + backward of the differentiable workload: its full run (``steps`` of the config)
     through autograd.PicSteps with checkpoints every ``every`` steps, the loss being the total
     electron kinetic energy sum w (gamma - 1) at the end, gradients w.r.t. the initial E, B and
@@ -260,7 +264,7 @@ def time_fwd_bwd(config_name, every, reps=3):
     from paper_2106_12919_amd import lib as piclib
 
     wl = inputs.config(config_name)
-    K = wl.steps
+    K = steps if steps > 0 else wl.steps
 
     def setup(flags):
         ctx = piclib.Context.for_workload(wl, flags=flags)
