@@ -216,7 +216,10 @@ pic_status pic_gather_push(pic_ctx ctx, const pic_fields* f, pic_species* sp, in
  * B_nod, J_nod, J_stag, rho_new hold the intermediates of the last step.  E and
  * B stay in Fourier space between the steps of one call (7 forward transforms on
  * entry, then 4 forward and 6 inverse per step).  Particles of each species may
- * be reordered (all per-particle arrays together) to group them by grid tile. */
+ * be reordered (all per-particle arrays together) to group them by grid tile, unless
+ * PIC_KEEP_ORDER (or PIC_STAGGERED_CYCLE).  The flags of pic_init select the variants:
+ * PIC_SPECTRAL_CENTERING, PIC_NODAL_SOLVER, PIC_STAGGERED_CYCLE, v_gal (Galilean) and
+ * PIC_AVERAGED (the particles then see E_avg, B_avg), as documented with each flag. */
 pic_status pic_step(pic_ctx ctx, pic_fields* f, pic_species* sp, int nsp, int nsteps);
 
 /* Adjoints of one species' particle state (caller-owned device arrays of dtype, n each). */
