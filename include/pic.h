@@ -262,6 +262,13 @@ pic_status pic_sync(pic_ctx ctx);
  * (Sec. 2 item iii), out[1] = total charge sum(rho_old) dV. */
 pic_status pic_diagnostics(pic_ctx ctx, const pic_fields* f, double out[2]);
 
+/* Gauss's-law residual of the state (synchronous; FP64 accumulation): *out =
+ * || [k]_s . E_hat + i rho_hat / eps0 || / || rho_hat / eps0 || over all modes, in the paper's Fourier
+ * convention (App. A; Gauss's law is the constraint the PSATD update of Sec. 4.2 preserves), from
+ * E_stag and rho_old (|| . || alone when rho is zero).  With PIC_NODAL_SOLVER, [k]_c and the nodal
+ * E.  Uses the context's k-space scratch (not during another call on the same context). */
+pic_status pic_gauss_residual(pic_ctx ctx, const pic_fields* f, double* out);
+
 /* Per-stage timing with HIP events on the context stream.  When enabled, each
  * stage launch of pic_step is bracketed by events; pic_stage_times returns, for
  * stage s < nstage, the accumulated milliseconds and the number of launches since

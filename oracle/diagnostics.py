@@ -38,10 +38,16 @@ def total_charge(rho, spacing):
     return float(np.sum(rho) * spacing[0] * spacing[1] * spacing[2])
 
 
-def gauss_residual(E_stag, rho, spacing, psatd_order):
+def gauss_residual(E_stag, rho, spacing, psatd_order, nodal=False):
+    """Relative Gauss's-law residual of E on the Yee grid and rho on the nodes, in the paper's
+    Fourier convention (App. A).  ``nodal``: every field at the nodes and [k]_c (Sec. 4.1)."""
     shape = rho.shape
-    ks = psatd.staggered_wave_vector(shape, spacing, psatd_order)
-    Eh = [transforms.forward(E_stag[d], spacing, OFFSETS[E_NAMES[d]]) for d in range(3)]
+    if nodal:
+        ks = psatd.centered_wave_vector(shape, spacing, psatd_order)
+        Eh = [transforms.forward(E_stag[d], spacing, (0.0, 0.0, 0.0)) for d in range(3)]
+    else:
+        ks = psatd.staggered_wave_vector(shape, spacing, psatd_order)
+        Eh = [transforms.forward(E_stag[d], spacing, OFFSETS[E_NAMES[d]]) for d in range(3)]
     rh = transforms.forward(rho, spacing, OFFSETS["rho"])
     div = ks[0] * Eh[0] + ks[1] * Eh[1] + ks[2] * Eh[2]
     res = div + 1j * rh / EPS0

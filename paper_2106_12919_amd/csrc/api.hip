@@ -1138,6 +1138,25 @@ pic_status do_step_adjoint(pic_ctx c, pic_fields* f, const pic_species* sp, int 
 }
 
 template <typename T>
+pic_status do_gauss(pic_ctx c, const pic_fields* f, double* out) {
+  Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
+  const pic_params& p = c->p;
+  const T* src[4] = {static_cast<const T*>(f->E_stag[0]), static_cast<const T*>(f->E_stag[1]),
+                     static_cast<const T*>(f->E_stag[2]), static_cast<const T*>(f->rho_old)};
+  cplx<T>* dst[4] = {e.scratch[0], e.scratch[1], e.scratch[2], e.scratch[3]};
+  forward_batch<T>(c, e, src, dst, 4);
+  (void)hipMemsetAsync(c->d_acc, 0, 2 * sizeof(double), c->stream);
+  const cplx<T>* E[3] = {e.scratch[0], e.scratch[1], e.scratch[2]};
+  gauss_residual<T>(e.tab, E, e.scratch[3], p.nx, p.ny, e.fft.nzh, e.fft.pz, p.nz, c->d_acc, c->stream);
+  double h[2];
+  hipError_t he = hipMemcpyAsync(h, c->d_acc, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+  if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+  if (he != hipSuccess) return c->fail(PIC_EHIP, std::string("pic_gauss_residual: ") + hipGetErrorString(he));
+  out[0] = h[1] > 0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
+  return c->check("pic_gauss_residual");
+}
+
+template <typename T>
 pic_status do_diag(pic_ctx c, const pic_fields* f, double out[2]) {
   const pic_params& p = c->p;
   const size_t N = ncells(p);
@@ -1372,6 +1391,14 @@ pic_status pic_diagnostics(pic_ctx ctx, const pic_fields* f, double out[2]) {
   if (!out) return ctx->fail(PIC_EINVAL, "out is NULL");
   if ((st = check_fields(ctx, f, true, true, false, false, false, false, true, false)) != PIC_OK) return st;
   return PIC_DISPATCH(ctx, do_diag, f, out);
+}
+
+pic_status pic_gauss_residual(pic_ctx ctx, const pic_fields* f, double* out) {
+  pic_status st = device_ok(ctx);
+  if (st != PIC_OK) return st;
+  if (!out) return ctx->fail(PIC_EINVAL, "out is NULL");
+  if ((st = check_fields(ctx, f, true, false, false, false, false, false, true, false)) != PIC_OK) return st;
+  return PIC_DISPATCH(ctx, do_gauss, f, out);
 }
 
 pic_status pic_profile(pic_ctx ctx, int enable) {

@@ -200,5 +200,10 @@ template <typename T>
 void sum_plain(const T* arr, int64_t n, double* acc, hipStream_t s);
 template <typename T>
 void add_into(T* dst, const T* src, int64_t n, hipStream_t s);
+// acc[0] += sum |sum_d D-_d E_d - rho|^2, acc[1] += sum |rho|^2 over the half-spectrum modes
+// (index-space spectra of the Yee components E and of rho), weighted as full-spectrum sums.
+template <typename T>
+void gauss_residual(const PsatdTables<T>& t, const cplx<T>* const E[3], const cplx<T>* rho, int nx, int ny, int nzh,
+                    int pz, int nz, double* acc, hipStream_t s);
 
 }  // namespace pic

@@ -80,6 +80,7 @@ def load():
                                      POINTER(pic_fields), POINTER(pic_species_adjoint)]),
         "pic_sync": (c_int, [c_void_p]),
         "pic_diagnostics": (c_int, [c_void_p, POINTER(pic_fields), POINTER(c_double)]),
+        "pic_gauss_residual": (c_int, [c_void_p, POINTER(pic_fields), POINTER(c_double)]),
         "pic_profile": (c_int, [c_void_p, c_int]),
         "pic_stage_times": (c_int, [c_void_p, POINTER(c_double), POINTER(c_int64), c_int]),
         "pic_stage_name": (c_char_p, [c_int]),
@@ -184,6 +185,12 @@ def pic_diagnostics(ctx, fields):
     out = (c_double * 2)()
     _check(load().pic_diagnostics(ctx, ctypes.byref(fields.struct()), out), ctx)
     return float(out[0]), float(out[1])
+
+
+def pic_gauss_residual(ctx, fields):
+    out = c_double()
+    _check(load().pic_gauss_residual(ctx, ctypes.byref(fields.struct()), ctypes.byref(out)), ctx)
+    return float(out.value)
 
 
 def pic_profile(ctx, enable=True):

@@ -111,3 +111,55 @@ def test_nodal_vacuum_plane_wave_dispersion(order):
     for d in range(3):
         np.testing.assert_allclose(E[d], Eref[d], atol=1e-12)
         np.testing.assert_allclose(B[d], Bref[d], atol=1e-12)
+
+
+def _yee_divergence(E, spacing, order):
+    """Real-space divergence at the nodes of Yee-grid E (E_d at +1/2 cell along d), with the
+    textbook staggered stencils: order 2 (f(x+h/2) - f(x-h/2)) / h; order 4 adds the
+    (9/8, -1/24) pair over +-h/2 and +-3h/2."""
+    coef = {2: [(1.0, 0)], 4: [(9.0 / 8.0, 0), (-1.0 / 24.0, 1)]}[order]
+    out = np.zeros(E[0].shape)
+    for d in range(3):
+        for c, s in coef:  # f(x + (s + 1/2) h) is E_d[i + s]; f(x - (s + 1/2) h) is E_d[i - s - 1]
+            out += c * (np.roll(E[d], -s, axis=d) - np.roll(E[d], s + 1, axis=d)) / spacing[d]
+    return out
+
+
+def _centered_divergence(E, spacing):
+    """Order-2 centered divergence at the nodes of nodal E: (f(x+h) - f(x-h)) / (2h)."""
+    return sum((np.roll(E[d], -1, axis=d) - np.roll(E[d], 1, axis=d)) / (2 * spacing[d]) for d in range(3))
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_gauss_residual_equals_real_space_yee_divergence_error(order):
+    """Parseval: the spectral residual with the order-2m [k]_s is the real-space L2 error of the
+    staggered finite-difference Gauss law (App. A convention, derivative <-> i k)."""
+    rng = np.random.default_rng(41)
+    shape, spacing = (8, 10, 6), (0.7, 1.1, 0.9)
+    E = [rng.standard_normal(shape) for _ in range(3)]
+    rho = rng.standard_normal(shape)
+    ref = np.linalg.norm(_yee_divergence(E, spacing, order) - rho) / np.linalg.norm(rho)
+    assert diagnostics.gauss_residual(E, rho, spacing, order) == pytest.approx(ref, rel=1e-12)
+    # a field built to satisfy the stencil's Gauss law exactly: rho := its divergence
+    rho2 = _yee_divergence(E, spacing, order)
+    assert diagnostics.gauss_residual(E, rho2, spacing, order) < 1e-13
+
+
+def test_gauss_residual_nodal_equals_centered_divergence_error():
+    rng = np.random.default_rng(42)
+    shape, spacing = (8, 10, 6), (0.7, 1.1, 0.9)
+    E = [rng.standard_normal(shape) for _ in range(3)]
+    rho = rng.standard_normal(shape)
+    ref = np.linalg.norm(_centered_divergence(E, spacing) - rho) / np.linalg.norm(rho)
+    assert diagnostics.gauss_residual(E, rho, spacing, 2, nodal=True) == pytest.approx(ref, rel=1e-12)
+
+
+def test_gauss_residual_special_cases():
+    rng = np.random.default_rng(43)
+    shape, spacing = (6, 6, 8), (1.0, 1.0, 1.0)
+    rho = rng.standard_normal(shape)
+    zero = [np.zeros(shape)] * 3
+    assert diagnostics.gauss_residual(zero, rho, spacing, 8) == pytest.approx(1.0, rel=1e-14)
+    # a uniform field has zero divergence at any order: the residual is again ||rho|| / ||rho||
+    const = [np.full(shape, 0.3), np.full(shape, -1.2), np.full(shape, 2.0)]
+    assert diagnostics.gauss_residual(const, rho, spacing, 0) == pytest.approx(1.0, rel=1e-12)
