@@ -248,6 +248,34 @@ struct FieldSlots<double> {
   }
 };
 
+// The box of the hybrid gather: for float two planes, (E_x, E_y, E_z, B_x) as one float4 per
+// node (16-byte stride) followed by (B_y, B_z) as one float2 per node (8-byte stride).  Lanes
+// reading 16 bytes each are served eight at a time; at a 16-byte node stride those eight
+// spread over every bank group, where the 32-byte stride of FieldSlots<float> reaches only
+// half of them.  Double keeps FieldSlots<double> (48-byte stride, already spread).
+template <typename T, int B3>
+struct GatherBox {
+  static constexpr int SLOTS = FieldSlots<T>::FS;
+  __device__ static inline void store(T* box, int e, const T* v) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) box[e * SLOTS + c] = v[c];
+  }
+  __device__ static inline void read(const T* box, int e, T* v) { FieldSlots<T>::read(box + (size_t)e * SLOTS, v); }
+};
+template <int B3>
+struct GatherBox<float, B3> {
+  static constexpr int SLOTS = 6;
+  __device__ static inline void store(float* box, int e, const float* v) {
+    reinterpret_cast<float4*>(box)[e] = make_float4(v[0], v[1], v[2], v[3]);
+    reinterpret_cast<float2*>(box + 4 * B3)[e] = make_float2(v[4], v[5]);
+  }
+  __device__ static inline void read(const float* box, int e, float* v) {
+    const float4 a = reinterpret_cast<const float4*>(box)[e];
+    const float2 b = reinterpret_cast<const float2*>(box + 4 * B3)[e];
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y;
+  }
+};
+
 // Periodic index of x in [-n, 3n).
 __device__ inline int wrap3(int x, int n) {
   x += (x < 0) ? n : 0;
@@ -255,9 +283,10 @@ __device__ inline int wrap3(int x, int n) {
   return (x >= n) ? x - n : x;
 }
 
-// Stages the six nodal components over the box of tile (t0x, t0y, t0z).  Each thread
-// issues the loads of all its nodes before storing any, so they are in flight together.
-template <typename T, int ORDER>
+// Stages the six nodal components over the box of tile (t0x, t0y, t0z), in the
+// FieldSlots layout or (GATHER) the GatherBox one.  Each thread issues the loads of all its
+// nodes before storing any, so they are in flight together.
+template <typename T, int ORDER, bool GATHER = false>
 __device__ inline void load_field_box(T* box, const Batch<const T*>& F, const GridGeom& g, int t0x, int t0y, int t0z) {
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
@@ -277,8 +306,12 @@ __device__ inline void load_field_box(T* box, const Batch<const T*>& F, const Gr
   for (int u = 0; u < PER; ++u) {
     const int e = (int)threadIdx.x + u * PIC_GATHER_BLOCK;
     if (e < X::B3) {
+      if (GATHER) {
+        GatherBox<T, X::B3>::store(box, e, v[u]);
+      } else {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) box[e * FS + c] = v[u][c];
+        for (int c = 0; c < 6; ++c) box[e * FS + c] = v[u][c];
+      }
     }
   }
 }
@@ -312,8 +345,8 @@ __device__ inline void boris(const T* f, T qdt2m, T& ux, T& uy, T& uz, BorisStat
   uz = b.umz + (b.upx * b.sy - b.upy * b.sx) + qdt2m * f[2];
 }
 
-// Gather at one particle from the LDS box (first support node at box index l*) or,
-// outside the margin, from the grid; then the relativistic Boris push and the move.
+// Gather at one particle from the LDS box (GatherBox layout; first support node at box
+// index l*) or, outside the margin, from the grid; then the relativistic Boris push and the move.
 template <typename T, int ORDER>
 __device__ inline void gather_push_one(const T* box, const Batch<const T*>& F, const GridGeom& g, int lx, int ly,
                                        int lz, int& i, int& j, int& k, T& ox, T& oy, T& oz, T& ux, T& uy, T& uz,
@@ -321,14 +354,13 @@ __device__ inline void gather_push_one(const T* box, const Batch<const T*>& F, c
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
   constexpr int NW = S::NW;
-  constexpr int FS = FieldSlots<T>::FS;
   T wx[NW], wy[NW], wz[NW];
   S::weights(ox, wx);
   S::weights(oy, wy);
   S::weights(oz, wz);
   T f[6] = {0, 0, 0, 0, 0, 0};
   if (lx >= 0 && ly >= 0 && lz >= 0) {
-    const T* p0 = box + (size_t)X::at(lx, ly, lz) * FS;
+    const int n0 = X::at(lx, ly, lz);
 #pragma unroll
     for (int a = 0; a < NW; ++a) {
 #pragma unroll
@@ -338,7 +370,7 @@ __device__ inline void gather_push_one(const T* box, const Batch<const T*>& F, c
         for (int cc = 0; cc < NW; ++cc) {
           const T w = wab * wz[cc];
           T v[6];
-          FieldSlots<T>::read(p0 + (a * X::B2 + b * X::B + cc) * FS, v);
+          GatherBox<T, X::B3>::read(box, n0 + a * X::B2 + b * X::B + cc, v);
 #pragma unroll
           for (int m = 0; m < 6; ++m) f[m] += w * v[m];
         }
@@ -403,7 +435,7 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_perm(GridGeom 
   int tx, ty, tz;
   tile_coords(tile, tg, tx, ty, tz);
   const int t0x = tx * kTile, t0y = ty * kTile, t0z = tz * kTile;
-  load_field_box<T, ORDER>(box, F, g, t0x, t0y, t0z);
+  load_field_box<T, ORDER, true>(box, F, g, t0x, t0y, t0z);
   __syncthreads();
   for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
     const int p = perm[qq];
@@ -460,7 +492,7 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
     cnt[threadIdx.x] = 0;
     if (nbr_bases) base[threadIdx.x] = nbr_bases[27 * tile + threadIdx.x];
   }
-  load_field_box<T, ORDER>(box, F, g, t0x, t0y, t0z);
+  load_field_box<T, ORDER, true>(box, F, g, t0x, t0y, t0z);
   __syncthreads();
   if (!nbr_bases) {
     // pass 1: particles per neighbour tile of the new grouping (the home tile, the
@@ -486,12 +518,13 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
     __syncthreads();
   }
   // pass 2: gather, push and write each particle to its slot, the next particle's
-  // loads in flight meanwhile
+  // loads in flight meanwhile.  They are issued after the slot is reserved: the rare
+  // global reservation returns into the slot's register, and the wait for it would
+  // otherwise also wait for the prefetch.
   Raw<T> nxt;
   if (beg + (int)threadIdx.x < end) load_raw<T, true>(in, beg + threadIdx.x, nxt);
   for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
     const Raw<T> r = nxt;
-    load_raw<T, true>(in, min(qq + (int)blockDim.x, end - 1), nxt);
     int i, j, k;
     (void)decode_cell(r.cell, g, nullptr, i, j, k);
     const int nb = neighbour_of_cell(i, j, k, tx, ty, tz, tg);
@@ -507,6 +540,7 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
     } else {
       slot = nb >= 0 ? base[nb] + atomicAdd(&cnt[nb], 1) : atomicAdd(&cursor[tile_of(i, j, k, tg)], 1);
     }
+    load_raw<T, true>(in, min(qq + (int)blockDim.x, end - 1), nxt);
     T ox = r.o[0], oy = r.o[1], oz = r.o[2];
     T ux = r.u[0], uy = r.u[1], uz = r.u[2];
     const int lx = box_index(i, t0x, g.nx), ly = box_index(j, t0y, g.ny), lz = box_index(k, t0z, g.nz);
@@ -1916,7 +1950,7 @@ void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3]
   const T qdt2m = (T)(in.q * g.dt / (2.0 * in.m));
   const T dtx = (T)(g.dt / g.dx), dty = (T)(g.dt / g.dy), dtz = (T)(g.dt / g.dz);
   const int Bx = deposit_box(g.shape_order);
-  const size_t lds = (size_t)Bx * Bx * Bx * FieldSlots<T>::FS * sizeof(T);
+  const size_t lds = (size_t)Bx * Bx * Bx * GatherBox<T, 1>::SLOTS * sizeof(T);
   const dim3 grid(t.ntiles + 1), block(PIC_GATHER_BLOCK);
   if (home_cursor) {
     if (g.shape_order == 1) {
