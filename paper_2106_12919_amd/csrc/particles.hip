@@ -1219,10 +1219,10 @@ __device__ inline void stencil_sums(const GridGeom& g, int i, int j, int k, T ox
   }
 }
 
-// The same sums from an LDS box holding FS slots per node (components C0.. of the node
-// adjacent); ``at`` is the box index of the first support node.
-template <typename T, int ORDER, int NV, int FS, int C0>
-__device__ inline void box_stencil_sums(const T* box, int at, T ox, T oy, T oz, T* val, T (*grad)[3]) {
+// The same sums from an LDS box; ``rd(n, v)`` reads the NV values of box node n and ``at``
+// is the box index of the first support node.
+template <typename T, int ORDER, int NV, typename RD>
+__device__ inline void box_stencil_sums(RD rd, int at, T ox, T oy, T oz, T* val, T (*grad)[3]) {
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
   constexpr int NW = S::NW;
@@ -1238,7 +1238,6 @@ __device__ inline void box_stencil_sums(const T* box, int at, T ox, T oy, T oz, 
     val[v] = 0;
     grad[v][0] = grad[v][1] = grad[v][2] = 0;
   }
-  const T* b0 = box + (size_t)at * FS + C0;
 #pragma unroll
   for (int a = 0; a < NW; ++a) {
 #pragma unroll
@@ -1247,18 +1246,28 @@ __device__ inline void box_stencil_sums(const T* box, int at, T ox, T oy, T oz, 
 #pragma unroll
       for (int c = 0; c < NW; ++c) {
         const T w = wab * wz[c], dx = gxab * wz[c], dy = gyab * wz[c], dz = wab * gz[c];
-        const T* nd = b0 + (a * X::B2 + b * X::B + c) * FS;
+        T x[NV];
+        rd(at + a * X::B2 + b * X::B + c, x);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          const T x = nd[v];
-          val[v] += w * x;
-          grad[v][0] += dx * x;
-          grad[v][1] += dy * x;
-          grad[v][2] += dz * x;
+          val[v] += w * x[v];
+          grad[v][0] += dx * x[v];
+          grad[v][1] += dy * x[v];
+          grad[v][2] += dz * x[v];
         }
       }
     }
   }
+}
+
+// The three adjoint current components of box node n from 4-slot nodes (16 bytes for float).
+__device__ inline void read_lj(const float* p, int n, float* v) {
+  const float4 a = reinterpret_cast<const float4*>(p)[n];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z;
+}
+__device__ inline void read_lj(const double* p, int n, double* v) {
+  const double2 a = reinterpret_cast<const double2*>(p)[2 * n];
+  v[0] = a.x; v[1] = a.y; v[2] = p[4 * n + 2];
 }
 
 // Reverse mode of gather + Boris push + move + deposition of particle p at time n (cell
@@ -1387,8 +1396,9 @@ __global__ void __launch_bounds__(256) k_particle_adjoint(GridGeom g, SpeciesVie
 }
 
 // One block per tile of the grouping of the particles' cells at n (slots [starts[t],
-// starts[t+1]) through perm): E, B (FieldSlots layout) and the adjoint sources rho, J
-// (4 slots per node) staged over the tile's box in LDS.  x^n, x^{n+1} and x^{n+1/2} lie
+// starts[t+1]) through perm): the adjoint currents (4 slots per node), E, B (GatherBox
+// layout) and the adjoint charge (a plane of its own) staged over the tile's box in LDS, in
+// that order, so that every plane starts aligned to its widest read.  x^n, x^{n+1} and x^{n+1/2} lie
 // within one cell of the tile, inside the box; anything outside is read from the grids.
 // Block ntiles passes the particles with invalid cells through.
 template <typename T, int ORDER>
@@ -1398,10 +1408,11 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_particle_adjoint_tiled(
     T dty, T dtz, int mobile) {
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
-  constexpr int FS = FieldSlots<T>::FS;
+  using GB = GatherBox<T, X::B3>;
   extern __shared__ __align__(16) unsigned char smem[];
-  T* fbox = reinterpret_cast<T*>(smem);
-  T* lbox = fbox + (size_t)X::B3 * FS;
+  T* ljbox = reinterpret_cast<T*>(smem);
+  T* fbox = ljbox + (size_t)X::B3 * 4;
+  T* lrbox = fbox + (size_t)X::B3 * GB::SLOTS;
   const int tile = xcd_major(blockIdx.x, gridDim.x);
   const int beg = starts[tile], end = starts[tile + 1];
   if (beg == end) return;
@@ -1416,7 +1427,7 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_particle_adjoint_tiled(
   int tx, ty, tz;
   tile_coords(tile, tg, tx, ty, tz);
   const int t0x = tx * kTile, t0y = ty * kTile, t0z = tz * kTile;
-  if (mobile) load_field_box<T, ORDER>(fbox, F, g, t0x, t0y, t0z);
+  if (mobile) load_field_box<T, ORDER, true>(fbox, F, g, t0x, t0y, t0z);
   {
     constexpr int PER = (X::B3 + PIC_GATHER_BLOCK - 1) / PIC_GATHER_BLOCK;
     const int ox0 = t0x - 1 + S::BASE, oy0 = t0y - 1 + S::BASE, oz0 = t0z - 1 + S::BASE;
@@ -1433,8 +1444,9 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_particle_adjoint_tiled(
     for (int u = 0; u < PER; ++u) {
       const int e = (int)threadIdx.x + u * PIC_GATHER_BLOCK;
       if (e < X::B3) {
+        lrbox[e] = v[u][0];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) lbox[e * 4 + c] = v[u][c];
+        for (int c = 0; c < 3; ++c) ljbox[e * 4 + c] = v[u][1 + c];
       }
     }
   }
@@ -1446,17 +1458,17 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_particle_adjoint_tiled(
   };
   auto sF = [&](int a, int b, int c, T x, T y, T z, T* val, T (*grad)[3]) {
     const int at = at_of(a, b, c);
-    if (at >= 0) box_stencil_sums<T, ORDER, 6, FS, 0>(fbox, at, x, y, z, val, grad);
+    if (at >= 0) box_stencil_sums<T, ORDER, 6>([&](int n, T* v) { GB::read(fbox, n, v); }, at, x, y, z, val, grad);
     else stencil_sums<T, ORDER, 6>(g, a, b, c, x, y, z, F.p, val, grad);
   };
   auto sRho = [&](int a, int b, int c, T x, T y, T z, T* val, T (*grad)[3]) {
     const int at = at_of(a, b, c);
-    if (at >= 0) box_stencil_sums<T, ORDER, 1, 4, 0>(lbox, at, x, y, z, val, grad);
+    if (at >= 0) box_stencil_sums<T, ORDER, 1>([&](int n, T* v) { v[0] = lrbox[n]; }, at, x, y, z, val, grad);
     else stencil_sums<T, ORDER, 1>(g, a, b, c, x, y, z, L.p, val, grad);
   };
   auto sJ = [&](int a, int b, int c, T x, T y, T z, T* val, T (*grad)[3]) {
     const int at = at_of(a, b, c);
-    if (at >= 0) box_stencil_sums<T, ORDER, 3, 4, 1>(lbox, at, x, y, z, val, grad);
+    if (at >= 0) box_stencil_sums<T, ORDER, 3>([&](int n, T* v) { read_lj(ljbox, n, v); }, at, x, y, z, val, grad);
     else stencil_sums<T, ORDER, 3>(g, a, b, c, x, y, z, LJ, val, grad);
   };
   for (int q = beg + threadIdx.x; q < end; q += blockDim.x) {
@@ -2068,7 +2080,7 @@ void particle_adjoint(const GridGeom& g, const TileGeom& t, const SpeciesView<T>
   const int mob = mobile ? 1 : 0;
   // LDS-staged boxes (E, B and the 4 adjoint sources) when they fit a workgroup's LDS
   const int Bx = deposit_box(g.shape_order);
-  const size_t lds = (size_t)Bx * Bx * Bx * (FieldSlots<T>::FS + 4) * sizeof(T);
+  const size_t lds = (size_t)Bx * Bx * Bx * (4 + GatherBox<T, 1>::SLOTS + 1) * sizeof(T);
   if (starts && lds <= 160 * 1024) {
     const dim3 grid((unsigned)t.ntiles + 1);
     if (g.shape_order == 1) {
