@@ -680,6 +680,46 @@ __device__ inline void scatter_lds(typename Fixed<T>::acc_t* box, int at, T ox, 
   }
 }
 
+// The current of one particle into a float box whose J^x, J^y share one 64-bit word per
+// node, J^y 2^32 + J^x in two's complement, followed by a J^z plane: one 64-bit LDS atomic
+// stands for two 32-bit ones.  The rounding adds leave K + n in each half (K = 0x4B400000,
+// |n| <= 2^22), so subtracting K 2^32 + K gives n_y 2^32 + n_x exactly, and since integer
+// addition is exact the word sums to (sum n_y) 2^32 + sum n_x, from which both sums (each
+// below 2^31 by the choice of scale) come back exactly (unpack_xy).
+template <int ORDER>
+__device__ inline void scatter_lds_packed_j(int* box, int at, float ox, float oy, float oz, const float* sv) {
+  using S = Shape<float, ORDER>;
+  using X = Box<S::NW>;
+  constexpr int NW = S::NW;
+  constexpr unsigned long long kBias = 0x4B4000004B400000ull;
+  float wx[NW], wy[NW], wz[NW];
+  S::weights(ox, wx);
+  S::weights(oy, wy);
+  S::weights(oz, wz);
+  unsigned long long* xy = reinterpret_cast<unsigned long long*>(box) + at;
+  int* z = box + 2 * X::B3 + at;
+#pragma unroll
+  for (int a = 0; a < NW; ++a) {
+#pragma unroll
+    for (int b = 0; b < NW; ++b) {
+      const float wab = wx[a] * wy[b];
+      const float xab = sv[0] * wab, yab = sv[1] * wab, zab = sv[2] * wab;
+#pragma unroll
+      for (int cc = 0; cc < NW; ++cc) {
+        const int rel = a * X::B2 + b * X::B + cc;
+        const unsigned lo = __float_as_uint(fmaf(xab, wz[cc], 12582912.0f));
+        const unsigned hi = __float_as_uint(fmaf(yab, wz[cc], 12582912.0f));
+        atomicAdd(xy + rel, (((unsigned long long)hi << 32) | lo) - kBias);
+        atomicAdd(z + rel, Fixed<float>::fma_round(zab, wz[cc]));
+      }
+    }
+  }
+}
+__device__ inline void unpack_xy(unsigned long long w, int& x, int& y) {
+  x = (int)(unsigned)w;
+  y = (int)((long long)(w - (unsigned long long)(long long)x) >> 32);
+}
+
 // Order of the particles inside a deposition chunk.  LDS atomics of a wave retire
 // without bank conflicts when the 32 lanes of each half wave address distinct words
 // modulo 32 (4-byte accumulators), or the 16 lanes of each quarter wave distinct
@@ -815,6 +855,9 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
   using O = DepositOrder<T>;
   constexpr int ncomp = WJ ? 4 : 1;
   constexpr int kWaves = DepositLds<T>::kWaves;
+  // Box planes: FP32 with J, (J^x, J^y) packed 64-bit words, J^z, then rho; otherwise rho, J^x, J^y, J^z.
+  constexpr bool PACK = WJ && sizeof(T) == 4;
+  typename Fixed<T>::acc_t* rbox = PACK ? box + 3 * X::B3 : box;
   T* red = L.red;
   T* redm = L.redm;
   int* shs = L.shs;
@@ -983,7 +1026,7 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
       const T qw = qdv * r.w;
       if (d.at_rho >= 0) {
         const T sv[1] = {ldexp(qw, sh[0])};
-        scatter_lds<T, ORDER, 1>(box, d.at_rho, d.ox, d.oy, d.oz, sv);
+        scatter_lds<T, ORDER, 1>(rbox, d.at_rho, d.ox, d.oy, d.oz, sv);
       } else {
         T* dst[1] = {out.p[0]};
         const T val[1] = {qw};
@@ -992,7 +1035,10 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
       if (WJ) {
         if (d.at_j >= 0) {
           const T sv[3] = {ldexp(qw * d.vx, sh[1]), ldexp(qw * d.vy, sh[2]), ldexp(qw * d.vz, sh[3])};
-          scatter_lds<T, ORDER, 3>(box + X::B3, d.at_j, d.hx, d.hy, d.hz, sv);
+          if constexpr (PACK)
+            scatter_lds_packed_j<ORDER>(box, d.at_j, d.hx, d.hy, d.hz, sv);
+          else
+            scatter_lds<T, ORDER, 3>(box + X::B3, d.at_j, d.hx, d.hy, d.hz, sv);
         } else {
           T* dst[3] = {out.p[1], out.p[2], out.p[3]};
           const T val[3] = {qw * d.vx, qw * d.vy, qw * d.vz};
@@ -1009,7 +1055,19 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
   }
   // the whole box goes to this tile's staging slot (plain stores, zeros included)
   T* dstage = stage + (size_t)tile * ncomp * X::B3;
-  for (int k = threadIdx.x; k < ncomp * X::B3; k += blockDim.x) dstage[k] = ldexp((T)box[k], -shs[k / X::B3]);
+  if constexpr (PACK) {
+    const unsigned long long* xy = reinterpret_cast<const unsigned long long*>(box);
+    for (int e = threadIdx.x; e < X::B3; e += blockDim.x) {
+      int jx, jy;
+      unpack_xy(xy[e], jx, jy);
+      dstage[e] = ldexp((T)rbox[e], -shs[0]);
+      dstage[X::B3 + e] = ldexp((T)jx, -shs[1]);
+      dstage[2 * X::B3 + e] = ldexp((T)jy, -shs[2]);
+      dstage[3 * X::B3 + e] = ldexp((T)box[2 * X::B3 + e], -shs[3]);
+    }
+  } else {
+    for (int k = threadIdx.x; k < ncomp * X::B3; k += blockDim.x) dstage[k] = ldexp((T)box[k], -shs[k / X::B3]);
+  }
 }
 
 // Waves per SIMD the register budget allows: FP32 cubic 3 (its LDS box admits three
