@@ -715,6 +715,40 @@ __device__ inline void scatter_lds_packed_j(int* box, int at, float ox, float oy
     }
   }
 }
+// NP pairs of values (sv[2 q], sv[2 q + 1]) into NP planes of packed 64-bit words, as
+// scatter_lds_packed_j does for (J^x, J^y).
+template <int ORDER, int NP>
+__device__ inline void scatter_lds_pairs(int* box, int at, float ox, float oy, float oz, const float* sv) {
+  using S = Shape<float, ORDER>;
+  using X = Box<S::NW>;
+  constexpr int NW = S::NW;
+  constexpr unsigned long long kBias = 0x4B4000004B400000ull;
+  float wx[NW], wy[NW], wz[NW];
+  S::weights(ox, wx);
+  S::weights(oy, wy);
+  S::weights(oz, wz);
+  unsigned long long* w0 = reinterpret_cast<unsigned long long*>(box) + at;
+#pragma unroll
+  for (int a = 0; a < NW; ++a) {
+#pragma unroll
+    for (int b = 0; b < NW; ++b) {
+      const float wab = wx[a] * wy[b];
+      float xab[2 * NP];
+#pragma unroll
+      for (int v = 0; v < 2 * NP; ++v) xab[v] = sv[v] * wab;
+#pragma unroll
+      for (int cc = 0; cc < NW; ++cc) {
+        const int rel = a * X::B2 + b * X::B + cc;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const unsigned lo = __float_as_uint(fmaf(xab[2 * q], wz[cc], 12582912.0f));
+          const unsigned hi = __float_as_uint(fmaf(xab[2 * q + 1], wz[cc], 12582912.0f));
+          atomicAdd(w0 + q * X::B3 + rel, (((unsigned long long)hi << 32) | lo) - kBias);
+        }
+      }
+    }
+  }
+}
 __device__ inline void unpack_xy(unsigned long long w, int& x, int& y) {
   x = (int)(unsigned)w;
   y = (int)((long long)(w - (unsigned long long)(long long)x) >> 32);
@@ -1543,7 +1577,8 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_particle_adjoint_tiled(
 // max of |val_v|, as in the deposition) and stored to the tile's staging slot for
 // k_deposit_reduce*; a particle outside the box margin goes to the grids with atomics.
 // The particles of each chunk are dealt over the residues of their first support node, as
-// in the deposition, so that the lanes of a wave hit distinct LDS banks.
+// in the deposition, so that the lanes of a wave hit distinct LDS banks.  FP32 packs the
+// components pairwise into 64-bit words (scatter_lds_pairs).
 template <typename T, int ORDER>
 __global__ void __launch_bounds__(256) k_scatter_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp,
                                                        const int* __restrict__ perm, const int* __restrict__ starts,
@@ -1668,7 +1703,10 @@ __global__ void __launch_bounds__(256) k_scatter_tiled(GridGeom g, TileGeom tg, 
         T sv[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) sv[v] = ldexp(x[v], sh[v]);
-        scatter_lds<T, ORDER, NV>(box, at, ox, oy, oz, sv);
+        if constexpr (sizeof(T) == 4)
+          scatter_lds_pairs<ORDER, NV / 2>(box, at, ox, oy, oz, sv);
+        else
+          scatter_lds<T, ORDER, NV>(box, at, ox, oy, oz, sv);
       } else {
         scatter<T, ORDER>(g, i, j, k, ox, oy, oz, out.p, x, NV);
       }
@@ -1676,7 +1714,18 @@ __global__ void __launch_bounds__(256) k_scatter_tiled(GridGeom g, TileGeom tg, 
     __syncthreads();
   }
   T* dstage = stage + (size_t)tile * NV * X::B3;
-  for (int e = threadIdx.x; e < NV * X::B3; e += blockDim.x) dstage[e] = ldexp((T)box[e], -shs[e / X::B3]);
+  if constexpr (sizeof(T) == 4) {
+    const unsigned long long* w = reinterpret_cast<const unsigned long long*>(box);
+    for (int e = threadIdx.x; e < (NV / 2) * X::B3; e += blockDim.x) {
+      const int q = e / X::B3, n = e - q * X::B3;
+      int lo, hi;
+      unpack_xy(w[e], lo, hi);
+      dstage[2 * q * X::B3 + n] = ldexp((T)lo, -shs[2 * q]);
+      dstage[(2 * q + 1) * X::B3 + n] = ldexp((T)hi, -shs[2 * q + 1]);
+    }
+  } else {
+    for (int e = threadIdx.x; e < NV * X::B3; e += blockDim.x) dstage[e] = ldexp((T)box[e], -shs[e / X::B3]);
+  }
 }
 
 // ---------------------------------------------------------------- fully staggered comparison cycle
