@@ -138,6 +138,11 @@ struct Engine : EngineBase {
   int* work = nullptr;      // tile counter of the persistent deposition
   T* stage = nullptr;       // per-tile deposition boxes, ntiles * 4 * deposit_box^3
   T* astage = nullptr;      // per-tile boxes of the reverse mode's scatter, ntiles * 6 * deposit_box^3 (on first use)
+  // rho, J of particles past their tile's box (zero between depositions), the two flags that
+  // say whether a deposition spilled, and the count of depositions that chose between them
+  T* spill[4] = {nullptr, nullptr, nullptr, nullptr};
+  int* spill_flag = nullptr;
+  unsigned dep_k = 0;
   std::vector<SpeciesScratch<T>> sps;
   cplx<T>* Eh[3] = {nullptr, nullptr, nullptr};
   cplx<T>* Bh[3] = {nullptr, nullptr, nullptr};
@@ -337,6 +342,12 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
       if ((err = hipMemset(e.Ah[q], 0, ns * sizeof(cplx<T>))) != hipSuccess) return err;
     }
   if ((err = e.alloc(&e.tmp, (size_t)p.nx * p.ny * p.nz)) != hipSuccess) return err;
+  for (int q = 0; q < 4; ++q) {
+    if ((err = e.alloc(&e.spill[q], (size_t)p.nx * p.ny * p.nz)) != hipSuccess) return err;
+    if ((err = hipMemset(e.spill[q], 0, (size_t)p.nx * p.ny * p.nz * sizeof(T))) != hipSuccess) return err;
+  }
+  if ((err = e.alloc(&e.spill_flag, 2)) != hipSuccess) return err;
+  if ((err = hipMemset(e.spill_flag, 0, 2 * sizeof(int))) != hipSuccess) return err;
   // deposition tiles of kTile^3 = 8^3 cells: the LDS box of 4 components is at most
   // 4 * 13^3 * 8 B = 70 KiB (FP64, cubic); the gather box 13^3 nodes * 6 components
   const GridGeom g = make_geom(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order);
@@ -514,16 +525,49 @@ pic_status do_center(pic_ctx c, int dir, int what, pic_fields* f) {
   return c->check("pic_center");
 }
 
+// The sum of the species' sources without a separate clear: the first species deposited
+// overwrites rho_new (starting from rho_static) and, if mobile, J_nod; later ones add.  Each
+// deposition sends particles past its tile boxes to the engine's spill arrays, which the
+// reduction folds in when that deposition's flag is set.
 template <typename T>
-void zero_sources(pic_ctx c, pic_fields* f, bool with_j) {
-  const size_t N = ncells(c->p);
-  if (f->rho_static)
-    (void)hipMemcpyAsync(f->rho_new, f->rho_static, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
-  else
-    (void)hipMemsetAsync(f->rho_new, 0, N * sizeof(T), c->stream);
-  if (with_j)
-    for (int d = 0; d < 3; ++d) (void)hipMemsetAsync(f->J_nod[d], 0, N * sizeof(T), c->stream);
-}
+struct SourceSum {
+  Engine<T>& e;
+  const pic_fields* f;
+  bool rho_done = false, j_done = false;
+  int* flag = nullptr;  // of the current deposition
+  SourceSum(Engine<T>& eng, const pic_fields* fields) : e(eng), f(fields) {}
+  // rho/J targets of deposit_tiled's direct path, and its flag
+  T* spill_rho() { return e.spill[0]; }
+  T* const* spill_j() { return e.spill + 1; }
+  int* begin() {
+    flag = e.spill_flag + (e.dep_k & 1u);
+    return flag;
+  }
+  ReduceArgs<T> reduce_args(bool with_j) {
+    ReduceArgs<T> ra;
+    ra.acc_mask = (rho_done ? 1 : 0) | (j_done ? 2 : 0);
+    ra.base = rho_done ? nullptr : static_cast<const T*>(f->rho_static);
+    for (int q = 0; q < 4; ++q) ra.spill[q] = e.spill[q];
+    ra.flag = flag;
+    ra.next_flag = e.spill_flag + ((e.dep_k + 1u) & 1u);
+    ++e.dep_k;
+    rho_done = true;
+    if (with_j) j_done = true;
+    return ra;
+  }
+  // what no species wrote: rho = rho_static (or zero), J = 0
+  void finish(pic_ctx c, bool with_j) {
+    const size_t N = ncells(c->p);
+    if (!rho_done) {
+      if (f->rho_static)
+        (void)hipMemcpyAsync(f->rho_new, f->rho_static, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
+      else
+        (void)hipMemsetAsync(f->rho_new, 0, N * sizeof(T), c->stream);
+    }
+    if (with_j && !j_done)
+      for (int d = 0; d < 3; ++d) (void)hipMemsetAsync(f->J_nod[d], 0, N * sizeof(T), c->stream);
+  }
+};
 
 template <typename T>
 void J_ptrs(pic_fields* f, T* J[3]) {
@@ -568,9 +612,9 @@ pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, 
     deposit_yee_all<T>(c, sp, nsp, f, with_j);
     return c->check("pic_deposit");
   }
-  zero_sources<T>(c, f, with_j);
   T* J[3];
   J_ptrs<T>(f, J);
+  SourceSum<T> sum(e, f);
   const GridGeom g = geom(c->p);
   for (int s = 0; s < nsp; ++s) {
     if (sp[s].n == 0) continue;
@@ -582,10 +626,13 @@ pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, 
     tile_sort(g, e.tiles, v.cell, v.n, e.t_counts, e.t_starts, e.t_cursor, x.dst, c->d_bad, c->stream);
     invert_perm(x.dst, x.perm, v.n, c->stream);
     const bool mobile = std::isfinite(sp[s].m);
+    int* flag = sum.begin();
     deposit_tiled<T>(g, e.tiles, v, x.perm, e.t_starts, with_j && mobile, e.stage, c->d_bad, nullptr, nullptr, e.work,
-                     static_cast<T*>(f->rho_new), J, c->stream);
-    deposit_reduce<T>(g, e.tiles, e.t_starts, e.stage, with_j && mobile, static_cast<T*>(f->rho_new), J, c->stream);
+                     sum.spill_rho(), sum.spill_j(), c->stream, flag);
+    deposit_reduce<T>(g, e.tiles, e.t_starts, e.stage, with_j && mobile, static_cast<T*>(f->rho_new), J, c->stream,
+                      sum.reduce_args(with_j && mobile));
   }
+  sum.finish(c, with_j);
   return c->check("pic_deposit");
 }
 
@@ -926,10 +973,7 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
       if ((st = do_center<T>(c, PIC_S2N, PIC_E, &t)) != PIC_OK) return st;
       if ((st = do_center<T>(c, PIC_S2N, PIC_B, &t)) != PIC_OK) return st;
     }
-    {
-      StageScope sc(c, ST_CLEAR);
-      zero_sources<T>(c, f, true);
-    }
+    SourceSum<T> sum(e, f);
     for (int q = 0; q < nsp; ++q) {
       if (sp[q].n == 0) continue;
       SpeciesScratch<T>& x = e.sps[q];
@@ -949,11 +993,12 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
         {
           StageScope sc(c, ST_DEPOSIT);  // positions moved < 1 cell: the grouping still holds them
           deposit_tiled<T>(g, e.tiles, v, x.perm, x.starts[0], mobile, e.stage, c->d_bad, nullptr, nullptr, e.work,
-                           static_cast<T*>(f->rho_new), Jn, c->stream);
+                           sum.spill_rho(), sum.spill_j(), c->stream, sum.begin());
         }
         {
           StageScope sc(c, ST_REDUCE);
-          deposit_reduce<T>(g, e.tiles, x.starts[0], e.stage, mobile, static_cast<T*>(f->rho_new), Jn, c->stream);
+          deposit_reduce<T>(g, e.tiles, x.starts[0], e.stage, mobile, static_cast<T*>(f->rho_new), Jn, c->stream,
+                            sum.reduce_args(mobile));
         }
         continue;
       }
@@ -993,15 +1038,20 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
         StageScope sc(c, ST_DEPOSIT);
         int* nextc = mobile ? x.counts[first ? 1 : L] : nullptr;
         deposit_tiled<T>(g, e.tiles, dep, nullptr, dep_starts, mobile, e.stage, c->d_bad, nextc,
-                         mobile ? x.nbr : nullptr, e.work, static_cast<T*>(f->rho_new), Jn, c->stream);
+                         mobile ? x.nbr : nullptr, e.work, sum.spill_rho(), sum.spill_j(), c->stream, sum.begin());
       }
       {
         StageScope sc(c, ST_REDUCE);
-        deposit_reduce<T>(g, e.tiles, dep_starts, e.stage, mobile, static_cast<T*>(f->rho_new), Jn, c->stream);
+        deposit_reduce<T>(g, e.tiles, dep_starts, e.stage, mobile, static_cast<T*>(f->rho_new), Jn, c->stream,
+                          sum.reduce_args(mobile));
       }
       if (first || mobile) in_scratch[q] = !in_scratch[q];
       // layout index of the grouping the particles are now in
       if (mobile) layout[q] = first ? 0 : 1 - L;
+    }
+    {
+      StageScope sc(c, ST_CLEAR);
+      sum.finish(c, true);
     }
     if (!spectral && !nodal) {
       StageScope sc(c, ST_N2S);

@@ -141,19 +141,42 @@ void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const 
 // sorted slots [starts[t], starts[t+1]); slot q holds particle perm[q], perm == nullptr:
 // q) into per-tile boxes in ``stage`` (ntiles * (with_j ? 4 : 1) * deposit_box^3
 // elements); particles that left the one-cell margin go straight to rho/J.
-// deposit_reduce then adds the overlapping boxes to the nodal arrays.
+// deposit_reduce then sums the overlapping boxes into the nodal arrays.
 // With next_counts != nullptr, the particles are also counted per tile of their cells
 // (the grouping of the next step), into next_counts[ntiles + 1] (invalid cells last),
 // and, when nbr_counts != nullptr, per tile t of this grouping and neighbour nb of t
 // (0..26, the tile offsets in {-1,0,1}^3 in x-major order) into nbr_counts[27 t + nb].
 // ``work`` is one int of device scratch (the tile counter of the persistent launch).
+// ``spill_flag`` (optional) is set to 1 whenever a particle goes to rho/J directly.
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
                    bool with_j, T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, T* rho,
-                   T* const J[3], hipStream_t s);
+                   T* const J[3], hipStream_t s, int* spill_flag = nullptr);
+// How deposit_reduce starts each node and what else it folds in.  By default it adds to the
+// nodal arrays.  With bit 0 (rho) or bit 1 (J) of acc_mask clear it overwrites them instead,
+// rho starting from ``base`` when given, else from zero.  When *flag != 0, the ``spill``
+// arrays (which hold what a deposit_tiled with rho/J = spill sent past its boxes, and are zero
+// otherwise) are added and cleared.  *next_flag is zeroed for the deposition after this one.
+template <typename T>
+struct ReduceArgs {
+  int acc_mask = 3;
+  const T* base = nullptr;
+  T* spill[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  const int* flag = nullptr;
+  int* next_flag = nullptr;
+  __device__ T start(int q, const T* o, size_t idx) const {
+    if (acc_mask & (q == 0 ? 1 : 2)) return o[idx];
+    return (q == 0 && base) ? base[idx] : (T)0;
+  }
+  __device__ T take_spill(int q, size_t idx) const {
+    const T v = spill[q][idx];
+    spill[q][idx] = 0;
+    return v;
+  }
+};
 template <typename T>
 void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, const T* stage, bool with_j, T* rho,
-                    T* const J[3], hipStream_t s);
+                    T* const J[3], hipStream_t s, const ReduceArgs<T>& ra = ReduceArgs<T>());
 
 // Reverse mode of gather + push + move + deposition of one species, particles at time n
 // visited in slot order (slot q -> particle perm[q]; perm == nullptr: q); with the tile

@@ -882,7 +882,7 @@ template <typename T, int ORDER, bool WJ>
 __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom& tg, const SpeciesView<T>& sp,
                                     const int* __restrict__ perm, const int* __restrict__ starts,
                                     const Batch<T*>& out, T* __restrict__ stage, T qdv, T hdtx, T hdty, T hdtz,
-                                    int* bad, int* next_counts, int* nbr_counts,
+                                    int* bad, int* next_counts, int* nbr_counts, int* spill_flag,
                                     typename Fixed<T>::acc_t* box, DepositLds<T>& L) {
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
@@ -1065,6 +1065,7 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
         T* dst[1] = {out.p[0]};
         const T val[1] = {qw};
         scatter<T, ORDER>(g, d.i, d.j, d.k, d.ox, d.oy, d.oz, dst, val, 1);
+        if (spill_flag) *spill_flag = 1;
       }
       if (WJ) {
         if (d.at_j >= 0) {
@@ -1077,6 +1078,7 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
           T* dst[3] = {out.p[1], out.p[2], out.p[3]};
           const T val[3] = {qw * d.vx, qw * d.vy, qw * d.vz};
           scatter<T, ORDER>(g, d.ih, d.jh, d.kh, d.hx, d.hy, d.hz, dst, val, 3);
+          if (spill_flag) *spill_flag = 1;
         }
       }
     }
@@ -1114,7 +1116,7 @@ template <typename T, int ORDER, bool WJ>
 __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK, sizeof(T) == 4 ? (ORDER == 3 ? 3 : 4) : 1)
     k_deposit_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp, const int* __restrict__ perm,
                     const int* __restrict__ starts, Batch<T*> out, T* __restrict__ stage, T qdv, T hdtx, T hdty,
-                    T hdtz, int* bad, int* next_counts, int* nbr_counts, int* work) {
+                    T hdtz, int* bad, int* next_counts, int* nbr_counts, int* work, int* spill_flag) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ DepositLds<T> L;
   auto* box = reinterpret_cast<typename Fixed<T>::acc_t*>(smem);
@@ -1126,11 +1128,11 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK, sizeof(T) == 4 ? (ORDER == 
       __syncthreads();
       if (tile > tg.ntiles) break;
       deposit_tile<T, ORDER, WJ>(tile, g, tg, sp, perm, starts, out, stage, qdv, hdtx, hdty, hdtz, bad, next_counts,
-                                 nbr_counts, box, L);
+                                 nbr_counts, spill_flag, box, L);
     }
   } else {
     deposit_tile<T, ORDER, WJ>(blockIdx.x, g, tg, sp, perm, starts, out, stage, qdv, hdtx, hdty, hdtz, bad,
-                               next_counts, nbr_counts, box, L);
+                               next_counts, nbr_counts, spill_flag, box, L);
   }
 }
 
@@ -1162,8 +1164,10 @@ __device__ inline int axis_candidates(int x, int nt, int* t, int* l) {
 // atomics.  Grids that are whole multiples of the tile; grid (z blocks, ny, nx).
 template <typename T, int ORDER, int NCOMP>
 __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGeom tg, const int* __restrict__ starts,
-                                                              const T* __restrict__ stage, Batch<T*> out) {
+                                                              const T* __restrict__ stage, Batch<T*> out,
+                                                              ReduceArgs<T> ra) {
   using X = Box<Shape<T, ORDER>::NW>;
+  if (ra.next_flag && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *ra.next_flag = 0;
   // grid (z blocks, ny, nx) flattened and renumbered XCD-major: rows next to each other
   // read the same staging lines
   const int nzb = gridDim.x;
@@ -1181,7 +1185,7 @@ __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGe
   const size_t idx = ((size_t)x * g.ny + y) * g.nz + z;
   T acc[NCOMP];
 #pragma unroll
-  for (int q = 0; q < NCOMP; ++q) acc[q] = out.p[q][idx];
+  for (int q = 0; q < NCOMP; ++q) acc[q] = ra.start(q, out.p[q], idx);
   bool use[8];
   const T* sb[8];
 #pragma unroll
@@ -1204,6 +1208,10 @@ __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGe
 #pragma unroll
     for (int m = 0; m < 8; ++m) acc[q] += v[m][q];
   }
+  if (ra.flag && *ra.flag) {
+#pragma unroll
+    for (int q = 0; q < NCOMP; ++q) acc[q] += ra.take_spill(q, idx);
+  }
 #pragma unroll
   for (int q = 0; q < NCOMP; ++q) out.p[q][idx] = acc[q];
 }
@@ -1213,9 +1221,12 @@ __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGe
 // grid node (t * kTile - 1 + BASE + l) mod n.
 template <typename T, int ORDER>
 __global__ void __launch_bounds__(256) k_deposit_reduce(GridGeom g, TileGeom tg, const int* __restrict__ starts,
-                                                        const T* __restrict__ stage, Batch<T*> out, int ncomp) {
+                                                        const T* __restrict__ stage, Batch<T*> out, int ncomp,
+                                                        ReduceArgs<T> ra) {
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
+  if (ra.next_flag && blockIdx.x == 0 && threadIdx.x == 0) *ra.next_flag = 0;
+  const bool spilled = ra.flag && *ra.flag;
   const long long N = (long long)g.nx * g.ny * g.nz;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < N;
        idx += (long long)gridDim.x * blockDim.x) {
@@ -1258,7 +1269,7 @@ __global__ void __launch_bounds__(256) k_deposit_reduce(GridGeom g, TileGeom tg,
           const T* sb = stage + (size_t)tile * ncomp * X::B3 + X::at(clx[a], cly[b], clz[c]);
           for (int q = 0; q < ncomp; ++q) acc[q] += sb[(size_t)q * X::B3];
         }
-    for (int q = 0; q < ncomp; ++q) out.p[q][idx] += acc[q];
+    for (int q = 0; q < ncomp; ++q) out.p[q][idx] = ra.start(q, out.p[q], idx) + acc[q] + (spilled ? ra.take_spill(q, idx) : (T)0);
   }
 }
 
@@ -2109,8 +2120,8 @@ int resident_blocks(const void* kernel, int block, size_t lds) {
 
 template <typename T, int ORDER, bool WJ>
 void launch_deposit(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
-                    T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, const Batch<T*>& out,
-                    hipStream_t s) {
+                    T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, int* spill_flag,
+                    const Batch<T*>& out, hipStream_t s) {
   const T qdv = (T)(sp.q / (g.dx * g.dy * g.dz));
   const T hx = (T)(0.5 * g.dt / g.dx), hy = (T)(0.5 * g.dt / g.dy), hz = (T)(0.5 * g.dt / g.dz);
   constexpr int B = Box<Shape<T, ORDER>::NW>::B;
@@ -2125,29 +2136,29 @@ void launch_deposit(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& 
     (void)hipMemsetAsync(work, 0, sizeof(int), s);
   }
   hipLaunchKernelGGL((k_deposit_tiled<T, ORDER, WJ>), dim3(nb), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm,
-                     starts, out, stage, qdv, hx, hy, hz, bad, next_counts, nbr_counts, work);
+                     starts, out, stage, qdv, hx, hy, hz, bad, next_counts, nbr_counts, work, spill_flag);
 }
 
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
                    bool with_j, T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, T* rho,
-                   T* const J[3], hipStream_t s) {
+                   T* const J[3], hipStream_t s, int* spill_flag) {
   if (sp.n <= 0) return;
   Batch<T*> out{};
   out.p[0] = rho;
   for (int d = 0; d < 3; ++d) out.p[1 + d] = J ? J[d] : nullptr;
   if (g.shape_order == 1) {
-    if (with_j) launch_deposit<T, 1, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, out, s);
-    else launch_deposit<T, 1, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, out, s);
+    if (with_j) launch_deposit<T, 1, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, out, s);
+    else launch_deposit<T, 1, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, out, s);
   } else {
-    if (with_j) launch_deposit<T, 3, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, out, s);
-    else launch_deposit<T, 3, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, out, s);
+    if (with_j) launch_deposit<T, 3, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, out, s);
+    else launch_deposit<T, 3, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, out, s);
   }
 }
 
 template <typename T>
 void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, const T* stage, bool with_j, T* rho,
-                    T* const J[3], hipStream_t s) {
+                    T* const J[3], hipStream_t s, const ReduceArgs<T>& ra) {
   Batch<T*> out{};
   out.p[0] = rho;
   for (int d = 0; d < 3; ++d) out.p[1 + d] = J ? J[d] : nullptr;
@@ -2156,20 +2167,20 @@ void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, con
     const unsigned bz = (unsigned)std::min(256, (g.nz + 63) / 64 * 64);
     const dim3 grid((unsigned)((g.nz + bz - 1) / bz), (unsigned)g.ny, (unsigned)g.nx);
     if (g.shape_order == 1) {
-      if (with_j) hipLaunchKernelGGL((k_deposit_reduce_whole<T, 1, 4>), grid, dim3(bz), 0, s, g, t, starts, stage, out);
-      else hipLaunchKernelGGL((k_deposit_reduce_whole<T, 1, 1>), grid, dim3(bz), 0, s, g, t, starts, stage, out);
+      if (with_j) hipLaunchKernelGGL((k_deposit_reduce_whole<T, 1, 4>), grid, dim3(bz), 0, s, g, t, starts, stage, out, ra);
+      else hipLaunchKernelGGL((k_deposit_reduce_whole<T, 1, 1>), grid, dim3(bz), 0, s, g, t, starts, stage, out, ra);
     } else {
-      if (with_j) hipLaunchKernelGGL((k_deposit_reduce_whole<T, 3, 4>), grid, dim3(bz), 0, s, g, t, starts, stage, out);
-      else hipLaunchKernelGGL((k_deposit_reduce_whole<T, 3, 1>), grid, dim3(bz), 0, s, g, t, starts, stage, out);
+      if (with_j) hipLaunchKernelGGL((k_deposit_reduce_whole<T, 3, 4>), grid, dim3(bz), 0, s, g, t, starts, stage, out, ra);
+      else hipLaunchKernelGGL((k_deposit_reduce_whole<T, 3, 1>), grid, dim3(bz), 0, s, g, t, starts, stage, out, ra);
     }
     return;
   }
   const long long N = (long long)g.nx * g.ny * g.nz;
   const unsigned nr = (unsigned)std::min<long long>((N + 255) / 256, 65536);
   if (g.shape_order == 1)
-    hipLaunchKernelGGL((k_deposit_reduce<T, 1>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, out, ncomp);
+    hipLaunchKernelGGL((k_deposit_reduce<T, 1>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, out, ncomp, ra);
   else
-    hipLaunchKernelGGL((k_deposit_reduce<T, 3>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, out, ncomp);
+    hipLaunchKernelGGL((k_deposit_reduce<T, 3>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, out, ncomp, ra);
 }
 
 template <typename T>
@@ -2235,17 +2246,17 @@ void scatter_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& s
     const unsigned bz = (unsigned)std::min(256, (g.nz + 63) / 64 * 64);
     const dim3 rgrid((unsigned)((g.nz + bz - 1) / bz), (unsigned)g.ny, (unsigned)g.nx);
     if (g.shape_order == 1)
-      hipLaunchKernelGGL((k_deposit_reduce_whole<T, 1, 6>), rgrid, dim3(bz), 0, s, g, t, starts, stage, o);
+      hipLaunchKernelGGL((k_deposit_reduce_whole<T, 1, 6>), rgrid, dim3(bz), 0, s, g, t, starts, stage, o, ReduceArgs<T>());
     else
-      hipLaunchKernelGGL((k_deposit_reduce_whole<T, 3, 6>), rgrid, dim3(bz), 0, s, g, t, starts, stage, o);
+      hipLaunchKernelGGL((k_deposit_reduce_whole<T, 3, 6>), rgrid, dim3(bz), 0, s, g, t, starts, stage, o, ReduceArgs<T>());
     return;
   }
   const long long N = (long long)g.nx * g.ny * g.nz;
   const unsigned nr = (unsigned)std::min<long long>((N + 255) / 256, 65536);
   if (g.shape_order == 1)
-    hipLaunchKernelGGL((k_deposit_reduce<T, 1>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, o, 6);
+    hipLaunchKernelGGL((k_deposit_reduce<T, 1>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, o, 6, ReduceArgs<T>());
   else
-    hipLaunchKernelGGL((k_deposit_reduce<T, 3>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, o, 6);
+    hipLaunchKernelGGL((k_deposit_reduce<T, 3>), dim3(nr), dim3(256), 0, s, g, t, starts, stage, o, 6, ReduceArgs<T>());
 }
 
 template <typename T>
@@ -2312,7 +2323,7 @@ void deposit_yee_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T
     hipLaunchKernelGGL((k_deposit_yee_tiled<T, 3>), grid, dim3(256), lds, s, g, t, sp, perm, starts, out, stage, qdv,
                        hx, hy, hz, with_j ? 1 : 0);
   }
-  deposit_reduce<T>(g, t, starts, stage, true, rho, J, s);
+  deposit_reduce<T>(g, t, starts, stage, true, rho, J, s, ReduceArgs<T>());
 }
 
 template <typename T>
@@ -2333,9 +2344,9 @@ void deposit_yee(const GridGeom& g, const SpeciesView<T>& sp, bool with_j, T* rh
 #define PIC_INST(T)                                                                                              \
   template void permute_species<T>(const SpeciesView<T>&, const SpeciesView<T>&, const int*, hipStream_t);       \
   template void deposit_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*, const int*, \
-                                 bool, T*, int*, int*, int*, int*, T*, T* const*, hipStream_t);                  \
+                                 bool, T*, int*, int*, int*, int*, T*, T* const*, hipStream_t, int*);            \
   template void deposit_reduce<T>(const GridGeom&, const TileGeom&, const int*, const T*, bool, T*, T* const*,   \
-                                  hipStream_t);                                                                  \
+                                  hipStream_t, const ReduceArgs<T>&);                                            \
   template void gather_push_tiled<T>(const GridGeom&, const TileGeom&, const T* const*, const T* const*,         \
                                      const SpeciesView<T>&, const SpeciesView<T>&, const int*, const int*, bool,  \
                                      int*, const int*, hipStream_t);                                              \
