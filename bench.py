@@ -18,7 +18,9 @@ transforms are inside the timed region).
 Prints one JSON line.  Rates: particle-pushes/s = Np*K/T (``value``) and grid
 cell updates/s = N*K/T.  ``roofline`` is the dominant stage's algorithmic bytes
 per launch over its mean duration, timed with HIP events on the stream the
-library launches on.  ``cpu_baseline`` times the FP64 NumPy oracle on the host
+library launches on.  ``lds_atomic_floor`` sets the deposition's mean duration
+against the time its LDS atomics alone take at the rates a probe measured on
+MI355X (the deposition is bound by those, not by HBM).  ``cpu_baseline`` times the FP64 NumPy oracle on the host
 on a bounded sample (the full grid part of one step plus 1/8 of the particles;
 the particle part is scaled by 8, it is linear in the particle count).
 """
@@ -34,6 +36,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# LDS atomic throughput per compute unit, lane operations per clock, measured on MI355X with a
+# probe (1024 blocks x 256 threads, immediate offsets): ds_add_u32 with the 32 lanes of each
+# half wave on distinct words modulo 32, ds_add_u64 with 16 lanes on distinct words modulo 16.
+LDS_U32_LANE_OPS = 14.5
+LDS_U64_LANE_OPS = 9.9
+CUS, CLOCK_HZ = 256, 2.4e9
+
+
+def deposit_lds_floor_ms(Np, shape_order, dtype):
+    """Time of the deposition's LDS atomics alone for Np particles depositing rho and J: FP32 adds
+    (J_x, J_y) as one 64-bit word and J_z, rho as 32-bit words per support node; FP64 adds four
+    64-bit words per node."""
+    nodes = (2 if shape_order == 1 else 4) ** 3
+    u64, u32 = (nodes, 2 * nodes) if dtype == "f32" else (4 * nodes, 0)
+    clocks_per_cu = Np * (u64 / LDS_U64_LANE_OPS + u32 / LDS_U32_LANE_OPS) / CUS
+    return clocks_per_cu / CLOCK_HZ * 1e3
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "laser128_f32_hbm_traffic.md")
 
 
@@ -390,6 +408,14 @@ def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0, v_gal=(0.0,
               key=lambda k: breakdown[k]["ms_avg"] * breakdown[k]["launches"])
     d = breakdown[dom]
     achieved = d["algo_bytes"] / (d["ms_avg"] * 1e-3) / 1e9
+    lds_floor = None
+    if "deposit" in breakdown:
+        fl = deposit_lds_floor_ms(Np, wl.shape_order, wl.dtype)
+        dep = breakdown["deposit"]["ms_avg"]
+        lds_floor = {"kernel": "deposit", "bound": "lds_atomics", "floor_ms": round(fl, 5), "ms_per_launch": dep,
+                     "frac": round(fl / dep, 4),
+                     "basis": f"{LDS_U32_LANE_OPS} (u32) and {LDS_U64_LANE_OPS} (u64) lane-ops/clk/CU measured, "
+                              f"{CUS} CUs at {CLOCK_HZ / 1e9} GHz"}
     ctx.close()
     return {
         "metric": "particle-pushes/s and grid-cell updates/s per PIC step, FP32 vs FP64, fwd and fwd+bwd",
@@ -414,6 +440,7 @@ def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0, v_gal=(0.0,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": recorded_traffic(dom) if (config_name == "laser128" and wl.dtype == "f32") else None,
                      "algo_bytes_per_launch": d["algo_bytes"], "ms_per_launch": d["ms_avg"]},
+        "lds_atomic_floor": lds_floor,
         "stages": breakdown,
     }
 
