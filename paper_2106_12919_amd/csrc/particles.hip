@@ -1136,6 +1136,9 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK, sizeof(T) == 4 ? (ORDER == 
   }
 }
 
+// Tiles along z of the largest grid (1024 / kTile): the reduction's occupancy table.
+constexpr int kMaxTilesZ = 1024 / kTile;
+
 // Per axis, the (tile, box index) pairs whose boxes hold grid node x on grids that are
 // whole multiples of the tile: its own tile t at l0 = x mod kTile + 1 - BASE, and
 // t - 1 at l0 + kTile or t + 1 at l0 - kTile when that index lies inside the box.
@@ -1167,17 +1170,30 @@ __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGe
                                                               const T* __restrict__ stage, Batch<T*> out,
                                                               ReduceArgs<T> ra) {
   using X = Box<Shape<T, ORDER>::NW>;
+  __shared__ unsigned char occ[4][kMaxTilesZ];  // occupancy of the row's (x, y) candidate tiles, by tz
   if (ra.next_flag && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *ra.next_flag = 0;
   // grid (z blocks, ny, nx) flattened and renumbered XCD-major: rows next to each other
   // read the same staging lines
   const int nzb = gridDim.x;
   const int L = xcd_major(blockIdx.x + nzb * (blockIdx.y + gridDim.y * blockIdx.z), nzb * gridDim.y * gridDim.z);
   const int z = (L % nzb) * blockDim.x + threadIdx.x;
-  if (z >= g.nz) return;
   const int y = (L / nzb) % g.ny, x = L / (nzb * g.ny);
   int tx[2], lx[2], ty[2], ly[2], tz[2], lz[2];
   const int nxc = axis_candidates<ORDER>(x, tg.ntx, tx, lx);
   const int nyc = axis_candidates<ORDER>(y, tg.nty, ty, ly);
+  // which tiles of the row's candidates hold particles (empty tiles' staging slots hold
+  // stale data and are skipped): loaded once per block, so that every staging load
+  // below issues without waiting for another global load
+  for (int e = threadIdx.x; e < 4 * tg.ntz; e += blockDim.x) {
+    const int ab = e / tg.ntz, t3 = e - ab * tg.ntz;
+    const int a = ab >> 1, b = ab & 1;
+    if (a < nxc && b < nyc) {
+      const int tile = (tx[a] * tg.nty + ty[b]) * tg.ntz + t3;
+      occ[ab][t3] = starts[tile] != starts[tile + 1];
+    }
+  }
+  __syncthreads();
+  if (z >= g.nz) return;
   const int nzc = axis_candidates<ORDER>(z, tg.ntz, tz, lz);
   // the eight combinations are unrolled: first every tile's occupancy, then the
   // staging loads of the occupied ones, all in flight before any sum (empty tiles'
@@ -1194,8 +1210,7 @@ __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGe
     const bool present = a < nxc && b < nyc && c < nzc;
     const int ia = present ? a : 0, ib = present ? b : 0, ic = present ? c : 0;
     const int tile = (tx[ia] * tg.nty + ty[ib]) * tg.ntz + tz[ic];
-    const int s0 = starts[tile], s1 = starts[tile + 1];  // loaded whether present or not
-    use[m] = present & (s0 != s1);
+    use[m] = present && occ[2 * ia + ib][tz[ic]];
     sb[m] = stage + (size_t)tile * NCOMP * X::B3 + X::at(lx[ia], ly[ib], lz[ic]);
   }
   T v[8][NCOMP];
