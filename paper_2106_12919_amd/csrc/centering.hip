@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(256) k_center_z(const T* __restrict__ in, T* _
 template <typename T, int M>
 void launch_strided(const T* in, T* out, const Coef<T>& cf, int Na, long long sa, int C, int O, long long os,
                     int shift, hipStream_t s) {
-  constexpr int L = (sizeof(T) == 4) ? 16 : 8;
+  constexpr int L = (sizeof(T) == 4) ? 32 : 8;
   dim3 grid((C + 255) / 256, (Na + L - 1) / L, O);
   hipLaunchKernelGGL((k_center_strided<T, M, L>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift);
 }

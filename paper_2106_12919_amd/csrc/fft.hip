@@ -138,7 +138,8 @@ __device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nlines, int ls, int js, 
 }
 
 // Largest element count per thread of one block's LDS tile (two buffers of kLdsBudget
-// bytes in all): every thread issues all its global loads before it stores any to LDS.
+// bytes in all): every thread issues all its global loads (those inside the tile) before it
+// stores any to LDS.
 constexpr size_t kLdsBudget = 65536;
 template <typename T>
 constexpr int kPerThread = (int)(kLdsBudget / (2 * sizeof(cplx<T>)) / kBlock);
@@ -167,11 +168,13 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z(Batch<const T*> in, Batch<cplx
   T v0[PER], v1[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int e = min((int)threadIdx.x + u * kBlock, total - 1);
-    const int q = e / N, j = e - q * N;
-    const size_t l = 2 * (size_t)(pair0 + q);
-    v0[u] = src[l * N + j];
-    v1[u] = src[(l + 1) * N + j];
+    const int e = (int)threadIdx.x + u * kBlock;
+    if (e < total) {
+      const int q = e / N, j = e - q * N;
+      const size_t l = 2 * (size_t)(pair0 + q);
+      v0[u] = src[l * N + j];
+      v1[u] = src[(l + 1) * N + j];
+    }
   }
   const cplx<T>* twl = stage_twiddles(b + (size_t)P * N, tw, p.twcount);
 #pragma unroll
@@ -213,12 +216,14 @@ __global__ void __launch_bounds__(kBlock) k_c2r_z(Batch<const cplx<T>*> in, Batc
   cplx<T> f[PER], g[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int e = min((int)threadIdx.x + u * kBlock, total - 1);
-    const int q = e / N, k = e - q * N;
-    const size_t l = 2 * (size_t)(pair0 + q);
-    const int kk = k <= half ? k : N - k;
-    f[u] = src[l * pz + kk];
-    g[u] = src[(l + 1) * pz + kk];
+    const int e = (int)threadIdx.x + u * kBlock;
+    if (e < total) {
+      const int q = e / N, k = e - q * N;
+      const size_t l = 2 * (size_t)(pair0 + q);
+      const int kk = k <= half ? k : N - k;
+      f[u] = src[l * pz + kk];
+      g[u] = src[(l + 1) * pz + kk];
+    }
   }
   const cplx<T>* twl = stage_twiddles(b + (size_t)P * N, tw, p.twcount);
 #pragma unroll
@@ -272,9 +277,11 @@ __global__ void __launch_bounds__(kBlock) k_fft_strided(Batch<const cplx<T>*> in
   cplx<T> v[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int e = min((int)threadIdx.x + u * kBlock, total - 1);
-    const int j = e >> tl_shift, i = min(e & (TL - 1), nl - 1);
-    v[u] = src[base + i + (size_t)j * elem_stride];
+    const int e = (int)threadIdx.x + u * kBlock;
+    if (e < total) {
+      const int j = e >> tl_shift, i = min(e & (TL - 1), nl - 1);
+      v[u] = src[base + i + (size_t)j * elem_stride];
+    }
   }
   const cplx<T>* twl = stage_twiddles(b + (size_t)TL * N, tw, p.twcount);
 #pragma unroll
