@@ -131,12 +131,25 @@ __global__ void __launch_bounds__(256) k_center_z(const T* __restrict__ in, T* _
   }
 }
 
+// Outputs per thread along the axis: FP32 the longest window of 32, 16 or 8 that still gives
+// at least two workgroups per compute unit (a longer window re-reads fewer halo rows, but
+// small grids need the workgroups); FP64 8.
 template <typename T, int M>
 void launch_strided(const T* in, T* out, const Coef<T>& cf, int Na, long long sa, int C, int O, long long os,
                     int shift, hipStream_t s) {
-  constexpr int L = (sizeof(T) == 4) ? 32 : 8;
-  dim3 grid((C + 255) / 256, (Na + L - 1) / L, O);
-  hipLaunchKernelGGL((k_center_strided<T, M, L>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift);
+  const long long cols = (C + 255) / 256;
+  auto blocks = [&](int L) { return cols * ((Na + L - 1) / L) * O; };
+  constexpr long long kMinBlocks = 512;
+  if (sizeof(T) == 4 && blocks(32) >= kMinBlocks) {
+    dim3 grid((unsigned)cols, (Na + 31) / 32, O);
+    hipLaunchKernelGGL((k_center_strided<T, M, 32>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift);
+  } else if (sizeof(T) == 4 && blocks(16) >= kMinBlocks) {
+    dim3 grid((unsigned)cols, (Na + 15) / 16, O);
+    hipLaunchKernelGGL((k_center_strided<T, M, 16>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift);
+  } else {
+    dim3 grid((unsigned)cols, (Na + 7) / 8, O);
+    hipLaunchKernelGGL((k_center_strided<T, M, 8>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift);
+  }
 }
 
 template <typename T>
