@@ -105,19 +105,31 @@ class DifferentiableRun:
 
 
 class _State:
-    """E, B (Yee), rho^n and one species' cell, offsets, momenta: separate contiguous tensors."""
+    """E, B (Yee), rho^n and one species' cell, offsets, momenta, held in three contiguous
+    buffers (fields (7, nx, ny, nz); cell (Np,); off and u as rows of one (6, Np_pad) float
+    buffer whose rows start 256-byte aligned), so that a copy of the state is three copies."""
 
-    def __init__(self, E, B, rho, cell, off, u):
-        self.E, self.B, self.rho, self.cell, self.off, self.u = E, B, rho, cell, off, u
+    def __init__(self, fbuf, cell, pbuf, n):
+        self.fbuf, self.cell, self.pbuf, self.n = fbuf, cell, pbuf, n
+        self.E = [fbuf[d] for d in range(3)]
+        self.B = [fbuf[3 + d] for d in range(3)]
+        self.rho = fbuf[6]
+        self.off = [pbuf[d, :n] for d in range(3)]
+        self.u = [pbuf[3 + d, :n] for d in range(3)]
 
     @classmethod
     def of(cls, E, B, rho, cell, off, u):
-        c = lambda t: t.detach().clone().contiguous()
-        return cls([c(E[d]) for d in range(3)], [c(B[d]) for d in range(3)], c(rho), c(cell),
-                   [c(off[d]) for d in range(3)], [c(u[d]) for d in range(3)])
+        fbuf = torch.stack([*(E[d] for d in range(3)), *(B[d] for d in range(3)), rho]).detach().contiguous()
+        n = int(cell.numel())
+        row = -(-n // 64) * 64  # 64 elements: at least 256 bytes per row start
+        pbuf = torch.zeros((6, row), dtype=fbuf.dtype, device=fbuf.device)
+        for d in range(3):
+            pbuf[d, :n].copy_(off[d].detach())
+            pbuf[3 + d, :n].copy_(u[d].detach())
+        return cls(fbuf, cell.detach().clone().contiguous(), pbuf, n)
 
     def clone(self):
-        return _State.of(self.E, self.B, self.rho, self.cell, self.off, self.u)
+        return _State(self.fbuf.clone(), self.cell.clone(), self.pbuf.clone(), self.n)
 
     def fields(self, run):
         f = run.work

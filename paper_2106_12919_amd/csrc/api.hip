@@ -483,8 +483,9 @@ size_t ncells(const pic_params& p) { return (size_t)p.nx * p.ny * p.nz; }
 
 // ------------------------------------------------------------------ stages
 
+// accumulate: the N2S transposes of E and B add into E_stag / B_stag instead of writing them.
 template <typename T>
-pic_status do_center(pic_ctx c, int dir, int what, pic_fields* f) {
+pic_status do_center(pic_ctx c, int dir, int what, pic_fields* f, bool accumulate = false) {
   Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
   const pic_params& p = c->p;
   const int m = p.center_order / 2;
@@ -511,13 +512,13 @@ pic_status do_center(pic_ctx c, int dir, int what, pic_fields* f) {
   } else if (dir == PIC_N2S && what == PIC_E) {  // transpose of (S2N, E)
     for (int d = 0; d < 3; ++d)
       center_axis<T>(static_cast<const T*>(f->E_nod[d]), static_cast<T*>(f->E_stag[d]), p.nx, p.ny, p.nz, d, 0, m,
-                     cf, c->stream);
+                     cf, c->stream, accumulate);
   } else if (dir == PIC_N2S && what == PIC_B) {  // transpose of (S2N, B): the same two axes
     for (int d = 0; d < 3; ++d) {
       const int a0 = (d == 0) ? 1 : 0;
       const int a1 = (d == 2) ? 1 : 2;
       center_axis<T>(static_cast<const T*>(f->B_nod[d]), e.tmp, p.nx, p.ny, p.nz, a1, 0, m, cf, c->stream);
-      center_axis<T>(e.tmp, static_cast<T*>(f->B_stag[d]), p.nx, p.ny, p.nz, a0, 0, m, cf, c->stream);
+      center_axis<T>(e.tmp, static_cast<T*>(f->B_stag[d]), p.nx, p.ny, p.nz, a0, 0, m, cf, c->stream, accumulate);
     }
   } else {
     return c->fail(PIC_EINVAL, "unsupported (dir, what) pair for pic_center");
@@ -1119,9 +1120,13 @@ pic_status do_step_adjoint(pic_ctx c, pic_fields* f, const pic_species* sp, int 
     StageScope sc(c, ST_N2S);
     if ((st = do_center<T>(c, PIC_S2N, PIC_J, a)) != PIC_OK) return st;  // J_stag -> J_nod (transpose of N2S)
   }
-  for (int d = 0; d < 3; ++d) {
-    (void)hipMemsetAsync(a->E_nod[d], 0, N * sizeof(T), c->stream);
-    (void)hipMemsetAsync(a->B_nod[d], 0, N * sizeof(T), c->stream);
+  {
+    Batch<T*> z{};
+    for (int d = 0; d < 3; ++d) {
+      z.p[d] = static_cast<T*>(a->E_nod[d]);
+      z.p[3 + d] = static_cast<T*>(a->B_nod[d]);
+    }
+    zero_arrays<T>(z, 6, (int64_t)N, c->stream);
   }
   const T* L[4] = {static_cast<const T*>(a->rho_new), static_cast<const T*>(a->J_nod[0]),
                    static_cast<const T*>(a->J_nod[1]), static_cast<const T*>(a->J_nod[2])};
@@ -1171,18 +1176,14 @@ pic_status do_step_adjoint(pic_ctx c, pic_fields* f, const pic_species* sp, int 
   } else {
     StageScope sc(c, ST_S2N);
     pic_fields t{};
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < 3; ++d) {  // the transposed centering adds straight into the state's adjoint
       t.E_nod[d] = a->E_nod[d];
       t.B_nod[d] = a->B_nod[d];
-      t.E_stag[d] = f->E_nod[d];  // the state's nodal fields are no longer needed: workspace
-      t.B_stag[d] = f->B_nod[d];
+      t.E_stag[d] = a->E_stag[d];
+      t.B_stag[d] = a->B_stag[d];
     }
-    if ((st = do_center<T>(c, PIC_N2S, PIC_E, &t)) != PIC_OK) return st;
-    if ((st = do_center<T>(c, PIC_N2S, PIC_B, &t)) != PIC_OK) return st;
-    for (int d = 0; d < 3; ++d) {
-      add_into<T>(static_cast<T*>(a->E_stag[d]), static_cast<const T*>(f->E_nod[d]), (int64_t)N, c->stream);
-      add_into<T>(static_cast<T*>(a->B_stag[d]), static_cast<const T*>(f->B_nod[d]), (int64_t)N, c->stream);
-    }
+    if ((st = do_center<T>(c, PIC_N2S, PIC_E, &t, true)) != PIC_OK) return st;
+    if ((st = do_center<T>(c, PIC_N2S, PIC_B, &t, true)) != PIC_OK) return st;
   }
   return c->check("pic_step_adjoint");
 }

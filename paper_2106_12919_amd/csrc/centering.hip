@@ -38,7 +38,7 @@ __device__ inline int xcd_major(int b, int n) {
 template <typename T, int M, int L>
 __global__ void __launch_bounds__(256) k_center_strided(const T* __restrict__ in, T* __restrict__ out, Coef<T> cf,
                                                         int Na, long long sa, int C, long long outer_stride,
-                                                        int shift) {
+                                                        int shift, int accumulate) {
   const int nb = gridDim.x * gridDim.y * gridDim.z;
   const int lb = xcd_major(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
   const int bx = lb % gridDim.x, by = (lb / gridDim.x) % gridDim.y, bz = lb / (gridDim.x * gridDim.y);
@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(256) k_center_strided(const T* __restrict__ in
       T acc = 0;
 #pragma unroll
       for (int n = 1; n <= M; ++n) acc += cf.c[n - 1] * (w[q + n + M - 1] + w[q - n + M]);
-      out[base + (size_t)(j0 + q) * sa] = acc;
+      T* o = out + base + (size_t)(j0 + q) * sa;
+      *o = accumulate ? *o + acc : acc;
     }
   }
 }
@@ -91,7 +92,7 @@ struct Vec16<double> {
 // 16-byte loads, then every thread forms outputs from LDS.
 template <typename T, int M>
 __global__ void __launch_bounds__(256) k_center_z(const T* __restrict__ in, T* __restrict__ out, Coef<T> cf, int nz,
-                                                  int nlines, int lpb, int shift) {
+                                                  int nlines, int lpb, int shift, int accumulate) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* s = reinterpret_cast<T*>(smem);
   constexpr int H = 2 * M - 1;  // halo elements per line
@@ -127,7 +128,8 @@ __global__ void __launch_bounds__(256) k_center_z(const T* __restrict__ in, T* _
     T acc = 0;
 #pragma unroll
     for (int n = 1; n <= M; ++n) acc += cf.c[n - 1] * (sl[n + M - 1] + sl[M - n]);
-    out[(size_t)(line0 + l) * nz + z] = acc;
+    T* o = out + (size_t)(line0 + l) * nz + z;
+    *o = accumulate ? *o + acc : acc;
   }
 }
 
@@ -136,28 +138,28 @@ __global__ void __launch_bounds__(256) k_center_z(const T* __restrict__ in, T* _
 // small grids need the workgroups); FP64 8.
 template <typename T, int M>
 void launch_strided(const T* in, T* out, const Coef<T>& cf, int Na, long long sa, int C, int O, long long os,
-                    int shift, hipStream_t s) {
+                    int shift, int acc, hipStream_t s) {
   const long long cols = (C + 255) / 256;
   auto blocks = [&](int L) { return cols * ((Na + L - 1) / L) * O; };
   constexpr long long kMinBlocks = 512;
   if (sizeof(T) == 4 && blocks(32) >= kMinBlocks) {
     dim3 grid((unsigned)cols, (Na + 31) / 32, O);
-    hipLaunchKernelGGL((k_center_strided<T, M, 32>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift);
+    hipLaunchKernelGGL((k_center_strided<T, M, 32>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift, acc);
   } else if (sizeof(T) == 4 && blocks(16) >= kMinBlocks) {
     dim3 grid((unsigned)cols, (Na + 15) / 16, O);
-    hipLaunchKernelGGL((k_center_strided<T, M, 16>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift);
+    hipLaunchKernelGGL((k_center_strided<T, M, 16>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift, acc);
   } else {
     dim3 grid((unsigned)cols, (Na + 7) / 8, O);
-    hipLaunchKernelGGL((k_center_strided<T, M, 8>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift);
+    hipLaunchKernelGGL((k_center_strided<T, M, 8>), grid, dim3(256), 0, s, in, out, cf, Na, sa, C, os, shift, acc);
   }
 }
 
 template <typename T>
 void dispatch_strided(int m, const T* in, T* out, const Coef<T>& cf, int Na, long long sa, int C, int O,
-                      long long os, int shift, hipStream_t s) {
+                      long long os, int shift, int acc, hipStream_t s) {
   switch (m) {
 #define PIC_CASE(MM) \
-  case MM: launch_strided<T, MM>(in, out, cf, Na, sa, C, O, os, shift, s); break;
+  case MM: launch_strided<T, MM>(in, out, cf, Na, sa, C, O, os, shift, acc, s); break;
     PIC_CASE(1) PIC_CASE(2) PIC_CASE(3) PIC_CASE(4) PIC_CASE(5) PIC_CASE(6) PIC_CASE(7) PIC_CASE(8)
     PIC_CASE(9) PIC_CASE(10) PIC_CASE(11) PIC_CASE(12) PIC_CASE(13) PIC_CASE(14) PIC_CASE(15) PIC_CASE(16)
 #undef PIC_CASE
@@ -169,13 +171,14 @@ void dispatch_strided(int m, const T* in, T* out, const Coef<T>& cf, int Na, lon
 
 template <typename T>
 void center_axis(const T* in, T* out, int nx, int ny, int nz, int axis, int shift, int m, const double* c,
-                 hipStream_t s) {
+                 hipStream_t s, bool accumulate) {
+  const int acc = accumulate ? 1 : 0;
   Coef<T> cf{};
   for (int n = 0; n < m && n < 16; ++n) cf.c[n] = (T)c[n];
   if (axis == 0) {
-    dispatch_strided<T>(m, in, out, cf, nx, (long long)ny * nz, ny * nz, 1, 0, shift, s);
+    dispatch_strided<T>(m, in, out, cf, nx, (long long)ny * nz, ny * nz, 1, 0, shift, acc, s);
   } else if (axis == 1) {
-    dispatch_strided<T>(m, in, out, cf, ny, nz, nz, nx, (long long)ny * nz, shift, s);
+    dispatch_strided<T>(m, in, out, cf, ny, nz, nz, nx, (long long)ny * nz, shift, acc, s);
   } else {
     const int nlines = nx * ny;
     const int lpb = nz >= 1024 ? 1 : 1024 / nz;
@@ -184,7 +187,7 @@ void center_axis(const T* in, T* out, int nx, int ny, int nz, int axis, int shif
     switch (m) {
 #define PIC_CASE(MM)                                                                                              \
   case MM:                                                                                                        \
-    hipLaunchKernelGGL((k_center_z<T, MM>), grid, dim3(256), lds, s, in, out, cf, nz, nlines, lpb, shift); \
+    hipLaunchKernelGGL((k_center_z<T, MM>), grid, dim3(256), lds, s, in, out, cf, nz, nlines, lpb, shift, acc); \
     break;
       PIC_CASE(1) PIC_CASE(2) PIC_CASE(3) PIC_CASE(4) PIC_CASE(5) PIC_CASE(6) PIC_CASE(7) PIC_CASE(8)
       PIC_CASE(9) PIC_CASE(10) PIC_CASE(11) PIC_CASE(12) PIC_CASE(13) PIC_CASE(14) PIC_CASE(15) PIC_CASE(16)
@@ -194,7 +197,9 @@ void center_axis(const T* in, T* out, int nx, int ny, int nz, int axis, int shif
   }
 }
 
-template void center_axis<float>(const float*, float*, int, int, int, int, int, int, const double*, hipStream_t);
-template void center_axis<double>(const double*, double*, int, int, int, int, int, int, const double*, hipStream_t);
+template void center_axis<float>(const float*, float*, int, int, int, int, int, int, const double*, hipStream_t,
+                                  bool);
+template void center_axis<double>(const double*, double*, int, int, int, int, int, int, const double*, hipStream_t,
+                                   bool);
 
 }  // namespace pic

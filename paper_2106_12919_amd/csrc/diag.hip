@@ -83,6 +83,13 @@ __global__ void __launch_bounds__(256) k_add_into(T* dst, const T* src, long lon
     dst[i] += src[i];
 }
 
+template <typename T>
+__global__ void __launch_bounds__(256) k_zero_arrays(Batch<T*> arrs, long long n) {
+  T* __restrict__ d = arrs.p[blockIdx.y];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    d[i] = (T)0;
+}
+
 }  // namespace
 
 template <typename T>
@@ -103,6 +110,11 @@ void gauss_residual(const PsatdTables<T>& t, const cplx<T>* const E[3], const cp
                      nz, acc);
 }
 template <typename T>
+void zero_arrays(const Batch<T*>& arrs, int count, int64_t n, hipStream_t s) {
+  if (count <= 0 || n <= 0) return;
+  hipLaunchKernelGGL((k_zero_arrays<T>), dim3(512, count), dim3(256), 0, s, arrs, (long long)n);
+}
+template <typename T>
 void add_into(T* dst, const T* src, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL((k_add_into<T>), dim3(2048), dim3(256), 0, s, dst, src, (long long)n);
 }
@@ -115,6 +127,8 @@ template void gauss_residual<float>(const PsatdTables<float>&, const cplx<float>
                                    int, int, int, double*, hipStream_t);
 template void gauss_residual<double>(const PsatdTables<double>&, const cplx<double>* const*, const cplx<double>*, int,
                                     int, int, int, int, double*, hipStream_t);
+template void zero_arrays<float>(const Batch<float*>&, int, int64_t, hipStream_t);
+template void zero_arrays<double>(const Batch<double*>&, int, int64_t, hipStream_t);
 template void add_into<float>(float*, const float*, int64_t, hipStream_t);
 template void add_into<double>(double*, const double*, int64_t, hipStream_t);
 

@@ -26,11 +26,11 @@ struct Fft3D {
 };
 
 // ---------------------------------------------------------------- centering (centering.hip)
-// out = centering of in along ``axis`` at order 2m with coefficients c[n-1] = alpha^s_{m,n}/2.
-// shift = 0: nodes -> cell centres; shift = -1: cell centres -> nodes.
+// out = centering of in along ``axis`` at order 2m with coefficients c[n-1] = alpha^s_{m,n}/2
+// (accumulate: out += it).  shift = 0: nodes -> cell centres; shift = -1: cell centres -> nodes.
 template <typename T>
 void center_axis(const T* in, T* out, int nx, int ny, int nz, int axis, int shift, int m, const double* c,
-                 hipStream_t s);
+                 hipStream_t s, bool accumulate = false);
 
 // ---------------------------------------------------------------- PSATD update (psatd.hip)
 template <typename T>
@@ -223,6 +223,9 @@ template <typename T>
 void sum_plain(const T* arr, int64_t n, double* acc, hipStream_t s);
 template <typename T>
 void add_into(T* dst, const T* src, int64_t n, hipStream_t s);
+// Zeroes count (<= 8) arrays of n elements in one launch.
+template <typename T>
+void zero_arrays(const Batch<T*>& arrs, int count, int64_t n, hipStream_t s);
 // acc[0] += sum |sum_d D-_d E_d - rho|^2, acc[1] += sum |rho|^2 over the half-spectrum modes
 // (index-space spectra of the Yee components E and of rho), weighted as full-spectrum sums.
 template <typename T>
