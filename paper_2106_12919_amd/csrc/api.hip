@@ -502,6 +502,9 @@ pic_status do_center(pic_ctx c, int dir, int what, pic_fields* f, bool accumulat
     for (int d = 0; d < 3; ++d) {
       const int a0 = (d == 0) ? 1 : 0;
       const int a1 = (d == 2) ? 1 : 2;
+      if (a1 == 2 && center_axis_then_z<T>(static_cast<const T*>(f->B_stag[d]), static_cast<T*>(f->B_nod[d]), p.nx,
+                                           p.ny, p.nz, a0, -1, m, cf, c->stream))
+        continue;  // B^x, B^y: both axes in one pass
       center_axis<T>(static_cast<const T*>(f->B_stag[d]), e.tmp, p.nx, p.ny, p.nz, a0, -1, m, cf, c->stream);
       center_axis<T>(e.tmp, static_cast<T*>(f->B_nod[d]), p.nx, p.ny, p.nz, a1, -1, m, cf, c->stream);
     }

@@ -67,6 +67,61 @@ __global__ void __launch_bounds__(256) k_center_strided(const T* __restrict__ in
   }
 }
 
+// Two axes in one pass, for the staggered-to-nodal centering of B^x (y, then z) and B^y (x,
+// then z): a block takes L rows along the strided axis (outer index fixed) for every z,
+// centres them along that axis in registers as k_center_strided does, stages the L centred
+// rows with their periodic z halo in LDS (row q at s[q * W + i] holds z = i + 1 - M + shift_z),
+// then centres along z as k_center_z does.  The same sums in the same order as the two passes,
+// without writing and re-reading the intermediate array.  Grid (row blocks, outer), XCD-major.
+template <typename T, int M, int L>
+__global__ void __launch_bounds__(256) k_center_strided_z(const T* __restrict__ in, T* __restrict__ out, Coef<T> cf,
+                                                          int Na, long long sa, long long outer_stride, int nz,
+                                                          int shift_a, int shift_z) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* s = reinterpret_cast<T*>(smem);
+  constexpr int H = 2 * M - 1;  // halo elements per row
+  constexpr int WIN = L + 2 * M - 1;
+  const int W = nz + H;
+  const int off = M - 1 - shift_z;  // index of z = 0
+  const int lb = xcd_major(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+  const int j0 = (lb % gridDim.x) * L;
+  const size_t obase = (size_t)(lb / gridDim.x) * outer_stride;
+  for (int z = threadIdx.x; z < nz; z += blockDim.x) {
+    T w[WIN];
+#pragma unroll
+    for (int i = 0; i < WIN; ++i) {
+      int row = (j0 - M + 1 + shift_a + i) % Na;
+      if (row < 0) row += Na;
+      w[i] = in[obase + (size_t)row * sa + z];
+    }
+#pragma unroll
+    for (int q = 0; q < L; ++q) {  // rows past Na (a partial last block) are formed but never stored
+      T acc = 0;
+#pragma unroll
+      for (int n = 1; n <= M; ++n) acc += cf.c[n - 1] * (w[q + n + M - 1] + w[q - n + M]);
+      s[q * W + off + z] = acc;
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < L * H; e += blockDim.x) {
+    const int q = e / H, h = e - q * H;
+    const int i = h < off ? h : nz + h;  // below z = 0, or beyond z = nz - 1
+    int z = (i - off) % nz;
+    if (z < 0) z += nz;
+    s[q * W + i] = s[q * W + off + z];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < L * nz; e += blockDim.x) {
+    const int q = e / nz, z = e - q * nz;
+    if (j0 + q >= Na) continue;
+    const T* sl = s + q * W + z;
+    T acc = 0;
+#pragma unroll
+    for (int n = 1; n <= M; ++n) acc += cf.c[n - 1] * (sl[n + M - 1] + sl[M - n]);
+    out[obase + (size_t)(j0 + q) * sa + z] = acc;
+  }
+}
+
 // 16-byte vector of T (four floats or two doubles).
 template <typename T>
 struct Vec16;
@@ -167,7 +222,58 @@ void dispatch_strided(int m, const T* in, T* out, const Coef<T>& cf, int Na, lon
   }
 }
 
+template <typename T, int M, int L>
+void launch_strided_z(const T* in, T* out, const Coef<T>& cf, int Na, long long sa, int O, long long os, int nz,
+                      int shift, hipStream_t s) {
+  const size_t lds = (size_t)L * (nz + 2 * M - 1) * sizeof(T);
+  hipLaunchKernelGGL((k_center_strided_z<T, M, L>), dim3((Na + L - 1) / L, O), dim3(256), lds, s, in, out, cf, Na,
+                     sa, os, nz, shift, shift);
+}
+
+// Rows per block of the fused pass: the longest of 32, 16, 8 (FP64: 8) whose LDS rows fit the
+// default 64 KiB and that still gives two workgroups per compute unit; 0 if none fits.
+template <typename T>
+int strided_z_rows(int m, int Na, int O, int nz) {
+  const int cand[3] = {32, 16, 8};
+  int best = 0;
+  for (int L : cand) {
+    if (sizeof(T) == 8 && L != 8) continue;
+    if ((size_t)L * (nz + 2 * m - 1) * sizeof(T) > 64 * 1024) continue;
+    if (best == 0) best = L;  // the longest that fits
+    if ((long long)((Na + L - 1) / L) * O >= 512) return L;
+  }
+  return best;
+}
+
+template <typename T, int M>
+bool dispatch_strided_z_m(const T* in, T* out, const Coef<T>& cf, int Na, long long sa, int O, long long os, int nz,
+                          int shift, hipStream_t s) {
+  switch (strided_z_rows<T>(M, Na, O, nz)) {
+    case 32: launch_strided_z<T, M, 32>(in, out, cf, Na, sa, O, os, nz, shift, s); return true;
+    case 16: launch_strided_z<T, M, 16>(in, out, cf, Na, sa, O, os, nz, shift, s); return true;
+    case 8: launch_strided_z<T, M, 8>(in, out, cf, Na, sa, O, os, nz, shift, s); return true;
+    default: return false;
+  }
+}
+
 }  // namespace
+
+template <typename T>
+bool center_axis_then_z(const T* in, T* out, int nx, int ny, int nz, int axis, int shift, int m, const double* c,
+                        hipStream_t s) {
+  Coef<T> cf{};
+  for (int n = 0; n < m && n < 16; ++n) cf.c[n] = (T)c[n];
+  const int Na = axis == 0 ? nx : ny, O = axis == 0 ? ny : nx;
+  const long long sa = axis == 0 ? (long long)ny * nz : nz, os = axis == 0 ? nz : (long long)ny * nz;
+  switch (m) {
+#define PIC_CASE(MM) \
+  case MM: return dispatch_strided_z_m<T, MM>(in, out, cf, Na, sa, O, os, nz, shift, s);
+    PIC_CASE(1) PIC_CASE(2) PIC_CASE(3) PIC_CASE(4) PIC_CASE(5) PIC_CASE(6) PIC_CASE(7) PIC_CASE(8)
+    PIC_CASE(9) PIC_CASE(10) PIC_CASE(11) PIC_CASE(12) PIC_CASE(13) PIC_CASE(14) PIC_CASE(15) PIC_CASE(16)
+#undef PIC_CASE
+    default: return false;
+  }
+}
 
 template <typename T>
 void center_axis(const T* in, T* out, int nx, int ny, int nz, int axis, int shift, int m, const double* c,
@@ -201,5 +307,10 @@ template void center_axis<float>(const float*, float*, int, int, int, int, int, 
                                   bool);
 template void center_axis<double>(const double*, double*, int, int, int, int, int, int, const double*, hipStream_t,
                                    bool);
+
+template bool center_axis_then_z<float>(const float*, float*, int, int, int, int, int, int, const double*,
+                                         hipStream_t);
+template bool center_axis_then_z<double>(const double*, double*, int, int, int, int, int, int, const double*,
+                                          hipStream_t);
 
 }  // namespace pic

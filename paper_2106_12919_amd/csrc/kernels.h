@@ -31,6 +31,12 @@ struct Fft3D {
 template <typename T>
 void center_axis(const T* in, T* out, int nx, int ny, int nz, int axis, int shift, int m, const double* c,
                  hipStream_t s, bool accumulate = false);
+// out = centering of in along ``axis`` (0 or 1), then along z, both with ``shift``, in one pass
+// (the same sums in the same order as two center_axis calls).  Returns false, launching
+// nothing, when no row block fits the LDS.
+template <typename T>
+bool center_axis_then_z(const T* in, T* out, int nx, int ny, int nz, int axis, int shift, int m, const double* c,
+                        hipStream_t s);
 
 // ---------------------------------------------------------------- PSATD update (psatd.hip)
 template <typename T>
