@@ -103,7 +103,7 @@ def stage_bytes(stage, N, M, Np, s):
         "center_s2n": 12 * N * s,      # 6 staggered components in, 6 nodal out
         "gather_push": 6 * N * s + Np * part_rw,
         "deposit": Np * part_r,        # particles read; the per-tile boxes are not algorithmic
-        "deposit_reduce": 4 * N * s,   # rho, J written once
+        "deposit_reduce": 5 * N * s,   # rho, J written once; the static ion background read once
         "center_n2s": 6 * N * s,       # 3 in, 3 out
         "fft_forward": 4 * (N * s + M * 2 * s),          # J (3) and rho: real in, half spectrum out
         "psatd_update": M * (11 * 2 * s + 5 * s + 6 * 2 * s),  # 11 spectra + 5 tables in, 6 out
@@ -111,7 +111,7 @@ def stage_bytes(stage, N, M, Np, s):
         "entry_forward": 7 * (N * s + M * 2 * s),
         "exit_inverse": 6 * (M * 2 * s + N * s),
         "tile_sort": Np * 12,          # cell read twice (count, rank), slot written
-        "clear_sources": 4 * N * s,    # rho <- static background, J <- 0
+        "clear_sources": 0,            # only what no species wrote (the first species' reduction overwrites)
     }[stage]
 
 
@@ -403,7 +403,7 @@ def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0, v_gal=(0.0,
         avg = ms / cnt
         b = stage_bytes(name, N, M, Np, s)
         breakdown[name] = {"ms_avg": round(avg, 5), "launches": cnt, "algo_bytes": b,
-                           "GBps": round(b / (avg * 1e-3) / 1e9, 1)}
+                           "GBps": round(b / (avg * 1e-3) / 1e9, 1) if avg > 0 else None}
     dom = max((k for k in breakdown if k not in ("entry_forward", "exit_inverse")),
               key=lambda k: breakdown[k]["ms_avg"] * breakdown[k]["launches"])
     d = breakdown[dom]
