@@ -352,6 +352,7 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
   // 4 * 13^3 * 8 B = 70 KiB (FP64, cubic); the gather box 13^3 nodes * 6 components
   const GridGeom g = make_geom(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order);
   e.tiles = make_tiles(g);
+  if ((err = e.alloc(&e.tiles.scan_tmp, (size_t)(e.tiles.ntiles + 1) / 8192 + 2)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_counts, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_starts, (size_t)e.tiles.ntiles + 2)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_cursor, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;

@@ -107,6 +107,7 @@ struct SpeciesView {
 };
 struct TileGeom {
   int ntx, nty, ntz, ntiles;
+  int* scan_tmp = nullptr;  // device scratch of the bucket scan: (ntiles + 1) / 8192 + 2 ints
 };
 TileGeom make_tiles(const GridGeom& g);  // tiles of kTile^3 cells
 // Edge length (nodes) of the LDS boxes of one tile: the tile, the shape support and a

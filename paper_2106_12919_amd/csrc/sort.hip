@@ -143,7 +143,61 @@ __global__ void __launch_bounds__(kSortBlock) k_tile_rank_lds(GridGeom g, TileGe
   }
 }
 
-// Exclusive scan of counts[0..m) into starts[0..m] and cursor[0..m), one block.
+// Exclusive scan of counts[0..m) into starts[0..m] (starts[m] = the total) and cursor[0..m)
+// by blocks of 1024 threads, in chunks of 1024 x 8 entries: thread t takes the 8 adjacent
+// entries at the chunk's base + 8 t (the block's loads and stores cover contiguous memory),
+// and the block scans the thread sums (a scan within each wave, then over the 16 wave totals).
+constexpr int kScanPer = 8;
+constexpr int kScanChunk = 1024 * kScanPer;
+constexpr int kScanWaves = 1024 / 64;
+
+// One chunk from ``carry`` (the sum of everything before it); returns the chunk's total.
+// Every thread of the block calls it.
+__device__ inline int scan_chunk(const int* __restrict__ counts, int* starts, int* cursor, int m, int base, int carry,
+                                 int* wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i0 = base + tid * kScanPer;
+  int v[kScanPer];
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    v[k] = (i0 + k < m) ? counts[i0 + k] : 0;
+    s += v[k];
+  }
+  int x = s;  // inclusive scan of the thread sums within the wave
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  if (wave == 0) {  // inclusive scan of the wave totals
+    int w = lane < kScanWaves ? wsum[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < kScanWaves; o <<= 1) {
+      const int y = __shfl_up(w, o, 64);
+      if (lane >= o) w += y;
+    }
+    if (lane < kScanWaves) wsum[lane] = w;
+  }
+  __syncthreads();
+  int run = carry + (wave > 0 ? wsum[wave - 1] : 0) + x - s;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    if (i0 + k < m) {
+      starts[i0 + k] = run;
+      cursor[i0 + k] = run;
+      run += v[k];
+    }
+  }
+  const int total = wsum[kScanWaves - 1];
+  __syncthreads();  // wsum is rewritten by the next chunk
+  return total;
+}
+
+// Up to one chunk (m <= kScanChunk), one block: thread t scans its own run of at most 8
+// adjacent entries serially, the block scans the run totals.
 __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ counts, int* starts, int* cursor, int m) {
   __shared__ int part[1024];
   const int tid = threadIdx.x;
@@ -159,13 +213,69 @@ __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ counts, i
     part[tid] += v;
     __syncthreads();
   }
-  int run = part[tid] - s;  // exclusive prefix of this chunk
+  int run = part[tid] - s;  // exclusive prefix of this run
   for (int i = lo; i < hi; ++i) {
     starts[i] = run;
     cursor[i] = run;
     run += counts[i];
   }
   if (tid == blockDim.x - 1) starts[m] = part[tid];
+}
+
+// Large m, first of three launches: sums[b] = the total of chunk b.
+__global__ void __launch_bounds__(1024) k_scan_sums(const int* __restrict__ counts, int m, int* sums) {
+  __shared__ int wsum[kScanWaves];
+  const int base = blockIdx.x * kScanChunk, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const int i = base + k * 1024 + (int)threadIdx.x;
+    if (i < m) s += counts[i];
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) wsum[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < kScanWaves; ++w) t += wsum[w];
+    sums[blockIdx.x] = t;
+  }
+}
+
+// Second launch (one block, nb <= 1024): sums -> their exclusive scan in place; *total = the sum.
+__global__ void __launch_bounds__(1024) k_scan_offsets(int* sums, int nb, int* total) {
+  __shared__ int wsum[kScanWaves];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int v = tid < nb ? sums[tid] : 0;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  int before = 0;
+  for (int w = 0; w < wave; ++w) before += wsum[w];
+  if (tid < nb) sums[tid] = before + x - v;
+  if (tid == 1023) *total = before + x;
+}
+
+// One block over every chunk in turn (the fallback without scratch).
+__global__ void __launch_bounds__(1024) k_scan_apply_serial(const int* __restrict__ counts, int* starts, int* cursor,
+                                                            int m) {
+  __shared__ int wsum[kScanWaves];
+  int carry = 0;
+  for (int base = 0; base < m; base += kScanChunk) carry += scan_chunk(counts, starts, cursor, m, base, carry, wsum);
+  if (threadIdx.x == 0) starts[m] = carry;
+}
+
+// Third launch: block b scans chunk b from its offset.
+__global__ void __launch_bounds__(1024) k_scan_apply(const int* __restrict__ counts, int* starts, int* cursor, int m,
+                                                     const int* __restrict__ offsets) {
+  __shared__ int wsum[kScanWaves];
+  (void)scan_chunk(counts, starts, cursor, m, blockIdx.x * kScanChunk, offsets[blockIdx.x], wsum);
 }
 
 // For every destination tile D of the new grouping: the slot runs of the particles that
@@ -239,6 +349,25 @@ TileGeom make_tiles(const GridGeom& g) {
   return t;
 }
 
+// The exclusive scan of the ntiles + 1 bucket counts: one block for up to one chunk, else
+// the three-launch form through t.scan_tmp (up to 1024 chunks: every grid pic_init accepts).
+void scan_buckets(const TileGeom& t, const int* counts, int* starts, int* cursor, hipStream_t s) {
+  const int m = t.ntiles + 1;
+  const int nb = (m + kScanChunk - 1) / kScanChunk;
+  if (nb <= 1) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, starts, cursor, m);
+    return;
+  }
+  if (nb > 1024 || !t.scan_tmp) {  // not reached through pic_init: a chunk per block in turn would be needed
+    hipLaunchKernelGGL(k_scan_apply_serial, dim3(1), dim3(1024), 0, s, counts, starts, cursor, m);
+    return;
+  }
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(1024), 0, s, counts, m, t.scan_tmp);
+  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, s, t.scan_tmp, nb, starts + m);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, s, counts, starts, cursor, m,
+                     (const int*)t.scan_tmp);
+}
+
 void tile_sort(const GridGeom& g, const TileGeom& t, const int32_t* cell, int64_t n, int* counts, int* starts,
                int* cursor, int* dst, int* bad, hipStream_t s) {
   // buckets 0..ntiles-1 are tiles, bucket ntiles collects invalid cells
@@ -252,7 +381,7 @@ void tile_sort(const GridGeom& g, const TileGeom& t, const int32_t* cell, int64_
     }
     if (n > 0)
       hipLaunchKernelGGL(k_tile_count_lds, dim3(nbl), dim3(kSortBlock), lds, s, g, t, cell, (long long)n, counts);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, starts, cursor, t.ntiles + 1);
+    scan_buckets(t, counts, starts, cursor, s);
     if (n > 0)
       hipLaunchKernelGGL(k_tile_rank_lds, dim3(nbl), dim3(kSortBlock), lds, s, g, t, cell, (long long)n, cursor, dst,
                          bad);
@@ -260,12 +389,12 @@ void tile_sort(const GridGeom& g, const TileGeom& t, const int32_t* cell, int64_
   }
   const unsigned nb = (unsigned)((n + 255) / 256);
   if (n > 0) hipLaunchKernelGGL(k_tile_count, dim3(nb), dim3(256), 0, s, g, t, cell, (long long)n, counts);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, starts, cursor, t.ntiles + 1);
+  scan_buckets(t, counts, starts, cursor, s);
   if (n > 0) hipLaunchKernelGGL(k_tile_rank, dim3(nb), dim3(256), 0, s, g, t, cell, (long long)n, cursor, dst, bad);
 }
 
 void scan_counts(const TileGeom& t, const int* counts, int* starts, int* cursor, hipStream_t s) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, starts, cursor, t.ntiles + 1);
+  scan_buckets(t, counts, starts, cursor, s);
 }
 
 void neighbour_bases(const TileGeom& t, const int* old_starts, const int* nbr_counts, const int* new_starts,
