@@ -196,8 +196,8 @@ __device__ inline int scan_chunk(const int* __restrict__ counts, int* starts, in
   return total;
 }
 
-// Up to one chunk (m <= kScanChunk), one block: thread t scans its own run of at most 8
-// adjacent entries serially, the block scans the run totals.
+// Up to two chunks (m <= 2 kScanChunk), one block: thread t scans its own run of at most 16
+// adjacent entries serially, the block scans the run totals (one launch beats three there).
 __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ counts, int* starts, int* cursor, int m) {
   __shared__ int part[1024];
   const int tid = threadIdx.x;
@@ -349,12 +349,12 @@ TileGeom make_tiles(const GridGeom& g) {
   return t;
 }
 
-// The exclusive scan of the ntiles + 1 bucket counts: one block for up to one chunk, else
+// The exclusive scan of the ntiles + 1 bucket counts: one block for up to two chunks, else
 // the three-launch form through t.scan_tmp (up to 1024 chunks: every grid pic_init accepts).
 void scan_buckets(const TileGeom& t, const int* counts, int* starts, int* cursor, hipStream_t s) {
   const int m = t.ntiles + 1;
   const int nb = (m + kScanChunk - 1) / kScanChunk;
-  if (nb <= 1) {
+  if (nb <= 2) {
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, starts, cursor, m);
     return;
   }
