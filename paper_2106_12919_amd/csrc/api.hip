@@ -142,6 +142,7 @@ struct Engine : EngineBase {
   // say whether a deposition spilled, and the count of depositions that chose between them
   T* spill[4] = {nullptr, nullptr, nullptr, nullptr};
   int* spill_flag = nullptr;
+  int* box_faces = nullptr;  // per tile, the outer faces of its deposition box that were staged
   unsigned dep_k = 0;
   std::vector<SpeciesScratch<T>> sps;
   cplx<T>* Eh[3] = {nullptr, nullptr, nullptr};
@@ -353,6 +354,7 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
   const GridGeom g = make_geom(p.nx, p.ny, p.nz, p.dx, p.dy, p.dz, p.dt, p.shape_order);
   e.tiles = make_tiles(g);
   if ((err = e.alloc(&e.tiles.scan_tmp, (size_t)(e.tiles.ntiles + 1) / 8192 + 2)) != hipSuccess) return err;
+  if ((err = e.alloc(&e.box_faces, (size_t)e.tiles.ntiles)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_counts, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_starts, (size_t)e.tiles.ntiles + 2)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_cursor, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;
@@ -553,6 +555,7 @@ struct SourceSum {
     ra.acc_mask = (rho_done ? 1 : 0) | (j_done ? 2 : 0);
     ra.base = rho_done ? nullptr : static_cast<const T*>(f->rho_static);
     for (int q = 0; q < 4; ++q) ra.spill[q] = e.spill[q];
+    ra.box_faces = e.box_faces;
     ra.flag = flag;
     ra.next_flag = e.spill_flag + ((e.dep_k + 1u) & 1u);
     ++e.dep_k;
@@ -633,7 +636,7 @@ pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, 
     const bool mobile = std::isfinite(sp[s].m);
     int* flag = sum.begin();
     deposit_tiled<T>(g, e.tiles, v, x.perm, e.t_starts, with_j && mobile, e.stage, c->d_bad, nullptr, nullptr, e.work,
-                     sum.spill_rho(), sum.spill_j(), c->stream, flag);
+                     sum.spill_rho(), sum.spill_j(), c->stream, flag, e.box_faces);
     deposit_reduce<T>(g, e.tiles, e.t_starts, e.stage, with_j && mobile, static_cast<T*>(f->rho_new), J, c->stream,
                       sum.reduce_args(with_j && mobile));
   }
@@ -998,7 +1001,7 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
         {
           StageScope sc(c, ST_DEPOSIT);  // positions moved < 1 cell: the grouping still holds them
           deposit_tiled<T>(g, e.tiles, v, x.perm, x.starts[0], mobile, e.stage, c->d_bad, nullptr, nullptr, e.work,
-                           sum.spill_rho(), sum.spill_j(), c->stream, sum.begin());
+                           sum.spill_rho(), sum.spill_j(), c->stream, sum.begin(), e.box_faces);
         }
         {
           StageScope sc(c, ST_REDUCE);
@@ -1043,7 +1046,8 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
         StageScope sc(c, ST_DEPOSIT);
         int* nextc = mobile ? x.counts[first ? 1 : L] : nullptr;
         deposit_tiled<T>(g, e.tiles, dep, nullptr, dep_starts, mobile, e.stage, c->d_bad, nextc,
-                         mobile ? x.nbr : nullptr, e.work, sum.spill_rho(), sum.spill_j(), c->stream, sum.begin());
+                         mobile ? x.nbr : nullptr, e.work, sum.spill_rho(), sum.spill_j(), c->stream, sum.begin(),
+                         e.box_faces);
       }
       {
         StageScope sc(c, ST_REDUCE);

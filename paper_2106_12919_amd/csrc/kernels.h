@@ -154,11 +154,14 @@ void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const 
 // and, when nbr_counts != nullptr, per tile t of this grouping and neighbour nb of t
 // (0..26, the tile offsets in {-1,0,1}^3 in x-major order) into nbr_counts[27 t + nb].
 // ``work`` is one int of device scratch (the tile counter of the persistent launch).
-// ``spill_flag`` (optional) is set to 1 whenever a particle goes to rho/J directly.
+// ``spill_flag`` (optional) is set to 1 whenever a particle goes to rho/J directly.  With
+// ``box_faces`` (ntiles ints, optional; used on grids of whole tiles) each tile stages only
+// the layers of its box that hold a nonzero value and records which outer faces it staged,
+// for a deposit_reduce with the same array in ReduceArgs::box_faces.
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
                    bool with_j, T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, T* rho,
-                   T* const J[3], hipStream_t s, int* spill_flag = nullptr);
+                   T* const J[3], hipStream_t s, int* spill_flag = nullptr, int* box_faces = nullptr);
 // How deposit_reduce starts each node and what else it folds in.  By default it adds to the
 // nodal arrays.  With bit 0 (rho) or bit 1 (J) of acc_mask clear it overwrites them instead,
 // rho starting from ``base`` when given, else from zero.  When *flag != 0, the ``spill``
@@ -171,6 +174,7 @@ struct ReduceArgs {
   T* spill[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   const int* flag = nullptr;
   int* next_flag = nullptr;
+  const int* box_faces = nullptr;  // per tile, the outer faces its deposition staged (null: all)
   __device__ T start(int q, const T* o, size_t idx) const {
     if (acc_mask & (q == 0 ? 1 : 2)) return o[idx];
     return (q == 0 && base) ? base[idx] : (T)0;

@@ -870,6 +870,7 @@ struct DepositLds {
   int cnt[27];
   int wtot[kWaves];
   int next_tile;
+  int cross;  // faces of the box holding a nonzero value (see deposit_tile)
   __align__(16) int hist[O::KG];
   unsigned short kr[O::CH];
   unsigned short order[O::CH];
@@ -882,7 +883,7 @@ template <typename T, int ORDER, bool WJ>
 __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom& tg, const SpeciesView<T>& sp,
                                     const int* __restrict__ perm, const int* __restrict__ starts,
                                     const Batch<T*>& out, T* __restrict__ stage, T qdv, T hdtx, T hdty, T hdtz,
-                                    int* bad, int* next_counts, int* nbr_counts, int* spill_flag,
+                                    int* bad, int* next_counts, int* nbr_counts, int* spill_flag, int* box_faces,
                                     typename Fixed<T>::acc_t* box, DepositLds<T>& L) {
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
@@ -966,6 +967,7 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
   }
   for (int k = threadIdx.x; k < ncomp * X::B3; k += blockDim.x) box[k] = 0;
   if (threadIdx.x < 27) cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) L.cross = 0;  // read only after the chunk loop's barriers
   for (int cb = beg; cb < end; cb += O::CH) {
     const int nc = min(O::CH, end - cb);
     if (threadIdx.x < O::KG) hist[threadIdx.x] = 0;
@@ -1089,20 +1091,53 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
     if (n > 0) atomicAdd(&next_counts[neighbour_key(threadIdx.x, ti, tj, tk, tg)], n);
     if (nbr_counts) nbr_counts[27 * tile + threadIdx.x] = n;
   }
-  // the whole box goes to this tile's staging slot (plain stores, zeros included)
-  T* dstage = stage + (size_t)tile * ncomp * X::B3;
-  if constexpr (PACK) {
-    const unsigned long long* xy = reinterpret_cast<const unsigned long long*>(box);
-    for (int e = threadIdx.x; e < X::B3; e += blockDim.x) {
-      int jx, jy;
-      unpack_xy(xy[e], jx, jy);
-      dstage[e] = ldexp((T)rbox[e], -shs[0]);
-      dstage[X::B3 + e] = ldexp((T)jx, -shs[1]);
-      dstage[2 * X::B3 + e] = ldexp((T)jy, -shs[2]);
-      dstage[3 * X::B3 + e] = ldexp((T)box[2 * X::B3 + e], -shs[3]);
+  // Only particles that left the tile since the grouping reach the outermost layers of the
+  // box (in-tile particles touch layers 1 .. B - 2), so with box_faces the tile stages only
+  // the x and y layers that hold a nonzero value: bit f of its face mask (faces x-, y-, z- at
+  // layer 0, then at layer B - 1) is set when face f does, and the reduction reads nothing
+  // outside.  z rows are always staged whole (their ends share memory sectors with the rest).
+  int faces = 0x3F;
+  if (box_faces) {
+    int mine = 4 | 32;  // faces this thread found nonzero, then OR-reduced over the wave: one atomic per wave
+    for (int e = threadIdx.x; e < 4 * X::B2; e += blockDim.x) {
+      const int k = e / X::B2, uv = e - k * X::B2, u = uv / X::B, v = uv - u * X::B;
+      const int f = (k & 1) + 3 * (k >> 1);  // x-, y-, x+, y+
+      const int l = k < 2 ? 0 : X::B - 1;
+      const int n = (k & 1) == 0 ? X::at(l, u, v) : X::at(u, l, v);
+      bool nz = rbox[n] != 0;
+      if (WJ) {
+        if constexpr (PACK)
+          nz = nz || reinterpret_cast<const unsigned long long*>(box)[n] != 0ull || box[2 * X::B3 + n] != 0;
+        else
+          nz = nz || box[X::B3 + n] != 0 || box[2 * X::B3 + n] != 0 || box[3 * X::B3 + n] != 0;
+      }
+      if (nz) mine |= 1 << f;
     }
-  } else {
-    for (int k = threadIdx.x; k < ncomp * X::B3; k += blockDim.x) dstage[k] = ldexp((T)box[k], -shs[k / X::B3]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mine |= __shfl_xor(mine, o, 64);
+    if ((threadIdx.x & 63) == 0 && mine) atomicOr(&L.cross, mine);
+    __syncthreads();
+    faces = L.cross;
+    if (threadIdx.x == 0) box_faces[tile] = faces;
+  }
+  const int lo[3] = {(faces & 1) ? 0 : 1, (faces & 2) ? 0 : 1, (faces & 4) ? 0 : 1};
+  const int hi[3] = {(faces & 8) ? X::B - 1 : X::B - 2, (faces & 16) ? X::B - 1 : X::B - 2,
+                     (faces & 32) ? X::B - 1 : X::B - 2};
+  T* dstage = stage + (size_t)tile * ncomp * X::B3;
+  for (int n = threadIdx.x; n < X::B3; n += blockDim.x) {
+    const int lx = n / X::B2, ly = (n / X::B) % X::B, lz = n % X::B;
+    if (lx < lo[0] || lx > hi[0] || ly < lo[1] || ly > hi[1] || lz < lo[2] || lz > hi[2]) continue;
+    dstage[n] = ldexp((T)rbox[n], -shs[0]);
+    if constexpr (PACK) {
+      int jx, jy;
+      unpack_xy(reinterpret_cast<const unsigned long long*>(box)[n], jx, jy);
+      dstage[X::B3 + n] = ldexp((T)jx, -shs[1]);
+      dstage[2 * X::B3 + n] = ldexp((T)jy, -shs[2]);
+      dstage[3 * X::B3 + n] = ldexp((T)box[2 * X::B3 + n], -shs[3]);
+    } else if (WJ) {
+#pragma unroll
+      for (int q = 1; q < 4; ++q) dstage[q * X::B3 + n] = ldexp((T)box[q * X::B3 + n], -shs[q]);
+    }
   }
 }
 
@@ -1116,7 +1151,8 @@ template <typename T, int ORDER, bool WJ>
 __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK, sizeof(T) == 4 ? (ORDER == 3 ? 3 : 4) : 1)
     k_deposit_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp, const int* __restrict__ perm,
                     const int* __restrict__ starts, Batch<T*> out, T* __restrict__ stage, T qdv, T hdtx, T hdty,
-                    T hdtz, int* bad, int* next_counts, int* nbr_counts, int* work, int* spill_flag) {
+                    T hdtz, int* bad, int* next_counts, int* nbr_counts, int* work, int* spill_flag,
+                    int* box_faces) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ DepositLds<T> L;
   auto* box = reinterpret_cast<typename Fixed<T>::acc_t*>(smem);
@@ -1128,11 +1164,11 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK, sizeof(T) == 4 ? (ORDER == 
       __syncthreads();
       if (tile > tg.ntiles) break;
       deposit_tile<T, ORDER, WJ>(tile, g, tg, sp, perm, starts, out, stage, qdv, hdtx, hdty, hdtz, bad, next_counts,
-                                 nbr_counts, spill_flag, box, L);
+                                 nbr_counts, spill_flag, box_faces, box, L);
     }
   } else {
     deposit_tile<T, ORDER, WJ>(blockIdx.x, g, tg, sp, perm, starts, out, stage, qdv, hdtx, hdty, hdtz, bad,
-                               next_counts, nbr_counts, spill_flag, box, L);
+                               next_counts, nbr_counts, spill_flag, box_faces, box, L);
   }
 }
 
@@ -1170,7 +1206,8 @@ __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGe
                                                               const T* __restrict__ stage, Batch<T*> out,
                                                               ReduceArgs<T> ra) {
   using X = Box<Shape<T, ORDER>::NW>;
-  __shared__ unsigned char occ[4][kMaxTilesZ];  // occupancy of the row's (x, y) candidate tiles, by tz
+  // per candidate tile of the row, by tz: 0 if empty, else 1 + 2 x its face mask
+  __shared__ unsigned char occ[4][kMaxTilesZ];
   if (ra.next_flag && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *ra.next_flag = 0;
   // grid (z blocks, ny, nx) flattened and renumbered XCD-major: rows next to each other
   // read the same staging lines
@@ -1189,7 +1226,8 @@ __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGe
     const int a = ab >> 1, b = ab & 1;
     if (a < nxc && b < nyc) {
       const int tile = (tx[a] * tg.nty + ty[b]) * tg.ntz + t3;
-      occ[ab][t3] = starts[tile] != starts[tile + 1];
+      occ[ab][t3] = starts[tile] != starts[tile + 1] ? (unsigned char)(1 + 2 * (ra.box_faces ? ra.box_faces[tile] : 0x3F))
+                                                     : (unsigned char)0;
     }
   }
   __syncthreads();
@@ -1210,7 +1248,11 @@ __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGe
     const bool present = a < nxc && b < nyc && c < nzc;
     const int ia = present ? a : 0, ib = present ? b : 0, ic = present ? c : 0;
     const int tile = (tx[ia] * tg.nty + ty[ib]) * tg.ntz + tz[ic];
-    use[m] = present && occ[2 * ia + ib][tz[ic]];
+    const int o = occ[2 * ia + ib][tz[ic]];
+    const int f = o >> 1;  // the staged layers: 1 .. B - 2, plus the faces in f
+    const bool in = (lx[ia] > 0 || (f & 1)) && (lx[ia] < X::B - 1 || (f & 8)) && (ly[ib] > 0 || (f & 2)) &&
+                    (ly[ib] < X::B - 1 || (f & 16)) && (lz[ic] > 0 || (f & 4)) && (lz[ic] < X::B - 1 || (f & 32));
+    use[m] = present && (o & 1) && in;
     sb[m] = stage + (size_t)tile * NCOMP * X::B3 + X::at(lx[ia], ly[ib], lz[ic]);
   }
   T v[8][NCOMP];
@@ -2136,7 +2178,7 @@ int resident_blocks(const void* kernel, int block, size_t lds) {
 template <typename T, int ORDER, bool WJ>
 void launch_deposit(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
                     T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, int* spill_flag,
-                    const Batch<T*>& out, hipStream_t s) {
+                    int* box_faces, const Batch<T*>& out, hipStream_t s) {
   const T qdv = (T)(sp.q / (g.dx * g.dy * g.dz));
   const T hx = (T)(0.5 * g.dt / g.dx), hy = (T)(0.5 * g.dt / g.dy), hz = (T)(0.5 * g.dt / g.dz);
   constexpr int B = Box<Shape<T, ORDER>::NW>::B;
@@ -2151,23 +2193,25 @@ void launch_deposit(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& 
     (void)hipMemsetAsync(work, 0, sizeof(int), s);
   }
   hipLaunchKernelGGL((k_deposit_tiled<T, ORDER, WJ>), dim3(nb), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm,
-                     starts, out, stage, qdv, hx, hy, hz, bad, next_counts, nbr_counts, work, spill_flag);
+                     starts, out, stage, qdv, hx, hy, hz, bad, next_counts, nbr_counts, work, spill_flag, box_faces);
 }
 
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
                    bool with_j, T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, T* rho,
-                   T* const J[3], hipStream_t s, int* spill_flag) {
+                   T* const J[3], hipStream_t s, int* spill_flag, int* box_faces) {
   if (sp.n <= 0) return;
+  // the face masks serve the whole-tile reduction only; the other one reads whole boxes
+  if (!(g.nx % kTile == 0 && g.ny % kTile == 0 && g.nz % kTile == 0)) box_faces = nullptr;
   Batch<T*> out{};
   out.p[0] = rho;
   for (int d = 0; d < 3; ++d) out.p[1 + d] = J ? J[d] : nullptr;
   if (g.shape_order == 1) {
-    if (with_j) launch_deposit<T, 1, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, out, s);
-    else launch_deposit<T, 1, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, out, s);
+    if (with_j) launch_deposit<T, 1, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, box_faces, out, s);
+    else launch_deposit<T, 1, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, box_faces, out, s);
   } else {
-    if (with_j) launch_deposit<T, 3, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, out, s);
-    else launch_deposit<T, 3, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, out, s);
+    if (with_j) launch_deposit<T, 3, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, box_faces, out, s);
+    else launch_deposit<T, 3, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, box_faces, out, s);
   }
 }
 
@@ -2359,7 +2403,7 @@ void deposit_yee(const GridGeom& g, const SpeciesView<T>& sp, bool with_j, T* rh
 #define PIC_INST(T)                                                                                              \
   template void permute_species<T>(const SpeciesView<T>&, const SpeciesView<T>&, const int*, hipStream_t);       \
   template void deposit_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*, const int*, \
-                                 bool, T*, int*, int*, int*, int*, T*, T* const*, hipStream_t, int*);            \
+                                 bool, T*, int*, int*, int*, int*, T*, T* const*, hipStream_t, int*, int*);      \
   template void deposit_reduce<T>(const GridGeom&, const TileGeom&, const int*, const T*, bool, T*, T* const*,   \
                                   hipStream_t, const ReduceArgs<T>&);                                            \
   template void gather_push_tiled<T>(const GridGeom&, const TileGeom&, const T* const*, const T* const*,         \
