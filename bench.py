@@ -52,6 +52,8 @@ def deposit_lds_floor_ms(Np, shape_order, dtype):
     u64, u32 = (nodes, 2 * nodes) if dtype == "f32" else (4 * nodes, 0)
     clocks_per_cu = Np * (u64 / LDS_U64_LANE_OPS + u32 / LDS_U32_LANE_OPS) / CUS
     return clocks_per_cu / CLOCK_HZ * 1e3
+
+
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "laser128_f32_hbm_traffic.md")
 
 
@@ -78,6 +80,7 @@ def recorded_traffic(stage):
     if rec.get("source_sha256") != kernel_source_hash():
         return None
     return rec.get("traffic_bytes_per_launch", {}).get(stage)
+
 
 CONFIG_TEXT = {
     "laser128": "laser128: 128x128x256 periodic, laser a0=2 lambda=16 waist=20 fwhm=30 into 2 ppc cold plasma "

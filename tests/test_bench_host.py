@@ -1,0 +1,46 @@
+"""Host logic of bench.py (no GPU): the refusal of more than one GPU, the algorithmic byte table,
+the LDS-atomic floor of the deposition and the gating of the recorded HBM traffic on the kernel
+sources."""
+
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in r.stdout + r.stderr
+
+
+def test_algorithmic_bytes():
+    N, M, Np, s = 8 * 8 * 8, 8 * 8 * 5, 100, 4
+    assert bench.stage_bytes("psatd_update", N, M, Np, s) == 39 * s * M  # 11 spectra + 5 tables in, 6 out
+    assert bench.stage_bytes("deposit_reduce", N, M, Np, s) == 5 * N * s
+    assert bench.stage_bytes("clear_sources", N, M, Np, s) == 0
+    assert bench.stage_bytes("fft_inverse", N, M, Np, s) == 6 * (2 * s * M + s * N)
+
+
+def test_lds_atomic_floor():
+    # cubic FP32: 64 64-bit and 128 32-bit lane operations per particle, 256 CUs at 2.4 GHz
+    per_cu = 1000
+    expected = per_cu * (64 / bench.LDS_U64_LANE_OPS + 128 / bench.LDS_U32_LANE_OPS) / 2.4e9 * 1e3
+    assert bench.deposit_lds_floor_ms(256 * per_cu, 3, "f32") == pytest.approx(expected)
+    # FP64 (CIC): four 64-bit words per node, 8 nodes
+    assert bench.deposit_lds_floor_ms(256, 1, "f64") == pytest.approx(32 / bench.LDS_U64_LANE_OPS / 2.4e9 * 1e3)
+
+
+def test_recorded_traffic_is_gated_on_the_kernel_sources(monkeypatch):
+    v = bench.recorded_traffic("deposit")
+    assert v is None or v > 0
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
+    assert bench.recorded_traffic("deposit") is None
