@@ -269,6 +269,15 @@ pic_status pic_diagnostics(pic_ctx ctx, const pic_fields* f, double out[2]);
  * E.  Uses the context's k-space scratch (not during another call on the same context). */
 pic_status pic_gauss_residual(pic_ctx ctx, const pic_fields* f, double* out);
 
+/* Continuity residual of a step's sources (synchronous; FP64 accumulation): *out =
+ * || (rho_hat^{n+1} - rho_hat^n) / dt + i [k]_s . J_hat || / || (rho_hat^{n+1} - rho_hat^n) / dt ||
+ * over all modes, in the paper's Fourier convention (App. A), from rho_old = rho^n, rho_new =
+ * rho^{n+1} and J_stag = J^{n+1/2} on the Yee grid (with PIC_NODAL_SOLVER: [k]_c and J_nod).  The
+ * direct deposition of Sec. 2 does not conserve charge, so this is a reported quantity, not zero;
+ * the field solve of Sec. 4.2 keeps Gauss's law exactly when it is zero.  (|| . || alone when rho
+ * does not change.)  Uses the context's k-space scratch (not during another call on the context). */
+pic_status pic_continuity_residual(pic_ctx ctx, const pic_fields* f, double* out);
+
 /* Per-stage timing with HIP events on the context stream.  When enabled, each
  * stage launch of pic_step is bracketed by events; pic_stage_times returns, for
  * stage s < nstage, the accumulated milliseconds and the number of launches since

@@ -7,6 +7,8 @@ Test infrastructure only (see ``oracle/__init__``).
 * total charge sum_i rho_i dV;
 * Gauss residual || [k]_s . E_hat + i rho_hat / eps0 || / || rho_hat / eps0 ||
   (App. A, Gauss's law used in the derivation of the update);
+* continuity residual || (rho_hat^{n+1} - rho_hat^n)/dt + i [k]_s . J_hat || / || (rho_hat^{n+1} - rho_hat^n)/dt ||
+  (App. A convention; the direct deposition of Sec. 2 does not make it zero);
 * stencil extent Gamma of a PSATD coefficient along an axis (Sec. 2 item (ii),
   eq. ``eq_stencil_extent``).
 """
@@ -14,7 +16,7 @@ Test infrastructure only (see ``oracle/__init__``).
 import numpy as np
 
 from . import psatd, transforms
-from .transforms import E_NAMES, OFFSETS
+from .transforms import E_NAMES, J_NAMES, OFFSETS
 
 EPS0 = 1.0
 MU0 = 1.0
@@ -52,6 +54,23 @@ def gauss_residual(E_stag, rho, spacing, psatd_order, nodal=False):
     div = ks[0] * Eh[0] + ks[1] * Eh[1] + ks[2] * Eh[2]
     res = div + 1j * rh / EPS0
     den = np.sqrt(np.sum(np.abs(rh / EPS0) ** 2))
+    num = np.sqrt(np.sum(np.abs(res) ** 2))
+    return float(num / den) if den > 0 else float(num)
+
+
+def continuity_residual(J, rho_old, rho_new, spacing, dt, psatd_order, nodal=False):
+    """Relative continuity residual of J^{n+1/2} (Yee grid; ``nodal``: at the nodes with [k]_c)
+    between rho^n and rho^{n+1} on the nodes, in the paper's Fourier convention (App. A)."""
+    shape = rho_old.shape
+    if nodal:
+        ks = psatd.centered_wave_vector(shape, spacing, psatd_order)
+        Jh = [transforms.forward(J[d], spacing, (0.0, 0.0, 0.0)) for d in range(3)]
+    else:
+        ks = psatd.staggered_wave_vector(shape, spacing, psatd_order)
+        Jh = [transforms.forward(J[d], spacing, OFFSETS[J_NAMES[d]]) for d in range(3)]
+    drho = (transforms.forward(rho_new, spacing, OFFSETS["rho"]) - transforms.forward(rho_old, spacing, OFFSETS["rho"])) / dt
+    res = drho + 1j * (ks[0] * Jh[0] + ks[1] * Jh[1] + ks[2] * Jh[2])
+    den = np.sqrt(np.sum(np.abs(drho) ** 2))
     num = np.sqrt(np.sum(np.abs(res) ** 2))
     return float(num / den) if den > 0 else float(num)
 

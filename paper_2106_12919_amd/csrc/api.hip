@@ -1196,23 +1196,35 @@ pic_status do_step_adjoint(pic_ctx c, pic_fields* f, const pic_species* sp, int 
   return c->check("pic_step_adjoint");
 }
 
+// Gauss's law (continuity = false: E_stag, rho_old) or the continuity equation (continuity =
+// true: J, rho_old = rho^n, rho_new = rho^{n+1}) in Fourier space; *out = ||r|| / ||source||.
 template <typename T>
-pic_status do_gauss(pic_ctx c, const pic_fields* f, double* out) {
+pic_status do_div_residual(pic_ctx c, const pic_fields* f, double* out, bool continuity) {
   Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
   const pic_params& p = c->p;
-  const T* src[4] = {static_cast<const T*>(f->E_stag[0]), static_cast<const T*>(f->E_stag[1]),
-                     static_cast<const T*>(f->E_stag[2]), static_cast<const T*>(f->rho_old)};
-  cplx<T>* dst[4] = {e.scratch[0], e.scratch[1], e.scratch[2], e.scratch[3]};
-  forward_batch<T>(c, e, src, dst, 4);
+  const bool nodal = (p.flags & PIC_NODAL_SOLVER) != 0;
+  const char* where = continuity ? "pic_continuity_residual" : "pic_gauss_residual";
+  const T* src[5];
+  for (int d = 0; d < 3; ++d)
+    src[d] = static_cast<const T*>(continuity ? (nodal ? f->J_nod[d] : f->J_stag[d]) : f->E_stag[d]);
+  src[3] = static_cast<const T*>(continuity ? f->rho_new : f->rho_old);
+  src[4] = static_cast<const T*>(f->rho_old);
+  cplx<T>* dst[5] = {e.scratch[0], e.scratch[1], e.scratch[2], e.scratch[3], e.scratch[4]};
+  forward_batch<T>(c, e, src, dst, continuity ? 5 : 4);
   (void)hipMemsetAsync(c->d_acc, 0, 2 * sizeof(double), c->stream);
-  const cplx<T>* E[3] = {e.scratch[0], e.scratch[1], e.scratch[2]};
-  gauss_residual<T>(e.tab, E, e.scratch[3], p.nx, p.ny, e.fft.nzh, e.fft.pz, p.nz, c->d_acc, c->stream);
+  const cplx<T>* V[3] = {e.scratch[0], e.scratch[1], e.scratch[2]};
+  if (continuity)
+    div_residual<T>(e.tab, V, e.scratch[3], 1.0 / p.dt, e.scratch[4], -1.0 / p.dt, p.nx, p.ny, e.fft.nzh, e.fft.pz,
+                    p.nz, c->d_acc, c->stream);
+  else
+    div_residual<T>(e.tab, V, e.scratch[3], -1.0, nullptr, 0.0, p.nx, p.ny, e.fft.nzh, e.fft.pz, p.nz, c->d_acc,
+                    c->stream);
   double h[2];
   hipError_t he = hipMemcpyAsync(h, c->d_acc, sizeof(h), hipMemcpyDeviceToHost, c->stream);
   if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
-  if (he != hipSuccess) return c->fail(PIC_EHIP, std::string("pic_gauss_residual: ") + hipGetErrorString(he));
+  if (he != hipSuccess) return c->fail(PIC_EHIP, std::string(where) + ": " + hipGetErrorString(he));
   out[0] = h[1] > 0 ? std::sqrt(h[0] / h[1]) : std::sqrt(h[0]);
-  return c->check("pic_gauss_residual");
+  return c->check(where);
 }
 
 template <typename T>
@@ -1457,7 +1469,16 @@ pic_status pic_gauss_residual(pic_ctx ctx, const pic_fields* f, double* out) {
   if (st != PIC_OK) return st;
   if (!out) return ctx->fail(PIC_EINVAL, "out is NULL");
   if ((st = check_fields(ctx, f, true, false, false, false, false, false, true, false)) != PIC_OK) return st;
-  return PIC_DISPATCH(ctx, do_gauss, f, out);
+  return PIC_DISPATCH(ctx, do_div_residual, f, out, false);
+}
+
+pic_status pic_continuity_residual(pic_ctx ctx, const pic_fields* f, double* out) {
+  pic_status st = device_ok(ctx);
+  if (st != PIC_OK) return st;
+  if (!out) return ctx->fail(PIC_EINVAL, "out is NULL");
+  const bool nodal = (ctx->p.flags & PIC_NODAL_SOLVER) != 0;
+  if ((st = check_fields(ctx, f, false, false, false, false, nodal, !nodal, true, true)) != PIC_OK) return st;
+  return PIC_DISPATCH(ctx, do_div_residual, f, out, true);
 }
 
 pic_status pic_profile(pic_ctx ctx, int enable) {

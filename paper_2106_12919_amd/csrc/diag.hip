@@ -1,5 +1,5 @@
 // Grid reductions accumulated in FP64 (field energy of Sec. 2 item iii, total
-// charge, the Gauss's-law residual of the spectra) and a plain element-wise add.
+// charge, the Gauss's-law and continuity residuals of the spectra) and element-wise helpers.
 #include "kernels.h"
 
 namespace pic {
@@ -39,17 +39,18 @@ __global__ void __launch_bounds__(256) k_sum_plain(const T* a, long long n, doub
   if (threadIdx.x == 0) atomicAdd(acc, v);
 }
 
-// Gauss's law in the paper's convention (App. A; the update's derivation assumes it):
-// [k]_s . E_hat = -i rho_hat / eps0.  With index-space spectra e_d of the Yee components and
-// D-_d = i [k_d]_s exp(-i k_d dx_d / 2), i [k_d]_s E_hat_d = D-_d e_d, so the residual is
-// r = sum_d D-_d e_d - rho_hat (eps0 = 1) and acc[0] += |r|^2, acc[1] += |rho_hat|^2 over the
-// half spectrum, each mode weighted by the number of full-spectrum modes it stands for
-// (1 at kz = 0 and at the Nyquist index of an even nz, 2 otherwise).
+// Residual of a divergence law in the paper's Fourier convention (App. A; derivative <-> i k):
+// r = i [k]_s . V_hat + ca A_hat + cb B_hat.  With index-space spectra v_d of the Yee components
+// and D-_d = i [k_d]_s exp(-i k_d dx_d / 2), i [k_d]_s V_hat_d = D-_d v_d.  Gauss's law (the
+// update's derivation assumes it, eps0 = 1): V = E, A = rho, ca = -1, no B.  Continuity:
+// V = J, A = rho^{n+1}, ca = 1/dt, B = rho^n, cb = -1/dt.  acc[0] += |r|^2 and
+// acc[1] += |ca A + cb B|^2 over the half spectrum, each mode weighted by the number of
+// full-spectrum modes it stands for (1 at kz = 0 and at the Nyquist index of an even nz, 2 otherwise).
 template <typename T>
-__global__ void __launch_bounds__(256) k_gauss_residual(Batch<const cplx<T>*> S, const cplx<T>* __restrict__ dmx,
-                                                        const cplx<T>* __restrict__ dmy,
-                                                        const cplx<T>* __restrict__ dmz, int nx, int ny, int nzh,
-                                                        int pz, int nz, double* acc) {
+__global__ void __launch_bounds__(256) k_div_residual(Batch<const cplx<T>*> S, const cplx<T>* __restrict__ dmx,
+                                                      const cplx<T>* __restrict__ dmy, const cplx<T>* __restrict__ dmz,
+                                                      double ca, double cb, int nx, int ny, int nzh, int pz, int nz,
+                                                      double* acc) {
   double num = 0, den = 0;
   const long long total = (long long)nx * ny * nzh;
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
@@ -58,15 +59,21 @@ __global__ void __launch_bounds__(256) k_gauss_residual(Batch<const cplx<T>*> S,
     const long long r = idx / nzh;
     const int j = (int)(r % ny), i = (int)(r / ny);
     const size_t a = (size_t)r * pz + kz;
-    const cplx<T> e0 = S.p[0][a], e1 = S.p[1][a], e2 = S.p[2][a], rh = S.p[3][a];
+    const cplx<T> e0 = S.p[0][a], e1 = S.p[1][a], e2 = S.p[2][a], ah = S.p[3][a];
+    double sx = ca * (double)ah.x, sy = ca * (double)ah.y;
+    if (S.p[4]) {
+      const cplx<T> bh = S.p[4][a];
+      sx += cb * (double)bh.x;
+      sy += cb * (double)bh.y;
+    }
     const cplx<T> px = dmx[i], py = dmy[j], pzz = dmz[kz];
     const double rx = (double)px.x * e0.x - (double)px.y * e0.y + (double)py.x * e1.x - (double)py.y * e1.y +
-                      (double)pzz.x * e2.x - (double)pzz.y * e2.y - (double)rh.x;
+                      (double)pzz.x * e2.x - (double)pzz.y * e2.y + sx;
     const double ry = (double)px.x * e0.y + (double)px.y * e0.x + (double)py.x * e1.y + (double)py.y * e1.x +
-                      (double)pzz.x * e2.y + (double)pzz.y * e2.x - (double)rh.y;
+                      (double)pzz.x * e2.y + (double)pzz.y * e2.x + sy;
     const double w = (kz == 0 || 2 * kz == nz) ? 1.0 : 2.0;
     num += w * (rx * rx + ry * ry);
-    den += w * ((double)rh.x * rh.x + (double)rh.y * rh.y);
+    den += w * (sx * sx + sy * sy);
   }
   num = block_sum(num);
   __syncthreads();
@@ -101,13 +108,14 @@ void sum_plain(const T* arr, int64_t n, double* acc, hipStream_t s) {
   hipLaunchKernelGGL((k_sum_plain<T>), dim3(1024), dim3(256), 0, s, arr, (long long)n, acc);
 }
 template <typename T>
-void gauss_residual(const PsatdTables<T>& t, const cplx<T>* const E[3], const cplx<T>* rho, int nx, int ny, int nzh,
-                    int pz, int nz, double* acc, hipStream_t s) {
+void div_residual(const PsatdTables<T>& t, const cplx<T>* const V[3], const cplx<T>* A, double ca, const cplx<T>* B,
+                  double cb, int nx, int ny, int nzh, int pz, int nz, double* acc, hipStream_t s) {
   Batch<const cplx<T>*> S{};
-  for (int d = 0; d < 3; ++d) S.p[d] = E[d];
-  S.p[3] = rho;
-  hipLaunchKernelGGL((k_gauss_residual<T>), dim3(1024), dim3(256), 0, s, S, t.Dm[0], t.Dm[1], t.Dm[2], nx, ny, nzh, pz,
-                     nz, acc);
+  for (int d = 0; d < 3; ++d) S.p[d] = V[d];
+  S.p[3] = A;
+  S.p[4] = B;
+  hipLaunchKernelGGL((k_div_residual<T>), dim3(1024), dim3(256), 0, s, S, t.Dm[0], t.Dm[1], t.Dm[2], ca, cb, nx, ny,
+                     nzh, pz, nz, acc);
 }
 template <typename T>
 void zero_arrays(const Batch<T*>& arrs, int count, int64_t n, hipStream_t s) {
@@ -123,10 +131,10 @@ template void sum_squares<float>(const Batch<const float*>&, int, int64_t, doubl
 template void sum_squares<double>(const Batch<const double*>&, int, int64_t, double*, hipStream_t);
 template void sum_plain<float>(const float*, int64_t, double*, hipStream_t);
 template void sum_plain<double>(const double*, int64_t, double*, hipStream_t);
-template void gauss_residual<float>(const PsatdTables<float>&, const cplx<float>* const*, const cplx<float>*, int, int,
-                                   int, int, int, double*, hipStream_t);
-template void gauss_residual<double>(const PsatdTables<double>&, const cplx<double>* const*, const cplx<double>*, int,
-                                    int, int, int, int, double*, hipStream_t);
+template void div_residual<float>(const PsatdTables<float>&, const cplx<float>* const*, const cplx<float>*, double,
+                                 const cplx<float>*, double, int, int, int, int, int, double*, hipStream_t);
+template void div_residual<double>(const PsatdTables<double>&, const cplx<double>* const*, const cplx<double>*, double,
+                                  const cplx<double>*, double, int, int, int, int, int, double*, hipStream_t);
 template void zero_arrays<float>(const Batch<float*>&, int, int64_t, hipStream_t);
 template void zero_arrays<double>(const Batch<double*>&, int, int64_t, hipStream_t);
 template void add_into<float>(float*, const float*, int64_t, hipStream_t);

@@ -237,10 +237,11 @@ void add_into(T* dst, const T* src, int64_t n, hipStream_t s);
 // Zeroes count (<= 8) arrays of n elements in one launch.
 template <typename T>
 void zero_arrays(const Batch<T*>& arrs, int count, int64_t n, hipStream_t s);
-// acc[0] += sum |sum_d D-_d E_d - rho|^2, acc[1] += sum |rho|^2 over the half-spectrum modes
-// (index-space spectra of the Yee components E and of rho), weighted as full-spectrum sums.
+// acc[0] += sum |sum_d D-_d V_d + ca A + cb B|^2, acc[1] += sum |ca A + cb B|^2 over the
+// half-spectrum modes (index-space spectra of the Yee components V and of A, B; B may be null),
+// weighted as full-spectrum sums.
 template <typename T>
-void gauss_residual(const PsatdTables<T>& t, const cplx<T>* const E[3], const cplx<T>* rho, int nx, int ny, int nzh,
-                    int pz, int nz, double* acc, hipStream_t s);
+void div_residual(const PsatdTables<T>& t, const cplx<T>* const V[3], const cplx<T>* A, double ca, const cplx<T>* B,
+                  double cb, int nx, int ny, int nzh, int pz, int nz, double* acc, hipStream_t s);
 
 }  // namespace pic

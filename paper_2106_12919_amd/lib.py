@@ -81,6 +81,7 @@ def load():
         "pic_sync": (c_int, [c_void_p]),
         "pic_diagnostics": (c_int, [c_void_p, POINTER(pic_fields), POINTER(c_double)]),
         "pic_gauss_residual": (c_int, [c_void_p, POINTER(pic_fields), POINTER(c_double)]),
+        "pic_continuity_residual": (c_int, [c_void_p, POINTER(pic_fields), POINTER(c_double)]),
         "pic_profile": (c_int, [c_void_p, c_int]),
         "pic_stage_times": (c_int, [c_void_p, POINTER(c_double), POINTER(c_int64), c_int]),
         "pic_stage_name": (c_char_p, [c_int]),
@@ -190,6 +191,12 @@ def pic_diagnostics(ctx, fields):
 def pic_gauss_residual(ctx, fields):
     out = c_double()
     _check(load().pic_gauss_residual(ctx, ctypes.byref(fields.struct()), ctypes.byref(out)), ctx)
+    return float(out.value)
+
+
+def pic_continuity_residual(ctx, fields):
+    out = c_double()
+    _check(load().pic_continuity_residual(ctx, ctypes.byref(fields.struct()), ctypes.byref(out)), ctx)
     return float(out.value)
 
 

@@ -163,3 +163,34 @@ def test_gauss_residual_special_cases():
     # a uniform field has zero divergence at any order: the residual is again ||rho|| / ||rho||
     const = [np.full(shape, 0.3), np.full(shape, -1.2), np.full(shape, 2.0)]
     assert diagnostics.gauss_residual(const, rho, spacing, 0) == pytest.approx(1.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_continuity_residual_equals_real_space_yee_error(order):
+    """Parseval: with the order-2m [k]_s the spectral continuity residual is the real-space L2 error
+    of (rho^{n+1} - rho^n)/dt + div J with the textbook staggered stencil (J_d at +1/2 cell along d)."""
+    rng = np.random.default_rng(44)
+    shape, spacing, dt = (8, 10, 6), (0.7, 1.1, 0.9), 0.37
+    J = [rng.standard_normal(shape) for _ in range(3)]
+    r0, r1 = rng.standard_normal(shape), rng.standard_normal(shape)
+    drho = (r1 - r0) / dt
+    ref = np.linalg.norm(drho + _yee_divergence(J, spacing, order)) / np.linalg.norm(drho)
+    assert diagnostics.continuity_residual(J, r0, r1, spacing, dt, order) == pytest.approx(ref, rel=1e-12)
+    # a charge-conserving pair: rho^{n+1} = rho^n - dt div J
+    r1c = r0 - dt * _yee_divergence(J, spacing, order)
+    assert diagnostics.continuity_residual(J, r0, r1c, spacing, dt, order) < 1e-13
+
+
+def test_continuity_residual_nodal_and_special_cases():
+    rng = np.random.default_rng(45)
+    shape, spacing, dt = (8, 10, 6), (0.7, 1.1, 0.9), 0.5
+    J = [rng.standard_normal(shape) for _ in range(3)]
+    r0, r1 = rng.standard_normal(shape), rng.standard_normal(shape)
+    drho = (r1 - r0) / dt
+    ref = np.linalg.norm(drho + _centered_divergence(J, spacing)) / np.linalg.norm(drho)
+    assert diagnostics.continuity_residual(J, r0, r1, spacing, dt, 2, nodal=True) == pytest.approx(ref, rel=1e-12)
+    zero = [np.zeros(shape)] * 3
+    assert diagnostics.continuity_residual(zero, r0, r1, spacing, dt, 16) == pytest.approx(1.0, rel=1e-14)
+    # uniform J has no divergence at any order
+    const = [np.full(shape, 0.4), np.full(shape, -0.2), np.full(shape, 1.3)]
+    assert diagnostics.continuity_residual(const, r0, r1, spacing, dt, 0) == pytest.approx(1.0, rel=1e-12)
