@@ -194,3 +194,38 @@ def test_continuity_residual_nodal_and_special_cases():
     # uniform J has no divergence at any order
     const = [np.full(shape, 0.4), np.full(shape, -0.2), np.full(shape, 1.3)]
     assert diagnostics.continuity_residual(const, r0, r1, spacing, dt, 0) == pytest.approx(1.0, rel=1e-12)
+
+
+# ---------------------------------------------------------------- field energy (Sec. 2 item (iii))
+
+def test_field_energy_of_a_sampled_plane_wave():
+    """Closed form: for a wave number m with 0 < m < n/2 along an axis of n points,
+    sum_j cos^2(2 pi m j / n + phi) = n/2.  E_x = A cos, B_y = A sin then give
+    W = 1/2 (sum E^2 + sum B^2) dV = 1/2 A^2 N dV (N cells), whatever the phase."""
+    shape, spacing = (6, 4, 10), (0.7, 1.3, 0.4)
+    N, dV = np.prod(shape), np.prod(spacing)
+    A, m, phi = 1.7, 3, 0.4
+    k = np.arange(shape[2])
+    ph = np.broadcast_to(2 * np.pi * m * k / shape[2] + phi, shape)
+    E = [A * np.cos(ph), np.zeros(shape), np.zeros(shape)]
+    B = [np.zeros(shape), A * np.sin(ph), np.zeros(shape)]
+    assert diagnostics.field_energy(E, B, spacing) == pytest.approx(0.5 * A * A * N * dV, rel=1e-14)
+    # E only: half of it (sum cos^2 = N/2 on its own)
+    zero = [np.zeros(shape)] * 3
+    assert diagnostics.field_energy(E, zero, spacing) == pytest.approx(0.25 * A * A * N * dV, rel=1e-14)
+
+
+def test_field_energy_equals_the_parseval_sum_of_the_spectra():
+    """Parseval in the App. A convention: a component's transform differs from the index-space DFT by
+    a phase of modulus one, so sum_j f_j^2 = (1/N) sum_k |f_hat(k)|^2 and
+    W = 1/2 dV (1/N) sum_k (|E_hat|^2 + |B_hat|^2) over every Yee component."""
+    from oracle import transforms
+    from oracle.transforms import B_NAMES, E_NAMES, OFFSETS
+    rng = np.random.default_rng(51)
+    shape, spacing = (8, 6, 12), (0.9, 1.1, 0.6)
+    E = [rng.standard_normal(shape) for _ in range(3)]
+    B = [rng.standard_normal(shape) for _ in range(3)]
+    N, dV = np.prod(shape), np.prod(spacing)
+    s = sum(np.sum(np.abs(transforms.forward(E[d], spacing, OFFSETS[E_NAMES[d]])) ** 2) for d in range(3))
+    s += sum(np.sum(np.abs(transforms.forward(B[d], spacing, OFFSETS[B_NAMES[d]])) ** 2) for d in range(3))
+    assert diagnostics.field_energy(E, B, spacing) == pytest.approx(0.5 * dV * s / N, rel=1e-13)

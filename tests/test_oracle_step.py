@@ -126,3 +126,48 @@ def test_staggered_deposit_is_the_transpose_of_the_staggered_gather(order):
         rhs = np.sum(sp["q"] * sp["w"] * v[d] * g)
         assert abs(lhs - rhs) <= 1e-12 * (abs(rhs) + 1)
         assert abs(np.sum(J[d]) * dV - np.sum(sp["q"] * sp["w"] * v[d])) <= 1e-12
+
+
+# ---------------------------------------------------------------- time level of the deposited current
+
+@pytest.mark.parametrize("axis,sign,v_gal", [(0, 1, 0.0), (1, -1, 0.0), (2, 1, 0.0), (2, 1, -0.3), (0, -1, 0.2)])
+def test_current_is_deposited_at_the_half_step_position(axis, sign, v_gal):
+    """Sec. 4.2 holds J constant over the step and places it at t^{n+1/2}.  A linear (CIC) weight is
+    affine in the particle's coordinate inside a cell, so for a particle that moves along one axis
+    without crossing a node, q w v S(x^{n+1/2} - x_i) equals the mean of q w v S(x^n - x_i) and
+    q w v S(x^{n+1} - x_i) exactly.  Depositing at x^n or at x^{n+1} (or with a wrong frame shift
+    in the Galilean case, where the grid moves with v_gal) breaks the identity by O(v dt)."""
+    shape, dt = (8, 6, 10), 0.5
+    vg = [0.0, 0.0, 0.0]
+    vg[axis] = v_gal
+    p = Params(shape, (1.0, 1.0, 1.0), dt, shape_order=1, center_order=4, psatd_order=8, v_gal=tuple(vg))
+    rng = np.random.default_rng(31 + axis)
+    n = 40
+    cells = np.column_stack([rng.integers(0, s, n) for s in shape]).astype(np.float64)
+    off = rng.uniform(0.0, 1.0, (n, 3))
+    u = np.zeros((n, 3))
+    u[:, axis] = sign * rng.uniform(0.2, 0.6, n)
+    gam = np.sqrt(1.0 + np.sum(u * u, axis=1))
+    disp = dt * (u[:, axis] / gam - v_gal)  # motion on the grid along the axis, |disp| < 0.4
+    # keep both end points inside the cell along the moving axis
+    lo = np.maximum(0.02, -disp + 0.02)
+    hi = np.minimum(0.98, 0.98 - disp)
+    off[:, axis] = lo + (hi - lo) * rng.uniform(0.0, 1.0, n)
+    pos0 = cells + off
+    w = rng.uniform(0.5, 1.5, n)
+    el = {"pos": pos0.copy(), "u": u.copy(), "w": w, "q": -1.0, "m": 1.0}
+    zero = [np.zeros(shape) for _ in range(3)]
+    state = {"E_stag": [z.copy() for z in zero], "B_stag": [z.copy() for z in zero],
+             "rho_old": deposit_rho([el], p)}
+    out = step(state, [el], p)
+    pos1 = pos0.copy()
+    pos1[:, axis] += disp
+    np.testing.assert_allclose(el["pos"], pos1, atol=1e-13)  # E = B = 0: a straight move
+    qwv = -1.0 * w * u[:, axis] / gam
+    dep = lambda pos: particles.deposit([qwv], pos, shape, p.spacing, 1)[0]
+    expect = 0.5 * (dep(pos0) + dep(pos1))
+    np.testing.assert_allclose(out["J_nod"][axis], expect, atol=1e-14)
+    assert np.max(np.abs(out["J_nod"][axis] - dep(pos1))) > 1e-3  # the end point is measurably different
+    for d in range(3):
+        if d != axis:
+            assert np.max(np.abs(out["J_nod"][d])) == 0.0
