@@ -277,3 +277,23 @@ def update_averaged(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, ac):
     E_avg = tuple(P1 * Eh[d] - 1j * C_LIGHT ** 2 * P2 * kxB[d] + Y4 * Jh[d]
                   + (Y3 * rho_old_h + Y2 * rho_new_h) * ks[d] for d in range(3))
     return E_avg, B_avg
+
+
+# ---------------------------------------------------------------- spectral current correction
+
+def current_correction(Jh, rho_old_h, rho_new_h, ks, dt):
+    """Projection of the current onto the discrete continuity equation (reading of the charge
+    conservation that Sec. 6 defers; the continuity law is the Fourier-space one of App. A,
+    (rho^{n+1} - rho^n)/dt + i [k]_s . J = 0, with the same [k]_s as the field solver):
+        J' = J - [k]_s ([k]_s . J - i (rho^{n+1} - rho^n)/dt) / |[k]_s|^2.
+    J' - J is parallel to [k]_s (a discrete gradient), so [k]_s x J, and with it the B update
+    and the transverse current, is unchanged.  Modes with |[k]_s| = 0 (k = 0; the Nyquist planes
+    of the centered [k]_c) have no longitudinal direction and keep J.  Paper-convention spectra
+    in and out."""
+    kx, ky, kz = np.broadcast_arrays(*ks)
+    k2 = kx * kx + ky * ky + kz * kz
+    has = k2 > 0
+    k2s = np.where(has, k2, 1.0)
+    mismatch = kx * Jh[0] + ky * Jh[1] + kz * Jh[2] - 1j * (rho_new_h - rho_old_h) / dt
+    f = np.where(has, mismatch / k2s, 0.0)
+    return (Jh[0] - kx * f, Jh[1] - ky * f, Jh[2] - kz * f)

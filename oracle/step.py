@@ -33,6 +33,11 @@ nodes, no centering, the same staggered PSATD update.
 With ``Params.nodal`` the same function runs the standard nodal PSATD cycle the paper
 compares against (Sec. 2, first cycle figure; Sec. 4.1 [k]_c): every field on the nodes,
 no centering, the update with the centered modified wave numbers.
+
+With ``Params.current_correction`` the field solve first projects J^{n+1/2} onto the
+Fourier-space continuity equation of App. A (``psatd.current_correction``), so that the update,
+which carries Gauss's law exactly when continuity holds, keeps it step after step (standard
+PSATD only; Sec. 6 leaves charge conservation open, this is the reading used).
 """
 
 from dataclasses import dataclass
@@ -55,6 +60,7 @@ class Params:
     v_gal: tuple = (0.0, 0.0, 0.0)  # Galilean velocity (Sec. 4.3); zero = standard PSATD
     averaged: bool = False  # averaged Galilean PSATD (Sec. 4.4): particles see the averaged fields
     staggered: bool = False  # the fully staggered comparison cycle: Yee gather and deposition, no centering
+    current_correction: bool = False  # project J onto the Fourier-space continuity equation before the solve
 
     @property
     def lengths(self):
@@ -140,6 +146,10 @@ def push_fields(E_stag, B_stag, J_stag, rho_old, rho_new, p):
     Jh = [fw(J_stag[d], J_NAMES[d]) for d in range(3)]
     rho_old_h = fw(rho_old, "rho")
     rho_new_h = fw(rho_new, "rho")
+    if p.current_correction:
+        if any(v != 0 for v in p.v_gal) or p.averaged:
+            raise ValueError("the current correction is stated for the standard PSATD continuity equation")
+        Jh = psatd.current_correction(Jh, rho_old_h, rho_new_h, ks, p.dt)
     if any(v != 0 for v in p.v_gal):  # standard Galilean PSATD (Sec. 4.3)
         kc = psatd.centered_wave_vector(p.shape, p.spacing, p.psatd_order)
         gc = psatd.galilean_coefficients(ks, kc, p.v_gal, p.dt)
