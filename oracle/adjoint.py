@@ -57,6 +57,8 @@ def push_fields_vjp(lam_E, lam_B, p):
     lEh = [transforms.forward(lam_E[d], p.spacing, offsets[E_NAMES[d]]) for d in range(3)]
     lBh = [transforms.forward(lam_B[d], p.spacing, offsets[B_NAMES[d]]) for d in range(3)]
     gE, gB, gJ, g_old, g_new = psatd.update_transpose(lEh, lBh, ks, coef)
+    if p.current_correction:
+        gJ, g_old, g_new = psatd.current_correction_transpose(gJ, g_old, g_new, ks, p.dt)
     inv = lambda g, name: transforms.inverse(g, p.spacing, offsets[name])
     return ([inv(gE[d], E_NAMES[d]) for d in range(3)] + [inv(gB[d], B_NAMES[d]) for d in range(3)]
             + [inv(gJ[d], J_NAMES[d]) for d in range(3)] + [inv(g_old, "rho"), inv(g_new, "rho")])

@@ -281,6 +281,14 @@ def update_averaged(Eh, Bh, Jh, rho_old_h, rho_new_h, ks, ac):
 
 # ---------------------------------------------------------------- spectral current correction
 
+def _has_direction(k2):
+    """Modes whose modified wave vector is nonzero.  The centered [k]_c vanishes at the Nyquist index
+    of an even axis in exact arithmetic; its sines leave ~1e-16 there, so a squared length below
+    1e-24 of the largest counts as zero (the smallest genuine |[k]|^2 on grids of <= 1024 points
+    is ~1e-5 of the largest)."""
+    return k2 > 1e-24 * np.max(k2)
+
+
 def current_correction(Jh, rho_old_h, rho_new_h, ks, dt):
     """Projection of the current onto the discrete continuity equation (reading of the charge
     conservation that Sec. 6 defers; the continuity law is the Fourier-space one of App. A,
@@ -292,8 +300,22 @@ def current_correction(Jh, rho_old_h, rho_new_h, ks, dt):
     in and out."""
     kx, ky, kz = np.broadcast_arrays(*ks)
     k2 = kx * kx + ky * ky + kz * kz
-    has = k2 > 0
+    has = _has_direction(k2)
     k2s = np.where(has, k2, 1.0)
     mismatch = kx * Jh[0] + ky * Jh[1] + kz * Jh[2] - 1j * (rho_new_h - rho_old_h) / dt
     f = np.where(has, mismatch / k2s, 0.0)
     return (Jh[0] - kx * f, Jh[1] - ky * f, Jh[2] - kz * f)
+
+
+def current_correction_transpose(gJ, g_old, g_new, ks, dt):
+    """Conjugate transpose of ``current_correction``: the projection J -> J - [k]_s ([k]_s . J)/|k|^2
+    is real symmetric, and J' depends on rho^{n+1} through + i [k]_s rho^{n+1} / (dt |k|^2) (and on
+    rho^n with the opposite sign), which contribute conj(i / (dt |k|^2)) [k]_s . lambda.  Given the
+    adjoint ``gJ`` of the corrected current, returns the adjoints of J, rho^n and rho^{n+1} with
+    ``g_old``, ``g_new`` (those of the update itself) added."""
+    kx, ky, kz = np.broadcast_arrays(*ks)
+    k2 = kx * kx + ky * ky + kz * kz
+    has = _has_direction(k2)
+    s = np.where(has, (kx * gJ[0] + ky * gJ[1] + kz * gJ[2]) / np.where(has, k2, 1.0), 0.0)
+    return ((gJ[0] - kx * s, gJ[1] - ky * s, gJ[2] - kz * s),
+            g_old + 1j * s / dt, g_new - 1j * s / dt)

@@ -149,6 +149,8 @@ def push_fields(E_stag, B_stag, J_stag, rho_old, rho_new, p):
     if p.current_correction:
         if any(v != 0 for v in p.v_gal) or p.averaged:
             raise ValueError("the current correction is stated for the standard PSATD continuity equation")
+        if p.nodal and p.psatd_order == 0:
+            raise ValueError("the nodal solver at infinite order has no real derivative at the Nyquist index")
         Jh = psatd.current_correction(Jh, rho_old_h, rho_new_h, ks, p.dt)
     if any(v != 0 for v in p.v_gal):  # standard Galilean PSATD (Sec. 4.3)
         kc = psatd.centered_wave_vector(p.shape, p.spacing, p.psatd_order)

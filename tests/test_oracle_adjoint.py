@@ -45,11 +45,11 @@ from oracle import particles
 from oracle.step import step
 
 
-@pytest.mark.parametrize("nodal", [False, True])
-def test_conjugate_transposed_update_matches_brute_force(nodal):
+@pytest.mark.parametrize("nodal,correction", [(False, False), (True, False), (False, True), (True, True)])
+def test_conjugate_transposed_update_matches_brute_force(nodal, correction):
     rng = np.random.default_rng(11)
     shape = (8, 8, 6)
-    p = Params(shape, (1.0, 1.0, 1.0), 0.5, 1, 4, 8, nodal=nodal)
+    p = Params(shape, (1.0, 1.0, 1.0), 0.5, 1, 4, 8, nodal=nodal, current_correction=correction)
     lam_E = [rng.standard_normal(shape) for _ in range(3)]
     lam_B = [rng.standard_normal(shape) for _ in range(3)]
     brute = adjoint.push_fields_transpose(lam_E, lam_B, p)
@@ -134,12 +134,13 @@ def _state_dot(lam, st, sps, lengths):
     return s
 
 
-@pytest.mark.parametrize("order,nodal,immobile", [(1, False, False), (3, False, True), (3, True, False)])
-def test_step_adjoint_against_directional_differences(order, nodal, immobile):
+@pytest.mark.parametrize("order,nodal,immobile,correction", [(1, False, False, False), (3, False, True, False),
+                                                              (3, True, False, False), (3, False, True, True)])
+def test_step_adjoint_against_directional_differences(order, nodal, immobile, correction):
     """<vjp(lambda), delta> = d/ds <lambda, step(x + s delta)> at s = 0 (central differences, FP64)."""
     rng = np.random.default_rng(16 + order)
     shape, spacing = (8, 8, 6), (1.0, 1.0, 1.0)
-    p = Params(shape, spacing, 0.5, order, 4, 8, nodal=nodal)
+    p = Params(shape, spacing, 0.5, order, 4, 8, nodal=nodal, current_correction=correction)
     n = 48
     state = {"E_stag": [0.3 * rng.standard_normal(shape) for _ in range(3)],
              "B_stag": [0.3 * rng.standard_normal(shape) for _ in range(3)],
