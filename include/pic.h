@@ -56,6 +56,29 @@ enum { PIC_J = 0, PIC_E = 1, PIC_B = 2 };
 enum { PIC_DEP_RHO_AND_J = 0, PIC_DEP_RHO_ONLY = 1 };
 /* pic_params.flags */
 enum {
+  /* Spectral current correction (standard PSATD only; v_gal = 0, not PIC_AVERAGED).  The direct
+   * deposition of the hybrid cycle does not satisfy the discrete continuity equation, and the
+   * paper leaves charge conservation to future work (Sec. 6).  With this flag the field solve
+   * first projects J^{n+1/2} onto the Fourier-space continuity equation of App. A with the
+   * solver's own modified wave number, in the paper's Fourier convention:
+   *   J <- J - [k]_s ([k]_s . J - i (rho^{n+1} - rho^n) / dt) / |[k]_s|^2
+   * (modes with |[k]_s| = 0 keep J: k = 0, whose charge the deposition conserves exactly, and
+   * with PIC_NODAL_SOLVER the Nyquist planes where [k]_c vanishes).  The change is a discrete
+   * gradient, so B and the transverse current are untouched; since the update carries Gauss's
+   * law exactly when continuity holds, a Gauss-consistent state stays so after every step.
+   * Applies to psatd_push_fields, pic_step and their reverse modes; J_stag (J_nod with the nodal
+   * solver) keeps the deposited, uncorrected current. */
+  PIC_CURRENT_CORRECTION = 1u << 0,
+  /* Bitwise run-to-run reproducibility: every output of pic_step, pic_deposit and pic_gather_push
+   * depends only on the inputs and not on the order in which the particles of a tile are visited
+   * or in which the device schedules work.  The deposition accumulates in fixed point (integer
+   * additions, exact in any order); with this flag each tile's fixed-point scale is chosen from
+   * its particle count and largest contribution instead of a floating-point sum (at most
+   * log2(particles per tile) fewer bits of headroom), and pic_step keeps every species in the
+   * caller's order (as PIC_KEEP_ORDER), so particle outputs are in a fixed order too.  The
+   * fully staggered cycle returns PIC_ENOMEM rather than fall back to its untiled deposition
+   * (float atomics) when scratch cannot be allocated. */
+  PIC_DETERMINISTIC = 1u << 1,
   /* pic_step applies the finite-order centering of J (nodes -> Yee) and of the updated
    * E, B (Yee -> nodes) as the stencils' exact Fourier symbols inside the per-mode
    * update: on the periodic grid the stencil of Sec. 3 is that multiplication (App. C),
@@ -64,7 +87,7 @@ enum {
    * the particles are as in the real-space cycle; E_nod, B_nod hold the centred fields of
    * the final time level (the real-space cycle leaves those of the last step's start).
    * pic_center and psatd_push_fields are unaffected. */
-  PIC_SPECTRAL_CENTERING = 1u << 0,
+  PIC_SPECTRAL_CENTERING = 1u << 2,
   /* Nodal comparison solver (Sec. 2, the standard nodal PSATD cycle the hybrid scheme is
    * measured against): every field sits on the nodes, derivatives use the centered
    * modified wave number [k]_c (Sec. 4.1 eq. centered_modified_wave_number) with no
@@ -72,13 +95,13 @@ enum {
    * the NODAL state, which pic_gather_push inside pic_step reads directly; pic_step leaves
    * E_nod, B_nod and J_stag untouched; psatd_push_fields reads J_stag as the nodal current.
    * Excludes PIC_SPECTRAL_CENTERING. */
-  PIC_NODAL_SOLVER = 1u << 1,
+  PIC_NODAL_SOLVER = 1u << 3,
   /* pic_step keeps every species in the caller's order: each step sorts the particles by
    * tile through a permutation (one counting sort per step) instead of regrouping the
    * arrays.  The results are those of the default cycle up to the summation order of the
    * deposition.  For callers that follow particles by index across steps (the reverse
    * mode, pic_step_adjoint). */
-  PIC_KEEP_ORDER = 1u << 2,
+  PIC_KEEP_ORDER = 1u << 4,
   /* Averaged Galilean PSATD (Sec. 4.4, eqs. eq_update_B/E_with_rho_averaged): E, B advance with
    * the Galilean update (v_gal, possibly zero), and each update also writes the averaged fields
    * <E>^{n+1}, <B>^{n+1} (coefficients Psi1, Psi2, Y1..Y4 of Sec. 4.4, built in FP64) into
@@ -86,15 +109,15 @@ enum {
    * the same J, over [t_n + dt/2, t_n + 3 dt/2].  pic_step gathers the particles' fields from
    * E_avg, B_avg (centred to the nodes): on entry they hold the averaged fields of time n (the
    * caller sets them, e.g. to E, B at the first step).  Excludes PIC_SPECTRAL_CENTERING. */
-  PIC_AVERAGED = 1u << 3,
+  PIC_AVERAGED = 1u << 5,
   /* The fully staggered cycle the paper compares the hybrid one against (Sec. 2; the staggered runs
    * of Sec. 5.2-5.3): no centering; pic_gather_push interpolates every component of E_stag, B_stag
    * from its own Yee positions (the B-spline centred on x_i + delta_c), pic_deposit adds J^d onto
    * the Yee positions of J^d (into J_stag; rho^{n+1} stays nodal) and pic_step runs that cycle with
-   * the same staggered PSATD update.  Particles keep the caller's order.  One particle per thread
-   * with global atomics (a comparison path, not tuned).  Excludes PIC_NODAL_SOLVER,
+   * the same staggered PSATD update.  Particles keep the caller's order.  Tiled like the hybrid
+   * gather and deposition, with six shifted stencils (a comparison path, not tuned).  Excludes PIC_NODAL_SOLVER,
    * PIC_SPECTRAL_CENTERING and PIC_AVERAGED; no reverse mode. */
-  PIC_STAGGERED_CYCLE = 1u << 4
+  PIC_STAGGERED_CYCLE = 1u << 6
 };
 
 typedef struct {
@@ -105,7 +128,7 @@ typedef struct {
   int32_t center_order;   /* finite-order centering 2m, even, 2..32, with 2m <= min(nx,ny,nz) (Sec. 3) */
   int32_t psatd_order;    /* order 2m_p of the staggered modified wave number [k]_s, even 2..64; 0 = infinite */
   pic_dtype dtype;        /* precision of fields, particles, FFTs; tables are always built in FP64 */
-  uint32_t flags;         /* 0 or PIC_SPECTRAL_CENTERING or PIC_NODAL_SOLVER, | PIC_KEEP_ORDER; other bits are rejected */
+  uint32_t flags;         /* an OR of the flags above (exclusions as documented with each); other bits are rejected */
   double v_gal[3];        /* Galilean velocity (in units of c), |v_gal| < 1; all zero = standard PSATD.  Nonzero:
                            * the standard Galilean PSATD update of Sec. 4.3 (eqs.
                            * eq_update_B/E_with_rho_galilean; coefficients built in FP64 from Sec. 4.1

@@ -287,6 +287,8 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
   if ((err = e.upload(&e.tab.X1, X1)) != hipSuccess) return err;
   if ((err = e.upload(&e.tab.X2, X2)) != hipSuccess) return err;
   if ((err = e.upload(&e.tab.X3, X3)) != hipSuccess) return err;
+  e.tab.cc = (p.flags & PIC_CURRENT_CORRECTION) != 0;
+  e.tab.inv_dt = (T)(1.0 / p.dt);
   if (p.v_gal[0] != 0 || p.v_gal[1] != 0 || p.v_gal[2] != 0 || (p.flags & PIC_AVERAGED)) {
     // standard Galilean PSATD (Sec. 4.3): W = v_gal . [k]_c per mode; averaged (Sec. 4.4) too
     std::vector<double> kc[3];
@@ -387,8 +389,8 @@ pic_status validate_params(const pic_params* p, std::string& msg) {
     return PIC_EUNSUPPORTED;
   }
   if (p->dtype != PIC_F32 && p->dtype != PIC_F64) { msg = "dtype must be PIC_F32 or PIC_F64"; return PIC_EINVAL; }
-  if (p->flags &
-      ~(uint32_t)(PIC_SPECTRAL_CENTERING | PIC_NODAL_SOLVER | PIC_KEEP_ORDER | PIC_AVERAGED | PIC_STAGGERED_CYCLE)) {
+  if (p->flags & ~(uint32_t)(PIC_CURRENT_CORRECTION | PIC_DETERMINISTIC | PIC_SPECTRAL_CENTERING | PIC_NODAL_SOLVER |
+                             PIC_KEEP_ORDER | PIC_AVERAGED | PIC_STAGGERED_CYCLE)) {
     msg = "unknown bit in flags";
     return PIC_EINVAL;
   }
@@ -400,6 +402,16 @@ pic_status validate_params(const pic_params* p, std::string& msg) {
   }
   if (vg2 > 0 && p->psatd_order == 0) {
     msg = "the Galilean solver needs a finite psatd_order ([k]_c at the Nyquist index)";
+    return PIC_EUNSUPPORTED;
+  }
+  if ((vg2 > 0 || (p->flags & PIC_AVERAGED)) && (p->flags & PIC_CURRENT_CORRECTION)) {
+    msg = "PIC_CURRENT_CORRECTION is built for the standard PSATD continuity equation (v_gal = 0, not averaged)";
+    return PIC_EUNSUPPORTED;
+  }
+  if ((p->flags & PIC_CURRENT_CORRECTION) && (p->flags & PIC_NODAL_SOLVER) && p->psatd_order == 0) {
+    // [k]_c = k is nonzero at the Nyquist index of an even axis, where the derivative of that
+    // self-conjugate mode has no real-valued action (the solver drops it there)
+    msg = "PIC_CURRENT_CORRECTION with PIC_NODAL_SOLVER needs a finite psatd_order";
     return PIC_EUNSUPPORTED;
   }
   if (vg2 > 0 && (p->flags & PIC_SPECTRAL_CENTERING)) {
@@ -479,6 +491,7 @@ GridGeom geom(const pic_params& p) {
   g.sgx = p.v_gal[0] * p.dt / p.dx;
   g.sgy = p.v_gal[1] * p.dt / p.dy;
   g.sgz = p.v_gal[2] * p.dt / p.dz;
+  g.det = (p.flags & PIC_DETERMINISTIC) != 0;
   return g;
 }
 
@@ -584,7 +597,7 @@ void J_ptrs(pic_fields* f, T* J[3]) {
 
 // The staggered cycle's sources: rho^{n+1} on the nodes, J on the Yee grid (J_stag).
 template <typename T>
-void deposit_yee_all(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, bool with_j) {
+pic_status deposit_yee_all(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, bool with_j) {
   const size_t N = ncells(c->p);
   if (f->rho_static)
     (void)hipMemcpyAsync(f->rho_new, f->rho_static, N * sizeof(T), hipMemcpyDeviceToDevice, c->stream);
@@ -602,6 +615,9 @@ void deposit_yee_all(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, b
     const SpeciesView<T> v = view<T>(sp[s]);
     const bool wj = with_j && std::isfinite(sp[s].m);
     if (e.ensure_species((size_t)s, sp[s].n) != hipSuccess) {  // no scratch: the untiled path
+      (void)hipGetLastError();
+      // its float atomics add in an order that varies between runs
+      if (g.det) return c->fail(PIC_ENOMEM, "pic_deposit: no scratch for the deterministic tiled deposition");
       deposit_yee<T>(g, v, wj, static_cast<T*>(f->rho_new), J, c->stream);
       continue;
     }
@@ -610,6 +626,7 @@ void deposit_yee_all(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, b
     invert_perm(x.dst, x.perm, v.n, c->stream);
     deposit_yee_tiled<T>(g, e.tiles, v, x.perm, x.starts[0], wj, e.stage, static_cast<T*>(f->rho_new), J, c->stream);
   }
+  return PIC_OK;
 }
 
 template <typename T>
@@ -617,7 +634,8 @@ pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, 
   Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
   const bool with_j = (mode == PIC_DEP_RHO_AND_J);
   if (yee_cycle(c->p)) {
-    deposit_yee_all<T>(c, sp, nsp, f, with_j);
+    pic_status st = deposit_yee_all<T>(c, sp, nsp, f, with_j);
+    if (st != PIC_OK) return st;
     return c->check("pic_deposit");
   }
   T* J[3];
@@ -968,7 +986,7 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
   }
   pic_status st;
   const bool spectral = (p.flags & PIC_SPECTRAL_CENTERING) != 0;
-  const bool keep = (p.flags & PIC_KEEP_ORDER) != 0;
+  const bool keep = (p.flags & (PIC_KEEP_ORDER | PIC_DETERMINISTIC)) != 0;
   for (int n = 0; n < nsteps; ++n) {
     if (!nodal && (!spectral || n == 0)) {  // spectral centering: later steps get E_nod, B_nod from the update
       StageScope sc(c, ST_S2N);

@@ -56,6 +56,10 @@ struct PsatdTables {
   cplx<T>* G[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   // Averaged Galilean PSATD (Sec. 4.4): Psi1, Psi2, Y1, Y2, Y3, Y4 (null unless averaging)
   cplx<T>* Av[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // Spectral current correction (standard PSATD): project J onto the Fourier-space
+  // continuity equation with (rho^{n+1} - rho^n) / dt before the update
+  int cc = 0;
+  T inv_dt = 0;
 };
 // With nodal != nullptr (spectral centering): J holds the NODAL current spectra, centred
 // to the Yee grid by the symbols Tc inside the update, and nodal[0..5] receive the
@@ -90,6 +94,12 @@ struct GridGeom {
   // Galilean frame (Sec. 4.3): the grid moves with v_gal, so a particle moves by
   // (v - v_gal) dt per step; sg = v_gal dt / (dx, dy, dz) in cells (0 for standard PSATD)
   double sgx, sgy, sgz;
+  // Deterministic depositions: each tile's fixed-point scale comes from the particle count
+  // times the largest contribution (a maximum and a count do not depend on the order in
+  // which the tile's particles are visited) instead of the floating-point sum of the
+  // contributions, whose rounding does.  Everything else of the deposition is integer
+  // arithmetic, exact in any order.
+  int det;
 };
 GridGeom make_geom(int nx, int ny, int nz, double dx, double dy, double dz, double dt, int shape_order);
 

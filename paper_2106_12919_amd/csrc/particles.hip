@@ -941,6 +941,7 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
         m += red[c * kWaves + w];
         x = fmax(x, redm[c * kWaves + w]);
       }
+      if (g.det) m = x * (T)(end - beg);  // order-independent bound (see GridGeom::det)
       // a little slack on the bound covers the rounding of the FP sum itself
       int e_sum = 0, e_max = 0;
       (void)frexp(m * fabs(qdv) * (T)(MaxWeight<ORDER>::value * 1.001), &e_sum);
@@ -1704,6 +1705,7 @@ __global__ void __launch_bounds__(256) k_scatter_tiled(GridGeom g, TileGeom tg, 
       m += red[v * kWaves + w];
       x = fmax(x, redm[v * kWaves + w]);
     }
+    if (g.det) m = x * (T)(end - beg);  // order-independent bound (see GridGeom::det)
     int e_sum = 0, e_max = 0;
     (void)frexp(m * (T)(MaxWeight<ORDER>::value * 1.001), &e_sum);
     (void)frexp(x * (T)1.001, &e_max);
@@ -2058,6 +2060,7 @@ __global__ void __launch_bounds__(256) k_deposit_yee_tiled(GridGeom g, TileGeom 
       m += red[c * kWaves + w];
       x = fmax(x, redm[c * kWaves + w]);
     }
+    if (g.det) m = x * (T)(end - beg);  // order-independent bound (see GridGeom::det)
     int e_sum = 0, e_max = 0;
     (void)frexp(m * (T)(MaxWeight<ORDER>::value * 1.001), &e_sum);
     (void)frexp(x * (T)1.001, &e_max);

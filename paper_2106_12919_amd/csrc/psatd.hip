@@ -35,7 +35,13 @@ namespace {
 // from the start values, into NOD (Yee-grid spectra), [k]_s = -i D+ for the charge term:
 //   <bx> = Psi1 bx + Psi2 (D+y ez - D+z ey) + Y1 (D+y jz - D+z jy)
 //   <ex> = Psi1 ex - Psi2 (D-y bz - D-z by) + Y4 jx - i (Y3 ro + Y2 rn) D+x.
-template <typename T, bool SPECTRAL, bool GAL, bool AVG = false>
+// CC (standard update): the current is first projected onto the Fourier-space continuity
+// equation of App. A, (rho^{n+1} - rho^n)/dt + i [k]_s . J = 0, with the update's own [k]_s.
+// In the paper's convention J' = J - [k]_s ([k]_s . J - i (rn - ro)/dt) / |[k]_s|^2; with the
+// index-space operators (D-_d D+_d = -[k_d]_s^2, |D+_d| = |[k_d]_s|) that is
+//   R = D-x jx + D-y jy + D-z jz + (rn - ro)/dt,   j_d' = j_d + D+_d R / |D+|^2,
+// and modes with |D+| = 0 (k = 0, the nodal solver's Nyquist planes) keep J.
+template <typename T, bool SPECTRAL, bool GAL, bool AVG = false, bool CC = false>
 __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cplx<T>*> F, Batch<const cplx<T>*> S,
                                                       Batch<cplx<T>*> NOD, int nx, int ny, int nzh, int pz) {
   const long long total = (long long)nx * ny * nzh;
@@ -83,6 +89,17 @@ __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cp
     jz = cmul(jz, tcz);
   }
   const cplx<T> ro = S.p[3][a], rn = S.p[4][a];
+  if (CC) {
+    const T k2 = px.x * px.x + px.y * px.y + py.x * py.x + py.y * py.y + pzd.x * pzd.x + pzd.y * pzd.y;
+    if (k2 > (T)0) {
+      const cplx<T> R =
+          cadd(cadd(cadd(cmul(mx, jx), cmul(my, jy)), cmul(mz, jz)), cscale(csub(rn, ro), t.inv_dt));
+      const cplx<T> f = cscale(R, (T)1 / k2);
+      jx = cadd(jx, cmul(px, f));
+      jy = cadd(jy, cmul(py, f));
+      jz = cadd(jz, cmul(pzd, f));
+    }
+  }
 
   // B update: curl terms with D+ (E, J live on edges; B on faces)
   const cplx<T> cEx = csub(cmul(py, ez), cmul(pzd, ey));
@@ -141,7 +158,9 @@ __global__ void __launch_bounds__(256) k_psatd_update(PsatdTables<T> t, Batch<cp
 // and rho^{n+1} (4).  With a x v = A_a v, (A_a)^H w = -(conj a) x w, so
 //   lE = C lE' + Sw (conj D+ x lB'),   lB = C lB' - Sw (conj D- x lE'),
 //   lJ = -X1 (conj D+ x lB') - Sw lE',  lro = X3 conj D+ . lE',  lrn = -X2 conj D+ . lE'.
-template <typename T>
+// CC: then the transpose of the current correction j' = j + D+ (D- . j + (rn - ro)/dt)/|D+|^2:
+//   s = conj D+ . lJ / |D+|^2,  lJ += conj D- s,  lrn += s/dt,  lro -= s/dt.
+template <typename T, bool CC = false>
 __global__ void __launch_bounds__(256) k_psatd_adjoint(PsatdTables<T> t, Batch<cplx<T>*> F, Batch<cplx<T>*> A, int nx,
                                                        int ny, int nzh, int pz) {
   const long long total = (long long)nx * ny * nzh;
@@ -171,11 +190,26 @@ __global__ void __launch_bounds__(256) k_psatd_adjoint(PsatdTables<T> t, Batch<c
   F.p[3][a] = csub(cscale(bx, C), cscale(mEx, Sw));
   F.p[4][a] = csub(cscale(by, C), cscale(mEy, Sw));
   F.p[5][a] = csub(cscale(bz, C), cscale(mEz, Sw));
-  A.p[0][a] = csub(cscale(pBx, -X1), cscale(ex, Sw));
-  A.p[1][a] = csub(cscale(pBy, -X1), cscale(ey, Sw));
-  A.p[2][a] = csub(cscale(pBz, -X1), cscale(ez, Sw));
-  A.p[3][a] = cscale(dE, X3);
-  A.p[4][a] = cscale(dE, -X2);
+  cplx<T> lj[3] = {csub(cscale(pBx, -X1), cscale(ex, Sw)), csub(cscale(pBy, -X1), cscale(ey, Sw)),
+                   csub(cscale(pBz, -X1), cscale(ez, Sw))};
+  cplx<T> lro = cscale(dE, X3), lrn = cscale(dE, -X2);
+  if (CC) {
+    const T k2 = px.x * px.x + px.y * px.y + py.x * py.x + py.y * py.y + pzd.x * pzd.x + pzd.y * pzd.y;
+    if (k2 > (T)0) {
+      const cplx<T> sj = cscale(cadd(cadd(cmul(px, lj[0]), cmul(py, lj[1])), cmul(pzd, lj[2])), (T)1 / k2);
+      lj[0] = cadd(lj[0], cmul(mx, sj));
+      lj[1] = cadd(lj[1], cmul(my, sj));
+      lj[2] = cadd(lj[2], cmul(mz, sj));
+      const cplx<T> sd = cscale(sj, t.inv_dt);
+      lrn = cadd(lrn, sd);
+      lro = csub(lro, sd);
+    }
+  }
+  A.p[0][a] = lj[0];
+  A.p[1][a] = lj[1];
+  A.p[2][a] = lj[2];
+  A.p[3][a] = lro;
+  A.p[4][a] = lrn;
 }
 
 }  // namespace
@@ -192,8 +226,11 @@ void psatd_adjoint(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const 
   A.p[3] = rho_old;
   A.p[4] = rho_new;
   const long long total = (long long)nx * ny * nzh;
-  hipLaunchKernelGGL((k_psatd_adjoint<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, t, F, A, nx, ny,
-                     nzh, pz);
+  const dim3 grid((unsigned)((total + 255) / 256));
+  if (t.cc)
+    hipLaunchKernelGGL((k_psatd_adjoint<T, true>), grid, dim3(256), 0, s, t, F, A, nx, ny, nzh, pz);
+  else
+    hipLaunchKernelGGL((k_psatd_adjoint<T, false>), grid, dim3(256), 0, s, t, F, A, nx, ny, nzh, pz);
 }
 
 template <typename T>
@@ -214,12 +251,18 @@ void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B
     for (int q = 0; q < 6; ++q) N.p[q] = nodal[q];
   const long long total = (long long)nx * ny * nzh;
   const dim3 grid((unsigned)((total + 255) / 256));
-  if (nodal && !t.Av[0])  // spectral centering (standard PSATD only)
+  if (nodal && !t.Av[0] && t.cc)  // spectral centering (standard PSATD only), current correction
+    hipLaunchKernelGGL((k_psatd_update<T, true, false, false, true>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh,
+                       pz);
+  else if (nodal && !t.Av[0])  // spectral centering (standard PSATD only)
     hipLaunchKernelGGL((k_psatd_update<T, true, false>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
   else if (t.Av[0])
     hipLaunchKernelGGL((k_psatd_update<T, false, true, true>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
   else if (t.G[0])
     hipLaunchKernelGGL((k_psatd_update<T, false, true>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
+  else if (t.cc)
+    hipLaunchKernelGGL((k_psatd_update<T, false, false, false, true>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh,
+                       pz);
   else
     hipLaunchKernelGGL((k_psatd_update<T, false, false>), grid, dim3(256), 0, s, t, F, S, N, nx, ny, nzh, pz);
 }

@@ -336,7 +336,7 @@ FastDiv make_fastdiv(uint32_t d) {
 
 GridGeom make_geom(int nx, int ny, int nz, double dx, double dy, double dz, double dt, int shape_order) {
   GridGeom g{nx, ny, nz, dx, dy, dz, dt, shape_order, make_fastdiv((uint32_t)ny), make_fastdiv((uint32_t)nz),
-             0.0, 0.0, 0.0};
+             0.0, 0.0, 0.0, 0};
   return g;
 }
 

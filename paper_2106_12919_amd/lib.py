@@ -22,11 +22,13 @@ PIC_F32, PIC_F64 = 0, 1
 PIC_N2S, PIC_S2N = 0, 1
 PIC_J, PIC_E, PIC_B = 0, 1, 2
 PIC_DEP_RHO_AND_J, PIC_DEP_RHO_ONLY = 0, 1
-PIC_SPECTRAL_CENTERING = 1 << 0
-PIC_NODAL_SOLVER = 1 << 1
-PIC_KEEP_ORDER = 1 << 2
-PIC_AVERAGED = 1 << 3
-PIC_STAGGERED_CYCLE = 1 << 4
+PIC_CURRENT_CORRECTION = 1 << 0
+PIC_DETERMINISTIC = 1 << 1
+PIC_SPECTRAL_CENTERING = 1 << 2
+PIC_NODAL_SOLVER = 1 << 3
+PIC_KEEP_ORDER = 1 << 4
+PIC_AVERAGED = 1 << 5
+PIC_STAGGERED_CYCLE = 1 << 6
 
 
 class pic_params(Structure):

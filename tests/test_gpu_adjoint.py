@@ -18,12 +18,13 @@ from paper_2106_12919_amd import inputs  # noqa: E402
 from paper_2106_12919_amd import lib as piclib  # noqa: E402
 
 
-@pytest.mark.parametrize("nodal", [False, True])
-def test_field_adjoint_matches_oracle_transpose(nodal):
-    banner(f"psatd_push_fields_adjoint vs brute-force oracle transpose, 8^3 FP64, nodal={nodal}")
+@pytest.mark.parametrize("nodal,correction", [(False, False), (True, False), (False, True), (True, True)])
+def test_field_adjoint_matches_oracle_transpose(nodal, correction):
+    banner(f"psatd_push_fields_adjoint vs brute-force oracle transpose, 8^3 FP64, nodal={nodal} "
+           f"correction={correction}")
     shape = (8, 8, 8)
-    flags = piclib.PIC_NODAL_SOLVER if nodal else 0
-    p = ostep.Params(shape, (1.0, 1.0, 1.0), 0.6, 1, 8, 16, nodal=nodal)
+    flags = (piclib.PIC_NODAL_SOLVER if nodal else 0) | (piclib.PIC_CURRENT_CORRECTION if correction else 0)
+    p = ostep.Params(shape, (1.0, 1.0, 1.0), 0.6, 1, 8, 16, nodal=nodal, current_correction=correction)
     ctx = piclib.Context(shape, (1.0, 1.0, 1.0), 0.6, 1, 8, 16, "f64", flags=flags)
     lam = inputs.random_grid(shape, seed=11, count=6)
     f = piclib.Fields(shape, "f64")

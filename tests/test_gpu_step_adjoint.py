@@ -21,17 +21,19 @@ from paper_2106_12919_amd import lib as piclib  # noqa: E402
 TD = {"f32": torch.float32, "f64": torch.float64}
 
 
-def _setup(shape, order, dtype, nodal=False, seed=7, ppc=2, field_amp=0.05, u_th=0.05):
+def _setup(shape, order, dtype, nodal=False, seed=7, ppc=2, field_amp=0.05, u_th=0.05, correction=False):
     wl = inputs.small(shape, ppc=ppc, shape_order=order, center_order=4, dtype=dtype, seed=seed,
                       field_amp=field_amp, u_th=u_th)
     flags = piclib.PIC_KEEP_ORDER | (piclib.PIC_NODAL_SOLVER if nodal else 0)
+    flags |= piclib.PIC_CURRENT_CORRECTION if correction else 0
     ctx = piclib.Context.for_workload(wl, flags=flags)
     f = piclib.Fields(shape, dtype)
     put(f.E_stag, rounded(wl.E, dtype))
     put(f.B_stag, rounded(wl.B, dtype))
     el = piclib.Species.from_host(wl.electrons, shape, dtype)
     ions = piclib.Species.from_host(wl.ions, shape, dtype)
-    p = ostep.Params(shape, wl.spacing, wl.dt, order, wl.center_order, wl.psatd_order, nodal=nodal)
+    p = ostep.Params(shape, wl.spacing, wl.dt, order, wl.center_order, wl.psatd_order, nodal=nodal,
+                     current_correction=correction)
     return wl, ctx, f, el, ions, p
 
 
@@ -68,12 +70,15 @@ def _device_adjoint(sp, gpos, gu, spacing, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("order,nodal", [(1, False), (3, False), (3, True)])
-def test_step_adjoint_matches_oracle(dtype, order, nodal):
-    """Every adjoint array elementwise against the oracle's reverse mode (FP64 inputs rounded to dtype)."""
+@pytest.mark.parametrize("order,nodal,correction", [(1, False, False), (3, False, False), (3, True, False),
+                                                    (3, False, True), (1, True, True)])
+def test_step_adjoint_matches_oracle(dtype, order, nodal, correction):
+    """Every adjoint array elementwise against the oracle's reverse mode (FP64 inputs rounded to dtype);
+    with PIC_CURRENT_CORRECTION the transposed projection of the current is part of the map."""
     shape = (16, 16, 24)
-    banner(f"pic_step_adjoint vs oracle step_vjp, dtype={dtype} order={order} nodal={nodal} shape={shape}")
-    wl, ctx, f, el, ions, p = _setup(shape, order, dtype, nodal, field_amp=0.2, u_th=0.3)
+    banner(f"pic_step_adjoint vs oracle step_vjp, dtype={dtype} order={order} nodal={nodal} "
+           f"correction={correction} shape={shape}")
+    wl, ctx, f, el, ions, p = _setup(shape, order, dtype, nodal, field_amp=0.2, u_th=0.3, correction=correction)
     rng = np.random.default_rng(31 + order)
     species = [el, ions]
     lam_host = {"E": rounded([rng.standard_normal(shape) for _ in range(3)], dtype),

@@ -69,6 +69,9 @@ def good_params(**kw):
     (dict(flags=piclib.PIC_STAGGERED_CYCLE | piclib.PIC_NODAL_SOLVER), piclib.PIC_EUNSUPPORTED),
     (dict(flags=piclib.PIC_STAGGERED_CYCLE | piclib.PIC_AVERAGED), piclib.PIC_EUNSUPPORTED),
     (dict(v_gal=(0.0, 0.0, 0.5), flags=piclib.PIC_SPECTRAL_CENTERING), piclib.PIC_EUNSUPPORTED),
+    (dict(v_gal=(0.0, 0.0, -0.4), flags=piclib.PIC_CURRENT_CORRECTION), piclib.PIC_EUNSUPPORTED),
+    (dict(flags=piclib.PIC_CURRENT_CORRECTION | piclib.PIC_AVERAGED), piclib.PIC_EUNSUPPORTED),
+    (dict(flags=piclib.PIC_CURRENT_CORRECTION | piclib.PIC_NODAL_SOLVER, psatd_order=0), piclib.PIC_EUNSUPPORTED),
 ])
 def test_init_rejects_bad_params(kw, code):
     lib = piclib.load()
@@ -83,10 +86,10 @@ def test_init_rejects_bad_params(kw, code):
 def test_init_rejects_flags_and_dtype():
     lib = piclib.load()
     p = good_params()
-    p.flags = 1 << 5  # an undefined bit (PIC_SPECTRAL_CENTERING is bit 0)
+    p.flags = 1 << 7  # an undefined bit (the flags of pic.h are bits 0..6)
     ctx = ctypes.c_void_p()
     assert lib.pic_init(ctypes.byref(p), None, ctypes.byref(ctx)) == piclib.PIC_EINVAL
-    p.flags = piclib.PIC_SPECTRAL_CENTERING | (1 << 1)
+    p.flags = piclib.PIC_SPECTRAL_CENTERING | piclib.PIC_NODAL_SOLVER
     assert lib.pic_init(ctypes.byref(p), None, ctypes.byref(ctx)) == piclib.PIC_EINVAL
     p = good_params()
     p.dtype = 7
