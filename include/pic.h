@@ -195,6 +195,18 @@ pic_status pic_set_stream(pic_ctx ctx, void* hip_stream);
 pic_status pic_deposit(pic_ctx ctx, const pic_species* sp, int nsp, pic_fields* f, int mode);
 /* (With PIC_STAGGERED_CYCLE: J^d onto the Yee positions of J^d, into f->J_stag; see the flag.) */
 
+/* pic_deposit for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments, results and kernels as
+ * pic_deposit (hybrid cycle), but the per-call tile sort of each species (two int32 per
+ * particle), which pic_deposit keeps in context scratch allocated on a species' first use, lives
+ * in a static device array of 32 MiB that the library holds on each GPU until the process ends;
+ * the call itself allocates and frees nothing (pic_init, which allocates, must have run).
+ * Limits and errors: at most 4,194,304 particles per species per call (PIC_EUNSUPPORTED beyond);
+ * PIC_EUNSUPPORTED with PIC_STAGGERED_CYCLE; PIC_EHIP if the array's device address could not be
+ * taken at pic_init.  Every call on one GPU (any context, any stream) shares that array: calls
+ * that overlap in time on one GPU race and must be ordered by the caller. */
+pic_status pic_deposit_noalloc(pic_ctx ctx, const pic_species* sp, int nsp, pic_fields* f, int mode);
+
 /* Finite-order centering (Sec. 3, eq. staggered_finite_sum, order center_order):
  *   dir = PIC_N2S, what = PIC_J : J_nod -> J_stag, J^d along axis d,
  *         f_{j+1/2} = sum_n alpha^s_{m,n} (f_{j+n} + f_{j+1-n}) / 2;

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -12,9 +13,42 @@
 
 using namespace pic;
 
+// Scratch of pic_deposit_noalloc: the per-call tile sort of each species (the slot of every
+// particle and its inverse, two int32 per particle) for callers that cannot allocate device
+// memory.  A file-scope device array: each GPU the library runs on holds its own copy until the
+// process ends, and every call on that GPU shares it.  Host code reaches it only through the
+// per-device address hipGetSymbolAddress returns (scratch_address below), never by its name.
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+constexpr int64_t kNoAllocMaxParticles = (int64_t)(kNoAllocScratchBytes / (2 * sizeof(int)));
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_init_error;
+
+// Device address of `scratch` on each device, taken once per device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* scratch_address(int dev, std::string& err) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) {
+    err = "device index beyond the scratch table";
+    return nullptr;
+  }
+  if (!g_scratch_ptr[dev]) {
+    void* q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !q) {
+      (void)hipGetLastError();
+      err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = q;
+  }
+  return g_scratch_ptr[dev];
+}
 
 const char* const kStageNames[] = {"center_s2n",   "gather_push", "deposit",       "center_n2s", "fft_forward",
                                    "psatd_update", "fft_inverse", "entry_forward", "tile_sort",  "clear_sources",
@@ -58,6 +92,8 @@ struct pic_ctx_s {
   int64_t stage_count[kNumStages] = {0};
   double* d_acc = nullptr;  // 2 doubles for reductions
   int* d_bad = nullptr;     // count of particles skipped for an out-of-range cell index
+  void* noalloc = nullptr;  // this device's copy of `scratch` (pic_deposit_noalloc), or null
+  std::string noalloc_err;
 
   pic_status fail(pic_status s, const std::string& msg) {
     err = msg;
@@ -629,8 +665,10 @@ pic_status deposit_yee_all(pic_ctx c, const pic_species* sp, int nsp, pic_fields
   return PIC_OK;
 }
 
+// sort_idx: null = each species' sort indices in the context's species scratch (allocated on
+// first use); else 2 n int32 of caller-provided device memory (pic_deposit_noalloc).
 template <typename T>
-pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, int mode) {
+pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, int mode, int* sort_idx = nullptr) {
   Engine<T>& e = static_cast<Engine<T>&>(*c->eng);
   const bool with_j = (mode == PIC_DEP_RHO_AND_J);
   if (yee_cycle(c->p)) {
@@ -644,16 +682,20 @@ pic_status do_deposit(pic_ctx c, const pic_species* sp, int nsp, pic_fields* f, 
   const GridGeom g = geom(c->p);
   for (int s = 0; s < nsp; ++s) {
     if (sp[s].n == 0) continue;
-    hipError_t he = e.ensure_species((size_t)s, sp[s].n);
-    if (he != hipSuccess) return c->fail(PIC_ENOMEM, std::string("pic_deposit: ") + hipGetErrorString(he));
-    SpeciesScratch<T>& x = e.sps[s];
+    int *dst = sort_idx, *perm = sort_idx ? sort_idx + sp[s].n : nullptr;
+    if (!sort_idx) {
+      hipError_t he = e.ensure_species((size_t)s, sp[s].n);
+      if (he != hipSuccess) return c->fail(PIC_ENOMEM, std::string("pic_deposit: ") + hipGetErrorString(he));
+      dst = e.sps[s].dst;
+      perm = e.sps[s].perm;
+    }
     const SpeciesView<T> v = view<T>(sp[s]);
     // visit the caller's particles in tile order through a permutation (caller order untouched)
-    tile_sort(g, e.tiles, v.cell, v.n, e.t_counts, e.t_starts, e.t_cursor, x.dst, c->d_bad, c->stream);
-    invert_perm(x.dst, x.perm, v.n, c->stream);
+    tile_sort(g, e.tiles, v.cell, v.n, e.t_counts, e.t_starts, e.t_cursor, dst, c->d_bad, c->stream);
+    invert_perm(dst, perm, v.n, c->stream);
     const bool mobile = std::isfinite(sp[s].m);
     int* flag = sum.begin();
-    deposit_tiled<T>(g, e.tiles, v, x.perm, e.t_starts, with_j && mobile, e.stage, c->d_bad, nullptr, nullptr, e.work,
+    deposit_tiled<T>(g, e.tiles, v, perm, e.t_starts, with_j && mobile, e.stage, c->d_bad, nullptr, nullptr, e.work,
                      sum.spill_rho(), sum.spill_j(), c->stream, flag, e.box_faces);
     deposit_reduce<T>(g, e.tiles, e.t_starts, e.stage, with_j && mobile, static_cast<T*>(f->rho_new), J, c->stream,
                       sum.reduce_args(with_j && mobile));
@@ -1329,6 +1371,8 @@ pic_status pic_init(const pic_params* p, void* hip_stream, pic_ctx* out) {
     g_init_error = "no HIP device";
     return PIC_EHIP;
   }
+  // this device's copy of the no-allocation scratch (an error is reported by pic_deposit_noalloc)
+  c->noalloc = scratch_address(c->device, c->noalloc_err);
   const int m = p->center_order / 2;
   c->ccoef.resize(m);
   alpha_staggered(m, c->ccoef.data());
@@ -1385,6 +1429,23 @@ pic_status pic_deposit(pic_ctx ctx, const pic_species* sp, int nsp, pic_fields* 
   if ((st = check_fields(ctx, f, false, false, false, false, wj && !yee, wj && yee, false, true)) != PIC_OK)
     return st;
   return PIC_DISPATCH(ctx, do_deposit, sp, nsp, f, mode);
+}
+
+pic_status pic_deposit_noalloc(pic_ctx ctx, const pic_species* sp, int nsp, pic_fields* f, int mode) {
+  pic_status st = device_ok(ctx);
+  if (st != PIC_OK) return st;
+  if (mode != PIC_DEP_RHO_AND_J && mode != PIC_DEP_RHO_ONLY) return ctx->fail(PIC_EINVAL, "bad deposit mode");
+  if (yee_cycle(ctx->p))
+    return ctx->fail(PIC_EUNSUPPORTED, "pic_deposit_noalloc: not with PIC_STAGGERED_CYCLE");
+  if ((st = check_species(ctx, sp, nsp)) != PIC_OK) return st;
+  for (int s = 0; s < nsp; ++s)
+    if (sp[s].n > kNoAllocMaxParticles)
+      return ctx->fail(PIC_EUNSUPPORTED, "pic_deposit_noalloc: more than " + std::to_string(kNoAllocMaxParticles) +
+                                             " particles in one species (the size of its static scratch)");
+  if (!ctx->noalloc) return ctx->fail(PIC_EHIP, "pic_deposit_noalloc: " + ctx->noalloc_err);
+  const bool wj = mode == PIC_DEP_RHO_AND_J;
+  if ((st = check_fields(ctx, f, false, false, false, false, wj, false, false, true)) != PIC_OK) return st;
+  return PIC_DISPATCH(ctx, do_deposit, sp, nsp, f, mode, static_cast<int*>(ctx->noalloc));
 }
 
 pic_status pic_center(pic_ctx ctx, int dir, int what, pic_fields* f) {

@@ -73,6 +73,7 @@ def load():
         "pic_destroy": (c_int, [c_void_p]),
         "pic_set_stream": (c_int, [c_void_p, c_void_p]),
         "pic_deposit": (c_int, [c_void_p, POINTER(pic_species), c_int, POINTER(pic_fields), c_int]),
+        "pic_deposit_noalloc": (c_int, [c_void_p, POINTER(pic_species), c_int, POINTER(pic_fields), c_int]),
         "pic_center": (c_int, [c_void_p, c_int, c_int, POINTER(pic_fields)]),
         "psatd_push_fields": (c_int, [c_void_p, POINTER(pic_fields)]),
         "psatd_push_fields_adjoint": (c_int, [c_void_p, POINTER(pic_fields)]),
@@ -146,6 +147,11 @@ def _species_array(species):
 def pic_deposit(ctx, species, fields, mode=PIC_DEP_RHO_AND_J):
     arr = _species_array(species)
     _check(load().pic_deposit(ctx, arr, len(species), ctypes.byref(fields.struct()), mode), ctx)
+
+
+def pic_deposit_noalloc(ctx, species, fields, mode=PIC_DEP_RHO_AND_J):
+    arr = _species_array(species)
+    _check(load().pic_deposit_noalloc(ctx, arr, len(species), ctypes.byref(fields.struct()), mode), ctx)
 
 
 def pic_center(ctx, direction, what, fields):
