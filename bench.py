@@ -1,28 +1,31 @@
 #!/usr/bin/env python
 """Throughput of the hybrid nodal-staggered PSATD PIC step on one MI355X.
 
-Workload (default): 128x128x256 periodic grid, Gaussian laser (wavelength 16
-cells, a0 = 2, waist 20, FWHM duration 30, x-polarised, +z) entering a cold
-electron plasma at 2 particles/cell for z >= 64 (6,291,456 macro-particles),
-immobile ions as a static background, cubic B-spline shape, centering order 16,
-PSATD order 16, c*dt = 0.5 cell, float32 fields and particles (FP64-built
-tables).  Synthetic and seeded (paper_2106_12919_amd.inputs).
+Workload (default, the largest configuration that fits one GPU): beam-driven wake on a
+384x384x768 periodic grid (113,246,208 cells): cold plasma at 1 particle per cell (n0 = 2/256)
+plus an electron drive beam (Gaussian, sigma_r = 8, sigma_z = 16 cells, gamma = 1000, 8 particles
+per cell inside 3 sigma) with its relativistic self-fields, 114,172,416 macro-particles, immobile
+ions as a static background, cubic B-spline shape, centering order 16, PSATD order 16,
+c*dt = 0.5 cell, float32 fields and particles (FP64-built tables).  Synthetic and seeded
+(paper_2106_12919_amd.inputs).
 
-One "step" is one full hybrid cycle: staggered-to-nodal centering of E, B ->
-gather + Boris push -> deposition of rho, J -> nodal-to-staggered centering of
-J -> forward FFTs of J, rho -> per-mode PSATD update -> inverse FFTs of E, B.
-The timed region is a single pic_step call of K steps with every input
-resident in HBM (E, B stay in Fourier space between steps; the call's entry
+One "step" is one full hybrid cycle: staggered-to-nodal centering of E, B -> gather + Boris push
+-> deposition of rho, J -> nodal-to-staggered centering of J -> forward FFTs of J, rho -> per-mode
+PSATD update -> inverse FFTs of E, B.  The timed region is a single pic_step call of K steps with
+every input resident in HBM (E, B stay in Fourier space between steps; the call's entry
 transforms are inside the timed region).
 
-Prints one JSON line.  Rates: particle-pushes/s = Np*K/T (``value``) and grid
-cell updates/s = N*K/T.  ``roofline`` is the dominant stage's algorithmic bytes
-per launch over its mean duration, timed with HIP events on the stream the
-library launches on.  ``lds_atomic_floor`` sets the deposition's mean duration
-against the time its LDS atomics alone take at the rates a probe measured on
-MI355X (the deposition is bound by those, not by HBM).  ``cpu_baseline`` times the FP64 NumPy oracle on the host
-on a bounded sample (the full grid part of one step plus 1/8 of the particles;
-the particle part is scaled by 8, it is linear in the particle count).
+Prints one JSON line.  Rates: particle-pushes/s = Np*K/T (``value``) and grid cell updates/s =
+N*K/T.  ``roofline`` is the dominant stage's algorithmic bytes per launch over its mean duration,
+timed with HIP events on the stream the library launches on.  ``lds_atomic_floor`` sets the
+deposition's mean duration against the time its LDS atomics alone take at the rates a probe
+measured on MI355X.  Further keys: ``fp64`` (the same workload in FP64, with the FP32 run's
+field and energy error against it), ``thermal256_sweep`` (the 256^3 CIC thermal plasma at
+centering orders 2..32 in FP32 and FP64, with the FP32 error against FP64 per order),
+``fwd_bwd`` (forward + backward of the 64x64x128 laser workload, 60 steps, kinetic-energy loss)
+and ``fwd_bwd_beam`` (of the beam-driven wake, beam-energy-loss objective), and
+``cpu_baseline``: the FP64 NumPy oracle on the host cores on a bounded sample (two steps of the
+beam-driven wake at 1/4 scale per axis; the particle part split over worker processes).
 """
 
 import argparse
@@ -54,7 +57,9 @@ def deposit_lds_floor_ms(Np, shape_order, dtype):
     return clocks_per_cu / CLOCK_HZ * 1e3
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "laser128_f32_hbm_traffic.md")
+def traffic_profile(config_name, dtype):
+    """The committed HBM-counter summary of a workload's bench command (FETCH_SIZE, WRITE_SIZE)."""
+    return os.path.join(ROOT, "profiles", f"{config_name}_{dtype}_hbm_traffic.md")
 
 
 def kernel_source_hash():
@@ -68,11 +73,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(stage):
+def recorded_traffic(stage, config_name="beam384", dtype="f32"):
     """Measured HBM bytes per launch of ``stage`` from the committed counter summary, or None
     when there is none or the kernel sources changed since the counters were taken."""
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(traffic_profile(config_name, dtype)).read()
         block = text.split("```json", 1)[1].split("```", 1)[0]
         rec = json.loads(block)
     except (OSError, IndexError, ValueError):
@@ -118,56 +123,104 @@ def stage_bytes(stage, N, M, Np, s):
     }[stage]
 
 
-def cpu_baseline(wl, Np):
-    """FP64 oracle on the host: grid part of one step + 1/8 of the particles, particle part scaled by 8."""
+# ------------------------------------------------------------------ CPU baseline (the oracle)
+
+_CPU = {}  # what the worker processes of the CPU baseline inherit (set before the pool forks)
+
+
+def _cpu_particle_part(k):
+    """Worker k of the CPU baseline: gather + push and deposition of its slice of the particles."""
+    from oracle import step as ostep
+    c = _CPU
+    n = c["sp"]["pos"].shape[0]
+    sel = slice(k * n // c["workers"], (k + 1) * n // c["workers"])
+    sp = {key: (val[sel] if key in ("pos", "u", "w") else val) for key, val in c["sp"].items()}
+    sp["pos"], sp["u"] = sp["pos"].copy(), sp["u"].copy()
+    v, pos_half = ostep.gather_push(sp, c["E_nod"], c["B_nod"], c["p"])
+    rho = ostep.deposit_rho([sp], c["p"])
+    J = ostep.deposit_current(sp, v, pos_half, c["p"])
+    return rho, J, sp["pos"], sp["u"]
+
+
+def cpu_workers():
+    """The host cores of this GPU's share (at most 16, whatever the machine's total)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(config_name="beam96", steps=2, workers=None):
+    """FP64 oracle on the host, timed over ``steps`` whole hybrid cycles of a bounded workload: the
+    grid part (centering, transforms, field solve) in this process, the particle part (gather +
+    push, deposition) split over ``workers`` forked processes.  Runs before anything touches the
+    GPU (the workers are forked from this process)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
     import numpy as np
 
     from oracle import step as ostep
+    from paper_2106_12919_amd import inputs
 
+    workers = workers or cpu_workers()
+    wl = inputs.config(config_name, dtype="f64")
     p = ostep.Params(wl.shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order)
-    frac = 8
-    sel = slice(0, wl.electrons.n // frac)
-    sp = {"pos": wl.electrons.positions(wl.spacing)[sel], "u": wl.electrons.u[sel].copy(),
-          "w": wl.electrons.w[sel], "q": wl.electrons.q, "m": wl.electrons.m}
-    r0 = resource.getrusage(resource.RUSAGE_SELF)
-    t0 = time.perf_counter()
-    E_nod, B_nod = ostep.center_fields_s2n(wl.E, wl.B, p)
-    t1 = time.perf_counter()
-    v, pos_half = ostep.gather_push(sp, E_nod, B_nod, p)
-    rho_new = ostep.deposit_rho([sp], p)
-    J_nod = ostep.deposit_current(sp, v, pos_half, p)
-    t2 = time.perf_counter()
-    J_stag = ostep.center_current_n2s(J_nod, p)
-    ostep.push_fields(wl.E, wl.B, J_stag, np.zeros(wl.shape), rho_new, p)
-    t3 = time.perf_counter()
-    r1 = resource.getrusage(resource.RUSAGE_SELF)
-    grid_s = (t1 - t0) + (t3 - t2)
-    part_s = (t2 - t1) * frac
-    step_s = grid_s + part_s
-    cpu_s = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    cores = max(1, round(cpu_s / (t3 - t0)))
+    sp = {"pos": wl.electrons.positions(wl.spacing), "u": wl.electrons.u.copy(), "w": wl.electrons.w,
+          "q": wl.electrons.q, "m": wl.electrons.m}
+    ions = {"pos": wl.ions.positions(wl.spacing), "u": wl.ions.u, "w": wl.ions.w, "q": 1.0, "m": np.inf}
+    rho_static = ostep.deposit_rho([ions], p)
+    state = {"E_stag": [np.array(a) for a in wl.E], "B_stag": [np.array(a) for a in wl.B],
+             "rho_old": ostep.deposit_rho([sp], p, rho_static)}
+    ctx = mp.get_context("fork")
+    ru = lambda: sum(getattr(resource.getrusage(w), f) for w in (resource.RUSAGE_SELF, resource.RUSAGE_CHILDREN)
+                     for f in ("ru_utime", "ru_stime"))
+    c0, t0 = ru(), time.perf_counter()
+    for _ in range(steps):
+        E_nod, B_nod = ostep.center_fields_s2n(state["E_stag"], state["B_stag"], p)
+        _CPU.update(sp=sp, E_nod=E_nod, B_nod=B_nod, p=p, workers=workers)
+        with ProcessPoolExecutor(workers, mp_context=ctx) as ex:
+            parts = list(ex.map(_cpu_particle_part, range(workers)))
+        rho_new = rho_static + sum(q[0] for q in parts)
+        J_nod = [sum(q[1][d] for q in parts) for d in range(3)]
+        sp["pos"] = np.concatenate([q[2] for q in parts])
+        sp["u"] = np.concatenate([q[3] for q in parts])
+        J_stag = ostep.center_current_n2s(J_nod, p)
+        E, B = ostep.push_fields(state["E_stag"], state["B_stag"], J_stag, state["rho_old"], rho_new, p)
+        state = {"E_stag": E, "B_stag": B, "rho_old": rho_new}
+    T, C = time.perf_counter() - t0, ru() - c0
+    _CPU.clear()
+    Np = wl.electrons.n
     return {
-        "value": Np / step_s, "unit": "particle-pushes/s", "cores": cores, "kind": "oracle",
-        "sample": f"one FP64 NumPy oracle step: full grid part ({grid_s:.1f} s) + particle part on "
-                  f"{wl.electrons.n // frac} of {wl.electrons.n} electrons ({t2 - t1:.1f} s, scaled x{frac}); "
-                  f"{step_s:.1f} s per step",
-        "cell_updates_per_s": wl.cells / step_s,
+        "value": Np * steps / T, "unit": "particle-pushes/s", "cores": max(1, round(C / T)), "kind": "oracle",
+        "sample": f"{steps} FP64 NumPy oracle steps of {config_name} ({wl.cells} cells, {Np} particles"
+                  + ("; the beam-driven wake at 1/4 scale per axis, the same per-cell physics" if config_name ==
+                     "beam96" else "") + f"), {T:.1f} s wall, {C:.1f} s CPU: grid part in one process, particle "
+                  f"part over {workers} worker processes",
+        "cell_updates_per_s": wl.cells * steps / T,
+        "workers": workers,
     }
 
+
+# ------------------------------------------------------------------ main
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="laser128", choices=sorted(CONFIG_TEXT))
+    ap.add_argument("--config", default="beam384", choices=sorted(CONFIG_TEXT))
     ap.add_argument("--dtype", default=None, choices=["f32", "f64"])
     ap.add_argument("--center-order", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--sweep-center-orders", default="", metavar="LIST",
-                    help="after the main measurement, time the same workload at each centering order of the "
-                         "comma-separated LIST ([sweep] lines on stderr, and JSON lines into --extra-json)")
-    ap.add_argument("--extra-json", default="", metavar="PATH")
+    ap.add_argument("--cpu-config", default="beam96", choices=sorted(CONFIG_TEXT),
+                    help="workload of the CPU oracle sample (default: the beam-driven wake at 1/4 scale)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 run of the main workload")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the 256^3 thermal plasma at centering orders 2..32 in FP32 and FP64")
+    ap.add_argument("--sweep-orders", default="2,4,8,16,32", metavar="LIST")
+    ap.add_argument("--sweep-steps", type=int, default=20)
     ap.add_argument("--spectral-centering", action="store_true",
                     help="apply the finite-order centering as its Fourier symbol inside the per-mode update "
                          "(PIC_SPECTRAL_CENTERING; same results up to rounding, no real-space centering passes)")
@@ -176,6 +229,8 @@ def main():
                          "no centering")
     ap.add_argument("--staggered-cycle", action="store_true",
                     help="run the fully staggered comparison cycle (PIC_STAGGERED_CYCLE) instead of the hybrid one")
+    ap.add_argument("--current-correction", action="store_true",
+                    help="project J onto the continuity equation before each field solve (PIC_CURRENT_CORRECTION)")
     ap.add_argument("--field-adjoint", action="store_true",
                     help="also time psatd_push_fields and its reverse mode psatd_push_fields_adjoint "
                          "(\"field_solve\" in the JSON line)")
@@ -184,13 +239,14 @@ def main():
     ap.add_argument("--averaged", action="store_true",
                     help="with --galilean: the averaged Galilean scheme (PIC_AVERAGED)")
     ap.add_argument("--no-adjoint", action="store_true",
-                    help="skip the forward+backward measurement of the differentiable workload (laser64, FP32, "
-                         "60 steps, kinetic-energy loss, checkpoints every 10 steps)")
+                    help="skip the forward+backward measurements (laser64 and the beam-driven wake)")
     ap.add_argument("--adjoint-config", default="laser64", choices=sorted(CONFIG_TEXT))
     ap.add_argument("--checkpoint-every", type=int, default=10)
     ap.add_argument("--adjoint-steps", type=int, default=0, metavar="K",
                     help="steps of the forward+backward run (default: the configuration's length)")
     ap.add_argument("--adjoint-reps", type=int, default=3)
+    ap.add_argument("--beam-adjoint-steps", type=int, default=20,
+                    help="steps of the beam-driven wake's forward+backward run (0: skip it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy a MIB-MiB float32 tensor 3 times (a plain copy kernel "
                          "of known size, the reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -201,22 +257,44 @@ def main():
               "the multi-GPU domain decomposition is described in DESIGN.md, not built.", file=sys.stderr)
         sys.exit(2)
 
+    cpu = None
+    if not args.no_cpu_baseline:  # first: its worker processes fork from this one, before any GPU use
+        print(f"[bench] timing the CPU oracle on {args.cpu_config} ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(args.cpu_config)
+        print(f"[bench] CPU oracle: {cpu['value']:.3e} pushes/s on {cpu['cores']} cores", file=sys.stderr,
+              flush=True)
+
     import torch
 
     from paper_2106_12919_amd import inputs
+    from paper_2106_12919_amd import lib as piclib
 
     torch.cuda.set_device(0)
     wl = inputs.config(args.config, dtype=args.dtype, center_order=args.center_order)
     print(f"[bench] workload {args.config} dtype={wl.dtype} cells={wl.cells} particles={wl.electrons.n}",
           file=sys.stderr, flush=True)
-    # PIC_SPECTRAL_CENTERING, PIC_NODAL_SOLVER, PIC_STAGGERED_CYCLE
-    flags = (1 if args.spectral_centering else 0) | (2 if args.nodal_solver else 0) | (16 if args.staggered_cycle else 0)
-    result = run_gpu(wl, args.config, args.steps, args.warmup, args.calibrate_copy, flags)
+    flags = ((piclib.PIC_SPECTRAL_CENTERING if args.spectral_centering else 0)
+             | (piclib.PIC_NODAL_SOLVER if args.nodal_solver else 0)
+             | (piclib.PIC_STAGGERED_CYCLE if args.staggered_cycle else 0)
+             | (piclib.PIC_CURRENT_CORRECTION if args.current_correction else 0))
+    keep = not args.no_fp64 and wl.dtype == "f32"
+    result, final32 = run_gpu(wl, args.config, args.steps, args.warmup, args.calibrate_copy, flags, keep=keep)
+    if keep:  # the same workload, steps and flags in FP64; the FP32 run's error against it
+        wl.dtype = "f64"
+        r64, final64 = run_gpu(wl, args.config, args.steps, args.warmup, 0, flags, keep=True)
+        wl.dtype = "f32"
+        result["fp64"] = {"value": r64["value"], "unit": "particle-pushes/s", "ms_per_step": r64["ms_per_step"],
+                          "cell_updates_per_s": r64["cell_updates_per_s"], "roofline": r64["roofline"],
+                          "stages": {k: v["ms_avg"] for k, v in r64["stages"].items()},
+                          "fp32_error_vs_fp64": field_errors(final32, final64, wl.spacing,
+                                                             steps=args.warmup + args.steps)}
+        del final32, final64
+        torch.cuda.empty_cache()
     if args.field_adjoint:
         result["field_solve"] = time_field_solve(wl, flags)
     if args.galilean is not None:
-        gflags = flags | (8 if args.averaged else 0)  # PIC_AVERAGED
-        r = run_gpu(wl, args.config, args.steps, args.warmup, 0, gflags, v_gal=(0.0, 0.0, args.galilean))
+        gflags = flags | (piclib.PIC_AVERAGED if args.averaged else 0)
+        r, _ = run_gpu(wl, args.config, args.steps, args.warmup, 0, gflags, v_gal=(0.0, 0.0, args.galilean))
         M = wl.shape[0] * wl.shape[1] * (wl.shape[2] // 2 + 1)
         s = 4 if wl.dtype == "f32" else 8
         # 11 spectra and 6 complex tables in, 6 spectra out (averaged: 6 more tables, 6 more spectra out)
@@ -226,25 +304,91 @@ def main():
                               "ms_per_step": r["ms_per_step"],
                               "value": r["value"], "stages": {k: v["ms_avg"] for k, v in r["stages"].items()},
                               "psatd_update_algo_bytes": upd, "psatd_update_GBps": round(upd / (ms * 1e-3) / 1e9, 1)}
+    del wl
+    if not args.no_sweep:
+        orders = [int(x) for x in args.sweep_orders.split(",") if x]
+        print(f"[bench] thermal256 at centering orders {orders}, FP32 and FP64 ...", file=sys.stderr, flush=True)
+        result["thermal256_sweep"] = sweep_thermal256(orders, args.sweep_steps)
     if not args.no_adjoint:
         print(f"[bench] forward+backward of {args.adjoint_config} ...", file=sys.stderr, flush=True)
         result["fwd_bwd"] = time_fwd_bwd(args.adjoint_config, args.checkpoint_every, reps=args.adjoint_reps,
                                          steps=args.adjoint_steps)
-    if args.sweep_center_orders:
-        for order in [int(x) for x in args.sweep_center_orders.split(",")]:
-            wl.center_order = order
-            r = run_gpu(wl, args.config, args.steps, args.warmup, 0, flags)
-            line = {"sweep": "center_order", "center_order": order, "dtype": wl.dtype, "value": r["value"],
-                    "ms_per_step": r["ms_per_step"], "cell_updates_per_s": r["cell_updates_per_s"],
-                    "stages": {k: v["ms_avg"] for k, v in r["stages"].items()}}
-            print("[sweep] " + json.dumps(line), file=sys.stderr, flush=True)
-            if args.extra_json:
-                with open(args.extra_json, "a") as fh:
-                    fh.write(json.dumps(line) + "\n")
-    if not args.no_cpu_baseline:
-        print("[bench] timing the CPU oracle sample ...", file=sys.stderr, flush=True)
-        result["cpu_baseline"] = cpu_baseline(wl, result["config"]["particles"])
+        if args.beam_adjoint_steps > 0:
+            print("[bench] forward+backward of beam384 (beam-energy-loss objective) ...", file=sys.stderr,
+                  flush=True)
+            result["fwd_bwd_beam"] = time_fwd_bwd("beam384", args.checkpoint_every, reps=1,
+                                                  steps=args.beam_adjoint_steps, loss="beam_energy_loss")
+    if cpu is not None:
+        result["cpu_baseline"] = cpu
     print(json.dumps(result))
+
+
+def field_errors(a, b, spacing, steps):
+    """FP32 fields ``a`` against FP64 fields ``b`` of the same run (dicts of E, B device tensors):
+    the largest max-norm and L2 (Sec. 5.2 eq. L2_norm_error) relative error over the six
+    components, and |W32 - W64| / W64 of the field energy (Sec. 2 item iii), accumulated in FP64."""
+    import torch
+    dV = spacing[0] * spacing[1] * spacing[2]
+    worst_max = worst_l2 = 0.0
+    W = [0.0, 0.0]
+    for name in ("E", "B"):
+        for x, y in zip(a[name], b[name]):
+            x64 = x.double()
+            d = x64 - y
+            ymax = float(torch.max(torch.abs(y)))
+            if ymax > 0:
+                worst_max = max(worst_max, float(torch.max(torch.abs(d))) / ymax)
+                worst_l2 = max(worst_l2, float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(y)))
+            W[0] += float(torch.sum(x64 * x64))
+            W[1] += float(torch.sum(y * y))
+            del x64, d
+    W = [0.5 * w * dV for w in W]
+    return {"after_steps": steps, "field_max_rel": worst_max, "field_l2_rel": worst_l2,
+            "W_rel": abs(W[0] - W[1]) / W[1] if W[1] > 0 else abs(W[0]), "reference": "the FP64 HIP path"}
+
+
+def sweep_thermal256(orders, steps, warmup=2):
+    """The 256^3 thermal plasma (134,217,728 particles, CIC) at each centering order in FP32 and
+    FP64: rates per dtype and order, and the FP32 run's field and energy error against the FP64 run
+    of the same order after the same steps.  Particles are uploaded once per dtype and restored from
+    a device copy before each run."""
+    import torch
+
+    from paper_2106_12919_amd import inputs
+    from paper_2106_12919_amd import lib as piclib
+
+    wl = inputs.config("thermal256")
+    out = {"workload": CONFIG_TEXT["thermal256"], "steps": steps, "warmup": warmup, "orders": {}}
+    dev = {}
+    for dtype in ("f32", "f64"):
+        el = piclib.Species.from_host(wl.electrons, wl.shape, dtype)
+        ions = piclib.Species.from_host(wl.ions, wl.shape, dtype)
+        dev[dtype] = (el, ions, el.cell.clone(), [t.clone() for t in el.off], [t.clone() for t in el.u],
+                      el.w.clone())
+    for order in orders:
+        wl.center_order = order
+        finals, row = {}, {}
+        for dtype in ("f32", "f64"):
+            el, ions, cell0, off0, u0, w0 = dev[dtype]
+            el.cell.copy_(cell0)
+            el.w.copy_(w0)
+            for d in range(3):
+                el.off[d].copy_(off0[d])
+                el.u[d].copy_(u0[d])
+            wl.dtype = dtype
+            r, fin = run_gpu(wl, "thermal256", steps, warmup, 0, 0, keep=True, species=(el, ions))
+            finals[dtype] = fin
+            row[dtype] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                          "cell_updates_per_s": r["cell_updates_per_s"],
+                          "stages": {k: v["ms_avg"] for k, v in r["stages"].items()},
+                          "roofline": r["roofline"]}
+            print(f"[sweep] order {order} {dtype}: {r['ms_per_step']:.3f} ms/step, {r['value']:.3e} pushes/s",
+                  file=sys.stderr, flush=True)
+        row["fp32_error_vs_fp64"] = field_errors(finals["f32"], finals["f64"], wl.spacing, steps + warmup)
+        out["orders"][str(order)] = row
+        del finals
+        torch.cuda.empty_cache()
+    return out
 
 
 def time_field_solve(wl, flags, reps=20):
@@ -272,12 +416,14 @@ def time_field_solve(wl, flags, reps=20):
     return out
 
 
-def time_fwd_bwd(config_name, every, reps=3, steps=0):
-    """Forward + backward of the differentiable workload: its full run (``steps`` of the config)
-    through autograd.PicSteps with checkpoints every ``every`` steps, the loss being the total
-    electron kinetic energy sum w (gamma - 1) at the end, gradients w.r.t. the initial E, B and
-    momenta; set against the same run of the production forward (pic_step, default flags).
-    Means of ``reps`` timed runs after one untimed run."""
+def time_fwd_bwd(config_name, every, reps=3, steps=0, loss="kinetic"):
+    """Forward + backward of a differentiable run: ``steps`` of the config (default its length)
+    through autograd.PicSteps with checkpoints every ``every`` steps, gradients w.r.t. the initial
+    E, B and momenta; set against the same run of the production forward (pic_step, default flags).
+    Losses: "kinetic", the total electron kinetic energy sum w (gamma - 1) at the end; and
+    "beam_energy_loss", the drive beam's energy loss sum_beam w (gamma^0 - gamma^end) (the beam's
+    particles follow the plasma's in the beam-driven wake's species).  Means of ``reps`` timed runs
+    after one untimed run."""
     import torch
 
     from paper_2106_12919_amd import autograd as pag
@@ -286,6 +432,7 @@ def time_fwd_bwd(config_name, every, reps=3, steps=0):
 
     wl = inputs.config(config_name)
     K = steps if steps > 0 else wl.steps
+    n_beam_start = wl.ions.n if loss == "beam_energy_loss" else 0  # the ions neutralise the plasma only
 
     def setup(flags):
         ctx = piclib.Context.for_workload(wl, flags=flags)
@@ -306,7 +453,7 @@ def time_fwd_bwd(config_name, every, reps=3, steps=0):
 
     ctx0, f0, el0 = setup(0)
     state0 = ([t.clone() for t in f0.E_stag], [t.clone() for t in f0.B_stag], f0.rho_old.clone(),
-              el0.cell.clone(), [t.clone() for t in el0.off], [t.clone() for t in el0.u])
+              el0.cell.clone(), [t.clone() for t in el0.off], [t.clone() for t in el0.u], el0.w.clone())
 
     def forward_only():
         for d in range(3):
@@ -316,14 +463,19 @@ def time_fwd_bwd(config_name, every, reps=3, steps=0):
             el0.u[d].copy_(state0[5][d])
         f0.rho_old.copy_(state0[2])
         el0.cell.copy_(state0[3])
+        el0.w.copy_(state0[6])
         piclib.pic_step(ctx0.ctx, f0, [el0], K)
 
     T_fwd = timed(forward_only)
     ctx0.close()
+    del state0, f0, el0
+    torch.cuda.empty_cache()
     ctx, f, el = setup(piclib.PIC_KEEP_ORDER)
     E_in, B_in, u_in = torch.stack(f.E_stag), torch.stack(f.B_stag), torch.stack(el.u)
     off_in = torch.stack(el.off)
     grads = {}
+    wb = el.w[n_beam_start:]
+    gamma0 = torch.sqrt(1 + torch.sum(u_in[:, n_beam_start:] ** 2, dim=0))
 
     def fwd_bwd():
         run = pag.DifferentiableRun(ctx, el.q, el.m, nsteps=K, checkpoint_every=every, rho_static=f.rho_static)
@@ -332,9 +484,13 @@ def time_fwd_bwd(config_name, every, reps=3, steps=0):
         u = u_in.clone().requires_grad_(True)
         out = pag.PicSteps.apply(run, el.cell, el.w, E, B, f.rho_old, off_in, u)
         uf = out[5]
-        loss = torch.sum(el.w * (torch.sqrt(1 + torch.sum(uf * uf, dim=0)) - 1))
-        loss.backward()
-        grads["loss"] = float(loss.detach())
+        if loss == "kinetic":
+            L = torch.sum(el.w * (torch.sqrt(1 + torch.sum(uf * uf, dim=0)) - 1))
+        else:
+            ub = uf[:, n_beam_start:]
+            L = torch.sum(wb * (gamma0 - torch.sqrt(1 + torch.sum(ub * ub, dim=0))))
+        L.backward()
+        grads["loss"] = float(L.detach())
         grads["norm"] = float(torch.sqrt(torch.sum(E.grad ** 2) + torch.sum(B.grad ** 2) + torch.sum(u.grad ** 2)))
 
     T_fb = timed(fwd_bwd)
@@ -346,8 +502,10 @@ def time_fwd_bwd(config_name, every, reps=3, steps=0):
     piclib.pic_profile(ctx.ctx, False)
     ctx.close()
     Np = wl.electrons.n
+    what = ("sum w (gamma - 1) of all electrons at the end" if loss == "kinetic" else
+            "beam energy loss sum_beam w (gamma^0 - gamma^end)")
     return {"workload": CONFIG_TEXT[config_name], "dtype": wl.dtype, "steps": K, "checkpoint_every": every,
-            "loss": "sum w (gamma - 1) at the end; gradients w.r.t. initial E, B (Yee) and u",
+            "loss": what + "; gradients w.r.t. initial E, B (Yee) and u",
             "forward_ms_per_step": round(1e3 * T_fwd / K, 4), "fwd_bwd_ms_per_step": round(1e3 * T_fb / K, 4),
             "fwd_bwd_over_forward": round(T_fb / T_fwd, 3),
             "fwd_bwd_particle_pushes_per_s": Np * K / T_fb, "fwd_bwd_cell_updates_per_s": wl.cells * K / T_fb,
@@ -355,16 +513,23 @@ def time_fwd_bwd(config_name, every, reps=3, steps=0):
             "stage_ms_total_one_run": {k: round(v[0], 3) for k, v in stages.items() if v[1]}}
 
 
-def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0, v_gal=(0.0, 0.0, 0.0)):
-    """Times ``steps`` hybrid cycles of the workload (one pic_step call) after ``warmup`` steps."""
+def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0, v_gal=(0.0, 0.0, 0.0), keep=False,
+            species=None):
+    """Times ``steps`` hybrid cycles of the workload (one pic_step call) after ``warmup`` steps.
+
+    Returns (result dict, final fields): with ``keep`` the final E_stag, B_stag as device tensors
+    ({"E": [...], "B": [...]}), else None.  ``species``: already uploaded (electrons, ions)."""
     import torch
 
     from paper_2106_12919_amd import lib as piclib
 
     ctx = piclib.Context.for_workload(wl, flags=flags, v_gal=v_gal)
     f = ctx.fields_from_workload(wl)
-    el = piclib.Species.from_host(wl.electrons, wl.shape, wl.dtype)
-    ions = piclib.Species.from_host(wl.ions, wl.shape, wl.dtype)
+    if species is None:
+        el = piclib.Species.from_host(wl.electrons, wl.shape, wl.dtype)
+        ions = piclib.Species.from_host(wl.ions, wl.shape, wl.dtype)
+    else:
+        el, ions = species
     ctx.init_charge(f, el, ions)
     del ions
     piclib.pic_step(ctx.ctx, f, [el], warmup)
@@ -419,8 +584,12 @@ def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0, v_gal=(0.0,
                      "frac": round(fl / dep, 4),
                      "basis": f"{LDS_U32_LANE_OPS} (u32) and {LDS_U64_LANE_OPS} (u64) lane-ops/clk/CU measured, "
                               f"{CUS} CUs at {CLOCK_HZ / 1e9} GHz"}
+    final = None
+    if keep:
+        final = {"E": [t.clone() for t in f.E_stag], "B": [t.clone() for t in f.B_stag]}
     ctx.close()
-    return {
+    del f
+    result = {
         "metric": "particle-pushes/s and grid-cell updates/s per PIC step, FP32 vs FP64, fwd and fwd+bwd",
         "value": Np * K / T,
         "unit": "particle-pushes/s",
@@ -432,20 +601,22 @@ def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0, v_gal=(0.0,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": wl.dtype,
-        "data": "synthetic (seeded laser + plasma workload)",
+        "data": "synthetic (seeded plasma, beam and laser workloads)",
         "config": {"workload": CONFIG_TEXT[config_name], "cells": N, "particles": Np,
                    "center_order": wl.center_order, "shape_order": wl.shape_order, "pass": "forward",
-                   "centering": ("none (nodal solver)" if flags & 2 else
-                                 "none (staggered cycle)" if flags & 16 else
-                                 "spectral" if flags & 1 else "real-space")},
+                   "centering": ("none (nodal solver)" if flags & piclib.PIC_NODAL_SOLVER else
+                                 "none (staggered cycle)" if flags & piclib.PIC_STAGGERED_CYCLE else
+                                 "spectral" if flags & piclib.PIC_SPECTRAL_CENTERING else "real-space"),
+                   "current_correction": bool(flags & piclib.PIC_CURRENT_CORRECTION)},
         "cell_updates_per_s": N * K / T,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic(dom) if (config_name == "laser128" and wl.dtype == "f32") else None,
+                     "traffic": recorded_traffic(dom, config_name, wl.dtype) if flags == 0 else None,
                      "algo_bytes_per_launch": d["algo_bytes"], "ms_per_launch": d["ms_avg"]},
         "lds_atomic_floor": lds_floor,
         "stages": breakdown,
     }
+    return result, final
 
 
 if __name__ == "__main__":

@@ -140,7 +140,10 @@ __device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nlines, int ls, int js, 
 // Largest element count per thread of one block's LDS tile (two buffers of kLdsBudget
 // bytes in all): every thread issues all its global loads (those inside the tile) before it
 // stores any to LDS.
-constexpr size_t kLdsBudget = 65536;
+#ifndef PIC_FFT_LDS_BUDGET
+#define PIC_FFT_LDS_BUDGET 65536
+#endif
+constexpr size_t kLdsBudget = PIC_FFT_LDS_BUDGET;
 template <typename T>
 constexpr int kPerThread = (int)(kLdsBudget / (2 * sizeof(cplx<T>)) / kBlock);
 
@@ -298,19 +301,24 @@ __global__ void __launch_bounds__(kBlock) k_fft_strided(Batch<const cplx<T>*> in
 }
 
 
-// Tiles fit the 64 KiB default LDS of a launch together with the twiddles (fewer than
-// n of them).
+// Tiles fit the LDS budget of a launch together with the twiddles (fewer than n of them).
 template <typename T>
+#ifndef PIC_FFT_ZPASS_ELEMS
+#define PIC_FFT_ZPASS_ELEMS 2048
+#endif
 int pairs_per_block(int n) {
-  int P = 2048 / n;
+  int P = PIC_FFT_ZPASS_ELEMS / n;
   if (P < 1) P = 1;
   while (P > 1 && (2 * (size_t)P * n + n) * sizeof(cplx<T>) > kLdsBudget) P /= 2;
   return P;
 }
 
+#ifndef PIC_FFT_MAX_TL_SHIFT
+#define PIC_FFT_MAX_TL_SHIFT 4
+#endif
 template <typename T>
 int lines_per_tile_shift(int n) {
-  int sh = 4;  // 16 lines
+  int sh = PIC_FFT_MAX_TL_SHIFT;  // 16 lines
   while (sh > 0 && (2 * ((size_t)1 << sh) * n + n) * sizeof(cplx<T>) > kLdsBudget) --sh;
   return sh;
 }
@@ -330,6 +338,7 @@ void strided_pass(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& out, i
   const int tpo = (inner_count + TL - 1) / TL;
   dim3 grid(outer_count * tpo, count);
   const size_t lds = fft_lds_bytes<T>((size_t)TL * p.n, p);
+  allow_lds((const void*)k_fft_strided<T, SIGN>, lds);
   hipLaunchKernelGGL((k_fft_strided<T, SIGN>), grid, dim3(kBlock), lds, s, in, out, p, tw, sh, inner_count, tpo,
                      outer_stride, elem_stride);
 }
@@ -373,8 +382,9 @@ void Fft3D<T>::forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, in
   const int nlines = nx * ny;
   const int P = pairs_per_block<T>(nz);
   dim3 grid((nlines / 2 + P - 1) / P, count);
-  hipLaunchKernelGGL((k_r2c_z<T>), grid, dim3(kBlock), fft_lds_bytes<T>((size_t)P * nz, plan[2]), s, in, out,
-                     plan[2], tw[2], nlines, pz, P);
+  const size_t lds = fft_lds_bytes<T>((size_t)P * nz, plan[2]);
+  allow_lds((const void*)k_r2c_z<T>, lds);
+  hipLaunchKernelGGL((k_r2c_z<T>), grid, dim3(kBlock), lds, s, in, out, plan[2], tw[2], nlines, pz, P);
   Batch<const cplx<T>*> cin;
   for (int i = 0; i < count; ++i) cin.p[i] = out.p[i];
   strided_pass<T, -1>(cin, out, count, plan[1], tw[1], nx, nzh, (long long)ny * pz, pz, s);
@@ -391,8 +401,9 @@ void Fft3D<T>::inverse(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& s
   const int nlines = nx * ny;
   const int P = pairs_per_block<T>(nz);
   dim3 grid((nlines / 2 + P - 1) / P, count);
-  hipLaunchKernelGGL((k_c2r_z<T>), grid, dim3(kBlock), fft_lds_bytes<T>((size_t)P * nz, plan[2]), s, cs, out,
-                     plan[2], tw[2], nlines, pz, P, scale);
+  const size_t lds = fft_lds_bytes<T>((size_t)P * nz, plan[2]);
+  allow_lds((const void*)k_c2r_z<T>, lds);
+  hipLaunchKernelGGL((k_c2r_z<T>), grid, dim3(kBlock), lds, s, cs, out, plan[2], tw[2], nlines, pz, P, scale);
 }
 
 template struct Fft3D<float>;

@@ -77,6 +77,10 @@ template <typename T>
 void psatd_adjoint(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B[3], cplx<T>* const J[3],
                    cplx<T>* rho_old, cplx<T>* rho_new, int nx, int ny, int nzh, int pz, hipStream_t s);
 
+// Lets a kernel launch with more than the default 64 KiB of dynamic LDS (gfx950: up to 160 KiB
+// per workgroup); a failure is cleared and left to the launch to report.
+void allow_lds(const void* kernel, size_t bytes);
+
 // ---------------------------------------------------------------- particles (particles.hip)
 // Division by a fixed divisor d (1 <= d < 2^31) as a multiply-high and a shift:
 // n / d == (mulhi(n, m) + n) >> s for 0 <= n < 2^31, with s = ceil(log2 d) and

@@ -251,3 +251,134 @@ def test_beam384_fp32_one_step_sampled():
     jz = -float(torch.sum(el.w.double() * uz / gam))
     assert abs(float(torch.sum(f.J_nod[2].double())) - jz) <= 1e-4 * abs(jz)
     ctx.close()
+
+
+def _plane_waves(shape, t, dt_order=16):
+    """Three vacuum plane waves on the grid, exact for the standard PSATD update (App. B: w = c|[k]_s|
+    for any dt): along z (E_x, B_y), along y (E_z, B_x) and oblique in x-y (E_z, B_x, B_y), each with
+    B = [k]_s x E / w, every component sampled at its Yee position."""
+    from oracle import fornberg
+    from oracle.transforms import OFFSETS
+    nx, ny, nz = shape
+    waves = [((0, 0, 101), "Ex"), ((0, 37, 0), "Ez"), ((5, 11, 0), "Ez")]
+    E = [np.zeros(shape) for _ in range(3)]
+    B = [np.zeros(shape) for _ in range(3)]
+    comp = {"Ex": 0, "Ey": 1, "Ez": 2}
+    for (mx, my, mz), ename in waves:
+        k = np.array([2 * np.pi * mx / nx, 2 * np.pi * my / ny, 2 * np.pi * mz / nz])
+        K = np.array([fornberg.k_staggered(kd, 1.0, dt_order) for kd in k])
+        w = np.sqrt(np.sum(K * K))
+        e = np.zeros(3)
+        e[comp[ename]] = 1.0
+        b = np.cross(K, e) / w
+
+        def sample(name, amp):
+            o = OFFSETS[name]
+            x = (np.arange(nx) + o[0])[:, None, None]
+            y = (np.arange(ny) + o[1])[None, :, None]
+            z = (np.arange(nz) + o[2])[None, None, :]
+            return amp * np.cos(k[0] * x + k[1] * y + k[2] * z - w * t)
+        for d, name in enumerate(("Ex", "Ey", "Ez")):
+            if e[d]:
+                E[d] = E[d] + sample(name, e[d])
+        for d, name in enumerate(("Bx", "By", "Bz")):
+            if b[d]:
+                B[d] = B[d] + sample(name, b[d])
+    return E, B
+
+
+def test_beam384_grid_field_solve_plane_waves():
+    """The field solve at the beam-driven wake's full size (384 x 384 x 768, FP32, PSATD order 16):
+    superposed vacuum plane waves along the 768-point axis, along a 384-point axis and oblique
+    advance by exactly w = c |[k]_s| per unit time (App. B), a closed form at any size; the field
+    energy is conserved."""
+    banner("beam384 grid FP32 field solve, vacuum plane waves against the closed form")
+    shape, dt = (384, 384, 768), 0.5
+    ctx = piclib.Context(shape, (1.0, 1.0, 1.0), dt, 3, 16, 16, "f32")
+    f = piclib.Fields(shape, "f32")
+    E0, B0 = _plane_waves(shape, 0.0)
+    for d in range(3):
+        f.E_stag[d].copy_(torch.from_numpy(E0[d]))
+        f.B_stag[d].copy_(torch.from_numpy(B0[d]))
+    del E0, B0
+    W0, _ = piclib.pic_diagnostics(ctx.ctx, f)
+    piclib.psatd_push_fields(ctx.ctx, f)
+    piclib.pic_sync(ctx.ctx)
+    W1, _ = piclib.pic_diagnostics(ctx.ctx, f)
+    E1, B1 = _plane_waves(shape, dt)
+    # 3-pass FP32 transforms of ~27 levels each way around the update: ~10 * 2 log2(N) eps32 of the amplitude
+    tol = 10 * 2 * np.log2(np.prod(shape)) * 2.0 ** -24 * 3
+    for d in range(3):
+        for got, ref, name in ((f.E_stag[d], E1[d], "E"), (f.B_stag[d], B1[d], "B")):
+            err = float(np.max(np.abs(got.cpu().numpy().astype(np.float64) - ref)))
+            assert err <= tol * 3.0, (name, d, err)
+    assert abs(W1 - W0) <= 1e-5 * W0
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype,center_order", [("f32", 32), ("f64", 2)])
+def test_thermal256_one_step_sampled(dtype, center_order):
+    """The 256^3 thermal plasma at full size (134,217,728 particles, CIC) at the ends of the centering
+    sweep, one pic_step in the caller's particle order, checked on samples the oracle computes one by
+    one: the staggered-to-nodal centering of E at sampled nodes, gather + push of 4,000 particles from
+    the GPU's nodal fields, the nodal-to-staggered centering of J at sampled nodes, and the
+    deposition's totals (charge, current)."""
+    from oracle import centering as ocent
+    from oracle import particles as opart
+    banner(f"thermal256 full size, one step, sampled checks, dtype={dtype} center_order={center_order}")
+    wl = inputs.config("thermal256", dtype=dtype, center_order=center_order)
+    shape = wl.shape
+    # start from random fields (E = B = 0 in the workload would leave the gather untested)
+    rng = np.random.default_rng(256)
+    wl.E = [0.01 * rng.standard_normal(shape) for _ in range(3)]
+    wl.B = [0.01 * rng.standard_normal(shape) for _ in range(3)]
+    ctx = piclib.Context.for_workload(wl, flags=piclib.PIC_KEEP_ORDER)
+    f = ctx.fields_from_workload(wl)
+    el = piclib.Species.from_host(wl.electrons, shape, dtype)
+    ions = piclib.Species.from_host(wl.ions, shape, dtype)
+    ctx.init_charge(f, el, ions)
+    del ions
+    q_ions = float(np.sum(wl.ions.w))
+    E0 = [t.cpu().numpy().astype(np.float64) for t in f.E_stag]
+    del wl
+    pick = rng.integers(0, el.n, 4000)
+    pos0 = el.positions(shape, (1.0, 1.0, 1.0))[pick]
+    u0 = np.stack([np64(x)[pick] for x in el.u], axis=1)
+    piclib.pic_step(ctx.ctx, f, [el], 1)
+    piclib.pic_sync(ctx.ctx)
+    m, dt = center_order // 2, 0.5
+    tol = 1e-5 if dtype == "f32" else 1e-12
+    scale = max(np.max(np.abs(a)) for a in E0)
+    for d in range(3):
+        Enod = f.E_nod[d].cpu().numpy()
+        for _ in range(40):
+            i, j, k = (int(rng.integers(0, n)) for n in shape)
+            line = (E0[0][:, j, k], E0[1][i, :, k], E0[2][i, j, :])[d]
+            ref = ocent.s2n_axis(line, 0, m)[(i, j, k)[d]]
+            assert abs(float(Enod[i, j, k]) - ref) <= tol * scale, ("E", d)
+    Jn = [t.cpu().numpy().astype(np.float64) for t in f.J_nod]
+    jscale = max(np.max(np.abs(a)) for a in Jn)
+    for d in range(3):
+        Js = f.J_stag[d].cpu().numpy()
+        for _ in range(40):
+            i, j, k = (int(rng.integers(0, n)) for n in shape)
+            line = (Jn[0][:, j, k], Jn[1][i, :, k], Jn[2][i, j, :])[d]
+            ref = ocent.n2s_axis(line, 0, m)[(i, j, k)[d]]
+            assert abs(float(Js[i, j, k]) - ref) <= tol * jscale, ("J", d)
+    EB = opart.gather([t.cpu().numpy() for t in f.E_nod] + [t.cpu().numpy() for t in f.B_nod], pos0,
+                      (1.0, 1.0, 1.0), 1)
+    u1 = opart.boris(u0.T, EB[:3], EB[3:], -1.0, 1.0, dt)
+    pos1 = opart.wrap(pos0 + dt * (u1 / opart.gamma(u1)).T, shape)
+    g_u = np.stack([np64(x)[pick] for x in el.u], axis=1)
+    ptol = 3e-6 if dtype == "f32" else 1e-12
+    assert np.max(np.abs(g_u - u1.T)) <= ptol
+    assert periodic_pos_err(el.positions(shape, (1.0, 1.0, 1.0))[pick], pos1, shape) <= ptol
+    q_el = -float(torch.sum(el.w.double()))
+    assert abs(float(torch.sum(f.rho_old.double())) - (q_el + q_ions)) <= (1e-5 if dtype == "f32" else 1e-12) * abs(q_el)
+    for d in range(3):
+        ud = el.u[d].double()
+        gam = torch.sqrt(1 + el.u[0].double() ** 2 + el.u[1].double() ** 2 + el.u[2].double() ** 2)
+        jd = -float(torch.sum(el.w.double() * ud / gam))
+        assert abs(float(torch.sum(f.J_nod[d].double())) - jd) <= (1e-4 if dtype == "f32" else 1e-10) * \
+            float(torch.sum(el.w.double() * torch.abs(ud) / gam))
+    ctx.close()

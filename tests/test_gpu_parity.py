@@ -32,8 +32,8 @@ def centering_tol(dtype, m, scale):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("order", [2, 4, 8, 16])
-@pytest.mark.parametrize("shape", [(16, 24, 32), (48, 16, 8)])
+@pytest.mark.parametrize("order", [2, 4, 8, 16, 32])
+@pytest.mark.parametrize("shape", [(16, 24, 32), (48, 16, 8), (32, 36, 64)])
 def test_center_parity(dtype, order, shape):
     if order > min(shape):
         pytest.skip("centering order above the smallest axis is rejected by pic_init")
