@@ -247,6 +247,11 @@ def main():
     ap.add_argument("--adjoint-reps", type=int, default=3)
     ap.add_argument("--beam-adjoint-steps", type=int, default=20,
                     help="steps of the beam-driven wake's forward+backward run (0: skip it)")
+    ap.add_argument("--precision-statement", default="", metavar="LIST",
+                    help="instead of timing: the FP32 error against the FP64 path over each listed workload's "
+                         "full length (e.g. laser128,laser64,beam384,thermal256), fields, energy, momenta, charge")
+    ap.add_argument("--precision-every", type=int, default=10, metavar="K",
+                    help="with --precision-statement: steps per pic_step call, the errors taken after each call")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy a MIB-MiB float32 tensor 3 times (a plain copy kernel "
                          "of known size, the reference for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -256,6 +261,14 @@ def main():
         print(f"bench.py: this build runs the hybrid PSATD step on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU domain decomposition is described in DESIGN.md, not built.", file=sys.stderr)
         sys.exit(2)
+
+    if args.precision_statement:
+        import torch
+        torch.cuda.set_device(0)
+        out = {"precision_statement": [precision_statement(name, args.precision_every)
+                                       for name in args.precision_statement.split(",")]}
+        print(json.dumps(out))
+        return
 
     cpu = None
     if not args.no_cpu_baseline:  # first: its worker processes fork from this one, before any GPU use
@@ -345,6 +358,66 @@ def field_errors(a, b, spacing, steps):
     W = [0.5 * w * dV for w in W]
     return {"after_steps": steps, "field_max_rel": worst_max, "field_l2_rel": worst_l2,
             "W_rel": abs(W[0] - W[1]) / W[1] if W[1] > 0 else abs(W[0]), "reference": "the FP64 HIP path"}
+
+
+def precision_statement(config_name, every=10):
+    """FP32 against FP64 over a workload's full length, in pic_step calls of ``every`` steps (a call
+    keeps E, B in Fourier space between its steps, as production runs do; each call adds one FP32
+    round trip of the state): both runs keep the caller's particle order (PIC_KEEP_ORDER), so
+    particles compare index by index.  After each call the worst max-norm and L2 relative field
+    error over the six components, |W32 - W64| / W64, the momentum error max |u32 - u64| / max |u64|,
+    and the electron charge error of the FP32 deposition |sum rho_e dV - sum q w| / |sum q w|; the
+    worst of each over the run and the final values."""
+    import torch
+
+    from paper_2106_12919_amd import inputs
+    from paper_2106_12919_amd import lib as piclib
+
+    wl = inputs.config(config_name)
+    orders = [2, 32] if config_name == "thermal256" else [wl.center_order]
+    results = []
+    for order in orders:
+        wl.center_order = order
+        runs = {}
+        for dtype in ("f32", "f64"):
+            wl.dtype = dtype
+            ctx = piclib.Context.for_workload(wl, flags=piclib.PIC_KEEP_ORDER)
+            f = ctx.fields_from_workload(wl)
+            el = piclib.Species.from_host(wl.electrons, wl.shape, dtype)
+            ions = piclib.Species.from_host(wl.ions, wl.shape, dtype)
+            ctx.init_charge(f, el, ions)
+            runs[dtype] = (ctx, f, el)
+        q_el = -float(torch.sum(runs["f64"][2].w))
+        dV = wl.spacing[0] * wl.spacing[1] * wl.spacing[2]
+        rows = []
+        for n0 in range(0, wl.steps, every):
+            k = min(every, wl.steps - n0)
+            n = n0 + k - 1
+            for dtype in ("f32", "f64"):
+                ctx, f, el = runs[dtype]
+                piclib.pic_step(ctx.ctx, f, [el], k)
+            torch.cuda.synchronize()
+            (c32, f32, e32), (c64, f64, e64) = runs["f32"], runs["f64"]
+            row = field_errors({"E": f32.E_stag, "B": f32.B_stag}, {"E": f64.E_stag, "B": f64.B_stag}, wl.spacing,
+                               n + 1)
+            umax = max(float(torch.max(torch.abs(t))) for t in e64.u)
+            row["u_max_rel"] = max(float(torch.max(torch.abs(a.double() - b))) for a, b in zip(e32.u, e64.u)) / umax
+            rho_e = f32.rho_old.double() - f32.rho_static.double()
+            row["charge_rel"] = abs(float(torch.sum(rho_e)) * dV - q_el) / abs(q_el)
+            rows.append(row)
+            if (n + 1) % 50 == 0 or n + 1 == wl.steps:
+                print(f"[precision] {config_name} order {order} step {n + 1}: |W32-W64|/W64 {row['W_rel']:.2e}, "
+                      f"field max rel {row['field_max_rel']:.2e}", file=sys.stderr, flush=True)
+        for dtype in ("f32", "f64"):
+            runs[dtype][0].close()
+        del runs
+        torch.cuda.empty_cache()
+        keys = ("field_max_rel", "field_l2_rel", "W_rel", "u_max_rel", "charge_rel")
+        results.append({"workload": CONFIG_TEXT[config_name], "center_order": order, "steps": wl.steps,
+                        "steps_per_call": every,
+                        "worst": {k: max(r[k] for r in rows) for k in keys},
+                        "final": {k: rows[-1][k] for k in keys}, "reference": "the FP64 HIP path"})
+    return results
 
 
 def sweep_thermal256(orders, steps, warmup=2):

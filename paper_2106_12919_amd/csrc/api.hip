@@ -800,7 +800,7 @@ void update_and_inverse(pic_ctx c, Engine<T>& e, pic_fields* f, int rho_old_slot
       aout.p[3 + d] = static_cast<T*>(f->B_avg[d]);
     }
     for (int i = 0; i < 6; ++i) ascr.p[i] = e.scratch[i];
-    e.fft.inverse(ain, ascr, aout, 6, (T)(1.0 / (double)ncells(p)), c->stream);
+    e.fft.inverse(ain, ascr, aout, 6, 1.0 / (double)ncells(p), c->stream);
     if (!state_out) return;  // pic_step: the state stays in Fourier space until the call's end
   }
   Batch<const cplx<T>*> in{};
@@ -813,7 +813,7 @@ void update_and_inverse(pic_ctx c, Engine<T>& e, pic_fields* f, int rho_old_slot
     out.p[3 + d] = static_cast<T*>(spectral ? f->B_nod[d] : f->B_stag[d]);
   }
   for (int i = 0; i < 6; ++i) scr.p[i] = e.scratch[i];
-  e.fft.inverse(in, scr, out, 6, (T)(1.0 / (double)ncells(p)), c->stream);
+  e.fft.inverse(in, scr, out, 6, 1.0 / (double)ncells(p), c->stream);
 }
 
 // The staggered state E_stag, B_stag from the resident spectra (end of a spectral-
@@ -831,7 +831,7 @@ void state_inverse(pic_ctx c, Engine<T>& e, pic_fields* f) {
     out.p[3 + d] = static_cast<T*>(f->B_stag[d]);
   }
   for (int i = 0; i < 6; ++i) scr.p[i] = e.scratch[i];
-  e.fft.inverse(in, scr, out, 6, (T)(1.0 / (double)ncells(c->p)), c->stream);
+  e.fft.inverse(in, scr, out, 6, 1.0 / (double)ncells(c->p), c->stream);
 }
 
 template <typename T>
@@ -884,7 +884,7 @@ pic_status do_push_fields_adjoint(pic_ctx c, pic_fields* f) {
     psatd_adjoint<T>(e.tab, e.Eh, e.Bh, e.Jh, e.rh[0], e.rh[1], p.nx, p.ny, e.fft.nzh, e.fft.pz, c->stream);
   }
   StageScope sc(c, ST_FFT_INV);
-  const T scale = (T)(1.0 / (double)ncells(p));
+  const double scale = 1.0 / (double)ncells(p);
   Batch<const cplx<T>*> in{};
   Batch<cplx<T>*> scr{};
   Batch<T*> out{};

@@ -23,16 +23,6 @@ struct Coef {
   T c[16];
 };
 
-// Workgroups go to the eight XCDs round-robin (b to XCD b mod 8), each with its own L2;
-// renumbering them XCD-major gives every XCD one contiguous range of logical indices,
-// so that blocks whose halos overlap share an L2.  A bijection on 0..n-1.
-__device__ inline int xcd_major(int b, int n) {
-  constexpr int kXcds = 8;
-  const int q = n / kXcds, r = n % kXcds;
-  const int x = b % kXcds, s = b / kXcds;
-  return x * q + min(x, r) + s;
-}
-
 // Strided axis: grid (column blocks, row blocks, outer) flattened and renumbered
 // XCD-major, row blocks next to each other (which share halo rows) on one XCD.
 template <typename T, int M, int L>

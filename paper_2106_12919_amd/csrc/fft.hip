@@ -32,14 +32,25 @@ __device__ inline void dft2(cplx<T>* v) {
   v[1] = csub(a, b);
 }
 
+// x times an irrational constant c = hi + lo (hi the nearest T, lo the remainder), rounded once:
+// the product carries c to twice the precision of T.  A constant rounded to T alone scales the
+// modes it touches by |fl(c)/c| != 1 on every pass, and in FP32 that is a systematic loss or gain
+// of field energy of ~1e-8 per butterfly stage, the same for every mode that goes through it.
+template <typename T>
+__device__ inline T mul_const(T x, T hi, T lo) {
+  return fma(hi, x, lo * x);
+}
+
 template <typename T, int SIGN>
 __device__ inline void dft3(cplx<T>* v) {
   // X1 = v0 - (v1+v2)/2 + SIGN i (sqrt3/2)(v1 - v2), X2 = conjugate combination.
-  const T h = (T)0.86602540378443864676372317075294;
+  constexpr double hd = 0.86602540378443864676372317075294;
+  const T hh = (T)hd, hl = (T)(hd - (double)(T)hd);
   cplx<T> t = cadd(v[1], v[2]);
   cplx<T> d = csub(v[1], v[2]);
   cplx<T> m = cmake(v[0].x - (T)0.5 * t.x, v[0].y - (T)0.5 * t.y);
-  cplx<T> r = cscale(cmul_i<T, SIGN>(d), h);
+  const cplx<T> id = cmul_i<T, SIGN>(d);
+  cplx<T> r = cmake(mul_const(id.x, hh, hl), mul_const(id.y, hh, hl));
   v[0] = cadd(v[0], t);
   v[1] = cadd(m, r);
   v[2] = csub(m, r);
@@ -59,15 +70,16 @@ __device__ inline void dft4(cplx<T>* v) {
 
 template <typename T, int SIGN>
 __device__ inline void dft8(cplx<T>* v) {
-  const T s = (T)0.70710678118654752440084436210485;
+  constexpr double sd = 0.70710678118654752440084436210485;
+  const T sh = (T)sd, sl = (T)(sd - (double)(T)sd);
   cplx<T> e[4] = {v[0], v[2], v[4], v[6]};
   cplx<T> o[4] = {v[1], v[3], v[5], v[7]};
   dft4<T, SIGN>(e);
   dft4<T, SIGN>(o);
   // twiddles w^k = exp(SIGN i 2 pi k / 8), k = 0..3
-  cplx<T> o1 = cmake(s * (o[1].x - (T)SIGN * o[1].y), s * (o[1].y + (T)SIGN * o[1].x));
+  cplx<T> o1 = cmake(mul_const(o[1].x - (T)SIGN * o[1].y, sh, sl), mul_const(o[1].y + (T)SIGN * o[1].x, sh, sl));
   cplx<T> o2 = cmul_i<T, SIGN>(o[2]);
-  cplx<T> o3 = cmake(s * (-o[3].x - (T)SIGN * o[3].y), s * (-o[3].y + (T)SIGN * o[3].x));
+  cplx<T> o3 = cmake(mul_const(-o[3].x - (T)SIGN * o[3].y, sh, sl), mul_const(-o[3].y + (T)SIGN * o[3].x, sh, sl));
   v[0] = cadd(e[0], o[0]);
   v[4] = csub(e[0], o[0]);
   v[1] = cadd(e[1], o1);
@@ -204,7 +216,8 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z(Batch<const T*> in, Batch<cplx
 // kz = nz/2 bins are dropped (real-output convention).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_c2r_z(Batch<const cplx<T>*> in, Batch<T*> out, FftPlan p,
-                                                  const cplx<T>* __restrict__ tw, int nlines, int pz, int P, T scale) {
+                                                  const cplx<T>* __restrict__ tw, int nlines, int pz, int P, T scale,
+                                                  T scale_lo) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = p.n;
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
@@ -251,8 +264,8 @@ __global__ void __launch_bounds__(kBlock) k_c2r_z(Batch<const cplx<T>*> in, Batc
     const int q = e / N, j = e - q * N;
     const size_t l = 2 * (size_t)(pair0 + q);
     const cplx<T> v = res[q * N + j];
-    dst[l * N + j] = v.x * scale;
-    dst[(l + 1) * N + j] = v.y * scale;
+    dst[l * N + j] = mul_const(v.x, scale, scale_lo);
+    dst[(l + 1) * N + j] = mul_const(v.y, scale, scale_lo);
   }
 }
 
@@ -270,7 +283,11 @@ __global__ void __launch_bounds__(kBlock) k_fft_strided(Batch<const cplx<T>*> in
   cplx<T>* b = a + (size_t)TL * N;
   const cplx<T>* __restrict__ src = in.p[blockIdx.y];
   cplx<T>* __restrict__ dst = out.p[blockIdx.y];
-  const int tile = blockIdx.x;
+#ifndef PIC_FFT_XCD
+#define PIC_FFT_XCD 1
+#endif
+  // tiles next to each other read and write the two halves of the same memory lines: one XCD
+  const int tile = PIC_FFT_XCD ? xcd_major(blockIdx.x, gridDim.x) : blockIdx.x;
   const int outer = tile / tiles_per_outer;
   const int inner0 = (tile - outer * tiles_per_outer) * TL;
   const int nl = min(TL, inner_count - inner0);
@@ -343,6 +360,30 @@ void strided_pass(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& out, i
                      outer_stride, elem_stride);
 }
 
+// A twiddle (c, s) = (cos, sin) of an exact angle in the run precision.  Rounding c and s
+// separately leaves |w|^2 - 1 up to ~1e-7 in FP32, the same factor on every pass through that
+// twiddle, which the field energy carried by those modes then gains or loses step after step.  In
+// FP32 the pair is chosen among the roundings of c and s and their neighbours (each within one
+// unit in the last place) as the one whose squared modulus is closest to 1; FP64 rounds directly.
+template <typename T>
+cplx<T> unit_twiddle(double c, double s) {
+  if (sizeof(T) == 8) return cmake((T)c, (T)s);
+  cplx<T> best = cmake((T)c, (T)s);
+  double err = std::fabs((double)best.x * best.x + (double)best.y * best.y - 1.0);
+  const float c0 = (float)c, s0 = (float)s;
+  const float cs[3] = {std::nextafter(c0, -2.0f), c0, std::nextafter(c0, 2.0f)};
+  const float ss[3] = {std::nextafter(s0, -2.0f), s0, std::nextafter(s0, 2.0f)};
+  for (float cc : cs)
+    for (float sc : ss) {
+      const double e = std::fabs((double)cc * cc + (double)sc * sc - 1.0);
+      if (e < err) {
+        err = e;
+        best = cmake((T)cc, (T)sc);
+      }
+    }
+  return best;
+}
+
 }  // namespace
 
 template <typename T>
@@ -359,7 +400,7 @@ hipError_t Fft3D<T>::init(int nx_, int ny_, int nz_) {
     double* h = new double[2 * (size_t)cnt]();
     fft_twiddles(plan[d], h);
     cplx<T>* hc = new cplx<T>[cnt];
-    for (int i = 0; i < cnt; ++i) hc[i] = cmake((T)h[2 * i], (T)h[2 * i + 1]);
+    for (int i = 0; i < cnt; ++i) hc[i] = unit_twiddle<T>(h[2 * i], h[2 * i + 1]);
     hipError_t e = hipMalloc(&tw[d], cnt * sizeof(cplx<T>));
     if (e == hipSuccess) e = hipMemcpy(tw[d], hc, cnt * sizeof(cplx<T>), hipMemcpyHostToDevice);
     delete[] h;
@@ -393,7 +434,8 @@ void Fft3D<T>::forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, in
 
 template <typename T>
 void Fft3D<T>::inverse(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& scratch, const Batch<T*>& out,
-                       int count, T scale, hipStream_t s) const {
+                       int count, double scale, hipStream_t s) const {
+  const T sc_hi = (T)scale, sc_lo = (T)(scale - (double)sc_hi);
   strided_pass<T, +1>(in, scratch, count, plan[0], tw[0], 1, ny * pz, 0, (long long)ny * pz, s);
   Batch<const cplx<T>*> cs;
   for (int i = 0; i < count; ++i) cs.p[i] = scratch.p[i];
@@ -403,7 +445,7 @@ void Fft3D<T>::inverse(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& s
   dim3 grid((nlines / 2 + P - 1) / P, count);
   const size_t lds = fft_lds_bytes<T>((size_t)P * nz, plan[2]);
   allow_lds((const void*)k_c2r_z<T>, lds);
-  hipLaunchKernelGGL((k_c2r_z<T>), grid, dim3(kBlock), lds, s, cs, out, plan[2], tw[2], nlines, pz, P, scale);
+  hipLaunchKernelGGL((k_c2r_z<T>), grid, dim3(kBlock), lds, s, cs, out, plan[2], tw[2], nlines, pz, P, sc_hi, sc_lo);
 }
 
 template struct Fft3D<float>;

@@ -20,9 +20,11 @@ struct Fft3D {
   // count <= kMaxBatch arrays, real -> spectrum
   void forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, int count, hipStream_t s) const;
   // spectrum -> real; ``scratch`` receives the partially transformed spectra (``in`` is preserved);
-  // the result is scaled by ``scale``.
+  // the result is scaled by ``scale`` (given in FP64 and applied to twice the run precision: 1/N is
+  // inexact in binary when N has a factor 3, and a rounded scale would change the field energy by
+  // the same factor on every inverse transform).
   void inverse(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& scratch, const Batch<T*>& out, int count,
-               T scale, hipStream_t s) const;
+               double scale, hipStream_t s) const;
 };
 
 // ---------------------------------------------------------------- centering (centering.hip)
@@ -76,6 +78,18 @@ void psatd_update(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B
 template <typename T>
 void psatd_adjoint(const PsatdTables<T>& t, cplx<T>* const E[3], cplx<T>* const B[3], cplx<T>* const J[3],
                    cplx<T>* rho_old, cplx<T>* rho_new, int nx, int ny, int nzh, int pz, hipStream_t s);
+
+// Workgroups of a launch go to the eight XCDs of the device round-robin (workgroup b
+// to XCD b mod 8), and each XCD has its own L2.  xcd_major renumbers the workgroups
+// 0..n-1 so that every XCD receives one contiguous range of logical indices: tiles
+// next to each other, which share halo nodes or halves of memory lines, then share an L2.
+// (A bijection for any n; only the speed depends on the dispatch order.)
+__device__ inline int xcd_major(int b, int n) {
+  constexpr int kXcds = 8;
+  const int q = n / kXcds, r = n % kXcds;
+  const int x = b % kXcds, s = b / kXcds;
+  return x * q + min(x, r) + s;
+}
 
 // Lets a kernel launch with more than the default 64 KiB of dynamic LDS (gfx950: up to 160 KiB
 // per workgroup); a failure is cleared and left to the launch to report.

@@ -210,17 +210,6 @@ __device__ inline void through_perm(const int* perm, int (&q)[U]) {
   }
 }
 
-// Workgroups of a launch go to the eight XCDs of the device round-robin (workgroup b
-// to XCD b mod 8), and each XCD has its own L2.  xcd_major renumbers the workgroups
-// 0..n-1 so that every XCD receives one contiguous range of logical indices: tiles
-// next to each other, whose boxes share halo nodes, then share an L2.  (A bijection
-// for any n; only the speed depends on the dispatch order.)
-__device__ inline int xcd_major(int b, int n) {
-  constexpr int kXcds = 8;
-  const int q = n / kXcds, r = n % kXcds;
-  const int x = b % kXcds, s = b / kXcds;
-  return x * q + min(x, r) + s;
-}
 
 // ---------------------------------------------------------------- gather + push
 
