@@ -19,6 +19,9 @@
 #ifndef PIC_DEPOSIT_BLOCK
 #define PIC_DEPOSIT_BLOCK 256
 #endif
+#ifndef PIC_DEPOSIT_CELL_KEY
+#define PIC_DEPOSIT_CELL_KEY 1
+#endif
 
 namespace pic {
 
@@ -963,8 +966,34 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
     if (threadIdx.x < O::KG) hist[threadIdx.x] = 0;
     __syncthreads();
     // pass 1: residue of each particle's first J (rho-only: rho) support node and its
-    // rank among the chunk's particles of that residue; all of a thread's particles in flight
-    {
+    // rank among the chunk's particles of that residue; all of a thread's particles in flight.
+    // When the bounds came from a pass of their own, the residue is taken from the particle's
+    // cell alone (one int per particle instead of its whole record): the first support node of
+    // the current shifts from it only when the half step crosses a cell face, and the deal only
+    // orders the atomics, it does not change their sums.
+    if (PIC_DEPOSIT_CELL_KEY && !single) {
+      const int e0 = threadIdx.x;
+      int qi[O::U];
+#pragma unroll
+      for (int u = 0; u < O::U; ++u) qi[u] = cb + min(e0 + u * PIC_DEPOSIT_BLOCK, nc - 1);
+      through_perm(perm, qi);
+      int c[O::U];
+#pragma unroll
+      for (int u = 0; u < O::U; ++u) c[u] = sp.cell[qi[u]];
+#pragma unroll
+      for (int u = 0; u < O::U; ++u) {
+        const int e = e0 + u * PIC_DEPOSIT_BLOCK;
+        if (e < nc) {
+          int i, j, k, key = 0;
+          if (decode_cell(c[u], g, nullptr, i, j, k)) {
+            const int lx = box_index(i, t0x, g.nx), ly = box_index(j, t0y, g.ny), lz = box_index(k, t0z, g.nz);
+            if (lx >= 0 && ly >= 0 && lz >= 0) key = X::at(lx, ly, lz) & (O::KG - 1);
+          }
+          const int rk = atomicAdd(&hist[key], 1);
+          kr[e] = (unsigned short)(rk * O::KG + key);
+        }
+      }
+    } else {
       const int e0 = threadIdx.x;
       int qi[O::U];
 #pragma unroll
