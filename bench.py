@@ -39,22 +39,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# LDS atomic throughput per compute unit, lane operations per clock, measured on MI355X with a
-# probe (1024 blocks x 256 threads, immediate offsets): ds_add_u32 with the 32 lanes of each
-# half wave on distinct words modulo 32, ds_add_u64 with 16 lanes on distinct words modulo 16.
-LDS_U32_LANE_OPS = 14.5
-LDS_U64_LANE_OPS = 9.9
 CUS, CLOCK_HZ = 256, 2.4e9
+# LDS atomic throughput (lane operations per second per CU) measured live by the library's probe
+# (pic_probe_lds_atomics: the deposition's address patterns) at the start of the GPU part
+LDS_RATES = {}
 
 
-def deposit_lds_floor_ms(Np, shape_order, dtype):
-    """Time of the deposition's LDS atomics alone for Np particles depositing rho and J: FP32 adds
-    (J_x, J_y) as one 64-bit word and J_z, rho as 32-bit words per support node; FP64 adds four
-    64-bit words per node."""
+def deposit_lds_floor_ms(Np, shape_order, dtype, rate32, rate64, cus=CUS):
+    """Time of the deposition's LDS atomics alone for Np particles depositing rho and J, at rate32
+    and rate64 lane operations per second per compute unit: FP32 adds (J_x, J_y) as one 64-bit word
+    and J_z, rho as 32-bit words per support node; FP64 adds four 64-bit words per node."""
     nodes = (2 if shape_order == 1 else 4) ** 3
     u64, u32 = (nodes, 2 * nodes) if dtype == "f32" else (4 * nodes, 0)
-    clocks_per_cu = Np * (u64 / LDS_U64_LANE_OPS + u32 / LDS_U32_LANE_OPS) / CUS
-    return clocks_per_cu / CLOCK_HZ * 1e3
+    return Np * (u64 / rate64 + u32 / rate32) / cus * 1e3
 
 
 def traffic_profile(config_name, dtype):
@@ -283,6 +280,10 @@ def main():
     from paper_2106_12919_amd import lib as piclib
 
     torch.cuda.set_device(0)
+    LDS_RATES[32] = piclib.pic_probe_lds_atomics(32, 4096)
+    LDS_RATES[64] = piclib.pic_probe_lds_atomics(64, 4096)
+    print(f"[bench] LDS atomics: {LDS_RATES[32] / CLOCK_HZ:.1f} (32-bit) and {LDS_RATES[64] / CLOCK_HZ:.1f} (64-bit) "
+          f"lane-ops per clock per CU at {CLOCK_HZ / 1e9} GHz", file=sys.stderr, flush=True)
     wl = inputs.config(args.config, dtype=args.dtype, center_order=args.center_order)
     print(f"[bench] workload {args.config} dtype={wl.dtype} cells={wl.cells} particles={wl.electrons.n}",
           file=sys.stderr, flush=True)
@@ -650,13 +651,14 @@ def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0, v_gal=(0.0,
     d = breakdown[dom]
     achieved = d["algo_bytes"] / (d["ms_avg"] * 1e-3) / 1e9
     lds_floor = None
-    if "deposit" in breakdown:
-        fl = deposit_lds_floor_ms(Np, wl.shape_order, wl.dtype)
+    if "deposit" in breakdown and LDS_RATES:
+        fl = deposit_lds_floor_ms(Np, wl.shape_order, wl.dtype, LDS_RATES[32], LDS_RATES[64])
         dep = breakdown["deposit"]["ms_avg"]
         lds_floor = {"kernel": "deposit", "bound": "lds_atomics", "floor_ms": round(fl, 5), "ms_per_launch": dep,
                      "frac": round(fl / dep, 4),
-                     "basis": f"{LDS_U32_LANE_OPS} (u32) and {LDS_U64_LANE_OPS} (u64) lane-ops/clk/CU measured, "
-                              f"{CUS} CUs at {CLOCK_HZ / 1e9} GHz"}
+                     "basis": f"{LDS_RATES[32] / CLOCK_HZ:.2f} (u32) and {LDS_RATES[64] / CLOCK_HZ:.2f} (u64) "
+                              f"lane-ops/clk/CU measured now by pic_probe_lds_atomics, {CUS} CUs at "
+                              f"{CLOCK_HZ / 1e9} GHz"}
     final = None
     if keep:
         final = {"E": [t.clone() for t in f.E_stag], "B": [t.clone() for t in f.B_stag]}

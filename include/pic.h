@@ -350,6 +350,17 @@ pic_status pic_centering_factor(int32_t n, int32_t center_order, double* out);
  * other side): n_axis doubles.  Costs one coefficient evaluation per mode of the grid. */
 pic_status pic_stencil_extent(const pic_params* p, int32_t axis, int32_t coefficient, double* out);
 
+/* ---- Measurement support (no context). */
+
+/* Throughput of integer LDS atomics on the current device, the bound of the fixed-point
+ * deposition: every workgroup issues `iters` (a multiple of 16, 16 .. 2^20) adds per thread of
+ * width_bits (32: ds_add_u32 with the 32 lanes of each half wave on distinct words modulo 32;
+ * 64: ds_add_u64 with the 16 lanes of each quarter wave on distinct words modulo 16, the patterns
+ * of the deposition's dealt order) into its own LDS array; *lane_ops_per_s_per_cu receives the
+ * lane operations per second per compute unit.  Synchronous, on the null stream; allocates a few
+ * bytes of device memory.  PIC_EINVAL for bad arguments, PIC_EHIP if a HIP call fails. */
+pic_status pic_probe_lds_atomics(int width_bits, int iters, double* lane_ops_per_s_per_cu);
+
 /* Text of the last error of ctx (or of the last failed pic_init when ctx is NULL). */
 const char* pic_last_error(pic_ctx ctx);
 const char* pic_strerror(pic_status s);

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpic.so")
-SOURCES = ["api.hip", "fft.hip", "centering.hip", "psatd.hip", "particles.hip", "sort.hip", "diag.hip", "tables.cpp"]
+SOURCES = ["api.hip", "fft.hip", "centering.hip", "psatd.hip", "particles.hip", "sort.hip", "diag.hip", "tables.cpp",
+           "probe.hip"]
 
 ARCH = "gfx950"
 FLAGS = [

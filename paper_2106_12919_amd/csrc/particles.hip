@@ -19,6 +19,9 @@
 #ifndef PIC_DEPOSIT_BLOCK
 #define PIC_DEPOSIT_BLOCK 256
 #endif
+#ifndef PIC_DEPOSIT_BOUND_LOAD
+#define PIC_DEPOSIT_BOUND_LOAD 1
+#endif
 #ifndef PIC_DEPOSIT_CELL_KEY
 #define PIC_DEPOSIT_CELL_KEY 1
 #endif
@@ -194,6 +197,16 @@ __device__ inline void load_raw(const SpeciesView<T>& sp, int p, Raw<T>& r) {
   r.cell = sp.cell[p];
 #pragma unroll
   for (int d = 0; d < 3; ++d) r.o[d] = sp.off[d][p];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) r.u[d] = WJ ? sp.u[d][p] : (T)0;
+  const bool has_w = sp.w != nullptr;
+  const T wv = (has_w ? sp.w : no_weight<T>())[has_w ? p : 0];
+  r.w = has_w ? wv : (T)sp.w_const;
+}
+
+// What the scale bounds need of a particle: its momentum (when WJ) and weight.
+template <typename T, bool WJ>
+__device__ inline void load_bound(const SpeciesView<T>& sp, int p, Raw<T>& r) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) r.u[d] = WJ ? sp.u[d][p] : (T)0;
   const bool has_w = sp.w != nullptr;
@@ -949,7 +962,12 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
       through_perm(perm, qi);
       Raw<T> r[O::U];
 #pragma unroll
-      for (int u = 0; u < O::U; ++u) load_raw<T, WJ>(sp, qi[u], r[u]);
+      for (int u = 0; u < O::U; ++u) {
+        if (PIC_DEPOSIT_BOUND_LOAD)
+          load_bound<T, WJ>(sp, qi[u], r[u]);
+        else
+          load_raw<T, WJ>(sp, qi[u], r[u]);
+      }
 #pragma unroll
       for (int u = 0; u < O::U; ++u)
         if (q0 + u * PIC_DEPOSIT_BLOCK < end) bound_add<T, WJ>(r[u], sw, mw);

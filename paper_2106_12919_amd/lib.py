@@ -95,6 +95,7 @@ def load():
                                             POINTER(c_double)]),
         "pic_centering_factor": (c_int, [ctypes.c_int32, ctypes.c_int32, POINTER(c_double)]),
         "pic_stencil_extent": (c_int, [POINTER(pic_params), ctypes.c_int32, ctypes.c_int32, POINTER(c_double)]),
+        "pic_probe_lds_atomics": (c_int, [c_int, c_int, POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -241,6 +242,13 @@ def pic_stencil_extent(params, axis, coefficient):
     out = (c_double * n)()
     _check(load().pic_stencil_extent(ctypes.byref(params), axis, coefficient, out))
     return [float(x) for x in out]
+
+
+def pic_probe_lds_atomics(width_bits, iters=4096):
+    """Lane operations per second per compute unit of 32- or 64-bit integer LDS atomics."""
+    out = c_double()
+    _check(load().pic_probe_lds_atomics(width_bits, iters, ctypes.byref(out)))
+    return out.value
 
 
 # ------------------------------------------------------------------ tensor containers

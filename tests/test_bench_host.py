@@ -31,12 +31,13 @@ def test_algorithmic_bytes():
 
 
 def test_lds_atomic_floor():
-    # cubic FP32: 64 64-bit and 128 32-bit lane operations per particle, 256 CUs at 2.4 GHz
+    # cubic FP32: 64 64-bit and 128 32-bit lane operations per particle on each of 256 CUs
+    r32, r64 = 14.5 * 2.4e9, 9.9 * 2.4e9
     per_cu = 1000
-    expected = per_cu * (64 / bench.LDS_U64_LANE_OPS + 128 / bench.LDS_U32_LANE_OPS) / 2.4e9 * 1e3
-    assert bench.deposit_lds_floor_ms(256 * per_cu, 3, "f32") == pytest.approx(expected)
+    expected = per_cu * (64 / r64 + 128 / r32) * 1e3
+    assert bench.deposit_lds_floor_ms(256 * per_cu, 3, "f32", r32, r64) == pytest.approx(expected)
     # FP64 (CIC): four 64-bit words per node, 8 nodes
-    assert bench.deposit_lds_floor_ms(256, 1, "f64") == pytest.approx(32 / bench.LDS_U64_LANE_OPS / 2.4e9 * 1e3)
+    assert bench.deposit_lds_floor_ms(256, 1, "f64", r32, r64) == pytest.approx(32 / r64 * 1e3)
 
 
 def test_recorded_traffic_is_gated_on_the_kernel_sources(monkeypatch):
@@ -44,3 +45,4 @@ def test_recorded_traffic_is_gated_on_the_kernel_sources(monkeypatch):
     assert v is None or v > 0
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
     assert bench.recorded_traffic("deposit") is None
+    assert bench.recorded_traffic("deposit", "laser128") is None
