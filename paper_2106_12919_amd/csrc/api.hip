@@ -179,7 +179,6 @@ struct Engine : EngineBase {
   T* spill[4] = {nullptr, nullptr, nullptr, nullptr};
   int* spill_flag = nullptr;
   int* box_faces = nullptr;  // per tile, the outer faces of its deposition box that were staged
-  void* tile_max = nullptr;  // per tile, 4 maxima of the push for the next deposition's scales (T-wide words)
   unsigned dep_k = 0;
   std::vector<SpeciesScratch<T>> sps;
   cplx<T>* Eh[3] = {nullptr, nullptr, nullptr};
@@ -394,11 +393,6 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
   e.tiles = make_tiles(g);
   if ((err = e.alloc(&e.tiles.scan_tmp, (size_t)(e.tiles.ntiles + 1) / 8192 + 2)) != hipSuccess) return err;
   if ((err = e.alloc(&e.box_faces, (size_t)e.tiles.ntiles)) != hipSuccess) return err;
-  {
-    T* tm = nullptr;
-    if ((err = e.alloc(&tm, 4 * ((size_t)e.tiles.ntiles + 1))) != hipSuccess) return err;
-    e.tile_max = tm;
-  }
   if ((err = e.alloc(&e.t_counts, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_starts, (size_t)e.tiles.ntiles + 2)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_cursor, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;
@@ -1054,22 +1048,20 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
       if (keep) {  // caller's order: every step visits the particles through a tile permutation
         const SpeciesView<T> v = view<T>(sp[q]);
         const bool mobile = std::isfinite(sp[q].m);
-        void* tmax = (mobile && g.shape_order == 1) ? e.tile_max : nullptr;
         {
           StageScope sc(c, ST_SORT);
           tile_sort(g, e.tiles, v.cell, v.n, x.counts[0], x.starts[0], x.cursor, x.dst, c->d_bad, c->stream);
           invert_perm(x.dst, x.perm, v.n, c->stream);
-          if (tmax) (void)hipMemsetAsync(tmax, 0, sizeof(T) * 4 * ((size_t)e.tiles.ntiles + 1), c->stream);
         }
         if (mobile) {
           StageScope sc(c, ST_PUSH);
           gather_push_tiled<T>(g, e.tiles, Enod, Bnod, v, v, x.perm, x.starts[0], false, nullptr, nullptr,
-                               c->stream, tmax);
+                               c->stream);
         }
         {
           StageScope sc(c, ST_DEPOSIT);  // positions moved < 1 cell: the grouping still holds them
           deposit_tiled<T>(g, e.tiles, v, x.perm, x.starts[0], mobile, e.stage, c->d_bad, nullptr, nullptr, e.work,
-                           sum.spill_rho(), sum.spill_j(), c->stream, sum.begin(), e.box_faces, tmax);
+                           sum.spill_rho(), sum.spill_j(), c->stream, sum.begin(), e.box_faces);
         }
         {
           StageScope sc(c, ST_REDUCE);
@@ -1082,9 +1074,6 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
       const SpeciesView<T> alt = in_scratch[q] ? view<T>(sp[q]) : scratch_view<T>(x, sp[q]);
       const bool mobile = std::isfinite(sp[q].m);
       const size_t nt = (size_t)e.tiles.ntiles;
-      // CIC: the push records each tile's maxima for the deposition's scales (no bounds pass).
-      // Cubic keeps the bounds pass: the extra registers of the push cost it more than the pass.
-      void* tmax = (mobile && g.shape_order == 1) ? e.tile_max : nullptr;
       // Grouping: on the first step a full counting sort of the caller's order; afterwards
       // the deposition of the previous step has counted the tiles of the current cells.
       const int L = layout[q];
@@ -1099,19 +1088,18 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
           neighbour_bases(e.tiles, x.starts[L], x.nbr, x.starts[1 - L], x.nbr_base, x.cursor, c->stream);
         }
         if (mobile) (void)hipMemsetAsync(x.counts[first ? 1 : L], 0, sizeof(int) * (nt + 1), c->stream);
-        if (tmax) (void)hipMemsetAsync(tmax, 0, sizeof(T) * 4 * (nt + 1), c->stream);
       }
       const int* dep_starts = first ? x.starts[0] : (mobile ? x.starts[1 - L] : x.starts[L]);
       {
         StageScope sc(c, ST_PUSH);
         if (first && mobile)
           gather_push_tiled<T>(g, e.tiles, Enod, Bnod, cur, alt, x.perm, x.starts[0], true, nullptr, nullptr,
-                               c->stream, tmax);
+                               c->stream);
         else if (first)
           permute_species<T>(cur, alt, x.dst, c->stream);
         else if (mobile)
           gather_push_tiled<T>(g, e.tiles, Enod, Bnod, cur, alt, nullptr, x.starts[L], true, x.cursor, x.nbr_base,
-                               c->stream, tmax);
+                               c->stream);
       }
       const SpeciesView<T> dep = (first || mobile) ? alt : cur;  // immobile species stay put after the first step
       {
@@ -1119,7 +1107,7 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
         int* nextc = mobile ? x.counts[first ? 1 : L] : nullptr;
         deposit_tiled<T>(g, e.tiles, dep, nullptr, dep_starts, mobile, e.stage, c->d_bad, nextc,
                          mobile ? x.nbr : nullptr, e.work, sum.spill_rho(), sum.spill_j(), c->stream, sum.begin(),
-                         e.box_faces, tmax);
+                         e.box_faces);
       }
       {
         StageScope sc(c, ST_REDUCE);

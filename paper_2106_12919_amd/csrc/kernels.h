@@ -165,14 +165,10 @@ void neighbour_bases(const TileGeom& t, const int* old_starts, const int* nbr_co
 // nbr_bases (optional, from neighbour_bases) holds, per home tile, the first slot of
 // its particles bound for each neighbour tile [27 * ntiles]; without it each block
 // counts its particles and reserves the runs with atomics on home_cursor.
-// tile_max (optional, 4 (ntiles + 1) words of the run's float width, zeroed beforehand):
-// receives, per tile of the grouping the particles are written in, the maxima of |w| and
-// |w v_d| after the push (the bit patterns of the non-negative values), for deposit_tiled.
 template <typename T>
 void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3], const T* const B[3],
                        const SpeciesView<T>& in, const SpeciesView<T>& out, const int* perm, const int* starts,
-                       bool write_sorted, int* home_cursor, const int* nbr_bases, hipStream_t s,
-                       void* tile_max = nullptr);
+                       bool write_sorted, int* home_cursor, const int* nbr_bases, hipStream_t s);
 template <typename T>
 void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const int* dst, hipStream_t s);
 // Deposition of one species in two launches.  deposit_tiled accumulates rho (at the
@@ -189,14 +185,11 @@ void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const 
 // ``spill_flag`` (optional) is set to 1 whenever a particle goes to rho/J directly.  With
 // ``box_faces`` (ntiles ints, optional; used on grids of whole tiles) each tile stages only
 // the layers of its box that hold a nonzero value and records which outer faces it staged,
-// for a deposit_reduce with the same array in ReduceArgs::box_faces.  With ``tile_max`` (the
-// maxima gather_push_tiled recorded for exactly this grouping) the fixed-point scales come
-// from them and the particle count, and no bounds pass runs.
+// for a deposit_reduce with the same array in ReduceArgs::box_faces.
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
                    bool with_j, T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, T* rho,
-                   T* const J[3], hipStream_t s, int* spill_flag = nullptr, int* box_faces = nullptr,
-                   const void* tile_max = nullptr);
+                   T* const J[3], hipStream_t s, int* spill_flag = nullptr, int* box_faces = nullptr);
 // How deposit_reduce starts each node and what else it folds in.  By default it adds to the
 // nodal arrays.  With bit 0 (rho) or bit 1 (J) of acc_mask clear it overwrites them instead,
 // rho starting from ``base`` when given, else from zero.  When *flag != 0, the ``spill``

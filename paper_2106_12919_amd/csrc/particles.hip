@@ -415,50 +415,6 @@ __device__ inline void copy_particle(const SpeciesView<T>& in, long long p, cons
   if (in.w) out.w[q] = in.w[p];
 }
 
-// The deposition's scale bounds of a particle after its push: |w| (rho) and |w v_d| (J^d), as
-// the deposition's own bounds take them (bound_add).  Non-negative floats order as their bit
-// patterns, so the maxima are taken with integer atomics.
-template <typename T>
-__device__ inline void push_bounds(T w, T ux, T uy, T uz, T* m) {
-  const T a = fabs(w);
-  const T ig = inv_sqrt((T)1 + ux * ux + uy * uy + uz * uz);
-  m[0] = fmax(m[0], a);
-  m[1] = fmax(m[1], a * fabs(ux * ig));
-  m[2] = fmax(m[2], a * fabs(uy * ig));
-  m[3] = fmax(m[3], a * fabs(uz * ig));
-}
-__device__ inline unsigned int max_bits(float x) { return __float_as_uint(x); }
-__device__ inline unsigned long long max_bits(double x) { return (unsigned long long)__double_as_longlong(x); }
-__device__ inline float from_max_bits(unsigned int b, float) { return __uint_as_float(b); }
-__device__ inline double from_max_bits(unsigned long long b, double) { return __longlong_as_double((long long)b); }
-template <typename T>
-struct MaxBitsOf;
-template <>
-struct MaxBitsOf<float> {
-  using type = unsigned int;
-};
-template <>
-struct MaxBitsOf<double> {
-  using type = unsigned long long;
-};
-template <typename T>
-using MaxBits = typename MaxBitsOf<T>::type;
-// Shapes whose push records the bounds (CIC); other orders ignore tile maxima on both sides.
-template <int ORDER>
-constexpr bool kPushBounds = ORDER == 1;
-
-// The block's maxima m[4] (per thread) into lds[4] (zeroed), by a wave reduction and one LDS
-// atomic per wave and component.  Every thread of the block calls it (converged).
-template <typename T>
-__device__ inline void block_max4(T* m, MaxBits<T>* lds) {
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    T x = m[c];
-    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_xor(x, o, 64));
-    if (__lane_id() == 0 && x > (T)0) atomicMax(&lds[c], max_bits(x));
-  }
-}
-
 // Gather + push through a permutation: one block per tile t of the particles'
 // current cells, slots q in [starts[t], starts[t+1]); slot q reads particle perm[q]
 // of ``in`` and writes it to slot q (write_sorted) or back to perm[q] of ``out``.
@@ -468,11 +424,9 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_perm(GridGeom 
                                                                        SpeciesView<T> in, SpeciesView<T> out,
                                                                        const int* __restrict__ perm,
                                                                        const int* __restrict__ starts, int write_sorted,
-                                                                       T qdt2m, T dtx, T dty, T dtz,
-                                                                       MaxBits<T>* __restrict__ tmax) {
+                                                                       T qdt2m, T dtx, T dty, T dtz) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* box = reinterpret_cast<T*>(smem);
-  __shared__ MaxBits<T> bmax[4];
   const int tile = xcd_major(blockIdx.x, gridDim.x);
   const int beg = starts[tile], end = starts[tile + 1];
   if (beg == end) return;
@@ -483,8 +437,6 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_perm(GridGeom 
     }
     return;
   }
-  if (kPushBounds<ORDER> && threadIdx.x < 4) bmax[threadIdx.x] = 0;
-  T am[4] = {0, 0, 0, 0};
   int tx, ty, tz;
   tile_coords(tile, tg, tx, ty, tz);
   const int t0x = tx * kTile, t0y = ty * kTile, t0z = tz * kTile;
@@ -507,12 +459,6 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_perm(GridGeom 
     out.off[2][wi] = oz;
     out.cell[wi] = (i * g.ny + j) * g.nz + k;
     if (in.w && (write_sorted || out.w != in.w)) out.w[wi] = in.w[p];
-    if (kPushBounds<ORDER> && tmax) push_bounds<T>(in.w ? in.w[p] : (T)in.w_const, ux, uy, uz, am);
-  }
-  if (kPushBounds<ORDER> && tmax) {  // this tile's bounds for the deposition that follows (one block per tile)
-    block_max4<T>(am, bmax);
-    __syncthreads();
-    if (threadIdx.x < 4) tmax[4 * tile + threadIdx.x] = bmax[threadIdx.x];
   }
 }
 
@@ -530,13 +476,11 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
                                                                        SpeciesView<T> in, SpeciesView<T> out,
                                                                        const int* __restrict__ home, int* cursor,
                                                                        const int* __restrict__ nbr_bases, T qdt2m,
-                                                                       T dtx, T dty, T dtz,
-                                                                       MaxBits<T>* __restrict__ tmax) {
+                                                                       T dtx, T dty, T dtz) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* box = reinterpret_cast<T*>(smem);
   __shared__ int cnt[27];
   __shared__ int base[27];
-  __shared__ MaxBits<T> nmax[27 * 4];  // per neighbour tile of the new grouping: its bounds
   const int tile = xcd_major(blockIdx.x, gridDim.x);
   const int beg = home[tile], end = home[tile + 1];
   if (beg == end) return;
@@ -553,9 +497,6 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
     cnt[threadIdx.x] = 0;
     if (nbr_bases) base[threadIdx.x] = nbr_bases[27 * tile + threadIdx.x];
   }
-  if (kPushBounds<ORDER>)
-    for (int e = threadIdx.x; e < 27 * 4; e += blockDim.x) nmax[e] = 0;
-  T am[4] = {0, 0, 0, 0};  // this thread's particles that stay in the home tile's group
   load_field_box<T, ORDER, true>(box, F, g, t0x, t0y, t0z);
   __syncthreads();
   if (!nbr_bases) {
@@ -617,26 +558,6 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
     out.off[2][slot] = oz;
     out.cell[slot] = (i * g.ny + j) * g.nz + k;
     if (in.w) out.w[slot] = r.w;
-    if (kPushBounds<ORDER> && tmax) {
-      if (nb == 13) {
-        push_bounds<T>(r.w, ux, uy, uz, am);
-      } else {  // rare: straight to the neighbour's (or, beyond the neighbours, the tile's) maxima
-        T m[4] = {0, 0, 0, 0};
-        push_bounds<T>(r.w, ux, uy, uz, m);
-        MaxBits<T>* dst = nb >= 0 ? nmax + 4 * nb : tmax + 4 * tile_of(i, j, k, tg);
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          if (m[c] > (T)0) atomicMax(&dst[c], max_bits(m[c]));
-      }
-    }
-  }
-  if (kPushBounds<ORDER> && tmax) {
-    block_max4<T>(am, nmax + 4 * 13);
-    __syncthreads();
-    for (int e = threadIdx.x; e < 27 * 4; e += blockDim.x) {
-      const MaxBits<T> v = nmax[e];
-      if (v) atomicMax(&tmax[4 * neighbour_key(e / 4, tx, ty, tz, tg) + (e % 4)], v);
-    }
   }
 }
 
@@ -968,7 +889,7 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
                                     const int* __restrict__ perm, const int* __restrict__ starts,
                                     const Batch<T*>& out, T* __restrict__ stage, T qdv, T hdtx, T hdty, T hdtz,
                                     int* bad, int* next_counts, int* nbr_counts, int* spill_flag, int* box_faces,
-                                    const MaxBits<T>* tmax, typename Fixed<T>::acc_t* box, DepositLds<T>& L) {
+                                    typename Fixed<T>::acc_t* box, DepositLds<T>& L) {
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
   using O = DepositOrder<T>;
@@ -1002,10 +923,7 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
   // MaxWeight times the tile's sum of those magnitudes (< 2^e_sum), every contribution
   // by their max (< 2^e_max).  A tile of one chunk takes the bounds in the chunk's
   // first pass; a larger one in a pass of its own.
-  // tmax: the maxima of |w| and |w v_d| over the tile's particles, taken by the push that produced
-  // them; the scales then follow from count x max (as in the deterministic mode) with no pass here
-  const bool pre = kPushBounds<ORDER> && tmax != nullptr;
-  const bool single = !pre && end - beg <= O::CH;
+  const bool single = end - beg <= O::CH;
   T sw[4] = {0, 0, 0, 0}, mw[4] = {0, 0, 0, 0};
   auto publish_bounds = [&]() {  // wave partials -> red / redm
 #pragma unroll
@@ -1036,16 +954,7 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
       shs[c] = Fixed<T>::shift(e_sum, e_max, 32 - __clz(end - beg));
     }
   };
-  if (pre) {
-    if (threadIdx.x < ncomp) {
-      const int c = threadIdx.x;
-      const T x = from_max_bits(tmax[4 * tile + c], (T)0);
-      int e_sum = 0, e_max = 0;
-      (void)frexp(x * (T)(end - beg) * fabs(qdv) * (T)(MaxWeight<ORDER>::value * 1.001), &e_sum);
-      (void)frexp(x * fabs(qdv) * (T)1.001, &e_max);
-      shs[c] = Fixed<T>::shift(e_sum, e_max, 32 - __clz(end - beg));
-    }
-  } else if (!single) {
+  if (!single) {
     for (int q0 = beg + threadIdx.x; q0 < end; q0 += O::U * PIC_DEPOSIT_BLOCK) {
       int qi[O::U];
 #pragma unroll
@@ -1080,7 +989,7 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
     // cell alone (one int per particle instead of its whole record): the first support node of
     // the current shifts from it only when the half step crosses a cell face, and the deal only
     // orders the atomics, it does not change their sums.
-    if (PIC_DEPOSIT_CELL_KEY && (pre || !single)) {
+    if (PIC_DEPOSIT_CELL_KEY && !single) {
       const int e0 = threadIdx.x;
       int qi[O::U];
 #pragma unroll
@@ -1280,7 +1189,7 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK, sizeof(T) == 4 ? (ORDER == 
     k_deposit_tiled(GridGeom g, TileGeom tg, SpeciesView<T> sp, const int* __restrict__ perm,
                     const int* __restrict__ starts, Batch<T*> out, T* __restrict__ stage, T qdv, T hdtx, T hdty,
                     T hdtz, int* bad, int* next_counts, int* nbr_counts, int* work, int* spill_flag,
-                    int* box_faces, const MaxBits<T>* __restrict__ tmax) {
+                    int* box_faces) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ DepositLds<T> L;
   auto* box = reinterpret_cast<typename Fixed<T>::acc_t*>(smem);
@@ -1292,11 +1201,11 @@ __global__ void __launch_bounds__(PIC_DEPOSIT_BLOCK, sizeof(T) == 4 ? (ORDER == 
       __syncthreads();
       if (tile > tg.ntiles) break;
       deposit_tile<T, ORDER, WJ>(tile, g, tg, sp, perm, starts, out, stage, qdv, hdtx, hdty, hdtz, bad, next_counts,
-                                 nbr_counts, spill_flag, box_faces, tmax, box, L);
+                                 nbr_counts, spill_flag, box_faces, box, L);
     }
   } else {
     deposit_tile<T, ORDER, WJ>(blockIdx.x, g, tg, sp, perm, starts, out, stage, qdv, hdtx, hdty, hdtz, bad,
-                               next_counts, nbr_counts, spill_flag, box_faces, tmax, box, L);
+                               next_counts, nbr_counts, spill_flag, box_faces, box, L);
   }
 }
 
@@ -2257,8 +2166,7 @@ int deposit_box(int shape_order) { return kTile + (shape_order == 1 ? 2 : 4) + 1
 template <typename T>
 void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3], const T* const B[3],
                        const SpeciesView<T>& in, const SpeciesView<T>& out, const int* perm, const int* starts,
-                       bool write_sorted, int* home_cursor, const int* nbr_bases, hipStream_t s, void* tile_max) {
-  MaxBits<T>* tmax = static_cast<MaxBits<T>*>(tile_max);
+                       bool write_sorted, int* home_cursor, const int* nbr_bases, hipStream_t s) {
   if (in.n <= 0) return;
   Batch<const T*> F{};
   for (int d = 0; d < 3; ++d) {
@@ -2274,22 +2182,22 @@ void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3]
     if (g.shape_order == 1) {
       allow_lds((const void*)k_gather_push_home<T, 1>, lds);
       hipLaunchKernelGGL((k_gather_push_home<T, 1>), grid, block, lds, s, g, t, F, in, out, starts, home_cursor,
-                         nbr_bases, qdt2m, dtx, dty, dtz, tmax);
+                         nbr_bases, qdt2m, dtx, dty, dtz);
     } else {
       allow_lds((const void*)k_gather_push_home<T, 3>, lds);
       hipLaunchKernelGGL((k_gather_push_home<T, 3>), grid, block, lds, s, g, t, F, in, out, starts, home_cursor,
-                         nbr_bases, qdt2m, dtx, dty, dtz, tmax);
+                         nbr_bases, qdt2m, dtx, dty, dtz);
     }
   } else {
     const int ws = write_sorted ? 1 : 0;
     if (g.shape_order == 1) {
       allow_lds((const void*)k_gather_push_perm<T, 1>, lds);
       hipLaunchKernelGGL((k_gather_push_perm<T, 1>), grid, block, lds, s, g, t, F, in, out, perm, starts, ws, qdt2m,
-                         dtx, dty, dtz, tmax);
+                         dtx, dty, dtz);
     } else {
       allow_lds((const void*)k_gather_push_perm<T, 3>, lds);
       hipLaunchKernelGGL((k_gather_push_perm<T, 3>), grid, block, lds, s, g, t, F, in, out, perm, starts, ws, qdt2m,
-                         dtx, dty, dtz, tmax);
+                         dtx, dty, dtz);
     }
   }
 }
@@ -2309,7 +2217,7 @@ int resident_blocks(const void* kernel, int block, size_t lds) {
 template <typename T, int ORDER, bool WJ>
 void launch_deposit(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
                     T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, int* spill_flag,
-                    int* box_faces, const Batch<T*>& out, hipStream_t s, const MaxBits<T>* tmax) {
+                    int* box_faces, const Batch<T*>& out, hipStream_t s) {
   const T qdv = (T)(sp.q / (g.dx * g.dy * g.dz));
   const T hx = (T)(0.5 * g.dt / g.dx), hy = (T)(0.5 * g.dt / g.dy), hz = (T)(0.5 * g.dt / g.dz);
   constexpr int B = Box<Shape<T, ORDER>::NW>::B;
@@ -2324,15 +2232,13 @@ void launch_deposit(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& 
     (void)hipMemsetAsync(work, 0, sizeof(int), s);
   }
   hipLaunchKernelGGL((k_deposit_tiled<T, ORDER, WJ>), dim3(nb), dim3(PIC_DEPOSIT_BLOCK), lds, s, g, t, sp, perm,
-                     starts, out, stage, qdv, hx, hy, hz, bad, next_counts, nbr_counts, work, spill_flag, box_faces,
-                     tmax);
+                     starts, out, stage, qdv, hx, hy, hz, bad, next_counts, nbr_counts, work, spill_flag, box_faces);
 }
 
 template <typename T>
 void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& sp, const int* perm, const int* starts,
                    bool with_j, T* stage, int* bad, int* next_counts, int* nbr_counts, int* work, T* rho,
-                   T* const J[3], hipStream_t s, int* spill_flag, int* box_faces, const void* tile_max) {
-  const MaxBits<T>* tmax = static_cast<const MaxBits<T>*>(tile_max);
+                   T* const J[3], hipStream_t s, int* spill_flag, int* box_faces) {
   if (sp.n <= 0) return;
   // the face masks serve the whole-tile reduction only; the other one reads whole boxes
   if (!(g.nx % kTile == 0 && g.ny % kTile == 0 && g.nz % kTile == 0)) box_faces = nullptr;
@@ -2340,11 +2246,11 @@ void deposit_tiled(const GridGeom& g, const TileGeom& t, const SpeciesView<T>& s
   out.p[0] = rho;
   for (int d = 0; d < 3; ++d) out.p[1 + d] = J ? J[d] : nullptr;
   if (g.shape_order == 1) {
-    if (with_j) launch_deposit<T, 1, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, box_faces, out, s, tmax);
-    else launch_deposit<T, 1, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, box_faces, out, s, tmax);
+    if (with_j) launch_deposit<T, 1, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, box_faces, out, s);
+    else launch_deposit<T, 1, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, box_faces, out, s);
   } else {
-    if (with_j) launch_deposit<T, 3, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, box_faces, out, s, tmax);
-    else launch_deposit<T, 3, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, box_faces, out, s, tmax);
+    if (with_j) launch_deposit<T, 3, true>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, box_faces, out, s);
+    else launch_deposit<T, 3, false>(g, t, sp, perm, starts, stage, bad, next_counts, nbr_counts, work, spill_flag, box_faces, out, s);
   }
 }
 
@@ -2536,13 +2442,12 @@ void deposit_yee(const GridGeom& g, const SpeciesView<T>& sp, bool with_j, T* rh
 #define PIC_INST(T)                                                                                              \
   template void permute_species<T>(const SpeciesView<T>&, const SpeciesView<T>&, const int*, hipStream_t);       \
   template void deposit_tiled<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const int*, const int*, \
-                                 bool, T*, int*, int*, int*, int*, T*, T* const*, hipStream_t, int*, int*,       \
-                                 const void*);                                                                   \
+                                 bool, T*, int*, int*, int*, int*, T*, T* const*, hipStream_t, int*, int*);      \
   template void deposit_reduce<T>(const GridGeom&, const TileGeom&, const int*, const T*, bool, T*, T* const*,   \
                                   hipStream_t, const ReduceArgs<T>&);                                            \
   template void gather_push_tiled<T>(const GridGeom&, const TileGeom&, const T* const*, const T* const*,         \
                                      const SpeciesView<T>&, const SpeciesView<T>&, const int*, const int*, bool,  \
-                                     int*, const int*, hipStream_t, void*);                                       \
+                                     int*, const int*, hipStream_t);                                              \
   template void particle_adjoint<T>(const GridGeom&, const TileGeom&, const SpeciesView<T>&, const Batch<T*>&,    \
                                     const int*, const int*, const T* const*, const T* const*, const Batch<T*>&,   \
                                     hipStream_t);                                                                 \
