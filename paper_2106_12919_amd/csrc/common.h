@@ -50,7 +50,50 @@ struct FftPlan {
   int twcount;
 };
 
-FftPlan make_fft_plan(int n);
+// The plan of an axis of n = 2^a 3^b points: the radix-3 stages first, then radix 8 with
+// a 4 x 4 or a 4 or a 2 for the rest of the power of two (nstages = -1 for other n).  A
+// constant expression, so that kernels specialised for an axis length take the same stages
+// and twiddle offsets as the table the host builds from it.
+constexpr FftPlan plan_of(int n) {
+  FftPlan p{};
+  p.n = n;
+  int rest = n, n3 = 0, n2 = 0;
+  while (rest > 0 && rest % 3 == 0) { rest /= 3; ++n3; }
+  while (rest > 0 && rest % 2 == 0) { rest /= 2; ++n2; }
+  int r[64] = {};
+  int k = 0;
+  if (rest == 1) {
+    for (int i = 0; i < n3; ++i) r[k++] = 3;
+    int n8 = n2 / 3;
+    const int rem = n2 % 3;
+    if (rem == 1 && n8 > 0) {
+      n8 -= 1;
+      for (int i = 0; i < n8; ++i) r[k++] = 8;
+      r[k++] = 4;
+      r[k++] = 4;
+    } else {
+      for (int i = 0; i < n8; ++i) r[k++] = 8;
+      if (rem == 2) r[k++] = 4;
+      if (rem == 1) r[k++] = 2;
+    }
+  }
+  if (rest != 1 || k > kMaxStages) {
+    p.nstages = -1;
+    return p;
+  }
+  p.nstages = k;
+  int ns = 1, off = 0;
+  for (int s = 0; s < k; ++s) {
+    p.radix[s] = r[s];
+    p.ns[s] = ns;
+    p.twoff[s] = off;
+    off += ns * (r[s] - 1);
+    ns *= r[s];
+  }
+  p.twcount = off;
+  return p;
+}
+inline FftPlan make_fft_plan(int n) { return plan_of(n); }
 // FP64 twiddles of a plan, 2*twcount doubles (re, im) of exp(-2 pi i k r/(ns R)).
 void fft_twiddles(const FftPlan& p, double* out);
 

@@ -17,6 +17,8 @@
 //           butterfly reads and writes free of bank conflicts.
 // Each Stockham stage reads its radix-R butterfly inputs from one LDS buffer and
 // writes the outputs in autosorted order to the other buffer.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace pic {
@@ -149,6 +151,33 @@ __device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nlines, int ls, int js, 
   return a;
 }
 
+// The transform of lines whose length N and count NL per block are compile-time constants:
+// every stage's radix, stride and twiddle offset is a constant of plan_of(N), so butterfly
+// indices need no runtime division and LDS offsets become instruction immediates.  Same
+// butterflies, in the same order, as fft_lds.  Returns the buffer holding the result.
+template <typename T, int SIGN, int N, int NL, bool LINE_FASTEST, int S = 0>
+__device__ inline cplx<T>* fft_lds_static(cplx<T>* a, cplx<T>* b, const cplx<T>* __restrict__ tw) {
+  constexpr FftPlan P = plan_of(N);
+  if constexpr (S == P.nstages) {
+    return a;
+  } else {
+    constexpr int R = P.radix[S], NS = P.ns[S], NB = N / R, TOTAL = NL * NB;
+    constexpr int LS = LINE_FASTEST ? 1 : N, JS = LINE_FASTEST ? NL : 1;
+    const cplx<T>* tws = tw + P.twoff[S];
+#pragma unroll
+    for (int w0 = 0; w0 < TOTAL; w0 += kBlock) {
+      const int w = w0 + (int)threadIdx.x;
+      if (TOTAL % kBlock == 0 || w < TOTAL) {
+        const int l = LINE_FASTEST ? w % NL : w / NB;
+        const int bi = LINE_FASTEST ? w / NL : w % NB;
+        butterfly<T, SIGN, R>(a, b, l * LS, JS, bi, NB, NS, tws);
+      }
+    }
+    __syncthreads();
+    return fft_lds_static<T, SIGN, N, NL, LINE_FASTEST, S + 1>(b, a, tw);
+  }
+}
+
 // Largest element count per thread of one block's LDS tile (two buffers of kLdsBudget
 // bytes in all): every thread issues all its global loads (those inside the tile) before it
 // stores any to LDS.
@@ -156,6 +185,13 @@ __device__ cplx<T>* fft_lds(cplx<T>* a, cplx<T>* b, int nlines, int ls, int js, 
 #define PIC_FFT_LDS_BUDGET 65536
 #endif
 constexpr size_t kLdsBudget = PIC_FFT_LDS_BUDGET;
+// Elements per z-pass block (line pairs times the line length) and the largest strided tile.
+#ifndef PIC_FFT_ZPASS_ELEMS
+#define PIC_FFT_ZPASS_ELEMS 2048
+#endif
+#ifndef PIC_FFT_MAX_TL_SHIFT
+#define PIC_FFT_MAX_TL_SHIFT 4
+#endif
 template <typename T>
 constexpr int kPerThread = (int)(kLdsBudget / (2 * sizeof(cplx<T>)) / kBlock);
 
@@ -318,25 +354,188 @@ __global__ void __launch_bounds__(kBlock) k_fft_strided(Batch<const cplx<T>*> in
 }
 
 
-// Tiles fit the LDS budget of a launch together with the twiddles (fewer than n of them).
+// ------------------------------------------------- kernels for compile-time axis lengths
+// The passes above with the axis length N, the pairs per z-pass block P and the lines per
+// strided tile TL as template constants (same data layout, LDS use and arithmetic).
+
+// Largest P (z pass) and TL (strided pass) that fit the LDS budget with the twiddles.
 template <typename T>
-#ifndef PIC_FFT_ZPASS_ELEMS
-#define PIC_FFT_ZPASS_ELEMS 2048
-#endif
-int pairs_per_block(int n) {
+constexpr int static_pairs(int n) {
   int P = PIC_FFT_ZPASS_ELEMS / n;
   if (P < 1) P = 1;
   while (P > 1 && (2 * (size_t)P * n + n) * sizeof(cplx<T>) > kLdsBudget) P /= 2;
   return P;
 }
+template <typename T>
+constexpr int static_lines(int n) {
+  int sh = PIC_FFT_MAX_TL_SHIFT;
+  while (sh > 0 && (2 * ((size_t)1 << sh) * n + n) * sizeof(cplx<T>) > kLdsBudget) --sh;
+  return 1 << sh;
+}
 
-#ifndef PIC_FFT_MAX_TL_SHIFT
-#define PIC_FFT_MAX_TL_SHIFT 4
-#endif
+template <typename T, int N>
+__global__ void __launch_bounds__(kBlock) k_r2c_z_n(Batch<const T*> in, Batch<cplx<T>*> out,
+                                                    const cplx<T>* __restrict__ tw, int nlines, int pz) {
+  constexpr int P = static_pairs<T>(N);
+  constexpr int TW = plan_of(N).twcount;
+  constexpr int PER = (P * N + kBlock - 1) / kBlock;
+  constexpr int NH = N / 2 + 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* b = a + (size_t)P * N;
+  const int pair0 = blockIdx.x * P;
+  const int np = min(P, nlines / 2 - pair0);
+  const unsigned total = (unsigned)(np * N);
+  const T* __restrict__ src = in.p[blockIdx.y] + (size_t)2 * pair0 * N;  // line 2 pair0 of this block
+  cplx<T>* __restrict__ dst = out.p[blockIdx.y] + (size_t)2 * pair0 * pz;
+  T v0[PER], v1[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const unsigned e = threadIdx.x + u * kBlock;
+    if (e < total) {
+      const unsigned q = e / N, j = e - q * N;
+      v0[u] = src[2 * q * N + j];
+      v1[u] = src[(2 * q + 1) * N + j];
+    }
+  }
+  const cplx<T>* twl = stage_twiddles(b + (size_t)P * N, tw, TW);
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const unsigned e = threadIdx.x + u * kBlock;
+    if (e < total) a[e] = cmake(v0[u], v1[u]);
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lds_static<T, -1, N, P, false>(a, b, twl);
+  constexpr int OUTER = (P * NH + kBlock - 1) / kBlock;
+#pragma unroll
+  for (int u = 0; u < OUTER; ++u) {
+    const unsigned e = threadIdx.x + u * kBlock;
+    if (e < (unsigned)(np * NH)) {
+      const unsigned q = e / NH, k = e - q * NH;
+      const cplx<T> zk = res[q * N + k];
+      const cplx<T> zn = res[q * N + (k == 0 ? 0 : N - k)];
+      const cplx<T> F = cmake((T)0.5 * (zk.x + zn.x), (T)0.5 * (zk.y - zn.y));
+      const cplx<T> G = cmake((T)0.5 * (zk.y + zn.y), (T)0.5 * (zn.x - zk.x));
+      dst[2 * q * pz + k] = F;
+      dst[(2 * q + 1) * pz + k] = G;
+    }
+  }
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(kBlock) k_c2r_z_n(Batch<const cplx<T>*> in, Batch<T*> out,
+                                                    const cplx<T>* __restrict__ tw, int nlines, int pz, T scale,
+                                                    T scale_lo) {
+  constexpr int P = static_pairs<T>(N);
+  constexpr int TW = plan_of(N).twcount;
+  constexpr int PER = (P * N + kBlock - 1) / kBlock;
+  constexpr int HALF = N / 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* b = a + (size_t)P * N;
+  const int pair0 = blockIdx.x * P;
+  const int np = min(P, nlines / 2 - pair0);
+  const unsigned total = (unsigned)(np * N);
+  const cplx<T>* __restrict__ src = in.p[blockIdx.y] + (size_t)2 * pair0 * pz;
+  T* __restrict__ dst = out.p[blockIdx.y] + (size_t)2 * pair0 * N;
+  cplx<T> f[PER], g[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const unsigned e = threadIdx.x + u * kBlock;
+    if (e < total) {
+      const unsigned q = e / N, k = e - q * N;
+      const unsigned kk = k <= HALF ? k : N - k;
+      f[u] = src[2 * q * pz + kk];
+      g[u] = src[(2 * q + 1) * pz + kk];
+    }
+  }
+  const cplx<T>* twl = stage_twiddles(b + (size_t)P * N, tw, TW);
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const unsigned e = threadIdx.x + u * kBlock;
+    if (e < total) {
+      const unsigned k = e % N;
+      cplx<T> F = f[u], G = g[u];
+      if (k > HALF) {
+        F = cconj(F);
+        G = cconj(G);
+      } else if (k == 0 || k == HALF) {
+        F.y = 0;
+        G.y = 0;
+      }
+      a[e] = cmake(F.x - G.y, F.y + G.x);
+    }
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lds_static<T, +1, N, P, false>(a, b, twl);
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const unsigned e = threadIdx.x + u * kBlock;
+    if (e < total) {
+      const unsigned q = e / N, j = e - q * N;
+      const cplx<T> v = res[e];
+      dst[2 * q * N + j] = mul_const(v.x, scale, scale_lo);
+      dst[(2 * q + 1) * N + j] = mul_const(v.y, scale, scale_lo);
+    }
+  }
+}
+
+// Strided pass with N and TL constant.  Thread t holds line i = t mod TL of the tile (kBlock
+// is a multiple of TL) at elements j = t / TL + u kBlock / TL, so its global address advances
+// by a constant number of rows per u.
+template <typename T, int SIGN, int N>
+__global__ void __launch_bounds__(kBlock) k_fft_strided_n(Batch<const cplx<T>*> in, Batch<cplx<T>*> out,
+                                                          const cplx<T>* __restrict__ tw, int inner_count,
+                                                          int tiles_per_outer, long long outer_stride,
+                                                          long long elem_stride) {
+  constexpr int TL = static_lines<T>(N);
+  static_assert(kBlock % TL == 0, "a block covers whole rows of the tile");
+  constexpr int TW = plan_of(N).twcount;
+  constexpr int TOTAL = N * TL;
+  constexpr int PER = (TOTAL + kBlock - 1) / kBlock;
+  constexpr int ROWS = kBlock / TL;  // rows advanced per u
+  extern __shared__ __align__(16) unsigned char smem[];
+  cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* b = a + (size_t)TL * N;
+  const int tile = PIC_FFT_XCD ? xcd_major(blockIdx.x, gridDim.x) : blockIdx.x;
+  const int outer = tile / tiles_per_outer;
+  const int inner0 = (tile - outer * tiles_per_outer) * TL;
+  const int nl = min(TL, inner_count - inner0);
+  const int i = (int)threadIdx.x % TL, j0 = (int)threadIdx.x / TL;
+  const long long row0 = (long long)outer * outer_stride + inner0 + min(i, nl - 1) + (long long)j0 * elem_stride;
+  const long long step = (long long)ROWS * elem_stride;
+  const cplx<T>* __restrict__ src = in.p[blockIdx.y] + row0;
+  cplx<T> v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u)
+    if (TOTAL % kBlock == 0 || (int)threadIdx.x + u * kBlock < TOTAL) v[u] = src[u * step];
+  const cplx<T>* twl = stage_twiddles(b + (size_t)TL * N, tw, TW);
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = (int)threadIdx.x + u * kBlock;
+    if (TOTAL % kBlock == 0 || e < TOTAL) a[e] = i < nl ? v[u] : cmake((T)0, (T)0);
+  }
+  __syncthreads();
+  cplx<T>* res = fft_lds_static<T, SIGN, N, TL, true>(a, b, twl);
+  if (i < nl) {
+    cplx<T>* __restrict__ dst = out.p[blockIdx.y] + row0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = (int)threadIdx.x + u * kBlock;
+      if (TOTAL % kBlock == 0 || e < TOTAL) dst[u * step] = res[e];
+    }
+  }
+}
+
+// Tiles fit the LDS budget of a launch together with the twiddles (fewer than n of them).
+template <typename T>
+int pairs_per_block(int n) {
+  return static_pairs<T>(n);
+}
 template <typename T>
 int lines_per_tile_shift(int n) {
-  int sh = PIC_FFT_MAX_TL_SHIFT;  // 16 lines
-  while (sh > 0 && (2 * ((size_t)1 << sh) * n + n) * sizeof(cplx<T>) > kLdsBudget) --sh;
+  int sh = 0;
+  while ((1 << sh) < static_lines<T>(n)) ++sh;
   return sh;
 }
 
@@ -346,10 +545,40 @@ size_t fft_lds_bytes(size_t elems, const FftPlan& p) {
   return (2 * elems + (size_t)(p.twcount > 0 ? p.twcount : 1)) * sizeof(cplx<T>);
 }
 
+#ifndef PIC_FFT_STATIC
+#define PIC_FFT_STATIC 1
+#endif
+// Calls f(std::integral_constant<int, n>) for the axis lengths that have kernels of their own
+// (those of the configurations this library is tuned on) and returns whether it did; other
+// lengths take the generic kernels.
+template <typename F>
+bool with_static_length(int n, F&& f) {
+  if (!PIC_FFT_STATIC) return false;
+  switch (n) {
+    case 64: f(std::integral_constant<int, 64>{}); return true;
+    case 128: f(std::integral_constant<int, 128>{}); return true;
+    case 256: f(std::integral_constant<int, 256>{}); return true;
+    case 384: f(std::integral_constant<int, 384>{}); return true;
+    case 768: f(std::integral_constant<int, 768>{}); return true;
+    default: return false;
+  }
+}
+
 template <typename T, int SIGN>
 void strided_pass(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& out, int count, const FftPlan& p,
                   const cplx<T>* tw, int outer_count, int inner_count, long long outer_stride, long long elem_stride,
                   hipStream_t s) {
+  if (with_static_length(p.n, [&](auto nc) {
+        constexpr int N = decltype(nc)::value;
+        constexpr int TL = static_lines<T>(N);
+        const int tpo = (inner_count + TL - 1) / TL;
+        dim3 grid(outer_count * tpo, count);
+        const size_t lds = fft_lds_bytes<T>((size_t)TL * N, p);
+        allow_lds((const void*)k_fft_strided_n<T, SIGN, N>, lds);
+        hipLaunchKernelGGL((k_fft_strided_n<T, SIGN, N>), grid, dim3(kBlock), lds, s, in, out, tw, inner_count, tpo,
+                           outer_stride, elem_stride);
+      }))
+    return;
   const int sh = lines_per_tile_shift<T>(p.n);
   const int TL = 1 << sh;
   const int tpo = (inner_count + TL - 1) / TL;
@@ -421,11 +650,20 @@ void Fft3D<T>::release() {
 template <typename T>
 void Fft3D<T>::forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, int count, hipStream_t s) const {
   const int nlines = nx * ny;
-  const int P = pairs_per_block<T>(nz);
-  dim3 grid((nlines / 2 + P - 1) / P, count);
-  const size_t lds = fft_lds_bytes<T>((size_t)P * nz, plan[2]);
-  allow_lds((const void*)k_r2c_z<T>, lds);
-  hipLaunchKernelGGL((k_r2c_z<T>), grid, dim3(kBlock), lds, s, in, out, plan[2], tw[2], nlines, pz, P);
+  if (!with_static_length(nz, [&](auto nc) {
+        constexpr int N = decltype(nc)::value;
+        constexpr int P = static_pairs<T>(N);
+        dim3 grid((nlines / 2 + P - 1) / P, count);
+        const size_t lds = fft_lds_bytes<T>((size_t)P * N, plan[2]);
+        allow_lds((const void*)k_r2c_z_n<T, N>, lds);
+        hipLaunchKernelGGL((k_r2c_z_n<T, N>), grid, dim3(kBlock), lds, s, in, out, tw[2], nlines, pz);
+      })) {
+    const int P = pairs_per_block<T>(nz);
+    dim3 grid((nlines / 2 + P - 1) / P, count);
+    const size_t lds = fft_lds_bytes<T>((size_t)P * nz, plan[2]);
+    allow_lds((const void*)k_r2c_z<T>, lds);
+    hipLaunchKernelGGL((k_r2c_z<T>), grid, dim3(kBlock), lds, s, in, out, plan[2], tw[2], nlines, pz, P);
+  }
   Batch<const cplx<T>*> cin;
   for (int i = 0; i < count; ++i) cin.p[i] = out.p[i];
   strided_pass<T, -1>(cin, out, count, plan[1], tw[1], nx, nzh, (long long)ny * pz, pz, s);
@@ -441,11 +679,21 @@ void Fft3D<T>::inverse(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& s
   for (int i = 0; i < count; ++i) cs.p[i] = scratch.p[i];
   strided_pass<T, +1>(cs, scratch, count, plan[1], tw[1], nx, nzh, (long long)ny * pz, pz, s);
   const int nlines = nx * ny;
-  const int P = pairs_per_block<T>(nz);
-  dim3 grid((nlines / 2 + P - 1) / P, count);
-  const size_t lds = fft_lds_bytes<T>((size_t)P * nz, plan[2]);
-  allow_lds((const void*)k_c2r_z<T>, lds);
-  hipLaunchKernelGGL((k_c2r_z<T>), grid, dim3(kBlock), lds, s, cs, out, plan[2], tw[2], nlines, pz, P, sc_hi, sc_lo);
+  if (!with_static_length(nz, [&](auto nc) {
+        constexpr int N = decltype(nc)::value;
+        constexpr int P = static_pairs<T>(N);
+        dim3 grid((nlines / 2 + P - 1) / P, count);
+        const size_t lds = fft_lds_bytes<T>((size_t)P * N, plan[2]);
+        allow_lds((const void*)k_c2r_z_n<T, N>, lds);
+        hipLaunchKernelGGL((k_c2r_z_n<T, N>), grid, dim3(kBlock), lds, s, cs, out, tw[2], nlines, pz, sc_hi, sc_lo);
+      })) {
+    const int P = pairs_per_block<T>(nz);
+    dim3 grid((nlines / 2 + P - 1) / P, count);
+    const size_t lds = fft_lds_bytes<T>((size_t)P * nz, plan[2]);
+    allow_lds((const void*)k_c2r_z<T>, lds);
+    hipLaunchKernelGGL((k_c2r_z<T>), grid, dim3(kBlock), lds, s, cs, out, plan[2], tw[2], nlines, pz, P, sc_hi,
+                       sc_lo);
+  }
 }
 
 template struct Fft3D<float>;

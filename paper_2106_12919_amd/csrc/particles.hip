@@ -288,28 +288,74 @@ __device__ inline int wrap3(int x, int n) {
   return (x >= n) ? x - n : x;
 }
 
+// Byte offset of a grid element in the loads of load_field_box: 32-bit for float (at most
+// 1024^3 cells, so below 2^32 bytes), which lets each load add it to the array's base held in
+// scalar registers; 64-bit for double.
+template <typename T>
+struct BoxOffset {
+  using type = size_t;
+};
+template <>
+struct BoxOffset<float> {
+  using type = unsigned int;
+};
+static_assert((size_t)1024 * 1024 * 1024 * sizeof(float) - 1 <= 0xffffffffu, "float offsets must fit 32 bits");
+
 // Stages the six nodal components over the box of tile (t0x, t0y, t0z), in the
-// FieldSlots layout or (GATHER) the GatherBox one.  Each thread issues the loads of all its
-// nodes before storing any, so they are in flight together.
+// FieldSlots layout or (GATHER) the GatherBox one.  Thread t takes box elements
+// e = t + u * PIC_GATHER_BLOCK; their coordinates (lx, ly, lz) advance by the block size
+// written in base B (no division per node).  Boxes inside the grid (all but the tiles on
+// its faces) skip the periodic wrap.  Each thread issues the loads of all its nodes before
+// storing any, so they are in flight together.
 template <typename T, int ORDER, bool GATHER = false>
 __device__ inline void load_field_box(T* box, const Batch<const T*>& F, const GridGeom& g, int t0x, int t0y, int t0z) {
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
+  using Off = typename BoxOffset<T>::type;
+  constexpr int B = X::B;
   constexpr int FS = FieldSlots<T>::FS;
   constexpr int PER = (X::B3 + PIC_GATHER_BLOCK - 1) / PIC_GATHER_BLOCK;
+  constexpr int DX = PIC_GATHER_BLOCK / X::B2, DY = (PIC_GATHER_BLOCK / B) % B, DZ = PIC_GATHER_BLOCK % B;
   const int ox0 = t0x - 1 + S::BASE, oy0 = t0y - 1 + S::BASE, oz0 = t0z - 1 + S::BASE;
+  const bool inner = ox0 >= 0 && ox0 + B <= g.nx && oy0 >= 0 && oy0 + B <= g.ny && oz0 >= 0 && oz0 + B <= g.nz;
+  const int t = threadIdx.x;
+  int lx = t / X::B2, ly = (t / B) % B, lz = t % B;
   T v[PER][6];
+  if (inner) {
+    const int sxy = g.ny * g.nz;
+    const int base = (ox0 * g.ny + oy0) * g.nz + oz0;
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = min((int)threadIdx.x + u * PIC_GATHER_BLOCK, X::B3 - 1);
-    const int lx = e / X::B2, ly = (e / X::B) % X::B, lz = e % X::B;
-    const size_t gi = ((size_t)wrap3(ox0 + lx, g.nx) * g.ny + wrap3(oy0 + ly, g.ny)) * g.nz + wrap3(oz0 + lz, g.nz);
+    for (int u = 0; u < PER; ++u) {
+      if (u < PER - 1 || t + u * PIC_GATHER_BLOCK < X::B3) {
+        const Off off = (Off)(base + lx * sxy + ly * g.nz + lz) * (Off)sizeof(T);
 #pragma unroll
-    for (int c = 0; c < 6; ++c) v[u][c] = F.p[c][gi];
+        for (int c = 0; c < 6; ++c) v[u][c] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(F.p[c]) + off);
+      }
+      lz += DZ;
+      ly += DY + (lz >= B ? 1 : 0);
+      lz -= lz >= B ? B : 0;
+      lx += DX + (ly >= B ? 1 : 0);
+      ly -= ly >= B ? B : 0;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      if (u < PER - 1 || t + u * PIC_GATHER_BLOCK < X::B3) {
+        const Off off = (Off)((wrap3(ox0 + lx, g.nx) * g.ny + wrap3(oy0 + ly, g.ny)) * g.nz + wrap3(oz0 + lz, g.nz)) *
+                        (Off)sizeof(T);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[u][c] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(F.p[c]) + off);
+      }
+      lz += DZ;
+      ly += DY + (lz >= B ? 1 : 0);
+      lz -= lz >= B ? B : 0;
+      lx += DX + (ly >= B ? 1 : 0);
+      ly -= ly >= B ? B : 0;
+    }
   }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int e = (int)threadIdx.x + u * PIC_GATHER_BLOCK;
+    const int e = t + u * PIC_GATHER_BLOCK;
     if (e < X::B3) {
       if (GATHER) {
         GatherBox<T, X::B3>::store(box, e, v[u]);

@@ -1,5 +1,6 @@
 """Parity with the oracle on the paths the timed and full-size runs take that the stage tests on
-small grids do not reach: the 384- and 768-point FFT axes of the beam-driven-wake grid, one
+small grids do not reach: the 384- and 768-point FFT axes of the beam-driven-wake grid and every
+axis length with transform kernels of its own, one
 pic_step call of several steps (E, B resident in Fourier space) for the standard, Galilean and
 averaged Galilean cycles, grids of more tiles than the single-launch bucket scan and the LDS
 bucket histogram hold, the beam-driven wake at 1/4 scale (gamma = 1000 beam), and several
@@ -36,6 +37,32 @@ def test_field_solve_on_the_beam_grid_axes(dtype, shape):
     ctx = piclib.Context(shape, (1.0, 1.0, 1.0), dt, 1, 8, 16, dtype)
     f = piclib.Fields(shape, dtype)
     src = rounded(inputs.random_grid(shape, seed=111, count=11), dtype)
+    put(f.E_stag, src[0:3])
+    put(f.B_stag, src[3:6])
+    put(f.J_stag, src[6:9])
+    put([f.rho_old, f.rho_new], src[9:11])
+    piclib.psatd_push_fields(ctx.ctx, f)
+    piclib.pic_sync(ctx.ctx)
+    E_ref, B_ref = ostep.push_fields(src[0:3], src[3:6], src[6:9], src[9], src[10], p)
+    tol = fft_tol(dtype, shape)
+    for d in range(3):
+        eE, eB = max_rel(np64(f.E_stag[d]), E_ref[d]), max_rel(np64(f.B_stag[d]), B_ref[d])
+        assert eE <= tol and eB <= tol, (d, eE, eB, tol)
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape", [(64, 128, 256), (128, 64, 384), (256, 256, 64), (768, 12, 128), (8, 768, 24)])
+def test_field_solve_on_the_specialised_axis_lengths(dtype, shape):
+    """The transforms have kernels of their own for axes of 64, 128, 256, 384 and 768 points; these
+    shapes put each of those lengths on x, y and z at least once (with a z pass whose last block holds
+    fewer line pairs than the others: 128 x 64 lines in pairs of 5 at 384 points, FP32)."""
+    banner(f"psatd_push_fields on specialised axis lengths dtype={dtype} shape={shape}")
+    dt = 0.5
+    p = ostep.Params(shape, (1.0, 1.0, 1.0), dt, 1, 8, 16)
+    ctx = piclib.Context(shape, (1.0, 1.0, 1.0), dt, 1, 8, 16, dtype)
+    f = piclib.Fields(shape, dtype)
+    src = rounded(inputs.random_grid(shape, seed=112, count=11), dtype)
     put(f.E_stag, src[0:3])
     put(f.B_stag, src[3:6])
     put(f.J_stag, src[6:9])
