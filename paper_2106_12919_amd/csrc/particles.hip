@@ -1022,28 +1022,40 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
     __syncthreads();
     finish_bounds();
   }
-  for (int k = threadIdx.x; k < ncomp * X::B3; k += blockDim.x) box[k] = 0;
+  {  // clear the box: 16-byte stores, then the words past the last whole 16 bytes
+    constexpr int W = (int)(ncomp * X::B3 * sizeof(typename Fixed<T>::acc_t) / sizeof(int));
+    int4* b4 = reinterpret_cast<int4*>(box);
+#pragma unroll
+    for (int k0 = 0; k0 < W / 4; k0 += PIC_DEPOSIT_BLOCK)
+      if ((W / 4) % PIC_DEPOSIT_BLOCK == 0 || k0 + (int)threadIdx.x < W / 4) b4[k0 + threadIdx.x] = make_int4(0, 0, 0, 0);
+    if ((int)threadIdx.x < W % 4) reinterpret_cast<int*>(box)[W / 4 * 4 + threadIdx.x] = 0;
+  }
   if (threadIdx.x < 27) cnt[threadIdx.x] = 0;
   if (threadIdx.x == 0) L.cross = 0;  // read only after the chunk loop's barriers
   for (int cb = beg; cb < end; cb += O::CH) {
     const int nc = min(O::CH, end - cb);
     if (threadIdx.x < O::KG) hist[threadIdx.x] = 0;
     __syncthreads();
-    // pass 1: residue of each particle's first J (rho-only: rho) support node and its
-    // rank among the chunk's particles of that residue; all of a thread's particles in flight.
-    // When the bounds came from a pass of their own, the residue is taken from the particle's
-    // cell alone (one int per particle instead of its whole record): the first support node of
-    // the current shifts from it only when the half step crosses a cell face, and the deal only
-    // orders the atomics, it does not change their sums.
-    if (PIC_DEPOSIT_CELL_KEY && !single) {
+    // pass 1: residue of each particle's first support node and its rank among the chunk's
+    // particles of that residue; all of a thread's particles in flight.  The residue is taken
+    // from the particle's cell alone (rho's first node; one int per particle instead of its whole
+    // record, with momentum and weight for the bounds of a single-chunk tile): the first support
+    // node of the current shifts from it only when the half step crosses a cell face, and the
+    // deal only orders the atomics, it does not change their sums.  PIC_DEPOSIT_CELL_KEY 0 keys
+    // by the current's first node instead.
+    if (PIC_DEPOSIT_CELL_KEY) {
       const int e0 = threadIdx.x;
       int qi[O::U];
 #pragma unroll
       for (int u = 0; u < O::U; ++u) qi[u] = cb + min(e0 + u * PIC_DEPOSIT_BLOCK, nc - 1);
       through_perm(perm, qi);
       int c[O::U];
+      Raw<T> r[O::U];
 #pragma unroll
-      for (int u = 0; u < O::U; ++u) c[u] = sp.cell[qi[u]];
+      for (int u = 0; u < O::U; ++u) {
+        c[u] = sp.cell[qi[u]];
+        if (single) load_bound<T, WJ>(sp, qi[u], r[u]);
+      }
 #pragma unroll
       for (int u = 0; u < O::U; ++u) {
         const int e = e0 + u * PIC_DEPOSIT_BLOCK;
@@ -1055,6 +1067,7 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
           }
           const int rk = atomicAdd(&hist[key], 1);
           kr[e] = (unsigned short)(rk * O::KG + key);
+          if (single) bound_add<T, WJ>(r[u], sw, mw);
         }
       }
     } else {
@@ -1206,21 +1219,38 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
   const int lo[3] = {(faces & 1) ? 0 : 1, (faces & 2) ? 0 : 1, (faces & 4) ? 0 : 1};
   const int hi[3] = {(faces & 8) ? X::B - 1 : X::B - 2, (faces & 16) ? X::B - 1 : X::B - 2,
                      (faces & 32) ? X::B - 1 : X::B - 2};
-  T* dstage = stage + (size_t)tile * ncomp * X::B3;
-  for (int n = threadIdx.x; n < X::B3; n += blockDim.x) {
-    const int lx = n / X::B2, ly = (n / X::B) % X::B, lz = n % X::B;
-    if (lx < lo[0] || lx > hi[0] || ly < lo[1] || ly > hi[1] || lz < lo[2] || lz > hi[2]) continue;
-    dstage[n] = ldexp((T)rbox[n], -shs[0]);
-    if constexpr (PACK) {
-      int jx, jy;
-      unpack_xy(reinterpret_cast<const unsigned long long*>(box)[n], jx, jy);
-      dstage[X::B3 + n] = ldexp((T)jx, -shs[1]);
-      dstage[2 * X::B3 + n] = ldexp((T)jy, -shs[2]);
-      dstage[3 * X::B3 + n] = ldexp((T)box[2 * X::B3 + n], -shs[3]);
-    } else if (WJ) {
-#pragma unroll
-      for (int q = 1; q < 4; ++q) dstage[q * X::B3 + n] = ldexp((T)box[q * X::B3 + n], -shs[q]);
+  // node n = t + u * PIC_DEPOSIT_BLOCK of thread t; its box coordinates advance by the block
+  // size written in base B, and each component plane of the tile's slot is a base of its own
+  T* const dstage = stage + (size_t)tile * ncomp * X::B3;
+  T* const plane[4] = {dstage, dstage + X::B3, dstage + 2 * X::B3, dstage + 3 * X::B3};
+  constexpr int SPER = (X::B3 + PIC_DEPOSIT_BLOCK - 1) / PIC_DEPOSIT_BLOCK;
+  constexpr int DX = PIC_DEPOSIT_BLOCK / X::B2, DY = (PIC_DEPOSIT_BLOCK / X::B) % X::B;
+  constexpr int DZ = PIC_DEPOSIT_BLOCK % X::B;
+  const int sh0 = -shs[0], sh1 = -shs[1], sh2 = -shs[2], sh3 = -shs[3];
+  int lx = (int)threadIdx.x / X::B2, ly = ((int)threadIdx.x / X::B) % X::B, lz = (int)threadIdx.x % X::B;
+#pragma unroll 1
+  for (int u = 0; u < SPER; ++u) {
+    const unsigned n = threadIdx.x + u * PIC_DEPOSIT_BLOCK;
+    if (n < (unsigned)X::B3 && lx >= lo[0] && lx <= hi[0] && ly >= lo[1] && ly <= hi[1] && lz >= lo[2] &&
+        lz <= hi[2]) {
+      plane[0][n] = ldexp((T)rbox[n], sh0);
+      if constexpr (PACK) {
+        int jx, jy;
+        unpack_xy(reinterpret_cast<const unsigned long long*>(box)[n], jx, jy);
+        plane[1][n] = ldexp((T)jx, sh1);
+        plane[2][n] = ldexp((T)jy, sh2);
+        plane[3][n] = ldexp((T)box[2 * X::B3 + n], sh3);
+      } else if (WJ) {
+        plane[1][n] = ldexp((T)box[X::B3 + n], sh1);
+        plane[2][n] = ldexp((T)box[2 * X::B3 + n], sh2);
+        plane[3][n] = ldexp((T)box[3 * X::B3 + n], sh3);
+      }
     }
+    lz += DZ;
+    ly += DY + (lz >= X::B ? 1 : 0);
+    lz -= lz >= X::B ? X::B : 0;
+    lx += DX + (ly >= X::B ? 1 : 0);
+    ly -= ly >= X::B ? X::B : 0;
   }
 }
 
