@@ -178,6 +178,55 @@ __device__ inline cplx<T>* fft_lds_static(cplx<T>* a, cplx<T>* b, const cplx<T>*
   }
 }
 
+// The same stages in one LDS buffer: every thread first takes the inputs of all its butterflies
+// of a stage into registers, and writes the outputs after the block's barrier.  Half the LDS of
+// the two-buffer form for the same tile, at one more barrier per stage.
+template <typename T, int SIGN, int N, int NL, bool LINE_FASTEST, int S = 0>
+__device__ inline void fft_lds_static_inplace(cplx<T>* a, const cplx<T>* __restrict__ tw) {
+  constexpr FftPlan P = plan_of(N);
+  if constexpr (S < P.nstages) {
+    constexpr int R = P.radix[S], NS = P.ns[S], NB = N / R, TOTAL = NL * NB;
+    constexpr int LS = LINE_FASTEST ? 1 : N, JS = LINE_FASTEST ? NL : 1;
+    constexpr int IT = (TOTAL + kBlock - 1) / kBlock;
+    const cplx<T>* tws = tw + P.twoff[S];
+    cplx<T> v[IT][R];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int w = it * kBlock + (int)threadIdx.x;
+      if (TOTAL % kBlock == 0 || w < TOTAL) {
+        const int l = LINE_FASTEST ? w % NL : w / NB;
+        const int bi = LINE_FASTEST ? w / NL : w % NB;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[it][r] = a[l * LS + (bi + r * NB) * JS];
+        if (NS > 1) {
+          const int k = bi % NS;
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            cplx<T> t = tws[k * (R - 1) + r - 1];
+            if (SIGN > 0) t.y = -t.y;
+            v[it][r] = cmul(v[it][r], t);
+          }
+        }
+        dft<T, SIGN, R>(v[it]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int w = it * kBlock + (int)threadIdx.x;
+      if (TOTAL % kBlock == 0 || w < TOTAL) {
+        const int l = LINE_FASTEST ? w % NL : w / NB;
+        const int bi = LINE_FASTEST ? w / NL : w % NB;
+        const int j0 = (bi / NS) * NS * R + bi % NS;
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[l * LS + (j0 + r * NS) * JS] = v[it][r];
+      }
+    }
+    __syncthreads();
+    fft_lds_static_inplace<T, SIGN, N, NL, LINE_FASTEST, S + 1>(a, tw);
+  }
+}
+
 // Largest element count per thread of one block's LDS tile (two buffers of kLdsBudget
 // bytes in all): every thread issues all its global loads (those inside the tile) before it
 // stores any to LDS.
@@ -366,10 +415,16 @@ constexpr int static_pairs(int n) {
   while (P > 1 && (2 * (size_t)P * n + n) * sizeof(cplx<T>) > kLdsBudget) P /= 2;
   return P;
 }
+#ifndef PIC_FFT_INPLACE
+#define PIC_FFT_INPLACE 1
+#endif
+// Tile buffers of the strided kernels for compile-time lengths: two (stages from one buffer to
+// the other) or one (PIC_FFT_INPLACE: stages in place).
+constexpr int kStaticBuffers = PIC_FFT_INPLACE ? 1 : 2;
 template <typename T>
-constexpr int static_lines(int n) {
+constexpr int static_lines(int n, int buffers = 2) {
   int sh = PIC_FFT_MAX_TL_SHIFT;
-  while (sh > 0 && (2 * ((size_t)1 << sh) * n + n) * sizeof(cplx<T>) > kLdsBudget) --sh;
+  while (sh > 0 && (buffers * ((size_t)1 << sh) * n + n) * sizeof(cplx<T>) > kLdsBudget) --sh;
   return 1 << sh;
 }
 
@@ -488,7 +543,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_strided_n(Batch<const cplx<T>*> 
                                                           const cplx<T>* __restrict__ tw, int inner_count,
                                                           int tiles_per_outer, long long outer_stride,
                                                           long long elem_stride) {
-  constexpr int TL = static_lines<T>(N);
+  constexpr int TL = static_lines<T>(N, kStaticBuffers);
   static_assert(kBlock % TL == 0, "a block covers whole rows of the tile");
   constexpr int TW = plan_of(N).twcount;
   constexpr int TOTAL = N * TL;
@@ -496,7 +551,7 @@ __global__ void __launch_bounds__(kBlock) k_fft_strided_n(Batch<const cplx<T>*> 
   constexpr int ROWS = kBlock / TL;  // rows advanced per u
   extern __shared__ __align__(16) unsigned char smem[];
   cplx<T>* a = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* b = a + (size_t)TL * N;
+  cplx<T>* b = a + (size_t)TL * N;  // second buffer (two-buffer stages) or the twiddles
   const int tile = PIC_FFT_XCD ? xcd_major(blockIdx.x, gridDim.x) : blockIdx.x;
   const int outer = tile / tiles_per_outer;
   const int inner0 = (tile - outer * tiles_per_outer) * TL;
@@ -509,14 +564,18 @@ __global__ void __launch_bounds__(kBlock) k_fft_strided_n(Batch<const cplx<T>*> 
 #pragma unroll
   for (int u = 0; u < PER; ++u)
     if (TOTAL % kBlock == 0 || (int)threadIdx.x + u * kBlock < TOTAL) v[u] = src[u * step];
-  const cplx<T>* twl = stage_twiddles(b + (size_t)TL * N, tw, TW);
+  const cplx<T>* twl = stage_twiddles(PIC_FFT_INPLACE ? b : b + (size_t)TL * N, tw, TW);
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = (int)threadIdx.x + u * kBlock;
     if (TOTAL % kBlock == 0 || e < TOTAL) a[e] = i < nl ? v[u] : cmake((T)0, (T)0);
   }
   __syncthreads();
-  cplx<T>* res = fft_lds_static<T, SIGN, N, TL, true>(a, b, twl);
+  cplx<T>* res = a;
+  if constexpr (PIC_FFT_INPLACE)
+    fft_lds_static_inplace<T, SIGN, N, TL, true>(a, twl);
+  else
+    res = fft_lds_static<T, SIGN, N, TL, true>(a, b, twl);
   if (i < nl) {
     cplx<T>* __restrict__ dst = out.p[blockIdx.y] + row0;
 #pragma unroll
@@ -570,10 +629,11 @@ void strided_pass(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& out, i
                   hipStream_t s) {
   if (with_static_length(p.n, [&](auto nc) {
         constexpr int N = decltype(nc)::value;
-        constexpr int TL = static_lines<T>(N);
+        constexpr int TL = static_lines<T>(N, kStaticBuffers);
         const int tpo = (inner_count + TL - 1) / TL;
         dim3 grid(outer_count * tpo, count);
-        const size_t lds = fft_lds_bytes<T>((size_t)TL * N, p);
+        const size_t lds = (kStaticBuffers * (size_t)TL * N + (size_t)(p.twcount > 0 ? p.twcount : 1)) *
+                           sizeof(cplx<T>);
         allow_lds((const void*)k_fft_strided_n<T, SIGN, N>, lds);
         hipLaunchKernelGGL((k_fft_strided_n<T, SIGN, N>), grid, dim3(kBlock), lds, s, in, out, tw, inner_count, tpo,
                            outer_stride, elem_stride);
