@@ -16,6 +16,16 @@
 #ifndef PIC_GATHER_BLOCK
 #define PIC_GATHER_BLOCK 512
 #endif
+// Workgroup of the production gather + push: FP32 cubic boxes (53 KB of LDS, a few hundred
+// particles per tile at the densities of the beam-driven wake) run three 256-thread
+// workgroups per CU, whose box loads and particle work then overlap; every other case runs
+// 512 threads (a double cubic box admits one workgroup per CU, linear tiles hold many more
+// particles per box).
+#ifndef PIC_GATHER_BLOCK_F32_CUBIC
+#define PIC_GATHER_BLOCK_F32_CUBIC 256
+#endif
+template <typename T, int ORDER>
+constexpr int kGatherBlock = (sizeof(T) == 4 && ORDER == 3) ? PIC_GATHER_BLOCK_F32_CUBIC : PIC_GATHER_BLOCK;
 #ifndef PIC_DEPOSIT_BLOCK
 #define PIC_DEPOSIT_BLOCK 256
 #endif
@@ -303,19 +313,19 @@ static_assert((size_t)1024 * 1024 * 1024 * sizeof(float) - 1 <= 0xffffffffu, "fl
 
 // Stages the six nodal components over the box of tile (t0x, t0y, t0z), in the
 // FieldSlots layout or (GATHER) the GatherBox one.  Thread t takes box elements
-// e = t + u * PIC_GATHER_BLOCK; their coordinates (lx, ly, lz) advance by the block size
+// e = t + u * BLOCK; their coordinates (lx, ly, lz) advance by the block size
 // written in base B (no division per node).  Boxes inside the grid (all but the tiles on
 // its faces) skip the periodic wrap.  Each thread issues the loads of all its nodes before
 // storing any, so they are in flight together.
-template <typename T, int ORDER, bool GATHER = false>
+template <typename T, int ORDER, bool GATHER = false, int BLOCK = PIC_GATHER_BLOCK>
 __device__ inline void load_field_box(T* box, const Batch<const T*>& F, const GridGeom& g, int t0x, int t0y, int t0z) {
   using S = Shape<T, ORDER>;
   using X = Box<S::NW>;
   using Off = typename BoxOffset<T>::type;
   constexpr int B = X::B;
   constexpr int FS = FieldSlots<T>::FS;
-  constexpr int PER = (X::B3 + PIC_GATHER_BLOCK - 1) / PIC_GATHER_BLOCK;
-  constexpr int DX = PIC_GATHER_BLOCK / X::B2, DY = (PIC_GATHER_BLOCK / B) % B, DZ = PIC_GATHER_BLOCK % B;
+  constexpr int PER = (X::B3 + BLOCK - 1) / BLOCK;
+  constexpr int DX = BLOCK / X::B2, DY = (BLOCK / B) % B, DZ = BLOCK % B;
   const int ox0 = t0x - 1 + S::BASE, oy0 = t0y - 1 + S::BASE, oz0 = t0z - 1 + S::BASE;
   const bool inner = ox0 >= 0 && ox0 + B <= g.nx && oy0 >= 0 && oy0 + B <= g.ny && oz0 >= 0 && oz0 + B <= g.nz;
   const int t = threadIdx.x;
@@ -326,7 +336,7 @@ __device__ inline void load_field_box(T* box, const Batch<const T*>& F, const Gr
     const int base = (ox0 * g.ny + oy0) * g.nz + oz0;
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      if (u < PER - 1 || t + u * PIC_GATHER_BLOCK < X::B3) {
+      if (u < PER - 1 || t + u * BLOCK < X::B3) {
         const Off off = (Off)(base + lx * sxy + ly * g.nz + lz) * (Off)sizeof(T);
 #pragma unroll
         for (int c = 0; c < 6; ++c) v[u][c] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(F.p[c]) + off);
@@ -340,7 +350,7 @@ __device__ inline void load_field_box(T* box, const Batch<const T*>& F, const Gr
   } else {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
-      if (u < PER - 1 || t + u * PIC_GATHER_BLOCK < X::B3) {
+      if (u < PER - 1 || t + u * BLOCK < X::B3) {
         const Off off = (Off)((wrap3(ox0 + lx, g.nx) * g.ny + wrap3(oy0 + ly, g.ny)) * g.nz + wrap3(oz0 + lz, g.nz)) *
                         (Off)sizeof(T);
 #pragma unroll
@@ -355,7 +365,7 @@ __device__ inline void load_field_box(T* box, const Batch<const T*>& F, const Gr
   }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
-    const int e = t + u * PIC_GATHER_BLOCK;
+    const int e = t + u * BLOCK;
     if (e < X::B3) {
       if (GATHER) {
         GatherBox<T, X::B3>::store(box, e, v[u]);
@@ -466,7 +476,7 @@ __device__ inline void copy_particle(const SpeciesView<T>& in, long long p, cons
 // of ``in`` and writes it to slot q (write_sorted) or back to perm[q] of ``out``.
 // Block ntiles carries particles with invalid cells along.
 template <typename T, int ORDER>
-__global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_perm(GridGeom g, TileGeom tg, Batch<const T*> F,
+__global__ void __launch_bounds__((kGatherBlock<T, ORDER>)) k_gather_push_perm(GridGeom g, TileGeom tg, Batch<const T*> F,
                                                                        SpeciesView<T> in, SpeciesView<T> out,
                                                                        const int* __restrict__ perm,
                                                                        const int* __restrict__ starts, int write_sorted,
@@ -486,7 +496,7 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_perm(GridGeom 
   int tx, ty, tz;
   tile_coords(tile, tg, tx, ty, tz);
   const int t0x = tx * kTile, t0y = ty * kTile, t0z = tz * kTile;
-  load_field_box<T, ORDER, true>(box, F, g, t0x, t0y, t0z);
+  load_field_box<T, ORDER, true, kGatherBlock<T, ORDER>>(box, F, g, t0x, t0y, t0z);
   __syncthreads();
   for (int qq = beg + threadIdx.x; qq < end; qq += blockDim.x) {
     const int p = perm[qq];
@@ -518,7 +528,7 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_perm(GridGeom 
 // deposition took), then gathers, pushes and writes each particle to base + its
 // rank from a second LDS count.  Block ntiles carries invalid cells to the last bucket.
 template <typename T, int ORDER>
-__global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom g, TileGeom tg, Batch<const T*> F,
+__global__ void __launch_bounds__((kGatherBlock<T, ORDER>)) k_gather_push_home(GridGeom g, TileGeom tg, Batch<const T*> F,
                                                                        SpeciesView<T> in, SpeciesView<T> out,
                                                                        const int* __restrict__ home, int* cursor,
                                                                        const int* __restrict__ nbr_bases, T qdt2m,
@@ -543,7 +553,7 @@ __global__ void __launch_bounds__(PIC_GATHER_BLOCK) k_gather_push_home(GridGeom 
     cnt[threadIdx.x] = 0;
     if (nbr_bases) base[threadIdx.x] = nbr_bases[27 * tile + threadIdx.x];
   }
-  load_field_box<T, ORDER, true>(box, F, g, t0x, t0y, t0z);
+  load_field_box<T, ORDER, true, kGatherBlock<T, ORDER>>(box, F, g, t0x, t0y, t0z);
   __syncthreads();
   if (!nbr_bases) {
     // pass 1: particles per neighbour tile of the new grouping (the home tile, the
@@ -2253,7 +2263,8 @@ void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3]
   const T dtx = (T)(g.dt / g.dx), dty = (T)(g.dt / g.dy), dtz = (T)(g.dt / g.dz);
   const int Bx = deposit_box(g.shape_order);
   const size_t lds = (size_t)Bx * Bx * Bx * GatherBox<T, 1>::SLOTS * sizeof(T);
-  const dim3 grid(t.ntiles + 1), block(PIC_GATHER_BLOCK);
+  const dim3 grid(t.ntiles + 1);
+  const dim3 block(g.shape_order == 1 ? kGatherBlock<T, 1> : kGatherBlock<T, 3>);
   if (home_cursor) {
     if (g.shape_order == 1) {
       allow_lds((const void*)k_gather_push_home<T, 1>, lds);
