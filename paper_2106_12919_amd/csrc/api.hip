@@ -172,7 +172,7 @@ struct Engine : EngineBase {
   int* t_starts = nullptr;  // ntiles + 2
   int* t_cursor = nullptr;  // ntiles + 1
   int* work = nullptr;      // tile counter of the persistent deposition
-  T* stage = nullptr;       // per-tile deposition boxes, ntiles * 4 * deposit_box^3
+  T* stage = nullptr;       // per-tile deposition boxes, ntiles * 4 * deposit_stage_slot
   T* astage = nullptr;      // per-tile boxes of the reverse mode's scatter, ntiles * 6 * deposit_box^3 (on first use)
   // rho, J of particles past their tile's box (zero between depositions), the two flags that
   // say whether a deposition spilled, and the count of depositions that chose between them
@@ -397,8 +397,10 @@ hipError_t build_engine(const pic_params& p, Engine<T>& e) {
   if ((err = e.alloc(&e.t_starts, (size_t)e.tiles.ntiles + 2)) != hipSuccess) return err;
   if ((err = e.alloc(&e.t_cursor, (size_t)e.tiles.ntiles + 1)) != hipSuccess) return err;
   if ((err = e.alloc(&e.work, 1)) != hipSuccess) return err;
-  const size_t B = (size_t)deposit_box(p.shape_order);
-  if ((err = e.alloc(&e.stage, (size_t)e.tiles.ntiles * 4 * B * B * B)) != hipSuccess) return err;
+  // the row layout of deposit_tiled (B x B x 16 per component) holds the node-major boxes
+  // (B^3) of the staggered cycle's deposition too
+  const size_t slot = (size_t)deposit_stage_slot(p.shape_order);
+  if ((err = e.alloc(&e.stage, (size_t)e.tiles.ntiles * 4 * slot)) != hipSuccess) return err;
   return hipSuccess;
 }
 
@@ -605,6 +607,7 @@ struct SourceSum {
     ra.base = rho_done ? nullptr : static_cast<const T*>(f->rho_static);
     for (int q = 0; q < 4; ++q) ra.spill[q] = e.spill[q];
     ra.box_faces = e.box_faces;
+    ra.rows = 1;  // deposit_tiled's staging layout
     ra.flag = flag;
     ra.next_flag = e.spill_flag + ((e.dep_k + 1u) & 1u);
     ++e.dep_k;

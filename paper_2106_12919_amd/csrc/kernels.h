@@ -141,6 +141,12 @@ TileGeom make_tiles(const GridGeom& g);  // tiles of kTile^3 cells
 // Edge length (nodes) of the LDS boxes of one tile: the tile, the shape support and a
 // one-cell margin on each side (particles move less than one cell per step).
 int deposit_box(int shape_order);
+// Elements per component of a tile's slot in the staging buffer of deposit_tiled: B x B rows
+// (B = deposit_box) of 16 values, row (lx, ly) holding box nodes lz = 0 .. B-1 at positions
+// lz + ((BASE + 3) mod 4) (BASE = -1 cubic, 0 linear) and zeros elsewhere.  The offset puts grid
+// nodes z = 4g .. 4g+3 at positions 4h .. 4h+3 of every box that covers them, so that the
+// reduction reads four nodes of a box as one aligned vector.
+int deposit_stage_slot(int shape_order);
 // Counting sort by tile of the particles' current cells: counts[ntiles+1],
 // starts[ntiles+2], cursor[ntiles+1] (scratch), dst[n] = each particle's slot in
 // tile order (tiles in order, then particles with invalid cells, counted in *bad).
@@ -174,9 +180,9 @@ void permute_species(const SpeciesView<T>& in, const SpeciesView<T>& out, const 
 // Deposition of one species in two launches.  deposit_tiled accumulates rho (at the
 // particles' positions) and, when with_j, J (at x - dt v/2) tile by tile (tile t owns
 // sorted slots [starts[t], starts[t+1]); slot q holds particle perm[q], perm == nullptr:
-// q) into per-tile boxes in ``stage`` (ntiles * (with_j ? 4 : 1) * deposit_box^3
-// elements); particles that left the one-cell margin go straight to rho/J.
-// deposit_reduce then sums the overlapping boxes into the nodal arrays.
+// q) into per-tile boxes in ``stage`` (ntiles * (with_j ? 4 : 1) * deposit_stage_slot
+// elements, row layout); particles that left the one-cell margin go straight to rho/J.
+// deposit_reduce with ReduceArgs::rows = 1 then sums the overlapping boxes into the nodal arrays.
 // With next_counts != nullptr, the particles are also counted per tile of their cells
 // (the grouping of the next step), into next_counts[ntiles + 1] (invalid cells last),
 // and, when nbr_counts != nullptr, per tile t of this grouping and neighbour nb of t
@@ -203,6 +209,9 @@ struct ReduceArgs {
   const int* flag = nullptr;
   int* next_flag = nullptr;
   const int* box_faces = nullptr;  // per tile, the outer faces its deposition staged (null: all)
+  // Staging layout: 0 = node-major boxes (B^3 per component); 1 = the zero-padded rows that
+  // deposit_tiled writes (deposit_stage_slot elements per component).
+  int rows = 0;
   __device__ T start(int q, const T* o, size_t idx) const {
     if (acc_mask & (q == 0 ? 1 : 2)) return o[idx];
     return (q == 0 && base) ? base[idx] : (T)0;

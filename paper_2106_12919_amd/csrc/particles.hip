@@ -182,6 +182,36 @@ struct Box {
   __device__ static inline int at(int lx, int ly, int lz) { return (lx * B + ly) * B + lz; }
 };
 
+// Row layout of a tile's staging slot (see deposit_stage_slot): per component B x B rows of
+// PZ values, box node (lx, ly, lz) at (lx * B + ly) * PZ + OFF + lz, zeros in the other positions.
+template <int ORDER>
+struct StageRows {
+  static constexpr int B = kTile + (ORDER == 1 ? 2 : 4) + 1;
+  static constexpr int BASE = ORDER == 1 ? 0 : -1;
+  static constexpr int PZ = 16;
+  static constexpr int OFF = (BASE + 3) & 3;
+  static constexpr int SLOT = B * B * PZ;
+  static_assert(OFF + B <= PZ, "a box row fits its padded row");
+  __device__ static inline int at(int lx, int ly, int lz) { return (lx * B + ly) * PZ + OFF + lz; }
+};
+
+// Four consecutive values as one 16-byte (float) or two 16-byte (double) accesses.
+__device__ inline void store4(float* p, const float* v) {
+  *reinterpret_cast<float4*>(p) = make_float4(v[0], v[1], v[2], v[3]);
+}
+__device__ inline void store4(double* p, const double* v) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(v[0], v[1]);
+  reinterpret_cast<double2*>(p)[1] = make_double2(v[2], v[3]);
+}
+__device__ inline void load4(const float* p, float* v) {
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+__device__ inline void load4(const double* p, double* v) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0], b = reinterpret_cast<const double2*>(p)[1];
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+}
+
 // One particle as stored: cell, offsets, momentum (when WJ) and weight.  Loaded in one
 // go, so that the loads of several particles are in flight together.
 template <typename T>
@@ -1229,38 +1259,38 @@ __device__ inline void deposit_tile(int tile, const GridGeom& g, const TileGeom&
   const int lo[3] = {(faces & 1) ? 0 : 1, (faces & 2) ? 0 : 1, (faces & 4) ? 0 : 1};
   const int hi[3] = {(faces & 8) ? X::B - 1 : X::B - 2, (faces & 16) ? X::B - 1 : X::B - 2,
                      (faces & 32) ? X::B - 1 : X::B - 2};
-  // node n = t + u * PIC_DEPOSIT_BLOCK of thread t; its box coordinates advance by the block
-  // size written in base B, and each component plane of the tile's slot is a base of its own
-  T* const dstage = stage + (size_t)tile * ncomp * X::B3;
-  T* const plane[4] = {dstage, dstage + X::B3, dstage + 2 * X::B3, dstage + 3 * X::B3};
-  constexpr int SPER = (X::B3 + PIC_DEPOSIT_BLOCK - 1) / PIC_DEPOSIT_BLOCK;
-  constexpr int DX = PIC_DEPOSIT_BLOCK / X::B2, DY = (PIC_DEPOSIT_BLOCK / X::B) % X::B;
-  constexpr int DZ = PIC_DEPOSIT_BLOCK % X::B;
+  // the tile's slot in rows (StageRows): thread t writes vectors it = t + u * PIC_DEPOSIT_BLOCK,
+  // four consecutive positions of row it / 4, every component, zeros outside the box row
+  using RL = StageRows<ORDER>;
+  static_assert(RL::B == X::B, "stage rows match the box");
+  T* const dstage = stage + (size_t)tile * ncomp * RL::SLOT;
   const int sh0 = -shs[0], sh1 = -shs[1], sh2 = -shs[2], sh3 = -shs[3];
-  int lx = (int)threadIdx.x / X::B2, ly = ((int)threadIdx.x / X::B) % X::B, lz = (int)threadIdx.x % X::B;
-#pragma unroll 1
-  for (int u = 0; u < SPER; ++u) {
-    const unsigned n = threadIdx.x + u * PIC_DEPOSIT_BLOCK;
-    if (n < (unsigned)X::B3 && lx >= lo[0] && lx <= hi[0] && ly >= lo[1] && ly <= hi[1] && lz >= lo[2] &&
-        lz <= hi[2]) {
-      plane[0][n] = ldexp((T)rbox[n], sh0);
+  for (int it = threadIdx.x; it < X::B2 * (RL::PZ / 4); it += blockDim.x) {
+    const int r = it >> 2, p0 = (it & 3) * 4;
+    const int lx = r / X::B, ly = r - lx * X::B;
+    if (lx < lo[0] || lx > hi[0] || ly < lo[1] || ly > hi[1]) continue;
+    T v[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int lz = p0 + i - RL::OFF;
+      const bool in = lz >= 0 && lz < X::B;
+      const int n = r * X::B + (in ? lz : 0);
+      v[0][i] = in ? ldexp((T)rbox[n], sh0) : (T)0;
       if constexpr (PACK) {
         int jx, jy;
         unpack_xy(reinterpret_cast<const unsigned long long*>(box)[n], jx, jy);
-        plane[1][n] = ldexp((T)jx, sh1);
-        plane[2][n] = ldexp((T)jy, sh2);
-        plane[3][n] = ldexp((T)box[2 * X::B3 + n], sh3);
+        v[1][i] = in ? ldexp((T)jx, sh1) : (T)0;
+        v[2][i] = in ? ldexp((T)jy, sh2) : (T)0;
+        v[3][i] = in ? ldexp((T)box[2 * X::B3 + n], sh3) : (T)0;
       } else if (WJ) {
-        plane[1][n] = ldexp((T)box[X::B3 + n], sh1);
-        plane[2][n] = ldexp((T)box[2 * X::B3 + n], sh2);
-        plane[3][n] = ldexp((T)box[3 * X::B3 + n], sh3);
+        v[1][i] = in ? ldexp((T)box[X::B3 + n], sh1) : (T)0;
+        v[2][i] = in ? ldexp((T)box[2 * X::B3 + n], sh2) : (T)0;
+        v[3][i] = in ? ldexp((T)box[3 * X::B3 + n], sh3) : (T)0;
       }
     }
-    lz += DZ;
-    ly += DY + (lz >= X::B ? 1 : 0);
-    lz -= lz >= X::B ? X::B : 0;
-    lx += DX + (ly >= X::B ? 1 : 0);
-    ly -= ly >= X::B ? X::B : 0;
+    T* const row = dstage + r * RL::PZ + p0;
+#pragma unroll
+    for (int q = 0; q < ncomp; ++q) store4(row + q * RL::SLOT, v[q]);
   }
 }
 
@@ -1396,6 +1426,93 @@ __global__ void __launch_bounds__(256) k_deposit_reduce_whole(GridGeom g, TileGe
   for (int q = 0; q < NCOMP; ++q) out.p[q][idx] = acc[q];
 }
 
+// The same sums over the row layout of deposit_tiled: each thread owns four consecutive nodes
+// z0 .. z0+3 (z0 a multiple of 4) of one grid row and reads each covering box's four values
+// as one aligned vector (zeros where the box ends inside the group).  Along z the group lies in
+// tile tz = z0 / kTile and in the box of tz - 1 (first half of the tile) or of tz + 1 (second
+// half); along x and y the candidates are those of the node.  Grid (z blocks, ny, nx),
+// XCD-major.
+template <typename T, int ORDER, int NCOMP>
+__global__ void __launch_bounds__(256) k_deposit_reduce_rows(GridGeom g, TileGeom tg, const int* __restrict__ starts,
+                                                             const T* __restrict__ stage, Batch<T*> out,
+                                                             ReduceArgs<T> ra) {
+  using RL = StageRows<ORDER>;
+  static_assert(kTile == 8, "two groups of four nodes per tile along z");
+  __shared__ unsigned char occ[4][kMaxTilesZ];
+  if (ra.next_flag && blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *ra.next_flag = 0;
+  const int nzb = gridDim.x;
+  const int L = xcd_major(blockIdx.x + nzb * (blockIdx.y + gridDim.y * blockIdx.z), nzb * gridDim.y * gridDim.z);
+  const int z0 = 4 * ((L % nzb) * blockDim.x + threadIdx.x);
+  const int y = (L / nzb) % g.ny, x = L / (nzb * g.ny);
+  int tx[2], lx[2], ty[2], ly[2];
+  const int nxc = axis_candidates<ORDER>(x, tg.ntx, tx, lx);
+  const int nyc = axis_candidates<ORDER>(y, tg.nty, ty, ly);
+  for (int e = threadIdx.x; e < 4 * tg.ntz; e += blockDim.x) {
+    const int ab = e / tg.ntz, t3 = e - ab * tg.ntz;
+    const int a = ab >> 1, b = ab & 1;
+    if (a < nxc && b < nyc) {
+      const int tile = (tx[a] * tg.nty + ty[b]) * tg.ntz + t3;
+      occ[ab][t3] = starts[tile] != starts[tile + 1] ? (unsigned char)(1 + 2 * (ra.box_faces ? ra.box_faces[tile] : 0x3F))
+                                                     : (unsigned char)0;
+    }
+  }
+  __syncthreads();
+  if (z0 >= g.nz) return;
+  const int tzc = z0 / kTile, dz = z0 - tzc * kTile;  // dz = 0 or 4
+  // the two z candidates (tile, position of z0 in its rows): c = tzc - 1, tzc or tzc, tzc + 1
+  int tz[2], pz[2];
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int c = (dz == 0 ? -1 : 0) + k;  // candidate tile offset from tzc
+    tz[k] = tzc + c < 0 ? tg.ntz - 1 : (tzc + c >= tg.ntz ? 0 : tzc + c);
+    pz[k] = dz - c * kTile + 1 - RL::BASE + RL::OFF;  // lz of z0 in that box, plus the row offset
+  }
+  const size_t idx = ((size_t)x * g.ny + y) * g.nz + z0;
+  bool use[8];
+  const T* sb[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int a = m >> 2, b = (m >> 1) & 1, c = m & 1;
+    const bool present = a < nxc && b < nyc;
+    const int ia = present ? a : 0, ib = present ? b : 0;
+    const int tile = (tx[ia] * tg.nty + ty[ib]) * tg.ntz + tz[c];
+    const int o = occ[2 * ia + ib][tz[c]];
+    const int f = o >> 1;  // staged x, y layers: 1 .. B - 2, plus the faces in f (z rows whole)
+    const bool in = (lx[ia] > 0 || (f & 1)) && (lx[ia] < RL::B - 1 || (f & 8)) && (ly[ib] > 0 || (f & 2)) &&
+                    (ly[ib] < RL::B - 1 || (f & 16));
+    use[m] = present && (o & 1) && in;
+    sb[m] = stage + (size_t)tile * NCOMP * RL::SLOT + (lx[ia] * RL::B + ly[ib]) * RL::PZ + pz[c];
+  }
+  const bool spilled = ra.flag && *ra.flag;
+  // one component at a time (its eight vectors in flight together); the empty asm keeps the
+  // compiler from hoisting the next component's loads, which would multiply the registers held
+#pragma unroll
+  for (int q = 0; q < NCOMP; ++q) {
+    T acc[4], v[8][4];
+    if (ra.acc_mask & (q == 0 ? 1 : 2)) load4(out.p[q] + idx, acc);
+    else if (q == 0 && ra.base) load4(ra.base + idx, acc);
+    else
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] = (T)0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      if (use[m]) load4(sb[m] + (size_t)q * RL::SLOT, v[m]);
+      else
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[m][i] = (T)0;
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] += v[m][i];
+    if (spilled)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] += ra.take_spill(q, idx + i);
+    store4(out.p[q] + idx, acc);
+    asm volatile("" ::: "memory");
+  }
+}
+
 // The same for any grid (partial tiles at the upper ends): candidate (tile, box index)
 // pairs per axis over the periodic images x - n, x, x + n, box node l of tile t being
 // grid node (t * kTile - 1 + BASE + l) mod n.
@@ -1446,8 +1563,10 @@ __global__ void __launch_bounds__(256) k_deposit_reduce(GridGeom g, TileGeom tg,
         for (int c = 0; c < nz_; ++c) {
           const int tile = (ctx_[a] * tg.nty + cty[b]) * tg.ntz + ctz[c];
           if (starts[tile] == starts[tile + 1]) continue;
-          const T* sb = stage + (size_t)tile * ncomp * X::B3 + X::at(clx[a], cly[b], clz[c]);
-          for (int q = 0; q < ncomp; ++q) acc[q] += sb[(size_t)q * X::B3];
+          const int slot = ra.rows ? StageRows<ORDER>::SLOT : X::B3;
+          const int at = ra.rows ? StageRows<ORDER>::at(clx[a], cly[b], clz[c]) : X::at(clx[a], cly[b], clz[c]);
+          const T* sb = stage + (size_t)tile * ncomp * slot + at;
+          for (int q = 0; q < ncomp; ++q) acc[q] += sb[(size_t)q * slot];
         }
     for (int q = 0; q < ncomp; ++q) out.p[q][idx] = ra.start(q, out.p[q], idx) + acc[q] + (spilled ? ra.take_spill(q, idx) : (T)0);
   }
@@ -2249,6 +2368,7 @@ void allow_lds(const void* kernel, size_t bytes) {
 }
 
 int deposit_box(int shape_order) { return kTile + (shape_order == 1 ? 2 : 4) + 1; }
+int deposit_stage_slot(int shape_order) { return shape_order == 1 ? StageRows<1>::SLOT : StageRows<3>::SLOT; }
 template <typename T>
 void gather_push_tiled(const GridGeom& g, const TileGeom& t, const T* const E[3], const T* const B[3],
                        const SpeciesView<T>& in, const SpeciesView<T>& out, const int* perm, const int* starts,
@@ -2348,6 +2468,19 @@ void deposit_reduce(const GridGeom& g, const TileGeom& t, const int* starts, con
   out.p[0] = rho;
   for (int d = 0; d < 3; ++d) out.p[1 + d] = J ? J[d] : nullptr;
   const int ncomp = with_j ? 4 : 1;
+  if (ra.rows && g.nx % kTile == 0 && g.ny % kTile == 0 && g.nz % kTile == 0) {
+    const int groups = g.nz / 4;
+    const unsigned bz = (unsigned)std::min(256, (groups + 63) / 64 * 64);
+    const dim3 grid((unsigned)((groups + bz - 1) / bz), (unsigned)g.ny, (unsigned)g.nx);
+    if (g.shape_order == 1) {
+      if (with_j) hipLaunchKernelGGL((k_deposit_reduce_rows<T, 1, 4>), grid, dim3(bz), 0, s, g, t, starts, stage, out, ra);
+      else hipLaunchKernelGGL((k_deposit_reduce_rows<T, 1, 1>), grid, dim3(bz), 0, s, g, t, starts, stage, out, ra);
+    } else {
+      if (with_j) hipLaunchKernelGGL((k_deposit_reduce_rows<T, 3, 4>), grid, dim3(bz), 0, s, g, t, starts, stage, out, ra);
+      else hipLaunchKernelGGL((k_deposit_reduce_rows<T, 3, 1>), grid, dim3(bz), 0, s, g, t, starts, stage, out, ra);
+    }
+    return;
+  }
   if (g.nx % kTile == 0 && g.ny % kTile == 0 && g.nz % kTile == 0) {
     const unsigned bz = (unsigned)std::min(256, (g.nz + 63) / 64 * 64);
     const dim3 grid((unsigned)((g.nz + bz - 1) / bz), (unsigned)g.ny, (unsigned)g.nx);
