@@ -768,14 +768,31 @@ void copy_species(const SpeciesView<T>& from, const SpeciesView<T>& to, hipStrea
 
 // forward transforms of the state (E, B) and/or sources (J, rho_old, rho_new)
 template <typename T>
-void forward_batch(pic_ctx c, Engine<T>& e, const T* const* src, cplx<T>* const* dst, int count) {
+void forward_batch(pic_ctx c, Engine<T>& e, const T* const* src, cplx<T>* const* dst, int count,
+                   const LineCenter<T>* lc = nullptr) {
   Batch<const T*> in{};
   Batch<cplx<T>*> out{};
   for (int i = 0; i < count; ++i) {
     in.p[i] = src[i];
     out.p[i] = dst[i];
   }
-  e.fft.forward(in, out, count, c->stream);
+  e.fft.forward(in, out, count, c->stream, lc);
+}
+
+// The centering of the real-space cycle as LineCenter of the transforms: J nodes -> Yee (J^d
+// along axis d; rho^{n+1}, the fourth array, stays nodal) before the forward transforms, and
+// E, B Yee -> nodes (E^d along d, B^d along the two other axes) after the inverse ones.
+template <typename T>
+LineCenter<T> transform_centering(pic_ctx c, bool to_nodes) {
+  LineCenter<T> lc;
+  lc.m = (int)c->ccoef.size();
+  for (int n = 0; n < lc.m; ++n) lc.c[n] = (T)c->ccoef[n];
+  lc.shift = to_nodes ? -1 : 0;
+  for (int a = 0; a < 3; ++a) {
+    lc.mask[a] = 1u << a;  // E^a (to the nodes) or J^a (to the Yee grid) along axis a
+    if (to_nodes) lc.mask[a] |= (7u & ~(1u << a)) << 3;  // B^d, d != a (arrays 3 + d)
+  }
+  return lc;
 }
 
 // The per-mode update, then the inverse transforms: of the staggered state into E_stag,
@@ -783,7 +800,7 @@ void forward_batch(pic_ctx c, Engine<T>& e, const T* const* src, cplx<T>* const*
 // the scratch spectra, into E_nod, B_nod.
 template <typename T>
 void update_and_inverse(pic_ctx c, Engine<T>& e, pic_fields* f, int rho_old_slot, bool spectral = false,
-                        bool state_out = true) {
+                        bool state_out = true, const LineCenter<T>* to_nodes = nullptr) {
   const pic_params& p = c->p;
   const bool avg = averaged(p);
   {
@@ -809,14 +826,15 @@ void update_and_inverse(pic_ctx c, Engine<T>& e, pic_fields* f, int rho_old_slot
   Batch<const cplx<T>*> in{};
   Batch<cplx<T>*> scr{};
   Batch<T*> out{};
+  const bool nod = spectral || to_nodes;  // (to_nodes: centred to the nodes inside the transforms)
   for (int d = 0; d < 3; ++d) {
     in.p[d] = spectral ? e.scratch[d] : e.Eh[d];
     in.p[3 + d] = spectral ? e.scratch[3 + d] : e.Bh[d];
-    out.p[d] = static_cast<T*>(spectral ? f->E_nod[d] : f->E_stag[d]);
-    out.p[3 + d] = static_cast<T*>(spectral ? f->B_nod[d] : f->B_stag[d]);
+    out.p[d] = static_cast<T*>(nod ? f->E_nod[d] : f->E_stag[d]);
+    out.p[3 + d] = static_cast<T*>(nod ? f->B_nod[d] : f->B_stag[d]);
   }
   for (int i = 0; i < 6; ++i) scr.p[i] = e.scratch[i];
-  e.fft.inverse(in, scr, out, 6, 1.0 / (double)ncells(p), c->stream);
+  e.fft.inverse(in, scr, out, 6, 1.0 / (double)ncells(p), c->stream, to_nodes);
 }
 
 // The staggered state E_stag, B_stag from the resident spectra (end of a spectral-
@@ -1032,8 +1050,17 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
   pic_status st;
   const bool spectral = (p.flags & PIC_SPECTRAL_CENTERING) != 0;
   const bool keep = (p.flags & (PIC_KEEP_ORDER | PIC_DETERMINISTIC)) != 0;
+  // Real-space cycle: on every step but the last of the call the centering runs inside the
+  // transforms (J_nod -> spectra of J on the Yee grid; updated spectra -> E_nod, B_nod of the
+  // next step).  The last step takes the separate passes, so that at return E_stag, B_stag,
+  // J_stag and E_nod, B_nod hold what the documented cycle leaves.
+  const bool fused = !spectral && !nodal && !avg && e.fft.centering_fusable();
+  const LineCenter<T> lc_j = fused ? transform_centering<T>(c, false) : LineCenter<T>();
+  const LineCenter<T> lc_eb = fused ? transform_centering<T>(c, true) : LineCenter<T>();
   for (int n = 0; n < nsteps; ++n) {
-    if (!nodal && (!spectral || n == 0)) {  // spectral centering: later steps get E_nod, B_nod from the update
+    const bool mid = fused && n + 1 < nsteps;  // this step's transforms centre
+    const bool nod_ready = fused && n > 0;     // E_nod, B_nod from the previous step's inverse
+    if (!nodal && (!spectral || n == 0) && !nod_ready) {  // spectral centering: later steps get E_nod, B_nod from the update
       StageScope sc(c, ST_S2N);
       pic_fields t = *f;  // averaged PSATD: the particles see the averaged fields
       if (avg)
@@ -1125,20 +1152,21 @@ pic_status do_step(pic_ctx c, pic_fields* f, pic_species* sp, int nsp, int nstep
       StageScope sc(c, ST_CLEAR);
       sum.finish(c, true);
     }
-    if (!spectral && !nodal) {
+    if (!spectral && !nodal && !mid) {
       StageScope sc(c, ST_N2S);
       if ((st = do_center<T>(c, PIC_N2S, PIC_J, f)) != PIC_OK) return st;
     }
     {
       StageScope sc(c, ST_FFT_FWD);
-      // spectral centering: the update centres J; nodal solver: J stays on the nodes
-      void* const* J = (spectral || nodal) ? f->J_nod : f->J_stag;
+      // spectral centering: the update centres J; nodal solver: J stays on the nodes; mid: the
+      // forward transforms centre J
+      void* const* J = (spectral || nodal || mid) ? f->J_nod : f->J_stag;
       const T* src[4] = {static_cast<const T*>(J[0]), static_cast<const T*>(J[1]), static_cast<const T*>(J[2]),
                          static_cast<const T*>(f->rho_new)};
       cplx<T>* dst[4] = {e.Jh[0], e.Jh[1], e.Jh[2], e.rh[1 - slot]};
-      forward_batch<T>(c, e, src, dst, 4);
+      forward_batch<T>(c, e, src, dst, 4, mid ? &lc_j : nullptr);
     }
-    update_and_inverse<T>(c, e, f, slot, spectral, !avg);
+    update_and_inverse<T>(c, e, f, slot, spectral, !avg, mid ? &lc_eb : nullptr);
     slot = 1 - slot;
     if ((st = c->check("pic_step")) != PIC_OK) return st;
   }

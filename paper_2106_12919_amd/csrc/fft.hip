@@ -227,6 +227,47 @@ __device__ inline void fft_lds_static_inplace(cplx<T>* a, const cplx<T>* __restr
   }
 }
 
+// The centering stencil of LineCenter along the lines of an LDS tile (element (l, j) of NL lines
+// of N points at l * LS + j * JS), in place: every thread forms the outputs of its elements from
+// LDS into registers, then writes them after the block's barrier.  SHIFT is the stencil's (0
+// before a forward transform, -1 after an inverse one).
+template <typename T, int N, int NL, bool LINE_FASTEST, int SHIFT>
+__device__ inline void center_tile(cplx<T>* a, const LineCenter<T>& lc) {
+  constexpr int LS = LINE_FASTEST ? 1 : N, JS = LINE_FASTEST ? NL : 1;
+  constexpr int TOTAL = N * NL, IT = (TOTAL + kBlock - 1) / kBlock;
+  cplx<T> o[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int w = it * kBlock + (int)threadIdx.x;
+    T sx = 0, sy = 0;
+    if (TOTAL % kBlock == 0 || w < TOTAL) {
+      const int l = LINE_FASTEST ? w % NL : w / N;
+      const int j = LINE_FASTEST ? w / NL : w % N;
+      const cplx<T>* line = a + l * LS;
+      for (int n = 1; n <= lc.m; ++n) {
+        int jp = j + n + SHIFT, jm = j - n + 1 + SHIFT;
+        jp -= jp >= N ? N : 0;
+        jm += jm < 0 ? N : 0;
+        const cplx<T> u = line[jp * JS], v = line[jm * JS];
+        sx = fma(lc.c[n - 1], u.x + v.x, sx);
+        sy = fma(lc.c[n - 1], u.y + v.y, sy);
+      }
+    }
+    o[it] = cmake(sx, sy);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int w = it * kBlock + (int)threadIdx.x;
+    if (TOTAL % kBlock == 0 || w < TOTAL) {
+      const int l = LINE_FASTEST ? w % NL : w / N;
+      const int j = LINE_FASTEST ? w / NL : w % N;
+      a[l * LS + j * JS] = o[it];
+    }
+  }
+  __syncthreads();
+}
+
 // Largest element count per thread of one block's LDS tile (two buffers of kLdsBudget
 // bytes in all): every thread issues all its global loads (those inside the tile) before it
 // stores any to LDS.
@@ -430,7 +471,8 @@ constexpr int static_lines(int n, int buffers = 2) {
 
 template <typename T, int N>
 __global__ void __launch_bounds__(kBlock) k_r2c_z_n(Batch<const T*> in, Batch<cplx<T>*> out,
-                                                    const cplx<T>* __restrict__ tw, int nlines, int pz) {
+                                                    const cplx<T>* __restrict__ tw, int nlines, int pz,
+                                                    LineCenter<T> lc, unsigned cmask) {
   constexpr int P = static_pairs<T>(N);
   constexpr int TW = plan_of(N).twcount;
   constexpr int PER = (P * N + kBlock - 1) / kBlock;
@@ -460,6 +502,7 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z_n(Batch<const T*> in, Batch<cp
     if (e < total) a[e] = cmake(v0[u], v1[u]);
   }
   __syncthreads();
+  if ((cmask >> blockIdx.y) & 1u) center_tile<T, N, P, false, 0>(a, lc);
   cplx<T>* res = fft_lds_static<T, -1, N, P, false>(a, b, twl);
   constexpr int OUTER = (P * NH + kBlock - 1) / kBlock;
 #pragma unroll
@@ -480,7 +523,7 @@ __global__ void __launch_bounds__(kBlock) k_r2c_z_n(Batch<const T*> in, Batch<cp
 template <typename T, int N>
 __global__ void __launch_bounds__(kBlock) k_c2r_z_n(Batch<const cplx<T>*> in, Batch<T*> out,
                                                     const cplx<T>* __restrict__ tw, int nlines, int pz, T scale,
-                                                    T scale_lo) {
+                                                    T scale_lo, LineCenter<T> lc, unsigned cmask) {
   constexpr int P = static_pairs<T>(N);
   constexpr int TW = plan_of(N).twcount;
   constexpr int PER = (P * N + kBlock - 1) / kBlock;
@@ -523,6 +566,7 @@ __global__ void __launch_bounds__(kBlock) k_c2r_z_n(Batch<const cplx<T>*> in, Ba
   }
   __syncthreads();
   cplx<T>* res = fft_lds_static<T, +1, N, P, false>(a, b, twl);
+  if ((cmask >> blockIdx.y) & 1u) center_tile<T, N, P, false, -1>(res, lc);
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const unsigned e = threadIdx.x + u * kBlock;
@@ -542,7 +586,7 @@ template <typename T, int SIGN, int N>
 __global__ void __launch_bounds__(kBlock) k_fft_strided_n(Batch<const cplx<T>*> in, Batch<cplx<T>*> out,
                                                           const cplx<T>* __restrict__ tw, int inner_count,
                                                           int tiles_per_outer, long long outer_stride,
-                                                          long long elem_stride) {
+                                                          long long elem_stride, LineCenter<T> lc, unsigned cmask) {
   constexpr int TL = static_lines<T>(N, kStaticBuffers);
   static_assert(kBlock % TL == 0, "a block covers whole rows of the tile");
   constexpr int TW = plan_of(N).twcount;
@@ -571,11 +615,14 @@ __global__ void __launch_bounds__(kBlock) k_fft_strided_n(Batch<const cplx<T>*> 
     if (TOTAL % kBlock == 0 || e < TOTAL) a[e] = i < nl ? v[u] : cmake((T)0, (T)0);
   }
   __syncthreads();
+  const bool cen = (cmask >> blockIdx.y) & 1u;
+  if (SIGN < 0 && cen) center_tile<T, N, TL, true, 0>(a, lc);  // forward: centre, then transform
   cplx<T>* res = a;
   if constexpr (PIC_FFT_INPLACE)
     fft_lds_static_inplace<T, SIGN, N, TL, true>(a, twl);
   else
     res = fft_lds_static<T, SIGN, N, TL, true>(a, b, twl);
+  if (SIGN > 0 && cen) center_tile<T, N, TL, true, -1>(res, lc);  // inverse: transform, then centre
   if (i < nl) {
     cplx<T>* __restrict__ dst = out.p[blockIdx.y] + row0;
 #pragma unroll
@@ -626,7 +673,7 @@ bool with_static_length(int n, F&& f) {
 template <typename T, int SIGN>
 void strided_pass(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& out, int count, const FftPlan& p,
                   const cplx<T>* tw, int outer_count, int inner_count, long long outer_stride, long long elem_stride,
-                  hipStream_t s) {
+                  hipStream_t s, const LineCenter<T>& lc = LineCenter<T>(), int axis = 0) {
   if (with_static_length(p.n, [&](auto nc) {
         constexpr int N = decltype(nc)::value;
         constexpr int TL = static_lines<T>(N, kStaticBuffers);
@@ -636,7 +683,7 @@ void strided_pass(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& out, i
                            sizeof(cplx<T>);
         allow_lds((const void*)k_fft_strided_n<T, SIGN, N>, lds);
         hipLaunchKernelGGL((k_fft_strided_n<T, SIGN, N>), grid, dim3(kBlock), lds, s, in, out, tw, inner_count, tpo,
-                           outer_stride, elem_stride);
+                           outer_stride, elem_stride, lc, lc.m > 0 ? lc.mask[axis] : 0u);
       }))
     return;
   const int sh = lines_per_tile_shift<T>(p.n);
@@ -708,7 +755,15 @@ void Fft3D<T>::release() {
 }
 
 template <typename T>
-void Fft3D<T>::forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, int count, hipStream_t s) const {
+bool Fft3D<T>::centering_fusable() const {
+  auto has = [](int n) { return with_static_length(n, [](auto) {}); };
+  return has(nx) && has(ny) && has(nz);
+}
+
+template <typename T>
+void Fft3D<T>::forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, int count, hipStream_t s,
+                       const LineCenter<T>* lcp) const {
+  const LineCenter<T> lc = lcp ? *lcp : LineCenter<T>();
   const int nlines = nx * ny;
   if (!with_static_length(nz, [&](auto nc) {
         constexpr int N = decltype(nc)::value;
@@ -716,7 +771,8 @@ void Fft3D<T>::forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, in
         dim3 grid((nlines / 2 + P - 1) / P, count);
         const size_t lds = fft_lds_bytes<T>((size_t)P * N, plan[2]);
         allow_lds((const void*)k_r2c_z_n<T, N>, lds);
-        hipLaunchKernelGGL((k_r2c_z_n<T, N>), grid, dim3(kBlock), lds, s, in, out, tw[2], nlines, pz);
+        hipLaunchKernelGGL((k_r2c_z_n<T, N>), grid, dim3(kBlock), lds, s, in, out, tw[2], nlines, pz, lc,
+                           lc.m > 0 ? lc.mask[2] : 0u);
       })) {
     const int P = pairs_per_block<T>(nz);
     dim3 grid((nlines / 2 + P - 1) / P, count);
@@ -726,18 +782,19 @@ void Fft3D<T>::forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, in
   }
   Batch<const cplx<T>*> cin;
   for (int i = 0; i < count; ++i) cin.p[i] = out.p[i];
-  strided_pass<T, -1>(cin, out, count, plan[1], tw[1], nx, nzh, (long long)ny * pz, pz, s);
-  strided_pass<T, -1>(cin, out, count, plan[0], tw[0], 1, ny * pz, 0, (long long)ny * pz, s);
+  strided_pass<T, -1>(cin, out, count, plan[1], tw[1], nx, nzh, (long long)ny * pz, pz, s, lc, 1);
+  strided_pass<T, -1>(cin, out, count, plan[0], tw[0], 1, ny * pz, 0, (long long)ny * pz, s, lc, 0);
 }
 
 template <typename T>
 void Fft3D<T>::inverse(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& scratch, const Batch<T*>& out,
-                       int count, double scale, hipStream_t s) const {
+                       int count, double scale, hipStream_t s, const LineCenter<T>* lcp) const {
+  const LineCenter<T> lc = lcp ? *lcp : LineCenter<T>();
   const T sc_hi = (T)scale, sc_lo = (T)(scale - (double)sc_hi);
-  strided_pass<T, +1>(in, scratch, count, plan[0], tw[0], 1, ny * pz, 0, (long long)ny * pz, s);
+  strided_pass<T, +1>(in, scratch, count, plan[0], tw[0], 1, ny * pz, 0, (long long)ny * pz, s, lc, 0);
   Batch<const cplx<T>*> cs;
   for (int i = 0; i < count; ++i) cs.p[i] = scratch.p[i];
-  strided_pass<T, +1>(cs, scratch, count, plan[1], tw[1], nx, nzh, (long long)ny * pz, pz, s);
+  strided_pass<T, +1>(cs, scratch, count, plan[1], tw[1], nx, nzh, (long long)ny * pz, pz, s, lc, 1);
   const int nlines = nx * ny;
   if (!with_static_length(nz, [&](auto nc) {
         constexpr int N = decltype(nc)::value;
@@ -745,7 +802,8 @@ void Fft3D<T>::inverse(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& s
         dim3 grid((nlines / 2 + P - 1) / P, count);
         const size_t lds = fft_lds_bytes<T>((size_t)P * N, plan[2]);
         allow_lds((const void*)k_c2r_z_n<T, N>, lds);
-        hipLaunchKernelGGL((k_c2r_z_n<T, N>), grid, dim3(kBlock), lds, s, cs, out, tw[2], nlines, pz, sc_hi, sc_lo);
+        hipLaunchKernelGGL((k_c2r_z_n<T, N>), grid, dim3(kBlock), lds, s, cs, out, tw[2], nlines, pz, sc_hi, sc_lo,
+                           lc, lc.m > 0 ? lc.mask[2] : 0u);
       })) {
     const int P = pairs_per_block<T>(nz);
     dim3 grid((nlines / 2 + P - 1) / P, count);

@@ -9,6 +9,20 @@ namespace pic {
 // Real 3D transforms of (nx, ny, nz) arrays, z contiguous.  The half spectrum is
 // stored (nx, ny, pz) with kz contiguous, kz < nz/2+1 used, pz >= nz/2+1 the row
 // pitch.  Forward: X[k] = sum_j x[j] exp(-2 pi i j.k / n) per axis (unnormalised).
+// Finite-order centering (Sec. 3) folded into the transform passes: array i of a batch is
+// centred along axis a (0 x, 1 y, 2 z) when bit i of mask[a] is set, by the periodic stencil
+//   out_j = sum_{n=1}^{m} c[n-1] (in_{j+n+shift} + in_{j-n+1+shift})
+// applied to the whole lines of that axis a pass holds in LDS (before the forward transform
+// along a, after the inverse one).  A stencil along one axis commutes with the transforms
+// along the others, so this is the real-space centering of the array, up to rounding.
+template <typename T>
+struct LineCenter {
+  int m = 0;      // half order (0: no centering)
+  int shift = 0;  // 0: nodes -> cell centres, -1: centres -> nodes
+  unsigned mask[3] = {0u, 0u, 0u};
+  T c[16] = {};
+};
+
 template <typename T>
 struct Fft3D {
   int nx = 0, ny = 0, nz = 0, nzh = 0, pz = 0;
@@ -17,14 +31,18 @@ struct Fft3D {
   hipError_t init(int nx, int ny, int nz);   // builds plans, uploads twiddles
   void release();
   size_t spectrum_elems() const { return (size_t)nx * ny * pz; }
-  // count <= kMaxBatch arrays, real -> spectrum
-  void forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, int count, hipStream_t s) const;
+  // Whether every axis length has transform kernels of its own (LineCenter needs them).
+  bool centering_fusable() const;
+  // count <= kMaxBatch arrays, real -> spectrum; lc (optional, centering_fusable() only):
+  // centering of the inputs folded into the passes
+  void forward(const Batch<const T*>& in, const Batch<cplx<T>*>& out, int count, hipStream_t s,
+               const LineCenter<T>* lc = nullptr) const;
   // spectrum -> real; ``scratch`` receives the partially transformed spectra (``in`` is preserved);
   // the result is scaled by ``scale`` (given in FP64 and applied to twice the run precision: 1/N is
   // inexact in binary when N has a factor 3, and a rounded scale would change the field energy by
   // the same factor on every inverse transform).
   void inverse(const Batch<const cplx<T>*>& in, const Batch<cplx<T>*>& scratch, const Batch<T*>& out, int count,
-               double scale, hipStream_t s) const;
+               double scale, hipStream_t s, const LineCenter<T>* lc = nullptr) const;
 };
 
 // ---------------------------------------------------------------- centering (centering.hip)

@@ -1,6 +1,7 @@
 """Parity with the oracle on the paths the timed and full-size runs take that the stage tests on
 small grids do not reach: the 384- and 768-point FFT axes of the beam-driven-wake grid and every
-axis length with transform kernels of its own, one
+axis length with transform kernels of its own, calls of several steps on grids whose transforms
+carry the centering (every axis length has kernels of its own), one
 pic_step call of several steps (E, B resident in Fourier space) for the standard, Galilean and
 averaged Galilean cycles, grids of more tiles than the single-launch bucket scan and the LDS
 bucket histogram hold, the beam-driven wake at 1/4 scale (gamma = 1000 beam), and several
@@ -74,6 +75,54 @@ def test_field_solve_on_the_specialised_axis_lengths(dtype, shape):
     for d in range(3):
         eE, eB = max_rel(np64(f.E_stag[d]), E_ref[d]), max_rel(np64(f.B_stag[d]), B_ref[d])
         assert eE <= tol and eB <= tol, (d, eE, eB, tol)
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype,shape_order,center_order", [("f64", 3, 8), ("f32", 3, 16), ("f64", 1, 4),
+                                                            ("f32", 1, 32)])
+def test_call_with_centering_in_the_transforms(dtype, shape_order, center_order):
+    """On a 64^3 grid every axis has transform kernels of its own, so a pic_step call of several
+    steps runs the real-space centering inside the transforms on every step but the last.  Against
+    the oracle's real-space cycle: the final staggered state, the nodal fields of the last step's
+    start, that step's J on the Yee grid, rho and every particle."""
+    banner(f"pic_step with centering in the transforms, 4 steps dtype={dtype} shape={shape_order} "
+           f"centering={center_order}")
+    shape, nsteps = (64, 64, 64), 4
+    wl = inputs.small(shape, ppc=1, shape_order=shape_order, center_order=center_order, dtype=dtype, u_th=0.2,
+                      field_amp=0.02, seed=71)
+    _ids(wl)
+    ctx = piclib.Context.for_workload(wl)
+    f = ctx.fields_from_workload(wl)
+    el = piclib.Species.from_host(wl.electrons, shape, dtype)
+    ions = piclib.Species.from_host(wl.ions, shape, dtype)
+    ctx.init_charge(f, el, ions)
+    p = ostep.Params(shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order)
+    osp = oracle_species(el, shape, wl.spacing)
+    oion = oracle_species(ions, shape, wl.spacing)
+    rho_static = ostep.deposit_rho([oion], p)
+    state = {"E_stag": rounded(wl.E, dtype), "B_stag": rounded(wl.B, dtype),
+             "rho_old": ostep.deposit_rho([osp], p, rho_static)}
+    piclib.pic_step(ctx.ctx, f, [el], nsteps)
+    piclib.pic_sync(ctx.ctx)
+    for n in range(nsteps):
+        if n == nsteps - 1:
+            E_nod, B_nod = ostep.center_fields_s2n(state["E_stag"], state["B_stag"], p)
+        out = ostep.step(state, [osp], p, rho_static)
+    tol = 1e-10 if dtype == "f64" else 2e-4
+    J_stag = ostep.center_current_n2s(out["J_nod"], p)
+    for d in range(3):
+        assert max_rel(np64(f.E_stag[d]), state["E_stag"][d]) <= tol, ("E", d)
+        assert max_rel(np64(f.B_stag[d]), state["B_stag"][d]) <= tol, ("B", d)
+        assert max_rel(np64(f.E_nod[d]), E_nod[d]) <= tol, ("E_nod", d)
+        assert max_rel(np64(f.B_nod[d]), B_nod[d]) <= tol, ("B_nod", d)
+        assert max_rel(np64(f.J_stag[d]), J_stag[d]) <= tol, ("J_stag", d)
+    assert max_rel(np64(f.rho_old), state["rho_old"]) <= tol
+    g_w = np64(el.w)
+    gi, oi = np.argsort(g_w), np.argsort(osp["w"])
+    g_pos = el.positions(shape, wl.spacing)[gi]
+    g_u = np.stack([np64(x) for x in el.u], axis=1)[gi]
+    assert periodic_pos_err(g_pos, osp["pos"][oi], p.lengths) <= (1e-11 if dtype == "f64" else 4e-5)
+    assert np.max(np.abs(g_u - osp["u"][oi])) <= (1e-11 if dtype == "f64" else 4e-5)
     ctx.close()
 
 
