@@ -246,7 +246,10 @@ pic_status pic_gather_push(pic_ctx ctx, const pic_fields* f, pic_species* sp, in
 
 /* nsteps >= 0 complete hybrid cycles.  State on entry: E_stag, B_stag at time n,
  * particles at x^n with u^{n-1/2}, rho_old = rho^n.  Each step runs
- * S2N centering -> gather+push -> deposit -> N2S centering -> PSATD update.  On
+ * S2N centering -> gather+push -> deposit -> N2S centering -> PSATD update.  (When every
+ * axis length is one of 64, 128, 256, 384, 768, the steps of a call before its last apply
+ * both centerings inside the transforms, to whole lines of the centred axis, with the same
+ * stencil: the results equal those of the separate passes up to rounding.)  On
  * return E_stag, B_stag, particles and rho_old are at time n+nsteps, and E_nod,
  * B_nod, J_nod, J_stag, rho_new hold the intermediates of the last step.  E and
  * B stay in Fourier space between the steps of one call (7 forward transforms on
