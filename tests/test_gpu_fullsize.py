@@ -7,6 +7,8 @@
   same FP32-rounded inputs, and every particle compared (identities by weight).
 * laser64 (64x64x128, 2,097,152 particles, cubic, centering 8, 60 steps): the gradient of
   the differentiable run (checkpoints every 10 steps) against central differences.
+* beam384 and thermal256: sampled one-step checks against the oracle, and calls of several
+  steps (the centering inside the transforms) against single-step calls.
 """
 
 import numpy as np
@@ -382,3 +384,38 @@ def test_thermal256_one_step_sampled(dtype, center_order):
         assert abs(float(torch.sum(f.J_nod[d].double())) - jd) <= (1e-4 if dtype == "f32" else 1e-10) * \
             float(torch.sum(el.w.double() * torch.abs(ud) / gam))
     ctx.close()
+
+
+@pytest.mark.parametrize("name,dtype", [("beam384", "f64"), ("thermal256", "f32")])
+def test_multi_step_call_matches_single_steps(name, dtype):
+    """The bench times calls of many steps, which on these grids centre inside the transforms on
+    every step but a call's last; single-step calls take the separate centering passes (the path
+    the sampled one-step tests above hold to the oracle).  Three steps in one call against three
+    calls of one step from the same inputs: the staggered fields, which every particle's current
+    feeds, and the charge density agree to rounding."""
+    banner(f"{name} full size, one call of 3 steps against 3 calls of one step, dtype={dtype}")
+    wl = inputs.config(name, dtype=dtype)
+    if name == "thermal256":  # random fields, so that the gather and push act from the first step
+        rng = np.random.default_rng(257)
+        wl.E = [0.01 * rng.standard_normal(wl.shape) for _ in range(3)]
+        wl.B = [0.01 * rng.standard_normal(wl.shape) for _ in range(3)]
+    results = []
+    for calls in ([3], [1, 1, 1]):
+        ctx = piclib.Context.for_workload(wl)
+        f = ctx.fields_from_workload(wl)
+        el = piclib.Species.from_host(wl.electrons, wl.shape, dtype)
+        ions = piclib.Species.from_host(wl.ions, wl.shape, dtype)
+        ctx.init_charge(f, el, ions)
+        del ions
+        for k in calls:
+            piclib.pic_step(ctx.ctx, f, [el], k)
+        piclib.pic_sync(ctx.ctx)
+        results.append([t.cpu().numpy() for t in (*f.E_stag, *f.B_stag, f.rho_old)])
+        ctx.close()
+        del f, el
+        torch.cuda.empty_cache()
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    for c, (a, b) in enumerate(zip(*results)):
+        err = max_rel(a, b)
+        print(f"[{name}] component {c}: max rel {err:.3e}", flush=True)
+        assert err <= tol, (c, err)
