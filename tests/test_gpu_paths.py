@@ -78,25 +78,30 @@ def test_field_solve_on_the_specialised_axis_lengths(dtype, shape):
     ctx.close()
 
 
-@pytest.mark.parametrize("dtype,shape_order,center_order", [("f64", 3, 8), ("f32", 3, 16), ("f64", 1, 4),
-                                                            ("f32", 1, 32)])
-def test_call_with_centering_in_the_transforms(dtype, shape_order, center_order):
+@pytest.mark.parametrize("dtype,shape_order,center_order,variant", [
+    ("f64", 3, 8, "standard"), ("f32", 3, 16, "standard"), ("f64", 1, 4, "standard"), ("f32", 1, 32, "standard"),
+    ("f64", 3, 8, "galilean"), ("f64", 3, 8, "correction")])
+def test_call_with_centering_in_the_transforms(dtype, shape_order, center_order, variant):
     """On a 64^3 grid every axis has transform kernels of its own, so a pic_step call of several
-    steps runs the real-space centering inside the transforms on every step but the last.  Against
-    the oracle's real-space cycle: the final staggered state, the nodal fields of the last step's
-    start, that step's J on the Yee grid, rho and every particle."""
+    steps runs the real-space centering inside the transforms on every step but the last (also with
+    the Galilean solver and the current correction).  Against the oracle's real-space cycle: the
+    final staggered state, the nodal fields of the last step's start, that step's J on the Yee grid,
+    rho and every particle."""
     banner(f"pic_step with centering in the transforms, 4 steps dtype={dtype} shape={shape_order} "
-           f"centering={center_order}")
+           f"centering={center_order} variant={variant}")
     shape, nsteps = (64, 64, 64), 4
+    v_gal = (0.0, 0.0, -0.9) if variant == "galilean" else (0.0, 0.0, 0.0)
+    flags = piclib.PIC_CURRENT_CORRECTION if variant == "correction" else 0
     wl = inputs.small(shape, ppc=1, shape_order=shape_order, center_order=center_order, dtype=dtype, u_th=0.2,
                       field_amp=0.02, seed=71)
     _ids(wl)
-    ctx = piclib.Context.for_workload(wl)
+    ctx = piclib.Context.for_workload(wl, flags=flags, v_gal=v_gal)
     f = ctx.fields_from_workload(wl)
     el = piclib.Species.from_host(wl.electrons, shape, dtype)
     ions = piclib.Species.from_host(wl.ions, shape, dtype)
     ctx.init_charge(f, el, ions)
-    p = ostep.Params(shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order)
+    p = ostep.Params(shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order, v_gal=v_gal,
+                     current_correction=(variant == "correction"))
     osp = oracle_species(el, shape, wl.spacing)
     oion = oracle_species(ions, shape, wl.spacing)
     rho_static = ostep.deposit_rho([oion], p)
