@@ -238,7 +238,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the forward+backward measurements (laser64 and the beam-driven wake)")
     ap.add_argument("--adjoint-config", default="laser64", choices=sorted(CONFIG_TEXT))
-    ap.add_argument("--checkpoint-every", type=int, default=10)
+    ap.add_argument("--checkpoint-every", default="auto", metavar="K|auto",
+                    help="checkpoint interval of the forward+backward legs; auto: every step when the "
+                         "states fit in half the free device memory, else the smallest interval that fits")
     ap.add_argument("--adjoint-steps", type=int, default=0, metavar="K",
                     help="steps of the forward+backward run (default: the configuration's length)")
     ap.add_argument("--adjoint-reps", type=int, default=3)
@@ -492,7 +494,9 @@ def time_field_solve(wl, flags, reps=20):
 
 def time_fwd_bwd(config_name, every, reps=3, steps=0, loss="kinetic"):
     """Forward + backward of a differentiable run: ``steps`` of the config (default its length)
-    through autograd.PicSteps with checkpoints every ``every`` steps, gradients w.r.t. the initial
+    through autograd.PicSteps with checkpoints every ``every`` steps ("auto": every step when the
+    states fit in half the free device memory, else the smallest interval that fits; reported as
+    ``checkpoint_every``), gradients w.r.t. the initial
     E, B and momenta; set against the same run of the production forward (pic_step, default flags).
     Losses: "kinetic", the total electron kinetic energy sum w (gamma - 1) at the end; and
     "beam_energy_loss", the drive beam's energy loss sum_beam w (gamma^0 - gamma^end) (the beam's
@@ -545,6 +549,10 @@ def time_fwd_bwd(config_name, every, reps=3, steps=0, loss="kinetic"):
     del state0, f0, el0
     torch.cuda.empty_cache()
     ctx, f, el = setup(piclib.PIC_KEEP_ORDER)
+    if every == "auto":  # store every state that fits in half the free memory
+        free, _ = torch.cuda.mem_get_info()
+        every = pag.checkpoint_interval(ctx, el.n, K, 0.5 * free)
+    every = int(every)
     E_in, B_in, u_in = torch.stack(f.E_stag), torch.stack(f.B_stag), torch.stack(el.u)
     off_in = torch.stack(el.off)
     grads = {}

@@ -6,7 +6,8 @@
 * ``PicSteps``: nsteps whole cycles (``pic_step`` with the caller's particle order kept) with
   gradients with respect to the initial fields, charge density, particle offsets and momenta,
   by ``pic_step_adjoint`` one step at a time, backwards, from states recomputed out of
-  checkpoints kept every ``checkpoint_every`` steps.
+  checkpoints kept every ``checkpoint_every`` steps (every step, with nothing recomputed, when
+  ``checkpoint_interval`` finds that the states fit in the memory given to them).
 
 Every computation runs in libpic's HIP kernels; this module only moves tensors in and out
 of the library's workspaces and keeps the checkpoints.
@@ -143,6 +144,32 @@ class _State:
         piclib.pic_step(run.pic.ctx, self.fields(run), [self.species(run, w)], n)
 
 
+def state_bytes(pic, n_particles):
+    """Device bytes of one stored state of a run (the _State buffers): E, B, rho and one species'
+    cell, offsets and momenta."""
+    elem = 4 if pic.dtype == "f32" else 8
+    nx, ny, nz = pic.shape
+    row = -(-int(n_particles) // 64) * 64
+    return 7 * nx * ny * nz * elem + 4 * int(n_particles) + 6 * row * elem
+
+
+def checkpoint_interval(pic, n_particles, nsteps, budget_bytes):
+    """The smallest checkpoint interval k whose states fit in ``budget_bytes``: ceil(nsteps / k)
+    checkpoints, plus, when k > 1, the k states of one segment recomputed in the backward pass and
+    its working copy.  k = 1 stores every step's state, and the backward pass then recomputes
+    nothing.  When no interval fits, the one that holds the fewest states."""
+    s = state_bytes(pic, n_particles)
+    n = int(nsteps)
+
+    def held(k):
+        return -(-n // k) + (k + 1 if k > 1 else 0)
+
+    for k in range(1, n + 1):
+        if held(k) * s <= budget_bytes:
+            return k
+    return min(range(1, n + 1), key=held)  # none fits: the fewest states held
+
+
 def _zeros_or(g, like):
     return torch.zeros_like(like) if g is None else g.contiguous()
 
@@ -191,11 +218,15 @@ class PicSteps(torch.autograd.Function):
         for seg in reversed(range(len(ctx.checkpoints))):
             n0 = seg * run.every
             k = min(run.every, run.nsteps - n0)
-            st = ctx.checkpoints[seg].clone()
-            states = [st.clone()]
-            for _ in range(k - 1):
-                st.step(run, w, 1)
-                states.append(st.clone())
+            if k == 1:  # pic_step_adjoint only reads the state: the checkpoint itself serves
+                states = [ctx.checkpoints[seg]]
+            else:
+                st = ctx.checkpoints[seg].clone()
+                states = [st.clone()]
+                for _ in range(k - 1):
+                    st.step(run, w, 1)
+                    states.append(st.clone())
+            ctx.checkpoints[seg] = None  # not needed again: free it for the segments before
             for sj in reversed(states):
                 piclib.pic_step_adjoint(run.pic.ctx, sj.fields(run), [sj.species(run, w)], adj, [asp])
                 adj.rho_old, adj.rho_new = adj.rho_new, adj.rho_old  # dL/drho^n carries to the step before

@@ -46,3 +46,23 @@ def test_recorded_traffic_is_gated_on_the_kernel_sources(monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
     assert bench.recorded_traffic("deposit") is None
     assert bench.recorded_traffic("deposit", "laser128") is None
+
+
+def test_checkpoint_interval_of_the_reverse_mode():
+    """The forward+backward legs store every step's state when the states fit the memory given to
+    them (nothing is recomputed), else take the smallest interval whose checkpoints and one
+    recomputed segment fit."""
+    from types import SimpleNamespace
+
+    from paper_2106_12919_amd import autograd as pag
+
+    pic = SimpleNamespace(shape=(64, 64, 128), dtype="f32")
+    n = 2_097_152
+    s = pag.state_bytes(pic, n)
+    assert s == 7 * 64 * 64 * 128 * 4 + 4 * n + 6 * n * 4  # n is a multiple of 64: no row padding
+    # 60 steps: k = 1 holds 60 states; k > 1 holds ceil(60 / k) + k + 1 (2: 33, 3: 24, 4: 20, 6: 17)
+    assert pag.checkpoint_interval(pic, n, 60, 60 * s) == 1
+    assert pag.checkpoint_interval(pic, n, 60, 59 * s) == 2
+    assert pag.checkpoint_interval(pic, n, 60, 20 * s) == 4
+    assert pag.checkpoint_interval(pic, n, 60, 16 * s) == 6  # none fits: the fewest held (17, first at k = 6)
+    assert pag.checkpoint_interval(SimpleNamespace(shape=(8, 8, 8), dtype="f64"), 100, 5, 1e12) == 1
