@@ -257,8 +257,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs the hybrid PSATD step on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU domain decomposition is described in DESIGN.md, not built.", file=sys.stderr)
+        print(f"bench.py: the hybrid PSATD step runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU domain decomposition is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     if args.precision_statement:

@@ -9,8 +9,8 @@ deposit |sum rho_e dV - sum q w| / |sum q w|.  Targets: 1e-5 on field energy,
 
 The oracle takes seconds to tens of seconds per step at these sizes: laser64 and laser128 over
 10 steps and the 64^3 thermal proxy of the 256^3 configuration at centering orders 2 and 32 run
-in every GPU test session; the other centering orders run with PIC_LONG_TESTS=1.  Each workload
-writes its table to gpurun_out/precision_<name>.json.
+in every GPU test session; the other centering orders run with PIC_LONG_TESTS=1.  With
+PIC_PRECISION_DIR set, each workload writes its table to that directory as precision_<name>.json.
 """
 
 import json
@@ -87,9 +87,11 @@ def run_statement(wl, nsteps):
         print(f"[precision] {wl.name} step {step}: |W32-W64|/W64 {row['W_rel']:.2e}", flush=True)
         del out
     ctx.close()
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", f"precision_{wl.name}.json"), "w") as fh:
-        json.dump({"workload": wl.name, "steps": rows}, fh, indent=1)
+    out_dir = os.environ.get("PIC_PRECISION_DIR")
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, f"precision_{wl.name}.json"), "w") as fh:
+            json.dump({"workload": wl.name, "steps": rows}, fh, indent=1)
     worst = {k: max(r[k] for r in rows) for k in rows[0] if k != "step"}
     fmax = max(v for k, v in worst.items() if k.endswith("_max") and k != "u_max")
     fl2 = max(v for k, v in worst.items() if k.endswith("_l2"))
