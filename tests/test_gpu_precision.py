@@ -19,7 +19,7 @@ import os
 import numpy as np
 import pytest
 
-from gpu_common import ROOT, banner, np64, oracle_species
+from gpu_common import banner, np64, oracle_species
 
 pytestmark = pytest.mark.gpu
 LONG = pytest.mark.skipif(not os.environ.get("PIC_LONG_TESTS"),
