@@ -200,6 +200,33 @@ def cpu_baseline(config_name="beam96", steps=2, workers=None):
     }
 
 
+def cpu_single_thread(config_name, steps):
+    """FP64 oracle in this process alone (one thread: NumPy's elementwise work and transforms run
+    single-threaded), ``steps`` whole hybrid cycles of ``config_name``."""
+    import numpy as np
+
+    from oracle import step as ostep
+    from paper_2106_12919_amd import inputs
+
+    wl = inputs.config(config_name, dtype="f64")
+    p = ostep.Params(wl.shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order)
+    sp = {"pos": wl.electrons.positions(wl.spacing), "u": wl.electrons.u.copy(), "w": wl.electrons.w,
+          "q": wl.electrons.q, "m": wl.electrons.m}
+    ions = {"pos": wl.ions.positions(wl.spacing), "u": wl.ions.u, "w": wl.ions.w, "q": 1.0, "m": np.inf}
+    rho_static = ostep.deposit_rho([ions], p)
+    state = {"E_stag": [np.array(a) for a in wl.E], "B_stag": [np.array(a) for a in wl.B],
+             "rho_old": ostep.deposit_rho([sp], p, rho_static)}
+    ru = lambda: sum(getattr(resource.getrusage(resource.RUSAGE_SELF), f) for f in ("ru_utime", "ru_stime"))
+    c0, t0 = ru(), time.perf_counter()
+    for _ in range(steps):
+        ostep.step(state, [sp], p, rho_static)
+    T, C = time.perf_counter() - t0, ru() - c0
+    Np = wl.electrons.n
+    return {"workload": config_name, "steps": steps, "value": Np * steps / T, "unit": "particle-pushes/s",
+            "cell_updates_per_s": wl.cells * steps / T, "wall_s": round(T, 2), "cpu_s": round(C, 2),
+            "cores": max(1, round(C / T))}
+
+
 # ------------------------------------------------------------------ main
 
 def main():
@@ -275,6 +302,8 @@ def main():
         cpu = cpu_baseline(args.cpu_config)
         print(f"[bench] CPU oracle: {cpu['value']:.3e} pushes/s on {cpu['cores']} cores", file=sys.stderr,
               flush=True)
+        # and on one thread, the two smallest configurations (thermal32 2 steps, laser64 1 step)
+        cpu["single_thread"] = [cpu_single_thread("thermal32", 2), cpu_single_thread("laser64", 1)]
 
     import torch
 
