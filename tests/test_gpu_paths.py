@@ -4,8 +4,9 @@ axis length with transform kernels of its own, calls of several steps on grids w
 carry the centering (every axis length has kernels of its own), one
 pic_step call of several steps (E, B resident in Fourier space) for the standard, Galilean and
 averaged Galilean cycles, grids of more tiles than the single-launch bucket scan and the LDS
-bucket histogram hold, the beam-driven wake at 1/4 scale (gamma = 1000 beam), and several
-species in one call in every order (two mobile species; an immobile one first or between)."""
+bucket histogram hold, the beam-driven wake at 1/4 scale (gamma = 1000 beam), several species
+in one call in every order (two mobile species; an immobile one first or between), and calls
+without particles (no species, or species of zero particles)."""
 
 import numpy as np
 import pytest
@@ -332,4 +333,57 @@ def test_several_species_in_one_call(dtype, order):
         g, r = ion.positions(shape, a.spacing), osp["ion"]["pos"]
         g, r = g[np.lexsort(g.T[::-1])], r[np.lexsort(r.T[::-1])]
         assert np.array_equal(g, r)
+    ctx.close()
+
+
+def _no_particles(q, m, dtype):
+    td = torch.float32 if dtype == "f32" else torch.float64
+    z = [torch.zeros(0, dtype=td, device="cuda") for _ in range(7)]
+    return piclib.Species(torch.zeros(0, dtype=torch.int32, device="cuda"), z[0:3], z[3:6], z[6], q, m)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape,species", [((16, 12, 24), "none"), ((64, 64, 128), "none"),
+                                           ((64, 64, 128), "empty"), ((16, 16, 24), "empty,el,empty")])
+def test_calls_without_particles(dtype, shape, species):
+    """The source-free case: with no species, or only species of zero particles, one call of three
+    steps is the vacuum field solve around the static charge (rho^{n+1} = rho_static, J = 0), on a
+    grid with partial tiles (generic transforms, separate centering passes) and on one whose
+    transforms carry the centering.  Species of zero particles around a mobile one change nothing:
+    the mobile one still writes the sources first."""
+    banner(f"pic_step without particles dtype={dtype} shape={shape} species={species}")
+    wl = _mobile(141, -1.0, 1.0, shape, dtype)
+    ctx = piclib.Context.for_workload(wl, flags=0)
+    f = ctx.fields_from_workload(wl)
+    el = piclib.Species.from_host(wl.electrons, shape, dtype)
+    ions = piclib.Species.from_host(wl.ions, shape, dtype)
+    empty = _no_particles(-1.0, 1.0, dtype)
+    names = [] if species == "none" else species.split(",")
+    dev = [el if k == "el" else empty for k in names]
+    # rho_static from the ions; rho_old from the species passed (rho_static alone without particles)
+    ctx.init_charge(f, empty if "el" not in names else el, ions)
+    p = ostep.Params(shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order)
+    rho_static = ostep.deposit_rho([oracle_species(ions, shape, wl.spacing)], p)
+    osp = [oracle_species(el, shape, wl.spacing)] if "el" in names else []
+    state = {"E_stag": rounded(wl.E, dtype), "B_stag": rounded(wl.B, dtype),
+             "rho_old": ostep.deposit_rho(osp, p, rho_static)}
+    nsteps = 3
+    piclib.pic_step(ctx.ctx, f, dev, nsteps)
+    piclib.pic_sync(ctx.ctx)
+    for _ in range(nsteps):
+        out = ostep.step(state, osp, p, rho_static)
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    for d in range(3):
+        assert max_rel(np64(f.E_stag[d]), state["E_stag"][d]) <= tol, ("E", d)
+        assert max_rel(np64(f.B_stag[d]), state["B_stag"][d]) <= tol, ("B", d)
+        if osp:
+            assert max_rel(np64(f.J_nod[d]), out["J_nod"][d]) <= tol, ("J", d)
+        else:
+            assert not torch.any(f.J_nod[d] != 0), ("J", d)
+    assert max_rel(np64(f.rho_old), state["rho_old"]) <= tol
+    if not osp:  # rho^{n+1} is the static charge, bit for bit
+        assert torch.equal(f.rho_old, f.rho_static)
+    else:
+        _compare_particles(el, osp[0], shape, wl.spacing, p.lengths, dtype, 1e-11 if dtype == "f64" else 2e-5,
+                           1e-11 if dtype == "f64" else 2e-5)
     ctx.close()
