@@ -79,6 +79,69 @@ def test_field_solve_on_the_specialised_axis_lengths(dtype, shape):
     ctx.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape", [(1024, 8, 16), (8, 1024, 16), (8, 16, 1024)])
+def test_field_solve_at_the_largest_axis_length(dtype, shape):
+    """Axes of 1024 points, the largest pic_init accepts, on x, y and z in turn: the generic
+    transform kernels at their narrowest tiles (one or two lines per strided tile, one or two line
+    pairs per z block)."""
+    banner(f"psatd_push_fields on 1024-point axes dtype={dtype} shape={shape}")
+    dt = 0.5
+    p = ostep.Params(shape, (1.0, 1.0, 1.0), dt, 1, 8, 16)
+    ctx = piclib.Context(shape, (1.0, 1.0, 1.0), dt, 1, 8, 16, dtype)
+    f = piclib.Fields(shape, dtype)
+    src = rounded(inputs.random_grid(shape, seed=113, count=11), dtype)
+    put(f.E_stag, src[0:3])
+    put(f.B_stag, src[3:6])
+    put(f.J_stag, src[6:9])
+    put([f.rho_old, f.rho_new], src[9:11])
+    piclib.psatd_push_fields(ctx.ctx, f)
+    piclib.pic_sync(ctx.ctx)
+    E_ref, B_ref = ostep.push_fields(src[0:3], src[3:6], src[6:9], src[9], src[10], p)
+    tol = fft_tol(dtype, shape)
+    for d in range(3):
+        eE, eB = max_rel(np64(f.E_stag[d]), E_ref[d]), max_rel(np64(f.B_stag[d]), B_ref[d])
+        assert eE <= tol and eB <= tol, (d, eE, eB, tol)
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape", [(16, 16, 1024), (16, 1024, 16)])
+def test_step_at_the_largest_axis_length(dtype, shape):
+    """One call of two full cycles on grids with a 1024-point axis (cubic shape, centering order
+    16): the centering passes on 1024-point lines (in FP64 the fused x/y-then-z pass does not fit
+    and separate passes run), 128 tiles along that axis, the generic transforms; every field and
+    every particle against the oracle."""
+    banner(f"pic_step on a grid with a 1024-point axis dtype={dtype} shape={shape}")
+    wl = inputs.small(shape, ppc=1, shape_order=3, center_order=16, dtype=dtype, u_th=0.1, field_amp=0.05,
+                      seed=142)
+    _ids(wl)
+    ctx = piclib.Context.for_workload(wl, flags=0)
+    f = ctx.fields_from_workload(wl)
+    el = piclib.Species.from_host(wl.electrons, shape, dtype)
+    ions = piclib.Species.from_host(wl.ions, shape, dtype)
+    ctx.init_charge(f, el, ions)
+    p = ostep.Params(shape, wl.spacing, wl.dt, wl.shape_order, wl.center_order, wl.psatd_order)
+    osp = oracle_species(el, shape, wl.spacing)
+    rho_static = ostep.deposit_rho([oracle_species(ions, shape, wl.spacing)], p)
+    state = {"E_stag": rounded(wl.E, dtype), "B_stag": rounded(wl.B, dtype),
+             "rho_old": ostep.deposit_rho([osp], p, rho_static)}
+    nsteps = 2
+    piclib.pic_step(ctx.ctx, f, [el], nsteps)
+    piclib.pic_sync(ctx.ctx)
+    for _ in range(nsteps):
+        out = ostep.step(state, [osp], p, rho_static)
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    for d in range(3):
+        assert max_rel(np64(f.E_stag[d]), state["E_stag"][d]) <= tol, ("E", d)
+        assert max_rel(np64(f.B_stag[d]), state["B_stag"][d]) <= tol, ("B", d)
+        assert max_rel(np64(f.J_nod[d]), out["J_nod"][d]) <= tol, ("J", d)
+    assert max_rel(np64(f.rho_old), state["rho_old"]) <= tol
+    _compare_particles(el, osp, shape, wl.spacing, p.lengths, dtype, 1e-11 if dtype == "f64" else 2e-5,
+                       1e-11 if dtype == "f64" else 2e-5)
+    ctx.close()
+
+
 @pytest.mark.parametrize("dtype,shape_order,center_order,variant", [
     ("f64", 3, 8, "standard"), ("f32", 3, 16, "standard"), ("f64", 1, 4, "standard"), ("f32", 1, 32, "standard"),
     ("f64", 3, 8, "galilean"), ("f64", 3, 8, "correction")])
