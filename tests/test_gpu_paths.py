@@ -5,8 +5,9 @@ carry the centering (every axis length has kernels of its own), one
 pic_step call of several steps (E, B resident in Fourier space) for the standard, Galilean and
 averaged Galilean cycles, grids of more tiles than the single-launch bucket scan and the LDS
 bucket histogram hold, the beam-driven wake at 1/4 scale (gamma = 1000 beam), several species
-in one call in every order (two mobile species; an immobile one first or between), and calls
-without particles (no species, or species of zero particles)."""
+in one call in every order (two mobile species; an immobile one first or between), calls without
+particles (no species, or species of zero particles), and grids with an axis of 1024 points, the
+largest accepted."""
 
 import numpy as np
 import pytest
