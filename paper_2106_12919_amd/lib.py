@@ -254,10 +254,12 @@ def pic_probe_lds_atomics(width_bits, iters=4096):
 # ------------------------------------------------------------------ tensor containers
 
 class Species:
-    """One species as separate contiguous device tensors (cell int32, off/u/w of the run dtype)."""
+    """One species as separate contiguous device tensors (cell int32, off/u/w of the run dtype); with
+    ``w`` None every particle has the weight ``w_const``."""
 
-    def __init__(self, cell, off, u, w, q, m):
+    def __init__(self, cell, off, u, w, q, m, w_const=0.0):
         self.cell, self.off, self.u, self.w, self.q, self.m = cell, list(off), list(u), w, float(q), float(m)
+        self.w_const = float(w_const)
 
     @classmethod
     def from_host(cls, sp, shape, dtype, device="cuda"):
@@ -289,7 +291,7 @@ class Species:
             s.off[d] = _ptr(self.off[d])
             s.u[d] = _ptr(self.u[d])
         s.w = _ptr(self.w)
-        s.w_const = 0.0
+        s.w_const = self.w_const
         s.q, s.m = self.q, self.m
         return s
 

@@ -6,8 +6,8 @@ pic_step call of several steps (E, B resident in Fourier space) for the standard
 averaged Galilean cycles, grids of more tiles than the single-launch bucket scan and the LDS
 bucket histogram hold, the beam-driven wake at 1/4 scale (gamma = 1000 beam), several species
 in one call in every order (two mobile species; an immobile one first or between), calls without
-particles (no species, or species of zero particles), and grids with an axis of 1024 points, the
-largest accepted."""
+particles (no species, or species of zero particles), grids with an axis of 1024 points, the
+largest accepted, and species of one constant weight (no weight array)."""
 
 import numpy as np
 import pytest
@@ -451,3 +451,45 @@ def test_calls_without_particles(dtype, shape, species):
         _compare_particles(el, osp[0], shape, wl.spacing, p.lengths, dtype, 1e-11 if dtype == "f64" else 2e-5,
                            1e-11 if dtype == "f64" else 2e-5)
     ctx.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape_order", [1, 3])
+def test_constant_weight_species(dtype, shape_order):
+    """A species without a weight array (w = NULL) takes w_const for every particle: one call of three
+    steps with the electrons and an immobile ion species both given that way gives bitwise the same
+    fields, sources and particles as the same species with an explicit array of that weight (the
+    particles as a set: the order inside a tile's run after regrouping is not unique)."""
+    shape = (16, 16, 24)
+    banner(f"pic_step with w_const species dtype={dtype} shape_order={shape_order}")
+    wl = inputs.small(shape, ppc=2, shape_order=shape_order, center_order=8, dtype=dtype, u_th=0.2,
+                      field_amp=0.05, seed=143)
+    assert np.all(wl.electrons.w == wl.electrons.w[0]) and np.all(wl.ions.w == wl.ions.w[0])
+    npd = np.float32 if dtype == "f32" else np.float64
+    runs = []
+    for constant in (False, True):
+        ctx = piclib.Context.for_workload(wl, flags=0)
+        f = ctx.fields_from_workload(wl)
+        el = piclib.Species.from_host(wl.electrons, shape, dtype)
+        ions = piclib.Species.from_host(wl.ions, shape, dtype)
+        if constant:
+            for sp, host in ((el, wl.electrons), (ions, wl.ions)):
+                sp.w, sp.w_const = None, float(npd(host.w[0]))
+        piclib.pic_deposit(ctx.ctx, [ions, el], f, piclib.PIC_DEP_RHO_ONLY)
+        f.rho_old.copy_(f.rho_new)
+        piclib.pic_step(ctx.ctx, f, [ions, el], 3)
+        piclib.pic_sync(ctx.ctx)
+        runs.append((ctx, f, el, ions))
+    (_, fa, ea, ia), (_, fb, eb, ib) = runs
+    for d in range(3):
+        assert torch.equal(fa.E_stag[d], fb.E_stag[d]) and torch.equal(fa.B_stag[d], fb.B_stag[d]), d
+        assert torch.equal(fa.J_nod[d], fb.J_nod[d]), d
+    assert torch.equal(fa.rho_old, fb.rho_old)
+    def records(sp):
+        r = np.stack([np64(sp.cell)] + [np64(x) for x in sp.off] + [np64(x) for x in sp.u], axis=1)
+        return r[np.lexsort(r.T[::-1])]
+
+    for a, b in ((ea, eb), (ia, ib)):
+        assert np.array_equal(records(a), records(b))
+    for ctx, *_ in runs:
+        ctx.close()
