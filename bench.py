@@ -335,6 +335,10 @@ def main():
                                                              steps=args.warmup + args.steps)}
         del final32, final64
         torch.cuda.empty_cache()
+    # the roofline against the copy rate this GPU reaches as well as against the peak
+    cb = copy_bandwidth()
+    result["hbm_copy"] = cb
+    result["roofline"]["frac_of_copy"] = round(result["roofline"]["achieved"] / cb["GBps"], 4)
     if args.field_adjoint:
         result["field_solve"] = time_field_solve(wl, flags)
     if args.galilean is not None:
@@ -622,6 +626,31 @@ def time_fwd_bwd(config_name, every, reps=3, steps=0, loss="kinetic"):
             "fwd_bwd_particle_pushes_per_s": Np * K / T_fb, "fwd_bwd_cell_updates_per_s": wl.cells * K / T_fb,
             "loss_value": grads["loss"], "grad_norm": grads["norm"],
             "stage_ms_total_one_run": {k: round(v[0], 3) for k, v in stages.items() if v[1]}}
+
+
+def copy_bandwidth(mib=1024, reps=5):
+    """Device-to-device copy rate in GB/s (bytes read plus written), best of ``reps`` copies of a
+    ``mib`` MiB buffer timed with events on the current stream: the HBM rate a streaming kernel
+    reaches in practice, beside the 8 TB/s peak."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"GBps": round(2 * n * 4 / (best * 1e-3) / 1e9, 1), "bytes_per_copy": 2 * n * 4,
+            "ms": round(best, 4), "kernel": "torch copy_ of a float32 buffer, best of %d" % reps}
 
 
 def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0, v_gal=(0.0, 0.0, 0.0), keep=False,
