@@ -705,7 +705,7 @@ def run_gpu(wl, config_name, steps, warmup, calibrate_copy, flags=0, v_gal=(0.0,
     Np = el.n
     s = 4 if wl.dtype == "f32" else 8
     breakdown = {}
-    ntiles = 1
+    ntiles = 1  # the library's particle tiles: 8 cells along each axis, partial ones at the upper ends
     for n in wl.shape:
         ntiles *= -(-n // 8)
     for name, (ms, cnt) in stages.items():
