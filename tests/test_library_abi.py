@@ -58,6 +58,7 @@ def good_params(**kw):
     (dict(center_order=3), piclib.PIC_EUNSUPPORTED),
     (dict(center_order=34), piclib.PIC_EUNSUPPORTED),
     (dict(center_order=0), piclib.PIC_EUNSUPPORTED),
+    (dict(shape=(16, 16, 8), center_order=16), piclib.PIC_EUNSUPPORTED),  # order above the smallest axis
     (dict(psatd_order=7), piclib.PIC_EUNSUPPORTED),
     (dict(psatd_order=66), piclib.PIC_EUNSUPPORTED),
     (dict(v_gal=(0.0, 0.0, -1.0)), piclib.PIC_EINVAL),          # |v_gal| must stay below c
